@@ -1,0 +1,336 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the pin it implements and the passage it follows.  None of
+them re-types the oracle's formulas: they use quadrature of the integral
+definitions (oracle/brute.py), dense library solves, exact permutations,
+Fourier closed forms, an independent ODE integrator and invariants.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from paper_2007_12227_amd.inputs import (H_FEL, H_FREE, H_PENDULUM, H_SHO_EXACT, Axis,
+                                         Hamiltonian, fel_gaussian, gaussian, pendulum_axes, rng)
+
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    vals = {}
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if line:
+            k, v = line.split("=", 1)
+            vals[k.strip()] = eval(v.strip(), {"pi": math.pi})  # numeric literals and pi only
+    return vals
+
+
+PAPER = _golden("paper_parameters.txt")
+
+
+# ---- P1: overlap integrals and the brute-force deposit (Sec. Algorithm, eqs. 8-9) ----
+
+def test_p1_overlap_is_cubic_bspline():
+    g = rng(11)
+    for _ in range(200):
+        h = g.uniform(0.1, 2.0)
+        a, b = g.uniform(-3, 3, 2)
+        assert brute.overlap(a, b, h) == pytest.approx(h * oracle.b3((a - b) / h), abs=1e-13)
+
+
+@pytest.mark.parametrize("px", [True, False])
+def test_p1_deposit_matches_quadrature_8x8(px):
+    g = rng(12)
+    x = Axis(-math.pi, math.pi, 8, True) if px else Axis(-1.0, 1.0, 8, False)
+    p = Axis(-3.0, 3.0, 8, False)
+    w = g.uniform(-1, 1, (8, 8))
+    # displacements up to several cells, in physical units, including wrap-around
+    dx = g.uniform(-3.5, 3.5, (8, 8)) * x.h
+    dp = g.uniform(-2.5, 2.5, (8, 8)) * p.h
+    b = oracle.deposit(x, p, dx / x.h, dp / p.h, w)
+    D = brute.transfer_matrix(x, p, dx, dp)
+    ref = (D.T @ w.reshape(-1)).reshape(8, 8) / (x.h * p.h)
+    np.testing.assert_allclose(b, ref, atol=1e-13, rtol=0)
+
+
+# ---- P3: separable solve == dense solve of the Kronecker mass matrix (eq. 10) ----
+
+@pytest.mark.parametrize("n,px,pp", [(8, True, False), (16, True, False), (8, False, False),
+                                     (8, True, True)])
+def test_p3_separable_solve_equals_dense(n, px, pp):
+    g = rng(13)
+    x = Axis(0.0, 1.0, n, px)
+    p = Axis(-0.5, 0.5, n, pp)
+    b = g.uniform(-1, 1, (n, n))
+    lam = brute.mass_matrix(x, p) / (x.h * p.h)
+    ref = np.linalg.solve(lam, b.reshape(-1)).reshape(n, n)
+    np.testing.assert_allclose(oracle.solve(x, p, b), ref, atol=1e-13, rtol=0)
+
+
+def test_p3_full_step_equals_dense_update():
+    """Three pendulum steps through orc_run == Lambda^{-1} Delta^T w by quadrature."""
+    x, p = pendulum_axes(8)
+    ham = Hamiltonian(H_PENDULUM, a=1.0)
+    w = rng(14).uniform(0, 1, (8, 8))
+    dt = 0.3
+    du, dv = oracle.push(x, p, ham, dt)
+    ref = w.copy()
+    for _ in range(3):
+        ref = brute.step_dense(x, p, du * x.h, dv * p.h, ref)
+    got = oracle.run(x, p, ham, w, dt, 3).w
+    np.testing.assert_allclose(got, ref, atol=1e-12, rtol=0)
+
+
+# ---- P2: conservation (Sec. Algorithm, eqs. 11-12) ----
+
+def test_p2_sum_conserved_periodic_periodic():
+    x = Axis(-math.pi, math.pi, 48, True)
+    p = Axis(-3.0, 3.0, 40, True)
+    w = rng(15).uniform(0, 1, (40, 48))
+    r = oracle.run(x, p, Hamiltonian(H_PENDULUM, a=1.3), w, 0.07, 40)
+    assert abs(r.w.sum() - w.sum()) <= 1e-13 * w.sum()
+
+
+def test_p2_sum_conserved_interior_support_open_p():
+    x, p = pendulum_axes(96)
+    w = gaussian(x, p, 0.5, 0.0, 0.3)
+    r = oracle.run(x, p, Hamiltonian(H_PENDULUM, a=1.0), w, 0.05, 60)
+    assert abs(r.w.sum() - w.sum()) <= 1e-12 * w.sum()
+
+
+# ---- P4: lattice-aligned maps are exact permutations ----
+
+def test_p4_free_streaming_integer_shift_is_row_rotation():
+    n, K = 32, 9
+    x = Axis(0.0, float(n), n, True)                 # h_x = 1
+    p = Axis(-float(K), float(n - 1 - K), n, False)  # h_p = 1, p_j = j - K
+    w = rng(16).uniform(-1, 1, (n, n))
+    got = oracle.run(x, p, Hamiltonian(H_FREE), w, 1.0, 3).w
+    ref = np.stack([np.roll(w[j], 3 * (j - K)) for j in range(n)])
+    np.testing.assert_allclose(got, ref, atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("quarter_turns", [1, 2])
+def test_p4_rotation_by_right_angles_is_permutation(quarter_turns):
+    n, h = 16, 0.25
+    half = 0.5 * (n - 1) * h
+    x = Axis(-half, half, n, False)
+    p = Axis(-half, half, n, False)
+    w = rng(17).uniform(-1, 1, (n, n))
+    got = oracle.run(x, p, Hamiltonian(H_SHO_EXACT, omega=1.0), w, quarter_turns * math.pi / 2, 1).w
+    # rotation by +90 deg maps (x, p) -> (p, -x): w'[n-1-m][k] = w[k][m]
+    ref = np.rot90(w, k=quarter_turns)  # numpy's rot90 is exactly this index map on [p][x]
+    np.testing.assert_allclose(got, ref, atol=1e-12, rtol=0)
+
+
+def test_p4_zero_motion_is_identity_including_open_edges():
+    x, p = Axis(0, 1, 12, False), Axis(0, 1, 10, False)
+    w = rng(18).uniform(-1, 1, (10, 12))
+    got = oracle.run(x, p, Hamiltonian(H_PENDULUM, a=0.0), w, 0.0, 5).w
+    np.testing.assert_allclose(got, w, atol=1e-13, rtol=0)
+
+
+# ---- P5: free streaming, Fourier closed form ----
+
+def test_p5_free_streaming_fourier_gain():
+    n = 64
+    x = Axis(0.0, 2 * math.pi, n, True)
+    p = Axis(-2.0, 2.0, 24, False)
+    dt, steps, k = 0.37, 7, 5
+    kappa = 2 * math.pi * k / n
+    phase = rng(19).uniform(0, 2 * math.pi, p.n)
+    m = np.arange(n)
+    w = np.cos(kappa * m[None, :] + phase[:, None])
+    got = oracle.run(x, p, Hamiltonian(H_FREE), w, dt, steps).w
+    ref = np.empty_like(w)
+    for j in range(p.n):
+        alpha = p.nodes()[j] * dt / x.h
+        # G = 3 sum_n e^{i kappa n} B3(n + alpha) / (2 + cos kappa); B3 from quadrature
+        nn = np.arange(math.floor(-alpha) - 3, math.floor(-alpha) + 4)
+        G = 3 * sum(np.exp(1j * kappa * q) * brute.overlap(q + alpha, 0.0, 1.0) for q in nn) \
+            / (2 + math.cos(kappa))
+        ref[j] = np.real(G**steps * np.exp(1j * (kappa * m + phase[j])))
+    np.testing.assert_allclose(got, ref, atol=1e-12, rtol=0)
+
+
+# ---- P6: exact rotation moves the centroid rigidly (Sec. Harmonic Oscillators) ----
+
+def test_p6_sho_centroid_rotates_rigidly_one_revolution():
+    theta = PAPER["sho_phase_advance"]
+    steps = PAPER["sho_steps_per_revolution"]
+    n = 96  # the solve's kernel decays as 0.268^k: keep the edges ~30 cells from the support
+    x = Axis(-4.0, 4.0, n, False)
+    p = Axis(-4.0, 4.0, n, False)
+    w0 = gaussian(x, p, 1.5, 0.0, 0.3)
+    r = oracle.run(x, p, Hamiltonian(H_SHO_EXACT, omega=1.0), w0, theta, steps, series=True)
+    X, P = np.meshgrid(x.nodes(), p.nodes())
+    c0 = np.array([(w0 * X).sum(), (w0 * P).sum()]) / w0.sum()
+    w = w0
+    for s in range(1, steps + 1):
+        w = oracle.run(x, p, Hamiltonian(H_SHO_EXACT, omega=1.0), w, theta, 1).w
+        c = np.array([(w * X).sum(), (w * P).sum()]) / w.sum()
+        ang = s * theta
+        ref = np.array([c0[0] * math.cos(ang) + c0[1] * math.sin(ang),
+                        -c0[0] * math.sin(ang) + c0[1] * math.cos(ang)])
+        np.testing.assert_allclose(c, ref, atol=1e-12)
+    np.testing.assert_allclose(r.w, w, atol=1e-13)
+    # one full revolution returns the centroid to its start
+    assert abs(r.series[-1]["sum_w"] - w0.sum()) < 1e-10 * w0.sum()
+
+
+# ---- P7, P8, P9: FEL (Sec. FEL simulations, eqs. 13a-c) ----
+
+def _fel_small(n=96, npp=128):
+    inst = fel_gaussian(n, 10, npp=npp)
+    return inst
+
+
+def test_p8_first_bunching_closed_form():
+    inst = _fel_small()
+    N0 = inst.w0.sum()
+    b0 = oracle.bunching(inst.x, inst.p, inst.ham, inst.dt, inst.w0, N0)
+    eta = inst.p.nodes()
+    g = np.exp(-eta**2 / (2 * 0.05**2))
+    ref = 0.005 * np.sum(g * np.exp(-1j * eta * inst.dt / 2)) / g.sum()
+    assert abs(b0 - ref) < 1e-15
+
+
+def test_p7_fel_invariant_conserved_before_edges():
+    inst = _fel_small()
+    r = oracle.run(inst.x, inst.p, inst.ham, inst.w0, inst.dt, 300, series=True)
+    E0 = abs(1e-3) ** 2 + (inst.w0 * inst.p.nodes()[:, None]).sum() / inst.w0.sum()
+    E = np.array([m["fel_invariant"] for m in r.series])
+    assert np.max(np.abs(E - E0)) < 1e-12
+    # the field has grown, so the invariant is not trivially constant
+    assert abs(r.A) > 5e-3
+
+
+def test_p7_detects_wrong_kick_field():
+    """The invariant breaks if the kick uses A instead of A + b dz/2 (a plausible
+    mistake), so P7 really pins the kick."""
+    inst = _fel_small()
+    w = inst.w0.copy()
+    A = complex(1e-3, 0)
+    N0 = w.sum()
+    x, p, ham, dz = inst.x, inst.p, inst.ham, inst.dt
+    E0 = abs(A) ** 2 + (w * p.nodes()[:, None]).sum() / N0
+    for _ in range(200):
+        b = oracle.bunching(x, p, ham, dz, w, N0)
+        du, dv = oracle.push(x, p, ham, dz, np.array([A.real, A.imag]))  # wrong: no b dz/2
+        w = oracle.solve(x, p, oracle.deposit(x, p, du, dv, w))
+        A += b * dz
+    E = abs(A) ** 2 + (w * p.nodes()[:, None]).sum() / N0
+    assert abs(E - E0) > 1e-9
+
+
+@pytest.mark.slow
+def test_p9_fel_linear_growth_rate():
+    inst = fel_gaussian(64, 600, npp=192)
+    r = oracle.run(inst.x, inst.p, inst.ham, inst.w0, inst.dt, 600, series=True)
+    z = inst.dt * np.arange(1, 601)
+    lnA = np.log(np.hypot([m["A_re"] for m in r.series], [m["A_im"] for m in r.series]))
+    sel = (z >= 2) & (z <= 6)
+    rate = np.polyfit(z[sel], lnA[sel], 1)[0]
+    # cold beam: lambda^3 = i, growth sqrt(3)/2; a 0.05 energy spread lowers it slightly
+    assert 0.80 < rate < math.sqrt(3) / 2 + 0.01
+
+
+# ---- P10, P11: linearity and the pendulum's point symmetry ----
+
+def test_p10_linearity_static_map():
+    x, p = pendulum_axes(40)
+    ham = Hamiltonian(H_PENDULUM, a=1.0)
+    g = rng(20)
+    w1, w2 = g.uniform(-1, 1, (40, 40)), g.uniform(-1, 1, (40, 40))
+    s = lambda w: oracle.run(x, p, ham, w, 0.11, 6).w
+    np.testing.assert_allclose(s(2.5 * w1 - 0.75 * w2), 2.5 * s(w1) - 0.75 * s(w2), atol=1e-12)
+
+
+def test_p11_pendulum_point_reflection_symmetry():
+    n = 64
+    x, p = pendulum_axes(n)
+    w = rng(21).uniform(0, 1, (n, n))
+    refl = lambda a: np.roll(a[::-1, ::-1], 1, axis=1)  # i -> (n - i) mod n, j -> n-1-j
+    w = w + refl(w)
+    r = oracle.run(x, p, Hamiltonian(H_PENDULUM, a=1.0), w, 0.05, 50).w
+    np.testing.assert_allclose(r, refl(r), atol=1e-12 * np.abs(r).max())
+
+
+# ---- the pendulum pusher against an independent ODE integrator ----
+
+def test_pendulum_push_is_second_order_against_ode():
+    from scipy.integrate import solve_ivp
+    x, p = pendulum_axes(8)
+    a = 1.3
+    ham = Hamiltonian(H_PENDULUM, a=a)
+    errs = []
+    for dt in (0.1, 0.05):
+        du, dv = oracle.push(x, p, ham, dt)
+        err = 0.0
+        for j in range(0, 8, 3):
+            for i in range(0, 8, 3):
+                z0 = [x.nodes()[i], p.nodes()[j]]
+                sol = solve_ivp(lambda t, z: [z[1], -a * math.sin(z[0])], (0, dt), z0,
+                                rtol=1e-12, atol=1e-12)
+                err = max(err, abs(z0[0] + du[j, i] * x.h - sol.y[0, -1]),
+                          abs(z0[1] + dv[j, i] * p.h - sol.y[1, -1]))
+        errs.append(err)
+    assert errs[0] < 1e-3
+    # local error O(dt^3): halving dt divides it by about 8
+    assert 6.0 < errs[0] / errs[1] < 10.0
+
+
+def test_round_fp32_mode_rounds_state():
+    x, p = pendulum_axes(16)
+    w = rng(22).uniform(0, 1, (16, 16))
+    r = oracle.run(x, p, Hamiltonian(H_PENDULUM, a=1.0), w, 0.05, 3, round_fp32=True)
+    assert np.array_equal(r.w, r.w.astype(np.float32).astype(np.float64))
+
+
+# ---- diagnostics: exact integrals of the tent expansion (Sec. Numerical Examples) ----
+
+@pytest.mark.parametrize("kind", [H_PENDULUM, H_SHO_EXACT])
+def test_moments_mass_and_energy_are_integrals_of_the_expansion(kind):
+    """Mass and energy = integrals of f = sum w Lambda Lambda (eq. 4), by composite
+    Simpson quadrature on a mesh with breakpoints at the nodes, over all space
+    (full tents at open edges)."""
+    x = Axis(-math.pi, math.pi, 8, True) if kind == H_PENDULUM else Axis(-2.0, 2.0, 8, False)
+    p = Axis(-3.0, 3.0, 7, False)
+    a = 1.7
+    w = rng(23).uniform(-0.2, 1.0, (p.n, x.n))
+    ham = Hamiltonian(kind, a=a)
+
+    def axis_mesh(ax, sub=120):
+        lo = ax.lo - (0 if ax.periodic else ax.h)
+        hi = ax.hi if ax.periodic else ax.hi + ax.h
+        nint = int(round((hi - lo) / ax.h)) * sub
+        t = np.linspace(lo, hi, nint + 1)
+        wt = np.ones(nint + 1)
+        wt[1:-1:2], wt[2:-1:2] = 4, 2
+        return t, wt * (hi - lo) / nint / 3
+
+    def basis(ax, t):
+        B = np.zeros((ax.n, t.size))
+        for j in range(ax.n):
+            centres = [ax.lo + j * ax.h] + ([ax.lo + j * ax.h + m * (ax.hi - ax.lo) for m in (-1, 1)]
+                                             if ax.periodic else [])
+            for c in centres:
+                B[j] += brute.tent(t - c, ax.h)
+        return B
+
+    tx, wx = axis_mesh(x)
+    tp, wp = axis_mesh(p)
+    f = basis(p, tp).T @ w @ basis(x, tx)          # f on the (p, x) mesh
+    mass = wp @ f @ wx
+    if kind == H_PENDULUM:
+        dens = 0.5 * tp[:, None] ** 2 - a * np.cos(tx)[None, :]
+    else:
+        dens = 0.5 * tp[:, None] ** 2 + 0.5 * tx[None, :] ** 2
+    energy = wp @ (dens * f) @ wx
+    m = oracle.moments(x, p, ham, w)
+    assert m["mass"] == pytest.approx(mass, rel=1e-12)
+    assert m["energy"] == pytest.approx(energy, rel=1e-10)
+    assert m["neg_mass"] == pytest.approx(-x.h * p.h * w[w < 0].sum(), rel=1e-14)
