@@ -1,0 +1,147 @@
+#!/usr/bin/env python3
+"""Throughput of the phase-space-conservation Vlasov step on one MI355X.
+
+One bench step = one full time step of the hot path (push, B-spline deposit,
+mass-matrix solves) over the 2048^2 pendulum with the uniform band start
+(|p| <= 2.5, 1% noise, dt 0.02; its full run is 1000 steps).  Inputs are
+resident in HBM before the timed region.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "node-steps/s (push+deposit) vs plain; % HBM roofline; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+ALG_BYTES_PER_NODE = 8  # each kernel reads one FP32 array and writes one
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed_steps(g, dt, steps, warmup):
+    import torch
+    g.step(dt, warmup)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    g.step(dt, steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def cpu_baseline(inst, steps):
+    import numpy as np
+
+    import oracle
+    w = inst.w0.astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.run(inst.x, inst.p, inst.ham, w, inst.dt, steps)
+    dt = time.perf_counter() - t0
+    return {"value": inst.nodes * steps / dt, "unit": "node-steps/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{steps} steps of the {inst.x.n}x{inst.p.n} pendulum band from its initial state "
+                      f"(FP64 C oracle, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=32)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 256 MiB device copy (scale for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU layout is a design, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2007_12227_amd import binding
+    from paper_2007_12227_amd.inputs import pendulum_band
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    binding.lib()
+    inst = pendulum_band(args.n)
+    N = inst.nodes
+
+    if args.copy_probe:
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    # plain path: default tiles, one launch per kernel
+    gp = binding.grid_for(inst)
+    gp.set_launch(False)
+    plain_s, _ = timed_steps(gp, inst.dt, args.steps, args.warmup)
+    gp.close()
+    plain = N * args.steps / plain_s
+    log(f"plain: {plain:.3e} node-steps/s ({1e6 * plain_s / args.steps:.2f} us/step)")
+
+    # tuned path: autotuned tiles, steps replayed from HIP graphs
+    g = binding.grid_for(inst)
+    tune_us = g.autotune(inst.dt)
+    tiles = g.tiles()
+    log(f"autotune: {tiles} ({tune_us:.2f} us/step)")
+    sec, wall = timed_steps(g, inst.dt, args.steps, args.warmup)
+    value = N * args.steps / sec
+    log(f"tuned: {value:.3e} node-steps/s ({1e6 * sec / args.steps:.2f} us/step, wall {wall:.3f} s)")
+
+    # per-kernel durations (HIP events on the grid's stream around each launch)
+    dep_us, sol_us = g.step_timed(inst.dt, 64)
+    m = g.moments()
+    g.close()
+    dom_name, dom_us = ("k_deposit", dep_us) if dep_us >= sol_us else ("k_solve", sol_us)
+    achieved = ALG_BYTES_PER_NODE * N / (dom_us * 1e-6) / 1e9
+    log(f"kernels: deposit {dep_us:.2f} us, solve {sol_us:.2f} us")
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "node-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"pendulum_band_{args.n}", "nx": args.n, "np": args.n, "dt": inst.dt,
+                   "a": 1.0, "tiles": tiles, "launch": "hip-graph"},
+        "plain": {"value": plain, "ms_per_step": 1e3 * plain_s / args.steps,
+                  "speedup": value / plain},
+        "kernels_us": {"k_deposit": dep_us, "k_solve": sol_us},
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "step_roofline_frac": ALG_BYTES_PER_NODE * N / (sec / args.steps) / 1e9 / HBM_PEAK_GBS,
+        "final_sum_w": m["sum_w"],
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(inst, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * vp.h -- C interface of libvp, the MI355X (gfx950) phase-space-conservation
+ * Vlasov solver of Edelen & Webb, "A Vlasov Algorithm Derived from Phase Space
+ * Conservation".
+ *
+ * The method (Sec. "An Algorithm Based on Phase Space Density Conservation"):
+ * the density is a sum of tent functions on a fixed 2-D lattice,
+ * f(x,p) = sum_j w_j Lambda(x-x_j) Lambda(p-p_j) (eq. 4).  One time step pushes
+ * every lattice node with a particle pusher (Sec. "The Vlasov Equation as Flows
+ * on Phase Space", eq. vlasov_flow), and projects the moved tents back onto the
+ * lattice: w_fin = Lambda^{-1} Delta^T w_in (eqs. 7-10), where Lambda is the
+ * tent mass matrix (eq. 8) and Delta the overlap of moved and fixed tents
+ * (eq. 9).  Coordinates are periodic and momenta open (Sec. "Numerical
+ * Examples"); weight pushed past an open edge is lost.
+ *
+ * Conventions for every call:
+ *  - return 0 on success, a negative VP_E* code on failure; no call throws;
+ *    vp_last_error() gives a thread-local message for the last failure;
+ *  - arrays are [n_p][n_x] with x fastest, FP32;
+ *  - device memory (the workspace, device pointers passed in) belongs to the
+ *    caller and must outlive the grid; the library frees nothing it did not
+ *    allocate and copies host arrays before returning;
+ *  - calls on one grid are not thread-safe; work is ordered on the grid's HIP
+ *    stream; vp_step and vp_batch_step return without waiting, vp_moments,
+ *    vp_get_density and vp_set_density wait for the stream.
+ */
+#ifndef VP_H
+#define VP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define VP_OK 0
+#define VP_EINVAL (-1)       /* invalid argument */
+#define VP_ENOMEM (-2)       /* workspace missing or too small */
+#define VP_ESTATE (-3)       /* call out of order (step before density/Hamiltonian) */
+#define VP_EHIP (-4)         /* a HIP runtime call failed */
+#define VP_EUNSUPPORTED (-5) /* valid for the method but not built here */
+#define VP_ENONFINITE (-6)   /* the state holds NaN or Inf */
+
+/* Hamiltonian kinds (Sec. "Numerical Examples") */
+#define VP_H_FREE 0       /* free streaming x' = p */
+#define VP_H_SHO_EXACT 1  /* H = (p^2+x^2)/2 advanced by its exact rotation (Sec. Harmonic Oscillators) */
+#define VP_H_PENDULUM 2   /* H = p^2/2 - a cos x, drift-kick-drift leapfrog (Sec. Harmonic Oscillators) */
+#define VP_H_FEL 3        /* 1-D FEL, eqs. 13a-c, self-consistent field A (Sec. FEL simulations) */
+
+typedef struct vp_grid vp_grid;
+typedef struct vp_batch vp_batch;
+
+/* One lattice axis.  periodic != 0: n nodes on [lo, hi), spacing (hi-lo)/n.
+ * periodic == 0: n nodes on [lo, hi] including both ends, spacing (hi-lo)/(n-1).
+ * n >= 4.  The momentum axis (p) must be open. */
+typedef struct {
+    double lo, hi;
+    int32_t n;
+    int32_t periodic;
+} vp_axis;
+
+/* Grid creation.  workspace: caller-owned device memory of at least
+ * vp_workspace_bytes(&x, &p) bytes, 256-byte aligned.  stream: a hipStream_t
+ * (NULL = the default stream) on which all work of this grid is ordered. */
+typedef struct {
+    vp_axis x, p;
+    void* workspace;
+    size_t workspace_bytes;
+    void* stream;
+} vp_grid_desc;
+
+/* The Hamiltonian and its pusher.
+ *  FREE:      dx = p dt.
+ *  SHO_EXACT: rotation of (x, p) by omega*dt; needs an open x axis.
+ *  PENDULUM:  V(x) = -a cos x; drift dt/2, kick -a sin(x) dt, drift dt/2.
+ *  FEL:       x = phase psi, p = energy eta, dt = dz; dpsi/dz = fel_delta + eta,
+ *             deta/dz = -2 Re[(A + i fel_sigma2 <e^{-i psi}>) e^{i psi}],
+ *             dA/dz = <e^{-i psi}> with <g> = N0^{-1} sum_j w_j g(psi_j) and N0 the
+ *             sum of the weights when the density was set.  Drift dz/2, kick dz
+ *             with the phases frozen (integrated exactly: A grows linearly
+ *             through the kick), drift dz/2.  A_re, A_im give the field at the
+ *             current step; vp_moments reports it as the run advances. */
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    double a;
+    double omega;
+    double fel_delta;
+    double fel_sigma2;
+    double A_re, A_im;
+} vp_hamiltonian;
+
+/* Diagnostics (Sec. "Numerical Examples": phase-space volume and entropy),
+ * accumulated in FP64.  With the tent basis, integrals of f are exact sums:
+ *  sum_w    = sum_j w_j
+ *  mass     = h_x h_p sum_j w_j                      (integral of f)
+ *  neg_mass = -h_x h_p sum_{w_j<0} w_j
+ *  l1       = h_x h_p sum_j |w_j|
+ *  entropy  = -h_x h_p sum_{w_j>0} w_j ln w_j
+ *  mean_p   = sum_j w_j p_j / sum_j w_j
+ *  energy   = integral of H f; exact tent integrals of p^2, x^2 and cos x
+ *  FEL: A, bunching <e^{-i psi}> at the lattice phases, and
+ *       fel_invariant = |A|^2 + N0^{-1} sum_j w_j eta_j (conserved by the step)
+ *  nonfinite = number of NaN/Inf weights (the call then returns VP_ENONFINITE). */
+typedef struct {
+    double sum_w, mass, neg_mass, l1, entropy, mean_p, energy;
+    double A_re, A_im, bunch_re, bunch_im, fel_invariant;
+    int64_t step;
+    int64_t nonfinite;
+} vp_moments_t;
+
+/* Tile shape of the two per-step kernels: the deposit tile (k1) and the solve
+ * tile (k2), in lattice nodes.  Zero fields keep the current value. */
+typedef struct {
+    int32_t k1_tx, k1_ty;
+    int32_t k2_tx, k2_ty;
+} vp_tiles;
+
+/* Bytes of device workspace a grid of this shape needs (0 if the axes are invalid). */
+size_t vp_workspace_bytes(const vp_axis* x, const vp_axis* p);
+
+/* Create a grid on the caller's workspace.  Fails with VP_EINVAL for invalid
+ * axes, VP_ENOMEM for a missing or small workspace, VP_EUNSUPPORTED for a
+ * periodic p axis. */
+int vp_create_grid(const vp_grid_desc* desc, vp_grid** out);
+
+/* Destroy a grid (NULL is allowed).  Waits for the grid's stream. */
+int vp_destroy_grid(vp_grid* g);
+
+/* Set the Hamiltonian (kind and parameters; for the FEL also the current field). */
+int vp_set_hamiltonian(vp_grid* g, const vp_hamiltonian* h);
+
+/* Set the weights w (n_p*n_x floats; device pointer if on_device, else host).
+ * Records N0 = sum w (FP64) and resets the step counter. */
+int vp_set_density(vp_grid* g, const float* w, int32_t on_device);
+
+/* Copy the current weights out (n_p*n_x floats). */
+int vp_get_density(vp_grid* g, float* w, int32_t on_device);
+
+/* Advance nsteps steps of size dt (dz for the FEL) on the grid's stream.
+ * VP_ESTATE if no density or Hamiltonian has been set. */
+int vp_step(vp_grid* g, double dt, int64_t nsteps);
+
+/* Diagnostics of the current state; waits for the stream. */
+int vp_moments(vp_grid* g, vp_moments_t* out);
+
+/* Tile shapes.  vp_set_tiles validates the shape (VP_EINVAL if a kernel's
+ * local memory would exceed its limit). */
+int vp_set_tiles(vp_grid* g, const vp_tiles* t);
+int vp_get_tiles(const vp_grid* g, vp_tiles* t);
+
+/* Launch mode of vp_step: use_graph != 0 replays the per-step kernels from a
+ * HIP graph of several steps; 0 launches each kernel directly ("plain"). */
+int vp_set_launch(vp_grid* g, int32_t use_graph);
+
+/* Measurement helper: nsteps steps exactly as vp_step with direct launches,
+ * with HIP events recorded on the grid's stream around every kernel.
+ * us[0] and us[1] receive the mean duration in microseconds of the deposit
+ * kernel and of the solve kernel.  Waits for the stream. */
+int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]);
+
+/* Time candidate tile shapes on this grid for step size dt and keep the
+ * fastest.  The state is restored afterwards.  best_us (may be NULL) receives
+ * the time per step of the chosen shape.  Results are cached per shape class. */
+int vp_autotune(vp_grid* g, double dt, double* best_us);
+
+/* Batched execution: n grids (each with its density and Hamiltonian set)
+ * advance together, one launch of each per-step kernel covering every tile of
+ * every grid.  dt[i] is grid i's step size.  All grids must use the same
+ * stream; the batch uses grids[0]'s stream.  The grids must outlive the batch
+ * and must not be stepped on their own while it exists. */
+int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch** out);
+int vp_batch_step(vp_batch* b, int64_t nsteps);
+int vp_batch_destroy(vp_batch* b);
+
+/* Status text and the calling thread's last error message. */
+const char* vp_status_string(int status);
+const char* vp_last_error(void);
+
+/* Host-side planning helper (no GPU needed): the source box a deposit tile
+ * scans.  Destination tile rows [by0,by1) and columns [bx0,bx1) of a grid with
+ * axes x, p under Hamiltonian h, step dt and (FEL) kick field
+ * kick_re + i kick_im.  box[4] receives [x0, x1, y0, y1): unwrapped source
+ * columns and source rows.  Every node whose pushed position deposits into
+ * the tile lies in the box. */
+int vp_plan_source_box(const vp_axis* x, const vp_axis* p, const vp_hamiltonian* h, double dt,
+                       double kick_re, double kick_im, int32_t bx0, int32_t bx1, int32_t by0,
+                       int32_t by1, int32_t box[4]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VP_H */

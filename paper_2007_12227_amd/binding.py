@@ -1,0 +1,266 @@
+"""ctypes binding of libvp (include/vp.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of ``libvp.so``; this module
+moves pointers and sizes across the C interface and turns status codes into
+exceptions.  PyTorch provides device memory (the grid workspace) and streams.
+If the library has not been built, ``lib()`` raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvp.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "vp.h")
+
+VP_OK, VP_EINVAL, VP_ENOMEM, VP_ESTATE, VP_EHIP, VP_EUNSUPPORTED, VP_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+H_FREE, H_SHO_EXACT, H_PENDULUM, H_FEL = 0, 1, 2, 3
+
+
+class VpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"vp error {code}: {msg}")
+        self.code = code
+
+
+class Axis(C.Structure):
+    _fields_ = [("lo", C.c_double), ("hi", C.c_double), ("n", C.c_int32), ("periodic", C.c_int32)]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("x", Axis), ("p", Axis), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("stream", C.c_void_p)]
+
+
+class Hamiltonian(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("a", C.c_double), ("omega", C.c_double),
+                ("fel_delta", C.c_double), ("fel_sigma2", C.c_double), ("A_re", C.c_double),
+                ("A_im", C.c_double)]
+
+
+MOMENT_FIELDS = ("sum_w", "mass", "neg_mass", "l1", "entropy", "mean_p", "energy", "A_re", "A_im",
+                 "bunch_re", "bunch_im", "fel_invariant")
+
+
+class Moments(C.Structure):
+    _fields_ = [(f, C.c_double) for f in MOMENT_FIELDS] + [("step", C.c_int64), ("nonfinite", C.c_int64)]
+
+
+class Tiles(C.Structure):
+    _fields_ = [("k1_tx", C.c_int32), ("k1_ty", C.c_int32), ("k2_tx", C.c_int32), ("k2_ty", C.c_int32)]
+
+
+_lib = None
+
+
+def declared_functions() -> list[str]:
+    """Names of the functions include/vp.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(vp_\w+)\s*\(", text, re.M)))
+
+
+def lib(load_torch: bool = True):
+    """Load libvp.so.  PyTorch is imported first so that the library binds to the
+    HIP runtime PyTorch already uses (one runtime per process)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                           "(or python paper_2007_12227_amd/build.py)")
+    if load_torch:
+        import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    L.vp_workspace_bytes.restype = C.c_size_t
+    L.vp_workspace_bytes.argtypes = [P(Axis), P(Axis)]
+    L.vp_create_grid.argtypes = [P(GridDesc), P(C.c_void_p)]
+    L.vp_destroy_grid.argtypes = [C.c_void_p]
+    L.vp_set_hamiltonian.argtypes = [C.c_void_p, P(Hamiltonian)]
+    L.vp_set_density.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
+    L.vp_get_density.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
+    L.vp_step.argtypes = [C.c_void_p, C.c_double, C.c_int64]
+    L.vp_moments.argtypes = [C.c_void_p, P(Moments)]
+    L.vp_step_timed.argtypes = [C.c_void_p, C.c_double, C.c_int64, P(C.c_double)]
+    L.vp_set_tiles.argtypes = [C.c_void_p, P(Tiles)]
+    L.vp_get_tiles.argtypes = [C.c_void_p, P(Tiles)]
+    L.vp_set_launch.argtypes = [C.c_void_p, C.c_int32]
+    L.vp_autotune.argtypes = [C.c_void_p, C.c_double, P(C.c_double)]
+    L.vp_batch_create.argtypes = [P(C.c_void_p), C.c_int32, P(C.c_double), P(C.c_void_p)]
+    L.vp_batch_step.argtypes = [C.c_void_p, C.c_int64]
+    L.vp_batch_destroy.argtypes = [C.c_void_p]
+    L.vp_status_string.restype = C.c_char_p
+    L.vp_status_string.argtypes = [C.c_int]
+    L.vp_last_error.restype = C.c_char_p
+    L.vp_plan_source_box.argtypes = [P(Axis), P(Axis), P(Hamiltonian), C.c_double, C.c_double, C.c_double,
+                                     C.c_int32, C.c_int32, C.c_int32, C.c_int32, P(C.c_int32)]
+    for name in declared_functions():
+        if name not in ("vp_workspace_bytes", "vp_status_string", "vp_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(rc: int) -> int:
+    if rc != VP_OK:
+        raise VpError(rc, lib().vp_last_error().decode())
+    return rc
+
+
+def axis(a) -> Axis:
+    return Axis(float(a.lo), float(a.hi), int(a.n), int(bool(a.periodic)))
+
+
+def hamiltonian(h) -> Hamiltonian:
+    return Hamiltonian(int(h.kind), 0, float(getattr(h, "a", 0.0)), float(getattr(h, "omega", 1.0)),
+                       float(getattr(h, "fel_delta", 0.0)), float(getattr(h, "fel_sigma2", 0.0)),
+                       float(getattr(h, "A_re", 0.0)), float(getattr(h, "A_im", 0.0)))
+
+
+def workspace_bytes(x, p) -> int:
+    return int(lib().vp_workspace_bytes(C.byref(axis(x)), C.byref(axis(p))))
+
+
+def plan_source_box(x, p, ham, dt, kick=0j, bx=(0, 0), by=(0, 0)) -> tuple[int, int, int, int]:
+    box = (C.c_int32 * 4)()
+    check(lib().vp_plan_source_box(C.byref(axis(x)), C.byref(axis(p)), C.byref(hamiltonian(ham)),
+                                   float(dt), float(complex(kick).real), float(complex(kick).imag),
+                                   int(bx[0]), int(bx[1]), int(by[0]), int(by[1]), box))
+    return tuple(int(v) for v in box)
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Grid:
+    """One lattice with its device state; all work runs on ``stream``."""
+
+    def __init__(self, x, p, stream=None, device="cuda"):
+        import torch
+        self.x, self.p = x, p
+        nbytes = workspace_bytes(x, p)
+        if nbytes == 0:
+            check(VP_EINVAL)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = base + (-base) % 256
+        self.stream = stream
+        desc = GridDesc(axis(x), axis(p), C.c_void_p(self._ws_ptr), nbytes, _stream_handle(stream))
+        h = C.c_void_p()
+        check(lib().vp_create_grid(C.byref(desc), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            check(lib().vp_destroy_grid(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_hamiltonian(self, ham):
+        check(lib().vp_set_hamiltonian(self._h, C.byref(hamiltonian(ham))))
+
+    def set_density(self, w):
+        import torch
+        if isinstance(w, torch.Tensor) and w.is_cuda:
+            t = w.to(torch.float32).contiguous()
+            assert t.numel() == self.x.n * self.p.n
+            check(lib().vp_set_density(self._h, C.c_void_p(t.data_ptr()), 1))
+        else:
+            a = np.ascontiguousarray(w, dtype=np.float32)
+            assert a.size == self.x.n * self.p.n
+            check(lib().vp_set_density(self._h, a.ctypes.data_as(C.c_void_p), 0))
+
+    def density(self) -> np.ndarray:
+        out = np.empty((self.p.n, self.x.n), dtype=np.float32)
+        check(lib().vp_get_density(self._h, out.ctypes.data_as(C.c_void_p), 0))
+        return out
+
+    def density_into(self, t):
+        """Copy the state into a CUDA float32 tensor of n_p*n_x elements."""
+        check(lib().vp_get_density(self._h, C.c_void_p(t.data_ptr()), 1))
+        return t
+
+    def step(self, dt: float, n: int = 1):
+        check(lib().vp_step(self._h, float(dt), int(n)))
+
+    def step_timed(self, dt: float, n: int) -> tuple[float, float]:
+        """n steps with per-kernel HIP events: mean (deposit_us, solve_us)."""
+        us = (C.c_double * 2)()
+        check(lib().vp_step_timed(self._h, float(dt), int(n), us))
+        return us[0], us[1]
+
+    def moments(self) -> dict:
+        m = Moments()
+        rc = lib().vp_moments(self._h, C.byref(m))
+        d = {f: getattr(m, f) for f in MOMENT_FIELDS}
+        d["step"], d["nonfinite"] = m.step, m.nonfinite
+        if rc not in (VP_OK, VP_ENONFINITE):
+            check(rc)
+        d["status"] = rc
+        return d
+
+    def set_tiles(self, k1=(0, 0), k2=(0, 0)):
+        check(lib().vp_set_tiles(self._h, C.byref(Tiles(k1[0], k1[1], k2[0], k2[1]))))
+
+    def tiles(self) -> dict:
+        t = Tiles()
+        check(lib().vp_get_tiles(self._h, C.byref(t)))
+        return {"k1": (t.k1_tx, t.k1_ty), "k2": (t.k2_tx, t.k2_ty)}
+
+    def set_launch(self, use_graph: bool):
+        check(lib().vp_set_launch(self._h, int(bool(use_graph))))
+
+    def autotune(self, dt: float) -> float:
+        us = C.c_double()
+        check(lib().vp_autotune(self._h, float(dt), C.byref(us)))
+        return us.value
+
+
+class Batch:
+    """Grids advanced together: one launch per kernel covers every tile of every grid."""
+
+    def __init__(self, grids: list[Grid], dts: list[float]):
+        self.grids = list(grids)
+        arr = (C.c_void_p * len(grids))(*[g.handle.value for g in grids])
+        d = (C.c_double * len(grids))(*[float(v) for v in dts])
+        h = C.c_void_p()
+        check(lib().vp_batch_create(arr, len(grids), d, C.byref(h)))
+        self._h = h
+
+    def step(self, n: int = 1):
+        check(lib().vp_batch_step(self._h, int(n)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            check(lib().vp_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def grid_for(inst, stream=None) -> Grid:
+    """A grid holding an input instance (paper_2007_12227_amd.inputs.Instance)."""
+    g = Grid(inst.x, inst.p, stream)
+    g.set_hamiltonian(inst.ham)
+    g.set_density(inst.w0)
+    return g

@@ -1,0 +1,811 @@
+// vp_api.hip -- host runtime of libvp: handles, validation, per-step plans,
+// launch lists, HIP graphs, batching and the tile autotuner.  See include/vp.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/vp.h"
+#include "vp_internal.h"
+
+using namespace vp;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) return fail(VP_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+constexpr int kMinTile = 8;
+constexpr size_t kMaxLds = 64 * 1024;
+constexpr int kGraphSteps = 16;
+
+bool axis_ok(const vp_axis* a) {
+    return a && a->n >= 4 && a->n <= (1 << 16) && isfinite(a->lo) && isfinite(a->hi) && a->hi > a->lo;
+}
+
+double spacing(const vp_axis& a) { return (a.hi - a.lo) / (a.periodic ? a.n : a.n - 1); }
+
+// Workspace layout: every piece 256-byte aligned.
+struct Layout {
+    size_t w0, w1, b, tab_x, tab_p, coef_x, coef_p, fel_ex, fel_eq, fel_state, partials, counters,
+        inst, off, moments, total;
+    size_t partial_doubles;
+};
+
+Layout layout(int nx, int np) {
+    Layout L{};
+    size_t n = (size_t)nx * np, o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    L.w0 = take(n * 4);
+    L.w1 = take(n * 4);
+    L.b = take(n * 4);
+    L.tab_x = take((size_t)nx * 16);
+    L.tab_p = take((size_t)np * 16);
+    L.coef_x = take((size_t)nx * 8);
+    L.coef_p = take((size_t)np * 8);
+    L.fel_ex = take((size_t)nx * 16);
+    L.fel_eq = take((size_t)np * 16);
+    L.fel_state = take(kFelStateLen * 8);
+    size_t tiles = (size_t)((nx + kMinTile - 1) / kMinTile) * ((np + kMinTile - 1) / kMinTile);
+    L.partial_doubles = std::max((size_t)kReduceBlocks * kMoments, 2 * tiles);
+    L.partials = take(L.partial_doubles * 8);
+    L.counters = take(4 * sizeof(uint32_t));
+    L.inst = take(sizeof(VpInst));
+    L.off = take(8 * sizeof(int32_t));
+    L.moments = take(kMoments * 8);
+    L.total = o;
+    return L;
+}
+
+// A list of instances launched together: one instance for a grid, many for a batch.
+struct LaunchList {
+    VpInst* d_inst = nullptr;
+    int32_t* d_off1 = nullptr;
+    int32_t* d_off2 = nullptr;
+    int ninst = 0, total1 = 0, total2 = 0;
+    size_t lds1 = 0, lds2 = 0;
+    hipStream_t stream = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+
+    void drop_graphs() {
+        for (auto& e : exec)
+            if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
+    }
+    LaunchArgs args(const int32_t* off, int total, int parity) const {
+        return LaunchArgs{d_inst, off, ninst, total, parity};
+    }
+    int enqueue_step(int parity) const {
+        HIP_TRY(launch_deposit(args(d_off1, total1, parity), total1, lds1, stream));
+        HIP_TRY(launch_solve(args(d_off2, total2, parity), total2, lds2, stream));
+        return VP_OK;
+    }
+    int build_graph(int rel_parity) {
+        hipGraph_t graph;
+        HIP_TRY(hipGraphCreate(&graph, 0));
+        hipGraphNode_t prev = nullptr;
+        std::vector<LaunchArgs> keep;
+        keep.reserve(2 * kGraphSteps);
+        for (int s = 0; s < kGraphSteps; ++s) {
+            for (int k = 0; k < 2; ++k) {
+                keep.push_back(k == 0 ? args(d_off1, total1, (rel_parity + s) & 1)
+                                      : args(d_off2, total2, (rel_parity + s) & 1));
+                void* kp[1] = {&keep.back()};
+                hipKernelNodeParams p{};
+                p.func = const_cast<void*>(k == 0 ? deposit_kernel() : solve_kernel());
+                p.gridDim = dim3(k == 0 ? total1 : total2);
+                p.blockDim = dim3(k == 0 ? kDepositThreads : kSolveThreads);
+                p.sharedMemBytes = (unsigned)(k == 0 ? lds1 : lds2);
+                p.kernelParams = kp;
+                p.extra = nullptr;
+                hipGraphNode_t node;
+                hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+                if (e != hipSuccess) {
+                    (void)hipGraphDestroy(graph);
+                    return fail(VP_EHIP, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+                }
+                prev = node;
+            }
+        }
+        hipError_t e = hipGraphInstantiate(&exec[rel_parity], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(VP_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        return VP_OK;
+    }
+    // Run n steps starting at relative parity rp.
+    int run(int64_t n, int rp, bool use_graph) {
+        int64_t done = 0;
+        if (use_graph && n >= kGraphSteps) {
+            if (!exec[rp]) {
+                int rc = build_graph(rp);
+                if (rc) return rc;
+            }
+            for (; done + kGraphSteps <= n; done += kGraphSteps) HIP_TRY(hipGraphLaunch(exec[rp], stream));
+        }
+        for (; done < n; ++done) {
+            int rc = enqueue_step((int)((rp + done) & 1));
+            if (rc) return rc;
+        }
+        return VP_OK;
+    }
+};
+
+}  // namespace
+
+struct vp_grid {
+    vp_axis x{}, p{};
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    Layout L{};
+    VpInst inst{};  // host copy of the device descriptor
+    LaunchList list;
+    vp_hamiltonian ham{};
+    bool has_ham = false, has_density = false;
+    bool plan_valid = false, bunch_valid = false;
+    double plan_dt = 0.0;
+    int parity = 0;
+    int64_t step = 0;
+    double N0 = 0.0;
+    vp_tiles tiles{};
+    bool use_graph = true;
+    bool in_batch = false;
+
+    template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+struct vp_batch {
+    std::vector<vp_grid*> grids;
+    LaunchList list;
+    int64_t steps_done = 0;
+};
+
+namespace {
+
+int validate_tiles(const vp_grid* g, const vp_tiles& t) {
+    if (t.k1_tx < kMinTile || t.k1_ty < 1 || t.k2_tx < kMinTile || t.k2_ty < kMinTile)
+        return fail(VP_EINVAL, "tile sizes below the minimum (k1_tx, k2_tx, k2_ty >= %d, k1_ty >= 1)", kMinTile);
+    if (t.k1_tx > 4096 || t.k1_ty > 1024 || t.k2_tx > 4096 || t.k2_ty > 4096)
+        return fail(VP_EINVAL, "tile sizes too large");
+    if (deposit_lds_bytes(t.k1_tx, t.k1_ty) > kMaxLds)
+        return fail(VP_EINVAL, "deposit tile %dx%d needs %zu bytes of LDS (limit %zu)", t.k1_tx, t.k1_ty,
+                    deposit_lds_bytes(t.k1_tx, t.k1_ty), kMaxLds);
+    if (solve_lds_bytes(t.k2_tx, t.k2_ty) > kMaxLds)
+        return fail(VP_EINVAL, "solve tile %dx%d needs %zu bytes of LDS (limit %zu)", t.k2_tx, t.k2_ty,
+                    solve_lds_bytes(t.k2_tx, t.k2_ty), kMaxLds);
+    (void)g;
+    return VP_OK;
+}
+
+vp_tiles clip_tiles(const vp_grid* g, vp_tiles t) {
+    t.k1_tx = std::min(t.k1_tx, g->x.n);
+    t.k1_ty = std::min(t.k1_ty, g->p.n);
+    t.k2_tx = std::min(t.k2_tx, g->x.n);
+    t.k2_ty = std::min(t.k2_ty, g->p.n);
+    return t;
+}
+
+// Upload the host descriptor and tile offsets of a single grid.
+int upload_inst(vp_grid* g) {
+    VpInst& I = g->inst;
+    const vp_tiles t = clip_tiles(g, g->tiles);
+    I.k1_tx = t.k1_tx;
+    I.k1_ty = t.k1_ty;
+    I.k1_tiles_x = (g->x.n + t.k1_tx - 1) / t.k1_tx;
+    I.k1_tiles = I.k1_tiles_x * ((g->p.n + t.k1_ty - 1) / t.k1_ty);
+    I.k2_tx = t.k2_tx;
+    I.k2_ty = t.k2_ty;
+    I.k2_tiles_x = (g->x.n + t.k2_tx - 1) / t.k2_tx;
+    I.k2_tiles = I.k2_tiles_x * ((g->p.n + t.k2_ty - 1) / t.k2_ty);
+    I.parity0 = 0;
+    int32_t off[4] = {0, I.k1_tiles, 0, I.k2_tiles};
+    HIP_TRY(hipMemcpyAsync(g->list.d_inst, &I, sizeof(VpInst), hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipMemcpyAsync(g->list.d_off1, off, sizeof off, hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->list.ninst = 1;
+    g->list.total1 = I.k1_tiles;
+    g->list.total2 = I.k2_tiles;
+    g->list.lds1 = deposit_lds_bytes(t.k1_tx, t.k1_ty);
+    g->list.lds2 = solve_lds_bytes(t.k2_tx, t.k2_ty);
+    g->list.drop_graphs();
+    return VP_OK;
+}
+
+void split(double v, float& hi, float& lo) {
+    hi = (float)v;
+    lo = (float)(v - (double)hi);
+}
+
+// Push parameters in cell units for step dt (FEL: the kick amplitudes alpha,
+// beta come from the device field at each step; kick_re/kick_im fill them in
+// for host-side planning).
+PushParams push_params(const vp_axis& x, const vp_axis& p, const vp_hamiltonian& H, double dt,
+                       double kick_re = 0.0, double kick_im = 0.0) {
+    const double hx = spacing(x), hp = spacing(p);
+    PushParams P{};
+    P.kind = H.kind;
+    P.nx = x.n;
+    P.np = p.n;
+    P.x_periodic = x.periodic ? 1 : 0;
+    P.x_lo = (float)x.lo;
+    P.hx = (float)hx;
+    P.p_lo = (float)p.lo;
+    P.hp = (float)hp;
+    if (H.kind == VP_H_SHO_EXACT) {
+        P.c = (float)cos(H.omega * dt);
+        P.s = (float)sin(H.omega * dt);
+        return P;
+    }
+    const double delta = H.kind == VP_H_FEL ? H.fel_delta : 0.0;
+    P.drift0 = (float)((delta + p.lo) * dt / hx);
+    P.drift1 = (float)(hp * dt / hx);
+    P.q0 = (float)(0.5 * dt * (delta + p.lo));
+    P.q1 = (float)(0.5 * dt * hp);
+    P.kd = H.kind == VP_H_FREE ? 0.0f : (float)(hp * dt / (2.0 * hx));
+    if (H.kind == VP_H_PENDULUM) P.beta = (float)(-H.a * dt / hp);
+    if (H.kind == VP_H_FEL) {
+        const double kick = -2.0 * dt / hp;
+        P.alpha = (float)(kick * kick_re);
+        P.beta = (float)(-kick * kick_im);
+    }
+    return P;
+}
+
+// Per-step tables of the push for step dt (FP64 on the host, stored FP32),
+// and the FP64 phase tables of the FEL bunching.
+int plan(vp_grid* g, double dt) {
+    const int nx = g->x.n, np = g->p.n;
+    const double hx = spacing(g->x), hp = spacing(g->p);
+    const vp_hamiltonian& H = g->ham;
+    std::vector<float4> tx(nx), tp(np);
+    std::vector<double2> ex(nx), eq(np);
+    g->inst.push = push_params(g->x, g->p, H, dt);
+    const double delta = H.kind == VP_H_FEL ? H.fel_delta : 0.0;
+    if (H.kind == VP_H_SHO_EXACT) {
+        const double th = H.omega * dt, c = cos(th), s = sin(th), cm1 = -2.0 * sin(0.5 * th) * sin(0.5 * th);
+        for (int i = 0; i < nx; ++i) {
+            double x = g->x.lo + i * hx;
+            float a, b, c2, d;
+            split(x * cm1 / hx, a, b);
+            split(-x * s / hp, c2, d);
+            tx[i] = make_float4(a, b, c2, d);
+        }
+        for (int j = 0; j < np; ++j) {
+            double p = g->p.lo + j * hp;
+            float a, b, c2, d;
+            split(p * s / hx, a, b);
+            split(p * cm1 / hp, c2, d);
+            tp[j] = make_float4(a, b, c2, d);
+        }
+        (void)c;
+    } else {
+        for (int i = 0; i < nx; ++i) {
+            double x = g->x.lo + i * hx;
+            tx[i] = make_float4((float)sin(x), (float)cos(x), 0.f, 0.f);
+            ex[i] = make_double2(cos(x), sin(x));
+        }
+        for (int j = 0; j < np; ++j) {
+            double v = delta + g->p.lo + j * hp;  // drift velocity of row j
+            double q = 0.5 * dt * v;
+            float a, b;
+            split(v * dt / hx, a, b);
+            tp[j] = make_float4(a, b, (float)sin(q), (float)cos(q));
+            eq[j] = make_double2(cos(q), sin(q));
+        }
+    }
+    VpInst& I = g->inst;
+    I.fel_kick = (float)(-2.0 * dt / hp);
+    I.fel_sigma2 = (float)H.fel_sigma2;
+    I.fel_dz = dt;
+    HIP_TRY(hipMemcpyAsync(g->at<float4>(g->L.tab_x), tx.data(), nx * sizeof(float4), hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipMemcpyAsync(g->at<float4>(g->L.tab_p), tp.data(), np * sizeof(float4), hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipMemcpyAsync(g->at<double2>(g->L.fel_ex), ex.data(), nx * sizeof(double2), hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipMemcpyAsync(g->at<double2>(g->L.fel_eq), eq.data(), np * sizeof(double2), hipMemcpyHostToDevice, g->stream));
+    int rc = upload_inst(g);  // synchronises, so the host vectors may go
+    if (rc) return rc;
+    g->plan_dt = dt;
+    g->plan_valid = true;
+    if (H.kind == VP_H_FEL) g->bunch_valid = false;
+    return VP_OK;
+}
+
+int launch_reduce_on(vp_grid* g, int mode, double dt) {
+    ReduceArgs R{};
+    R.w = g->at<float>(g->parity ? g->L.w1 : g->L.w0);
+    R.nx = g->x.n;
+    R.np = g->p.n;
+    R.kind = g->ham.kind;
+    R.mode = mode;
+    R.x_lo = g->x.lo;
+    R.hx = spacing(g->x);
+    R.p_lo = g->p.lo;
+    R.hp = spacing(g->p);
+    R.a = g->ham.a;
+    R.inv_n0 = g->N0 != 0.0 ? 1.0 / g->N0 : 0.0;
+    R.fel_ex = g->at<double2>(g->L.fel_ex);
+    R.fel_eq = g->at<double2>(g->L.fel_eq);
+    R.partials = g->at<double>(g->L.partials);
+    R.counter = g->at<uint32_t>(g->L.counters) + 1;
+    R.out = mode == 1 ? g->at<double>(g->L.fel_state) : g->at<double>(g->L.moments);
+    R.dz = dt;
+    HIP_TRY(launch_reduce(R, g->stream));
+    return VP_OK;
+}
+
+// Prepare a grid for stepping with dt: plan and, for the FEL, the bunching of
+// the current state at the half-drift phases of this dz.
+int prepare(vp_grid* g, double dt) {
+    if (!g->has_ham || !g->has_density)
+        return fail(VP_ESTATE, "set the Hamiltonian and the density before stepping");
+    if (!isfinite(dt)) return fail(VP_EINVAL, "dt must be finite");
+    if (!g->plan_valid || g->plan_dt != dt) {
+        int rc = plan(g, dt);
+        if (rc) return rc;
+    }
+    if (g->ham.kind == VP_H_FEL && !g->bunch_valid) {
+        int rc = launch_reduce_on(g, 1, dt);
+        if (rc) return rc;
+        g->bunch_valid = true;
+    }
+    return VP_OK;
+}
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, long>, vp_tiles> g_tune_cache;
+
+}  // namespace
+
+extern "C" {
+
+size_t vp_workspace_bytes(const vp_axis* x, const vp_axis* p) {
+    if (!axis_ok(x) || !axis_ok(p)) return 0;
+    return layout(x->n, p->n).total;
+}
+
+int vp_create_grid(const vp_grid_desc* d, vp_grid** out) {
+    if (!d || !out) return fail(VP_EINVAL, "null argument");
+    *out = nullptr;
+    if (!axis_ok(&d->x) || !axis_ok(&d->p)) return fail(VP_EINVAL, "invalid axis (need n >= 4, hi > lo, finite)");
+    if (d->p.periodic) return fail(VP_EUNSUPPORTED, "the momentum axis must be open");
+    Layout L = layout(d->x.n, d->p.n);
+    if (!d->workspace) return fail(VP_ENOMEM, "no workspace");
+    if (d->workspace_bytes < L.total)
+        return fail(VP_ENOMEM, "workspace of %zu bytes, need %zu", d->workspace_bytes, L.total);
+    if (reinterpret_cast<uintptr_t>(d->workspace) % 256)
+        return fail(VP_EINVAL, "workspace must be 256-byte aligned");
+    vp_grid* g = new vp_grid();
+    g->x = d->x;
+    g->p = d->p;
+    g->stream = reinterpret_cast<hipStream_t>(d->stream);
+    g->ws = reinterpret_cast<char*>(d->workspace);
+    g->L = L;
+    g->tiles = vp_tiles{128, 32, 64, 64};
+    g->list.stream = g->stream;
+    g->list.d_inst = g->at<VpInst>(L.inst);
+    g->list.d_off1 = g->at<int32_t>(L.off);
+    g->list.d_off2 = g->at<int32_t>(L.off) + 2;
+    VpInst& I = g->inst;
+    I.w[0] = g->at<float>(L.w0);
+    I.w[1] = g->at<float>(L.w1);
+    I.b = g->at<float>(L.b);
+    I.tab_x = g->at<float4>(L.tab_x);
+    I.tab_p = g->at<float4>(L.tab_p);
+    I.coef_x = g->at<float2>(L.coef_x);
+    I.coef_p = g->at<float2>(L.coef_p);
+    I.fel_ex = g->at<double2>(L.fel_ex);
+    I.fel_eq = g->at<double2>(L.fel_eq);
+    I.fel_state = g->at<double>(L.fel_state);
+    I.partials = g->at<double>(L.partials);
+    I.counters = g->at<uint32_t>(L.counters);
+    // LU coefficients of tridiag(1,4,1) on an open axis: d_0 = 4, m_k = 1/d_{k-1}, d_k = 4 - m_k
+    auto coefs = [](int n) {
+        std::vector<float2> c(n);
+        double dprev = 0.0;
+        for (int k = 0; k < n; ++k) {
+            double m = k == 0 ? 0.0 : 1.0 / dprev;
+            double dk = 4.0 - m;
+            c[k] = make_float2((float)m, (float)(1.0 / dk));
+            dprev = dk;
+        }
+        return c;
+    };
+    std::vector<float2> cx = coefs(d->x.n), cp = coefs(d->p.n);
+    // DC-exact gain: the FP32 interior coefficient m gives gain m/(1+m)^2 per axis
+    const double mf = (double)(float)(2.0 - sqrt(3.0));
+    const double S = pow((1.0 + mf) * (1.0 + mf) / mf, 2);
+    split(S, I.scale_hi, I.scale_lo);
+    std::vector<double> st(kFelStateLen, 0.0);
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpyAsync(g->at<float2>(L.coef_x), cx.data(), cx.size() * 8, hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->at<float2>(L.coef_p), cp.data(), cp.size() * 8, hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->at<double>(L.fel_state), st.data(), st.size() * 8, hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g->at<uint32_t>(L.counters), 0, 4 * sizeof(uint32_t), g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) {
+        delete g;
+        return fail(VP_EHIP, "grid initialisation: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return VP_OK;
+}
+
+int vp_destroy_grid(vp_grid* g) {
+    if (!g) return VP_OK;
+    if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
+    (void)hipStreamSynchronize(g->stream);
+    g->list.drop_graphs();
+    delete g;
+    return VP_OK;
+}
+
+int vp_set_hamiltonian(vp_grid* g, const vp_hamiltonian* h) {
+    if (!g || !h) return fail(VP_EINVAL, "null argument");
+    if (h->kind < VP_H_FREE || h->kind > VP_H_FEL) return fail(VP_EINVAL, "unknown Hamiltonian kind %d", h->kind);
+    if (!isfinite(h->a) || !isfinite(h->omega) || !isfinite(h->fel_delta) || !isfinite(h->fel_sigma2) ||
+        !isfinite(h->A_re) || !isfinite(h->A_im))
+        return fail(VP_EINVAL, "non-finite Hamiltonian parameter");
+    if (h->kind == VP_H_SHO_EXACT && g->x.periodic)
+        return fail(VP_EUNSUPPORTED, "the exact rotation needs an open x axis");
+    if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
+    g->ham = *h;
+    g->has_ham = true;
+    g->plan_valid = false;
+    g->bunch_valid = false;
+    if (h->kind == VP_H_FEL) {
+        double A[2] = {h->A_re, h->A_im};
+        HIP_TRY(hipMemcpyAsync(g->at<double>(g->L.fel_state) + kA, A, sizeof A, hipMemcpyHostToDevice, g->stream));
+        HIP_TRY(hipStreamSynchronize(g->stream));
+    }
+    return VP_OK;
+}
+
+int vp_set_density(vp_grid* g, const float* w, int32_t on_device) {
+    if (!g || !w) return fail(VP_EINVAL, "null argument");
+    if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
+    const size_t bytes = (size_t)g->x.n * g->p.n * sizeof(float);
+    float* dst = g->at<float>(g->parity ? g->L.w1 : g->L.w0);
+    HIP_TRY(hipMemcpyAsync(dst, w, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, g->stream));
+    int rc = launch_reduce_on(g, 0, 0.0);
+    if (rc) return rc;
+    double m[kMoments];
+    HIP_TRY(hipMemcpyAsync(m, g->at<double>(g->L.moments), sizeof m, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->N0 = m[0];
+    HIP_TRY(hipMemcpyAsync(g->at<double>(g->L.fel_state) + kN0, &g->N0, sizeof(double), hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->has_density = true;
+    g->bunch_valid = false;
+    g->step = 0;
+    return VP_OK;
+}
+
+int vp_get_density(vp_grid* g, float* w, int32_t on_device) {
+    if (!g || !w) return fail(VP_EINVAL, "null argument");
+    if (!g->has_density) return fail(VP_ESTATE, "no density set");
+    const size_t bytes = (size_t)g->x.n * g->p.n * sizeof(float);
+    HIP_TRY(hipMemcpyAsync(w, g->at<float>(g->parity ? g->L.w1 : g->L.w0), bytes,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return VP_OK;
+}
+
+int vp_step(vp_grid* g, double dt, int64_t nsteps) {
+    if (!g) return fail(VP_EINVAL, "null grid");
+    if (nsteps < 0) return fail(VP_EINVAL, "negative step count");
+    if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
+    int rc = prepare(g, dt);
+    if (rc) return rc;
+    if (nsteps == 0) return VP_OK;
+    rc = g->list.run(nsteps, g->parity, g->use_graph);
+    if (rc) return rc;
+    g->parity = (int)((g->parity + nsteps) & 1);
+    g->step += nsteps;
+    return VP_OK;
+}
+
+int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]) {
+    if (!g || !us) return fail(VP_EINVAL, "null argument");
+    if (nsteps <= 0) return fail(VP_EINVAL, "need at least one step");
+    if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
+    int rc = prepare(g, dt);
+    if (rc) return rc;
+    std::vector<hipEvent_t> ev(3 * nsteps);
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    const LaunchList& L = g->list;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const int par = (int)((g->parity + s) & 1);
+        HIP_TRY(hipEventRecord(ev[3 * s], g->stream));
+        HIP_TRY(launch_deposit(L.args(L.d_off1, L.total1, par), L.total1, L.lds1, g->stream));
+        HIP_TRY(hipEventRecord(ev[3 * s + 1], g->stream));
+        HIP_TRY(launch_solve(L.args(L.d_off2, L.total2, par), L.total2, L.lds2, g->stream));
+        HIP_TRY(hipEventRecord(ev[3 * s + 2], g->stream));
+    }
+    HIP_TRY(hipEventSynchronize(ev.back()));
+    double t0 = 0.0, t1 = 0.0;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        float a = 0.f, b = 0.f;
+        HIP_TRY(hipEventElapsedTime(&a, ev[3 * s], ev[3 * s + 1]));
+        HIP_TRY(hipEventElapsedTime(&b, ev[3 * s + 1], ev[3 * s + 2]));
+        t0 += a;
+        t1 += b;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    us[0] = 1000.0 * t0 / nsteps;
+    us[1] = 1000.0 * t1 / nsteps;
+    g->parity = (int)((g->parity + nsteps) & 1);
+    g->step += nsteps;
+    return VP_OK;
+}
+
+int vp_moments(vp_grid* g, vp_moments_t* out) {
+    if (!g || !out) return fail(VP_EINVAL, "null argument");
+    if (!g->has_density) return fail(VP_ESTATE, "no density set");
+    int rc = launch_reduce_on(g, 0, 0.0);
+    if (rc) return rc;
+    double m[kMoments], st[kFelStateLen];
+    HIP_TRY(hipMemcpyAsync(m, g->at<double>(g->L.moments), sizeof m, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipMemcpyAsync(st, g->at<double>(g->L.fel_state), sizeof st, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    const double cell = spacing(g->x) * spacing(g->p);
+    memset(out, 0, sizeof *out);
+    out->sum_w = m[0];
+    out->mass = cell * m[0];
+    out->neg_mass = -cell * m[1];
+    out->l1 = cell * m[2];
+    out->entropy = -cell * m[3];
+    out->mean_p = m[0] != 0.0 ? m[4] / m[0] : 0.0;
+    out->energy = cell * m[5];
+    out->step = g->step;
+    out->nonfinite = (int64_t)m[9];
+    if (g->has_ham && g->ham.kind == VP_H_FEL) {
+        const double n0 = g->N0 != 0.0 ? g->N0 : 1.0;
+        out->A_re = st[kA];
+        out->A_im = st[kA + 1];
+        out->bunch_re = m[6] / n0;
+        out->bunch_im = m[7] / n0;
+        out->fel_invariant = st[kA] * st[kA] + st[kA + 1] * st[kA + 1] + m[4] / n0;
+    }
+    if (out->nonfinite) return fail(VP_ENONFINITE, "%lld non-finite weights", (long long)out->nonfinite);
+    return VP_OK;
+}
+
+int vp_set_tiles(vp_grid* g, const vp_tiles* t) {
+    if (!g || !t) return fail(VP_EINVAL, "null argument");
+    if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
+    vp_tiles n = g->tiles;
+    if (t->k1_tx) n.k1_tx = t->k1_tx;
+    if (t->k1_ty) n.k1_ty = t->k1_ty;
+    if (t->k2_tx) n.k2_tx = t->k2_tx;
+    if (t->k2_ty) n.k2_ty = t->k2_ty;
+    int rc = validate_tiles(g, n);
+    if (rc) return rc;
+    g->tiles = n;
+    g->plan_valid = false;
+    return VP_OK;
+}
+
+int vp_get_tiles(const vp_grid* g, vp_tiles* t) {
+    if (!g || !t) return fail(VP_EINVAL, "null argument");
+    *t = g->tiles;
+    return VP_OK;
+}
+
+int vp_set_launch(vp_grid* g, int32_t use_graph) {
+    if (!g) return fail(VP_EINVAL, "null grid");
+    g->use_graph = use_graph != 0;
+    return VP_OK;
+}
+
+int vp_autotune(vp_grid* g, double dt, double* best_us) {
+    if (!g) return fail(VP_EINVAL, "null grid");
+    if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
+    int rc = prepare(g, dt);
+    if (rc) return rc;
+    const double hx = spacing(g->x), hp = spacing(g->p);
+    const long disp = lround(fabs(dt) * (std::max(fabs(g->p.lo), fabs(g->p.hi)) / hx + fabs(g->ham.a) / hp));
+    const auto key = std::make_tuple((int)g->ham.kind, g->x.n, g->p.n, disp);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end() && !best_us) {
+            g->tiles = it->second;
+            g->plan_valid = false;
+            return prepare(g, dt);
+        }
+    }
+    // save the state (weights, FEL scalars, parity, step) to restore afterwards
+    const size_t n = (size_t)g->x.n * g->p.n;
+    std::vector<float> saved(n);
+    std::vector<double> saved_st(kFelStateLen);
+    HIP_TRY(hipMemcpyAsync(saved.data(), g->at<float>(g->parity ? g->L.w1 : g->L.w0), n * 4, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipMemcpyAsync(saved_st.data(), g->at<double>(g->L.fel_state), kFelStateLen * 8, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    const int saved_parity = g->parity;
+    const int64_t saved_step = g->step;
+    const bool saved_graph = g->use_graph;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    auto time_tiles = [&](const vp_tiles& t, float* us) -> int {
+        if (validate_tiles(g, t)) return VP_EINVAL;
+        g->tiles = t;
+        g->plan_valid = false;
+        int r = prepare(g, dt);
+        if (r) return r;
+        const int reps = 8;
+        r = g->list.run(2, g->parity, false);
+        if (r) return r;
+        HIP_TRY(hipEventRecord(e0, g->stream));
+        r = g->list.run(reps, g->parity, false);
+        if (r) return r;
+        HIP_TRY(hipEventRecord(e1, g->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        *us = 1000.f * ms / reps;
+        return VP_OK;
+    };
+    const int k1c[][2] = {{64, 16}, {64, 32}, {128, 16}, {128, 32}, {128, 64}, {256, 16}, {256, 32}};
+    const int k2c[][2] = {{32, 64}, {64, 32}, {64, 64}, {128, 32}, {128, 64}, {96, 96}};
+    vp_tiles best = g->tiles;
+    float best_t = 1e30f;
+    for (auto& c : k1c) {
+        vp_tiles t = best;
+        t.k1_tx = c[0];
+        t.k1_ty = c[1];
+        float us;
+        if (time_tiles(t, &us) == VP_OK && us < best_t) { best_t = us; best = t; }
+    }
+    for (auto& c : k2c) {
+        vp_tiles t = best;
+        t.k2_tx = c[0];
+        t.k2_ty = c[1];
+        float us;
+        if (time_tiles(t, &us) == VP_OK && us < best_t) { best_t = us; best = t; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g->tiles = best;
+    g->plan_valid = false;
+    g->parity = saved_parity;
+    g->step = saved_step;
+    g->use_graph = saved_graph;
+    HIP_TRY(hipMemcpyAsync(g->at<float>(g->parity ? g->L.w1 : g->L.w0), saved.data(), n * 4, hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipMemcpyAsync(g->at<double>(g->L.fel_state), saved_st.data(), kFelStateLen * 8, hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->bunch_valid = false;
+    rc = prepare(g, dt);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    if (best_us) *best_us = best_t;
+    return VP_OK;
+}
+
+int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch** out) {
+    if (!grids || !dt || !out || n <= 0) return fail(VP_EINVAL, "invalid batch arguments");
+    *out = nullptr;
+    hipStream_t s = grids[0] ? grids[0]->stream : nullptr;
+    for (int k = 0; k < n; ++k) {
+        if (!grids[k]) return fail(VP_EINVAL, "null grid %d", k);
+        if (grids[k]->in_batch) return fail(VP_ESTATE, "grid %d already belongs to a batch", k);
+        for (int q = 0; q < k; ++q)
+            if (grids[q] == grids[k]) return fail(VP_EINVAL, "grid %d listed twice", k);
+    }
+    for (int k = 0; k < n; ++k) {
+        int rc = prepare(grids[k], dt[k]);
+        if (rc) return rc;
+        HIP_TRY(hipStreamSynchronize(grids[k]->stream));
+    }
+    std::vector<VpInst> insts(n);
+    std::vector<int32_t> off1(n + 1, 0), off2(n + 1, 0);
+    size_t lds1 = 0, lds2 = 0;
+    for (int k = 0; k < n; ++k) {
+        insts[k] = grids[k]->inst;
+        insts[k].parity0 = grids[k]->parity;
+        off1[k + 1] = off1[k] + insts[k].k1_tiles;
+        off2[k + 1] = off2[k] + insts[k].k2_tiles;
+        lds1 = std::max(lds1, deposit_lds_bytes(insts[k].k1_tx, insts[k].k1_ty));
+        lds2 = std::max(lds2, solve_lds_bytes(insts[k].k2_tx, insts[k].k2_ty));
+    }
+    vp_batch* b = new vp_batch();
+    b->grids.assign(grids, grids + n);
+    LaunchList& L = b->list;
+    L.stream = s;
+    L.ninst = n;
+    L.total1 = off1[n];
+    L.total2 = off2[n];
+    L.lds1 = lds1;
+    L.lds2 = lds2;
+    hipError_t e = hipMalloc(&L.d_inst, sizeof(VpInst) * n);
+    if (e == hipSuccess) e = hipMalloc(&L.d_off1, sizeof(int32_t) * (n + 1));
+    if (e == hipSuccess) e = hipMalloc(&L.d_off2, sizeof(int32_t) * (n + 1));
+    if (e == hipSuccess) e = hipMemcpyAsync(L.d_inst, insts.data(), sizeof(VpInst) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.d_off1, off1.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.d_off2, off2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(L.d_inst);
+        (void)hipFree(L.d_off1);
+        (void)hipFree(L.d_off2);
+        delete b;
+        return fail(VP_EHIP, "batch setup: %s", hipGetErrorString(e));
+    }
+    for (auto* g : b->grids) g->in_batch = true;
+    *out = b;
+    return VP_OK;
+}
+
+int vp_batch_step(vp_batch* b, int64_t nsteps) {
+    if (!b) return fail(VP_EINVAL, "null batch");
+    if (nsteps < 0) return fail(VP_EINVAL, "negative step count");
+    if (nsteps == 0) return VP_OK;
+    int rc = b->list.run(nsteps, (int)(b->steps_done & 1), true);
+    if (rc) return rc;
+    b->steps_done += nsteps;
+    for (auto* g : b->grids) {
+        g->parity = (int)((g->parity + nsteps) & 1);
+        g->step += nsteps;
+    }
+    return VP_OK;
+}
+
+int vp_batch_destroy(vp_batch* b) {
+    if (!b) return VP_OK;
+    (void)hipStreamSynchronize(b->list.stream);
+    b->list.drop_graphs();
+    (void)hipFree(b->list.d_inst);
+    (void)hipFree(b->list.d_off1);
+    (void)hipFree(b->list.d_off2);
+    for (auto* g : b->grids) g->in_batch = false;
+    delete b;
+    return VP_OK;
+}
+
+const char* vp_status_string(int s) {
+    switch (s) {
+    case VP_OK: return "ok";
+    case VP_EINVAL: return "invalid argument";
+    case VP_ENOMEM: return "workspace missing or too small";
+    case VP_ESTATE: return "call out of order";
+    case VP_EHIP: return "HIP runtime error";
+    case VP_EUNSUPPORTED: return "unsupported configuration";
+    case VP_ENONFINITE: return "non-finite state";
+    default: return "unknown status";
+    }
+}
+
+const char* vp_last_error(void) { return g_err; }
+
+int vp_plan_source_box(const vp_axis* x, const vp_axis* p, const vp_hamiltonian* h, double dt, double kick_re,
+                       double kick_im, int32_t bx0, int32_t bx1, int32_t by0, int32_t by1, int32_t box[4]) {
+    if (!axis_ok(x) || !axis_ok(p) || !h || !box) return fail(VP_EINVAL, "invalid argument");
+    PushParams P = push_params(*x, *p, *h, dt, kick_re, kick_im);
+    int b[4];
+    source_box(P, bx0, bx1, by0, by1, b);
+    for (int k = 0; k < 4; ++k) box[k] = b[k];
+    return VP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,227 @@
+// vp_internal.h -- data layout shared by the host runtime and the gfx950 kernels of libvp.
+//
+// One step of the method (Edelen & Webb, Sec. "An Algorithm Based on Phase
+// Space Density Conservation", eqs. 6-10) runs as two kernels:
+//   k_deposit: every lattice node is pushed (its position is its index, so
+//              nothing but w is read) and its weight is scattered onto the
+//              4x4 lattice taps of its moved tent with cubic B-spline weights
+//              (the tent-tent overlap of eq. 9).  A workgroup owns one
+//              destination tile held in LDS and scans the box of source nodes
+//              that can reach it; the tile is written to b once.
+//   k_solve:   w_out = (M_x^{-1} (x) M_p^{-1}) b, the tent mass matrix of eq. 8,
+//              M = tridiag(1/6, 2/3, 1/6), cyclic on a periodic axis.  A
+//              workgroup solves an LDS tile plus a 16-node halo per side with
+//              the LU recursions of M; the halo makes the tile independent of
+//              its neighbours to within (2-sqrt 3)^16 ~ 7e-10.  For the FEL its
+//              epilogue also forms the FP64 bunching of the new state.
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#ifndef __HIP_DEVICE_COMPILE__
+#include <cmath>
+#endif
+
+namespace vp {
+
+enum Kind : int32_t { kFree = 0, kSho = 1, kPendulum = 2, kFel = 3 };
+
+constexpr int kHalo = 16;         // warm-up nodes on each side of a solve tile
+constexpr int kPad = 4;           // trash border of a deposit tile (per side)
+constexpr int kFixBits = 57;      // deposit tile sums: fixed point at 2^-57 of the box's max|w|
+constexpr int kDepositThreads = 256;
+constexpr int kSolveThreads = 256;
+constexpr int kReduceBlocks = 256;
+constexpr int kReduceThreads = 256;
+constexpr int kMoments = 10;      // FP64 sums produced by the reduction kernel
+
+// Parameters of the push in cell units and of the source-box bound.
+//  FREE / PENDULUM / FEL: node (i, j) moves by
+//     dv = alpha cos(phi_i + q_j) + beta sin(phi_i + q_j)
+//     du = drift_j + kd * dv
+//  with phi_i = x_lo + i hx, q_j = q0 + j q1, drift_j = drift0 + j drift1.
+//  SHO: (x, p) -> (x c + p s, -x s + p c).
+struct PushParams {
+    int32_t kind;
+    int32_t nx, np, x_periodic;
+    float x_lo, hx, p_lo, hp;
+    float drift0, drift1;
+    float q0, q1;
+    float alpha, beta;
+    float kd;
+    float c, s;
+};
+
+__host__ __device__ inline float vp_floor(float v) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return floorf(v);
+#else
+    return std::floor(v);
+#endif
+}
+__host__ __device__ inline float vp_sin(float v) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return sinf(v);
+#else
+    return std::sin(v);
+#endif
+}
+
+// Range [lo, hi] of sin over the interval [a, b], a <= b.
+__host__ __device__ inline void sin_range(float a, float b, float* lo, float* hi) {
+    const float two_pi = 6.28318530717958647f, half_pi = 1.57079632679489662f;
+    if (!(b - a < two_pi)) {
+        *lo = -1.0f;
+        *hi = 1.0f;
+        return;
+    }
+    float sa = vp_sin(a), sb = vp_sin(b);
+    float l = sa < sb ? sa : sb, h = sa < sb ? sb : sa;
+    float kmax = vp_floor((b - half_pi) / two_pi);  // largest k with pi/2 + 2k pi <= b
+    if (half_pi + two_pi * kmax >= a) h = 1.0f;
+    float kmin = vp_floor((b + half_pi) / two_pi);  // largest k with -pi/2 + 2k pi <= b
+    if (-half_pi + two_pi * kmin >= a) l = -1.0f;
+    // guard against rounding of the endpoint values
+    *lo = l - 1e-6f;
+    *hi = h + 1e-6f;
+}
+
+__host__ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+__host__ __device__ inline int ifloor(float v) { return (int)vp_floor(v); }
+__host__ __device__ inline int iceil(float v) { return -(int)vp_floor(-v); }
+
+// Box of source nodes [x0,x1) x [y0,y1) (columns unwrapped on a periodic axis)
+// whose moved tents can deposit into destination columns [bx0,bx1) and rows
+// [by0,by1).  A node at cell position (u, v) touches columns floor(u)-1 ..
+// floor(u)+2, so it reaches the tile only if u in [bx0-2, bx1+1) and
+// v in [by0-2, by1+1); one more cell of margin absorbs rounding.  The
+// displacement is bounded by interval arithmetic over the candidate box, then
+// the bound is tightened once with the phase range of that box.
+__host__ __device__ inline void source_box(const PushParams& P, int bx0, int bx1, int by0, int by1,
+                                           int box[4]) {
+    const float ulo = (float)bx0 - 3.0f, uhi = (float)bx1 + 2.0f;
+    const float vlo = (float)by0 - 3.0f, vhi = (float)by1 + 2.0f;
+    int x0, x1, y0, y1;
+    if (P.kind == kSho) {
+        // preimage of the dest rectangle under the rotation: rotate its corners back
+        float X[2] = {P.x_lo + ulo * P.hx, P.x_lo + uhi * P.hx};
+        float Pm[2] = {P.p_lo + vlo * P.hp, P.p_lo + vhi * P.hp};
+        float xmn = 3.4e38f, xmx = -3.4e38f, pmn = 3.4e38f, pmx = -3.4e38f;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                float x = X[a] * P.c - Pm[b] * P.s, p = X[a] * P.s + Pm[b] * P.c;
+                xmn = x < xmn ? x : xmn;
+                xmx = x > xmx ? x : xmx;
+                pmn = p < pmn ? p : pmn;
+                pmx = p > pmx ? p : pmx;
+            }
+        x0 = ifloor((xmn - P.x_lo) / P.hx) - 1;
+        x1 = iceil((xmx - P.x_lo) / P.hx) + 2;
+        y0 = ifloor((pmn - P.p_lo) / P.hp) - 1;
+        y1 = iceil((pmx - P.p_lo) / P.hp) + 2;
+    } else {
+        float R = P.kind == kFree ? 0.0f : sqrtf(P.alpha * P.alpha + P.beta * P.beta);
+        float dvmin = -R, dvmax = R;
+        x0 = x1 = y0 = y1 = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            y0 = ifloor(vlo - dvmax) - 1;
+            y1 = iceil(vhi - dvmin) + 1;
+            y0 = y0 < 0 ? 0 : y0;
+            y1 = y1 > P.np ? P.np : y1;
+            if (y1 <= y0) break;
+            float da = P.drift0 + (float)y0 * P.drift1, db = P.drift0 + (float)(y1 - 1) * P.drift1;
+            float dmin = da < db ? da : db, dmax = da < db ? db : da;
+            float va = dvmax > -dvmin ? dvmax : -dvmin;
+            float kk = P.kd < 0 ? -P.kd : P.kd;
+            float umin = dmin - kk * va, umax = dmax + kk * va;
+            x0 = ifloor(ulo - umax) - 1;
+            x1 = iceil(uhi - umin) + 1;
+            if (pass == 1 || R == 0.0f) break;
+            // tighten dv with the phase range phi + q over the candidate box
+            float qa = P.q0 + (float)y0 * P.q1, qb = P.q0 + (float)(y1 - 1) * P.q1;
+            float qmin = qa < qb ? qa : qb, qmax = qa < qb ? qb : qa;
+            float th0 = atan2f(P.alpha, P.beta);  // dv = R sin(phi + q + th0)
+            float pa = P.x_lo + (float)x0 * P.hx + qmin + th0;
+            float pb = P.x_lo + (float)(x1 - 1) * P.hx + qmax + th0;
+            float slo, shi;
+            sin_range(pa, pb, &slo, &shi);
+            dvmin = R * slo;
+            dvmax = R * shi;
+        }
+    }
+    if (!P.x_periodic) {
+        x0 = x0 < 0 ? 0 : x0;
+        x1 = x1 > P.nx ? P.nx : x1;
+    }
+    y0 = y0 < 0 ? 0 : y0;
+    y1 = y1 > P.np ? P.np : y1;
+    if (x1 < x0) x1 = x0;
+    if (y1 < y0) y1 = y0;
+    box[0] = x0;
+    box[1] = x1;
+    box[2] = y0;
+    box[3] = y1;
+}
+
+// One grid instance as the kernels see it.  A single grid is a batch of one.
+struct VpInst {
+    PushParams push;
+    int32_t k1_tx, k1_ty, k1_tiles_x, k1_tiles;
+    int32_t k2_tx, k2_ty, k2_tiles_x, k2_tiles;
+    int32_t parity0;         // index of the current state buffer when the launch list was built
+    int32_t pad0;
+    float scale_hi, scale_lo;  // DC-exact gain of the two solves, hi + lo
+    float fel_kick;            // -2 dz / h_eta (cells per unit field)
+    float fel_sigma2;
+    double fel_dz;
+    float* w[2];
+    float* b;
+    const float4* tab_x;     // per column push table
+    const float4* tab_p;     // per row push table
+    const float2* coef_x;    // (m_i, 1/d_i) of the LU of tridiag(1,4,1), open x only
+    const float2* coef_p;    // same along p (always open)
+    const double2* fel_ex;   // (cos phi_i, sin phi_i)
+    const double2* fel_eq;   // (cos q_j, sin q_j), q_j the half drift of row j
+    double* fel_state;       // [A_re, A_im, b_re, b_im, N0, dz_b, ...]
+    double* partials;        // per solve tile: bunching partial (re, im)
+    uint32_t* counters;      // [0]: solve epilogue
+};
+
+// fel_state slots
+enum { kA = 0, kBn = 2, kN0 = 4, kDzB = 5, kFelStateLen = 16 };
+
+struct LaunchArgs {
+    const VpInst* inst;
+    const int32_t* off;  // [ninst+1] exclusive prefix of tile counts
+    int32_t ninst;
+    int32_t total;
+    int32_t parity;      // step parity relative to each instance's parity0
+};
+
+struct ReduceArgs {
+    const float* w;
+    int32_t nx, np, kind, mode;   // mode 0: moments, 1: FEL bunching
+    double x_lo, hx, p_lo, hp, a;
+    double inv_n0;
+    const double2* fel_ex;
+    const double2* fel_eq;
+    double* partials;             // [kReduceBlocks][kMoments]
+    uint32_t* counter;
+    double* out;                  // moments: [kMoments]; bunching: fel_state
+    double dz;
+};
+
+// launchers (vp_kernels.hip)
+hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t launch_solve(const LaunchArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+const void* deposit_kernel();
+const void* solve_kernel();
+
+inline size_t deposit_lds_bytes(int tx, int ty) { return sizeof(int64_t) * (size_t)(tx + 2 * kPad) * (ty + 2 * kPad); }
+__host__ __device__ inline int solve_ldw(int tx) { int w = tx + 2 * kHalo; return (w & 1) ? w : w + 1; }
+inline size_t solve_lds_bytes(int tx, int ty) { return sizeof(float) * (size_t)solve_ldw(tx) * (ty + 2 * kHalo); }
+
+}  // namespace vp

@@ -1,0 +1,67 @@
+"""Write the oracle's results of the full-length workloads (too slow to recompute
+inside a test) as strided samples.  Calls only the FP64 oracle and the seeded
+input generators.
+
+    python tests/golden/make_full_runs.py [--only NAME]
+
+For each workload it stores, at the recorded steps: a strided sample of the
+FP64 state (float64), the full-array sum and L1 norm, the FEL field, and the
+relative L1 distance of the FP32-state run (state rounded to float after every
+step) from the FP64 run: the floor any implementation with FP32 state reaches.
+"""
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+from paper_2007_12227_amd.inputs import fel_gaussian, pendulum_band, pendulum_gaussian  # noqa: E402
+
+WORKLOADS = {
+    # name: (instance factory, checkpoints, sample stride)
+    "pendulum_gaussian_128": (lambda: pendulum_gaussian(128), (1, 100, 200), 1),
+    "pendulum_band_2048": (lambda: pendulum_band(2048), (1, 500, 1000), 8),
+    "fel_gaussian_1024": (lambda: fel_gaussian(1024), (1, 500, 1000, 1500, 2000), 4),
+}
+
+
+def run(name):
+    make, checkpoints, stride = WORKLOADS[name]
+    inst = make()
+    out = {"steps": np.array(checkpoints), "stride": np.array(stride)}
+    w64 = inst.w0.copy()
+    w32 = inst.w0.astype(np.float32).astype(np.float64)
+    w64 = w32.copy()  # both runs start from the FP32 input the GPU receives
+    A64 = A32 = complex(inst.ham.A_re, inst.ham.A_im)
+    N0 = w32.sum()
+    done = 0
+    t0 = time.time()
+    for s in checkpoints:
+        r64 = oracle.run(inst.x, inst.p, inst.ham, w64, inst.dt, s - done, A0=A64, N0=N0)
+        r32 = oracle.run(inst.x, inst.p, inst.ham, w32, inst.dt, s - done, A0=A32, N0=N0,
+                         round_fp32=True)
+        w64, A64, w32, A32 = r64.w, r64.A, r32.w, r32.A
+        done = s
+        out[f"sample_{s}"] = w64[::stride, ::stride].copy()
+        out[f"sum_{s}"] = np.array(w64.sum())
+        out[f"l1_{s}"] = np.array(np.abs(w64).sum())
+        out[f"A_{s}"] = np.array([A64.real, A64.imag])
+        out[f"fp32_floor_{s}"] = np.array(oracle.rel_l1(w32, w64))
+        out[f"fp32_floor_w0_{s}"] = np.array(np.abs(w32 - w64).sum() / np.abs(inst.w0).sum())
+        print(f"{name}: step {s} floor {float(out[f'fp32_floor_{s}']):.3e} "
+              f"({time.time() - t0:.0f}s)", flush=True)
+    np.savez_compressed(os.path.join(HERE, f"oracle_{name}.npz"), **out)
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--only", default=None)
+    args = ap.parse_args()
+    for name in WORKLOADS:
+        if args.only in (None, name):
+            run(name)

@@ -1,0 +1,133 @@
+"""Host-side tests of the C interface: symbols, validation, planning.  No GPU."""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_12227_amd import binding as B
+from paper_2007_12227_amd.inputs import (H_FEL, H_FREE, H_PENDULUM, H_SHO_EXACT, Axis, Hamiltonian,
+                                         fel_axes, pendulum_axes, rng)
+
+
+@pytest.fixture(scope="module")
+def L():
+    return B.lib()
+
+
+def test_library_exports_every_declared_symbol(L):
+    names = B.declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_workspace_bytes(L):
+    x, p = pendulum_axes(128)
+    n1 = B.workspace_bytes(x, p)
+    assert n1 >= 3 * 128 * 128 * 4
+    assert B.workspace_bytes(*pendulum_axes(256)) > n1
+    assert L.vp_workspace_bytes(C.byref(B.Axis(0, 1, 3, 1)), C.byref(B.axis(p))) == 0
+    assert L.vp_workspace_bytes(C.byref(B.Axis(1, 0, 16, 1)), C.byref(B.axis(p))) == 0
+    assert L.vp_workspace_bytes(None, C.byref(B.axis(p))) == 0
+
+
+def _create(L, x, p, ws, nbytes):
+    desc = B.GridDesc(x, p, C.c_void_p(ws), nbytes, None)
+    h = C.c_void_p()
+    return L.vp_create_grid(C.byref(desc), C.byref(h)), h
+
+
+def test_create_grid_validation(L):
+    x, p = pendulum_axes(64)
+    need = B.workspace_bytes(x, p)
+    assert L.vp_create_grid(None, None) == B.VP_EINVAL
+    assert _create(L, B.Axis(0, 1, 2, 1), B.axis(p), 256, need)[0] == B.VP_EINVAL
+    assert _create(L, B.axis(x), B.Axis(-1, 1, 64, 1), 256, need)[0] == B.VP_EUNSUPPORTED
+    assert _create(L, B.axis(x), B.axis(p), 0, need)[0] == B.VP_ENOMEM
+    assert _create(L, B.axis(x), B.axis(p), 256, need - 1)[0] == B.VP_ENOMEM
+    assert _create(L, B.axis(x), B.axis(p), 258, need)[0] == B.VP_EINVAL
+    assert b"256-byte" in L.vp_last_error()
+
+
+def test_null_handles(L):
+    assert L.vp_destroy_grid(None) == B.VP_OK
+    assert L.vp_batch_destroy(None) == B.VP_OK
+    assert L.vp_step(None, 0.1, 1) == B.VP_EINVAL
+    assert L.vp_moments(None, None) == B.VP_EINVAL
+    assert L.vp_set_hamiltonian(None, None) == B.VP_EINVAL
+    assert L.vp_batch_step(None, 1) == B.VP_EINVAL
+    assert L.vp_batch_create(None, 0, None, None) == B.VP_EINVAL
+
+
+def test_status_strings(L):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.vp_status_string(code)
+    assert L.vp_status_string(-99) == b"unknown status"
+
+
+# ---- the deposit tile's source box: every node that reaches the tile is in it ----
+
+def _check_box(x, p, ham, dt, kick, tile, box):
+    du, dv = oracle.push(x, p, ham, dt, None if kick is None else np.array([kick.real, kick.imag]))
+    bx0, bx1, by0, by1 = tile
+    x0, x1, y0, y1 = box
+    j, i = np.meshgrid(np.arange(p.n), np.arange(x.n), indexing="ij")
+    u = i + du
+    v = j + dv
+    ku, kv = np.floor(u), np.floor(v)
+    row_hit = (kv >= by0 - 2) & (kv <= by1)
+    shifts = range(-3, 4) if x.periodic else (0,)
+    for m in shifts:
+        col_hit = (ku + m * x.n >= bx0 - 2) & (ku + m * x.n <= bx1)
+        hit = row_hit & col_hit
+        ii = i[hit] + m * x.n
+        jj = j[hit]
+        assert np.all((ii >= x0) & (ii < x1)), (tile, box, ii.min(), ii.max())
+        assert np.all((jj >= y0) & (jj < y1)), (tile, box, jj.min(), jj.max())
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_source_box_contains_every_reaching_node(seed):
+    g = rng(100 + seed)
+    for _ in range(12):
+        kind = [H_FREE, H_PENDULUM, H_FEL, H_SHO_EXACT][g.integers(0, 4)]
+        n = int(g.integers(16, 160))
+        kick = None
+        if kind == H_SHO_EXACT:
+            half = 3.0
+            x = Axis(-half, half, n, False)
+            p = Axis(-half, half, int(g.integers(16, 160)), False)
+            ham = Hamiltonian(kind, omega=1.0)
+            dt = g.uniform(-math.pi, math.pi)
+        elif kind == H_FEL:
+            x, p = fel_axes(n, int(g.integers(16, 160)))
+            ham = Hamiltonian(kind)
+            dt = g.uniform(0.005, 0.05)
+            kick = complex(*g.uniform(-0.6, 0.6, 2))
+        else:
+            x, p = pendulum_axes(n, int(g.integers(16, 160)))
+            ham = Hamiltonian(kind, a=g.uniform(0.3, 2.5))
+            dt = g.uniform(0.005, 0.2)
+        tx = int(g.integers(8, max(9, x.n)))
+        ty = int(g.integers(1, max(2, p.n // 2)))
+        bx0 = int(g.integers(0, x.n)) // tx * tx
+        by0 = int(g.integers(0, p.n)) // ty * ty
+        tile = (bx0, min(bx0 + tx, x.n), by0, min(by0 + ty, p.n))
+        box = B.plan_source_box(x, p, ham, dt, kick if kick is not None else 0j, tile[:2], tile[2:])
+        _check_box(x, p, ham, dt, kick, tile, box)
+
+
+def test_source_box_is_tight_for_smooth_pendulum():
+    """The box is the tile shifted by the local displacement, not widened by the
+    global maximum: for the 2048^2 pendulum at dt 0.02 a 128x32 tile scans
+    under 1.6x its own area."""
+    x, p = pendulum_axes(2048)
+    ham = Hamiltonian(H_PENDULUM, a=1.0)
+    worst = 0.0
+    for by0 in range(0, 2048, 32 * 9):
+        for bx0 in range(0, 2048, 128 * 3):
+            x0, x1, y0, y1 = B.plan_source_box(x, p, ham, 0.02, 0j, (bx0, bx0 + 128), (by0, by0 + 32))
+            worst = max(worst, (x1 - x0) * (y1 - y0) / (128 * 32))
+    assert worst < 1.6

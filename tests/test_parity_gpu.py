@@ -1,0 +1,179 @@
+"""GPU (HIP, FP32) vs the FP64 oracle on the same seeded inputs, through the C interface.
+
+Bars: relative L1 <= 1e-5 after one step from the same weights, <= 1e-4 after
+a full run (the precision the method is asked to hold in FP32).  Inputs span
+several tiles with ragged tails; tile shapes are varied to cover every edge
+of the tiling.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_12227_amd.inputs import (H_FEL, H_FREE, H_PENDULUM, H_SHO_EXACT, Axis, Hamiltonian,
+                                         fel_gaussian, gaussian, pendulum_axes, pendulum_band,
+                                         pendulum_gaussian, rng)
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2007_12227_amd import binding
+    binding.lib()
+    return binding
+
+
+def gpu_run(B, x, p, ham, w0, dt, steps, tiles=None, graph=True):
+    g = B.Grid(x, p)
+    if tiles:
+        g.set_tiles(*tiles)
+    g.set_launch(graph)
+    g.set_hamiltonian(ham)
+    g.set_density(w0)
+    g.step(dt, steps)
+    out = g.density().astype(np.float64)
+    m = g.moments()
+    g.close()
+    return out, m
+
+
+def one_step_ref(x, p, ham, w32, dt):
+    return oracle.run(x, p, ham, w32.astype(np.float64), dt, 1).w
+
+
+TILINGS = [None, ((64, 16), (32, 32)), ((24, 5), (40, 24)), ((200, 24), (120, 56))]
+
+
+@pytest.mark.parametrize("tiles", TILINGS)
+def test_one_step_pendulum_ragged(B, tiles):
+    x, p = pendulum_axes(200, 150)
+    w = (gaussian(x, p, 0.3, 0.8, 0.5) + 1e-3 * rng(31).random((150, 200))).astype(np.float32)
+    ham = Hamiltonian(H_PENDULUM, a=1.3)
+    got, _ = gpu_run(B, x, p, ham, w, 0.07, 1, tiles)
+    ref = one_step_ref(x, p, ham, w, 0.07)
+    assert oracle.rel_l1(got, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("kind", [H_FREE, H_PENDULUM, H_SHO_EXACT, H_FEL])
+def test_one_step_each_kind(B, kind):
+    if kind == H_SHO_EXACT:
+        x, p = Axis(-4, 4, 130, False), Axis(-4, 4, 97, False)
+        ham = Hamiltonian(kind, omega=1.0)
+        dt = 0.4
+        w = gaussian(x, p, 1.0, -0.5, 0.6)
+    elif kind == H_FEL:
+        inst = fel_gaussian(96, 1, npp=160)
+        x, p, dt, w = inst.x, inst.p, inst.dt, inst.w0
+        ham = Hamiltonian(kind, A_re=0.02, A_im=-0.01)
+    else:
+        x, p = pendulum_axes(144, 100)
+        ham = Hamiltonian(kind, a=0.9)
+        dt = 0.13
+        w = gaussian(x, p, -1.0, 0.5, 0.5) + 1e-3 * rng(32).random((p.n, x.n))
+    w = w.astype(np.float32)
+    got, _ = gpu_run(B, x, p, ham, w, dt, 1, ((64, 16), (64, 32)))
+    if kind == H_FEL:
+        A0 = complex(ham.A_re, ham.A_im)
+        ref = oracle.run(x, p, ham, w.astype(np.float64), dt, 1, A0=A0).w
+    else:
+        ref = one_step_ref(x, p, ham, w, dt)
+    assert oracle.rel_l1(got, ref) <= 1e-5
+
+
+def test_full_run_pendulum_gaussian_128(B):
+    inst = pendulum_gaussian(128)
+    w32 = inst.w0.astype(np.float32)
+    got, m = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, inst.steps)
+    ref = oracle.run(inst.x, inst.p, inst.ham, w32.astype(np.float64), inst.dt, inst.steps).w
+    err = oracle.rel_l1(got, ref)
+    print(f"pendulum_gaussian_128 200 steps: rel L1 {err:.3e}")
+    assert err <= 1e-4
+    assert m["step"] == inst.steps
+
+
+def test_graph_and_plain_launches_agree(B):
+    inst = pendulum_gaussian(128)
+    w32 = inst.w0.astype(np.float32)
+    a, _ = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 40, graph=True)
+    b, _ = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 40, graph=False)
+    assert oracle.rel_l1(a, b) <= 1e-6
+
+
+# ---- pins re-run on the GPU path ----
+
+def test_gpu_rotation_quarter_turn_is_permutation(B):
+    n, h = 48, 0.25
+    half = 0.5 * (n - 1) * h
+    x = p = Axis(-half, half, n, False)
+    w = rng(33).uniform(-1, 1, (n, n)).astype(np.float32)
+    got, _ = gpu_run(B, x, p, Hamiltonian(H_SHO_EXACT, omega=1.0), w, math.pi / 2, 1, ((16, 8), (16, 16)))
+    np.testing.assert_allclose(got, np.rot90(w.astype(np.float64)), atol=2e-6)
+
+
+def test_gpu_free_streaming_integer_shift(B):
+    n, K = 64, 21
+    x = Axis(0.0, float(n), n, True)
+    p = Axis(-float(K), float(n - 1 - K), n, False)
+    w = rng(34).uniform(-1, 1, (n, n)).astype(np.float32)
+    got, _ = gpu_run(B, x, p, Hamiltonian(H_FREE), w, 1.0, 3, ((16, 8), (32, 16)))
+    ref = np.stack([np.roll(w[j].astype(np.float64), 3 * (j - K)) for j in range(n)])
+    np.testing.assert_allclose(got, ref, atol=2e-6)
+
+
+def test_gpu_mass_conserved(B):
+    x, p = pendulum_axes(256)
+    w = gaussian(x, p, 0.5, 0.0, 0.3).astype(np.float32)
+    s0 = float(w.astype(np.float64).sum())
+    got, m = gpu_run(B, x, p, Hamiltonian(H_PENDULUM, a=1.0), w, 0.05, 400)
+    assert abs(m["sum_w"] - s0) <= 2e-6 * s0
+    assert abs(got.sum() - s0) <= 2e-6 * s0
+
+
+def test_moments_match_oracle(B):
+    inst = pendulum_gaussian(128)
+    w32 = inst.w0.astype(np.float32)
+    got, m = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 10)
+    ref = oracle.moments(inst.x, inst.p, inst.ham, got)
+    for k in ("sum_w", "mass", "neg_mass", "l1", "entropy", "mean_p", "energy"):
+        assert m[k] == pytest.approx(ref[k], rel=1e-10, abs=1e-12), k
+
+
+# ---- FEL ----
+
+def test_fel_run_and_invariant(B):
+    inst = fel_gaussian(256, 300, npp=256)
+    w32 = inst.w0.astype(np.float32)
+    got, m = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 300)
+    r = oracle.run(inst.x, inst.p, inst.ham, w32.astype(np.float64), inst.dt, 300)
+    err = oracle.rel_l1(got, r.w)
+    print(f"fel 256^2 300 steps: rel L1 {err:.3e}, A gpu {m['A_re']:+.6e}{m['A_im']:+.6e}j "
+          f"oracle {r.A:.6e}")
+    assert err <= 1e-4
+    assert abs(complex(m["A_re"], m["A_im"]) - r.A) <= 1e-4 * abs(r.A)
+    E0 = 1e-6 + float((w32.astype(np.float64) * inst.p.nodes()[:, None]).sum() / w32.sum())
+    assert abs(m["fel_invariant"] - E0) <= 1e-7
+
+
+# ---- full sizes ----
+
+def test_one_step_full_size_pendulum_band_2048(B):
+    inst = pendulum_band(2048)
+    w32 = inst.w0.astype(np.float32)
+    got, _ = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 1)
+    ref = one_step_ref(inst.x, inst.p, inst.ham, w32, inst.dt)
+    assert oracle.rel_l1(got, ref) <= 1e-5
+
+
+def test_one_step_full_size_fel_1024(B):
+    inst = fel_gaussian(1024)
+    w32 = inst.w0.astype(np.float32)
+    got, _ = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 1)
+    ref = oracle.run(inst.x, inst.p, inst.ham, w32.astype(np.float64), inst.dt, 1).w
+    assert oracle.rel_l1(got, ref) <= 1e-5
