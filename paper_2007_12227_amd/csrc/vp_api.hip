@@ -37,7 +37,22 @@ int fail(int code, const char* fmt, ...) {
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 constexpr int kMinTile = 8;
-constexpr size_t kMaxLds = 64 * 1024;
+constexpr size_t kDefaultLds = 64 * 1024;
+size_t g_max_lds = kDefaultLds;  // raised once per process to what the device allows (160 KiB on gfx950)
+std::once_flag g_lds_once;
+
+// Let both per-step kernels use the device's full LDS per workgroup.
+void raise_lds_limit() {
+    std::call_once(g_lds_once, [] {
+        int dev = 0, lim = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return;
+        if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return;
+        if (lim <= (int)kDefaultLds) return;
+        if (hipFuncSetAttribute(deposit_kernel(), hipFuncAttributeMaxDynamicSharedMemorySize, lim - 1024) != hipSuccess) return;
+        if (hipFuncSetAttribute(solve_kernel(), hipFuncAttributeMaxDynamicSharedMemorySize, lim - 1024) != hipSuccess) return;
+        g_max_lds = (size_t)(lim - 1024);
+    });
+}
 constexpr int kGraphSteps = 16;
 
 bool axis_ok(const vp_axis* a) {
@@ -184,14 +199,16 @@ namespace {
 int validate_tiles(const vp_grid* g, const vp_tiles& t) {
     if (t.k1_tx < kMinTile || t.k1_ty < 1 || t.k2_tx < kMinTile || t.k2_ty < kMinTile)
         return fail(VP_EINVAL, "tile sizes below the minimum (k1_tx, k2_tx, k2_ty >= %d, k1_ty >= 1)", kMinTile);
-    if (t.k1_tx > 4096 || t.k1_ty > 1024 || t.k2_tx > 4096 || t.k2_ty > 4096)
-        return fail(VP_EINVAL, "tile sizes too large");
-    if (deposit_lds_bytes(t.k1_tx, t.k1_ty) > kMaxLds)
+    if (t.k1_tx > 4096 || t.k1_ty > 1024)
+        return fail(VP_EINVAL, "deposit tile too large");
+    if (t.k2_tx > kMaxSolveTile || t.k2_ty > kMaxSolveTile)
+        return fail(VP_EINVAL, "solve tile sides must be at most %d", kMaxSolveTile);
+    if (deposit_lds_bytes(t.k1_tx, t.k1_ty) > g_max_lds)
         return fail(VP_EINVAL, "deposit tile %dx%d needs %zu bytes of LDS (limit %zu)", t.k1_tx, t.k1_ty,
-                    deposit_lds_bytes(t.k1_tx, t.k1_ty), kMaxLds);
-    if (solve_lds_bytes(t.k2_tx, t.k2_ty) > kMaxLds)
+                    deposit_lds_bytes(t.k1_tx, t.k1_ty), g_max_lds);
+    if (solve_lds_bytes(t.k2_tx, t.k2_ty) > g_max_lds)
         return fail(VP_EINVAL, "solve tile %dx%d needs %zu bytes of LDS (limit %zu)", t.k2_tx, t.k2_ty,
-                    solve_lds_bytes(t.k2_tx, t.k2_ty), kMaxLds);
+                    solve_lds_bytes(t.k2_tx, t.k2_ty), g_max_lds);
     (void)g;
     return VP_OK;
 }
@@ -392,13 +409,14 @@ int vp_create_grid(const vp_grid_desc* d, vp_grid** out) {
         return fail(VP_ENOMEM, "workspace of %zu bytes, need %zu", d->workspace_bytes, L.total);
     if (reinterpret_cast<uintptr_t>(d->workspace) % 256)
         return fail(VP_EINVAL, "workspace must be 256-byte aligned");
+    raise_lds_limit();
     vp_grid* g = new vp_grid();
     g->x = d->x;
     g->p = d->p;
     g->stream = reinterpret_cast<hipStream_t>(d->stream);
     g->ws = reinterpret_cast<char*>(d->workspace);
     g->L = L;
-    g->tiles = vp_tiles{128, 32, 64, 64};
+    g->tiles = vp_tiles{64, 32, 64, 32};
     g->list.stream = g->stream;
     g->list.d_inst = g->at<VpInst>(L.inst);
     g->list.d_off1 = g->at<int32_t>(L.off);
@@ -429,10 +447,6 @@ int vp_create_grid(const vp_grid_desc* d, vp_grid** out) {
         return c;
     };
     std::vector<float2> cx = coefs(d->x.n), cp = coefs(d->p.n);
-    // DC-exact gain: the FP32 interior coefficient m gives gain m/(1+m)^2 per axis
-    const double mf = (double)(float)(2.0 - sqrt(3.0));
-    const double S = pow((1.0 + mf) * (1.0 + mf) / mf, 2);
-    split(S, I.scale_hi, I.scale_lo);
     std::vector<double> st(kFelStateLen, 0.0);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpyAsync(g->at<float2>(L.coef_x), cx.data(), cx.size() * 8, hipMemcpyHostToDevice, g->stream);
@@ -490,6 +504,18 @@ int vp_set_density(vp_grid* g, const float* w, int32_t on_device) {
     HIP_TRY(hipMemcpyAsync(m, g->at<double>(g->L.moments), sizeof m, hipMemcpyDeviceToHost, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
     g->N0 = m[0];
+    {
+        // fixed-point scale of the deposit tile sums: 2^(40 - e), max|w0| < 2^e
+        const double wmax = m[8];
+        int e = 0;
+        if (wmax > 0.0 && isfinite(wmax)) {
+            (void)frexp(wmax, &e);  // wmax = f 2^e, f in [0.5, 1)
+            e = std::max(e, kFixBits - 126);
+        }
+        g->inst.fix_scale = ldexpf(1.0f, kFixBits - e);
+        g->inst.fix_inv = ldexpf(1.0f, e - kFixBits);
+        g->plan_valid = false;
+    }
     HIP_TRY(hipMemcpyAsync(g->at<double>(g->L.fel_state) + kN0, &g->N0, sizeof(double), hipMemcpyHostToDevice, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
     g->has_density = true;
@@ -664,8 +690,8 @@ int vp_autotune(vp_grid* g, double dt, double* best_us) {
         *us = 1000.f * ms / reps;
         return VP_OK;
     };
-    const int k1c[][2] = {{64, 16}, {64, 32}, {128, 16}, {128, 32}, {128, 64}, {256, 16}, {256, 32}};
-    const int k2c[][2] = {{32, 64}, {64, 32}, {64, 64}, {128, 32}, {128, 64}, {96, 96}};
+    const int k1c[][2] = {{64, 16}, {64, 32}, {64, 64}, {128, 16}, {128, 32}, {128, 64}, {256, 16}, {256, 32}};
+    const int k2c[][2] = {{32, 32}, {32, 64}, {64, 32}, {64, 64}, {128, 32}, {96, 64}, {128, 64}};
     vp_tiles best = g->tiles;
     float best_t = 1e30f;
     for (auto& c : k1c) {

@@ -29,8 +29,10 @@ namespace vp {
 enum Kind : int32_t { kFree = 0, kSho = 1, kPendulum = 2, kFel = 3 };
 
 constexpr int kHalo = 16;         // warm-up nodes on each side of a solve tile
+constexpr int kEdge = 32;         // nodes from an open edge whose LU coefficients are tabulated
+constexpr int kMaxSolveTile = 256;
 constexpr int kPad = 4;           // trash border of a deposit tile (per side)
-constexpr int kFixBits = 57;      // deposit tile sums: fixed point at 2^-57 of the box's max|w|
+constexpr int kFixBits = 40;      // deposit tile sums: fixed point at 2^-40 of the initial max|w|
 constexpr int kDepositThreads = 256;
 constexpr int kSolveThreads = 256;
 constexpr int kReduceBlocks = 256;
@@ -172,7 +174,7 @@ struct VpInst {
     int32_t k2_tx, k2_ty, k2_tiles_x, k2_tiles;
     int32_t parity0;         // index of the current state buffer when the launch list was built
     int32_t pad0;
-    float scale_hi, scale_lo;  // DC-exact gain of the two solves, hi + lo
+    float fix_scale, fix_inv;  // deposit fixed-point scale 2^(40-e), max|w0| < 2^e, and its inverse
     float fel_kick;            // -2 dz / h_eta (cells per unit field)
     float fel_sigma2;
     double fel_dz;
@@ -222,6 +224,6 @@ const void* solve_kernel();
 
 inline size_t deposit_lds_bytes(int tx, int ty) { return sizeof(int64_t) * (size_t)(tx + 2 * kPad) * (ty + 2 * kPad); }
 __host__ __device__ inline int solve_ldw(int tx) { int w = tx + 2 * kHalo; return (w & 1) ? w : w + 1; }
-inline size_t solve_lds_bytes(int tx, int ty) { return sizeof(float) * (size_t)solve_ldw(tx) * (ty + 2 * kHalo); }
+inline size_t solve_lds_bytes(int tx, int ty) { return 2 * sizeof(float) * (size_t)solve_ldw(tx) * (ty + 2 * kHalo); }
 
 }  // namespace vp

@@ -37,29 +37,35 @@ __device__ inline void split_cell(float hi, float lo, int& k, float& t) {
     t = r;
 }
 
+// Round v in [0, 1] to a multiple of 2^-23 ((v + 1) - 1, both steps exact or
+// correctly rounded, never contracted).
+__device__ inline float grid23(float v) { return __fsub_rn(__fadd_rn(v, 1.0f), 1.0f); }
+
 // Cubic B-spline tap weights B3(t+1), B3(t), B3(1-t), B3(2-t) for t in [0,1).
-// The second tap is 1 minus the others, so the four sum to one to rounding
-// (the partition of unity behind the conservation argument of eqs. 11-12).
+// They sum to exactly one in FP32 (the partition of unity behind the
+// conservation argument of eqs. 11-12): three taps are rounded to multiples
+// of 2^-23, so their sum and 1 minus it are exact and give the fourth.
+// (Without that rounding, 1 - sum itself rounds, biased: at t = 0 the taps
+// sum to 1 - 3e-8 and the state would lose that much mass per axis per step.)
 __device__ inline void bspline_taps(float t, float (&b)[4]) {
     const float sixth = 1.0f / 6.0f;
     float s = 1.0f - t;
     float t2 = t * t;
-    b[0] = (s * sixth) * (s * s);
-    b[3] = (t * sixth) * t2;
-    b[2] = fmaf(0.5f, t + t2, sixth) - 3.0f * b[3];
+    b[0] = grid23((s * sixth) * (s * s));
+    const float t3 = (t * sixth) * t2;
+    b[3] = grid23(t3);
+    b[2] = grid23(fmaf(0.5f, t + t2, sixth) - 3.0f * t3);
     b[1] = 1.0f - ((b[0] + b[3]) + b[2]);
 }
 
-// Round a float of magnitude below 2^62 to a 64-bit integer (two's complement
-// bits): v = hi * 2^32 + lo with hi = floor(v / 2^32) and 0 <= lo < 2^32; both
-// parts are exact in FP32 whenever |v| >= 2^32, and for smaller |v| the low
-// part rounds to a multiple of at most 2^8, i.e. 2^-49 of the tile maximum.
+// Round a float of magnitude below 2^51 to the nearest 64-bit integer (two's
+// complement bits) with an exact format conversion: adding 1.5 * 2^52 to the
+// (exact) double of v leaves round-to-nearest(v) in the low 52 bits of the
+// sum's encoding, two's complement relative to the constant's encoding.  No
+// arithmetic on the state is done in FP64: the double only carries the bits.
 __device__ inline unsigned long long fix64(float v) {
-    const float hf = floorf(v * 2.3283064365386963e-10f);  // 2^-32
-    const int hi = (int)hf;
-    const float lo = fminf(fmaf(hf, -4294967296.0f, v), 4294967040.0f);
-    const unsigned lo_u = (unsigned)lo;
-    return ((unsigned long long)(unsigned)hi << 32) + (unsigned long long)lo_u;
+    const double d = (double)v + 6755399441055744.0;  // 1.5 * 2^52
+    return (unsigned long long)(__double_as_longlong(d) - 0x4338000000000000ll);
 }
 
 // Locate the instance of a flattened tile index (thread 0 only).
@@ -81,6 +87,78 @@ __device__ inline int wrap_index(int i, int n, float inv_n) {
     return r;
 }
 
+// In-place solve of M y = b, M = tridiag(1/6, 2/3, 1/6), along n elements of L
+// (stride apart), written as
+//     y = b - T^{-1} (D2 b),   T = 6 M = tridiag(1, 4, 1),  D2 b = b[k-1] - 2 b[k] + b[k+1]
+// (T = 6 I + D2, so 6 T^{-1} = I - T^{-1} D2).  The LU recursions of T then only
+// carry the correction T^{-1} D2 b, so their FP32 rounding (whose fixed point
+// is biased on slowly varying data) acts on a term much smaller than b, and
+// the mass the line carries is kept to ~1e-10 per step instead of ~1e-8.
+// Neighbours outside [0, n) count as zero: exact at an open edge (the
+// truncated M), and a cut inside the lattice only disturbs the halo.
+// first = index of L[0] from the open edge if below kEdge (exact tabulated
+// edge coefficients), else kEdge (interior constants).  Z (same layout as L)
+// holds the forward sweep.  Loads are issued eight elements ahead.
+template <bool EDGE>
+__device__ inline float lu_m(int g, const float2* edge) { return (EDGE && g < kEdge) ? edge[g].x : kMinf; }
+template <bool EDGE>
+__device__ inline float lu_dinv(int g, const float2* edge) { return (EDGE && g < kEdge) ? edge[g].y : kMinf; }
+
+template <bool EDGE>
+__device__ inline void solve_line_t(float* L, float* Z, int stride, int n, int first, const float2* edge) {
+    float prev = 0.0f, cur = L[0], acc = 0.0f;
+    int k = 0;
+    for (; k + 8 < n; k += 8) {
+        float nx[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) nx[u] = L[(k + 1 + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float m = lu_m<EDGE>(first + k + u, edge);
+            acc = fmaf(-m, acc, (prev + nx[u]) - 2.0f * cur);
+            Z[(k + u) * stride] = acc;
+            prev = cur;
+            cur = nx[u];
+        }
+    }
+    for (; k < n; ++k) {
+        const float next = k + 1 < n ? L[(k + 1) * stride] : 0.0f;
+        const float m = lu_m<EDGE>(first + k, edge);
+        acc = fmaf(-m, acc, (prev + next) - 2.0f * cur);
+        Z[k * stride] = acc;
+        prev = cur;
+        cur = next;
+    }
+    float c = 0.0f;
+    k = n - 1;
+    for (; k >= 7; k -= 8) {
+        float zv[8], bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            zv[u] = Z[(k - u) * stride];
+            bv[u] = L[(k - u) * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float dinv = lu_dinv<EDGE>(first + k - u, edge);
+            c = (zv[u] - c) * dinv;
+            L[(k - u) * stride] = bv[u] - c;
+        }
+    }
+    for (; k >= 0; --k) {
+        const float dinv = lu_dinv<EDGE>(first + k, edge);
+        c = (Z[k * stride] - c) * dinv;
+        L[k * stride] = L[k * stride] - c;
+    }
+}
+
+// Lines that start kEdge or more nodes from an open edge (all lines of a
+// periodic axis) use only the interior constants: no table reads in the loop.
+__device__ inline void solve_line(float* L, float* Z, int stride, int n, int first, const float2* edge) {
+    if (first >= kEdge) solve_line_t<false>(L, Z, stride, n, first, edge);
+    else solve_line_t<true>(L, Z, stride, n, first, edge);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -96,7 +174,6 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
     extern __shared__ long long acc[];
     __shared__ int s_d, s_box[4];
     __shared__ float s_ab[2];
-    __shared__ float s_max[kDepositThreads / 64];
 
     for (int item = blockIdx.x; item < A.total; item += gridDim.x) {
         if (threadIdx.x == 0) s_d = find_instance(A.off, A.ninst, item);
@@ -140,29 +217,13 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
         const bool periodic = I.push.x_periodic != 0;
 
         // Tile sums are exact fixed-point integers: every tap value is rounded
-        // to a multiple of 2^-57 * max|w| over the source box and accumulated
+        // to a multiple of 2^-40 of the instance's initial max|w| and summed
         // with 64-bit integer LDS atomics, so the sum does not depend on the
         // order of the atomics (bitwise reproducible).  The map is area
-        // preserving, so a cell collects about max|w|; 6 spare bits cover 64x.
-        float wmax = 0.0f;
-        for (int s = threadIdx.x; s < nsrc; s += blockDim.x) {
-            int r = (int)(((float)s + 0.5f) * inv_bw);
-            int c = s - r * bw;
-            if (c < 0) { c += bw; --r; }
-            if (c >= bw) { c -= bw; ++r; }
-            const int ii = bx0 + c;
-            const int i = periodic ? wrap_index(ii, nx, inv_nx) : ii;
-            wmax = fmaxf(wmax, fabsf(w_in[(size_t)(by0 + r) * nx + i]));
-        }
-        for (int o = 32; o > 0; o >>= 1) wmax = fmaxf(wmax, __shfl_xor(wmax, o));
-        if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = wmax;
-        __syncthreads();
-        wmax = s_max[0];
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) wmax = fmaxf(wmax, s_max[k]);
-        // scale = 2^(57 - e) with max|w| < 2^e
-        const int e = wmax > 0.0f ? max(ilogbf(wmax) + 1, kFixBits - 127) : 0;
-        const float scale = ldexpf(1.0f, kFixBits - e), inv_scale = ldexpf(1.0f, e - kFixBits);
-        const int nsrc_live = wmax > 0.0f ? nsrc : 0;
+        // preserving, so a cell collects about max|w|; a tap must stay below
+        // 2^11 max|w| (the conversion's range) and a sum below 2^23 max|w|.
+        const float scale = I.fix_scale, inv_scale = I.fix_inv;
+        const int nsrc_live = scale > 0.0f ? nsrc : 0;
 
         for (int s = threadIdx.x; s < nsrc_live; s += blockDim.x) {
             int r = (int)(((float)s + 0.5f) * inv_bw);
@@ -222,21 +283,20 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// k_solve: w_out = (M_x^{-1} (x) M_p^{-1}) b on one tile.  Each line is solved
-// with the LU recursions of T = tridiag(1,4,1) = 6 M:
-//   forward  z_k = b_k - m_k z_{k-1},   backward y_k = (z_k - y_{k+1}) / d_k,
-// with exact per-node (m_k, 1/d_k) on an open axis (so the true edges are
-// exact) and the interior constants on a periodic one.  Where the tile's halo
-// is cut inside the lattice the recursion starts from zero; the error decays
-// by 2 - sqrt 3 per node and is ~7e-10 after the 16-node halo.  The factor 6
-// per axis is applied once at the end as scale_hi + scale_lo, chosen so that
-// the FP32 coefficients give a DC gain of exactly one.
+// k_solve: w_out = (M_x^{-1} (x) M_p^{-1}) b on one tile, one line at a time
+// (solve_line): the LU recursions of T = tridiag(1,4,1),
+//   forward  z_k = r_k - m_k z_{k-1},   backward c_k = (z_k - c_{k+1}) / d_k,
+// with exact per-node (m_k, 1/d_k) near an open edge (so the true edges are
+// exact) and the interior constants elsewhere.  Where the tile's halo is cut
+// inside the lattice the recursion starts from zero; the error decays by
+// 2 - sqrt 3 per node and is ~7e-10 after the 16-node halo.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
     extern __shared__ float lds[];
     __shared__ int s_d;
     __shared__ double s_red[2][kSolveThreads / 64];
     __shared__ int s_last;
+    __shared__ float2 s_edge_x[kEdge], s_edge_p[kEdge];
 
     for (int item = blockIdx.x; item < A.total; item += gridDim.x) {
         if (threadIdx.x == 0) s_d = find_instance(A.off, A.ninst, item);
@@ -254,12 +314,19 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
         const int rr0 = max(0, Y0 - kHalo), rr1 = min(np, Y1 + kHalo);
         const int RW = rc1 - rc0, RH = rr1 - rr0;
         const int ldw = solve_ldw(I.k2_tx);
+        const int zoff = ldw * (I.k2_ty + 2 * kHalo);  // second buffer: the forward sweeps
         const int par = (I.parity0 + A.parity) & 1;
         float* __restrict__ w_out = I.w[par ^ 1];
         const float* __restrict__ b = I.b;
         const float inv_nx = 1.0f / (float)nx;
         const float inv_rw = 1.0f / (float)RW;
 
+        // LU coefficients differ from the interior constant only within
+        // kEdge nodes of an open axis' first node; stage those in LDS.
+        if (threadIdx.x < kEdge) {
+            s_edge_p[threadIdx.x] = I.coef_p[min((int)threadIdx.x, np - 1)];
+            s_edge_x[threadIdx.x] = periodic ? make_float2(kMinf, kMinf) : I.coef_x[min((int)threadIdx.x, nx - 1)];
+        }
         for (int k = threadIdx.x; k < RW * RH; k += blockDim.x) {
             int r = (int)(((float)k + 0.5f) * inv_rw);
             int c = k - r * RW;
@@ -274,17 +341,10 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
         // x lines: one thread per row of the region
         for (int r = threadIdx.x; r < RH; r += blockDim.x) {
             float* L = lds + r * ldw;
-            float z = 0.0f;
-            if (periodic) {
-                for (int c = 0; c < RW; ++c) { z = fmaf(-kMinf, z, L[c]); L[c] = z; }
-                float y = 0.0f;
-                for (int c = RW - 1; c >= 0; --c) { y = (L[c] - y) * kMinf; L[c] = y; }
-            } else {
-                const float2* cf = I.coef_x + rc0;
-                for (int c = 0; c < RW; ++c) { z = fmaf(-cf[c].x, z, L[c]); L[c] = z; }
-                float y = 0.0f;
-                for (int c = RW - 1; c >= 0; --c) { y = (L[c] - y) * cf[c].y; L[c] = y; }
-            }
+            // a periodic axis, or a region starting kEdge or more nodes from
+            // the open edge, only sees the interior constants
+            const bool edge = !periodic && rc0 < kEdge;
+            solve_line(L, L + zoff, 1, RW, edge ? rc0 : kEdge, s_edge_x);
         }
         __syncthreads();
 
@@ -294,25 +354,15 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
         double acc_re = 0.0, acc_im = 0.0;
         for (int c = threadIdx.x; c < tw; c += blockDim.x) {
             const int lc = X0 - rc0 + c;
-            const float2* cf = I.coef_p + rr0;
-            float z = 0.0f;
-            for (int r = 0; r < RH; ++r) {
-                z = fmaf(-cf[r].x, z, lds[r * ldw + lc]);
-                lds[r * ldw + lc] = z;
-            }
-            float y = 0.0f;
+            solve_line(lds + lc, lds + zoff + lc, ldw, RH, rr0 < kEdge ? rr0 : kEdge, s_edge_p);
             double cre = 0.0, cim = 0.0;
-            for (int r = RH - 1; r >= 0; --r) {
-                y = (lds[r * ldw + lc] - y) * cf[r].y;
-                const int gr = rr0 + r;
-                if (gr >= Y0 && gr < Y1) {
-                    const float out = fmaf(y, I.scale_hi, y * I.scale_lo);
-                    w_out[(size_t)gr * nx + X0 + c] = out;
-                    if (fel) {
-                        const double2 e = I.fel_eq[gr];
-                        cre += (double)out * e.x;
-                        cim -= (double)out * e.y;
-                    }
+            for (int gr = Y0; gr < Y1; ++gr) {
+                const float out = lds[(gr - rr0) * ldw + lc];
+                w_out[(size_t)gr * nx + X0 + c] = out;
+                if (fel) {
+                    const double2 e = I.fel_eq[gr];
+                    cre += (double)out * e.x;
+                    cim -= (double)out * e.y;
                 }
             }
             if (fel) {
@@ -379,7 +429,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
 // ---------------------------------------------------------------------------
 // k_reduce: FP64 sums over one state, fixed-order (deterministic) reduction.
 //  mode 0 (diagnostics): sum w, sum_{w<0} w, sum |w|, sum_{w>0} w ln w,
-//    sum w p, sum w (kinetic + potential), sum w cos x, sum w sin x, #nonfinite.
+//    sum w p, sum w (kinetic + potential), sum w cos x, sum w sin x, max |w|,
+//    #nonfinite.
 //  mode 1 (FEL bunching): sum w e^{-i (phi_i + q_j)} / N0 -> fel_state.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
@@ -407,6 +458,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
         if (!isfinite(w)) { acc[9] += 1.0; continue; }
         const double x = R.x_lo + (double)i * R.hx, p = R.p_lo + (double)j * R.hp;
         acc[0] += w;
+        acc[8] = fmax(acc[8], fabs(w));
         if (w < 0.0) acc[1] += w;
         acc[2] += fabs(w);
         if (w > 0.0) acc[3] += w * log(w);
@@ -422,7 +474,10 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
     }
 #pragma unroll
     for (int k = 0; k < kMoments; ++k)
-        for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_down(acc[k], o);
+        for (int o = 32; o > 0; o >>= 1) {
+            const double v = __shfl_down(acc[k], o);
+            acc[k] = k == 8 ? fmax(acc[k], v) : acc[k] + v;
+        }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0)
         for (int k = 0; k < kMoments; ++k) s_part[wid][k] = acc[k];
@@ -430,7 +485,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
     if (threadIdx.x == 0) {
         for (int k = 0; k < kMoments; ++k) {
             double s = 0.0;
-            for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += s_part[q][k];
+            for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s = k == 8 ? fmax(s, s_part[q][k]) : s + s_part[q][k];
             R.partials[blockIdx.x * kMoments + k] = s;
         }
         __threadfence();
@@ -441,8 +496,10 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
     __threadfence();
     if (threadIdx.x < kMoments) {
         double s = 0.0;
-        for (unsigned q = 0; q < gridDim.x; ++q)
-            s += __builtin_nontemporal_load(&R.partials[q * kMoments + threadIdx.x]);
+        for (unsigned q = 0; q < gridDim.x; ++q) {
+            const double v = __builtin_nontemporal_load(&R.partials[q * kMoments + threadIdx.x]);
+            s = threadIdx.x == 8 ? fmax(s, v) : s + v;
+        }
         if (R.mode == 1) {
             if (threadIdx.x < 2) R.out[kBn + threadIdx.x] = s * R.inv_n0;
             if (threadIdx.x == 0) R.out[kDzB] = R.dz;

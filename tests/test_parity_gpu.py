@@ -48,7 +48,7 @@ def one_step_ref(x, p, ham, w32, dt):
     return oracle.run(x, p, ham, w32.astype(np.float64), dt, 1).w
 
 
-TILINGS = [None, ((64, 16), (32, 32)), ((24, 5), (40, 24)), ((200, 24), (120, 56))]
+TILINGS = [None, ((64, 16), (32, 32)), ((24, 5), (40, 24)), ((200, 24), (120, 24))]
 
 
 @pytest.mark.parametrize("tiles", TILINGS)
@@ -132,8 +132,11 @@ def test_gpu_mass_conserved(B):
     w = gaussian(x, p, 0.5, 0.0, 0.3).astype(np.float32)
     s0 = float(w.astype(np.float64).sum())
     got, m = gpu_run(B, x, p, Hamiltonian(H_PENDULUM, a=1.0), w, 0.05, 400)
-    assert abs(m["sum_w"] - s0) <= 2e-6 * s0
-    assert abs(got.sum() - s0) <= 2e-6 * s0
+    # the taps sum to exactly one and the solve keeps the line mass to ~1e-10:
+    # what is left is unbiased rounding
+    print(f"mass drift over 400 steps: {(m['sum_w'] - s0) / s0:+.3e}")
+    assert abs(m["sum_w"] - s0) <= 2e-7 * s0
+    assert abs(got.sum() - s0) <= 2e-7 * s0
 
 
 def test_moments_match_oracle(B):
