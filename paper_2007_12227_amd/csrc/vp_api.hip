@@ -330,7 +330,7 @@ int plan(vp_grid* g, double dt) {
         }
     }
     VpInst& I = g->inst;
-    I.fel_kick = (float)(-2.0 * dt / hp);
+    I.fel_kick = -2.0 * dt / hp;
     I.fel_sigma2 = (float)H.fel_sigma2;
     I.fel_dz = dt;
     HIP_TRY(hipMemcpyAsync(g->at<float4>(g->L.tab_x), tx.data(), nx * sizeof(float4), hipMemcpyHostToDevice, g->stream));

@@ -175,8 +175,9 @@ struct VpInst {
     int32_t parity0;         // index of the current state buffer when the launch list was built
     int32_t pad0;
     float fix_scale, fix_inv;  // deposit fixed-point scale 2^(40-e), max|w0| < 2^e, and its inverse
-    float fel_kick;            // -2 dz / h_eta (cells per unit field)
     float fel_sigma2;
+    float pad1;
+    double fel_kick;           // -2 dz / h_eta (cells per unit field), FP64: the field coupling
     double fel_dz;
     float* w[2];
     float* b;

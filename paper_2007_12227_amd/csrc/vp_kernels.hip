@@ -58,13 +58,12 @@ __device__ inline void bspline_taps(float t, float (&b)[4]) {
     b[1] = 1.0f - ((b[0] + b[3]) + b[2]);
 }
 
-// Round a float of magnitude below 2^51 to the nearest 64-bit integer (two's
-// complement bits) with an exact format conversion: adding 1.5 * 2^52 to the
-// (exact) double of v leaves round-to-nearest(v) in the low 52 bits of the
-// sum's encoding, two's complement relative to the constant's encoding.  No
-// arithmetic on the state is done in FP64: the double only carries the bits.
-__device__ inline unsigned long long fix64(float v) {
-    const double d = (double)v + 6755399441055744.0;  // 1.5 * 2^52
+// Round a value of magnitude below 2^51 to the nearest 64-bit integer (two's
+// complement bits) exactly: adding 1.5 * 2^52 leaves round-to-nearest(v) in
+// the low 52 bits of the sum's encoding, two's complement relative to the
+// constant's encoding.
+__device__ inline unsigned long long fix64(double v) {
+    const double d = v + 6755399441055744.0;  // 1.5 * 2^52
     return (unsigned long long)(__double_as_longlong(d) - 0x4338000000000000ll);
 }
 
@@ -198,8 +197,8 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
                 const double* st = I.fel_state;
                 double are = st[kA] + 0.5 * I.fel_dz * st[kBn] - (double)I.fel_sigma2 * st[kBn + 1];
                 double aim = st[kA + 1] + 0.5 * I.fel_dz * st[kBn + 1] + (double)I.fel_sigma2 * st[kBn];
-                P.alpha = (float)((double)I.fel_kick * are);
-                P.beta = (float)(-(double)I.fel_kick * aim);
+                P.alpha = (float)(I.fel_kick * are);
+                P.beta = (float)(-I.fel_kick * aim);
             }
             s_ab[0] = P.alpha;
             s_ab[1] = P.beta;
@@ -222,7 +221,7 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
         // order of the atomics (bitwise reproducible).  The map is area
         // preserving, so a cell collects about max|w|; a tap must stay below
         // 2^11 max|w| (the conversion's range) and a sum below 2^23 max|w|.
-        const float scale = I.fix_scale, inv_scale = I.fix_inv;
+        const float scale = I.fix_scale, inv_scale = I.fix_inv;  // exact powers of two
         const int nsrc_live = scale > 0.0f ? nsrc : 0;
 
         for (int s = threadIdx.x; s < nsrc_live; s += blockDim.x) {
@@ -262,12 +261,18 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
             const int c0 = clampi(ii + ku - 1 - X0 + kPad, 0, cmax);
             const int r0 = clampi(j + kv - 1 - Y0 + kPad, 0, rmax);
             long long* base = acc + r0 * ldw + c0;
+            // tap value w * bp * bx formed in FP64 and rounded once, exactly,
+            // into the fixed-point tile sum: the deposit adds no FP32 product
+            // rounding to the state (the FEL instability amplifies it)
+            double bxd[4];
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) bxd[rr] = (double)bx[rr];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const float wq = w * bp[q];
+                const double wq = (double)w * (double)bp[q];
                 long long* row = base + q * ldw;
 #pragma unroll
-                for (int rr = 0; rr < 4; ++rr) atomicAdd((unsigned long long*)(row + rr), fix64(wq * bx[rr]));
+                for (int rr = 0; rr < 4; ++rr) atomicAdd((unsigned long long*)(row + rr), fix64(wq * bxd[rr]));
             }
         }
         __syncthreads();

@@ -5,7 +5,7 @@ input generators.
     python tests/golden/make_full_runs.py [--only NAME]
 
 For each workload it stores, at the recorded steps: a strided sample of the
-FP64 state (float64), the full-array sum and L1 norm, the FEL field, and the
+FP64 state (rounded to float32), the full-array sum and L1 norm, the FEL field, and the
 relative L1 distance of the FP32-state run (state rounded to float after every
 step) from the FP64 run: the floor any implementation with FP32 state reaches.
 """
@@ -25,8 +25,8 @@ from paper_2007_12227_amd.inputs import fel_gaussian, pendulum_band, pendulum_ga
 WORKLOADS = {
     # name: (instance factory, checkpoints, sample stride)
     "pendulum_gaussian_128": (lambda: pendulum_gaussian(128), (1, 100, 200), 1),
-    "pendulum_band_2048": (lambda: pendulum_band(2048), (1, 500, 1000), 8),
-    "fel_gaussian_1024": (lambda: fel_gaussian(1024), (1, 500, 1000, 1500, 2000), 4),
+    "pendulum_band_2048": (lambda: pendulum_band(2048), (1, 500, 1000), 16),
+    "fel_gaussian_1024": (lambda: fel_gaussian(1024), (1, 500, 1000, 1500, 2000), 8),
 }
 
 
@@ -47,7 +47,7 @@ def run(name):
                          round_fp32=True)
         w64, A64, w32, A32 = r64.w, r64.A, r32.w, r32.A
         done = s
-        out[f"sample_{s}"] = w64[::stride, ::stride].copy()
+        out[f"sample_{s}"] = w64[::stride, ::stride].astype(np.float32)
         out[f"sum_{s}"] = np.array(w64.sum())
         out[f"l1_{s}"] = np.array(np.abs(w64).sum())
         out[f"A_{s}"] = np.array([A64.real, A64.imag])

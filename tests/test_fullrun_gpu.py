@@ -1,0 +1,66 @@
+"""Full-length runs at the workloads' real sizes, in the launch configuration
+the benchmark times (autotuned tiles, steps replayed from HIP graphs), against
+strided samples of the FP64 oracle's run (tests/golden/make_full_runs.py).
+Bar: relative L1 <= 1e-4 on the sample; the FP32-storage floor of the same
+run (oracle with its state rounded to float every step) is printed beside it."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_12227_amd.inputs import fel_gaussian, pendulum_band, pendulum_gaussian
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2007_12227_amd import binding
+    binding.lib()
+    return binding
+
+
+def run_against_golden(B, inst, name, autotune=True):
+    ref = np.load(os.path.join(GOLDEN, f"oracle_{name}.npz"))
+    stride = int(ref["stride"])
+    g = B.Grid(inst.x, inst.p)
+    g.set_hamiltonian(inst.ham)
+    g.set_density(inst.w0.astype(np.float32))
+    if autotune:
+        g.autotune(inst.dt)
+    done, worst = 0, 0.0
+    for s in ref["steps"]:
+        g.step(inst.dt, int(s) - done)
+        done = int(s)
+        got = g.density()[::stride, ::stride].astype(np.float64)
+        exp = ref[f"sample_{s}"].astype(np.float64)
+        err = float(np.abs(got - exp).sum() / np.abs(exp).sum())
+        m = g.moments()
+        print(f"{name} step {s}: rel L1 (sample) {err:.3e}  FP32-state floor {float(ref[f'fp32_floor_{s}']):.3e}"
+              f"  sum_w gpu {m['sum_w']:.10e} oracle {float(ref[f'sum_{s}']):.10e}", flush=True)
+        worst = max(worst, err)
+        # mass accounting against the initial mass (the FEL loses almost all of
+        # it through the open energy edges after saturation)
+        assert abs(m["sum_w"] - float(ref[f"sum_{s}"])) <= 1e-6 * abs(float(ref["sum_1"]))
+        if inst.ham.kind == 3:
+            A = complex(*ref[f"A_{s}"])
+            assert abs(complex(m["A_re"], m["A_im"]) - A) <= 1e-3 * abs(A), (m["A_re"], m["A_im"], A)
+    g.close()
+    return worst
+
+
+def test_full_run_pendulum_gaussian_128(B):
+    assert run_against_golden(B, pendulum_gaussian(128), "pendulum_gaussian_128", autotune=False) <= 1e-4
+
+
+def test_full_run_pendulum_band_2048(B):
+    assert run_against_golden(B, pendulum_band(2048), "pendulum_band_2048") <= 1e-4
+
+
+def test_full_run_fel_gaussian_1024(B):
+    assert run_against_golden(B, fel_gaussian(1024), "fel_gaussian_1024") <= 1e-4
