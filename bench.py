@@ -43,6 +43,78 @@ def timed_steps(g, dt, steps, warmup):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
+def bench_fel(binding, steps):
+    """1024^2 FEL (Gaussian in energy, A0 = 1e-3, dz = 0.01), tuned launch."""
+    from paper_2007_12227_amd.inputs import fel_gaussian
+    inst = fel_gaussian(1024, steps)
+    g = binding.grid_for(inst)
+    g.autotune(inst.dt)
+    sec, _ = timed_steps(g, inst.dt, steps, 0)
+    m = g.moments()
+    g.close()
+    return {"workload": "fel_gaussian_1024", "steps": steps, "value": inst.nodes * steps / sec,
+            "ms_per_step": 1e3 * sec / steps, "A_abs": abs(complex(m["A_re"], m["A_im"]))}
+
+
+def bench_batched(binding, steps, count):
+    """256 pendulum instances, n log-uniform in [64, 1024], one launch per kernel
+    per step for all of them, against each instance run alone (plain)."""
+    import torch
+
+    from paper_2007_12227_amd.inputs import batch_instances
+    insts = batch_instances(count, seed=4, steps=steps)
+    work = sum(i.nodes for i in insts) * steps
+    grids = [binding.grid_for(i) for i in insts]
+    for g, i in zip(grids, insts):
+        g.autotune(i.dt, cached=True)   # tuned once per shape class
+    batch = binding.Batch(grids, [i.dt for i in insts])
+    batch.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    batch.close()
+    for g in grids:
+        g.close()
+    # plain: one solve at a time, default tiles, direct launches
+    plain_sec = 0.0
+    for i in insts:
+        g = binding.grid_for(i)
+        g.set_launch(False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.step(i.dt, steps)
+        torch.cuda.synchronize()
+        plain_sec += time.perf_counter() - t1
+        g.close()
+    return {"workload": f"batched_{count}_pendulum_64_1024", "steps": steps,
+            "total_nodes": sum(i.nodes for i in insts), "value": work / sec,
+            "ms_per_step": 1e3 * sec / steps, "plain_value": work / plain_sec,
+            "speedup_vs_plain": plain_sec / sec}
+
+
+def bench_served(binding, nreq, load, capacity, budget_gib):
+    """Poisson arrivals of mixed requests (70% pendulum, 30% FEL, n in
+    [128, 2048], 100..2000 steps) served with continuous batching under an HBM
+    budget, against the one-at-a-time server on the same trace."""
+    from paper_2007_12227_amd import serving
+    from paper_2007_12227_amd.inputs import request_trace
+    probe = request_trace(nreq, seed=5, rate=1.0)
+    mean_work = sum(r.n * r.n * r.steps for r in probe) / nreq
+    rate = load * capacity / mean_work
+    trace = request_trace(nreq, seed=5, rate=rate)
+    srv = serving.Server(budget_bytes=int(budget_gib * (1 << 30)), chunk=64, realtime=True)
+    res = srv.run(trace)
+    out = serving.summary(res)
+    base = serving.summary(serving.serve_one_at_a_time(trace, realtime=True))
+    out.update({"workload": f"served_{nreq}_mixed", "load": load, "rate_per_s": rate,
+                "budget_gib": budget_gib, "iterations": srv.iterations,
+                "batch_rebuilds": srv.batch_rebuilds,
+                "plain": {k: base[k] for k in ("node_steps_per_s", "p50_latency_s", "p99_latency_s", "wall_s")}})
+    return out
+
+
 def cpu_baseline(inst, steps):
     import numpy as np
 
@@ -67,6 +139,14 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (scale for HBM counters)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline workload (no FEL / batched / served lines)")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--fel-steps", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-budget-gib", type=float, default=4.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -138,6 +218,14 @@ def main():
         "step_roofline_frac": ALG_BYTES_PER_NODE * N / (sec / args.steps) / 1e9 / HBM_PEAK_GBS,
         "final_sum_w": m["sum_w"],
     }
+    if not args.no_extras:
+        line["fel"] = bench_fel(binding, args.fel_steps)
+        log(f"fel: {line['fel']}")
+        line["batched"] = bench_batched(binding, args.batch_steps, args.batch_count)
+        log(f"batched: {line['batched']}")
+        line["served"] = bench_served(binding, args.serve_requests, args.serve_load,
+                                      line["batched"]["value"], args.serve_budget_gib)
+        log(f"served: {line['served']}")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inst, args.cpu_steps)
     print(json.dumps(line), flush=True)

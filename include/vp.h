@@ -111,11 +111,11 @@ typedef struct {
     int64_t nonfinite;
 } vp_moments_t;
 
-/* Tile shape of the two per-step kernels: the deposit tile (k1) and the solve
- * tile (k2), in lattice nodes.  Zero fields keep the current value. */
+/* Tile shape of the deposit kernel (destination tile, in lattice nodes).
+ * Zero fields keep the current value.  (The two solve kernels work on fixed
+ * 32-node line segments.) */
 typedef struct {
     int32_t k1_tx, k1_ty;
-    int32_t k2_tx, k2_ty;
 } vp_tiles;
 
 /* Bytes of device workspace a grid of this shape needs (0 if the axes are invalid). */
@@ -146,8 +146,8 @@ int vp_step(vp_grid* g, double dt, int64_t nsteps);
 /* Diagnostics of the current state; waits for the stream. */
 int vp_moments(vp_grid* g, vp_moments_t* out);
 
-/* Tile shapes.  vp_set_tiles validates the shape (VP_EINVAL if a kernel's
- * local memory would exceed its limit). */
+/* Deposit tile shape.  vp_set_tiles validates it (VP_EINVAL if the tile's
+ * local memory would exceed the device limit). */
 int vp_set_tiles(vp_grid* g, const vp_tiles* t);
 int vp_get_tiles(const vp_grid* g, vp_tiles* t);
 
@@ -157,13 +157,15 @@ int vp_set_launch(vp_grid* g, int32_t use_graph);
 
 /* Measurement helper: nsteps steps exactly as vp_step with direct launches,
  * with HIP events recorded on the grid's stream around every kernel.
- * us[0] and us[1] receive the mean duration in microseconds of the deposit
- * kernel and of the solve kernel.  Waits for the stream. */
-int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]);
+ * us[0], us[1], us[2] receive the mean duration in microseconds of the
+ * deposit, x-solve and p-solve kernels.  Waits for the stream. */
+int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[3]);
 
 /* Time candidate tile shapes on this grid for step size dt and keep the
- * fastest.  The state is restored afterwards.  best_us (may be NULL) receives
- * the time per step of the chosen shape.  Results are cached per shape class. */
+ * fastest.  The state is restored afterwards.  best_us receives the time per
+ * step of the chosen shape.  Choices are cached per shape class (kind, axis
+ * lengths and largest displacement in half-octave buckets); with best_us ==
+ * NULL a cached choice is applied without timing. */
 int vp_autotune(vp_grid* g, double dt, double* best_us);
 
 /* Batched execution: n grids (each with its density and Hamiltonian set)

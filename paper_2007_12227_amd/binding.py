@@ -51,7 +51,7 @@ class Moments(C.Structure):
 
 
 class Tiles(C.Structure):
-    _fields_ = [("k1_tx", C.c_int32), ("k1_ty", C.c_int32), ("k2_tx", C.c_int32), ("k2_ty", C.c_int32)]
+    _fields_ = [("k1_tx", C.c_int32), ("k1_ty", C.c_int32)]
 
 
 _lib = None
@@ -199,11 +199,11 @@ class Grid:
     def step(self, dt: float, n: int = 1):
         check(lib().vp_step(self._h, float(dt), int(n)))
 
-    def step_timed(self, dt: float, n: int) -> tuple[float, float]:
-        """n steps with per-kernel HIP events: mean (deposit_us, solve_us)."""
-        us = (C.c_double * 2)()
+    def step_timed(self, dt: float, n: int) -> tuple[float, float, float]:
+        """n steps with per-kernel HIP events: mean (deposit, x-solve, p-solve) microseconds."""
+        us = (C.c_double * 3)()
         check(lib().vp_step_timed(self._h, float(dt), int(n), us))
-        return us[0], us[1]
+        return us[0], us[1], us[2]
 
     def moments(self) -> dict:
         m = Moments()
@@ -215,18 +215,24 @@ class Grid:
         d["status"] = rc
         return d
 
-    def set_tiles(self, k1=(0, 0), k2=(0, 0)):
-        check(lib().vp_set_tiles(self._h, C.byref(Tiles(k1[0], k1[1], k2[0], k2[1]))))
+    def set_tiles(self, k1=(0, 0)):
+        """Deposit tile shape (columns, rows)."""
+        check(lib().vp_set_tiles(self._h, C.byref(Tiles(k1[0], k1[1]))))
 
     def tiles(self) -> dict:
         t = Tiles()
         check(lib().vp_get_tiles(self._h, C.byref(t)))
-        return {"k1": (t.k1_tx, t.k1_ty), "k2": (t.k2_tx, t.k2_ty)}
+        return {"k1": (t.k1_tx, t.k1_ty)}
 
     def set_launch(self, use_graph: bool):
         check(lib().vp_set_launch(self._h, int(bool(use_graph))))
 
-    def autotune(self, dt: float) -> float:
+    def autotune(self, dt: float, cached: bool = False) -> float:
+        """Pick tile shapes by timing candidates; with cached=True reuse the
+        choice made for the same shape class if there is one (returns 0.0)."""
+        if cached:
+            check(lib().vp_autotune(self._h, float(dt), None))
+            return 0.0
         us = C.c_double()
         check(lib().vp_autotune(self._h, float(dt), C.byref(us)))
         return us.value

@@ -49,7 +49,6 @@ void raise_lds_limit() {
         if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return;
         if (lim <= (int)kDefaultLds) return;
         if (hipFuncSetAttribute(deposit_kernel(), hipFuncAttributeMaxDynamicSharedMemorySize, lim - 1024) != hipSuccess) return;
-        if (hipFuncSetAttribute(solve_kernel(), hipFuncAttributeMaxDynamicSharedMemorySize, lim - 1024) != hipSuccess) return;
         g_max_lds = (size_t)(lim - 1024);
     });
 }
@@ -82,7 +81,8 @@ Layout layout(int nx, int np) {
     L.fel_ex = take((size_t)nx * 16);
     L.fel_eq = take((size_t)np * 16);
     L.fel_state = take(kFelStateLen * 8);
-    size_t tiles = (size_t)((nx + kMinTile - 1) / kMinTile) * ((np + kMinTile - 1) / kMinTile);
+    // p-solve tiles (FEL bunching partials) and reduction blocks
+    size_t tiles = (size_t)((nx + kSolvePThreads - 1) / kSolvePThreads) * ((np + kSeg - 1) / kSeg);
     L.partial_doubles = std::max((size_t)kReduceBlocks * kMoments, 2 * tiles);
     L.partials = take(L.partial_doubles * 8);
     L.counters = take(4 * sizeof(uint32_t));
@@ -96,10 +96,11 @@ Layout layout(int nx, int np) {
 // A list of instances launched together: one instance for a grid, many for a batch.
 struct LaunchList {
     VpInst* d_inst = nullptr;
-    int32_t* d_off1 = nullptr;
-    int32_t* d_off2 = nullptr;
-    int ninst = 0, total1 = 0, total2 = 0;
-    size_t lds1 = 0, lds2 = 0;
+    int32_t* d_off1 = nullptr;  // deposit tiles
+    int32_t* d_offx = nullptr;  // x-solve tiles
+    int32_t* d_offp = nullptr;  // p-solve tiles
+    int ninst = 0, total1 = 0, totalx = 0, totalp = 0;
+    size_t lds1 = 0;
     hipStream_t stream = nullptr;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
 
@@ -110,9 +111,17 @@ struct LaunchList {
     LaunchArgs args(const int32_t* off, int total, int parity) const {
         return LaunchArgs{d_inst, off, ninst, total, parity};
     }
+    // the three kernels of one step: {kernel, off, total, lds, threads}
+    struct K { const void* fn; const int32_t* off; int total; size_t lds; int threads; };
+    void kernels(K (&k)[3]) const {
+        k[0] = K{deposit_kernel(), d_off1, total1, lds1, kDepositThreads};
+        k[1] = K{solve_x_kernel(), d_offx, totalx, 0, kSolveXThreads};
+        k[2] = K{solve_p_kernel(), d_offp, totalp, 0, kSolvePThreads};
+    }
     int enqueue_step(int parity) const {
         HIP_TRY(launch_deposit(args(d_off1, total1, parity), total1, lds1, stream));
-        HIP_TRY(launch_solve(args(d_off2, total2, parity), total2, lds2, stream));
+        HIP_TRY(launch_solve_x(args(d_offx, totalx, parity), totalx, stream));
+        HIP_TRY(launch_solve_p(args(d_offp, totalp, parity), totalp, stream));
         return VP_OK;
     }
     int build_graph(int rel_parity) {
@@ -120,17 +129,18 @@ struct LaunchList {
         HIP_TRY(hipGraphCreate(&graph, 0));
         hipGraphNode_t prev = nullptr;
         std::vector<LaunchArgs> keep;
-        keep.reserve(2 * kGraphSteps);
+        keep.reserve(3 * kGraphSteps);
+        K ks[3];
+        kernels(ks);
         for (int s = 0; s < kGraphSteps; ++s) {
-            for (int k = 0; k < 2; ++k) {
-                keep.push_back(k == 0 ? args(d_off1, total1, (rel_parity + s) & 1)
-                                      : args(d_off2, total2, (rel_parity + s) & 1));
+            for (const K& k : ks) {
+                keep.push_back(args(k.off, k.total, (rel_parity + s) & 1));
                 void* kp[1] = {&keep.back()};
                 hipKernelNodeParams p{};
-                p.func = const_cast<void*>(k == 0 ? deposit_kernel() : solve_kernel());
-                p.gridDim = dim3(k == 0 ? total1 : total2);
-                p.blockDim = dim3(k == 0 ? kDepositThreads : kSolveThreads);
-                p.sharedMemBytes = (unsigned)(k == 0 ? lds1 : lds2);
+                p.func = const_cast<void*>(k.fn);
+                p.gridDim = dim3(k.total);
+                p.blockDim = dim3(k.threads);
+                p.sharedMemBytes = (unsigned)k.lds;
                 p.kernelParams = kp;
                 p.extra = nullptr;
                 hipGraphNode_t node;
@@ -197,18 +207,12 @@ struct vp_batch {
 namespace {
 
 int validate_tiles(const vp_grid* g, const vp_tiles& t) {
-    if (t.k1_tx < kMinTile || t.k1_ty < 1 || t.k2_tx < kMinTile || t.k2_ty < kMinTile)
-        return fail(VP_EINVAL, "tile sizes below the minimum (k1_tx, k2_tx, k2_ty >= %d, k1_ty >= 1)", kMinTile);
-    if (t.k1_tx > 4096 || t.k1_ty > 1024)
-        return fail(VP_EINVAL, "deposit tile too large");
-    if (t.k2_tx > kMaxSolveTile || t.k2_ty > kMaxSolveTile)
-        return fail(VP_EINVAL, "solve tile sides must be at most %d", kMaxSolveTile);
+    if (t.k1_tx < kMinTile || t.k1_ty < 1)
+        return fail(VP_EINVAL, "deposit tile below the minimum (k1_tx >= %d, k1_ty >= 1)", kMinTile);
+    if (t.k1_tx > 4096 || t.k1_ty > 1024) return fail(VP_EINVAL, "deposit tile too large");
     if (deposit_lds_bytes(t.k1_tx, t.k1_ty) > g_max_lds)
         return fail(VP_EINVAL, "deposit tile %dx%d needs %zu bytes of LDS (limit %zu)", t.k1_tx, t.k1_ty,
                     deposit_lds_bytes(t.k1_tx, t.k1_ty), g_max_lds);
-    if (solve_lds_bytes(t.k2_tx, t.k2_ty) > g_max_lds)
-        return fail(VP_EINVAL, "solve tile %dx%d needs %zu bytes of LDS (limit %zu)", t.k2_tx, t.k2_ty,
-                    solve_lds_bytes(t.k2_tx, t.k2_ty), g_max_lds);
     (void)g;
     return VP_OK;
 }
@@ -216,8 +220,6 @@ int validate_tiles(const vp_grid* g, const vp_tiles& t) {
 vp_tiles clip_tiles(const vp_grid* g, vp_tiles t) {
     t.k1_tx = std::min(t.k1_tx, g->x.n);
     t.k1_ty = std::min(t.k1_ty, g->p.n);
-    t.k2_tx = std::min(t.k2_tx, g->x.n);
-    t.k2_ty = std::min(t.k2_ty, g->p.n);
     return t;
 }
 
@@ -229,20 +231,19 @@ int upload_inst(vp_grid* g) {
     I.k1_ty = t.k1_ty;
     I.k1_tiles_x = (g->x.n + t.k1_tx - 1) / t.k1_tx;
     I.k1_tiles = I.k1_tiles_x * ((g->p.n + t.k1_ty - 1) / t.k1_ty);
-    I.k2_tx = t.k2_tx;
-    I.k2_ty = t.k2_ty;
-    I.k2_tiles_x = (g->x.n + t.k2_tx - 1) / t.k2_tx;
-    I.k2_tiles = I.k2_tiles_x * ((g->p.n + t.k2_ty - 1) / t.k2_ty);
+    const int ny64 = (g->p.n + kSolveXThreads - 1) / kSolveXThreads;
+    I.kx_tiles = ((g->x.n + kSeg - 1) / kSeg) * ny64;
+    I.k2_tiles = ((g->x.n + kSolvePThreads - 1) / kSolvePThreads) * ((g->p.n + kSeg - 1) / kSeg);
     I.parity0 = 0;
-    int32_t off[4] = {0, I.k1_tiles, 0, I.k2_tiles};
+    int32_t off[6] = {0, I.k1_tiles, 0, I.kx_tiles, 0, I.k2_tiles};
     HIP_TRY(hipMemcpyAsync(g->list.d_inst, &I, sizeof(VpInst), hipMemcpyHostToDevice, g->stream));
     HIP_TRY(hipMemcpyAsync(g->list.d_off1, off, sizeof off, hipMemcpyHostToDevice, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
     g->list.ninst = 1;
     g->list.total1 = I.k1_tiles;
-    g->list.total2 = I.k2_tiles;
+    g->list.totalx = I.kx_tiles;
+    g->list.totalp = I.k2_tiles;
     g->list.lds1 = deposit_lds_bytes(t.k1_tx, t.k1_ty);
-    g->list.lds2 = solve_lds_bytes(t.k2_tx, t.k2_ty);
     g->list.drop_graphs();
     return VP_OK;
 }
@@ -387,7 +388,7 @@ int prepare(vp_grid* g, double dt) {
 }
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, long>, vp_tiles> g_tune_cache;
+std::map<std::tuple<int, int, int, long>, vp_tiles> g_tune_cache;  // shape class -> tiles
 
 }  // namespace
 
@@ -416,11 +417,12 @@ int vp_create_grid(const vp_grid_desc* d, vp_grid** out) {
     g->stream = reinterpret_cast<hipStream_t>(d->stream);
     g->ws = reinterpret_cast<char*>(d->workspace);
     g->L = L;
-    g->tiles = vp_tiles{64, 32, 64, 32};
+    g->tiles = vp_tiles{64, 32};
     g->list.stream = g->stream;
     g->list.d_inst = g->at<VpInst>(L.inst);
     g->list.d_off1 = g->at<int32_t>(L.off);
-    g->list.d_off2 = g->at<int32_t>(L.off) + 2;
+    g->list.d_offx = g->at<int32_t>(L.off) + 2;
+    g->list.d_offp = g->at<int32_t>(L.off) + 4;
     VpInst& I = g->inst;
     I.w[0] = g->at<float>(L.w0);
     I.w[1] = g->at<float>(L.w1);
@@ -548,35 +550,35 @@ int vp_step(vp_grid* g, double dt, int64_t nsteps) {
     return VP_OK;
 }
 
-int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]) {
+int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[3]) {
     if (!g || !us) return fail(VP_EINVAL, "null argument");
     if (nsteps <= 0) return fail(VP_EINVAL, "need at least one step");
     if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
     int rc = prepare(g, dt);
     if (rc) return rc;
-    std::vector<hipEvent_t> ev(3 * nsteps);
+    std::vector<hipEvent_t> ev(4 * nsteps);
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
     const LaunchList& L = g->list;
     for (int64_t s = 0; s < nsteps; ++s) {
         const int par = (int)((g->parity + s) & 1);
-        HIP_TRY(hipEventRecord(ev[3 * s], g->stream));
+        HIP_TRY(hipEventRecord(ev[4 * s], g->stream));
         HIP_TRY(launch_deposit(L.args(L.d_off1, L.total1, par), L.total1, L.lds1, g->stream));
-        HIP_TRY(hipEventRecord(ev[3 * s + 1], g->stream));
-        HIP_TRY(launch_solve(L.args(L.d_off2, L.total2, par), L.total2, L.lds2, g->stream));
-        HIP_TRY(hipEventRecord(ev[3 * s + 2], g->stream));
+        HIP_TRY(hipEventRecord(ev[4 * s + 1], g->stream));
+        HIP_TRY(launch_solve_x(L.args(L.d_offx, L.totalx, par), L.totalx, g->stream));
+        HIP_TRY(hipEventRecord(ev[4 * s + 2], g->stream));
+        HIP_TRY(launch_solve_p(L.args(L.d_offp, L.totalp, par), L.totalp, g->stream));
+        HIP_TRY(hipEventRecord(ev[4 * s + 3], g->stream));
     }
     HIP_TRY(hipEventSynchronize(ev.back()));
-    double t0 = 0.0, t1 = 0.0;
-    for (int64_t s = 0; s < nsteps; ++s) {
-        float a = 0.f, b = 0.f;
-        HIP_TRY(hipEventElapsedTime(&a, ev[3 * s], ev[3 * s + 1]));
-        HIP_TRY(hipEventElapsedTime(&b, ev[3 * s + 1], ev[3 * s + 2]));
-        t0 += a;
-        t1 += b;
-    }
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int64_t s = 0; s < nsteps; ++s)
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev[4 * s + k], ev[4 * s + k + 1]));
+            t[k] += ms;
+        }
     for (auto& e : ev) (void)hipEventDestroy(e);
-    us[0] = 1000.0 * t0 / nsteps;
-    us[1] = 1000.0 * t1 / nsteps;
+    for (int k = 0; k < 3; ++k) us[k] = 1000.0 * t[k] / nsteps;
     g->parity = (int)((g->parity + nsteps) & 1);
     g->step += nsteps;
     return VP_OK;
@@ -620,8 +622,6 @@ int vp_set_tiles(vp_grid* g, const vp_tiles* t) {
     vp_tiles n = g->tiles;
     if (t->k1_tx) n.k1_tx = t->k1_tx;
     if (t->k1_ty) n.k1_ty = t->k1_ty;
-    if (t->k2_tx) n.k2_tx = t->k2_tx;
-    if (t->k2_ty) n.k2_ty = t->k2_ty;
     int rc = validate_tiles(g, n);
     if (rc) return rc;
     g->tiles = n;
@@ -646,9 +646,12 @@ int vp_autotune(vp_grid* g, double dt, double* best_us) {
     if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
     int rc = prepare(g, dt);
     if (rc) return rc;
+    // shape class: kind, half-octave buckets of the axis lengths and of the
+    // largest displacement in cells
     const double hx = spacing(g->x), hp = spacing(g->p);
-    const long disp = lround(fabs(dt) * (std::max(fabs(g->p.lo), fabs(g->p.hi)) / hx + fabs(g->ham.a) / hp));
-    const auto key = std::make_tuple((int)g->ham.kind, g->x.n, g->p.n, disp);
+    const double disp = fabs(dt) * (std::max(fabs(g->p.lo), fabs(g->p.hi)) / hx + fabs(g->ham.a) / hp);
+    const auto key = std::make_tuple((int)g->ham.kind, (int)lround(2.0 * log2((double)g->x.n)),
+                                     (int)lround(2.0 * log2((double)g->p.n)), (long)lround(2.0 * log2(1.0 + disp)));
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -691,20 +694,12 @@ int vp_autotune(vp_grid* g, double dt, double* best_us) {
         return VP_OK;
     };
     const int k1c[][2] = {{64, 16}, {64, 32}, {64, 64}, {128, 16}, {128, 32}, {128, 64}, {256, 16}, {256, 32}};
-    const int k2c[][2] = {{32, 32}, {32, 64}, {64, 32}, {64, 64}, {128, 32}, {96, 64}, {128, 64}};
     vp_tiles best = g->tiles;
     float best_t = 1e30f;
     for (auto& c : k1c) {
         vp_tiles t = best;
         t.k1_tx = c[0];
         t.k1_ty = c[1];
-        float us;
-        if (time_tiles(t, &us) == VP_OK && us < best_t) { best_t = us; best = t; }
-    }
-    for (auto& c : k2c) {
-        vp_tiles t = best;
-        t.k2_tx = c[0];
-        t.k2_ty = c[1];
         float us;
         if (time_tiles(t, &us) == VP_OK && us < best_t) { best_t = us; best = t; }
     }
@@ -745,15 +740,15 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
         HIP_TRY(hipStreamSynchronize(grids[k]->stream));
     }
     std::vector<VpInst> insts(n);
-    std::vector<int32_t> off1(n + 1, 0), off2(n + 1, 0);
-    size_t lds1 = 0, lds2 = 0;
+    std::vector<int32_t> off1(n + 1, 0), offx(n + 1, 0), offp(n + 1, 0);
+    size_t lds1 = 0;
     for (int k = 0; k < n; ++k) {
         insts[k] = grids[k]->inst;
         insts[k].parity0 = grids[k]->parity;
         off1[k + 1] = off1[k] + insts[k].k1_tiles;
-        off2[k + 1] = off2[k] + insts[k].k2_tiles;
+        offx[k + 1] = offx[k] + insts[k].kx_tiles;
+        offp[k + 1] = offp[k] + insts[k].k2_tiles;
         lds1 = std::max(lds1, deposit_lds_bytes(insts[k].k1_tx, insts[k].k1_ty));
-        lds2 = std::max(lds2, solve_lds_bytes(insts[k].k2_tx, insts[k].k2_ty));
     }
     vp_batch* b = new vp_batch();
     b->grids.assign(grids, grids + n);
@@ -761,20 +756,21 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
     L.stream = s;
     L.ninst = n;
     L.total1 = off1[n];
-    L.total2 = off2[n];
+    L.totalx = offx[n];
+    L.totalp = offp[n];
     L.lds1 = lds1;
-    L.lds2 = lds2;
     hipError_t e = hipMalloc(&L.d_inst, sizeof(VpInst) * n);
-    if (e == hipSuccess) e = hipMalloc(&L.d_off1, sizeof(int32_t) * (n + 1));
-    if (e == hipSuccess) e = hipMalloc(&L.d_off2, sizeof(int32_t) * (n + 1));
+    if (e == hipSuccess) e = hipMalloc(&L.d_off1, sizeof(int32_t) * 3 * (n + 1));
+    L.d_offx = L.d_off1 + (n + 1);
+    L.d_offp = L.d_off1 + 2 * (n + 1);
     if (e == hipSuccess) e = hipMemcpyAsync(L.d_inst, insts.data(), sizeof(VpInst) * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(L.d_off1, off1.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(L.d_off2, off2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.d_offx, offx.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.d_offp, offp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipFree(L.d_inst);
         (void)hipFree(L.d_off1);
-        (void)hipFree(L.d_off2);
         delete b;
         return fail(VP_EHIP, "batch setup: %s", hipGetErrorString(e));
     }
@@ -803,7 +799,6 @@ int vp_batch_destroy(vp_batch* b) {
     b->list.drop_graphs();
     (void)hipFree(b->list.d_inst);
     (void)hipFree(b->list.d_off1);
-    (void)hipFree(b->list.d_off2);
     for (auto* g : b->grids) g->in_batch = false;
     delete b;
     return VP_OK;

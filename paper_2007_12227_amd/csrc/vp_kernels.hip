@@ -86,79 +86,105 @@ __device__ inline int wrap_index(int i, int n, float inv_n) {
     return r;
 }
 
-// In-place solve of M y = b, M = tridiag(1/6, 2/3, 1/6), along n elements of L
-// (stride apart), written as
+// LU coefficients at node g from the open edge: tabulated below kEdge, the
+// interior constant beyond.  Branch-free: the (clamped) table read is
+// unconditional and a select picks the value.
+template <bool EDGE>
+__device__ inline float lu_m(int g, const float2* edge) {
+    if (!EDGE) return kMinf;
+    const float t = edge[min(g, kEdge - 1)].x;
+    return g < kEdge ? t : kMinf;
+}
+template <bool EDGE>
+__device__ inline float lu_dinv(int g, const float2* edge) {
+    if (!EDGE) return kMinf;
+    const float t = edge[min(g, kEdge - 1)].y;
+    return g < kEdge ? t : kMinf;
+}
+
+// Solve M y = b, M = tridiag(1/6, 2/3, 1/6), along one line of n <= kLine
+// values v[0..n) (registers; entries past n are zero), written as
 //     y = b - T^{-1} (D2 b),   T = 6 M = tridiag(1, 4, 1),  D2 b = b[k-1] - 2 b[k] + b[k+1]
 // (T = 6 I + D2, so 6 T^{-1} = I - T^{-1} D2).  The LU recursions of T then only
 // carry the correction T^{-1} D2 b, so their FP32 rounding (whose fixed point
-// is biased on slowly varying data) acts on a term much smaller than b, and
-// the mass the line carries is kept to ~1e-10 per step instead of ~1e-8.
+// is biased on slowly varying data) acts on a term much smaller than b: the
+// mass a line carries is kept to ~1e-10 per step instead of ~1e-8.
 // Neighbours outside [0, n) count as zero: exact at an open edge (the
 // truncated M), and a cut inside the lattice only disturbs the halo.
-// first = index of L[0] from the open edge if below kEdge (exact tabulated
-// edge coefficients), else kEdge (interior constants).  Z (same layout as L)
-// holds the forward sweep.  Loads are issued eight elements ahead.
+// first = index of v[0] from the open edge when below kEdge (EDGE: the exact
+// tabulated LU coefficients apply there), interior constants elsewhere.
+// The solution replaces v.  Fixed length, fully unrolled, no branches.
 template <bool EDGE>
-__device__ inline float lu_m(int g, const float2* edge) { return (EDGE && g < kEdge) ? edge[g].x : kMinf; }
-template <bool EDGE>
-__device__ inline float lu_dinv(int g, const float2* edge) { return (EDGE && g < kEdge) ? edge[g].y : kMinf; }
-
-template <bool EDGE>
-__device__ inline void solve_line_t(float* L, float* Z, int stride, int n, int first, const float2* edge) {
-    float prev = 0.0f, cur = L[0], acc = 0.0f;
-    int k = 0;
-    for (; k + 8 < n; k += 8) {
-        float nx[8];
+__device__ inline void line_solve(float (&v)[kLine], int n, int first, const float2* edge) {
+    float z[kLine];
+    float acc = 0.0f;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) nx[u] = L[(k + 1 + u) * stride];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const float m = lu_m<EDGE>(first + k + u, edge);
-            acc = fmaf(-m, acc, (prev + nx[u]) - 2.0f * cur);
-            Z[(k + u) * stride] = acc;
-            prev = cur;
-            cur = nx[u];
-        }
-    }
-    for (; k < n; ++k) {
-        const float next = k + 1 < n ? L[(k + 1) * stride] : 0.0f;
-        const float m = lu_m<EDGE>(first + k, edge);
-        acc = fmaf(-m, acc, (prev + next) - 2.0f * cur);
-        Z[k * stride] = acc;
-        prev = cur;
-        cur = next;
+    for (int k = 0; k < kLine; ++k) {
+        const float r = ((k > 0 ? v[k - 1] : 0.0f) + (k + 1 < kLine ? v[k + 1] : 0.0f)) - 2.0f * v[k];
+        acc = fmaf(-lu_m<EDGE>(first + k, edge), acc, r);
+        acc = k < n ? acc : 0.0f;
+        z[k] = acc;
     }
     float c = 0.0f;
-    k = n - 1;
-    for (; k >= 7; k -= 8) {
-        float zv[8], bv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            zv[u] = Z[(k - u) * stride];
-            bv[u] = L[(k - u) * stride];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const float dinv = lu_dinv<EDGE>(first + k - u, edge);
-            c = (zv[u] - c) * dinv;
-            L[(k - u) * stride] = bv[u] - c;
-        }
-    }
-    for (; k >= 0; --k) {
-        const float dinv = lu_dinv<EDGE>(first + k, edge);
-        c = (Z[k * stride] - c) * dinv;
-        L[k * stride] = L[k * stride] - c;
+    for (int k = kLine - 1; k >= 0; --k) {
+        c = (z[k] - c) * lu_dinv<EDGE>(first + k, edge);
+        v[k] -= c;
     }
 }
 
-// Lines that start kEdge or more nodes from an open edge (all lines of a
-// periodic axis) use only the interior constants: no table reads in the loop.
-__device__ inline void solve_line(float* L, float* Z, int stride, int n, int first, const float2* edge) {
-    if (first >= kEdge) solve_line_t<false>(L, Z, stride, n, first, edge);
-    else solve_line_t<true>(L, Z, stride, n, first, edge);
+__device__ inline void line_solve_any(float (&v)[kLine], int n, int first, const float2* edge) {
+    if (first >= kEdge) line_solve<false>(v, n, first, edge);
+    else line_solve<true>(v, n, first, edge);
 }
 
 }  // namespace
+
+// Push one node (source row j, unwrapped column ii, weight w already scaled to
+// fixed point) and add its 16 B-spline taps into the LDS tile.
+__device__ inline void deposit_node(long long* acc, int j, int ii, float w, float4 tx, float4 tp, int kind,
+                                    float alpha, float beta, float kd, int X0, int Y0, int ldw, int cmax,
+                                    int rmax) {
+    if (w == 0.0f) return;
+    int ku, kv;
+    float fu, fv;
+    if (kind == kSho) {
+        float su, eu, sv, ev;
+        two_sum(tx.x, tp.x, su, eu);
+        two_sum(tx.z, tp.z, sv, ev);
+        split_cell(su, eu + (tx.y + tp.y), ku, fu);
+        split_cell(sv, ev + (tx.w + tp.w), kv, fv);
+    } else {
+        // phase phi_i + q_j from the per-axis sine/cosine tables
+        const float cph = tx.y * tp.w - tx.x * tp.z;
+        const float sph = tx.x * tp.w + tx.y * tp.z;
+        const float dv = alpha * cph + beta * sph;
+        float su, eu;
+        two_sum(tp.x, dv * kd, su, eu);
+        split_cell(su, eu + tp.y, ku, fu);
+        split_cell(dv, 0.0f, kv, fv);
+    }
+    float bx[4], bp[4];
+    bspline_taps(fu, bx);
+    bspline_taps(fv, bp);
+    // tap (q, r) lands on row j + kv - 1 + q, column ii + ku - 1 + r
+    const int c0 = clampi(ii + ku - 1 - X0 + kPad, 0, cmax);
+    const int r0 = clampi(j + kv - 1 - Y0 + kPad, 0, rmax);
+    long long* base = acc + r0 * ldw + c0;
+    // tap value w * bp * bx formed in FP64 and rounded once, exactly, into
+    // the fixed-point tile sum: the deposit adds no FP32 product rounding to
+    // the state (the FEL instability amplifies it)
+    double bxd[4];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) bxd[rr] = (double)bx[rr];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double wq = (double)w * (double)bp[q];
+        long long* row = base + q * ldw;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) atomicAdd((unsigned long long*)(row + rr), fix64(wq * bxd[rr]));
+    }
+}
 
 // ---------------------------------------------------------------------------
 // k_deposit: push every node of the tile's source box and scatter its weight
@@ -224,55 +250,32 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
         const float scale = I.fix_scale, inv_scale = I.fix_inv;  // exact powers of two
         const int nsrc_live = scale > 0.0f ? nsrc : 0;
 
-        for (int s = threadIdx.x; s < nsrc_live; s += blockDim.x) {
-            int r = (int)(((float)s + 0.5f) * inv_bw);
-            int c = s - r * bw;
-            if (c < 0) { c += bw; --r; }
-            if (c >= bw) { c -= bw; ++r; }
-            const int j = by0 + r;
-            const int ii = bx0 + c;  // unwrapped source column
-            const int i = periodic ? wrap_index(ii, nx, inv_nx) : ii;
-            const float w = w_in[(size_t)j * nx + i] * scale;
-            if (w == 0.0f) continue;
-            const float4 tx = I.tab_x[i];
-            const float4 tp = I.tab_p[j];
-            int ku, kv;
-            float fu, fv;
-            if (kind == kSho) {
-                float su, eu, sv, ev;
-                two_sum(tx.x, tp.x, su, eu);
-                two_sum(tx.z, tp.z, sv, ev);
-                split_cell(su, eu + (tx.y + tp.y), ku, fu);
-                split_cell(sv, ev + (tx.w + tp.w), kv, fv);
-            } else {
-                // phase phi_i + q_j from the per-axis sine/cosine tables
-                const float cph = tx.y * tp.w - tx.x * tp.z;
-                const float sph = tx.x * tp.w + tx.y * tp.z;
-                const float dv = alpha * cph + beta * sph;
-                float su, eu;
-                two_sum(tp.x, dv * kd, su, eu);
-                split_cell(su, eu + tp.y, ku, fu);
-                split_cell(dv, 0.0f, kv, fv);
+        // Four sources per thread and iteration, every load issued before any
+        // use, so an iteration waits for one memory latency, not a chain.
+        constexpr int kU = 4;
+        for (int s0 = threadIdx.x; s0 < nsrc_live; s0 += kU * blockDim.x) {
+            int jj[kU], iiu[kU];
+            float wv[kU];
+            float4 txv[kU], tpv[kU];
+#pragma unroll
+            for (int h = 0; h < kU; ++h) {
+                const int s = min(s0 + h * (int)blockDim.x, nsrc_live - 1);
+                int r = (int)(((float)s + 0.5f) * inv_bw);
+                int c = s - r * bw;
+                if (c < 0) { c += bw; --r; }
+                if (c >= bw) { c -= bw; ++r; }
+                jj[h] = by0 + r;
+                iiu[h] = bx0 + c;  // unwrapped source column
+                const int i = periodic ? wrap_index(iiu[h], nx, inv_nx) : iiu[h];
+                wv[h] = w_in[(size_t)jj[h] * nx + i];
+                txv[h] = I.tab_x[i];
+                tpv[h] = I.tab_p[jj[h]];
             }
-            float bx[4], bp[4];
-            bspline_taps(fu, bx);
-            bspline_taps(fv, bp);
-            // tap (q, r) lands on row j + kv - 1 + q, column ii + ku - 1 + r
-            const int c0 = clampi(ii + ku - 1 - X0 + kPad, 0, cmax);
-            const int r0 = clampi(j + kv - 1 - Y0 + kPad, 0, rmax);
-            long long* base = acc + r0 * ldw + c0;
-            // tap value w * bp * bx formed in FP64 and rounded once, exactly,
-            // into the fixed-point tile sum: the deposit adds no FP32 product
-            // rounding to the state (the FEL instability amplifies it)
-            double bxd[4];
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) bxd[rr] = (double)bx[rr];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double wq = (double)w * (double)bp[q];
-                long long* row = base + q * ldw;
-#pragma unroll
-                for (int rr = 0; rr < 4; ++rr) atomicAdd((unsigned long long*)(row + rr), fix64(wq * bxd[rr]));
+            for (int h = 0; h < kU; ++h) {
+                if (s0 + h * (int)blockDim.x >= nsrc_live) break;
+                deposit_node(acc, jj[h], iiu[h], wv[h] * scale, txv[h], tpv[h], kind, alpha, beta, kd, X0, Y0,
+                             ldw, cmax, rmax);
             }
         }
         __syncthreads();
@@ -288,20 +291,26 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// k_solve: w_out = (M_x^{-1} (x) M_p^{-1}) b on one tile, one line at a time
-// (solve_line): the LU recursions of T = tridiag(1,4,1),
+// The mass-matrix solve (M_x^{-1} (x) M_p^{-1}) b in two kernels, one lattice
+// line segment per lane (line_solve): LU recursions of T = tridiag(1,4,1),
 //   forward  z_k = r_k - m_k z_{k-1},   backward c_k = (z_k - c_{k+1}) / d_k,
 // with exact per-node (m_k, 1/d_k) near an open edge (so the true edges are
-// exact) and the interior constants elsewhere.  Where the tile's halo is cut
-// inside the lattice the recursion starts from zero; the error decays by
-// 2 - sqrt 3 per node and is ~7e-10 after the 16-node halo.
+// exact) and the interior constants elsewhere.  A segment carries a 16-node
+// halo on each side; where the halo is cut inside the lattice the recursion
+// starts from zero, an error that decays by 2 - sqrt 3 per node and is ~7e-10
+// at the segment.
+//  k_solve_x: b -> the old state buffer (free once the deposit has read it).
+//    A wavefront owns 64 rows x kSeg columns; the rows plus halos are staged
+//    in LDS (coalesced) and each lane solves one row from registers.
+//  k_solve_p: that buffer -> the new state.  A lane owns kSeg rows of one
+//    column and streams the column plus halos straight from global memory
+//    into registers (coalesced across lanes); no LDS.  For the FEL its
+//    epilogue also forms the FP64 bunching of the new state.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
-    extern __shared__ float lds[];
+__global__ __launch_bounds__(kSolveXThreads) void k_solve_x(LaunchArgs A) {
+    __shared__ float lds[kSolveXThreads * (kLine + 1)];
     __shared__ int s_d;
-    __shared__ double s_red[2][kSolveThreads / 64];
-    __shared__ int s_last;
-    __shared__ float2 s_edge_x[kEdge], s_edge_p[kEdge];
+    __shared__ float2 s_edge[kEdge];
 
     for (int item = blockIdx.x; item < A.total; item += gridDim.x) {
         if (threadIdx.x == 0) s_d = find_instance(A.off, A.ninst, item);
@@ -311,69 +320,108 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
         const int t = item - A.off[d];
         const int nx = I.push.nx, np = I.push.np;
         const bool periodic = I.push.x_periodic != 0;
-        const int tyi = t / I.k2_tiles_x, txi = t - tyi * I.k2_tiles_x;
-        const int X0 = txi * I.k2_tx, X1 = min(X0 + I.k2_tx, nx);
-        const int Y0 = tyi * I.k2_ty, Y1 = min(Y0 + I.k2_ty, np);
+        const int tiles_x = (nx + kSeg - 1) / kSeg;
+        const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
+        const int X0 = txi * kSeg, X1 = min(X0 + kSeg, nx);
+        const int Y0 = tyi * kSolveXThreads, Y1 = min(Y0 + kSolveXThreads, np);
         const int rc0 = periodic ? X0 - kHalo : max(0, X0 - kHalo);
         const int rc1 = periodic ? X1 + kHalo : min(nx, X1 + kHalo);
-        const int rr0 = max(0, Y0 - kHalo), rr1 = min(np, Y1 + kHalo);
-        const int RW = rc1 - rc0, RH = rr1 - rr0;
-        const int ldw = solve_ldw(I.k2_tx);
-        const int zoff = ldw * (I.k2_ty + 2 * kHalo);  // second buffer: the forward sweeps
+        const int RW = rc1 - rc0, th = Y1 - Y0, tw = X1 - X0;
         const int par = (I.parity0 + A.parity) & 1;
-        float* __restrict__ w_out = I.w[par ^ 1];
-        const float* __restrict__ b = I.b;
+        const float* __restrict__ src = I.b;
+        float* __restrict__ dst = I.w[par];  // the state just deposited from
         const float inv_nx = 1.0f / (float)nx;
-        const float inv_rw = 1.0f / (float)RW;
+        constexpr int ldw = kLine + 1;
 
-        // LU coefficients differ from the interior constant only within
-        // kEdge nodes of an open axis' first node; stage those in LDS.
-        if (threadIdx.x < kEdge) {
-            s_edge_p[threadIdx.x] = I.coef_p[min((int)threadIdx.x, np - 1)];
-            s_edge_x[threadIdx.x] = periodic ? make_float2(kMinf, kMinf) : I.coef_x[min((int)threadIdx.x, nx - 1)];
-        }
-        for (int k = threadIdx.x; k < RW * RH; k += blockDim.x) {
-            int r = (int)(((float)k + 0.5f) * inv_rw);
-            int c = k - r * RW;
-            if (c < 0) { c += RW; --r; }
-            if (c >= RW) { c -= RW; ++r; }
-            int gc = rc0 + c;
+        if (threadIdx.x < kEdge)
+            s_edge[threadIdx.x] = periodic ? make_float2(kMinf, kMinf) : I.coef_x[min((int)threadIdx.x, nx - 1)];
+        // stage rows Y0..Y1, columns rc0..rc1: lane = column, loop over rows
+        for (int c = threadIdx.x; c < kLine; c += blockDim.x) {
+            int gc = rc0 + min(c, RW - 1);
             if (periodic) gc = wrap_index(gc, nx, inv_nx);
-            lds[r * ldw + c] = b[(size_t)(rr0 + r) * nx + gc];
+            const float* col = src + (size_t)Y0 * nx + gc;
+#pragma unroll 16
+            for (int r = 0; r < th; ++r) lds[r * ldw + c] = c < RW ? col[(size_t)r * nx] : 0.0f;
         }
         __syncthreads();
 
-        // x lines: one thread per row of the region
-        for (int r = threadIdx.x; r < RH; r += blockDim.x) {
-            float* L = lds + r * ldw;
-            // a periodic axis, or a region starting kEdge or more nodes from
-            // the open edge, only sees the interior constants
-            const bool edge = !periodic && rc0 < kEdge;
-            solve_line(L, L + zoff, 1, RW, edge ? rc0 : kEdge, s_edge_x);
+        const int first = (!periodic && rc0 < kEdge) ? rc0 : kEdge;
+        if ((int)threadIdx.x < th) {
+            float v[kLine];
+            float* row = lds + threadIdx.x * ldw;
+#pragma unroll
+            for (int k = 0; k < kLine; ++k) v[k] = row[k];
+            line_solve_any(v, RW, first, s_edge);
+#pragma unroll
+            for (int k = 0; k < kLine; ++k) row[k] = v[k];
         }
         __syncthreads();
 
-        // p lines: one thread per output column
-        const int tw = X1 - X0;
+        for (int c = threadIdx.x; c < tw; c += blockDim.x) {
+            float* col = dst + (size_t)Y0 * nx + X0 + c;
+            const int lc = X0 - rc0 + c;
+#pragma unroll 16
+            for (int r = 0; r < th; ++r) col[(size_t)r * nx] = lds[r * ldw + lc];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kSolvePThreads) void k_solve_p(LaunchArgs A) {
+    __shared__ int s_d;
+    __shared__ int s_last;
+    __shared__ float2 s_edge[kEdge];
+    __shared__ double s_red[2][kSolvePThreads / 64];
+
+    for (int item = blockIdx.x; item < A.total; item += gridDim.x) {
+        if (threadIdx.x == 0) s_d = find_instance(A.off, A.ninst, item);
+        __syncthreads();
+        const int d = __builtin_amdgcn_readfirstlane(s_d);
+        const VpInst& I = A.inst[d];
+        const int t = item - A.off[d];
+        const int nx = I.push.nx, np = I.push.np;
+        const int tiles_x = (nx + kSolvePThreads - 1) / kSolvePThreads;
+        const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
+        const int col = txi * kSolvePThreads + threadIdx.x;
+        const int Y0 = tyi * kSeg, Y1 = min(Y0 + kSeg, np);
+        const int rr0 = max(0, Y0 - kHalo), rr1 = min(np, Y1 + kHalo);
+        const int RH = rr1 - rr0;
+        const int par = (I.parity0 + A.parity) & 1;
+        const float* __restrict__ src = I.w[par];
+        float* __restrict__ dst = I.w[par ^ 1];
+
+        if (threadIdx.x < kEdge) s_edge[threadIdx.x] = I.coef_p[min((int)threadIdx.x, np - 1)];
+        __syncthreads();
+
         const bool fel = I.push.kind == kFel;
         double acc_re = 0.0, acc_im = 0.0;
-        for (int c = threadIdx.x; c < tw; c += blockDim.x) {
-            const int lc = X0 - rc0 + c;
-            solve_line(lds + lc, lds + zoff + lc, ldw, RH, rr0 < kEdge ? rr0 : kEdge, s_edge_p);
+        if (col < nx) {
+            float v[kLine];
+            const float* c0 = src + (size_t)rr0 * nx + col;
+#pragma unroll
+            for (int k = 0; k < kLine; ++k) {
+                const float x = c0[(size_t)min(k, RH - 1) * nx];
+                v[k] = k < RH ? x : 0.0f;
+            }
+            line_solve_any(v, RH, rr0 < kEdge ? rr0 : kEdge, s_edge);
+            float* o = dst + col;
+            const int lo = Y0 - rr0;
             double cre = 0.0, cim = 0.0;
-            for (int gr = Y0; gr < Y1; ++gr) {
-                const float out = lds[(gr - rr0) * ldw + lc];
-                w_out[(size_t)gr * nx + X0 + c] = out;
-                if (fel) {
-                    const double2 e = I.fel_eq[gr];
-                    cre += (double)out * e.x;
-                    cim -= (double)out * e.y;
+#pragma unroll
+            for (int k = 0; k < kLine; ++k) {
+                if (k >= lo && k < lo + (Y1 - Y0)) {
+                    o[(size_t)(rr0 + k) * nx] = v[k];
+                    if (fel) {
+                        const double2 e = I.fel_eq[rr0 + k];  // times e^{-i q}
+                        cre += (double)v[k] * e.x;
+                        cim -= (double)v[k] * e.y;
+                    }
                 }
             }
             if (fel) {
-                const double2 e = I.fel_ex[X0 + c];  // times e^{-i phi}
-                acc_re += cre * e.x + cim * e.y;
-                acc_im += cim * e.x - cre * e.y;
+                const double2 e = I.fel_ex[col];  // times e^{-i phi}
+                acc_re = cre * e.x + cim * e.y;
+                acc_im = cim * e.x - cre * e.y;
             }
         }
 
@@ -412,7 +460,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
                 if (lane == 0) { s_red[0][wid] = re; s_red[1][wid] = im; }
                 __syncthreads();
                 if (threadIdx.x == 0) {
-                    re = 0.0; im = 0.0;
+                    re = 0.0;
+                    im = 0.0;
                     for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { re += s_red[0][k]; im += s_red[1][k]; }
                     double* st = I.fel_state;
                     const double inv_n0 = 1.0 / st[kN0];
@@ -524,8 +573,13 @@ hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_solve(const LaunchArgs& a, int grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL(k_solve, dim3(grid), dim3(kSolveThreads), lds, s, a);
+hipError_t launch_solve_x(const LaunchArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_solve_x, dim3(grid), dim3(kSolveXThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_p(const LaunchArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_solve_p, dim3(grid), dim3(kSolvePThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -535,6 +589,7 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
 }
 
 const void* deposit_kernel() { return reinterpret_cast<const void*>(&k_deposit); }
-const void* solve_kernel() { return reinterpret_cast<const void*>(&k_solve); }
+const void* solve_x_kernel() { return reinterpret_cast<const void*>(&k_solve_x); }
+const void* solve_p_kernel() { return reinterpret_cast<const void*>(&k_solve_p); }
 
 }  // namespace vp
