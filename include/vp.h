@@ -42,6 +42,7 @@ extern "C" {
 #define VP_EHIP (-4)         /* a HIP runtime call failed */
 #define VP_EUNSUPPORTED (-5) /* valid for the method but not built here */
 #define VP_ENONFINITE (-6)   /* the state holds NaN or Inf */
+#define VP_ERANGE (-7)       /* a deposit cell sum left the fixed-point range */
 
 /* Hamiltonian kinds (Sec. "Numerical Examples") */
 #define VP_H_FREE 0       /* free streaming x' = p */
@@ -103,7 +104,11 @@ typedef struct {
  *  energy   = integral of H f; exact tent integrals of p^2, x^2 and cos x
  *  FEL: A, bunching <e^{-i psi}> at the lattice phases, and
  *       fel_invariant = |A|^2 + N0^{-1} sum_j w_j eta_j (conserved by the step)
- *  nonfinite = number of NaN/Inf weights (the call then returns VP_ENONFINITE). */
+ *  nonfinite = number of NaN/Inf weights (the call then returns VP_ENONFINITE).
+ *  The call returns VP_ERANGE (after filling *out) if, since the density was
+ *  set, a deposit cell sum exceeded 2^6 x 2^e, max|w0| < 2^e: the deposit
+ *  sums cells as fixed point at 2^(e-40), exact up to 2^7 x 2^e.  The
+ *  transported weights of a conservative step stay near max|w0|. */
 typedef struct {
     double sum_w, mass, neg_mass, l1, entropy, mean_p, energy;
     double A_re, A_im, bunch_re, bunch_im, fel_invariant;
@@ -133,7 +138,8 @@ int vp_destroy_grid(vp_grid* g);
 int vp_set_hamiltonian(vp_grid* g, const vp_hamiltonian* h);
 
 /* Set the weights w (n_p*n_x floats; device pointer if on_device, else host).
- * Records N0 = sum w (FP64) and resets the step counter. */
+ * Records N0 = sum w (FP64) and max|w| (the deposit's fixed-point scale),
+ * clears the range flag and resets the step counter. */
 int vp_set_density(vp_grid* g, const float* w, int32_t on_device);
 
 /* Copy the current weights out (n_p*n_x floats). */

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvp.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "vp.h")
 
-VP_OK, VP_EINVAL, VP_ENOMEM, VP_ESTATE, VP_EHIP, VP_EUNSUPPORTED, VP_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+VP_OK, VP_EINVAL, VP_ENOMEM, VP_ESTATE, VP_EHIP, VP_EUNSUPPORTED, VP_ENONFINITE, VP_ERANGE = 0, -1, -2, -3, -4, -5, -6, -7
 H_FREE, H_SHO_EXACT, H_PENDULUM, H_FEL = 0, 1, 2, 3
 
 
@@ -210,7 +210,7 @@ class Grid:
         rc = lib().vp_moments(self._h, C.byref(m))
         d = {f: getattr(m, f) for f in MOMENT_FIELDS}
         d["step"], d["nonfinite"] = m.step, m.nonfinite
-        if rc not in (VP_OK, VP_ENONFINITE):
+        if rc not in (VP_OK, VP_ENONFINITE, VP_ERANGE):
             check(rc)
         d["status"] = rc
         return d

@@ -507,7 +507,7 @@ int vp_set_density(vp_grid* g, const float* w, int32_t on_device) {
     HIP_TRY(hipStreamSynchronize(g->stream));
     g->N0 = m[0];
     {
-        // fixed-point scale of the deposit tile sums: 2^(40 - e), max|w0| < 2^e
+        // fixed-point scale of the deposit cell sums: 2^(40 - e), max|w0| < 2^e
         const double wmax = m[8];
         int e = 0;
         if (wmax > 0.0 && isfinite(wmax)) {
@@ -519,6 +519,7 @@ int vp_set_density(vp_grid* g, const float* w, int32_t on_device) {
         g->plan_valid = false;
     }
     HIP_TRY(hipMemcpyAsync(g->at<double>(g->L.fel_state) + kN0, &g->N0, sizeof(double), hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipMemsetAsync(g->at<uint32_t>(g->L.counters) + kRangeFlag, 0, sizeof(uint32_t), g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
     g->has_density = true;
     g->bunch_valid = false;
@@ -590,8 +591,10 @@ int vp_moments(vp_grid* g, vp_moments_t* out) {
     int rc = launch_reduce_on(g, 0, 0.0);
     if (rc) return rc;
     double m[kMoments], st[kFelStateLen];
+    uint32_t flags[4];
     HIP_TRY(hipMemcpyAsync(m, g->at<double>(g->L.moments), sizeof m, hipMemcpyDeviceToHost, g->stream));
     HIP_TRY(hipMemcpyAsync(st, g->at<double>(g->L.fel_state), sizeof st, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipMemcpyAsync(flags, g->at<uint32_t>(g->L.counters), sizeof flags, hipMemcpyDeviceToHost, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
     const double cell = spacing(g->x) * spacing(g->p);
     memset(out, 0, sizeof *out);
@@ -613,6 +616,8 @@ int vp_moments(vp_grid* g, vp_moments_t* out) {
         out->fel_invariant = st[kA] * st[kA] + st[kA + 1] * st[kA + 1] + m[4] / n0;
     }
     if (out->nonfinite) return fail(VP_ENONFINITE, "%lld non-finite weights", (long long)out->nonfinite);
+    if (flags[kRangeFlag])
+        return fail(VP_ERANGE, "a deposit cell sum exceeded 2^6 x 2^e, max|w0| < 2^e (fixed-point range)");
     return VP_OK;
 }
 
@@ -813,6 +818,7 @@ const char* vp_status_string(int s) {
     case VP_EHIP: return "HIP runtime error";
     case VP_EUNSUPPORTED: return "unsupported configuration";
     case VP_ENONFINITE: return "non-finite state";
+    case VP_ERANGE: return "deposit fixed-point range exceeded";
     default: return "unknown status";
     }
 }

@@ -31,7 +31,7 @@ enum Kind : int32_t { kFree = 0, kSho = 1, kPendulum = 2, kFel = 3 };
 constexpr int kHalo = 16;         // warm-up nodes on each side of a solve tile
 constexpr int kEdge = 32;         // nodes from an open edge whose LU coefficients are tabulated
 constexpr int kPad = 4;           // trash border of a deposit tile (per side)
-constexpr int kFixBits = 40;      // deposit tile sums: fixed point at 2^-40 of the initial max|w|
+constexpr int kFixBits = 40;      // deposit cell sums: 64-bit fixed point at 2^-40 of 2^e > max|w0|
 constexpr int kDepositThreads = 256;
 constexpr int kSeg = 32;                 // solve segment length per lane (kept nodes)
 constexpr int kLine = kSeg + 2 * kHalo;  // a lane's line: segment plus both halos
@@ -192,8 +192,10 @@ struct VpInst {
     const double2* fel_eq;   // (cos q_j, sin q_j), q_j the half drift of row j
     double* fel_state;       // [A_re, A_im, b_re, b_im, N0, dz_b, ...]
     double* partials;        // per p-solve tile: bunching partial (re, im)
-    uint32_t* counters;      // [0]: solve epilogue
+    uint32_t* counters;      // [0]: solve epilogue, [1]: reduction, [kRangeFlag]: deposit range
 };
+
+constexpr int kRangeFlag = 2;  // counters slot set when a deposit cell sum leaves half its range
 
 // fel_state slots
 enum { kA = 0, kBn = 2, kN0 = 4, kDzB = 5, kFelStateLen = 16 };
@@ -228,6 +230,7 @@ const void* deposit_kernel();
 const void* solve_x_kernel();
 const void* solve_p_kernel();
 
+// Deposit LDS image: (tx + 8) x (ty + 8) 64-bit cells.
 inline size_t deposit_lds_bytes(int tx, int ty) { return sizeof(int64_t) * (size_t)(tx + 2 * kPad) * (ty + 2 * kPad); }
 
 }  // namespace vp

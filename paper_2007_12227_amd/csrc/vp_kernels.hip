@@ -5,8 +5,10 @@
 // of a tent moved to u (in cells) with the tent of node c is h B3(u - c), B3 the
 // centred cubic B-spline (eq. 9), and Lambda = h_x h_p M_x (x) M_p with
 // M = tridiag(1/6, 2/3, 1/6) (eq. 8).  k_deposit forms b = Delta^T w / (h_x h_p),
-// k_solve forms (M_x^{-1} (x) M_p^{-1}) b.  All state arithmetic is FP32; FP64
-// is used only for the FEL bunching sum and the diagnostics.
+// k_solve_x and k_solve_p form (M_x^{-1} (x) M_p^{-1}) b.  The state and the
+// solves are FP32; the deposit's tap weights and products are FP64 (full rate
+// on gfx950), rounded once into exact fixed-point tile sums; the FEL bunching
+// sum and the diagnostics are FP64.
 #include "vp_internal.h"
 
 namespace vp {
@@ -22,50 +24,48 @@ __device__ inline void two_sum(float a, float b, float& s, float& e) {
     e = (a - (s - bb)) + (b - bb);
 }
 
-// Integer part and fraction in [0,1) of hi + lo, |lo| small.
+// Integer part and fraction of hi + lo, |lo| small: the fraction of hi plus
+// lo lies in [-1, 2), and its own floor moves the carry into the integer part
+// (no branches).  The fraction is in [0, 1], reaching 1 only when a tiny
+// negative fraction rounds up; the taps of t = 1 at cell k are those of
+// t = 0 at cell k + 1, so either form deposits the same weights.
 __device__ inline void split_cell(float hi, float lo, int& k, float& t) {
-    float f = floorf(hi);
-    float r = (hi - f) + lo;
-    if (r >= 1.0f) {
-        r -= 1.0f;
-        f += 1.0f;
-    } else if (r < 0.0f) {
-        r += 1.0f;
-        f -= 1.0f;
-    }
-    k = (int)f;
-    t = r;
+    const float f = floorf(hi);
+    const float r = (hi - f) + lo;
+    const float g = floorf(r);
+    k = (int)(f + g);
+    t = r - g;
 }
 
-// Round v in [0, 1] to a multiple of 2^-23 ((v + 1) - 1, both steps exact or
-// correctly rounded, never contracted).
-__device__ inline float grid23(float v) { return __fsub_rn(__fadd_rn(v, 1.0f), 1.0f); }
-
-// Cubic B-spline tap weights B3(t+1), B3(t), B3(1-t), B3(2-t) for t in [0,1).
-// They sum to exactly one in FP32 (the partition of unity behind the
-// conservation argument of eqs. 11-12): three taps are rounded to multiples
-// of 2^-23, so their sum and 1 minus it are exact and give the fourth.
-// (Without that rounding, 1 - sum itself rounds, biased: at t = 0 the taps
-// sum to 1 - 3e-8 and the state would lose that much mass per axis per step.)
-__device__ inline void bspline_taps(float t, float (&b)[4]) {
-    const float sixth = 1.0f / 6.0f;
-    float s = 1.0f - t;
-    float t2 = t * t;
-    b[0] = grid23((s * sixth) * (s * s));
-    const float t3 = (t * sixth) * t2;
-    b[3] = grid23(t3);
-    b[2] = grid23(fmaf(0.5f, t + t2, sixth) - 3.0f * t3);
-    b[1] = 1.0f - ((b[0] + b[3]) + b[2]);
+// Cubic B-spline tap weights B3(t+1), B3(t), B3(1-t), B3(2-t) for t in [0,1),
+// in FP64 (eq. 9).  The second tap is one minus the other three, so the taps
+// sum to one to FP64 rounding (the partition of unity behind the conservation
+// argument of eqs. 11-12), far below the 2^-40 fixed-point grid the products
+// are rounded to.
+__device__ inline void bspline_taps(float tf, double (&b)[4]) {
+    const double sixth = 1.0 / 6.0;
+    const double t = (double)tf, s = 1.0 - t, t2 = t * t;
+    b[0] = (s * sixth) * (s * s);
+    const double t3 = (t * sixth) * t2;
+    b[3] = t3;
+    b[2] = fma(0.5, t + t2, sixth) - 3.0 * t3;
+    b[1] = 1.0 - ((b[0] + b[3]) + b[2]);
 }
 
-// Round a value of magnitude below 2^51 to the nearest 64-bit integer (two's
-// complement bits) exactly: adding 1.5 * 2^52 leaves round-to-nearest(v) in
-// the low 52 bits of the sum's encoding, two's complement relative to the
-// constant's encoding.
-__device__ inline unsigned long long fix64(double v) {
-    const double d = v + 6755399441055744.0;  // 1.5 * 2^52
-    return (unsigned long long)(__double_as_longlong(d) - 0x4338000000000000ll);
+// 1.5 * 2^52: adding it to a value of magnitude below 2^51 leaves the value
+// rounded to the nearest integer in the low bits of the sum's encoding,
+// two's complement on top of the constant's encoding 0x4338 << 48.
+constexpr double kFixMagic = 6755399441055744.0;
+
+// Encoding of round(a * b) + 1.5 * 2^52, |a b| < 2^47: the FMA rounds the
+// exact product once, straight onto the integer grid.  Summed as 64-bit
+// integers, n such words give n (0x4338 << 48) + sum of the integers, whose
+// low 48 bits are the sum itself modulo 2^48: exact while |sum| < 2^47
+// (fix48_value), with no per-tap subtraction of the constant.
+__device__ inline unsigned long long fix48_word(double a, double b) {
+    return (unsigned long long)__double_as_longlong(fma(a, b, kFixMagic));
 }
+__device__ inline long long fix48_value(long long sum) { return (long long)((unsigned long long)sum << 16) >> 16; }
 
 // Locate the instance of a flattened tile index (thread 0 only).
 __device__ inline int find_instance(const int32_t* off, int ninst, int item) {
@@ -86,57 +86,111 @@ __device__ inline int wrap_index(int i, int n, float inv_n) {
     return r;
 }
 
-// LU coefficients at node g from the open edge: tabulated below kEdge, the
-// interior constant beyond.  Branch-free: the (clamped) table read is
-// unconditional and a select picks the value.
-template <bool EDGE>
-__device__ inline float lu_m(int g, const float2* edge) {
-    if (!EDGE) return kMinf;
-    const float t = edge[min(g, kEdge - 1)].x;
-    return g < kEdge ? t : kMinf;
+// Global-memory views of device pointers (loads through them are global, not
+// flat, loads) and a 32-bit offset pinned to a vector register: a running
+// row offset then costs one register and one add per row, instead of one
+// precomputed 64-bit address per row.
+#ifdef __HIP_DEVICE_COMPILE__
+#define VP_GLOBAL __attribute__((address_space(1)))
+#else
+#define VP_GLOBAL
+#endif
+typedef VP_GLOBAL const float gfloat;
+typedef VP_GLOBAL const float4 gfloat4;
+__device__ inline gfloat* as_global(const float* p) { return (gfloat*)p; }
+__device__ inline gfloat4* as_global(const float4* p) { return (gfloat4*)p; }
+__device__ inline unsigned in_vgpr(unsigned v) {
+    asm volatile("" : "+v"(v));
+    return v;
 }
-template <bool EDGE>
-__device__ inline float lu_dinv(int g, const float2* edge) {
-    if (!EDGE) return kMinf;
-    const float t = edge[min(g, kEdge - 1)].y;
-    return g < kEdge ? t : kMinf;
+// Make a wave-uniform value available here (its scalar load waited for
+// before a loop, not inside it: there the wait would also drain every LDS
+// operation in flight, since both share one counter).
+template <class T>
+__device__ inline void settle(T v) {
+    asm volatile("" ::"s"(v));
 }
 
-// Solve M y = b, M = tridiag(1/6, 2/3, 1/6), along one line of n <= kLine
-// values v[0..n) (registers; entries past n are zero), written as
+// Workgroups are dispatched to the 8 XCDs round-robin.  When the grid has
+// one workgroup per tile, give each XCD a contiguous run of tiles, so that
+// neighbouring tiles (which share halo and source data) meet in one L2.
+constexpr int kXcds = 8;
+__device__ inline int xcd_tile(int b, int total) {
+    const int xcd = b % kXcds, k = b / kXcds, q = total / kXcds, r = total % kXcds;
+    return xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+}
+__device__ inline int tile_of(int item, int total) {
+    return (int)gridDim.x == total ? xcd_tile(item, total) : item;
+}
+
+// LU coefficients of T = tridiag(1, 4, 1) at position k of a line: on a
+// line that starts at an open edge (EDGE) the exact per-node values for
+// k < kEdge (edge table), elsewhere the interior constant 2 - sqrt 3, also on
+// every line that starts at a cut.  k is a compile-time index once unrolled.
+template <bool EDGE>
+__device__ inline float lu_m(int k, const float2* edge) { return (EDGE && k < kEdge) ? edge[k].x : kMinf; }
+template <bool EDGE>
+__device__ inline float lu_dinv(int k, const float2* edge) { return (EDGE && k < kEdge) ? edge[k].y : kMinf; }
+
+// Solve M y = b, M = tridiag(1/6, 2/3, 1/6), along one line of kLine values
+// v[] (registers), written as
 //     y = b - T^{-1} (D2 b),   T = 6 M = tridiag(1, 4, 1),  D2 b = b[k-1] - 2 b[k] + b[k+1]
 // (T = 6 I + D2, so 6 T^{-1} = I - T^{-1} D2).  The LU recursions of T then only
 // carry the correction T^{-1} D2 b, so their FP32 rounding (whose fixed point
 // is biased on slowly varying data) acts on a term much smaller than b: the
 // mass a line carries is kept to ~1e-10 per step instead of ~1e-8.
-// Neighbours outside [0, n) count as zero: exact at an open edge (the
+// Neighbours outside the line count as zero: exact at an open edge (the
 // truncated M), and a cut inside the lattice only disturbs the halo.
-// first = index of v[0] from the open edge when below kEdge (EDGE: the exact
-// tabulated LU coefficients apply there), interior constants elsewhere.
-// The solution replaces v.  Fixed length, fully unrolled, no branches.
-template <bool EDGE>
-__device__ inline void line_solve(float (&v)[kLine], int n, int first, const float2* edge) {
+// MASKED: the lattice line is shorter than kLine; v[k] is zero for k >= n
+// and the recursion ends at n (an open edge).  Otherwise every index
+// condition is a compile-time one.  The solution replaces v.
+template <bool EDGE, bool MASKED>
+__device__ inline void line_solve(float (&v)[kLine], int n, const float2* edge) {
     float z[kLine];
     float acc = 0.0f;
 #pragma unroll
     for (int k = 0; k < kLine; ++k) {
         const float r = ((k > 0 ? v[k - 1] : 0.0f) + (k + 1 < kLine ? v[k + 1] : 0.0f)) - 2.0f * v[k];
-        acc = fmaf(-lu_m<EDGE>(first + k, edge), acc, r);
-        acc = k < n ? acc : 0.0f;
+        acc = fmaf(-lu_m<EDGE>(k, edge), acc, r);
+        if (MASKED) acc = k < n ? acc : 0.0f;
         z[k] = acc;
     }
     float c = 0.0f;
 #pragma unroll
     for (int k = kLine - 1; k >= 0; --k) {
-        c = (z[k] - c) * lu_dinv<EDGE>(first + k, edge);
+        c = (z[k] - c) * lu_dinv<EDGE>(k, edge);
         v[k] -= c;
     }
 }
 
-__device__ inline void line_solve_any(float (&v)[kLine], int n, int first, const float2* edge) {
-    if (first >= kEdge) line_solve<false>(v, n, first, edge);
-    else line_solve<true>(v, n, first, edge);
+// The same solve on a line held in LDS (row[0..kLine), zero from n on): only
+// the forward intermediate z lives in registers, b is read back for the update.
+template <bool EDGE, bool MASKED>
+__device__ inline void line_solve_lds(float* row, int n, const float2* edge) {
+    float z[kLine];
+    float acc = 0.0f, bm = 0.0f, b0 = row[0];
+#pragma unroll
+    for (int k = 0; k < kLine; ++k) {
+        const float bp = k + 1 < kLine ? row[k + 1] : 0.0f;
+        const float r = (bm + bp) - 2.0f * b0;
+        acc = fmaf(-lu_m<EDGE>(k, edge), acc, r);
+        if (MASKED) acc = k < n ? acc : 0.0f;
+        z[k] = acc;
+        bm = b0;
+        b0 = bp;
+    }
+    float c = 0.0f;
+#pragma unroll
+    for (int k = kLine - 1; k >= 0; --k) {
+        c = (z[k] - c) * lu_dinv<EDGE>(k, edge);
+        row[k] -= c;
+    }
 }
+
+// Start of the kLine window around a segment starting at s0 on an open axis
+// of n nodes: kHalo before the segment, shifted to lie inside [0, n) so that a
+// window near an edge ends exactly at it (0 when n < kLine).
+__device__ inline int open_window(int s0, int n) { return max(0, min(s0 - kHalo, n - kLine)); }
 
 }  // namespace
 
@@ -164,25 +218,22 @@ __device__ inline void deposit_node(long long* acc, int j, int ii, float w, floa
         split_cell(su, eu + tp.y, ku, fu);
         split_cell(dv, 0.0f, kv, fv);
     }
-    float bx[4], bp[4];
+    double bx[4], bp[4];
     bspline_taps(fu, bx);
     bspline_taps(fv, bp);
     // tap (q, r) lands on row j + kv - 1 + q, column ii + ku - 1 + r
     const int c0 = clampi(ii + ku - 1 - X0 + kPad, 0, cmax);
     const int r0 = clampi(j + kv - 1 - Y0 + kPad, 0, rmax);
     long long* base = acc + r0 * ldw + c0;
-    // tap value w * bp * bx formed in FP64 and rounded once, exactly, into
-    // the fixed-point tile sum: the deposit adds no FP32 product rounding to
-    // the state (the FEL instability amplifies it)
-    double bxd[4];
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) bxd[rr] = (double)bx[rr];
+    // tap value w * bp * bx: FP64 product, rounded once, exactly, into the
+    // fixed-point tile sum, so the deposit adds no product rounding to the
+    // state (the FEL instability amplifies it)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const double wq = (double)w * (double)bp[q];
-        long long* row = base + q * ldw;
+        const double wq = (double)w * bp[q];
+        unsigned long long* row = (unsigned long long*)(base + q * ldw);
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) atomicAdd((unsigned long long*)(row + rr), fix64(wq * bxd[rr]));
+        for (int rr = 0; rr < 4; ++rr) atomicAdd(row + rr, fix48_word(wq, bx[rr]));
     }
 }
 
@@ -200,7 +251,8 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
     __shared__ int s_d, s_box[4];
     __shared__ float s_ab[2];
 
-    for (int item = blockIdx.x; item < A.total; item += gridDim.x) {
+    for (int it = blockIdx.x; it < A.total; it += gridDim.x) {
+        const int item = tile_of(it, A.total);
         if (threadIdx.x == 0) s_d = find_instance(A.off, A.ninst, item);
         __syncthreads();
         const int d = __builtin_amdgcn_readfirstlane(s_d);
@@ -232,60 +284,98 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
         }
         __syncthreads();
 
-        const int bx0 = s_box[0], bw = s_box[1] - s_box[0];
+        const int bx0 = s_box[0], bw = max(s_box[1] - s_box[0], 1);
         const int by0 = s_box[2], bh = s_box[3] - s_box[2];
-        const int nsrc = (bw > 0 && bh > 0) ? bw * bh : 0;
-        const float inv_bw = 1.0f / (float)max(bw, 1);
+        const int nsrc = (s_box[1] > s_box[0] && bh > 0) ? bw * bh : 0;
         const float inv_nx = 1.0f / (float)nx;
         const float alpha = s_ab[0], beta = s_ab[1], kd = I.push.kd;
         const int kind = I.push.kind;
         const bool periodic = I.push.x_periodic != 0;
 
         // Tile sums are exact fixed-point integers: every tap value is rounded
-        // to a multiple of 2^-40 of the instance's initial max|w| and summed
-        // with 64-bit integer LDS atomics, so the sum does not depend on the
-        // order of the atomics (bitwise reproducible).  The map is area
-        // preserving, so a cell collects about max|w|; a tap must stay below
-        // 2^11 max|w| (the conversion's range) and a sum below 2^23 max|w|.
+        // to a multiple of 2^-40 of 2^e > max|w0| (the instance's initial
+        // weights) and summed with 64-bit integer LDS atomics, so the sum does
+        // not depend on the order of the atomics or on the tiling (bitwise
+        // reproducible).  The map is area preserving and the weights are
+        // carried along it, so a cell collects about max|w|; a cell sum must
+        // stay below 2^7 x 2^e (2^47 units, fix48_value): cells beyond 2^6 x 2^e
+        // set the instance's range flag.
         const float scale = I.fix_scale, inv_scale = I.fix_inv;  // exact powers of two
         const int nsrc_live = scale > 0.0f ? nsrc : 0;
 
-        // Four sources per thread and iteration, every load issued before any
-        // use, so an iteration waits for one memory latency, not a chain.
+        // Thread t takes the box's sources s = t, t + T, t + 2T, ... (s = r bw + c):
+        // its (row, column) advance by (T / bw, T % bw) per source with one
+        // carry.  On a periodic axis the column wraps with one correction per
+        // side while the box lies within [-nx, 2 nx) (always, unless the
+        // lattice is narrower than the box).
+        constexpr int T = kDepositThreads;
+        const int dr = T / bw, dc = T - dr * bw;
+        const int cnt = (int)threadIdx.x < nsrc_live ? (nsrc_live - 1 - (int)threadIdx.x) / T + 1 : 0;
+        const bool wrap_near = bx0 >= -nx && bx0 + bw <= 2 * nx;
+        int r = (int)threadIdx.x / bw;
+        int c = (int)threadIdx.x - r * bw;
+        gfloat* __restrict__ w_g = as_global(w_in);
+        gfloat4* __restrict__ tab_x = as_global(I.tab_x);
+        gfloat4* __restrict__ tab_p = as_global(I.tab_p);
+        settle(w_g);
+        settle(tab_x);
+        settle(tab_p);
+        auto column = [&](int iu) {
+            if (!periodic) return iu;
+            if (wrap_near) return iu + (iu < 0 ? nx : 0) - (iu >= nx ? nx : 0);
+            return wrap_index(iu, nx, inv_nx);
+        };
+        auto next = [&]() {
+            c += dc;
+            r += dr;
+            const bool carry = c >= bw;
+            c -= carry ? bw : 0;
+            r += carry ? 1 : 0;
+        };
+
+        // Four sources per iteration, every load issued before any use, so an
+        // iteration waits for one memory latency, not a chain; the last
+        // sources (fewer than four) one at a time.
         constexpr int kU = 4;
-        for (int s0 = threadIdx.x; s0 < nsrc_live; s0 += kU * blockDim.x) {
+        int left = cnt;
+        for (; left >= kU; left -= kU) {
             int jj[kU], iiu[kU];
             float wv[kU];
             float4 txv[kU], tpv[kU];
 #pragma unroll
             for (int h = 0; h < kU; ++h) {
-                const int s = min(s0 + h * (int)blockDim.x, nsrc_live - 1);
-                int r = (int)(((float)s + 0.5f) * inv_bw);
-                int c = s - r * bw;
-                if (c < 0) { c += bw; --r; }
-                if (c >= bw) { c -= bw; ++r; }
                 jj[h] = by0 + r;
                 iiu[h] = bx0 + c;  // unwrapped source column
-                const int i = periodic ? wrap_index(iiu[h], nx, inv_nx) : iiu[h];
-                wv[h] = w_in[(size_t)jj[h] * nx + i];
-                txv[h] = I.tab_x[i];
-                tpv[h] = I.tab_p[jj[h]];
+                const int i = column(iiu[h]);
+                wv[h] = w_g[(size_t)jj[h] * nx + i];
+                txv[h] = tab_x[(unsigned)i];
+                tpv[h] = tab_p[(unsigned)jj[h]];
+                next();
             }
 #pragma unroll
-            for (int h = 0; h < kU; ++h) {
-                if (s0 + h * (int)blockDim.x >= nsrc_live) break;
+            for (int h = 0; h < kU; ++h)
                 deposit_node(acc, jj[h], iiu[h], wv[h] * scale, txv[h], tpv[h], kind, alpha, beta, kd, X0, Y0,
                              ldw, cmax, rmax);
-            }
+        }
+        for (; left > 0; --left) {
+            const int j = by0 + r, iu = bx0 + c, i = column(iu);
+            const float wj = w_g[(size_t)j * nx + i];
+            const float4 tx = tab_x[(unsigned)i], tp = tab_p[(unsigned)j];
+            next();
+            deposit_node(acc, j, iu, wj * scale, tx, tp, kind, alpha, beta, kd, X0, Y0, ldw, cmax, rmax);
         }
         __syncthreads();
 
         const int tw = X1 - X0, th = Y1 - Y0;
         float* __restrict__ b = I.b;
+        bool out_of_range = false;
         for (int k = threadIdx.x; k < tw * th; k += blockDim.x) {
-            int rr = k / tw, cc = k - rr * tw;
-            b[(size_t)(Y0 + rr) * nx + X0 + cc] = (float)acc[(rr + kPad) * ldw + cc + kPad] * inv_scale;
+            const int rr = k / tw, cc = k - rr * tw;
+            const long long v = fix48_value(acc[(rr + kPad) * ldw + cc + kPad]);
+            out_of_range |= (unsigned long long)v + (1ull << 46) >= (1ull << 47);
+            b[(size_t)(Y0 + rr) * nx + X0 + cc] = (float)v * inv_scale;
         }
+        if (out_of_range) atomicOr(&I.counters[kRangeFlag], 1u);
         __syncthreads();
     }
 }
@@ -308,11 +398,13 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
 //    epilogue also forms the FP64 bunching of the new state.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kSolveXThreads) void k_solve_x(LaunchArgs A) {
-    __shared__ float lds[kSolveXThreads * (kLine + 1)];
+    constexpr int ldw = kLine + 1;
+    __shared__ float lds[kSolveXThreads * ldw];
     __shared__ int s_d;
     __shared__ float2 s_edge[kEdge];
 
-    for (int item = blockIdx.x; item < A.total; item += gridDim.x) {
+    for (int it = blockIdx.x; it < A.total; it += gridDim.x) {
+        const int item = tile_of(it, A.total);
         if (threadIdx.x == 0) s_d = find_instance(A.off, A.ninst, item);
         __syncthreads();
         const int d = __builtin_amdgcn_readfirstlane(s_d);
@@ -322,46 +414,62 @@ __global__ __launch_bounds__(kSolveXThreads) void k_solve_x(LaunchArgs A) {
         const bool periodic = I.push.x_periodic != 0;
         const int tiles_x = (nx + kSeg - 1) / kSeg;
         const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
-        const int X0 = txi * kSeg, X1 = min(X0 + kSeg, nx);
-        const int Y0 = tyi * kSolveXThreads, Y1 = min(Y0 + kSolveXThreads, np);
-        const int rc0 = periodic ? X0 - kHalo : max(0, X0 - kHalo);
-        const int rc1 = periodic ? X1 + kHalo : min(nx, X1 + kHalo);
-        const int RW = rc1 - rc0, th = Y1 - Y0, tw = X1 - X0;
+        const int X0 = txi * kSeg, tw = min(kSeg, nx - X0);
+        const int Y0 = tyi * kSolveXThreads, th = min(kSolveXThreads, np - Y0);
+        // the line window: kLine columns from w0 (unwrapped on a periodic axis)
+        const int w0 = periodic ? X0 - kHalo : open_window(X0, nx);
+        const int n = periodic ? kLine : min(kLine, nx);
+        const bool edge = !periodic && w0 == 0, masked = n < kLine;
         const int par = (I.parity0 + A.parity) & 1;
         const float* __restrict__ src = I.b;
         float* __restrict__ dst = I.w[par];  // the state just deposited from
-        const float inv_nx = 1.0f / (float)nx;
-        constexpr int ldw = kLine + 1;
 
-        if (threadIdx.x < kEdge)
-            s_edge[threadIdx.x] = periodic ? make_float2(kMinf, kMinf) : I.coef_x[min((int)threadIdx.x, nx - 1)];
-        // stage rows Y0..Y1, columns rc0..rc1: lane = column, loop over rows
-        for (int c = threadIdx.x; c < kLine; c += blockDim.x) {
-            int gc = rc0 + min(c, RW - 1);
-            if (periodic) gc = wrap_index(gc, nx, inv_nx);
-            const float* col = src + (size_t)Y0 * nx + gc;
-#pragma unroll 16
-            for (int r = 0; r < th; ++r) lds[r * ldw + c] = c < RW ? col[(size_t)r * nx] : 0.0f;
+        if (edge && threadIdx.x < kEdge) s_edge[threadIdx.x] = I.coef_x[min((int)threadIdx.x, nx - 1)];
+        // stage rows Y0..Y0+th of the window: lane = column
+        {
+            static_assert(kLine == kSolveXThreads, "one staged column per lane");
+            const int c = threadIdx.x;
+            int gc = w0 + min(c, n - 1);
+            if (periodic) gc = wrap_index(gc, nx, 1.0f / (float)nx);
+            gfloat* base = as_global(src) + (size_t)Y0 * nx;
+            unsigned q = in_vgpr((unsigned)gc);  // running offset (< 64 rows x nx)
+            const bool live = c < n;
+            if (th == kSolveXThreads) {
+                // a full tile: every row's load in flight at once
+                float tv[kSolveXThreads];
+#pragma unroll
+                for (int r = 0; r < kSolveXThreads; ++r) {
+                    tv[r] = base[q];
+                    q += (unsigned)nx;
+                }
+#pragma unroll
+                for (int r = 0; r < kSolveXThreads; ++r) lds[r * ldw + c] = live ? tv[r] : 0.0f;
+            } else {
+                for (int r = 0; r < th; ++r) {
+                    lds[r * ldw + c] = live ? base[q] : 0.0f;
+                    q += (unsigned)nx;
+                }
+            }
         }
         __syncthreads();
 
-        const int first = (!periodic && rc0 < kEdge) ? rc0 : kEdge;
         if ((int)threadIdx.x < th) {
-            float v[kLine];
             float* row = lds + threadIdx.x * ldw;
-#pragma unroll
-            for (int k = 0; k < kLine; ++k) v[k] = row[k];
-            line_solve_any(v, RW, first, s_edge);
-#pragma unroll
-            for (int k = 0; k < kLine; ++k) row[k] = v[k];
+            if (masked) line_solve_lds<true, true>(row, n, s_edge);
+            else if (edge) line_solve_lds<true, false>(row, n, s_edge);
+            else line_solve_lds<false, false>(row, n, s_edge);
         }
         __syncthreads();
 
-        for (int c = threadIdx.x; c < tw; c += blockDim.x) {
-            float* col = dst + (size_t)Y0 * nx + X0 + c;
-            const int lc = X0 - rc0 + c;
-#pragma unroll 16
-            for (int r = 0; r < th; ++r) col[(size_t)r * nx] = lds[r * ldw + lc];
+        {
+            // two rows per store instruction: lane = (row parity, column)
+            static_assert(kSeg * 2 == kSolveXThreads, "two rows of a segment per wavefront");
+            const int c = threadIdx.x % kSeg;
+            if (c < tw) {
+                float* out = dst + (size_t)Y0 * nx + X0 + c;
+                const float* l = lds + (X0 - w0 + c);
+                for (int r = threadIdx.x / kSeg; r < th; r += 2) out[(size_t)r * nx] = l[r * ldw];
+            }
         }
         __syncthreads();
     }
@@ -373,7 +481,8 @@ __global__ __launch_bounds__(kSolvePThreads) void k_solve_p(LaunchArgs A) {
     __shared__ float2 s_edge[kEdge];
     __shared__ double s_red[2][kSolvePThreads / 64];
 
-    for (int item = blockIdx.x; item < A.total; item += gridDim.x) {
+    for (int it = blockIdx.x; it < A.total; it += gridDim.x) {
+        const int item = tile_of(it, A.total);
         if (threadIdx.x == 0) s_d = find_instance(A.off, A.ninst, item);
         __syncthreads();
         const int d = __builtin_amdgcn_readfirstlane(s_d);
@@ -383,40 +492,59 @@ __global__ __launch_bounds__(kSolvePThreads) void k_solve_p(LaunchArgs A) {
         const int tiles_x = (nx + kSolvePThreads - 1) / kSolvePThreads;
         const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
         const int col = txi * kSolvePThreads + threadIdx.x;
-        const int Y0 = tyi * kSeg, Y1 = min(Y0 + kSeg, np);
-        const int rr0 = max(0, Y0 - kHalo), rr1 = min(np, Y1 + kHalo);
-        const int RH = rr1 - rr0;
+        const int Y0 = tyi * kSeg, kept = min(kSeg, np - Y0);
+        const int w0 = open_window(Y0, np), n = min(kLine, np);
+        const bool edge = w0 == 0, masked = n < kLine;
+        const int lo = Y0 - w0;  // the kept rows are window positions lo .. lo + kept
         const int par = (I.parity0 + A.parity) & 1;
         const float* __restrict__ src = I.w[par];
         float* __restrict__ dst = I.w[par ^ 1];
 
-        if (threadIdx.x < kEdge) s_edge[threadIdx.x] = I.coef_p[min((int)threadIdx.x, np - 1)];
+        if (edge && threadIdx.x < kEdge) s_edge[threadIdx.x] = I.coef_p[min((int)threadIdx.x, np - 1)];
         __syncthreads();
 
         const bool fel = I.push.kind == kFel;
         double acc_re = 0.0, acc_im = 0.0;
         if (col < nx) {
             float v[kLine];
-            const float* c0 = src + (size_t)rr0 * nx + col;
+            gfloat* base = as_global(src) + (size_t)w0 * nx;
+            if (!masked) {
+                unsigned q = in_vgpr((unsigned)col);  // running offset (< kLine rows x nx)
 #pragma unroll
-            for (int k = 0; k < kLine; ++k) {
-                const float x = c0[(size_t)min(k, RH - 1) * nx];
-                v[k] = k < RH ? x : 0.0f;
-            }
-            line_solve_any(v, RH, rr0 < kEdge ? rr0 : kEdge, s_edge);
-            float* o = dst + col;
-            const int lo = Y0 - rr0;
-            double cre = 0.0, cim = 0.0;
-#pragma unroll
-            for (int k = 0; k < kLine; ++k) {
-                if (k >= lo && k < lo + (Y1 - Y0)) {
-                    o[(size_t)(rr0 + k) * nx] = v[k];
-                    if (fel) {
-                        const double2 e = I.fel_eq[rr0 + k];  // times e^{-i q}
-                        cre += (double)v[k] * e.x;
-                        cim -= (double)v[k] * e.y;
-                    }
+                for (int k = 0; k < kLine; ++k) {
+                    v[k] = base[q];
+                    q += (unsigned)nx;
                 }
+                if (edge) line_solve<true, false>(v, n, s_edge);
+                else line_solve<false, false>(v, n, s_edge);
+            } else {
+                const int nv = (int)in_vgpr((unsigned)n);
+#pragma unroll
+                for (int k = 0; k < kLine; ++k) {
+                    const unsigned q = in_vgpr((unsigned)(min(k, nv - 1) * nx + col));
+                    const float x = base[q];
+                    v[k] = k < nv ? x : 0.0f;
+                }
+                line_solve<true, true>(v, n, s_edge);
+            }
+            float* o = dst + (size_t)w0 * nx + col;
+            double cre = 0.0, cim = 0.0;
+            auto keep = [&](int k) {
+                o[(size_t)k * nx] = v[k];
+                if (fel) {
+                    const double2 e = I.fel_eq[w0 + k];  // times e^{-i q}
+                    cre += (double)v[k] * e.x;
+                    cim -= (double)v[k] * e.y;
+                }
+            };
+            if (lo == kHalo && kept == kSeg) {
+#pragma unroll
+                for (int k = kHalo; k < kHalo + kSeg; ++k) keep(k);
+            } else {
+                const int lov = (int)in_vgpr((unsigned)lo);
+#pragma unroll
+                for (int k = 0; k < kLine; ++k)
+                    if ((unsigned)(k - lov) < (unsigned)kept) keep(k);
             }
             if (fel) {
                 const double2 e = I.fel_ex[col];  // times e^{-i phi}
