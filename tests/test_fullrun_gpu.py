@@ -70,14 +70,27 @@ def test_full_run_pendulum_band_2048(B):
     assert run_against_golden(B, pendulum_band(2048), "pendulum_band_2048") <= 1e-4
 
 
+def chaotic_checkpoints(bar=1e-4):
+    """FEL checkpoints whose result rounding decides: there, equally valid FP32
+    runs (tests/golden/fel_sensitivity.py: the FP32-state oracle with 1e-7
+    relative noise per step, two seeds) already drift from the exact run by
+    more than a tenth of the bar."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "fel_sensitivity.txt"))
+    return sorted({int(k) for _, k, err, _ in rows if err > 0.1 * bar})
+
+
 def test_full_run_fel_gaussian_1024(B):
-    """Through saturation (step 1000) the bar is the standard relative L1.
-    After it the beam has left the energy window through the open edges
-    (at step 1500 the weights inside sum to 5e-6 of the start, at 2000 the sum
-    is a negative Gibbs residue) and the run is chaotic: differences at the
-    1e-9 level of a different tiling grow to 1e-4 of that residue.  There the
-    error is held to 1e-4 of ||w0||_1 (printed beside the standard number and
-    the FP32-state floor), with the field A and the mass accounting checked."""
-    early, late = run_against_golden(B, fel_gaussian(1024), "fel_gaussian_1024", chaotic_after=1000)
+    """Standard relative L1 <= 1e-4 where the result is a property of the
+    implementation (through step 500: noisy FP32 runs agree with the exact
+    one to ~1e-6).  By step 1000 the field has saturated, the beam has left
+    the energy window through the open edges (the weights inside sum to 0.4%
+    of the start, later to a Gibbs residue), and two noisy FP32 runs that
+    differ only in the noise seed land 3.6e-6 and 9.0e-5 from the exact run:
+    there the error is held to 1e-4 of ||w0||_1 (printed beside the standard
+    number and the FP32-state floor), with the field A and the mass
+    accounting checked at every checkpoint."""
+    chaotic = chaotic_checkpoints()
+    assert chaotic and min(chaotic) > 500, chaotic
+    early, late = run_against_golden(B, fel_gaussian(1024), "fel_gaussian_1024", chaotic_after=min(chaotic) - 1)
     assert early <= 1e-4
     assert late <= 1e-4
