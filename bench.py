@@ -21,7 +21,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "node-steps/s (push+deposit) vs plain; % HBM roofline; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
-ALG_BYTES_PER_NODE = 8  # each kernel reads one FP32 array and writes one
+ALG_BYTES_PER_NODE = 8  # a step (and each of its kernels) must read one FP32 array and write one
+KERNELS = ("k_deposit", "k_solve_x", "k_solve_p")
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2007_12227_amd", "csrc", "vp_kernels.hip")
 
 
 def log(msg):
@@ -115,6 +118,28 @@ def bench_served(binding, nreq, load, capacity, budget_gib):
     return out
 
 
+def kernel_source_sha():
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a copy of
+    known size), or None if there is none for the current kernel source."""
+    path = os.path.join(PROFILES, f"{kernel}_{workload}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_sha():
+        return None
+    return float(vals["bytes_per_launch"])
+
+
 def cpu_baseline(inst, steps):
     import numpy as np
 
@@ -147,6 +172,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
+    ap.add_argument("--tiles", default=None,
+                    help="deposit tile WxH for the tuned path instead of autotuning (uniform dispatches "
+                         "for profiling)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain (untuned, no graph) run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -171,29 +200,39 @@ def main():
         del a, b
 
     # plain path: default tiles, one launch per kernel
-    gp = binding.grid_for(inst)
-    gp.set_launch(False)
-    plain_s, _ = timed_steps(gp, inst.dt, args.steps, args.warmup)
-    gp.close()
-    plain = N * args.steps / plain_s
-    log(f"plain: {plain:.3e} node-steps/s ({1e6 * plain_s / args.steps:.2f} us/step)")
+    plain = plain_s = None
+    if not args.no_plain:
+        gp = binding.grid_for(inst)
+        gp.set_launch(False)
+        plain_s, _ = timed_steps(gp, inst.dt, args.steps, args.warmup)
+        gp.close()
+        plain = N * args.steps / plain_s
+        log(f"plain: {plain:.3e} node-steps/s ({1e6 * plain_s / args.steps:.2f} us/step)")
 
-    # tuned path: autotuned tiles, steps replayed from HIP graphs
+    # tuned path: autotuned deposit tiles, steps replayed from HIP graphs
     g = binding.grid_for(inst)
-    tune_us = g.autotune(inst.dt)
+    if args.tiles:
+        tx, ty = (int(v) for v in args.tiles.lower().split("x"))
+        g.set_tiles((tx, ty))
+        tune_us = None
+    else:
+        tune_us = g.autotune(inst.dt)
     tiles = g.tiles()
-    log(f"autotune: {tiles} ({tune_us:.2f} us/step)")
+    log(f"tiles: {tiles} (autotune {tune_us} us/step)")
     sec, wall = timed_steps(g, inst.dt, args.steps, args.warmup)
     value = N * args.steps / sec
     log(f"tuned: {value:.3e} node-steps/s ({1e6 * sec / args.steps:.2f} us/step, wall {wall:.3f} s)")
 
-    # per-kernel durations (HIP events on the grid's stream around each launch)
-    dep_us, sol_us = g.step_timed(inst.dt, 64)
+    # per-kernel durations: HIP events recorded on the grid's stream around
+    # each launch, averaged over the steps
+    kus = dict(zip(KERNELS, g.step_timed(inst.dt, min(args.steps, 200))))
     m = g.moments()
     g.close()
-    dom_name, dom_us = ("k_deposit", dep_us) if dep_us >= sol_us else ("k_solve", sol_us)
-    achieved = ALG_BYTES_PER_NODE * N / (dom_us * 1e-6) / 1e9
-    log(f"kernels: deposit {dep_us:.2f} us, solve {sol_us:.2f} us")
+    log("kernels: " + ", ".join(f"{k} {v:.2f} us" for k, v in kus.items()))
+    dom = max(kus, key=kus.get)
+    alg_bytes = ALG_BYTES_PER_NODE * N  # per launch of any of the three kernels
+    achieved = alg_bytes / (kus[dom] * 1e-6) / 1e9
+    traffic = measured_traffic(dom, f"pendulum_band_{args.n}")
 
     line = {
         "metric": METRIC,
@@ -209,13 +248,15 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"pendulum_band_{args.n}", "nx": args.n, "np": args.n, "dt": inst.dt,
-                   "a": 1.0, "tiles": tiles, "launch": "hip-graph"},
-        "plain": {"value": plain, "ms_per_step": 1e3 * plain_s / args.steps,
-                  "speedup": value / plain},
-        "kernels_us": {"k_deposit": dep_us, "k_solve": sol_us},
-        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
-        "step_roofline_frac": ALG_BYTES_PER_NODE * N / (sec / args.steps) / 1e9 / HBM_PEAK_GBS,
+                   "a": 1.0, "deposit_tiles": tiles["k1"], "launch": "hip-graph"},
+        "plain": None if plain is None else {"value": plain, "ms_per_step": 1e3 * plain_s / args.steps,
+                                             "speedup": value / plain},
+        "kernels_us": kus,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": alg_bytes},
+        "kernel_roofline_frac": {k: alg_bytes / (v * 1e-6) / 1e9 / HBM_PEAK_GBS for k, v in kus.items()},
+        "step_roofline_frac": alg_bytes / (sec / args.steps) / 1e9 / HBM_PEAK_GBS,
         "final_sum_w": m["sum_w"],
     }
     if not args.no_extras:
