@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 METRIC = "node-steps/s (push+deposit) vs plain; % HBM roofline; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
 ALG_BYTES_PER_NODE = 8  # a step (and each of its kernels) must read one FP32 array and write one
-KERNELS = ("k_deposit", "k_solve_x", "k_solve_p")
+KERNELS = ("k_deposit", "k_solve")
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2007_12227_amd", "csrc", "vp_kernels.hip")
 

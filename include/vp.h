@@ -117,8 +117,7 @@ typedef struct {
 } vp_moments_t;
 
 /* Tile shape of the deposit kernel (destination tile, in lattice nodes).
- * Zero fields keep the current value.  (The two solve kernels work on fixed
- * 32-node line segments.) */
+ * Zero fields keep the current value.  (The solve works on fixed 32x32 tiles.) */
 typedef struct {
     int32_t k1_tx, k1_ty;
 } vp_tiles;
@@ -163,9 +162,9 @@ int vp_set_launch(vp_grid* g, int32_t use_graph);
 
 /* Measurement helper: nsteps steps exactly as vp_step with direct launches,
  * with HIP events recorded on the grid's stream around every kernel.
- * us[0], us[1], us[2] receive the mean duration in microseconds of the
- * deposit, x-solve and p-solve kernels.  Waits for the stream. */
-int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[3]);
+ * us[0] and us[1] receive the mean duration in microseconds of the deposit
+ * kernel and of the solve kernel.  Waits for the stream. */
+int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]);
 
 /* Time candidate tile shapes on this grid for step size dt and keep the
  * fastest.  The state is restored afterwards.  best_us receives the time per

@@ -199,11 +199,11 @@ class Grid:
     def step(self, dt: float, n: int = 1):
         check(lib().vp_step(self._h, float(dt), int(n)))
 
-    def step_timed(self, dt: float, n: int) -> tuple[float, float, float]:
-        """n steps with per-kernel HIP events: mean (deposit, x-solve, p-solve) microseconds."""
-        us = (C.c_double * 3)()
+    def step_timed(self, dt: float, n: int) -> tuple[float, float]:
+        """n steps with per-kernel HIP events: mean (deposit, solve) microseconds."""
+        us = (C.c_double * 2)()
         check(lib().vp_step_timed(self._h, float(dt), int(n), us))
-        return us[0], us[1], us[2]
+        return us[0], us[1]
 
     def moments(self) -> dict:
         m = Moments()

@@ -81,8 +81,8 @@ Layout layout(int nx, int np) {
     L.fel_ex = take((size_t)nx * 16);
     L.fel_eq = take((size_t)np * 16);
     L.fel_state = take(kFelStateLen * 8);
-    // p-solve tiles (FEL bunching partials) and reduction blocks
-    size_t tiles = (size_t)((nx + kSolvePThreads - 1) / kSolvePThreads) * ((np + kSeg - 1) / kSeg);
+    // solve tiles (FEL bunching partials) and reduction blocks
+    size_t tiles = (size_t)((nx + kSeg - 1) / kSeg) * ((np + kSeg - 1) / kSeg);
     L.partial_doubles = std::max((size_t)kReduceBlocks * kMoments, 2 * tiles);
     L.partials = take(L.partial_doubles * 8);
     L.counters = take(4 * sizeof(uint32_t));
@@ -97,9 +97,8 @@ Layout layout(int nx, int np) {
 struct LaunchList {
     VpInst* d_inst = nullptr;
     int32_t* d_off1 = nullptr;  // deposit tiles
-    int32_t* d_offx = nullptr;  // x-solve tiles
-    int32_t* d_offp = nullptr;  // p-solve tiles
-    int ninst = 0, total1 = 0, totalx = 0, totalp = 0;
+    int32_t* d_off2 = nullptr;  // solve tiles
+    int ninst = 0, total1 = 0, total2 = 0;
     size_t lds1 = 0;
     hipStream_t stream = nullptr;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -111,17 +110,15 @@ struct LaunchList {
     LaunchArgs args(const int32_t* off, int total, int parity) const {
         return LaunchArgs{d_inst, off, ninst, total, parity};
     }
-    // the three kernels of one step: {kernel, off, total, lds, threads}
+    // the two kernels of one step: {kernel, off, total, lds, threads}
     struct K { const void* fn; const int32_t* off; int total; size_t lds; int threads; };
-    void kernels(K (&k)[3]) const {
+    void kernels(K (&k)[2]) const {
         k[0] = K{deposit_kernel(), d_off1, total1, lds1, kDepositThreads};
-        k[1] = K{solve_x_kernel(), d_offx, totalx, 0, kSolveXThreads};
-        k[2] = K{solve_p_kernel(), d_offp, totalp, 0, kSolvePThreads};
+        k[1] = K{solve_kernel(), d_off2, total2, 0, kSolveThreads};
     }
     int enqueue_step(int parity) const {
         HIP_TRY(launch_deposit(args(d_off1, total1, parity), total1, lds1, stream));
-        HIP_TRY(launch_solve_x(args(d_offx, totalx, parity), totalx, stream));
-        HIP_TRY(launch_solve_p(args(d_offp, totalp, parity), totalp, stream));
+        HIP_TRY(launch_solve(args(d_off2, total2, parity), total2, stream));
         return VP_OK;
     }
     int build_graph(int rel_parity) {
@@ -129,8 +126,8 @@ struct LaunchList {
         HIP_TRY(hipGraphCreate(&graph, 0));
         hipGraphNode_t prev = nullptr;
         std::vector<LaunchArgs> keep;
-        keep.reserve(3 * kGraphSteps);
-        K ks[3];
+        keep.reserve(2 * kGraphSteps);
+        K ks[2];
         kernels(ks);
         for (int s = 0; s < kGraphSteps; ++s) {
             for (const K& k : ks) {
@@ -231,18 +228,15 @@ int upload_inst(vp_grid* g) {
     I.k1_ty = t.k1_ty;
     I.k1_tiles_x = (g->x.n + t.k1_tx - 1) / t.k1_tx;
     I.k1_tiles = I.k1_tiles_x * ((g->p.n + t.k1_ty - 1) / t.k1_ty);
-    const int ny64 = (g->p.n + kSolveXThreads - 1) / kSolveXThreads;
-    I.kx_tiles = ((g->x.n + kSeg - 1) / kSeg) * ny64;
-    I.k2_tiles = ((g->x.n + kSolvePThreads - 1) / kSolvePThreads) * ((g->p.n + kSeg - 1) / kSeg);
+    I.k2_tiles = ((g->x.n + kSeg - 1) / kSeg) * ((g->p.n + kSeg - 1) / kSeg);
     I.parity0 = 0;
-    int32_t off[6] = {0, I.k1_tiles, 0, I.kx_tiles, 0, I.k2_tiles};
+    int32_t off[4] = {0, I.k1_tiles, 0, I.k2_tiles};
     HIP_TRY(hipMemcpyAsync(g->list.d_inst, &I, sizeof(VpInst), hipMemcpyHostToDevice, g->stream));
     HIP_TRY(hipMemcpyAsync(g->list.d_off1, off, sizeof off, hipMemcpyHostToDevice, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
     g->list.ninst = 1;
     g->list.total1 = I.k1_tiles;
-    g->list.totalx = I.kx_tiles;
-    g->list.totalp = I.k2_tiles;
+    g->list.total2 = I.k2_tiles;
     g->list.lds1 = deposit_lds_bytes(t.k1_tx, t.k1_ty);
     g->list.drop_graphs();
     return VP_OK;
@@ -421,8 +415,7 @@ int vp_create_grid(const vp_grid_desc* d, vp_grid** out) {
     g->list.stream = g->stream;
     g->list.d_inst = g->at<VpInst>(L.inst);
     g->list.d_off1 = g->at<int32_t>(L.off);
-    g->list.d_offx = g->at<int32_t>(L.off) + 2;
-    g->list.d_offp = g->at<int32_t>(L.off) + 4;
+    g->list.d_off2 = g->at<int32_t>(L.off) + 2;
     VpInst& I = g->inst;
     I.w[0] = g->at<float>(L.w0);
     I.w[1] = g->at<float>(L.w1);
@@ -551,35 +544,33 @@ int vp_step(vp_grid* g, double dt, int64_t nsteps) {
     return VP_OK;
 }
 
-int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[3]) {
+int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]) {
     if (!g || !us) return fail(VP_EINVAL, "null argument");
     if (nsteps <= 0) return fail(VP_EINVAL, "need at least one step");
     if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
     int rc = prepare(g, dt);
     if (rc) return rc;
-    std::vector<hipEvent_t> ev(4 * nsteps);
+    std::vector<hipEvent_t> ev(3 * nsteps);
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
     const LaunchList& L = g->list;
     for (int64_t s = 0; s < nsteps; ++s) {
         const int par = (int)((g->parity + s) & 1);
-        HIP_TRY(hipEventRecord(ev[4 * s], g->stream));
+        HIP_TRY(hipEventRecord(ev[3 * s], g->stream));
         HIP_TRY(launch_deposit(L.args(L.d_off1, L.total1, par), L.total1, L.lds1, g->stream));
-        HIP_TRY(hipEventRecord(ev[4 * s + 1], g->stream));
-        HIP_TRY(launch_solve_x(L.args(L.d_offx, L.totalx, par), L.totalx, g->stream));
-        HIP_TRY(hipEventRecord(ev[4 * s + 2], g->stream));
-        HIP_TRY(launch_solve_p(L.args(L.d_offp, L.totalp, par), L.totalp, g->stream));
-        HIP_TRY(hipEventRecord(ev[4 * s + 3], g->stream));
+        HIP_TRY(hipEventRecord(ev[3 * s + 1], g->stream));
+        HIP_TRY(launch_solve(L.args(L.d_off2, L.total2, par), L.total2, g->stream));
+        HIP_TRY(hipEventRecord(ev[3 * s + 2], g->stream));
     }
     HIP_TRY(hipEventSynchronize(ev.back()));
-    double t[3] = {0.0, 0.0, 0.0};
+    double t[2] = {0.0, 0.0};
     for (int64_t s = 0; s < nsteps; ++s)
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 2; ++k) {
             float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, ev[4 * s + k], ev[4 * s + k + 1]));
+            HIP_TRY(hipEventElapsedTime(&ms, ev[3 * s + k], ev[3 * s + k + 1]));
             t[k] += ms;
         }
     for (auto& e : ev) (void)hipEventDestroy(e);
-    for (int k = 0; k < 3; ++k) us[k] = 1000.0 * t[k] / nsteps;
+    for (int k = 0; k < 2; ++k) us[k] = 1000.0 * t[k] / nsteps;
     g->parity = (int)((g->parity + nsteps) & 1);
     g->step += nsteps;
     return VP_OK;
@@ -745,14 +736,13 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
         HIP_TRY(hipStreamSynchronize(grids[k]->stream));
     }
     std::vector<VpInst> insts(n);
-    std::vector<int32_t> off1(n + 1, 0), offx(n + 1, 0), offp(n + 1, 0);
+    std::vector<int32_t> off1(n + 1, 0), off2(n + 1, 0);
     size_t lds1 = 0;
     for (int k = 0; k < n; ++k) {
         insts[k] = grids[k]->inst;
         insts[k].parity0 = grids[k]->parity;
         off1[k + 1] = off1[k] + insts[k].k1_tiles;
-        offx[k + 1] = offx[k] + insts[k].kx_tiles;
-        offp[k + 1] = offp[k] + insts[k].k2_tiles;
+        off2[k + 1] = off2[k] + insts[k].k2_tiles;
         lds1 = std::max(lds1, deposit_lds_bytes(insts[k].k1_tx, insts[k].k1_ty));
     }
     vp_batch* b = new vp_batch();
@@ -761,17 +751,14 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
     L.stream = s;
     L.ninst = n;
     L.total1 = off1[n];
-    L.totalx = offx[n];
-    L.totalp = offp[n];
+    L.total2 = off2[n];
     L.lds1 = lds1;
     hipError_t e = hipMalloc(&L.d_inst, sizeof(VpInst) * n);
-    if (e == hipSuccess) e = hipMalloc(&L.d_off1, sizeof(int32_t) * 3 * (n + 1));
-    L.d_offx = L.d_off1 + (n + 1);
-    L.d_offp = L.d_off1 + 2 * (n + 1);
+    if (e == hipSuccess) e = hipMalloc(&L.d_off1, sizeof(int32_t) * 2 * (n + 1));
+    L.d_off2 = L.d_off1 + (n + 1);
     if (e == hipSuccess) e = hipMemcpyAsync(L.d_inst, insts.data(), sizeof(VpInst) * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(L.d_off1, off1.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(L.d_offx, offx.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(L.d_offp, offp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.d_off2, off2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipFree(L.d_inst);

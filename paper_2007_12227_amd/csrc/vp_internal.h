@@ -1,19 +1,20 @@
 // vp_internal.h -- data layout shared by the host runtime and the gfx950 kernels of libvp.
 //
 // One step of the method (Edelen & Webb, Sec. "An Algorithm Based on Phase
-// Space Density Conservation", eqs. 6-10) runs as three kernels:
+// Space Density Conservation", eqs. 6-10) runs as two kernels:
 //   k_deposit: every lattice node is pushed (its position is its index, so
 //              nothing but w is read) and its weight is scattered onto the
 //              4x4 lattice taps of its moved tent with cubic B-spline weights
 //              (the tent-tent overlap of eq. 9).  A workgroup owns one
 //              destination tile held in LDS and scans the box of source nodes
 //              that can reach it; the tile is written to b once.
-//   k_solve_x, k_solve_p: w_out = (M_x^{-1} (x) M_p^{-1}) b, the tent mass
-//              matrix of eq. 8, M = tridiag(1/6, 2/3, 1/6), cyclic on a periodic
-//              axis: one line segment per lane, with a 16-node halo per side
-//              that makes it independent of its neighbours to within
-//              (2-sqrt 3)^16 ~ 7e-10.  For the FEL the p solve's epilogue also
-//              forms the FP64 bunching of the new state.
+//   k_solve:   w_out = (M_x^{-1} (x) M_p^{-1}) b, the tent mass matrix of
+//              eq. 8, M = tridiag(1/6, 2/3, 1/6), cyclic on a periodic axis.  A
+//              wavefront owns a 32x32 output tile and solves the 64x64 window
+//              around it (a 16-node halo per side makes the tile independent of
+//              its neighbours to within (2-sqrt 3)^16 ~ 7e-10), rows then
+//              columns, one line per lane.  For the FEL its epilogue also forms
+//              the FP64 bunching of the new state.
 #pragma once
 
 #include <stdint.h>
@@ -35,8 +36,7 @@ constexpr int kFixBits = 40;      // deposit cell sums: 64-bit fixed point at 2^
 constexpr int kDepositThreads = 256;
 constexpr int kSeg = 32;                 // solve segment length per lane (kept nodes)
 constexpr int kLine = kSeg + 2 * kHalo;  // a lane's line: segment plus both halos
-constexpr int kSolveXThreads = 64;       // x solve: rows per wavefront tile
-constexpr int kSolvePThreads = 256;      // p solve: columns per tile
+constexpr int kSolveThreads = kLine;     // solve: one window line per lane
 constexpr int kReduceBlocks = 256;
 constexpr int kReduceThreads = 256;
 constexpr int kMoments = 10;      // FP64 sums produced by the reduction kernel
@@ -173,8 +173,8 @@ __host__ __device__ inline void source_box(const PushParams& P, int bx0, int bx1
 struct VpInst {
     PushParams push;
     int32_t k1_tx, k1_ty, k1_tiles_x, k1_tiles;
-    int32_t kx_tiles;        // x-solve tiles: kSeg columns x kSolveXThreads rows
-    int32_t k2_tiles;        // p-solve tiles: kSolvePThreads columns x kSeg rows
+    int32_t k2_tiles;        // solve tiles: kSeg x kSeg nodes
+    int32_t pad2;
     int32_t parity0;         // index of the current state buffer when the launch list was built
     int32_t pad0;
     float fix_scale, fix_inv;  // deposit fixed-point scale 2^(40-e), max|w0| < 2^e, and its inverse
@@ -191,7 +191,7 @@ struct VpInst {
     const double2* fel_ex;   // (cos phi_i, sin phi_i)
     const double2* fel_eq;   // (cos q_j, sin q_j), q_j the half drift of row j
     double* fel_state;       // [A_re, A_im, b_re, b_im, N0, dz_b, ...]
-    double* partials;        // per p-solve tile: bunching partial (re, im)
+    double* partials;        // per solve tile: bunching partial (re, im)
     uint32_t* counters;      // [0]: solve epilogue, [1]: reduction, [kRangeFlag]: deposit range
 };
 
@@ -223,12 +223,10 @@ struct ReduceArgs {
 
 // launchers (vp_kernels.hip)
 hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, hipStream_t s);
-hipError_t launch_solve_x(const LaunchArgs& a, int grid, hipStream_t s);
-hipError_t launch_solve_p(const LaunchArgs& a, int grid, hipStream_t s);
+hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 const void* deposit_kernel();
-const void* solve_x_kernel();
-const void* solve_p_kernel();
+const void* solve_kernel();
 
 // Deposit LDS image: (tx + 8) x (ty + 8) 64-bit cells.
 inline size_t deposit_lds_bytes(int tx, int ty) { return sizeof(int64_t) * (size_t)(tx + 2 * kPad) * (ty + 2 * kPad); }

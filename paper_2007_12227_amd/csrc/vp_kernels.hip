@@ -5,7 +5,7 @@
 // of a tent moved to u (in cells) with the tent of node c is h B3(u - c), B3 the
 // centred cubic B-spline (eq. 9), and Lambda = h_x h_p M_x (x) M_p with
 // M = tridiag(1/6, 2/3, 1/6) (eq. 8).  k_deposit forms b = Delta^T w / (h_x h_p),
-// k_solve_x and k_solve_p form (M_x^{-1} (x) M_p^{-1}) b.  The state and the
+// k_solve forms (M_x^{-1} (x) M_p^{-1}) b.  The state and the
 // solves are FP32; the deposit's tap weights and products are FP64 (full rate
 // on gfx950), rounded once into exact fixed-point tile sums; the FEL bunching
 // sum and the diagnostics are FP64.
@@ -111,6 +111,10 @@ __device__ inline void settle(T v) {
     asm volatile("" ::"s"(v));
 }
 
+// s_waitcnt immediate that waits for every vector-memory load (vmcnt 0) and
+// nothing else (expcnt 7, lgkmcnt 15).
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 // Workgroups are dispatched to the 8 XCDs round-robin.  When the grid has
 // one workgroup per tile, give each XCD a contiguous run of tiles, so that
 // neighbouring tiles (which share halo and source data) meet in one L2.
@@ -123,14 +127,35 @@ __device__ inline int tile_of(int item, int total) {
     return (int)gridDim.x == total ? xcd_tile(item, total) : item;
 }
 
-// LU coefficients of T = tridiag(1, 4, 1) at position k of a line: on a
-// line that starts at an open edge (EDGE) the exact per-node values for
-// k < kEdge (edge table), elsewhere the interior constant 2 - sqrt 3, also on
-// every line that starts at a cut.  k is a compile-time index once unrolled.
+// LU coefficients of T = tridiag(1, 4, 1) on a line that starts at an open
+// edge: d_0 = 4, m_k = 1/d_{k-1}, d_k = 4 - m_k.  They converge to the interior
+// constants m = 1/d = 2 - sqrt 3 well within kEdge nodes.  Computed at compile
+// time in FP64 and rounded once, so an unrolled solve folds them into its
+// instructions (no table, no registers).
+struct LuEdge {
+    float m[kEdge], dinv[kEdge];
+};
+constexpr LuEdge lu_edge_table() {
+    LuEdge t{};
+    double dprev = 0.0;
+    for (int k = 0; k < kEdge; ++k) {
+        const double m = k == 0 ? 0.0 : 1.0 / dprev;
+        const double d = 4.0 - m;
+        t.m[k] = (float)m;
+        t.dinv[k] = (float)(1.0 / d);
+        dprev = d;
+    }
+    return t;
+}
+constexpr LuEdge kLuEdge = lu_edge_table();
+
+// Coefficients at position k of a line (a compile-time index once unrolled):
+// the edge values on a line that starts at an open edge (EDGE), the interior
+// constant elsewhere and on every line that starts at a cut.
 template <bool EDGE>
-__device__ inline float lu_m(int k, const float2* edge) { return (EDGE && k < kEdge) ? edge[k].x : kMinf; }
+__device__ inline float lu_m(int k) { return (EDGE && k < kEdge) ? kLuEdge.m[k] : kMinf; }
 template <bool EDGE>
-__device__ inline float lu_dinv(int k, const float2* edge) { return (EDGE && k < kEdge) ? edge[k].y : kMinf; }
+__device__ inline float lu_dinv(int k) { return (EDGE && k < kEdge) ? kLuEdge.dinv[k] : kMinf; }
 
 // Solve M y = b, M = tridiag(1/6, 2/3, 1/6), along one line of kLine values
 // v[] (registers), written as
@@ -145,45 +170,21 @@ __device__ inline float lu_dinv(int k, const float2* edge) { return (EDGE && k <
 // and the recursion ends at n (an open edge).  Otherwise every index
 // condition is a compile-time one.  The solution replaces v.
 template <bool EDGE, bool MASKED>
-__device__ inline void line_solve(float (&v)[kLine], int n, const float2* edge) {
+__device__ inline void line_solve(float (&v)[kLine], int n) {
     float z[kLine];
     float acc = 0.0f;
 #pragma unroll
     for (int k = 0; k < kLine; ++k) {
         const float r = ((k > 0 ? v[k - 1] : 0.0f) + (k + 1 < kLine ? v[k + 1] : 0.0f)) - 2.0f * v[k];
-        acc = fmaf(-lu_m<EDGE>(k, edge), acc, r);
+        acc = fmaf(-lu_m<EDGE>(k), acc, r);
         if (MASKED) acc = k < n ? acc : 0.0f;
         z[k] = acc;
     }
     float c = 0.0f;
 #pragma unroll
     for (int k = kLine - 1; k >= 0; --k) {
-        c = (z[k] - c) * lu_dinv<EDGE>(k, edge);
+        c = (z[k] - c) * lu_dinv<EDGE>(k);
         v[k] -= c;
-    }
-}
-
-// The same solve on a line held in LDS (row[0..kLine), zero from n on): only
-// the forward intermediate z lives in registers, b is read back for the update.
-template <bool EDGE, bool MASKED>
-__device__ inline void line_solve_lds(float* row, int n, const float2* edge) {
-    float z[kLine];
-    float acc = 0.0f, bm = 0.0f, b0 = row[0];
-#pragma unroll
-    for (int k = 0; k < kLine; ++k) {
-        const float bp = k + 1 < kLine ? row[k + 1] : 0.0f;
-        const float r = (bm + bp) - 2.0f * b0;
-        acc = fmaf(-lu_m<EDGE>(k, edge), acc, r);
-        if (MASKED) acc = k < n ? acc : 0.0f;
-        z[k] = acc;
-        bm = b0;
-        b0 = bp;
-    }
-    float c = 0.0f;
-#pragma unroll
-    for (int k = kLine - 1; k >= 0; --k) {
-        c = (z[k] - c) * lu_dinv<EDGE>(k, edge);
-        row[k] -= c;
     }
 }
 
@@ -381,27 +382,34 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// The mass-matrix solve (M_x^{-1} (x) M_p^{-1}) b in two kernels, one lattice
-// line segment per lane (line_solve): LU recursions of T = tridiag(1,4,1),
+// k_solve: w_new = (M_x^{-1} (x) M_p^{-1}) b in one pass, one lattice line per
+// lane (line_solve: the LU recursions of T = tridiag(1,4,1),
 //   forward  z_k = r_k - m_k z_{k-1},   backward c_k = (z_k - c_{k+1}) / d_k,
-// with exact per-node (m_k, 1/d_k) near an open edge (so the true edges are
-// exact) and the interior constants elsewhere.  A segment carries a 16-node
-// halo on each side; where the halo is cut inside the lattice the recursion
-// starts from zero, an error that decays by 2 - sqrt 3 per node and is ~7e-10
-// at the segment.
-//  k_solve_x: b -> the old state buffer (free once the deposit has read it).
-//    A wavefront owns 64 rows x kSeg columns; the rows plus halos are staged
-//    in LDS (coalesced) and each lane solves one row from registers.
-//  k_solve_p: that buffer -> the new state.  A lane owns kSeg rows of one
-//    column and streams the column plus halos straight from global memory
-//    into registers (coalesced across lanes); no LDS.  For the FEL its
-//    epilogue also forms the FP64 bunching of the new state.
+// with exact per-node (m_k, 1/d_k) on a line that starts at an open edge).
+// A workgroup (one wavefront) owns a kSeg x kSeg output tile and stages from b
+// the kLine x kLine window around it: the tile plus kHalo nodes on every side,
+// wrapped on a periodic axis and shifted to end at the edge on an open one.
+// Where the window is cut inside the lattice the recursions start from zero,
+// an error that decays by 2 - sqrt 3 per node and is ~7e-10 at the tile.
+// Lane r solves window row r along x in registers and puts it back in LDS;
+// lane c then solves window column c along p and writes the kept rows of the
+// kept columns.  The x-solved intermediate never leaves LDS.  For the FEL the
+// epilogue forms the FP64 bunching of the new state: a fixed-order per-tile
+// partial, and the instance's last tile sums the partials in tile order and
+// advances A (eq. 13c).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kSolveXThreads) void k_solve_x(LaunchArgs A) {
+template <int K>
+__device__ inline void solve_line_kind(float (&v)[kLine], int n) {
+    if (K == 2) line_solve<true, true>(v, n);
+    else if (K == 1) line_solve<true, false>(v, n);
+    else line_solve<false, false>(v, n);
+}
+
+__global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
+    static_assert(kSolveThreads == kLine, "one window line per lane");
     constexpr int ldw = kLine + 1;
-    __shared__ float lds[kSolveXThreads * ldw];
+    __shared__ float lds[kLine * ldw];
     __shared__ int s_d;
-    __shared__ float2 s_edge[kEdge];
 
     for (int it = blockIdx.x; it < A.total; it += gridDim.x) {
         const int item = tile_of(it, A.total);
@@ -415,141 +423,94 @@ __global__ __launch_bounds__(kSolveXThreads) void k_solve_x(LaunchArgs A) {
         const int tiles_x = (nx + kSeg - 1) / kSeg;
         const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
         const int X0 = txi * kSeg, tw = min(kSeg, nx - X0);
-        const int Y0 = tyi * kSolveXThreads, th = min(kSolveXThreads, np - Y0);
-        // the line window: kLine columns from w0 (unwrapped on a periodic axis)
-        const int w0 = periodic ? X0 - kHalo : open_window(X0, nx);
-        const int n = periodic ? kLine : min(kLine, nx);
-        const bool edge = !periodic && w0 == 0, masked = n < kLine;
+        const int Y0 = tyi * kSeg, th = min(kSeg, np - Y0);
+        // windows of kLine nodes per axis (x unwrapped on a periodic axis)
+        const int wx = periodic ? X0 - kHalo : open_window(X0, nx);
+        const int nwx = periodic ? kLine : min(kLine, nx);
+        const int wp = open_window(Y0, np), nwp = min(kLine, np);
+        const int kind_x = periodic ? 0 : (nwx < kLine ? 2 : (wx == 0 ? 1 : 0));
+        const int kind_p = nwp < kLine ? 2 : (wp == 0 ? 1 : 0);
         const int par = (I.parity0 + A.parity) & 1;
         const float* __restrict__ src = I.b;
-        float* __restrict__ dst = I.w[par];  // the state just deposited from
-
-        if (edge && threadIdx.x < kEdge) s_edge[threadIdx.x] = I.coef_x[min((int)threadIdx.x, nx - 1)];
-        // stage rows Y0..Y0+th of the window: lane = column
-        {
-            static_assert(kLine == kSolveXThreads, "one staged column per lane");
-            const int c = threadIdx.x;
-            int gc = w0 + min(c, n - 1);
-            if (periodic) gc = wrap_index(gc, nx, 1.0f / (float)nx);
-            gfloat* base = as_global(src) + (size_t)Y0 * nx;
-            unsigned q = in_vgpr((unsigned)gc);  // running offset (< 64 rows x nx)
-            const bool live = c < n;
-            if (th == kSolveXThreads) {
-                // a full tile: every row's load in flight at once
-                float tv[kSolveXThreads];
-#pragma unroll
-                for (int r = 0; r < kSolveXThreads; ++r) {
-                    tv[r] = base[q];
-                    q += (unsigned)nx;
-                }
-#pragma unroll
-                for (int r = 0; r < kSolveXThreads; ++r) lds[r * ldw + c] = live ? tv[r] : 0.0f;
-            } else {
-                for (int r = 0; r < th; ++r) {
-                    lds[r * ldw + c] = live ? base[q] : 0.0f;
-                    q += (unsigned)nx;
-                }
-            }
-        }
-        __syncthreads();
-
-        if ((int)threadIdx.x < th) {
-            float* row = lds + threadIdx.x * ldw;
-            if (masked) line_solve_lds<true, true>(row, n, s_edge);
-            else if (edge) line_solve_lds<true, false>(row, n, s_edge);
-            else line_solve_lds<false, false>(row, n, s_edge);
-        }
-        __syncthreads();
-
-        {
-            // two rows per store instruction: lane = (row parity, column)
-            static_assert(kSeg * 2 == kSolveXThreads, "two rows of a segment per wavefront");
-            const int c = threadIdx.x % kSeg;
-            if (c < tw) {
-                float* out = dst + (size_t)Y0 * nx + X0 + c;
-                const float* l = lds + (X0 - w0 + c);
-                for (int r = threadIdx.x / kSeg; r < th; r += 2) out[(size_t)r * nx] = l[r * ldw];
-            }
-        }
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(kSolvePThreads) void k_solve_p(LaunchArgs A) {
-    __shared__ int s_d;
-    __shared__ int s_last;
-    __shared__ float2 s_edge[kEdge];
-    __shared__ double s_red[2][kSolvePThreads / 64];
-
-    for (int it = blockIdx.x; it < A.total; it += gridDim.x) {
-        const int item = tile_of(it, A.total);
-        if (threadIdx.x == 0) s_d = find_instance(A.off, A.ninst, item);
-        __syncthreads();
-        const int d = __builtin_amdgcn_readfirstlane(s_d);
-        const VpInst& I = A.inst[d];
-        const int t = item - A.off[d];
-        const int nx = I.push.nx, np = I.push.np;
-        const int tiles_x = (nx + kSolvePThreads - 1) / kSolvePThreads;
-        const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
-        const int col = txi * kSolvePThreads + threadIdx.x;
-        const int Y0 = tyi * kSeg, kept = min(kSeg, np - Y0);
-        const int w0 = open_window(Y0, np), n = min(kLine, np);
-        const bool edge = w0 == 0, masked = n < kLine;
-        const int lo = Y0 - w0;  // the kept rows are window positions lo .. lo + kept
-        const int par = (I.parity0 + A.parity) & 1;
-        const float* __restrict__ src = I.w[par];
         float* __restrict__ dst = I.w[par ^ 1];
+        const int lane = threadIdx.x;
 
-        if (edge && threadIdx.x < kEdge) s_edge[threadIdx.x] = I.coef_p[min((int)threadIdx.x, np - 1)];
+        // stage the window: lane = window column.  Every row is loaded straight
+        // into its LDS row (global_load_lds: no registers hold the data), all
+        // rows in flight; lanes past the window and rows past a short lattice
+        // are zero.
+        {
+            int gc = wx + min(lane, nwx - 1);
+            if (periodic) gc = wrap_index(gc, nx, 1.0f / (float)nx);
+            const int rows = kind_p == 2 ? nwp : kLine;
+            if (lane < nwx) {
+                gfloat* p = as_global(src) + (size_t)wp * nx + gc;
+                for (int r = 0; r < rows; ++r)
+                    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(p + (size_t)r * nx),
+                                                     (__attribute__((address_space(3))) void*)(lds + r * ldw), 4, 0, 0);
+            } else {
+                for (int r = 0; r < rows; ++r) lds[r * ldw + lane] = 0.0f;
+            }
+            for (int r = rows; r < kLine; ++r) lds[r * ldw + lane] = 0.0f;
+            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+        }
         __syncthreads();
 
+        // x: lane = window row
+        {
+            float v[kLine];
+            float* row = lds + lane * ldw;
+#pragma unroll
+            for (int k = 0; k < kLine; ++k) v[k] = row[k];
+            if (kind_x == 2) solve_line_kind<2>(v, nwx);
+            else if (kind_x == 1) solve_line_kind<1>(v, nwx);
+            else solve_line_kind<0>(v, nwx);
+#pragma unroll
+            for (int k = 0; k < kLine; ++k) row[k] = v[k];
+        }
+        __syncthreads();
+
+        // p: lane = window column; the kept rows of the kept columns go out
         const bool fel = I.push.kind == kFel;
         double acc_re = 0.0, acc_im = 0.0;
-        if (col < nx) {
+        {
             float v[kLine];
-            gfloat* base = as_global(src) + (size_t)w0 * nx;
-            if (!masked) {
-                unsigned q = in_vgpr((unsigned)col);  // running offset (< kLine rows x nx)
+            float* col = lds + lane;
 #pragma unroll
-                for (int k = 0; k < kLine; ++k) {
-                    v[k] = base[q];
-                    q += (unsigned)nx;
-                }
-                if (edge) line_solve<true, false>(v, n, s_edge);
-                else line_solve<false, false>(v, n, s_edge);
-            } else {
-                const int nv = (int)in_vgpr((unsigned)n);
+            for (int k = 0; k < kLine; ++k) v[k] = col[k * ldw];
+            if (kind_p == 2) solve_line_kind<2>(v, nwp);
+            else if (kind_p == 1) solve_line_kind<1>(v, nwp);
+            else solve_line_kind<0>(v, nwp);
+            const int cx = lane - (X0 - wx);  // kept column, when in [0, tw)
+            if (cx >= 0 && cx < tw) {
+                const int gx = X0 + cx;
+                const int lo = Y0 - wp;  // the kept rows are window rows lo .. lo + th
+                float* o = dst + (size_t)Y0 * nx + gx;
+                unsigned qo = in_vgpr(0u);  // running offset of the kept row (< kSeg rows x nx)
+                double cre = 0.0, cim = 0.0;
+                auto keep = [&](int k) {
+                    o[qo] = v[k];
+                    qo += (unsigned)nx;
+                    if (fel) {
+                        const double2 e = I.fel_eq[wp + k];  // times e^{-i q}
+                        cre += (double)v[k] * e.x;
+                        cim -= (double)v[k] * e.y;
+                    }
+                };
+                if (lo == kHalo && th == kSeg) {
 #pragma unroll
-                for (int k = 0; k < kLine; ++k) {
-                    const unsigned q = in_vgpr((unsigned)(min(k, nv - 1) * nx + col));
-                    const float x = base[q];
-                    v[k] = k < nv ? x : 0.0f;
+                    for (int k = kHalo; k < kHalo + kSeg; ++k) keep(k);
+                } else {
+                    const int lov = (int)in_vgpr((unsigned)lo);
+#pragma unroll
+                    for (int k = 0; k < kLine; ++k)
+                        if ((unsigned)(k - lov) < (unsigned)th) keep(k);
                 }
-                line_solve<true, true>(v, n, s_edge);
-            }
-            float* o = dst + (size_t)w0 * nx + col;
-            double cre = 0.0, cim = 0.0;
-            auto keep = [&](int k) {
-                o[(size_t)k * nx] = v[k];
                 if (fel) {
-                    const double2 e = I.fel_eq[w0 + k];  // times e^{-i q}
-                    cre += (double)v[k] * e.x;
-                    cim -= (double)v[k] * e.y;
+                    const double2 e = I.fel_ex[gx];  // times e^{-i phi}
+                    acc_re = cre * e.x + cim * e.y;
+                    acc_im = cim * e.x - cre * e.y;
                 }
-            };
-            if (lo == kHalo && kept == kSeg) {
-#pragma unroll
-                for (int k = kHalo; k < kHalo + kSeg; ++k) keep(k);
-            } else {
-                const int lov = (int)in_vgpr((unsigned)lo);
-#pragma unroll
-                for (int k = 0; k < kLine; ++k)
-                    if ((unsigned)(k - lov) < (unsigned)kept) keep(k);
-            }
-            if (fel) {
-                const double2 e = I.fel_ex[col];  // times e^{-i phi}
-                acc_re = cre * e.x + cim * e.y;
-                acc_im = cim * e.x - cre * e.y;
             }
         }
 
@@ -560,23 +521,19 @@ __global__ __launch_bounds__(kSolvePThreads) void k_solve_p(LaunchArgs A) {
                 acc_re += __shfl_down(acc_re, o);
                 acc_im += __shfl_down(acc_im, o);
             }
-            const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-            if (lane == 0) { s_red[0][wid] = acc_re; s_red[1][wid] = acc_im; }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                double re = 0.0, im = 0.0;
-                for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { re += s_red[0][k]; im += s_red[1][k]; }
-                I.partials[2 * t] = re;
-                I.partials[2 * t + 1] = im;
+            bool last = false;
+            if (lane == 0) {
+                I.partials[2 * t] = acc_re;
+                I.partials[2 * t + 1] = acc_im;
                 __threadfence();
                 const uint32_t prev = atomicAdd(I.counters, 1u);
-                s_last = (prev == (uint32_t)(I.k2_tiles - 1));
+                last = prev == (uint32_t)(I.k2_tiles - 1);
             }
-            __syncthreads();
-            if (s_last) {
+            last = __shfl(last ? 1 : 0, 0) != 0;
+            if (last) {
                 __threadfence();
                 double re = 0.0, im = 0.0;
-                for (int k = threadIdx.x; k < I.k2_tiles; k += blockDim.x) {
+                for (int k = lane; k < I.k2_tiles; k += kSolveThreads) {
                     re += __builtin_nontemporal_load(&I.partials[2 * k]);
                     im += __builtin_nontemporal_load(&I.partials[2 * k + 1]);
                 }
@@ -584,13 +541,7 @@ __global__ __launch_bounds__(kSolvePThreads) void k_solve_p(LaunchArgs A) {
                     re += __shfl_down(re, o);
                     im += __shfl_down(im, o);
                 }
-                __syncthreads();
-                if (lane == 0) { s_red[0][wid] = re; s_red[1][wid] = im; }
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    re = 0.0;
-                    im = 0.0;
-                    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { re += s_red[0][k]; im += s_red[1][k]; }
+                if (lane == 0) {
                     double* st = I.fel_state;
                     const double inv_n0 = 1.0 / st[kN0];
                     // A advances by the bunching of the state that was pushed (eq. 13c)
@@ -701,13 +652,8 @@ hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_solve_x(const LaunchArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_solve_x, dim3(grid), dim3(kSolveXThreads), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_solve_p(const LaunchArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_solve_p, dim3(grid), dim3(kSolvePThreads), 0, s, a);
+hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_solve, dim3(grid), dim3(kSolveThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -717,7 +663,6 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
 }
 
 const void* deposit_kernel() { return reinterpret_cast<const void*>(&k_deposit); }
-const void* solve_x_kernel() { return reinterpret_cast<const void*>(&k_solve_x); }
-const void* solve_p_kernel() { return reinterpret_cast<const void*>(&k_solve_p); }
+const void* solve_kernel() { return reinterpret_cast<const void*>(&k_solve); }
 
 }  // namespace vp
