@@ -24,7 +24,7 @@ HBM_PEAK_GBS = 8000.0
 ALG_BYTES_PER_NODE = 8  # a step (and each of its kernels) must read one FP32 array and write one
 KERNELS = ("k_deposit", "k_solve")
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2007_12227_amd", "csrc", "vp_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2007_12227_amd", "csrc", f) for f in ("vp_kernels.hip", "vp_internal.h")]
 
 
 def log(msg):
@@ -119,14 +119,19 @@ def bench_served(binding, nreq, load, capacity, budget_gib):
 
 
 def kernel_source_sha():
+    """Hash of the kernel sources (kernels and the instance layout they read)."""
     import hashlib
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, deposit_tiles):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a copy of
-    known size), or None if there is none for the current kernel source."""
+    known size), or None if there is none for the current kernel source and
+    deposit tile shape."""
     path = os.path.join(PROFILES, f"{kernel}_{workload}_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -136,6 +141,8 @@ def measured_traffic(kernel, workload):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_sha():
+        return None
+    if vals.get("deposit_tiles") != "x".join(str(v) for v in deposit_tiles):
         return None
     return float(vals["bytes_per_launch"])
 
@@ -232,7 +239,7 @@ def main():
     dom = max(kus, key=kus.get)
     alg_bytes = ALG_BYTES_PER_NODE * N  # per launch of any of the three kernels
     achieved = alg_bytes / (kus[dom] * 1e-6) / 1e9
-    traffic = measured_traffic(dom, f"pendulum_band_{args.n}")
+    traffic = measured_traffic(dom, f"pendulum_band_{args.n}", tiles["k1"])
 
     line = {
         "metric": METRIC,

@@ -163,7 +163,8 @@ int vp_set_launch(vp_grid* g, int32_t use_graph);
 /* Measurement helper: nsteps steps exactly as vp_step with direct launches,
  * with HIP events recorded on the grid's stream around every kernel.
  * us[0] and us[1] receive the mean duration in microseconds of the deposit
- * kernel and of the solve kernel.  Waits for the stream. */
+ * kernel and of the solve (for the FEL including the field update that
+ * follows it).  Waits for the stream. */
 int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]);
 
 /* Time candidate tile shapes on this grid for step size dt and keep the

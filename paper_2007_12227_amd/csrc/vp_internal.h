@@ -14,7 +14,8 @@
 //              around it (a 16-node halo per side makes the tile independent of
 //              its neighbours to within (2-sqrt 3)^16 ~ 7e-10), rows then
 //              columns, one line per lane.  For the FEL its epilogue also forms
-//              the FP64 bunching of the new state.
+//              the FP64 bunching partials of the new state, which k_fel_field
+//              sums to advance the FEL field.
 #pragma once
 
 #include <stdint.h>
@@ -37,6 +38,7 @@ constexpr int kDepositThreads = 256;
 constexpr int kSeg = 32;                 // solve segment length per lane (kept nodes)
 constexpr int kLine = kSeg + 2 * kHalo;  // a lane's line: segment plus both halos
 constexpr int kSolveThreads = kLine;     // solve: one window line per lane
+constexpr int kFieldThreads = 256;       // FEL field update: one workgroup per instance
 constexpr int kReduceBlocks = 256;
 constexpr int kReduceThreads = 256;
 constexpr int kMoments = 10;      // FP64 sums produced by the reduction kernel
@@ -186,13 +188,11 @@ struct VpInst {
     float* b;
     const float4* tab_x;     // per column push table
     const float4* tab_p;     // per row push table
-    const float2* coef_x;    // (m_i, 1/d_i) of the LU of tridiag(1,4,1), open x only
-    const float2* coef_p;    // same along p (always open)
     const double2* fel_ex;   // (cos phi_i, sin phi_i)
     const double2* fel_eq;   // (cos q_j, sin q_j), q_j the half drift of row j
     double* fel_state;       // [A_re, A_im, b_re, b_im, N0, dz_b, ...]
     double* partials;        // per solve tile: bunching partial (re, im)
-    uint32_t* counters;      // [0]: solve epilogue, [1]: reduction, [kRangeFlag]: deposit range
+    uint32_t* counters;      // [1]: reduction, [kRangeFlag]: deposit range
 };
 
 constexpr int kRangeFlag = 2;  // counters slot set when a deposit cell sum leaves half its range
@@ -224,9 +224,11 @@ struct ReduceArgs {
 // launchers (vp_kernels.hip)
 hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, hipStream_t s);
 hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s);
+hipError_t launch_fel_field(const LaunchArgs& a, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 const void* deposit_kernel();
 const void* solve_kernel();
+const void* fel_field_kernel();
 
 // Deposit LDS image: (tx + 8) x (ty + 8) 64-bit cells.
 inline size_t deposit_lds_bytes(int tx, int ty) { return sizeof(int64_t) * (size_t)(tx + 2 * kPad) * (ty + 2 * kPad); }

@@ -395,8 +395,7 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
 // lane c then solves window column c along p and writes the kept rows of the
 // kept columns.  The x-solved intermediate never leaves LDS.  For the FEL the
 // epilogue forms the FP64 bunching of the new state: a fixed-order per-tile
-// partial, and the instance's last tile sums the partials in tile order and
-// advances A (eq. 13c).
+// partial per tile (k_fel_field sums them).
 // ---------------------------------------------------------------------------
 template <int K>
 __device__ inline void solve_line_kind(float (&v)[kLine], int n) {
@@ -409,6 +408,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
     static_assert(kSolveThreads == kLine, "one window line per lane");
     constexpr int ldw = kLine + 1;
     __shared__ float lds[kLine * ldw];
+    __shared__ double2 s_eq[kSeg];  // FEL: e^{iq} of the tile's rows
     __shared__ int s_d;
 
     for (int it = blockIdx.x; it < A.total; it += gridDim.x) {
@@ -435,6 +435,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
         float* __restrict__ dst = I.w[par ^ 1];
         const int lane = threadIdx.x;
 
+        const bool fel = I.push.kind == kFel;
+        if (fel && lane < th) s_eq[lane] = I.fel_eq[Y0 + lane];
         // stage the window: lane = window column.  Every row is loaded straight
         // into its LDS row (global_load_lds: no registers hold the data), all
         // rows in flight; lanes past the window and rows past a short lattice
@@ -471,7 +473,6 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
         __syncthreads();
 
         // p: lane = window column; the kept rows of the kept columns go out
-        const bool fel = I.push.kind == kFel;
         double acc_re = 0.0, acc_im = 0.0;
         {
             float v[kLine];
@@ -487,24 +488,35 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
                 const int lo = Y0 - wp;  // the kept rows are window rows lo .. lo + th
                 float* o = dst + (size_t)Y0 * nx + gx;
                 unsigned qo = in_vgpr(0u);  // running offset of the kept row (< kSeg rows x nx)
-                double cre = 0.0, cim = 0.0;
-                auto keep = [&](int k) {
+                auto store = [&](int k) {
                     o[qo] = v[k];
                     qo += (unsigned)nx;
-                    if (fel) {
-                        const double2 e = I.fel_eq[wp + k];  // times e^{-i q}
-                        cre += (double)v[k] * e.x;
-                        cim -= (double)v[k] * e.y;
-                    }
+                };
+                // FEL: the bunching sums first, in a loop with no stores, so that
+                // its table loads are not ordered behind the stores
+                double cre = 0.0, cim = 0.0;
+                auto bunch = [&](int k) {
+                    const double2 e = s_eq[wp + k - Y0];  // times e^{-i q}
+                    cre += (double)v[k] * e.x;
+                    cim -= (double)v[k] * e.y;
                 };
                 if (lo == kHalo && th == kSeg) {
+                    if (fel) {
 #pragma unroll
-                    for (int k = kHalo; k < kHalo + kSeg; ++k) keep(k);
+                        for (int k = kHalo; k < kHalo + kSeg; ++k) bunch(k);
+                    }
+#pragma unroll
+                    for (int k = kHalo; k < kHalo + kSeg; ++k) store(k);
                 } else {
                     const int lov = (int)in_vgpr((unsigned)lo);
+                    if (fel) {
+#pragma unroll
+                        for (int k = 0; k < kLine; ++k)
+                            if ((unsigned)(k - lov) < (unsigned)th) bunch(k);
+                    }
 #pragma unroll
                     for (int k = 0; k < kLine; ++k)
-                        if ((unsigned)(k - lov) < (unsigned)th) keep(k);
+                        if ((unsigned)(k - lov) < (unsigned)th) store(k);
                 }
                 if (fel) {
                     const double2 e = I.fel_ex[gx];  // times e^{-i phi}
@@ -515,47 +527,63 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
         }
 
         if (fel) {
-            // FP64 bunching of the new state: tile partial, then the last tile
-            // of the instance sums all partials in tile order.
+            // FP64 bunching of the new state: this tile's partial (k_fel_field
+            // sums the partials)
             for (int o = 32; o > 0; o >>= 1) {
                 acc_re += __shfl_down(acc_re, o);
                 acc_im += __shfl_down(acc_im, o);
             }
-            bool last = false;
             if (lane == 0) {
                 I.partials[2 * t] = acc_re;
                 I.partials[2 * t + 1] = acc_im;
-                __threadfence();
-                const uint32_t prev = atomicAdd(I.counters, 1u);
-                last = prev == (uint32_t)(I.k2_tiles - 1);
-            }
-            last = __shfl(last ? 1 : 0, 0) != 0;
-            if (last) {
-                __threadfence();
-                double re = 0.0, im = 0.0;
-                for (int k = lane; k < I.k2_tiles; k += kSolveThreads) {
-                    re += __builtin_nontemporal_load(&I.partials[2 * k]);
-                    im += __builtin_nontemporal_load(&I.partials[2 * k + 1]);
-                }
-                for (int o = 32; o > 0; o >>= 1) {
-                    re += __shfl_down(re, o);
-                    im += __shfl_down(im, o);
-                }
-                if (lane == 0) {
-                    double* st = I.fel_state;
-                    const double inv_n0 = 1.0 / st[kN0];
-                    // A advances by the bunching of the state that was pushed (eq. 13c)
-                    st[kA] += I.fel_dz * st[kBn];
-                    st[kA + 1] += I.fel_dz * st[kBn + 1];
-                    st[kBn] = re * inv_n0;
-                    st[kBn + 1] = im * inv_n0;
-                    st[kDzB] = I.fel_dz;
-                    __threadfence();
-                    atomicExch(I.counters, 0u);
-                }
             }
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_fel_field: one workgroup per instance of the launch list; for an FEL
+// instance it sums the solve's per-tile bunching partials in a fixed order
+// (thread-strided, then a fixed shuffle tree) and advances the field: A moves
+// by dz times the bunching of the state that was pushed (eq. 13c), and the new
+// state's bunching is kept for the next kick.  A kernel of its own, because a
+// last-tile-sums scheme inside k_solve needs a device-scope release per tile,
+// which on a multi-XCD part writes back the L2 and costs more than the solve.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kFieldThreads) void k_fel_field(LaunchArgs A) {
+    __shared__ double s_red[2][kFieldThreads / 64];
+    const VpInst& I = A.inst[blockIdx.x];
+    if (I.push.kind != kFel) return;
+    double re = 0.0, im = 0.0;
+    for (int k = threadIdx.x; k < I.k2_tiles; k += kFieldThreads) {
+        re += I.partials[2 * k];
+        im += I.partials[2 * k + 1];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        re += __shfl_down(re, o);
+        im += __shfl_down(im, o);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_red[0][wid] = re;
+        s_red[1][wid] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        re = 0.0;
+        im = 0.0;
+        for (int k = 0; k < kFieldThreads / 64; ++k) {
+            re += s_red[0][k];
+            im += s_red[1][k];
+        }
+        double* st = I.fel_state;
+        const double inv_n0 = 1.0 / st[kN0];
+        st[kA] += I.fel_dz * st[kBn];
+        st[kA + 1] += I.fel_dz * st[kBn + 1];
+        st[kBn] = re * inv_n0;
+        st[kBn + 1] = im * inv_n0;
+        st[kDzB] = I.fel_dz;
     }
 }
 
@@ -657,6 +685,11 @@ hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_fel_field(const LaunchArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_fel_field, dim3(a.ninst), dim3(kFieldThreads), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a);
     return hipGetLastError();
@@ -664,5 +697,6 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
 
 const void* deposit_kernel() { return reinterpret_cast<const void*>(&k_deposit); }
 const void* solve_kernel() { return reinterpret_cast<const void*>(&k_solve); }
+const void* fel_field_kernel() { return reinterpret_cast<const void*>(&k_fel_field); }
 
 }  // namespace vp
