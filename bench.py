@@ -237,7 +237,7 @@ def main():
     g.close()
     log("kernels: " + ", ".join(f"{k} {v:.2f} us" for k, v in kus.items()))
     dom = max(kus, key=kus.get)
-    alg_bytes = ALG_BYTES_PER_NODE * N  # per launch of any of the three kernels
+    alg_bytes = ALG_BYTES_PER_NODE * N  # per launch of either step kernel
     achieved = alg_bytes / (kus[dom] * 1e-6) / 1e9
     traffic = measured_traffic(dom, f"pendulum_band_{args.n}", tiles["k1"])
 

@@ -1,7 +1,8 @@
 // vp_internal.h -- data layout shared by the host runtime and the gfx950 kernels of libvp.
 //
 // One step of the method (Edelen & Webb, Sec. "An Algorithm Based on Phase
-// Space Density Conservation", eqs. 6-10) runs as two kernels:
+// Space Density Conservation", eqs. 6-10) runs as two kernels (plus, for the
+// FEL, a one-workgroup field update, k_fel_field):
 //   k_deposit: every lattice node is pushed (its position is its index, so
 //              nothing but w is read) and its weight is scattered onto the
 //              4x4 lattice taps of its moved tent with cubic B-spline weights

@@ -119,6 +119,33 @@ def test_graph_and_plain_launches_agree(B):
     assert oracle.rel_l1(a, b) <= 1e-6
 
 
+@pytest.mark.parametrize("kind", ["pendulum", "fel"])
+def test_results_bitwise_independent_of_deposit_tiling(B, kind):
+    """The deposit sums taps as exact integers, so any tiling (each node is
+    pushed by every tile whose source box holds it) gives the same bits."""
+    inst = pendulum_band(256, steps=30) if kind == "pendulum" else fel_gaussian(192, 30, npp=160)
+    ref = None
+    for k1 in [(64, 32), (128, 16), (24, 5), (200, 24), (16, 8)]:
+        g = B.grid_for(inst)
+        g.set_tiles(k1)
+        g.step(inst.dt, 30)
+        got = g.density()
+        g.close()
+        if ref is None:
+            ref = got
+        else:
+            assert np.array_equal(got, ref), k1
+
+
+def test_fel_graph_and_plain_launches_agree(B):
+    inst = fel_gaussian(192, 40, npp=160)
+    w32 = inst.w0.astype(np.float32)
+    a, ma = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 40, graph=True)
+    b, mb = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 40, graph=False)
+    assert np.array_equal(a, b)
+    assert (ma["A_re"], ma["A_im"]) == (mb["A_re"], mb["A_im"])
+
+
 # ---- pins re-run on the GPU path ----
 
 def test_gpu_rotation_quarter_turn_is_permutation(B):
