@@ -127,11 +127,16 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload, deposit_tiles):
+def deposit_shape(tiles):
+    """Deposit launch shape as "COLSxROWSxTHREADS"."""
+    return "x".join(str(v) for v in (*tiles["k1"], tiles["threads"]))
+
+
+def measured_traffic(kernel, workload, shape):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a copy of
     known size), or None if there is none for the current kernel source and
-    deposit tile shape."""
+    deposit launch shape."""
     path = os.path.join(PROFILES, f"{kernel}_{workload}_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -142,7 +147,7 @@ def measured_traffic(kernel, workload, deposit_tiles):
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_sha():
         return None
-    if vals.get("deposit_tiles") != "x".join(str(v) for v in deposit_tiles):
+    if vals.get("deposit_shape") != shape:
         return None
     return float(vals["bytes_per_launch"])
 
@@ -180,8 +185,8 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
     ap.add_argument("--tiles", default=None,
-                    help="deposit tile WxH for the tuned path instead of autotuning (uniform dispatches "
-                         "for profiling)")
+                    help="deposit launch shape COLSxROWSxTHREADS for the tuned path instead of autotuning "
+                         "(uniform dispatches for profiling)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (untuned, no graph) run")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -219,8 +224,8 @@ def main():
     # tuned path: autotuned deposit tiles, steps replayed from HIP graphs
     g = binding.grid_for(inst)
     if args.tiles:
-        tx, ty = (int(v) for v in args.tiles.lower().split("x"))
-        g.set_tiles((tx, ty))
+        tx, ty, nt = (int(v) for v in args.tiles.lower().split("x"))
+        g.set_tiles((tx, ty), nt)
         tune_us = None
     else:
         tune_us = g.autotune(inst.dt)
@@ -239,7 +244,7 @@ def main():
     dom = max(kus, key=kus.get)
     alg_bytes = ALG_BYTES_PER_NODE * N  # per launch of either step kernel
     achieved = alg_bytes / (kus[dom] * 1e-6) / 1e9
-    traffic = measured_traffic(dom, f"pendulum_band_{args.n}", tiles["k1"])
+    traffic = measured_traffic(dom, f"pendulum_band_{args.n}", deposit_shape(tiles))
 
     line = {
         "metric": METRIC,
@@ -255,7 +260,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"pendulum_band_{args.n}", "nx": args.n, "np": args.n, "dt": inst.dt,
-                   "a": 1.0, "deposit_tiles": tiles["k1"], "launch": "hip-graph"},
+                   "a": 1.0, "deposit_tiles": tiles["k1"], "deposit_threads": tiles["threads"],
+                   "launch": "hip-graph"},
         "plain": None if plain is None else {"value": plain, "ms_per_step": 1e3 * plain_s / args.steps,
                                              "speedup": value / plain},
         "kernels_us": kus,

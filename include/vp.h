@@ -116,10 +116,12 @@ typedef struct {
     int64_t nonfinite;
 } vp_moments_t;
 
-/* Tile shape of the deposit kernel (destination tile, in lattice nodes).
- * Zero fields keep the current value.  (The solve works on fixed 32x32 tiles.) */
+/* Launch shape of the deposit kernel: destination tile (in lattice nodes) and
+ * threads per workgroup (a multiple of 64, at most 1024).  Zero fields keep
+ * the current value.  (The solve works on fixed 32x32 tiles.) */
 typedef struct {
     int32_t k1_tx, k1_ty;
+    int32_t k1_threads;
 } vp_tiles;
 
 /* Bytes of device workspace a grid of this shape needs (0 if the axes are invalid). */
@@ -151,8 +153,10 @@ int vp_step(vp_grid* g, double dt, int64_t nsteps);
 /* Diagnostics of the current state; waits for the stream. */
 int vp_moments(vp_grid* g, vp_moments_t* out);
 
-/* Deposit tile shape.  vp_set_tiles validates it (VP_EINVAL if the tile's
- * local memory would exceed the device limit). */
+/* Deposit launch shape.  vp_set_tiles validates it (VP_EINVAL if the tile's
+ * local memory would exceed the device limit or the thread count is not a
+ * multiple of 64 in [64, 1024]).  A new grid starts from a shape chosen by
+ * its lattice size; vp_autotune picks one by timing. */
 int vp_set_tiles(vp_grid* g, const vp_tiles* t);
 int vp_get_tiles(const vp_grid* g, vp_tiles* t);
 

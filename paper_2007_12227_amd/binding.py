@@ -51,7 +51,7 @@ class Moments(C.Structure):
 
 
 class Tiles(C.Structure):
-    _fields_ = [("k1_tx", C.c_int32), ("k1_ty", C.c_int32)]
+    _fields_ = [("k1_tx", C.c_int32), ("k1_ty", C.c_int32), ("k1_threads", C.c_int32)]
 
 
 _lib = None
@@ -215,14 +215,15 @@ class Grid:
         d["status"] = rc
         return d
 
-    def set_tiles(self, k1=(0, 0)):
-        """Deposit tile shape (columns, rows)."""
-        check(lib().vp_set_tiles(self._h, C.byref(Tiles(k1[0], k1[1]))))
+    def set_tiles(self, k1=(0, 0), threads: int = 0):
+        """Deposit launch shape: tile (columns, rows) and threads per workgroup
+        (zero keeps the current value)."""
+        check(lib().vp_set_tiles(self._h, C.byref(Tiles(k1[0], k1[1], threads))))
 
     def tiles(self) -> dict:
         t = Tiles()
         check(lib().vp_get_tiles(self._h, C.byref(t)))
-        return {"k1": (t.k1_tx, t.k1_ty)}
+        return {"k1": (t.k1_tx, t.k1_ty), "threads": t.k1_threads}
 
     def set_launch(self, use_graph: bool):
         check(lib().vp_set_launch(self._h, int(bool(use_graph))))

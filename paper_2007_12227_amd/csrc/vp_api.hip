@@ -63,7 +63,7 @@ double spacing(const vp_axis& a) { return (a.hi - a.lo) / (a.periodic ? a.n : a.
 // Workspace layout: every piece 256-byte aligned.
 struct Layout {
     size_t w0, w1, b, tab_x, tab_p, fel_ex, fel_eq, fel_state, partials, counters,
-        inst, off, moments, total;
+        inst, off, moments, boxes, total;
     size_t partial_doubles;
 };
 
@@ -87,6 +87,7 @@ Layout layout(int nx, int np) {
     L.inst = take(sizeof(VpInst));
     L.off = take(8 * sizeof(int32_t));
     L.moments = take(kMoments * 8);
+    L.boxes = take(box_capacity(nx, np) * sizeof(int4));
     L.total = o;
     return L;
 }
@@ -99,6 +100,7 @@ struct LaunchList {
     int ninst = 0, total1 = 0, total2 = 0;
     bool has_fel = false;  // an FEL instance: the field kernel follows the solve
     size_t lds1 = 0;
+    int threads1 = 256;  // deposit workgroup size
     hipStream_t stream = nullptr;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
 
@@ -112,13 +114,13 @@ struct LaunchList {
     // the kernels of one step: {kernel, off, total (= grid), lds, threads}
     struct K { const void* fn; const int32_t* off; int total; size_t lds; int threads; };
     int kernels(K (&k)[3]) const {
-        k[0] = K{deposit_kernel(), d_off1, total1, lds1, kDepositThreads};
+        k[0] = K{deposit_kernel(), d_off1, total1, lds1, threads1};
         k[1] = K{solve_kernel(), d_off2, total2, 0, kSolveThreads};
         k[2] = K{fel_field_kernel(), d_off2, ninst, 0, kFieldThreads};
         return has_fel ? 3 : 2;
     }
     int enqueue_step(int parity) const {
-        HIP_TRY(launch_deposit(args(d_off1, total1, parity), total1, lds1, stream));
+        HIP_TRY(launch_deposit(args(d_off1, total1, parity), total1, lds1, threads1, stream));
         HIP_TRY(launch_solve(args(d_off2, total2, parity), total2, stream));
         if (has_fel) HIP_TRY(launch_fel_field(args(d_off2, ninst, parity), stream));
         return VP_OK;
@@ -210,11 +212,24 @@ int validate_tiles(const vp_grid* g, const vp_tiles& t) {
     if (t.k1_tx < kMinTile || t.k1_ty < 1)
         return fail(VP_EINVAL, "deposit tile below the minimum (k1_tx >= %d, k1_ty >= 1)", kMinTile);
     if (t.k1_tx > 4096 || t.k1_ty > 1024) return fail(VP_EINVAL, "deposit tile too large");
+    if (t.k1_threads < 64 || t.k1_threads > kDepositMaxThreads || t.k1_threads % 64)
+        return fail(VP_EINVAL, "deposit threads %d: need a multiple of 64 in [64, %d]", t.k1_threads,
+                    kDepositMaxThreads);
     if (deposit_lds_bytes(t.k1_tx, t.k1_ty) > g_max_lds)
         return fail(VP_EINVAL, "deposit tile %dx%d needs %zu bytes of LDS (limit %zu)", t.k1_tx, t.k1_ty,
                     deposit_lds_bytes(t.k1_tx, t.k1_ty), g_max_lds);
     (void)g;
     return VP_OK;
+}
+
+// Starting deposit shape by lattice size: the largest of the timed shapes
+// that still gives every compute unit a tile (256 of them), since larger
+// tiles rescan fewer halo sources and keep more waves per compute unit.
+vp_tiles default_tiles(int nx, int np) {
+    const double nodes = (double)nx * np;
+    if (nodes >= 256.0 * 128 * 128) return vp_tiles{128, 128, 1024};
+    if (nodes >= 256.0 * 128 * 64) return vp_tiles{128, 64, 512};
+    return vp_tiles{64, 32, 256};
 }
 
 vp_tiles clip_tiles(const vp_grid* g, vp_tiles t) {
@@ -233,6 +248,23 @@ int upload_inst(vp_grid* g) {
     I.k1_tiles = I.k1_tiles_x * ((g->p.n + t.k1_ty - 1) / t.k1_ty);
     I.k2_tiles = ((g->x.n + kSeg - 1) / kSeg) * ((g->p.n + kSeg - 1) / kSeg);
     I.parity0 = 0;
+    // source boxes of a push that does not depend on the state: planned here
+    // once, instead of by one thread of every deposit tile at every step
+    I.boxes = nullptr;
+    std::vector<int4> boxes;
+    if (I.push.kind != kFel && (size_t)I.k1_tiles <= box_capacity(g->x.n, g->p.n)) {
+        boxes.resize(I.k1_tiles);
+        for (int t2 = 0; t2 < I.k1_tiles; ++t2) {
+            const int tyi = t2 / I.k1_tiles_x, txi = t2 - tyi * I.k1_tiles_x;
+            const int X0 = txi * I.k1_tx, Y0 = tyi * I.k1_ty;
+            int b[4];
+            source_box(I.push, X0, std::min(X0 + I.k1_tx, g->x.n), Y0, std::min(Y0 + I.k1_ty, g->p.n), b);
+            boxes[t2] = make_int4(b[0], b[1], b[2], b[3]);
+        }
+        I.boxes = g->at<int4>(g->L.boxes);
+        HIP_TRY(hipMemcpyAsync(g->at<int4>(g->L.boxes), boxes.data(), boxes.size() * sizeof(int4),
+                               hipMemcpyHostToDevice, g->stream));
+    }
     int32_t off[4] = {0, I.k1_tiles, 0, I.k2_tiles};
     HIP_TRY(hipMemcpyAsync(g->list.d_inst, &I, sizeof(VpInst), hipMemcpyHostToDevice, g->stream));
     HIP_TRY(hipMemcpyAsync(g->list.d_off1, off, sizeof off, hipMemcpyHostToDevice, g->stream));
@@ -242,6 +274,7 @@ int upload_inst(vp_grid* g) {
     g->list.total1 = I.k1_tiles;
     g->list.total2 = I.k2_tiles;
     g->list.lds1 = deposit_lds_bytes(t.k1_tx, t.k1_ty);
+    g->list.threads1 = t.k1_threads;
     g->list.drop_graphs();
     return VP_OK;
 }
@@ -415,7 +448,7 @@ int vp_create_grid(const vp_grid_desc* d, vp_grid** out) {
     g->stream = reinterpret_cast<hipStream_t>(d->stream);
     g->ws = reinterpret_cast<char*>(d->workspace);
     g->L = L;
-    g->tiles = vp_tiles{64, 32};
+    g->tiles = default_tiles(d->x.n, d->p.n);
     g->list.stream = g->stream;
     g->list.d_inst = g->at<VpInst>(L.inst);
     g->list.d_off1 = g->at<int32_t>(L.off);
@@ -543,7 +576,7 @@ int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]) {
     for (int64_t s = 0; s < nsteps; ++s) {
         const int par = (int)((g->parity + s) & 1);
         HIP_TRY(hipEventRecord(ev[3 * s], g->stream));
-        HIP_TRY(launch_deposit(L.args(L.d_off1, L.total1, par), L.total1, L.lds1, g->stream));
+        HIP_TRY(launch_deposit(L.args(L.d_off1, L.total1, par), L.total1, L.lds1, L.threads1, g->stream));
         HIP_TRY(hipEventRecord(ev[3 * s + 1], g->stream));
         HIP_TRY(launch_solve(L.args(L.d_off2, L.total2, par), L.total2, g->stream));
         if (L.has_fel) HIP_TRY(launch_fel_field(L.args(L.d_off2, L.ninst, par), g->stream));
@@ -606,6 +639,7 @@ int vp_set_tiles(vp_grid* g, const vp_tiles* t) {
     vp_tiles n = g->tiles;
     if (t->k1_tx) n.k1_tx = t->k1_tx;
     if (t->k1_ty) n.k1_ty = t->k1_ty;
+    if (t->k1_threads) n.k1_threads = t->k1_threads;
     int rc = validate_tiles(g, n);
     if (rc) return rc;
     g->tiles = n;
@@ -677,13 +711,15 @@ int vp_autotune(vp_grid* g, double dt, double* best_us) {
         *us = 1000.f * ms / reps;
         return VP_OK;
     };
-    const int k1c[][2] = {{64, 16}, {64, 32}, {64, 64}, {128, 16}, {128, 32}, {128, 64}, {256, 16}, {256, 32}};
+    const int k1c[][3] = {{64, 16, 256},  {64, 32, 256},  {64, 64, 256},   {128, 32, 256},  {64, 64, 512},
+                          {128, 64, 512}, {128, 64, 640}, {128, 64, 1024}, {128, 128, 1024}, {256, 64, 1024}};
     vp_tiles best = g->tiles;
     float best_t = 1e30f;
     for (auto& c : k1c) {
         vp_tiles t = best;
         t.k1_tx = c[0];
         t.k1_ty = c[1];
+        t.k1_threads = c[2];
         float us;
         // a candidate must beat the incumbent by 2%, so that near-ties (timing
         // noise) do not flip the choice from run to run
@@ -728,7 +764,9 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
     std::vector<VpInst> insts(n);
     std::vector<int32_t> off1(n + 1, 0), off2(n + 1, 0);
     size_t lds1 = 0;
+    int threads1 = 64;
     for (int k = 0; k < n; ++k) {
+        threads1 = std::max(threads1, grids[k]->list.threads1);
         insts[k] = grids[k]->inst;
         insts[k].parity0 = grids[k]->parity;
         off1[k + 1] = off1[k] + insts[k].k1_tiles;
@@ -745,6 +783,7 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
     L.has_fel = false;
     for (int k = 0; k < n; ++k) L.has_fel |= insts[k].push.kind == kFel;
     L.lds1 = lds1;
+    L.threads1 = threads1;  // the deposit loops stride by the workgroup size: any size serves every tile
     hipError_t e = hipMalloc(&L.d_inst, sizeof(VpInst) * n);
     if (e == hipSuccess) e = hipMalloc(&L.d_off1, sizeof(int32_t) * 2 * (n + 1));
     L.d_off2 = L.d_off1 + (n + 1);

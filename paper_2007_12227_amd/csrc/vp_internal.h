@@ -35,7 +35,7 @@ constexpr int kHalo = 16;         // warm-up nodes on each side of a solve tile
 constexpr int kEdge = 32;         // nodes from an open edge whose LU coefficients are tabulated
 constexpr int kPad = 4;           // trash border of a deposit tile (per side)
 constexpr int kFixBits = 40;      // deposit cell sums: 64-bit fixed point at 2^-40 of 2^e > max|w0|
-constexpr int kDepositThreads = 256;
+constexpr int kDepositMaxThreads = 1024;  // deposit workgroup: a multiple of 64 up to this
 constexpr int kSeg = 32;                 // solve segment length per lane (kept nodes)
 constexpr int kLine = kSeg + 2 * kHalo;  // a lane's line: segment plus both halos
 constexpr int kSolveThreads = kLine;     // solve: one window line per lane
@@ -194,7 +194,16 @@ struct VpInst {
     double* fel_state;       // [A_re, A_im, b_re, b_im, N0, dz_b, ...]
     double* partials;        // per solve tile: bunching partial (re, im)
     uint32_t* counters;      // [1]: reduction, [kRangeFlag]: deposit range
+    const int4* boxes;       // per deposit tile: source box (x0, x1, y0, y1) planned on the host,
+                             // or null: the deposit plans it (the FEL kick depends on the field)
 };
+
+// Host-planned source boxes: room for one per deposit tile of 32 x 16 nodes
+// (smaller tiles plan their boxes in the kernel).
+constexpr int kBoxTileX = 32, kBoxTileY = 16;
+inline size_t box_capacity(int nx, int np) {
+    return (size_t)((nx + kBoxTileX - 1) / kBoxTileX) * ((np + kBoxTileY - 1) / kBoxTileY);
+}
 
 constexpr int kRangeFlag = 2;  // counters slot set when a deposit cell sum leaves half its range
 
@@ -223,7 +232,7 @@ struct ReduceArgs {
 };
 
 // launchers (vp_kernels.hip)
-hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s);
 hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_fel_field(const LaunchArgs& a, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);

@@ -97,8 +97,12 @@ __device__ inline int wrap_index(int i, int n, float inv_n) {
 #endif
 typedef VP_GLOBAL const float gfloat;
 typedef VP_GLOBAL const float4 gfloat4;
+typedef VP_GLOBAL float gfloat_out;
 __device__ inline gfloat* as_global(const float* p) { return (gfloat*)p; }
 __device__ inline gfloat4* as_global(const float4* p) { return (gfloat4*)p; }
+// Stores through a global (not flat) pointer: a flat store also counts on
+// the LDS counter, so a later wait for an LDS read would wait for it too.
+__device__ inline gfloat_out* as_global_out(float* p) { return (gfloat_out*)p; }
 __device__ inline unsigned in_vgpr(unsigned v) {
     asm volatile("" : "+v"(v));
     return v;
@@ -197,13 +201,13 @@ __device__ inline int open_window(int s0, int n) { return max(0, min(s0 - kHalo,
 
 // Push one node (source row j, unwrapped column ii, weight w already scaled to
 // fixed point) and add its 16 B-spline taps into the LDS tile.
-__device__ inline void deposit_node(long long* acc, int j, int ii, float w, float4 tx, float4 tp, int kind,
-                                    float alpha, float beta, float kd, int X0, int Y0, int ldw, int cmax,
-                                    int rmax) {
-    if (w == 0.0f) return;
+template <bool SHO>
+__device__ inline void deposit_node(long long* acc, int j, int ii, float w, float4 tx, float4 tp,
+                                    float alpha, float beta, float kd, int X0, int Y0, int tw, int th, int ldw,
+                                    int cmax, int rmax) {
     int ku, kv;
     float fu, fv;
-    if (kind == kSho) {
+    if (SHO) {
         float su, eu, sv, ev;
         two_sum(tx.x, tp.x, su, eu);
         two_sum(tx.z, tp.z, sv, ev);
@@ -222,9 +226,12 @@ __device__ inline void deposit_node(long long* acc, int j, int ii, float w, floa
     double bx[4], bp[4];
     bspline_taps(fu, bx);
     bspline_taps(fv, bp);
-    // tap (q, r) lands on row j + kv - 1 + q, column ii + ku - 1 + r
-    const int c0 = clampi(ii + ku - 1 - X0 + kPad, 0, cmax);
-    const int r0 = clampi(j + kv - 1 - Y0 + kPad, 0, rmax);
+    // tap (q, r) lands on tile row row0 + q, column col0 + r; a node none of
+    // whose taps meets the tile adds nothing (its lane sits the atomics out)
+    const int col0 = ii + ku - 1 - X0, row0 = j + kv - 1 - Y0;
+    if ((unsigned)(col0 + 3) >= (unsigned)(tw + 3) || (unsigned)(row0 + 3) >= (unsigned)(th + 3)) return;
+    const int c0 = clampi(col0 + kPad, 0, cmax);
+    const int r0 = clampi(row0 + kPad, 0, rmax);
     long long* base = acc + r0 * ldw + c0;
     // tap value w * bp * bx: FP64 product, rounded once, exactly, into the
     // fixed-point tile sum, so the deposit adds no product rounding to the
@@ -238,6 +245,91 @@ __device__ inline void deposit_node(long long* acc, int j, int ii, float w, floa
     }
 }
 
+// The box's sources s = r bw + c, handed out to the wavefronts in chunks of
+// 64 kU consecutive sources from an LDS counter: a wave that runs ahead takes
+// more chunks, so the waves of a tile finish together (a static split leaves
+// them waiting at the barrier for the slowest one).  Lane l takes sources
+// c0 + l + 64 h of chunk c0.  COL: 0 open x axis; 1 periodic, box within
+// [-nx, 2 nx) (one correction per side); 2 periodic, general wrap.  Kind and
+// wrap mode are template parameters, so the loop body is one basic block,
+// free of per-node branches.
+constexpr int kU = 4;            // sources per lane per chunk, their loads all in flight
+constexpr int kChunk = 64 * kU;  // sources per chunk
+
+struct SourceScan {
+    long long* acc;
+    int* next;  // LDS: start of the next unclaimed chunk
+    gfloat* w;
+    gfloat4* tab_x;
+    gfloat4* tab_p;
+    int nx, bx0, by0, bw, nsrc;
+    float inv_nx, scale, alpha, beta, kd;
+    double inv_bw;
+    int X0, Y0, tw, th, ldw, cmax, rmax;
+};
+
+template <bool SHO, int COL>
+__device__ inline void scan_sources(const SourceScan& S) {
+    gfloat* __restrict__ w_g = S.w;
+    gfloat4* __restrict__ tab_x = S.tab_x;
+    gfloat4* __restrict__ tab_p = S.tab_p;
+    settle(w_g);
+    settle(tab_x);
+    settle(tab_p);
+    const int nx = S.nx, bw = S.bw, nsrc = S.nsrc;
+    const int lane = (int)(threadIdx.x & 63);
+    const int dr = 64 / bw, dc = 64 - dr * bw;  // step between a lane's sources
+    auto column = [&](int iu) {
+        if (COL == 0) return iu;
+        if (COL == 1) return iu + (iu < 0 ? nx : 0) - (iu >= nx ? nx : 0);
+        return wrap_index(iu, nx, S.inv_nx);
+    };
+    for (;;) {
+        int claim = 0;
+        if (lane == 0) claim = atomicAdd(S.next, kChunk);
+        const int c0 = __builtin_amdgcn_readfirstlane(claim);
+        if (c0 >= nsrc) break;
+        // (row, column) of the lane's first source: an FP64 quotient, within
+        // one unit of the exact one, then corrected
+        const int s0 = c0 + lane;
+        int r = (int)((double)s0 * S.inv_bw);
+        int c = s0 - r * bw;
+        r += c < 0 ? -1 : (c >= bw ? 1 : 0);
+        c += c < 0 ? bw : (c >= bw ? -bw : 0);
+        int jj[kU], iiu[kU];
+        float wv[kU];
+        float4 txv[kU], tpv[kU];
+#pragma unroll
+        for (int h = 0; h < kU; ++h) {
+            // a source past the box (last chunk) reads row by0 and weighs zero
+            const bool valid = s0 + 64 * h < nsrc;
+            jj[h] = S.by0 + (valid ? r : 0);
+            iiu[h] = S.bx0 + c;
+            const int i = column(iiu[h]);
+            wv[h] = w_g[(size_t)jj[h] * nx + i];
+            wv[h] = valid ? wv[h] : 0.0f;
+            txv[h] = tab_x[(unsigned)i];
+            tpv[h] = tab_p[(unsigned)jj[h]];
+            c += dc;
+            r += dr;
+            const bool carry = c >= bw;
+            c -= carry ? bw : 0;
+            r += carry ? 1 : 0;
+        }
+        // keep the table loads above the skip test (issued with the weights)
+        asm volatile("" ::: "memory");
+        // a chunk whose weights are all zero (in every lane) adds nothing
+        bool live = false;
+#pragma unroll
+        for (int h = 0; h < kU; ++h) live |= wv[h] != 0.0f;
+        if (!__any(live)) continue;
+#pragma unroll
+        for (int h = 0; h < kU; ++h)
+            deposit_node<SHO>(S.acc, jj[h], iiu[h], wv[h] * S.scale, txv[h], tpv[h], S.alpha, S.beta, S.kd, S.X0,
+                              S.Y0, S.tw, S.th, S.ldw, S.cmax, S.rmax);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_deposit: push every node of the tile's source box and scatter its weight
 // into the LDS image of the destination tile, then write the tile of b once.
@@ -247,9 +339,9 @@ __device__ inline void deposit_node(long long* acc, int j, int ii, float w, floa
 // Every tap index is clamped into that border, so no access can leave LDS
 // whatever the push does; taps that land outside the tile are dropped there.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
-    extern __shared__ long long acc[];
-    __shared__ int s_d, s_box[4];
+__global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
+    extern __shared__ __align__(16) long long acc[];  // 16-byte aligned: read four cells at a time
+    __shared__ int s_d, s_box[4], s_next;
     __shared__ float s_ab[2];
 
     for (int it = blockIdx.x; it < A.total; it += gridDim.x) {
@@ -268,8 +360,19 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
         const int par = (I.parity0 + A.parity) & 1;
         const float* __restrict__ w_in = I.w[par];
 
+        // a host-planned box: its load is in flight while the tile is cleared
+        int4 hb = make_int4(0, 0, 0, 0);
+        if (threadIdx.x == 0 && I.boxes) hb = I.boxes[t];
         for (int k = threadIdx.x; k < ldw * ldh; k += blockDim.x) acc[k] = 0ll;
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0 && I.boxes) {
+            s_ab[0] = I.push.alpha;
+            s_ab[1] = I.push.beta;
+            s_next = 0;
+            s_box[0] = hb.x;
+            s_box[1] = hb.y;
+            s_box[2] = hb.z;
+            s_box[3] = hb.w;
+        } else if (threadIdx.x == 0) {
             PushParams P = I.push;
             if (P.kind == kFel) {
                 // kick field: A at mid-kick plus the space-charge term, A + b dz/2 + i sigma2 b
@@ -281,6 +384,7 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
             }
             s_ab[0] = P.alpha;
             s_ab[1] = P.beta;
+            s_next = 0;
             source_box(P, X0, X1, Y0, Y1, s_box);
         }
         __syncthreads();
@@ -304,77 +408,90 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(LaunchArgs A) {
         const float scale = I.fix_scale, inv_scale = I.fix_inv;  // exact powers of two
         const int nsrc_live = scale > 0.0f ? nsrc : 0;
 
-        // Thread t takes the box's sources s = t, t + T, t + 2T, ... (s = r bw + c):
-        // its (row, column) advance by (T / bw, T % bw) per source with one
-        // carry.  On a periodic axis the column wraps with one correction per
-        // side while the box lies within [-nx, 2 nx) (always, unless the
-        // lattice is narrower than the box).
-        constexpr int T = kDepositThreads;
-        const int dr = T / bw, dc = T - dr * bw;
-        const int cnt = (int)threadIdx.x < nsrc_live ? (nsrc_live - 1 - (int)threadIdx.x) / T + 1 : 0;
+        // On a periodic axis the column wraps with one correction per side
+        // while the box lies within [-nx, 2 nx) (always, unless the lattice is
+        // narrower than the box).
+        SourceScan S;
+        S.acc = acc;
+        S.next = &s_next;
+        S.w = as_global(w_in);
+        S.tab_x = as_global(I.tab_x);
+        S.tab_p = as_global(I.tab_p);
+        S.nx = nx;
+        S.bx0 = bx0;
+        S.by0 = by0;
+        S.bw = bw;
+        S.nsrc = nsrc_live;
+        S.inv_nx = inv_nx;
+        S.inv_bw = 1.0 / (double)bw;
+        S.scale = scale;
+        S.alpha = alpha;
+        S.beta = beta;
+        S.kd = kd;
+        S.X0 = X0;
+        S.Y0 = Y0;
+        S.tw = X1 - X0;
+        S.th = Y1 - Y0;
+        S.ldw = ldw;
+        S.cmax = cmax;
+        S.rmax = rmax;
         const bool wrap_near = bx0 >= -nx && bx0 + bw <= 2 * nx;
-        int r = (int)threadIdx.x / bw;
-        int c = (int)threadIdx.x - r * bw;
-        gfloat* __restrict__ w_g = as_global(w_in);
-        gfloat4* __restrict__ tab_x = as_global(I.tab_x);
-        gfloat4* __restrict__ tab_p = as_global(I.tab_p);
-        settle(w_g);
-        settle(tab_x);
-        settle(tab_p);
-        auto column = [&](int iu) {
-            if (!periodic) return iu;
-            if (wrap_near) return iu + (iu < 0 ? nx : 0) - (iu >= nx ? nx : 0);
-            return wrap_index(iu, nx, inv_nx);
-        };
-        auto next = [&]() {
-            c += dc;
-            r += dr;
-            const bool carry = c >= bw;
-            c -= carry ? bw : 0;
-            r += carry ? 1 : 0;
-        };
-
-        // Four sources per iteration, every load issued before any use, so an
-        // iteration waits for one memory latency, not a chain; the last
-        // sources (fewer than four) one at a time.
-        constexpr int kU = 4;
-        int left = cnt;
-        for (; left >= kU; left -= kU) {
-            int jj[kU], iiu[kU];
-            float wv[kU];
-            float4 txv[kU], tpv[kU];
-#pragma unroll
-            for (int h = 0; h < kU; ++h) {
-                jj[h] = by0 + r;
-                iiu[h] = bx0 + c;  // unwrapped source column
-                const int i = column(iiu[h]);
-                wv[h] = w_g[(size_t)jj[h] * nx + i];
-                txv[h] = tab_x[(unsigned)i];
-                tpv[h] = tab_p[(unsigned)jj[h]];
-                next();
-            }
-#pragma unroll
-            for (int h = 0; h < kU; ++h)
-                deposit_node(acc, jj[h], iiu[h], wv[h] * scale, txv[h], tpv[h], kind, alpha, beta, kd, X0, Y0,
-                             ldw, cmax, rmax);
-        }
-        for (; left > 0; --left) {
-            const int j = by0 + r, iu = bx0 + c, i = column(iu);
-            const float wj = w_g[(size_t)j * nx + i];
-            const float4 tx = tab_x[(unsigned)i], tp = tab_p[(unsigned)j];
-            next();
-            deposit_node(acc, j, iu, wj * scale, tx, tp, kind, alpha, beta, kd, X0, Y0, ldw, cmax, rmax);
+        const int col = !periodic ? 0 : wrap_near ? 1 : 2;
+        if (kind == kSho) {
+            if (col == 0) scan_sources<true, 0>(S);
+            else if (col == 1) scan_sources<true, 1>(S);
+            else scan_sources<true, 2>(S);
+        } else {
+            if (col == 0) scan_sources<false, 0>(S);
+            else if (col == 1) scan_sources<false, 1>(S);
+            else scan_sources<false, 2>(S);
         }
         __syncthreads();
 
         const int tw = X1 - X0, th = Y1 - Y0;
-        float* __restrict__ b = I.b;
+        const int T = blockDim.x;
+        gfloat_out* __restrict__ b = as_global_out(I.b);
         bool out_of_range = false;
-        for (int k = threadIdx.x; k < tw * th; k += blockDim.x) {
-            const int rr = k / tw, cc = k - rr * tw;
-            const long long v = fix48_value(acc[(rr + kPad) * ldw + cc + kPad]);
+        // A cell goes out as v 2^(e-40) rounded once to FP32 (v, 48 bits, is
+        // exact in FP64 and the scale is a power of two).
+        const double inv_scale_d = (double)inv_scale;
+        auto cell = [&](long long word) {
+            const long long v = fix48_value(word);
             out_of_range |= (unsigned long long)v + (1ull << 46) >= (1ull << 47);
-            b[(size_t)(Y0 + rr) * nx + X0 + cc] = (float)v * inv_scale;
+            return (float)((double)v * inv_scale_d);
+        };
+        // Thread t takes items k = t, t + T, ... of the tile, k = rr w + cc:
+        // (rr, cc) advance by (T / w, T % w) with one carry.
+        if ((I.k1_tx & 3) == 0 && (nx & 3) == 0) {
+            // four consecutive cells per item (two 16-byte LDS reads, one
+            // 16-byte store): rows of the tile and of b start 32-byte and
+            // 16-byte aligned
+            const int tq = tw >> 2;
+            const int wdr = T / tq, wdc = T - wdr * tq;
+            int rr = (int)threadIdx.x / tq, cq = (int)threadIdx.x - rr * tq;
+            while (rr < th) {
+                const long long* src = acc + (rr + kPad) * ldw + 4 * cq + kPad;
+                const longlong2 a0 = reinterpret_cast<const longlong2*>(src)[0];
+                const longlong2 a1 = reinterpret_cast<const longlong2*>(src)[1];
+                const float4 o = make_float4(cell(a0.x), cell(a0.y), cell(a1.x), cell(a1.y));
+                reinterpret_cast<VP_GLOBAL float4*>(b + (size_t)(Y0 + rr) * nx + X0)[cq] = o;
+                cq += wdc;
+                rr += wdr;
+                const bool carry = cq >= tq;
+                cq -= carry ? tq : 0;
+                rr += carry ? 1 : 0;
+            }
+        } else {
+            const int wdr = T / tw, wdc = T - wdr * tw;
+            int rr = (int)threadIdx.x / tw, cc = (int)threadIdx.x - rr * tw;
+            while (rr < th) {
+                b[(size_t)(Y0 + rr) * nx + X0 + cc] = cell(acc[(rr + kPad) * ldw + cc + kPad]);
+                cc += wdc;
+                rr += wdr;
+                const bool carry = cc >= tw;
+                cc -= carry ? tw : 0;
+                rr += carry ? 1 : 0;
+            }
         }
         if (out_of_range) atomicOr(&I.counters[kRangeFlag], 1u);
         __syncthreads();
@@ -432,7 +549,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
         const int kind_p = nwp < kLine ? 2 : (wp == 0 ? 1 : 0);
         const int par = (I.parity0 + A.parity) & 1;
         const float* __restrict__ src = I.b;
-        float* __restrict__ dst = I.w[par ^ 1];
+        gfloat_out* __restrict__ dst = as_global_out(I.w[par ^ 1]);
         const int lane = threadIdx.x;
 
         const bool fel = I.push.kind == kFel;
@@ -486,7 +603,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
             if (cx >= 0 && cx < tw) {
                 const int gx = X0 + cx;
                 const int lo = Y0 - wp;  // the kept rows are window rows lo .. lo + th
-                float* o = dst + (size_t)Y0 * nx + gx;
+                gfloat_out* o = dst + (size_t)Y0 * nx + gx;
                 unsigned qo = in_vgpr(0u);  // running offset of the kept row (< kSeg rows x nx)
                 auto store = [&](int k) {
                     o[qo] = v[k];
@@ -675,8 +792,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
     }
 }
 
-hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL(k_deposit, dim3(grid), dim3(kDepositThreads), lds, s, a);
+hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s) {
+    hipLaunchKernelGGL(k_deposit, dim3(grid), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 

@@ -32,7 +32,8 @@ def test_ragged_mixed_batch_equals_alone(B):
     insts = batch_instances(24, seed=40, steps=30, n_min=48, n_max=300)
     insts += [fel_gaussian(96, 30, npp=128), fel_gaussian(160, 30, npp=64)]
     grids = [B.grid_for(i) for i in insts]
-    grids[3].set_tiles((32, 8))     # per-instance tile shapes in one launch
+    grids[3].set_tiles((32, 8), 128)       # per-instance tile shapes in one launch,
+    grids[5].set_tiles((128, 64), 1024)    # which runs at the largest workgroup size
     batch = B.Batch(grids, [i.dt for i in insts])
     batch.step(13)
     batch.step(17)                            # odd split: the parity bookkeeping
@@ -41,7 +42,7 @@ def test_ragged_mixed_batch_equals_alone(B):
         got = g.density()
         ref_g = B.grid_for(inst)
         if k == 3:
-            ref_g.set_tiles((32, 8))
+            ref_g.set_tiles((32, 8), 128)
         ref_g.step(inst.dt, 30)
         assert np.array_equal(got, ref_g.density()), k
         assert g.moments()["step"] == 30

@@ -33,7 +33,7 @@ def B():
 def gpu_run(B, x, p, ham, w0, dt, steps, tiles=None, graph=True):
     g = B.Grid(x, p)
     if tiles:
-        g.set_tiles(tiles)
+        g.set_tiles(tiles[:2], tiles[2] if len(tiles) > 2 else 0)
     g.set_launch(graph)
     g.set_hamiltonian(ham)
     g.set_density(w0)
@@ -48,8 +48,8 @@ def one_step_ref(x, p, ham, w32, dt):
     return oracle.run(x, p, ham, w32.astype(np.float64), dt, 1).w
 
 
-# deposit tile shapes (columns, rows); the solves use fixed 32-node segments
-TILINGS = [None, (64, 16), (24, 5), (200, 24)]
+# deposit launch shapes (columns, rows[, threads]); the solves use fixed 32-node segments
+TILINGS = [None, (64, 16), (24, 5, 64), (200, 24, 1024), (128, 128, 1024)]
 
 
 @pytest.mark.parametrize("tiles", TILINGS)
@@ -121,13 +121,15 @@ def test_graph_and_plain_launches_agree(B):
 
 @pytest.mark.parametrize("kind", ["pendulum", "fel"])
 def test_results_bitwise_independent_of_deposit_tiling(B, kind):
-    """The deposit sums taps as exact integers, so any tiling (each node is
-    pushed by every tile whose source box holds it) gives the same bits."""
+    """The deposit sums taps as exact integers, so any tiling and workgroup
+    size (each node is pushed by every tile whose source box holds it) gives
+    the same bits."""
     inst = pendulum_band(256, steps=30) if kind == "pendulum" else fel_gaussian(192, 30, npp=160)
     ref = None
-    for k1 in [(64, 32), (128, 16), (24, 5), (200, 24), (16, 8)]:
+    for k1 in [(64, 32, 256), (128, 16, 512), (24, 5, 64), (200, 24, 1024), (16, 8, 128), (128, 128, 1024),
+               (96, 40, 320)]:
         g = B.grid_for(inst)
-        g.set_tiles(k1)
+        g.set_tiles(k1[:2], k1[2])
         g.step(inst.dt, 30)
         got = g.density()
         g.close()
