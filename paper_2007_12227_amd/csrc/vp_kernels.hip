@@ -203,8 +203,8 @@ __device__ inline int open_window(int s0, int n) { return max(0, min(s0 - kHalo,
 // fixed point) and add its 16 B-spline taps into the LDS tile.
 template <bool SHO>
 __device__ inline void deposit_node(long long* acc, int j, int ii, float w, float4 tx, float4 tp,
-                                    float alpha, float beta, float kd, int X0, int Y0, int tw, int th, int ldw,
-                                    int cmax, int rmax) {
+                                    float alpha, float beta, float kd, int X0, int Y0, int tw, int th,
+                                    int ldw) {
     int ku, kv;
     float fu, fv;
     if (SHO) {
@@ -223,16 +223,17 @@ __device__ inline void deposit_node(long long* acc, int j, int ii, float w, floa
         split_cell(su, eu + tp.y, ku, fu);
         split_cell(dv, 0.0f, kv, fv);
     }
+    // tap (q, r) lands on tile row row0 + q, column col0 + r; a node none of
+    // whose taps meets the tile adds nothing (its lane sits the taps out).
+    // The test also bounds every access: col0 in [-3, tw) and row0 in
+    // [-3, th) put the taps inside the tile and its border of kPad cells,
+    // whatever the push produced (a non-finite position included).
+    const int col0 = ii + ku - 1 - X0, row0 = j + kv - 1 - Y0;
+    if ((unsigned)(col0 + 3) >= (unsigned)(tw + 3) || (unsigned)(row0 + 3) >= (unsigned)(th + 3)) return;
     double bx[4], bp[4];
     bspline_taps(fu, bx);
     bspline_taps(fv, bp);
-    // tap (q, r) lands on tile row row0 + q, column col0 + r; a node none of
-    // whose taps meets the tile adds nothing (its lane sits the atomics out)
-    const int col0 = ii + ku - 1 - X0, row0 = j + kv - 1 - Y0;
-    if ((unsigned)(col0 + 3) >= (unsigned)(tw + 3) || (unsigned)(row0 + 3) >= (unsigned)(th + 3)) return;
-    const int c0 = clampi(col0 + kPad, 0, cmax);
-    const int r0 = clampi(row0 + kPad, 0, rmax);
-    long long* base = acc + r0 * ldw + c0;
+    long long* base = acc + __umul24(row0 + kPad, ldw) + (col0 + kPad);
     // tap value w * bp * bx: FP64 product, rounded once, exactly, into the
     // fixed-point tile sum, so the deposit adds no product rounding to the
     // state (the FEL instability amplifies it)
@@ -265,7 +266,7 @@ struct SourceScan {
     int nx, bx0, by0, bw, nsrc;
     float inv_nx, scale, alpha, beta, kd;
     double inv_bw;
-    int X0, Y0, tw, th, ldw, cmax, rmax;
+    int X0, Y0, tw, th, ldw;
 };
 
 template <bool SHO, int COL>
@@ -306,7 +307,7 @@ __device__ inline void scan_sources(const SourceScan& S) {
             jj[h] = S.by0 + (valid ? r : 0);
             iiu[h] = S.bx0 + c;
             const int i = column(iiu[h]);
-            wv[h] = w_g[(size_t)jj[h] * nx + i];
+            wv[h] = w_g[(size_t)__umul24(jj[h], nx) + i];  // < 2^32: both axes have at most 2^16 nodes
             wv[h] = valid ? wv[h] : 0.0f;
             txv[h] = tab_x[(unsigned)i];
             tpv[h] = tab_p[(unsigned)jj[h]];
@@ -326,7 +327,7 @@ __device__ inline void scan_sources(const SourceScan& S) {
 #pragma unroll
         for (int h = 0; h < kU; ++h)
             deposit_node<SHO>(S.acc, jj[h], iiu[h], wv[h] * S.scale, txv[h], tpv[h], S.alpha, S.beta, S.kd, S.X0,
-                              S.Y0, S.tw, S.th, S.ldw, S.cmax, S.rmax);
+                              S.Y0, S.tw, S.th, S.ldw);
     }
 }
 
@@ -335,9 +336,9 @@ __device__ inline void scan_sources(const SourceScan& S) {
 // into the LDS image of the destination tile, then write the tile of b once.
 // (Integer LDS atomics: gfx950 executes ds_add_f32 some 40x slower than
 // ds_add_u32, and integer sums are order independent.)
-// LDS holds (tx + 8) x (ty + 8) cells: the tile plus a 4-cell trash border.
-// Every tap index is clamped into that border, so no access can leave LDS
-// whatever the push does; taps that land outside the tile are dropped there.
+// LDS holds (tx + 8) x (ty + 8) cells: the tile plus a border of kPad cells
+// that takes the taps of nodes near the tile's edge which fall outside it;
+// they are dropped with it.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
     extern __shared__ __align__(16) long long acc[];  // 16-byte aligned: read four cells at a time
@@ -356,7 +357,6 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
         const int X0 = txi * I.k1_tx, X1 = min(X0 + I.k1_tx, nx);
         const int Y0 = tyi * I.k1_ty, Y1 = min(Y0 + I.k1_ty, np);
         const int ldw = I.k1_tx + 2 * kPad, ldh = I.k1_ty + 2 * kPad;
-        const int cmax = I.k1_tx + kPad, rmax = I.k1_ty + kPad;
         const int par = (I.parity0 + A.parity) & 1;
         const float* __restrict__ w_in = I.w[par];
 
@@ -433,8 +433,6 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
         S.tw = X1 - X0;
         S.th = Y1 - Y0;
         S.ldw = ldw;
-        S.cmax = cmax;
-        S.rmax = rmax;
         const bool wrap_near = bx0 >= -nx && bx0 + bw <= 2 * nx;
         const int col = !periodic ? 0 : wrap_near ? 1 : 2;
         if (kind == kSho) {
