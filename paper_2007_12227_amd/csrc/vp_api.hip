@@ -764,9 +764,15 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
     std::vector<VpInst> insts(n);
     std::vector<int32_t> off1(n + 1, 0), off2(n + 1, 0);
     size_t lds1 = 0;
-    int threads1 = 64;
+    // one workgroup size serves every tile of the launch (the deposit loops
+    // stride by it): the one most of the tiles were tuned with (a small grid
+    // timed alone may pick a large workgroup for its few tiles)
+    std::map<int, long> tiles_at;
+    for (int k = 0; k < n; ++k) tiles_at[grids[k]->list.threads1] += grids[k]->inst.k1_tiles;
+    int threads1 = tiles_at.begin()->first;
+    for (auto& kv : tiles_at)
+        if (kv.second > tiles_at[threads1]) threads1 = kv.first;
     for (int k = 0; k < n; ++k) {
-        threads1 = std::max(threads1, grids[k]->list.threads1);
         insts[k] = grids[k]->inst;
         insts[k].parity0 = grids[k]->parity;
         off1[k + 1] = off1[k] + insts[k].k1_tiles;
@@ -783,7 +789,7 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
     L.has_fel = false;
     for (int k = 0; k < n; ++k) L.has_fel |= insts[k].push.kind == kFel;
     L.lds1 = lds1;
-    L.threads1 = threads1;  // the deposit loops stride by the workgroup size: any size serves every tile
+    L.threads1 = threads1;
     hipError_t e = hipMalloc(&L.d_inst, sizeof(VpInst) * n);
     if (e == hipSuccess) e = hipMalloc(&L.d_off1, sizeof(int32_t) * 2 * (n + 1));
     L.d_off2 = L.d_off1 + (n + 1);
