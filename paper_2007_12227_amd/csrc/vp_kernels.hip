@@ -42,13 +42,17 @@ __device__ inline void split_cell(float hi, float lo, int& k, float& t) {
 // sum to one to FP64 rounding (the partition of unity behind the conservation
 // argument of eqs. 11-12), far below the 2^-40 fixed-point grid the products
 // are rounded to.
+// Every fused multiply-add is written out and the compiler forms no other:
+// the taps are the same bits in every inlined copy, so the deposit's exact
+// sums do not depend on which copy (kind of push, wrap mode) pushed a node.
 __device__ inline void bspline_taps(float tf, double (&b)[4]) {
+#pragma clang fp contract(off)
     const double sixth = 1.0 / 6.0;
     const double t = (double)tf, s = 1.0 - t, t2 = t * t;
     b[0] = (s * sixth) * (s * s);
     const double t3 = (t * sixth) * t2;
     b[3] = t3;
-    b[2] = fma(0.5, t + t2, sixth) - 3.0 * t3;
+    b[2] = fma(-3.0, t3, fma(0.5, fma(t, t, t), sixth));
     b[1] = 1.0 - ((b[0] + b[3]) + b[2]);
 }
 
@@ -205,6 +209,7 @@ template <bool SHO>
 __device__ inline void deposit_node(long long* acc, int j, int ii, float w, float4 tx, float4 tp,
                                     float alpha, float beta, float kd, int X0, int Y0, int tw, int th,
                                     int ldw) {
+#pragma clang fp contract(off)  // the same bits in every inlined copy (see bspline_taps)
     int ku, kv;
     float fu, fv;
     if (SHO) {
@@ -215,9 +220,9 @@ __device__ inline void deposit_node(long long* acc, int j, int ii, float w, floa
         split_cell(sv, ev + (tx.w + tp.w), kv, fv);
     } else {
         // phase phi_i + q_j from the per-axis sine/cosine tables
-        const float cph = tx.y * tp.w - tx.x * tp.z;
-        const float sph = tx.x * tp.w + tx.y * tp.z;
-        const float dv = alpha * cph + beta * sph;
+        const float cph = fmaf(tx.y, tp.w, -(tx.x * tp.z));
+        const float sph = fmaf(tx.x, tp.w, tx.y * tp.z);
+        const float dv = fmaf(alpha, cph, beta * sph);
         float su, eu;
         two_sum(tp.x, dv * kd, su, eu);
         split_cell(su, eu + tp.y, ku, fu);
@@ -389,9 +394,14 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
         }
         __syncthreads();
 
-        const int bx0 = s_box[0], bw = max(s_box[1] - s_box[0], 1);
-        const int by0 = s_box[2], bh = s_box[3] - s_box[2];
-        const int nsrc = (s_box[1] > s_box[0] && bh > 0) ? bw * bh : 0;
+        // the box is the same for every lane: said so, the loop's branches on it
+        // are scalar
+        const int bx0 = __builtin_amdgcn_readfirstlane(s_box[0]);
+        const int bx1 = __builtin_amdgcn_readfirstlane(s_box[1]);
+        const int by0 = __builtin_amdgcn_readfirstlane(s_box[2]);
+        const int bh = __builtin_amdgcn_readfirstlane(s_box[3]) - by0;
+        const int bw = max(bx1 - bx0, 1);
+        const int nsrc = (bx1 > bx0 && bh > 0) ? bw * bh : 0;
         const float inv_nx = 1.0f / (float)nx;
         const float alpha = s_ab[0], beta = s_ab[1], kd = I.push.kd;
         const int kind = I.push.kind;
