@@ -175,7 +175,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--cpu-steps", type=int, default=64)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (scale for HBM counters)")
     ap.add_argument("--no-extras", action="store_true",
