@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from paper_2007_12227_amd.inputs import (H_FEL, H_FREE, H_PENDULUM, H_SHO_EXACT, Axis, Hamiltonian,
-                                         fel_gaussian, gaussian, pendulum_axes, pendulum_band,
+                                         fel_flattop, fel_gaussian, gaussian, pendulum_axes, pendulum_band,
                                          pendulum_gaussian, rng)
 
 pytestmark = pytest.mark.gpu
@@ -204,6 +204,39 @@ def test_fel_run_and_invariant(B):
     assert abs(complex(m["A_re"], m["A_im"]) - r.A) <= 1e-4 * abs(r.A)
     E0 = 1e-6 + float((w32.astype(np.float64) * inst.p.nodes()[:, None]).sum() / w32.sum())
     assert abs(m["fel_invariant"] - E0) <= 1e-7
+
+
+def test_fel_detuning_and_space_charge(B):
+    """The full FEL model of eqs. 13a-c: detuning in the phase drift, space
+    charge in the kick; against the oracle, with the invariant |A|^2 + <eta>."""
+    base = fel_gaussian(256, 200, npp=256)
+    ham = Hamiltonian(H_FEL, A_re=1e-3, fel_delta=0.3, fel_sigma2=0.4)
+    w32 = base.w0.astype(np.float32)
+    got, m = gpu_run(B, base.x, base.p, ham, w32, base.dt, 200)
+    r = oracle.run(base.x, base.p, ham, w32.astype(np.float64), base.dt, 200)
+    err = oracle.rel_l1(got, r.w)
+    print(f"fel delta 0.3 sigma2 0.4, 200 steps: rel L1 {err:.3e}, A gpu {m['A_re']:+.6e}{m['A_im']:+.6e}j "
+          f"oracle {r.A:.6e}")
+    assert err <= 1e-4
+    assert abs(complex(m["A_re"], m["A_im"]) - r.A) <= 1e-4 * abs(r.A)
+    E0 = 1e-6 + float((w32.astype(np.float64) * base.p.nodes()[:, None]).sum() / w32.sum())
+    assert abs(m["fel_invariant"] - E0) <= 1e-7
+
+
+def test_fel_flattop_start(B):
+    """The hard-edged start (|eta| <= 0.1): the projection rings at the edges
+    and makes negative weights; the GPU follows the oracle, negative mass
+    included."""
+    inst = fel_flattop(256, 200)
+    w32 = inst.w0.astype(np.float32)
+    got, m = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 200)
+    r = oracle.run(inst.x, inst.p, inst.ham, w32.astype(np.float64), inst.dt, 200)
+    err = oracle.rel_l1(got, r.w)
+    ref = oracle.moments(inst.x, inst.p, inst.ham, r.w, r.A, N0=float(w32.astype(np.float64).sum()))
+    print(f"fel flat-top 200 steps: rel L1 {err:.3e}, neg mass gpu {m['neg_mass']:.6e} oracle {ref['neg_mass']:.6e}")
+    assert err <= 1e-4
+    assert ref["neg_mass"] > 0.0
+    assert abs(m["neg_mass"] - ref["neg_mass"]) <= 1e-4 * ref["l1"]
 
 
 # ---- full sizes ----
