@@ -37,7 +37,7 @@ class _Axis(C.Structure):
 
 
 class _Ham(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("a", C.c_double),
+    _fields_ = [("kind", C.c_int32), ("integrator", C.c_int32), ("a", C.c_double),
                 ("omega", C.c_double), ("fel_delta", C.c_double), ("fel_sigma2", C.c_double)]
 
 
@@ -65,6 +65,7 @@ def lib():
         L.orc_deposit.argtypes = [P(_Axis), P(_Axis), dp, dp, dp, dp]
         L.orc_solve.argtypes = [P(_Axis), P(_Axis), dp]
         L.orc_bunching.argtypes = [P(_Axis), P(_Axis), P(_Ham), C.c_double, dp, C.c_double, dp]
+        L.orc_push_rk4.argtypes = [P(_Axis), P(_Axis), P(_Ham), C.c_double, dp, C.c_double, dp, dp, dp, dp]
         L.orc_moments_of.argtypes = [P(_Axis), P(_Axis), P(_Ham), dp, dp, C.c_double, C.c_int64,
                                      P(_Moments)]
         L.orc_run.argtypes = [P(_Axis), P(_Axis), P(_Ham), C.c_double, C.c_int64, dp, dp,
@@ -80,7 +81,8 @@ def _ax(a) -> _Axis:
 
 
 def _ham(h) -> _Ham:
-    return _Ham(int(h.kind), 0, float(h.a), float(h.omega), float(h.fel_delta), float(h.fel_sigma2))
+    return _Ham(int(h.kind), int(getattr(h, "integrator", 0)), float(h.a), float(h.omega),
+                float(h.fel_delta), float(h.fel_sigma2))
 
 
 def _dptr(arr: np.ndarray):
@@ -115,6 +117,19 @@ def solve(x, p, b):
     out = np.array(b, dtype=np.float64, order="C", copy=True)
     lib().orc_solve(_ax(x), _ax(p), _dptr(out))
     return out
+
+
+def push_rk4(x, p, ham, dz, w, N0, A):
+    """One FEL Runge-Kutta step of every node: displacements (du, dv) in cells
+    and the new field."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    a = np.array([complex(A).real, complex(A).imag])
+    du = np.empty((p.n, x.n))
+    dv = np.empty((p.n, x.n))
+    an = np.zeros(2)
+    lib().orc_push_rk4(_ax(x), _ax(p), _ham(ham), float(dz), _dptr(w), float(N0), _dptr(a), _dptr(du),
+                       _dptr(dv), _dptr(an))
+    return du, dv, complex(an[0], an[1])
 
 
 def bunching(x, p, ham, dz, w, N0):

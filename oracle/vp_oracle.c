@@ -31,7 +31,9 @@
  *  - FEL (Sec. FEL simulations, eqs. 13a-c): drift-kick-drift with the kick
  *    sub-flow integrated exactly (phase frozen, so <e^{-i Phi}> is constant and
  *    A grows linearly through the kick); the average <.> is N0^{-1} sum w e^{-i psi}
- *    over the nodes at their half-drift phases, N0 = sum w at the start;
+ *    over the nodes at their half-drift phases, N0 = sum w at the start.  The
+ *    paper's own integrator, fourth-order Runge-Kutta, is the alternative
+ *    (orc_push_rk4): there <.> is taken at each stage's phases;
  *  - periodic axis: n nodes on [lo,hi); open axis: n nodes including both ends,
  *    full tents at the edge nodes, taps that fall outside are lost
  *    (Sec. Numerical Examples: open momentum boundaries lose density).
@@ -56,9 +58,12 @@ typedef struct {
     int32_t periodic;
 } orc_axis;
 
+#define ORC_DKD 0 /* FEL integrator: drift, exact kick, drift */
+#define ORC_RK4 1 /* FEL integrator: classical fourth-order Runge-Kutta (Sec. FEL simulations) */
+
 typedef struct {
     int32_t kind;
-    int32_t reserved;
+    int32_t integrator; /* FEL only: ORC_DKD or ORC_RK4 */
     double a;          /* pendulum amplitude, V = -a cos x */
     double omega;      /* rotation angle per unit time */
     double fel_delta;  /* detuning, eq. 13a */
@@ -253,6 +258,90 @@ void orc_bunching(const orc_axis* ax, const orc_axis* ap, const orc_ham* h, doub
     b[1] = im / N0;
 }
 
+/* ---- FEL by the classical Runge-Kutta method (Sec. FEL simulations) ----
+ *
+ * The lattice nodes are the particles of eqs. 13a-c: psi_k' = delta + eta_k,
+ * eta_k' = F(psi_k, A, b) = -2 Re[(A + i sigma2 b) e^{i psi_k}], A' = b with
+ * b = N0^{-1} sum_k w_k e^{-i psi_k} over the current phases.  One step of
+ * size h takes the four stages of the method; each needs the bunching of its
+ * own stage phases, a sum over all nodes.  Stage s (s = 1..4) evaluates the
+ * slopes at psi_s = psi + c_s h k_{s-1}^psi, eta_s = eta + c_s h k_{s-1}^eta,
+ * A_s = A + c_s h b_{s-1}, with c = (0, 1/2, 1/2, 1); the update weighs the
+ * stages 1, 2, 2, 1 over 6.  The weights w stay fixed through the step: they
+ * are the particles' charges, moved only by the projection that follows. */
+
+static double fel_force(const orc_ham* h, double ph, const double A[2], const double b[2]) {
+    /* -2 Re[(A + i sigma2 b) e^{i ph}] */
+    const double re = A[0] - h->fel_sigma2 * b[1], im = A[1] + h->fel_sigma2 * b[0];
+    return -2.0 * (re * cos(ph) - im * sin(ph));
+}
+
+static void add_bunch(double wk, double ph, double* acc) {
+    acc[0] += wk * cos(ph);
+    acc[1] -= wk * sin(ph);
+}
+
+/* Displacements (cells) of every node over one RK4 step, and the new field. */
+void orc_push_rk4(const orc_axis* ax, const orc_axis* ap, const orc_ham* h, double dz, const double* w,
+                  double N0, const double* A, double* du, double* dv, double* A_new) {
+    const long nx = ax->n, np = ap->n;
+    const double hx = spacing(ax), hp = spacing(ap), d = h->fel_delta;
+    double b[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    double As[4][2];
+    /* stage 1 and 2 phases need no bunching: psi, and psi + (h/2)(delta + eta) */
+    for (long j = 0; j < np; ++j) {
+        const double eta = node_at(ap, j);
+        for (long i = 0; i < nx; ++i) {
+            const double psi = node_at(ax, i), wk = w[j * nx + i];
+            add_bunch(wk, psi, b[0]);
+            add_bunch(wk, psi + 0.5 * dz * (d + eta), b[1]);
+        }
+    }
+    for (int c = 0; c < 2; ++c) b[0][c] /= N0, b[1][c] /= N0;
+    for (int c = 0; c < 2; ++c) {
+        As[0][c] = A[c];
+        As[1][c] = A[c] + 0.5 * dz * b[0][c];
+        As[2][c] = A[c] + 0.5 * dz * b[1][c];
+    }
+    /* stages 3 and 4: their phases need the slopes of stages 1 and 2 */
+    for (long j = 0; j < np; ++j) {
+        const double eta = node_at(ap, j);
+        for (long i = 0; i < nx; ++i) {
+            const double psi = node_at(ax, i), wk = w[j * nx + i];
+            const double k1e = fel_force(h, psi, As[0], b[0]);
+            const double psi2 = psi + 0.5 * dz * (d + eta), eta2 = eta + 0.5 * dz * k1e;
+            const double k2e = fel_force(h, psi2, As[1], b[1]);
+            const double psi3 = psi + 0.5 * dz * (d + eta2);
+            const double eta3 = eta + 0.5 * dz * k2e;
+            const double psi4 = psi + dz * (d + eta3);
+            add_bunch(wk, psi3, b[2]);
+            add_bunch(wk, psi4, b[3]);
+        }
+    }
+    for (int c = 0; c < 2; ++c) {
+        b[2][c] /= N0, b[3][c] /= N0;
+        As[3][c] = A[c] + dz * b[2][c];
+    }
+    /* the step itself */
+#pragma omp parallel for schedule(static)
+    for (long j = 0; j < np; ++j) {
+        const double eta = node_at(ap, j);
+        for (long i = 0; i < nx; ++i) {
+            const double psi = node_at(ax, i);
+            const double k1p = d + eta, k1e = fel_force(h, psi, As[0], b[0]);
+            const double psi2 = psi + 0.5 * dz * k1p, eta2 = eta + 0.5 * dz * k1e;
+            const double k2p = d + eta2, k2e = fel_force(h, psi2, As[1], b[1]);
+            const double psi3 = psi + 0.5 * dz * k2p, eta3 = eta + 0.5 * dz * k2e;
+            const double k3p = d + eta3, k3e = fel_force(h, psi3, As[2], b[2]);
+            const double psi4 = psi + dz * k3p, eta4 = eta + dz * k3e;
+            const double k4p = d + eta4, k4e = fel_force(h, psi4, As[3], b[3]);
+            du[j * nx + i] = dz / 6.0 * (k1p + 2.0 * k2p + 2.0 * k3p + k4p) / hx;
+            dv[j * nx + i] = dz / 6.0 * (k1e + 2.0 * k2e + 2.0 * k3e + k4e) / hp;
+        }
+    }
+    for (int c = 0; c < 2; ++c) A_new[c] = A[c] + dz / 6.0 * (b[0][c] + 2.0 * b[1][c] + 2.0 * b[2][c] + b[3][c]);
+}
+
 /* ---- diagnostics (Sec. Numerical Examples: phase-space volume and entropy) ---- */
 
 static double sinc(double y) { return y == 0.0 ? 1.0 : sin(y) / y; }
@@ -321,7 +410,12 @@ int orc_run(const orc_axis* ax, const orc_axis* ap, const orc_ham* h, double dt,
     int static_map = h->kind != ORC_FEL;
     if (static_map) orc_push(ax, ap, h, dt, NULL, du, dv);
     for (int64_t s = 0; s < nsteps; ++s) {
-        if (!static_map) {
+        if (!static_map && h->integrator == ORC_RK4) {
+            double An[2];
+            orc_push_rk4(ax, ap, h, dt, w, N0, A, du, dv, An);
+            A[0] = An[0];
+            A[1] = An[1];
+        } else if (!static_map) {
             double bn[2];
             orc_bunching(ax, ap, h, dt, w, N0, bn);
             /* kick field: A grows linearly through the kick, so the kick sees

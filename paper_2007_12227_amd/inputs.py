@@ -22,6 +22,7 @@ import numpy as np
 
 # Hamiltonian kinds, numbered as in the C interface (include/vp.h).
 H_FREE, H_SHO_EXACT, H_PENDULUM, H_FEL = 0, 1, 2, 3
+FEL_DKD, FEL_RK4 = 0, 1   # FEL integrators
 
 
 @dataclass(frozen=True)
@@ -48,6 +49,7 @@ class Hamiltonian:
     fel_sigma2: float = 0.0  # FEL space-charge coefficient
     A_re: float = 0.0        # FEL field at the current step
     A_im: float = 0.0
+    integrator: int = 0      # FEL: FEL_DKD (exact-kick drift-kick-drift) or FEL_RK4
 
 
 @dataclass
