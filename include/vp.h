@@ -50,6 +50,10 @@ extern "C" {
 #define VP_H_PENDULUM 2   /* H = p^2/2 - a cos x, drift-kick-drift leapfrog (Sec. Harmonic Oscillators) */
 #define VP_H_FEL 3        /* 1-D FEL, eqs. 13a-c, self-consistent field A (Sec. FEL simulations) */
 
+/* FEL integrators */
+#define VP_FEL_DKD 0 /* drift dz/2, exact kick dz, drift dz/2 (one bunching per step) */
+#define VP_FEL_RK4 1 /* classical fourth-order Runge-Kutta, the paper's integrator (four bunchings per step) */
+
 typedef struct vp_grid vp_grid;
 typedef struct vp_batch vp_batch;
 
@@ -82,10 +86,13 @@ typedef struct {
  *             sum of the weights when the density was set.  Drift dz/2, kick dz
  *             with the phases frozen (integrated exactly: A grows linearly
  *             through the kick), drift dz/2.  A_re, A_im give the field at the
- *             current step; vp_moments reports it as the run advances. */
+ *             current step; vp_moments reports it as the run advances.
+ *             With integrator VP_FEL_RK4 the nodes, as particles of charge w,
+ *             and A are advanced by the classical Runge-Kutta method instead,
+ *             each stage taking <.> over its own stage phases. */
 typedef struct {
     int32_t kind;
-    int32_t reserved;
+    int32_t integrator; /* FEL only: VP_FEL_DKD or VP_FEL_RK4; 0 otherwise */
     double a;
     double omega;
     double fel_delta;
@@ -167,8 +174,9 @@ int vp_set_launch(vp_grid* g, int32_t use_graph);
 /* Measurement helper: nsteps steps exactly as vp_step with direct launches,
  * with HIP events recorded on the grid's stream around every kernel.
  * us[0] and us[1] receive the mean duration in microseconds of the deposit
- * kernel and of the solve (for the FEL including the field update that
- * follows it).  Waits for the stream. */
+ * kernel (for the Runge-Kutta FEL including the stage sums before it) and of
+ * the solve (for the FEL including the field update that follows it).  Waits
+ * for the stream. */
 int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]);
 
 /* Time candidate tile shapes on this grid for step size dt and keep the

@@ -37,7 +37,7 @@ class GridDesc(C.Structure):
 
 
 class Hamiltonian(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("a", C.c_double), ("omega", C.c_double),
+    _fields_ = [("kind", C.c_int32), ("integrator", C.c_int32), ("a", C.c_double), ("omega", C.c_double),
                 ("fel_delta", C.c_double), ("fel_sigma2", C.c_double), ("A_re", C.c_double),
                 ("A_im", C.c_double)]
 
@@ -116,7 +116,8 @@ def axis(a) -> Axis:
 
 
 def hamiltonian(h) -> Hamiltonian:
-    return Hamiltonian(int(h.kind), 0, float(getattr(h, "a", 0.0)), float(getattr(h, "omega", 1.0)),
+    return Hamiltonian(int(h.kind), int(getattr(h, "integrator", 0)), float(getattr(h, "a", 0.0)),
+                       float(getattr(h, "omega", 1.0)),
                        float(getattr(h, "fel_delta", 0.0)), float(getattr(h, "fel_sigma2", 0.0)),
                        float(getattr(h, "A_re", 0.0)), float(getattr(h, "A_im", 0.0)))
 

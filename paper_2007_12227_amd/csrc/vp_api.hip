@@ -81,7 +81,7 @@ Layout layout(int nx, int np) {
     L.fel_state = take(kFelStateLen * 8);
     // solve tiles (FEL bunching partials) and reduction blocks
     size_t tiles = (size_t)((nx + kSeg - 1) / kSeg) * ((np + kSeg - 1) / kSeg);
-    L.partial_doubles = std::max((size_t)kReduceBlocks * kMoments, 2 * tiles);
+    L.partial_doubles = std::max((size_t)kReduceBlocks * kMoments, kPartialsPerTile * tiles);
     L.partials = take(L.partial_doubles * 8);
     L.counters = take(4 * sizeof(uint32_t));
     L.inst = take(sizeof(VpInst));
@@ -99,6 +99,7 @@ struct LaunchList {
     int32_t* d_off2 = nullptr;  // solve tiles
     int ninst = 0, total1 = 0, total2 = 0;
     bool has_fel = false;  // an FEL instance: the field kernel follows the solve
+    bool has_rk4 = false;  // a Runge-Kutta FEL instance: its stage sums precede the deposit
     size_t lds1 = 0;
     int threads1 = 256;  // deposit workgroup size
     hipStream_t stream = nullptr;
@@ -108,18 +109,27 @@ struct LaunchList {
         for (auto& e : exec)
             if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
     }
-    LaunchArgs args(const int32_t* off, int total, int parity) const {
-        return LaunchArgs{d_inst, off, ninst, total, parity};
+    LaunchArgs args(const int32_t* off, int total, int parity, int mode = 0) const {
+        return LaunchArgs{d_inst, off, ninst, total, parity, mode};
     }
-    // the kernels of one step: {kernel, off, total (= grid), lds, threads}
-    struct K { const void* fn; const int32_t* off; int total; size_t lds; int threads; };
-    int kernels(K (&k)[3]) const {
-        k[0] = K{deposit_kernel(), d_off1, total1, lds1, threads1};
-        k[1] = K{solve_kernel(), d_off2, total2, 0, kSolveThreads};
-        k[2] = K{fel_field_kernel(), d_off2, ninst, 0, kFieldThreads};
-        return has_fel ? 3 : 2;
+    // the kernels of one step: {kernel, off, total (= grid), lds, threads, mode}
+    struct K { const void* fn; const int32_t* off; int total; size_t lds; int threads; int mode; };
+    int kernels(K (&k)[5]) const {
+        int n = 0;
+        if (has_rk4) {
+            k[n++] = K{fel_stage_kernel(), d_off2, total2, 0, kStageThreads, 0};
+            k[n++] = K{fel_field_kernel(), d_off2, ninst, 0, kFieldThreads, 1};
+        }
+        k[n++] = K{deposit_kernel(), d_off1, total1, lds1, threads1, 0};
+        k[n++] = K{solve_kernel(), d_off2, total2, 0, kSolveThreads, 0};
+        if (has_fel) k[n++] = K{fel_field_kernel(), d_off2, ninst, 0, kFieldThreads, 0};
+        return n;
     }
     int enqueue_step(int parity) const {
+        if (has_rk4) {
+            HIP_TRY(launch_fel_stage(args(d_off2, total2, parity), total2, stream));
+            HIP_TRY(launch_fel_field(args(d_off2, ninst, parity, 1), stream));
+        }
         HIP_TRY(launch_deposit(args(d_off1, total1, parity), total1, lds1, threads1, stream));
         HIP_TRY(launch_solve(args(d_off2, total2, parity), total2, stream));
         if (has_fel) HIP_TRY(launch_fel_field(args(d_off2, ninst, parity), stream));
@@ -130,13 +140,13 @@ struct LaunchList {
         HIP_TRY(hipGraphCreate(&graph, 0));
         hipGraphNode_t prev = nullptr;
         std::vector<LaunchArgs> keep;
-        keep.reserve(3 * kGraphSteps);
-        K ks[3];
+        keep.reserve(5 * kGraphSteps);
+        K ks[5];
         const int nk = kernels(ks);
         for (int s = 0; s < kGraphSteps; ++s) {
             for (int ki = 0; ki < nk; ++ki) {
                 const K& k = ks[ki];
-                keep.push_back(args(k.off, k.total, (rel_parity + s) & 1));
+                keep.push_back(args(k.off, k.total, (rel_parity + s) & 1, k.mode));
                 void* kp[1] = {&keep.back()};
                 hipKernelNodeParams p{};
                 p.func = const_cast<void*>(k.fn);
@@ -271,6 +281,7 @@ int upload_inst(vp_grid* g) {
     HIP_TRY(hipStreamSynchronize(g->stream));
     g->list.ninst = 1;
     g->list.has_fel = I.push.kind == kFel;
+    g->list.has_rk4 = I.push.kind == kFel && I.push.rk4;
     g->list.total1 = I.k1_tiles;
     g->list.total2 = I.k2_tiles;
     g->list.lds1 = deposit_lds_bytes(t.k1_tx, t.k1_ty);
@@ -315,6 +326,7 @@ PushParams push_params(const vp_axis& x, const vp_axis& p, const vp_hamiltonian&
         const double kick = -2.0 * dt / hp;
         P.alpha = (float)(kick * kick_re);
         P.beta = (float)(-kick * kick_im);
+        P.rk4 = H.integrator == VP_FEL_RK4 ? 1 : 0;
     }
     return P;
 }
@@ -494,6 +506,8 @@ int vp_set_hamiltonian(vp_grid* g, const vp_hamiltonian* h) {
         return fail(VP_EINVAL, "non-finite Hamiltonian parameter");
     if (h->kind == VP_H_SHO_EXACT && g->x.periodic)
         return fail(VP_EUNSUPPORTED, "the exact rotation needs an open x axis");
+    if (h->integrator != VP_FEL_DKD && !(h->kind == VP_H_FEL && h->integrator == VP_FEL_RK4))
+        return fail(VP_EINVAL, "integrator %d: only the FEL takes VP_FEL_RK4", h->integrator);
     if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
     g->ham = *h;
     g->has_ham = true;
@@ -576,6 +590,10 @@ int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]) {
     for (int64_t s = 0; s < nsteps; ++s) {
         const int par = (int)((g->parity + s) & 1);
         HIP_TRY(hipEventRecord(ev[3 * s], g->stream));
+        if (L.has_rk4) {
+            HIP_TRY(launch_fel_stage(L.args(L.d_off2, L.total2, par), L.total2, g->stream));
+            HIP_TRY(launch_fel_field(L.args(L.d_off2, L.ninst, par, 1), g->stream));
+        }
         HIP_TRY(launch_deposit(L.args(L.d_off1, L.total1, par), L.total1, L.lds1, L.threads1, g->stream));
         HIP_TRY(hipEventRecord(ev[3 * s + 1], g->stream));
         HIP_TRY(launch_solve(L.args(L.d_off2, L.total2, par), L.total2, g->stream));
@@ -787,7 +805,10 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
     L.total1 = off1[n];
     L.total2 = off2[n];
     L.has_fel = false;
-    for (int k = 0; k < n; ++k) L.has_fel |= insts[k].push.kind == kFel;
+    for (int k = 0; k < n; ++k) {
+        L.has_fel |= insts[k].push.kind == kFel;
+        L.has_rk4 |= insts[k].push.kind == kFel && insts[k].push.rk4;
+    }
     L.lds1 = lds1;
     L.threads1 = threads1;
     hipError_t e = hipMalloc(&L.d_inst, sizeof(VpInst) * n);

@@ -40,6 +40,7 @@ constexpr int kSeg = 32;                 // solve segment length per lane (kept 
 constexpr int kLine = kSeg + 2 * kHalo;  // a lane's line: segment plus both halos
 constexpr int kSolveThreads = kLine;     // solve: one window line per lane
 constexpr int kFieldThreads = 256;       // FEL field update: one workgroup per instance
+constexpr int kStageThreads = 64;        // FEL Runge-Kutta stage sums: one wavefront per solve tile
 constexpr int kReduceBlocks = 256;
 constexpr int kReduceThreads = 256;
 constexpr int kMoments = 10;      // FP64 sums produced by the reduction kernel
@@ -59,6 +60,7 @@ struct PushParams {
     float alpha, beta;
     float kd;
     float c, s;
+    int32_t rk4;  // FEL by Runge-Kutta (the deposit reads its stage constants; alpha bounds |dv|)
 };
 
 __host__ __device__ inline float vp_floor(float v) {
@@ -145,7 +147,8 @@ __host__ __device__ inline void source_box(const PushParams& P, int bx0, int bx1
             float umin = dmin - kk * va, umax = dmax + kk * va;
             x0 = ifloor(ulo - umax) - 1;
             x1 = iceil(uhi - umin) + 1;
-            if (pass == 1 || R == 0.0f) break;
+            // (the Runge-Kutta push has no single phase to tighten with)
+            if (pass == 1 || R == 0.0f || P.rk4) break;
             // tighten dv with the phase range phi + q over the candidate box
             float qa = P.q0 + (float)y0 * P.q1, qb = P.q0 + (float)(y1 - 1) * P.q1;
             float qmin = qa < qb ? qa : qb, qmax = qa < qb ? qb : qa;
@@ -208,7 +211,12 @@ inline size_t box_capacity(int nx, int np) {
 constexpr int kRangeFlag = 2;  // counters slot set when a deposit cell sum leaves half its range
 
 // fel_state slots
-enum { kA = 0, kBn = 2, kN0 = 4, kDzB = 5, kFelStateLen = 16 };
+//   A: field; Bn: bunching at the half-drift phases (the exact-kick step's,
+//   and the Runge-Kutta step's stage 2); B1, B3, B4: the Runge-Kutta stages'
+//   bunchings at the lattice phases and at stages 3 and 4; An: the field after
+//   the Runge-Kutta step in progress
+enum { kA = 0, kBn = 2, kN0 = 4, kDzB = 5, kB1 = 6, kB3 = 8, kB4 = 10, kAn = 12, kFelStateLen = 16 };
+constexpr int kPartialsPerTile = 4;  // per solve tile: two complex FP64 bunching sums
 
 struct LaunchArgs {
     const VpInst* inst;
@@ -216,6 +224,7 @@ struct LaunchArgs {
     int32_t ninst;
     int32_t total;
     int32_t parity;      // step parity relative to each instance's parity0
+    int32_t mode;        // k_fel_field: 0 after the solve, 1 after the Runge-Kutta stage sums
 };
 
 struct ReduceArgs {
@@ -235,10 +244,12 @@ struct ReduceArgs {
 hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s);
 hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_fel_field(const LaunchArgs& a, hipStream_t s);
+hipError_t launch_fel_stage(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 const void* deposit_kernel();
 const void* solve_kernel();
 const void* fel_field_kernel();
+const void* fel_stage_kernel();
 
 // Deposit LDS image: (tx + 8) x (ty + 8) 64-bit cells.
 inline size_t deposit_lds_bytes(int tx, int ty) { return sizeof(int64_t) * (size_t)(tx + 2 * kPad) * (ty + 2 * kPad); }

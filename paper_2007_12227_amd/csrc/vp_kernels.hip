@@ -203,21 +203,54 @@ __device__ inline int open_window(int s0, int n) { return max(0, min(s0 - kHalo,
 
 }  // namespace
 
+// Push kinds of the deposit: a phase-dependent kick (free, pendulum, FEL by
+// the exact-kick step), the exact rotation, and the FEL by Runge-Kutta.
+enum PushKind { kPushPhase = 0, kPushSho = 1, kPushRk4 = 2 };
+
+// Runge-Kutta stage constants of one FEL step of size h (cell units):
+// slope of stage s, k_s = a_s cos psi_s + b_s sin psi_s, and
+//   dv = cdv (k1 + 2 k2 + 2 k3 + k4),  du = drift + cdu (k1 + k2 + k3),
+//   psi_2 = phi + q, psi_3 = psi_2 + t3 k1, psi_4 = psi_2 + q + t4 k2.
+struct RkConsts {
+    float a[4], b[4];
+    float cdv, cdu, t3, t4;
+};
+
 // Push one node (source row j, unwrapped column ii, weight w already scaled to
 // fixed point) and add its 16 B-spline taps into the LDS tile.
-template <bool SHO>
+template <int PUSH>
 __device__ inline void deposit_node(long long* acc, int j, int ii, float w, float4 tx, float4 tp,
-                                    float alpha, float beta, float kd, int X0, int Y0, int tw, int th,
-                                    int ldw) {
+                                    float alpha, float beta, float kd, const RkConsts& rk, int X0, int Y0,
+                                    int tw, int th, int ldw) {
 #pragma clang fp contract(off)  // the same bits in every inlined copy (see bspline_taps)
     int ku, kv;
     float fu, fv;
-    if (SHO) {
+    if (PUSH == kPushSho) {
         float su, eu, sv, ev;
         two_sum(tx.x, tp.x, su, eu);
         two_sum(tx.z, tp.z, sv, ev);
         split_cell(su, eu + (tx.y + tp.y), ku, fu);
         split_cell(sv, ev + (tx.w + tp.w), kv, fv);
+    } else if (PUSH == kPushRk4) {
+        // the four stages of the FEL equations (eqs. 13a-c) at this node;
+        // cos/sin of each stage phase by rotating the table's e^{i phi}
+        const float k1 = fmaf(rk.a[0], tx.y, rk.b[0] * tx.x);
+        const float c2 = fmaf(tx.y, tp.w, -(tx.x * tp.z));
+        const float s2 = fmaf(tx.x, tp.w, tx.y * tp.z);
+        const float k2 = fmaf(rk.a[1], c2, rk.b[1] * s2);
+        float sn, cs;
+        sincosf(rk.t3 * k1, &sn, &cs);
+        const float c3 = fmaf(c2, cs, -(s2 * sn)), s3 = fmaf(s2, cs, c2 * sn);
+        const float k3 = fmaf(rk.a[2], c3, rk.b[2] * s3);
+        const float c2q = fmaf(c2, tp.w, -(s2 * tp.z)), s2q = fmaf(s2, tp.w, c2 * tp.z);
+        sincosf(rk.t4 * k2, &sn, &cs);
+        const float c4 = fmaf(c2q, cs, -(s2q * sn)), s4 = fmaf(s2q, cs, c2q * sn);
+        const float k4 = fmaf(rk.a[3], c4, rk.b[3] * s4);
+        const float dv = rk.cdv * ((k1 + k4) + 2.0f * (k2 + k3));
+        float su, eu;
+        two_sum(tp.x, rk.cdu * ((k1 + k2) + k3), su, eu);
+        split_cell(su, eu + tp.y, ku, fu);
+        split_cell(dv, 0.0f, kv, fv);
     } else {
         // phase phi_i + q_j from the per-axis sine/cosine tables
         const float cph = fmaf(tx.y, tp.w, -(tx.x * tp.z));
@@ -272,9 +305,10 @@ struct SourceScan {
     float inv_nx, scale, alpha, beta, kd;
     double inv_bw;
     int X0, Y0, tw, th, ldw;
+    RkConsts rk;
 };
 
-template <bool SHO, int COL>
+template <int PUSH, int COL>
 __device__ inline void scan_sources(const SourceScan& S) {
     gfloat* __restrict__ w_g = S.w;
     gfloat4* __restrict__ tab_x = S.tab_x;
@@ -331,8 +365,8 @@ __device__ inline void scan_sources(const SourceScan& S) {
         if (!__any(live)) continue;
 #pragma unroll
         for (int h = 0; h < kU; ++h)
-            deposit_node<SHO>(S.acc, jj[h], iiu[h], wv[h] * S.scale, txv[h], tpv[h], S.alpha, S.beta, S.kd, S.X0,
-                              S.Y0, S.tw, S.th, S.ldw);
+            deposit_node<PUSH>(S.acc, jj[h], iiu[h], wv[h] * S.scale, txv[h], tpv[h], S.alpha, S.beta, S.kd, S.rk,
+                               S.X0, S.Y0, S.tw, S.th, S.ldw);
     }
 }
 
@@ -349,6 +383,7 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
     extern __shared__ __align__(16) long long acc[];  // 16-byte aligned: read four cells at a time
     __shared__ int s_d, s_box[4], s_next;
     __shared__ float s_ab[2];
+    __shared__ RkConsts s_rk;
 
     for (int it = blockIdx.x; it < A.total; it += gridDim.x) {
         const int item = tile_of(it, A.total);
@@ -379,7 +414,33 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
             s_box[3] = hb.w;
         } else if (threadIdx.x == 0) {
             PushParams P = I.push;
-            if (P.kind == kFel) {
+            if (P.kind == kFel && P.rk4) {
+                // stage fields A_s and bunchings b_s of the Runge-Kutta step
+                // (b1, b2 of the state, b3, b4 from k_fel_stage), FP64
+                const double* st = I.fel_state;
+                const double h = I.fel_dz, sg = (double)I.fel_sigma2;
+                const double bre[4] = {st[kB1], st[kBn], st[kB3], st[kB4]};
+                const double bim[4] = {st[kB1 + 1], st[kBn + 1], st[kB3 + 1], st[kB4 + 1]};
+                const double cA[4] = {0.0, 0.5 * h, 0.5 * h, h};  // A_s = A + cA_s b_{s-1}
+                double rmax = 0.0;
+                for (int k = 0; k < 4; ++k) {
+                    const double are = st[kA] + (k ? cA[k] * bre[k - 1] : 0.0);
+                    const double aim = st[kA + 1] + (k ? cA[k] * bim[k - 1] : 0.0);
+                    // F = -2 Re[(A + i sigma2 b) e^{i psi}] = a cos psi + b sin psi
+                    const double re = are - sg * bim[k], im = aim + sg * bre[k];
+                    s_rk.a[k] = (float)(-2.0 * re);
+                    s_rk.b[k] = (float)(2.0 * im);
+                    rmax = fmax(rmax, sqrt(re * re + im * im));
+                }
+                const double hp = (double)P.hp, hx = (double)P.hx;
+                s_rk.cdv = (float)(h / (6.0 * hp));
+                s_rk.cdu = (float)(h * h / (6.0 * hx));
+                s_rk.t3 = (float)(0.25 * h * h);
+                s_rk.t4 = (float)(0.5 * h * h);
+                // |dv| <= (h / hp) 2 max_s |A_s + i sigma2 b_s|; |du - drift| <= kd |dv|max
+                P.alpha = (float)(2.0 * h / hp * rmax);
+                P.beta = 0.0f;
+            } else if (P.kind == kFel) {
                 // kick field: A at mid-kick plus the space-charge term, A + b dz/2 + i sigma2 b
                 const double* st = I.fel_state;
                 double are = st[kA] + 0.5 * I.fel_dz * st[kBn] - (double)I.fel_sigma2 * st[kBn + 1];
@@ -443,16 +504,32 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
         S.tw = X1 - X0;
         S.th = Y1 - Y0;
         S.ldw = ldw;
+        const bool rk4 = kind == kFel && I.push.rk4;
+        if (rk4) {
+            auto uni = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
+            for (int k = 0; k < 4; ++k) {
+                S.rk.a[k] = uni(s_rk.a[k]);
+                S.rk.b[k] = uni(s_rk.b[k]);
+            }
+            S.rk.cdv = uni(s_rk.cdv);
+            S.rk.cdu = uni(s_rk.cdu);
+            S.rk.t3 = uni(s_rk.t3);
+            S.rk.t4 = uni(s_rk.t4);
+        }
         const bool wrap_near = bx0 >= -nx && bx0 + bw <= 2 * nx;
         const int col = !periodic ? 0 : wrap_near ? 1 : 2;
         if (kind == kSho) {
-            if (col == 0) scan_sources<true, 0>(S);
-            else if (col == 1) scan_sources<true, 1>(S);
-            else scan_sources<true, 2>(S);
+            if (col == 0) scan_sources<kPushSho, 0>(S);
+            else if (col == 1) scan_sources<kPushSho, 1>(S);
+            else scan_sources<kPushSho, 2>(S);
+        } else if (rk4) {
+            if (col == 0) scan_sources<kPushRk4, 0>(S);
+            else if (col == 1) scan_sources<kPushRk4, 1>(S);
+            else scan_sources<kPushRk4, 2>(S);
         } else {
-            if (col == 0) scan_sources<false, 0>(S);
-            else if (col == 1) scan_sources<false, 1>(S);
-            else scan_sources<false, 2>(S);
+            if (col == 0) scan_sources<kPushPhase, 0>(S);
+            else if (col == 1) scan_sources<kPushPhase, 1>(S);
+            else scan_sources<kPushPhase, 2>(S);
         }
         __syncthreads();
 
@@ -598,7 +675,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
         __syncthreads();
 
         // p: lane = window column; the kept rows of the kept columns go out
-        double acc_re = 0.0, acc_im = 0.0;
+        const bool rk4 = fel && I.push.rk4;
+        double acc_re = 0.0, acc_im = 0.0, acc1_re = 0.0, acc1_im = 0.0;
         {
             float v[kLine];
             float* col = lds + lane;
@@ -618,12 +696,14 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
                     qo += (unsigned)nx;
                 };
                 // FEL: the bunching sums first, in a loop with no stores, so that
-                // its table loads are not ordered behind the stores
-                double cre = 0.0, cim = 0.0;
+                // its table loads are not ordered behind the stores; the
+                // Runge-Kutta step also needs the sum at the lattice phases
+                double cre = 0.0, cim = 0.0, c1 = 0.0;
                 auto bunch = [&](int k) {
                     const double2 e = s_eq[wp + k - Y0];  // times e^{-i q}
                     cre += (double)v[k] * e.x;
                     cim -= (double)v[k] * e.y;
+                    if (rk4) c1 += (double)v[k];
                 };
                 if (lo == kHalo && th == kSeg) {
                     if (fel) {
@@ -647,20 +727,28 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
                     const double2 e = I.fel_ex[gx];  // times e^{-i phi}
                     acc_re = cre * e.x + cim * e.y;
                     acc_im = cim * e.x - cre * e.y;
+                    acc1_re = c1 * e.x;
+                    acc1_im = -c1 * e.y;
                 }
             }
         }
 
         if (fel) {
-            // FP64 bunching of the new state: this tile's partial (k_fel_field
-            // sums the partials)
+            // FP64 bunching of the new state: this tile's partials, at the
+            // half-drift phases and (Runge-Kutta) at the lattice phases
+            // (k_fel_field sums the partials)
             for (int o = 32; o > 0; o >>= 1) {
                 acc_re += __shfl_down(acc_re, o);
                 acc_im += __shfl_down(acc_im, o);
+                acc1_re += __shfl_down(acc1_re, o);
+                acc1_im += __shfl_down(acc1_im, o);
             }
             if (lane == 0) {
-                I.partials[2 * t] = acc_re;
-                I.partials[2 * t + 1] = acc_im;
+                double* pt = I.partials + kPartialsPerTile * t;
+                pt[0] = acc_re;
+                pt[1] = acc_im;
+                pt[2] = acc1_re;
+                pt[3] = acc1_im;
             }
         }
         __syncthreads();
@@ -669,46 +757,137 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
 
 // ---------------------------------------------------------------------------
 // k_fel_field: one workgroup per instance of the launch list; for an FEL
-// instance it sums the solve's per-tile bunching partials in a fixed order
-// (thread-strided, then a fixed shuffle tree) and advances the field: A moves
-// by dz times the bunching of the state that was pushed (eq. 13c), and the new
-// state's bunching is kept for the next kick.  A kernel of its own, because a
-// last-tile-sums scheme inside k_solve needs a device-scope release per tile,
-// which on a multi-XCD part writes back the L2 and costs more than the solve.
+// instance it sums the per-tile bunching partials of the preceding kernel in a
+// fixed order (thread-strided, then a fixed shuffle tree) and advances the
+// field (eq. 13c).  A kernel of its own, because a last-tile-sums scheme
+// inside k_solve needs a device-scope release per tile, which on a multi-XCD
+// part writes back the L2 and costs more than the solve.
+//  mode 0 (after k_solve; partials: the new state's bunching at the half-drift
+//    and at the lattice phases).  Exact-kick step: A moves by dz times the
+//    bunching of the state that was pushed; Runge-Kutta: A takes the step's
+//    new value.  The new bunchings are kept for the next step.
+//  mode 1 (after k_fel_stage, Runge-Kutta only; partials: the bunching at the
+//    phases of stages 3 and 4): keeps b3, b4 and forms the step's new field
+//    A + dz/6 (b1 + 2 b2 + 2 b3 + b4).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kFieldThreads) void k_fel_field(LaunchArgs A) {
-    __shared__ double s_red[2][kFieldThreads / 64];
+    __shared__ double s_red[kPartialsPerTile][kFieldThreads / 64];
     const VpInst& I = A.inst[blockIdx.x];
-    if (I.push.kind != kFel) return;
-    double re = 0.0, im = 0.0;
-    for (int k = threadIdx.x; k < I.k2_tiles; k += kFieldThreads) {
-        re += I.partials[2 * k];
-        im += I.partials[2 * k + 1];
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        re += __shfl_down(re, o);
-        im += __shfl_down(im, o);
-    }
+    if (I.push.kind != kFel || (A.mode == 1 && !I.push.rk4)) return;
+    double acc[kPartialsPerTile] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < I.k2_tiles; k += kFieldThreads)
+        for (int c = 0; c < kPartialsPerTile; ++c) acc[c] += I.partials[kPartialsPerTile * k + c];
+    for (int o = 32; o > 0; o >>= 1)
+        for (int c = 0; c < kPartialsPerTile; ++c) acc[c] += __shfl_down(acc[c], o);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) {
-        s_red[0][wid] = re;
-        s_red[1][wid] = im;
-    }
+    if (lane == 0)
+        for (int c = 0; c < kPartialsPerTile; ++c) s_red[c][wid] = acc[c];
     __syncthreads();
     if (threadIdx.x == 0) {
-        re = 0.0;
-        im = 0.0;
-        for (int k = 0; k < kFieldThreads / 64; ++k) {
-            re += s_red[0][k];
-            im += s_red[1][k];
+        for (int c = 0; c < kPartialsPerTile; ++c) {
+            acc[c] = 0.0;
+            for (int k = 0; k < kFieldThreads / 64; ++k) acc[c] += s_red[c][k];
         }
         double* st = I.fel_state;
-        const double inv_n0 = 1.0 / st[kN0];
-        st[kA] += I.fel_dz * st[kBn];
-        st[kA + 1] += I.fel_dz * st[kBn + 1];
-        st[kBn] = re * inv_n0;
-        st[kBn + 1] = im * inv_n0;
-        st[kDzB] = I.fel_dz;
+        const double inv_n0 = 1.0 / st[kN0], h = I.fel_dz;
+        if (A.mode == 1) {
+            st[kB3] = acc[0] * inv_n0;
+            st[kB3 + 1] = acc[1] * inv_n0;
+            st[kB4] = acc[2] * inv_n0;
+            st[kB4 + 1] = acc[3] * inv_n0;
+            for (int c = 0; c < 2; ++c)
+                st[kAn + c] = st[kA + c] + h / 6.0 * (st[kB1 + c] + 2.0 * st[kBn + c] + 2.0 * st[kB3 + c] + st[kB4 + c]);
+            return;
+        }
+        if (I.push.rk4) {
+            st[kA] = st[kAn];
+            st[kA + 1] = st[kAn + 1];
+            st[kB1] = acc[2] * inv_n0;
+            st[kB1 + 1] = acc[3] * inv_n0;
+        } else {
+            st[kA] += h * st[kBn];
+            st[kA + 1] += h * st[kBn + 1];
+        }
+        st[kBn] = acc[0] * inv_n0;
+        st[kBn + 1] = acc[1] * inv_n0;
+        st[kDzB] = h;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_fel_stage: the bunching at the phases of the Runge-Kutta step's stages 3
+// and 4 (FEL only), FP64, one per-tile partial per solve tile of 32 x 32 nodes
+// (one wavefront: lane l takes column l mod 32 and every other row).  With
+// k1 = a1 cos phi + b1 sin phi and k2 = a2 cos psi2 + b2 sin psi2 the slopes of
+// stages 1 and 2 (fields A1 = A, A2 = A + dz/2 b1), the phases are
+// psi3 = phi + q + dz^2/4 k1 and psi4 = phi + 2 q + dz^2/2 k2, q the half drift
+// of the node's row.  k1 depends on the column only, so stage 3's sum is a
+// column sum of w e^{-i q} turned by e^{-i(phi + dz^2/4 k1)}.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kStageThreads) void k_fel_stage(LaunchArgs A) {
+    const int lane = threadIdx.x;
+    for (int item = blockIdx.x; item < A.total; item += gridDim.x) {
+        const int d = __builtin_amdgcn_readfirstlane(find_instance(A.off, A.ninst, item));
+        const VpInst& I = A.inst[d];
+        if (I.push.kind != kFel || !I.push.rk4) continue;
+        const int t = item - A.off[d];
+        const int nx = I.push.nx, np = I.push.np;
+        const int tiles_x = (nx + kSeg - 1) / kSeg;
+        const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
+        const int X0 = txi * kSeg, tw = min(kSeg, nx - X0);
+        const int Y0 = tyi * kSeg, th = min(kSeg, np - Y0);
+        const int par = (I.parity0 + A.parity) & 1;
+        const float* __restrict__ w = I.w[par];
+        const double* st = I.fel_state;
+        const double h = I.fel_dz, sg = (double)I.fel_sigma2;
+        // slope coefficients of stages 1 and 2 (as in the deposit, FP64)
+        const double b1r = st[kB1], b1i = st[kB1 + 1], b2r = st[kBn], b2i = st[kBn + 1];
+        const double a1r = st[kA] - sg * b1i, a1i = st[kA + 1] + sg * b1r;
+        const double a2r = st[kA] + 0.5 * h * b1r - sg * b2i, a2i = st[kA + 1] + 0.5 * h * b1i + sg * b2r;
+        const double t3 = 0.25 * h * h, t4 = 0.5 * h * h;
+        double s3r = 0.0, s3i = 0.0, s4r = 0.0, s4i = 0.0;
+        const int col = lane & 31;
+        if (col < tw) {
+            const int gx = X0 + col;
+            const double2 ex = I.fel_ex[gx];
+            double cre = 0.0, cim = 0.0;
+            for (int r = lane >> 5; r < th; r += 2) {
+                const int j = Y0 + r;
+                const double wk = (double)w[(size_t)j * nx + gx];
+                const double2 eq = I.fel_eq[j];
+                cre += wk * eq.x;
+                cim -= wk * eq.y;
+                // e^{i psi2} = e^{i phi} e^{i q}
+                const double c2 = ex.x * eq.x - ex.y * eq.y, s2 = ex.y * eq.x + ex.x * eq.y;
+                const double k2 = -2.0 * (a2r * c2 - a2i * s2);
+                double sn, cs;
+                sincos(t4 * k2, &sn, &cs);
+                // e^{i psi4} = e^{i psi2} e^{i q} e^{i t4 k2}
+                const double c2q = c2 * eq.x - s2 * eq.y, s2q = s2 * eq.x + c2 * eq.y;
+                const double c4 = c2q * cs - s2q * sn, s4 = s2q * cs + c2q * sn;
+                s4r += wk * c4;
+                s4i -= wk * s4;
+            }
+            const double k1 = -2.0 * (a1r * ex.x - a1i * ex.y);
+            double sn, cs;
+            sincos(t3 * k1, &sn, &cs);
+            const double c3 = ex.x * cs - ex.y * sn, s3 = ex.y * cs + ex.x * sn;  // e^{i(phi + t3 k1)}
+            s3r = cre * c3 + cim * s3;
+            s3i = cim * c3 - cre * s3;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            s3r += __shfl_down(s3r, o);
+            s3i += __shfl_down(s3i, o);
+            s4r += __shfl_down(s4r, o);
+            s4i += __shfl_down(s4i, o);
+        }
+        if (lane == 0) {
+            double* pt = I.partials + kPartialsPerTile * t;
+            pt[0] = s3r;
+            pt[1] = s3i;
+            pt[2] = s4r;
+            pt[3] = s4i;
+        }
     }
 }
 
@@ -717,7 +896,8 @@ __global__ __launch_bounds__(kFieldThreads) void k_fel_field(LaunchArgs A) {
 //  mode 0 (diagnostics): sum w, sum_{w<0} w, sum |w|, sum_{w>0} w ln w,
 //    sum w p, sum w (kinetic + potential), sum w cos x, sum w sin x, max |w|,
 //    #nonfinite.
-//  mode 1 (FEL bunching): sum w e^{-i (phi_i + q_j)} / N0 -> fel_state.
+//  mode 1 (FEL bunching): sum w e^{-i (phi_i + q_j)} / N0 and
+//    sum w e^{-i phi_i} / N0 -> fel_state.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
     __shared__ double s_part[kReduceThreads / 64][kMoments];
@@ -739,6 +919,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
             // e^{-i(phi+q)} = (cos phi cos q - sin phi sin q) - i (sin phi cos q + cos phi sin q)
             acc[0] += w * (ex.x * eq.x - ex.y * eq.y);
             acc[1] -= w * (ex.y * eq.x + ex.x * eq.y);
+            // and at the lattice phases, e^{-i phi} (the Runge-Kutta step's stage 1)
+            acc[2] += w * ex.x;
+            acc[3] -= w * ex.y;
             continue;
         }
         if (!isfinite(w)) { acc[9] += 1.0; continue; }
@@ -788,6 +971,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
         }
         if (R.mode == 1) {
             if (threadIdx.x < 2) R.out[kBn + threadIdx.x] = s * R.inv_n0;
+            else if (threadIdx.x < 4) R.out[kB1 + threadIdx.x - 2] = s * R.inv_n0;
             if (threadIdx.x == 0) R.out[kDzB] = R.dz;
         } else {
             R.out[threadIdx.x] = s;
@@ -815,6 +999,11 @@ hipError_t launch_fel_field(const LaunchArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_fel_stage(const LaunchArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_fel_stage, dim3(grid), dim3(kStageThreads), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a);
     return hipGetLastError();
@@ -823,5 +1012,6 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
 const void* deposit_kernel() { return reinterpret_cast<const void*>(&k_deposit); }
 const void* solve_kernel() { return reinterpret_cast<const void*>(&k_solve); }
 const void* fel_field_kernel() { return reinterpret_cast<const void*>(&k_fel_field); }
+const void* fel_stage_kernel() { return reinterpret_cast<const void*>(&k_fel_stage); }
 
 }  // namespace vp

@@ -2,11 +2,13 @@
 every grid.  The deposit accumulates in integers and the solve has no atomics,
 so every instance must come out bit-identical to the same instance run alone;
 sampled small instances are also checked against the FP64 oracle."""
+import dataclasses
+
 import numpy as np
 import pytest
 
 import oracle
-from paper_2007_12227_amd.inputs import batch_instances, fel_gaussian
+from paper_2007_12227_amd.inputs import FEL_RK4, batch_instances, fel_gaussian
 
 pytestmark = pytest.mark.gpu
 
@@ -31,6 +33,8 @@ def alone(B, inst, steps):
 def test_ragged_mixed_batch_equals_alone(B):
     insts = batch_instances(24, seed=40, steps=30, n_min=48, n_max=300)
     insts += [fel_gaussian(96, 30, npp=128), fel_gaussian(160, 30, npp=64)]
+    rk = fel_gaussian(112, 30, npp=96)   # and one advanced by the Runge-Kutta integrator
+    insts.append(dataclasses.replace(rk, ham=dataclasses.replace(rk.ham, integrator=FEL_RK4, fel_sigma2=0.3)))
     grids = [B.grid_for(i) for i in insts]
     grids[3].set_tiles((32, 8), 128)       # per-instance tile shapes in one launch,
     grids[5].set_tiles((128, 64), 1024)    # which runs at the largest workgroup size

@@ -12,7 +12,9 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2007_12227_amd.inputs import (H_FEL, H_FREE, H_PENDULUM, H_SHO_EXACT, Axis, Hamiltonian,
+import dataclasses
+
+from paper_2007_12227_amd.inputs import (FEL_RK4, H_FEL, H_FREE, H_PENDULUM, H_SHO_EXACT, Axis, Hamiltonian,
                                          fel_flattop, fel_gaussian, gaussian, pendulum_axes, pendulum_band,
                                          pendulum_gaussian, rng)
 
@@ -119,12 +121,19 @@ def test_graph_and_plain_launches_agree(B):
     assert oracle.rel_l1(a, b) <= 1e-6
 
 
-@pytest.mark.parametrize("kind", ["pendulum", "fel"])
+def rk4(inst, **kw):
+    """The same instance advanced by the Runge-Kutta FEL integrator."""
+    return dataclasses.replace(inst, ham=dataclasses.replace(inst.ham, integrator=FEL_RK4, **kw))
+
+
+@pytest.mark.parametrize("kind", ["pendulum", "fel", "fel_rk4"])
 def test_results_bitwise_independent_of_deposit_tiling(B, kind):
     """The deposit sums taps as exact integers, so any tiling and workgroup
     size (each node is pushed by every tile whose source box holds it) gives
     the same bits."""
     inst = pendulum_band(256, steps=30) if kind == "pendulum" else fel_gaussian(192, 30, npp=160)
+    if kind == "fel_rk4":
+        inst = rk4(inst, fel_sigma2=0.3)
     ref = None
     for k1 in [(64, 32, 256), (128, 16, 512), (24, 5, 64), (200, 24, 1024), (16, 8, 128), (128, 128, 1024),
                (96, 40, 320)]:
@@ -239,6 +248,66 @@ def test_fel_flattop_start(B):
     assert abs(m["neg_mass"] - ref["neg_mass"]) <= 1e-4 * ref["l1"]
 
 
+# ---- FEL by the Runge-Kutta integrator ----
+
+def test_fel_rk4_one_step(B):
+    """One Runge-Kutta step (four stage bunchings) of the full model from the
+    same FP32 weights: the state to the one-step bar and the field to FP64
+    rounding (both sides form every bunching in FP64 from the same weights)."""
+    inst = fel_gaussian(96, 1, npp=160)
+    ham = Hamiltonian(H_FEL, A_re=0.02, A_im=-0.01, fel_delta=0.3, fel_sigma2=0.4, integrator=FEL_RK4)
+    w32 = inst.w0.astype(np.float32)
+    got, m = gpu_run(B, inst.x, inst.p, ham, w32, inst.dt, 1, (64, 16))
+    r = oracle.run(inst.x, inst.p, ham, w32.astype(np.float64), inst.dt, 1)
+    assert oracle.rel_l1(got, r.w) <= 1e-5
+    assert abs(complex(m["A_re"], m["A_im"]) - r.A) <= 1e-12
+
+
+@pytest.mark.parametrize("delta,sigma2", [(0.0, 0.0), (0.3, 0.4)])
+def test_fel_rk4_run(B, delta, sigma2):
+    """200 Runge-Kutta steps through the start of the exponential growth,
+    against the oracle: state, field and the invariant |A|^2 + <eta> (which
+    the method keeps to its order, not exactly)."""
+    base = fel_gaussian(256, 200, npp=256)
+    ham = Hamiltonian(H_FEL, A_re=1e-3, fel_delta=delta, fel_sigma2=sigma2, integrator=FEL_RK4)
+    w32 = base.w0.astype(np.float32)
+    got, m = gpu_run(B, base.x, base.p, ham, w32, base.dt, 200)
+    r = oracle.run(base.x, base.p, ham, w32.astype(np.float64), base.dt, 200)
+    ref = oracle.moments(base.x, base.p, ham, r.w, r.A, N0=float(w32.astype(np.float64).sum()))
+    err = oracle.rel_l1(got, r.w)
+    print(f"fel rk4 delta {delta} sigma2 {sigma2}, 200 steps: rel L1 {err:.3e}, "
+          f"A gpu {m['A_re']:+.6e}{m['A_im']:+.6e}j oracle {r.A:.6e}")
+    assert err <= 1e-4
+    assert abs(complex(m["A_re"], m["A_im"]) - r.A) <= 1e-4 * abs(r.A)
+    assert abs(m["fel_invariant"] - ref["fel_invariant"]) <= 1e-7
+
+
+def test_fel_rk4_graph_and_plain_launches_agree(B):
+    inst = rk4(fel_gaussian(192, 40, npp=160))
+    w32 = inst.w0.astype(np.float32)
+    a, ma = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 40, graph=True)
+    b, mb = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 40, graph=False)
+    assert np.array_equal(a, b)
+    assert (ma["A_re"], ma["A_im"]) == (mb["A_re"], mb["A_im"])
+
+
+def test_fel_rk4_step_size_change(B):
+    """A new dz re-plans the tables and recomputes the state's bunchings: 20
+    steps at dz then 20 at dz/2 match the oracle run the same way."""
+    inst = rk4(fel_gaussian(128, 40, npp=160), fel_sigma2=0.2)
+    w32 = inst.w0.astype(np.float32)
+    g = B.grid_for(dataclasses.replace(inst, w0=w32))
+    g.step(inst.dt, 20)
+    g.step(0.5 * inst.dt, 20)
+    got, m = g.density().astype(np.float64), g.moments()
+    g.close()
+    N0 = float(w32.astype(np.float64).sum())
+    r1 = oracle.run(inst.x, inst.p, inst.ham, w32.astype(np.float64), inst.dt, 20)
+    r2 = oracle.run(inst.x, inst.p, inst.ham, r1.w, 0.5 * inst.dt, 20, A0=r1.A, N0=N0)
+    assert oracle.rel_l1(got, r2.w) <= 1e-4
+    assert abs(complex(m["A_re"], m["A_im"]) - r2.A) <= 1e-4 * abs(r2.A)
+
+
 # ---- full sizes ----
 
 def test_one_step_full_size_pendulum_band_2048(B):
@@ -247,6 +316,15 @@ def test_one_step_full_size_pendulum_band_2048(B):
     got, _ = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 1)
     ref = one_step_ref(inst.x, inst.p, inst.ham, w32, inst.dt)
     assert oracle.rel_l1(got, ref) <= 1e-5
+
+
+def test_one_step_full_size_fel_rk4_1024(B):
+    inst = rk4(fel_gaussian(1024), fel_sigma2=0.2)
+    w32 = inst.w0.astype(np.float32)
+    got, m = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 1)
+    r = oracle.run(inst.x, inst.p, inst.ham, w32.astype(np.float64), inst.dt, 1)
+    assert oracle.rel_l1(got, r.w) <= 1e-5
+    assert abs(complex(m["A_re"], m["A_im"]) - r.A) <= 1e-12
 
 
 def test_one_step_full_size_fel_1024(B):
