@@ -46,16 +46,21 @@ def timed_steps(g, dt, steps, warmup):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
-def bench_fel(binding, steps):
-    """1024^2 FEL (Gaussian in energy, A0 = 1e-3, dz = 0.01), tuned launch."""
+def bench_fel(binding, steps, integrator=0):
+    """1024^2 FEL (Gaussian in energy, A0 = 1e-3, dz = 0.01), tuned launch;
+    integrator 0: exact-kick drift-kick-drift, 1: classical Runge-Kutta."""
+    import dataclasses
+
     from paper_2007_12227_amd.inputs import fel_gaussian
     inst = fel_gaussian(1024, steps)
+    inst = dataclasses.replace(inst, ham=dataclasses.replace(inst.ham, integrator=integrator))
     g = binding.grid_for(inst)
     g.autotune(inst.dt)
     sec, _ = timed_steps(g, inst.dt, steps, 0)
     m = g.moments()
     g.close()
-    return {"workload": "fel_gaussian_1024", "steps": steps, "value": inst.nodes * steps / sec,
+    name = "fel_gaussian_1024" + ("_rk4" if integrator else "")
+    return {"workload": name, "steps": steps, "value": inst.nodes * steps / sec,
             "ms_per_step": 1e3 * sec / steps, "A_abs": abs(complex(m["A_re"], m["A_im"]))}
 
 
@@ -277,6 +282,8 @@ def main():
     if not args.no_extras:
         line["fel"] = bench_fel(binding, args.fel_steps)
         log(f"fel: {line['fel']}")
+        line["fel_rk4"] = bench_fel(binding, args.fel_steps, integrator=1)
+        log(f"fel_rk4: {line['fel_rk4']}")
         line["batched"] = bench_batched(binding, args.batch_steps, args.batch_count)
         log(f"batched: {line['batched']}")
         line["served"] = bench_served(binding, args.serve_requests, args.serve_load,

@@ -80,7 +80,7 @@ Layout layout(int nx, int np) {
     L.fel_eq = take((size_t)np * 16);
     L.fel_state = take(kFelStateLen * 8);
     // solve tiles (FEL bunching partials) and reduction blocks
-    size_t tiles = (size_t)((nx + kSeg - 1) / kSeg) * ((np + kSeg - 1) / kSeg);
+    size_t tiles = (size_t)((nx + kSegX - 1) / kSegX) * ((np + kSegP - 1) / kSegP);
     L.partial_doubles = std::max((size_t)kReduceBlocks * kMoments, kPartialsPerTile * tiles);
     L.partials = take(L.partial_doubles * 8);
     L.counters = take(4 * sizeof(uint32_t));
@@ -256,7 +256,7 @@ int upload_inst(vp_grid* g) {
     I.k1_ty = t.k1_ty;
     I.k1_tiles_x = (g->x.n + t.k1_tx - 1) / t.k1_tx;
     I.k1_tiles = I.k1_tiles_x * ((g->p.n + t.k1_ty - 1) / t.k1_ty);
-    I.k2_tiles = ((g->x.n + kSeg - 1) / kSeg) * ((g->p.n + kSeg - 1) / kSeg);
+    I.k2_tiles = ((g->x.n + kSegX - 1) / kSegX) * ((g->p.n + kSegP - 1) / kSegP);
     I.parity0 = 0;
     // source boxes of a push that does not depend on the state: planned here
     // once, instead of by one thread of every deposit tile at every step

@@ -11,10 +11,10 @@
 //              that can reach it; the tile is written to b once.
 //   k_solve:   w_out = (M_x^{-1} (x) M_p^{-1}) b, the tent mass matrix of
 //              eq. 8, M = tridiag(1/6, 2/3, 1/6), cyclic on a periodic axis.  A
-//              wavefront owns a 32x32 output tile and solves the 64x64 window
+//              wavefront owns a 32x64 output tile and solves the 64x96 window
 //              around it (a 16-node halo per side makes the tile independent of
-//              its neighbours to within (2-sqrt 3)^16 ~ 7e-10), rows then
-//              columns, one line per lane.  For the FEL its epilogue also forms
+//              its neighbours to within (2-sqrt 3)^16 ~ 7e-10), columns then
+//              rows, one line per lane.  For the FEL its epilogue also forms
 //              the FP64 bunching partials of the new state, which k_fel_field
 //              sums to advance the FEL field.
 #pragma once
@@ -36,9 +36,11 @@ constexpr int kEdge = 32;         // nodes from an open edge whose LU coefficien
 constexpr int kPad = 4;           // trash border of a deposit tile (per side)
 constexpr int kFixBits = 40;      // deposit cell sums: 64-bit fixed point at 2^-40 of 2^e > max|w0|
 constexpr int kDepositMaxThreads = 1024;  // deposit workgroup: a multiple of 64 up to this
-constexpr int kSeg = 32;                 // solve segment length per lane (kept nodes)
-constexpr int kLine = kSeg + 2 * kHalo;  // a lane's line: segment plus both halos
-constexpr int kSolveThreads = kLine;     // solve: one window line per lane
+constexpr int kSegX = 32;                  // solve tile: kSegX columns by kSegP rows (kept nodes)
+constexpr int kSegP = 64;
+constexpr int kLineX = kSegX + 2 * kHalo;  // window line along x: the kept segment plus both halos
+constexpr int kLineP = kSegP + 2 * kHalo;  // window line along p
+constexpr int kSolveThreads = 64;          // solve: one wavefront (a window column, then a kept row, per lane)
 constexpr int kFieldThreads = 256;       // FEL field update: one workgroup per instance
 constexpr int kStageThreads = 64;        // FEL Runge-Kutta stage sums: one wavefront per solve tile
 constexpr int kReduceBlocks = 256;
@@ -179,7 +181,7 @@ __host__ __device__ inline void source_box(const PushParams& P, int bx0, int bx1
 struct VpInst {
     PushParams push;
     int32_t k1_tx, k1_ty, k1_tiles_x, k1_tiles;
-    int32_t k2_tiles;        // solve tiles: kSeg x kSeg nodes
+    int32_t k2_tiles;        // solve tiles: kSegX x kSegP nodes
     int32_t pad2;
     int32_t parity0;         // index of the current state buffer when the launch list was built
     int32_t pad0;

@@ -123,6 +123,10 @@ __device__ inline void settle(T v) {
 // nothing else (expcnt 7, lgkmcnt 15).
 constexpr int kWaitVmcnt0 = 0x0F70;
 
+// Fourth word of a raw buffer resource (gfx9 family): 32-bit data format,
+// no range check beyond the 2^32-byte window the resource spans.
+constexpr int kBufferWord3 = 0x00020000;
+
 // Workgroups are dispatched to the 8 XCDs round-robin.  When the grid has
 // one workgroup per tile, give each XCD a contiguous run of tiles, so that
 // neighbouring tiles (which share halo and source data) meet in one L2.
@@ -165,7 +169,7 @@ __device__ inline float lu_m(int k) { return (EDGE && k < kEdge) ? kLuEdge.m[k] 
 template <bool EDGE>
 __device__ inline float lu_dinv(int k) { return (EDGE && k < kEdge) ? kLuEdge.dinv[k] : kMinf; }
 
-// Solve M y = b, M = tridiag(1/6, 2/3, 1/6), along one line of kLine values
+// Solve M y = b, M = tridiag(1/6, 2/3, 1/6), along one line of N values
 // v[] (registers), written as
 //     y = b - T^{-1} (D2 b),   T = 6 M = tridiag(1, 4, 1),  D2 b = b[k-1] - 2 b[k] + b[k+1]
 // (T = 6 I + D2, so 6 T^{-1} = I - T^{-1} D2).  The LU recursions of T then only
@@ -174,32 +178,61 @@ __device__ inline float lu_dinv(int k) { return (EDGE && k < kEdge) ? kLuEdge.di
 // mass a line carries is kept to ~1e-10 per step instead of ~1e-8.
 // Neighbours outside the line count as zero: exact at an open edge (the
 // truncated M), and a cut inside the lattice only disturbs the halo.
-// MASKED: the lattice line is shorter than kLine; v[k] is zero for k >= n
+// MASKED: the lattice line is shorter than N; v[k] is zero for k >= n
 // and the recursion ends at n (an open edge).  Otherwise every index
-// condition is a compile-time one.  The solution replaces v.
-template <bool EDGE, bool MASKED>
-__device__ inline void line_solve(float (&v)[kLine], int n) {
-    float z[kLine];
+// condition is a compile-time one.  The solution replaces v[LO..N); the
+// backward sweep stops at LO, below which the caller keeps nothing (the
+// values there are left as they were), so z[k < LO] and v[k < LO] are dead
+// after the forward sweep and hold no registers.
+template <int N, int LO, bool EDGE, bool MASKED>
+__device__ inline void line_solve(float (&v)[N], int n) {
+    float z[N];
     float acc = 0.0f;
 #pragma unroll
-    for (int k = 0; k < kLine; ++k) {
-        const float r = ((k > 0 ? v[k - 1] : 0.0f) + (k + 1 < kLine ? v[k + 1] : 0.0f)) - 2.0f * v[k];
+    for (int k = 0; k < N; ++k) {
+        const float r = ((k > 0 ? v[k - 1] : 0.0f) + (k + 1 < N ? v[k + 1] : 0.0f)) - 2.0f * v[k];
         acc = fmaf(-lu_m<EDGE>(k), acc, r);
         if (MASKED) acc = k < n ? acc : 0.0f;
         z[k] = acc;
     }
     float c = 0.0f;
 #pragma unroll
-    for (int k = kLine - 1; k >= 0; --k) {
+    for (int k = N - 1; k >= LO; --k) {
         c = (z[k] - c) * lu_dinv<EDGE>(k);
         v[k] -= c;
     }
 }
 
-// Start of the kLine window around a segment starting at s0 on an open axis
-// of n nodes: kHalo before the segment, shifted to lie inside [0, n) so that a
-// window near an edge ends exactly at it (0 when n < kLine).
-__device__ inline int open_window(int s0, int n) { return max(0, min(s0 - kHalo, n - kLine)); }
+// The same solve on a line that starts at an open edge (or is a whole short
+// line, MASKED) with the forward sweep's z of the first NL nodes kept in LDS
+// (zs[k * stride]) rather than in registers: not much more than one line of
+// registers is live, where v and z would take two.  For the few windows that need it; the backward sweep's LDS reads do not
+// depend on the recursion, so they are issued ahead of it.
+template <int N, int NL, bool MASKED>
+__device__ inline void line_solve_lds(float (&v)[N], int n, float* zs, int stride) {
+    float zr[N - NL];  // z of the nodes past the first NL
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const float r = ((k > 0 ? v[k - 1] : 0.0f) + (k + 1 < N ? v[k + 1] : 0.0f)) - 2.0f * v[k];
+        acc = fmaf(-lu_m<true>(k), acc, r);
+        if (MASKED) acc = k < n ? acc : 0.0f;
+        if (k < NL) zs[k * stride] = acc;
+        else zr[k - NL] = acc;
+    }
+    asm volatile("" ::: "memory");  // read z back from LDS (not forwarded from the stores)
+    float c = 0.0f;
+#pragma unroll
+    for (int k = N - 1; k >= 0; --k) {
+        c = ((k < NL ? zs[k * stride] : zr[k - NL]) - c) * lu_dinv<true>(k);
+        v[k] -= c;
+    }
+}
+
+// Start of the window of `line` nodes around a segment starting at s0 on an
+// open axis of n nodes: kHalo before the segment, shifted to lie inside
+// [0, n) so that a window near an edge ends exactly at it (0 when n < line).
+__device__ inline int open_window(int s0, int n, int line) { return max(0, min(s0 - kHalo, n - line)); }
 
 }  // namespace
 
@@ -588,29 +621,32 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
 // lane (line_solve: the LU recursions of T = tridiag(1,4,1),
 //   forward  z_k = r_k - m_k z_{k-1},   backward c_k = (z_k - c_{k+1}) / d_k,
 // with exact per-node (m_k, 1/d_k) on a line that starts at an open edge).
-// A workgroup (one wavefront) owns a kSeg x kSeg output tile and stages from b
-// the kLine x kLine window around it: the tile plus kHalo nodes on every side,
-// wrapped on a periodic axis and shifted to end at the edge on an open one.
-// Where the window is cut inside the lattice the recursions start from zero,
-// an error that decays by 2 - sqrt 3 per node and is ~7e-10 at the tile.
-// Lane r solves window row r along x in registers and puts it back in LDS;
-// lane c then solves window column c along p and writes the kept rows of the
-// kept columns.  The x-solved intermediate never leaves LDS.  For the FEL the
-// epilogue forms the FP64 bunching of the new state: a fixed-order per-tile
-// partial per tile (k_fel_field sums them).
+// The two factors commute, so the p solves go first.  A workgroup (one
+// wavefront) owns a kSegX x kSegP output tile inside the kLineX x kLineP
+// window around it: kHalo more nodes on every side, wrapped on a periodic
+// axis and shifted to end at the edge on an open one.  Where the window is
+// cut inside the lattice the recursions start from zero, an error that decays
+// by 2 - sqrt 3 per node and is ~7e-10 at the tile.
+//  p phase: lane c loads window column c of b straight into registers (each
+//    load instruction reads one row's kLineX consecutive nodes: two cache
+//    lines), solves it along p and puts the kept rows into LDS.
+//  x phase: lane r solves kept row r along x in LDS.
+//  out:     the kept columns of the kept rows go out, two rows per store.
+// The intermediate never leaves LDS (16.6 KB), and with at most 256 VGPRs
+// eight tiles are resident per compute unit: all 2048 tiles of a 2048^2
+// lattice at once.  For the FEL the write-out also forms the FP64 bunching
+// partials of the new state, per tile (k_fel_field sums them).
 // ---------------------------------------------------------------------------
-template <int K>
-__device__ inline void solve_line_kind(float (&v)[kLine], int n) {
-    if (K == 2) line_solve<true, true>(v, n);
-    else if (K == 1) line_solve<true, false>(v, n);
-    else line_solve<false, false>(v, n);
-}
-
-__global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
-    static_assert(kSolveThreads == kLine, "one window line per lane");
-    constexpr int ldw = kLine + 1;
-    __shared__ float lds[kLine * ldw];
-    __shared__ double2 s_eq[kSeg];  // FEL: e^{iq} of the tile's rows
+__global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_solve(LaunchArgs A) {
+    static_assert(kSolveThreads == kLineX && kSolveThreads == kSegP && kSegX * 2 == kSolveThreads,
+                  "p phase: a window column per lane; x phase: a kept row per lane; out: two rows per store");
+    // kept rows at pitch ldx: 16-byte aligned, and the 16-byte accesses of
+    // consecutive rows (x phase, lane = row) fall on disjoint banks
+    constexpr int ldx = kLineX + 4;
+    constexpr int kStageRows = kSegP;  // window rows staged in LDS (the rest in registers)
+    static_assert(kStageRows * kLineX <= kSegP * ldx, "the staged rows fit the LDS of the kept rows");
+    __shared__ float xs[kSegP * ldx];  // staged rows, then the kept rows p-solved, then x-solved in place
+    __shared__ double2 s_eq[kSegP];    // FEL: e^{iq} of the tile's rows
     __shared__ int s_d;
 
     for (int it = blockIdx.x; it < A.total; it += gridDim.x) {
@@ -622,109 +658,214 @@ __global__ __launch_bounds__(kSolveThreads) void k_solve(LaunchArgs A) {
         const int t = item - A.off[d];
         const int nx = I.push.nx, np = I.push.np;
         const bool periodic = I.push.x_periodic != 0;
-        const int tiles_x = (nx + kSeg - 1) / kSeg;
+        const int tiles_x = (nx + kSegX - 1) / kSegX;
         const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
-        const int X0 = txi * kSeg, tw = min(kSeg, nx - X0);
-        const int Y0 = tyi * kSeg, th = min(kSeg, np - Y0);
-        // windows of kLine nodes per axis (x unwrapped on a periodic axis)
-        const int wx = periodic ? X0 - kHalo : open_window(X0, nx);
-        const int nwx = periodic ? kLine : min(kLine, nx);
-        const int wp = open_window(Y0, np), nwp = min(kLine, np);
-        const int kind_x = periodic ? 0 : (nwx < kLine ? 2 : (wx == 0 ? 1 : 0));
-        const int kind_p = nwp < kLine ? 2 : (wp == 0 ? 1 : 0);
+        const int X0 = txi * kSegX, tw = min(kSegX, nx - X0);
+        const int Y0 = tyi * kSegP, th = min(kSegP, np - Y0);
+        // windows (x unwrapped on a periodic axis)
+        const int wx = periodic ? X0 - kHalo : open_window(X0, nx, kLineX);
+        const int nwx = periodic ? kLineX : min(kLineX, nx);
+        const int wp = open_window(Y0, np, kLineP), nwp = min(kLineP, np);
+        const int kind_p = nwp < kLineP ? 2 : (wp == 0 ? 1 : 0);
+        const int lo_p = Y0 - wp;  // the kept rows are window rows lo_p .. lo_p + th
         const int par = (I.parity0 + A.parity) & 1;
-        const float* __restrict__ src = I.b;
         gfloat_out* __restrict__ dst = as_global_out(I.w[par ^ 1]);
         const int lane = threadIdx.x;
 
         const bool fel = I.push.kind == kFel;
         if (fel && lane < th) s_eq[lane] = I.fel_eq[Y0 + lane];
-        // stage the window: lane = window column.  Every row is loaded straight
-        // into its LDS row (global_load_lds: no registers hold the data), all
-        // rows in flight; lanes past the window and rows past a short lattice
-        // are zero.
+
+        // p: lane = window column c (columns past a narrow open lattice are zero)
         {
-            int gc = wx + min(lane, nwx - 1);
-            if (periodic) gc = wrap_index(gc, nx, 1.0f / (float)nx);
-            const int rows = kind_p == 2 ? nwp : kLine;
-            if (lane < nwx) {
-                gfloat* p = as_global(src) + (size_t)wp * nx + gc;
-                for (int r = 0; r < rows; ++r)
-                    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(p + (size_t)r * nx),
-                                                     (__attribute__((address_space(3))) void*)(lds + r * ldw), 4, 0, 0);
-            } else {
-                for (int r = 0; r < rows; ++r) lds[r * ldw + lane] = 0.0f;
+            // stage the window: rows 0 .. kStageRows go straight into LDS, row k
+            // at xs + k kLineX (global_load_lds: one row's kLineX consecutive
+            // nodes per instruction, no registers hold the data), the rest into
+            // registers through a buffer resource based at the window's first
+            // row (the row's byte offset is wave-uniform, the lane's column
+            // offset 32 bits); all rows in flight, rows past a short lattice zero
+            float v[kLineP];
+            {
+                const int rows = kind_p == 2 ? nwp : kLineP;
+                const int rows_lds = min(rows, kStageRows);
+                int gc = wx + lane;
+                if (periodic) gc = wrap_index(gc, nx, 1.0f / (float)nx);
+                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                    (void*)(I.b + (size_t)wp * nx), (short)0, -1, kBufferWord3);
+                const int ub = gc * 4;         // < 2^18: a row has at most 2^16 nodes
+                const int row_bytes = nx * 4;  // k row_bytes < kLineP 2^18
+                if (lane < nwx) {
+                    gfloat* p = as_global(I.b) + (size_t)wp * nx + gc;
+                    for (int k = 0; k < rows_lds; ++k)
+                        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(p + (size_t)k * nx),
+                                                         (__attribute__((address_space(3))) void*)(xs + k * kLineX), 4, 0, 0);
+                    if (rows == kLineP) {
+#pragma unroll
+                        for (int k = kStageRows; k < kLineP; ++k)
+                            v[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, ub, k * row_bytes, 0));
+                    } else {
+#pragma unroll
+                        for (int k = kStageRows; k < kLineP; ++k)
+                            v[k] = k < rows ? __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, ub, k * row_bytes, 0)) : 0.0f;
+                    }
+                } else {
+                    for (int k = 0; k < rows_lds; ++k) xs[k * kLineX + lane] = 0.0f;
+#pragma unroll
+                    for (int k = kStageRows; k < kLineP; ++k) v[k] = 0.0f;
+                }
+                for (int k = rows_lds; k < kStageRows; ++k) xs[k * kLineX + lane] = 0.0f;
+                __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
             }
-            for (int r = rows; r < kLine; ++r) lds[r * ldw + lane] = 0.0f;
-            __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+#pragma unroll
+            for (int k = 0; k < kStageRows; ++k) v[k] = xs[k * kLineX + lane];
+            // Every lane has its column in registers before any kept row is
+            // written over the staging image (the LDS operations of one
+            // wavefront take effect in program order).
+            float* out = xs + lane;
+            if (kind_p == 0) {
+                line_solve<kLineP, kHalo, false, false>(v, nwp);
+                if (lo_p == kHalo) {
+#pragma unroll
+                    for (int r = 0; r < kSegP; ++r) out[r * ldx] = v[kHalo + r];
+                } else {
+                    const int lov = (int)in_vgpr((unsigned)lo_p);
+#pragma unroll
+                    for (int k = kHalo; k < kLineP; ++k)
+                        if ((unsigned)(k - lov) < (unsigned)kSegP) out[(k - lov) * ldx] = v[k];
+                }
+            } else if (kind_p == 1 && lo_p == 0 && th == kSegP) {
+                // a full window at the open edge that keeps its first kSegP
+                // rows: the halo's results are dead, so v[kSegP..] frees early
+                line_solve<kLineP, 0, true, false>(v, nwp);
+#pragma unroll
+                for (int r = 0; r < kSegP; ++r) out[r * ldx] = v[r];
+            } else {
+                // a short lattice (masked) or a window at the edge that keeps
+                // other rows: z goes to the staging image (this lane's column
+                // of it, b being in registers by now), and the kept rows are
+                // written once every z has been read back
+                if (kind_p == 2) line_solve_lds<kLineP, kStageRows, true>(v, nwp, xs + lane, kLineX);
+                else line_solve_lds<kLineP, kStageRows, false>(v, nwp, xs + lane, kLineX);
+#pragma unroll
+                for (int k = 0; k < kLineP; ++k)
+                    if ((unsigned)(k - lo_p) < (unsigned)th) out[(k - lo_p) * ldx] = v[k];
+            }
         }
         __syncthreads();
 
-        // x: lane = window row
+        // x: lane = kept row r, solved in place (rows past the tile are solved and dropped)
         {
-            float v[kLine];
-            float* row = lds + lane * ldw;
+            float v[kLineX];
+            float4* row = reinterpret_cast<float4*>(xs + lane * ldx);
 #pragma unroll
-            for (int k = 0; k < kLine; ++k) v[k] = row[k];
-            if (kind_x == 2) solve_line_kind<2>(v, nwx);
-            else if (kind_x == 1) solve_line_kind<1>(v, nwx);
-            else solve_line_kind<0>(v, nwx);
+            for (int q = 0; q < kLineX / 4; ++q) {
+                const float4 a = row[q];
+                v[4 * q] = a.x;
+                v[4 * q + 1] = a.y;
+                v[4 * q + 2] = a.z;
+                v[4 * q + 3] = a.w;
+            }
+            int q0 = 0, q1 = kLineX / 4;  // quads written back
+            if (periodic) {
+                line_solve<kLineX, kHalo, false, false>(v, kLineX);
+                q0 = kHalo / 4;
+                q1 = (kHalo + kSegX) / 4;
+            } else {
+                const int kind_x = nwx < kLineX ? 2 : (wx == 0 ? 1 : 0);
+                if (kind_x == 2) line_solve<kLineX, 0, true, true>(v, nwx);
+                else if (kind_x == 1) line_solve<kLineX, 0, true, false>(v, nwx);
+                else line_solve<kLineX, 0, false, false>(v, nwx);
+            }
 #pragma unroll
-            for (int k = 0; k < kLine; ++k) row[k] = v[k];
+            for (int q = 0; q < kLineX / 4; ++q)
+                if (q >= q0 && q < q1) row[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
         }
         __syncthreads();
 
-        // p: lane = window column; the kept rows of the kept columns go out
+        // out: the kept columns of the kept rows; FEL: the bunching sums
         const bool rk4 = fel && I.push.rk4;
         double acc_re = 0.0, acc_im = 0.0, acc1_re = 0.0, acc1_im = 0.0;
-        {
-            float v[kLine];
-            float* col = lds + lane;
-#pragma unroll
-            for (int k = 0; k < kLine; ++k) v[k] = col[k * ldw];
-            if (kind_p == 2) solve_line_kind<2>(v, nwp);
-            else if (kind_p == 1) solve_line_kind<1>(v, nwp);
-            else solve_line_kind<0>(v, nwp);
-            const int cx = lane - (X0 - wx);  // kept column, when in [0, tw)
-            if (cx >= 0 && cx < tw) {
-                const int gx = X0 + cx;
-                const int lo = Y0 - wp;  // the kept rows are window rows lo .. lo + th
-                gfloat_out* o = dst + (size_t)Y0 * nx + gx;
-                unsigned qo = in_vgpr(0u);  // running offset of the kept row (< kSeg rows x nx)
-                auto store = [&](int k) {
-                    o[qo] = v[k];
-                    qo += (unsigned)nx;
-                };
-                // FEL: the bunching sums first, in a loop with no stores, so that
-                // its table loads are not ordered behind the stores; the
-                // Runge-Kutta step also needs the sum at the lattice phases
-                double cre = 0.0, cim = 0.0, c1 = 0.0;
-                auto bunch = [&](int k) {
-                    const double2 e = s_eq[wp + k - Y0];  // times e^{-i q}
-                    cre += (double)v[k] * e.x;
-                    cim -= (double)v[k] * e.y;
-                    if (rk4) c1 += (double)v[k];
-                };
-                if (lo == kHalo && th == kSeg) {
+        const int lo_x = X0 - wx;  // the kept columns are window columns lo_x .. lo_x + tw
+        if ((nx & 3) == 0 && (lo_x & 3) == 0) {
+            // lane = column quad q of rows (lane / kQuads) + kRowsPer i: 16-byte
+            // LDS reads and stores, kRowsPer rows per store (rows of b and of
+            // the tile start 16-byte aligned, and tw is a multiple of four)
+            constexpr int kQuads = kSegX / 4, kRowsPer = kSolveThreads / kQuads;
+            const int q = lane & (kQuads - 1), r0 = lane / kQuads;
+            if (4 * q < tw) {
+                const float* in = xs + r0 * ldx + lo_x + 4 * q;
+                gfloat_out* o = dst + (size_t)(Y0 + r0) * nx + X0 + 4 * q;
+                unsigned qo = in_vgpr(0u);  // running offset of the row (< kSegP rows x nx)
+                double cre[4] = {0.0, 0.0, 0.0, 0.0}, cim[4] = {0.0, 0.0, 0.0, 0.0}, c1[4] = {0.0, 0.0, 0.0, 0.0};
+                auto row = [&](int i) {
+                    const float4 y = *reinterpret_cast<const float4*>(in + i * kRowsPer * ldx);
+                    *reinterpret_cast<VP_GLOBAL float4*>(o + qo) = y;
+                    qo += (unsigned)(kRowsPer * nx);
                     if (fel) {
+                        const double2 e = s_eq[r0 + kRowsPer * i];  // times e^{-i q}
+                        const float yy[4] = {y.x, y.y, y.z, y.w};
 #pragma unroll
-                        for (int k = kHalo; k < kHalo + kSeg; ++k) bunch(k);
+                        for (int j = 0; j < 4; ++j) {
+                            cre[j] += (double)yy[j] * e.x;
+                            cim[j] -= (double)yy[j] * e.y;
+                            if (rk4) c1[j] += (double)yy[j];
+                        }
                     }
+                };
+                const int rows = (th - r0 + kRowsPer - 1) / kRowsPer;  // this lane's kept rows
+                if (rows == kSegP / kRowsPer) {
 #pragma unroll
-                    for (int k = kHalo; k < kHalo + kSeg; ++k) store(k);
+                    for (int i = 0; i < kSegP / kRowsPer; ++i) row(i);
                 } else {
-                    const int lov = (int)in_vgpr((unsigned)lo);
-                    if (fel) {
-#pragma unroll
-                        for (int k = 0; k < kLine; ++k)
-                            if ((unsigned)(k - lov) < (unsigned)th) bunch(k);
-                    }
-#pragma unroll
-                    for (int k = 0; k < kLine; ++k)
-                        if ((unsigned)(k - lov) < (unsigned)th) store(k);
+                    for (int i = 0; i < rows; ++i) row(i);
                 }
                 if (fel) {
-                    const double2 e = I.fel_ex[gx];  // times e^{-i phi}
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const double2 e = I.fel_ex[X0 + 4 * q + j];  // times e^{-i phi}
+                        acc_re += cre[j] * e.x + cim[j] * e.y;
+                        acc_im += cim[j] * e.x - cre[j] * e.y;
+                        acc1_re += c1[j] * e.x;
+                        acc1_im -= c1[j] * e.y;
+                    }
+                }
+            }
+        } else {
+            // lane = kept column c of rows (lane / kSegX) + 2 i, two rows per store
+            const int c = lane & (kSegX - 1), r0 = lane / kSegX;
+            if (c < tw) {
+                const float* in = xs + r0 * ldx + lo_x + c;
+                gfloat_out* o = dst + (size_t)(Y0 + r0) * nx + X0 + c;
+                unsigned qo = in_vgpr(0u);  // running offset of the row (< kSegP rows x nx)
+                double cre = 0.0, cim = 0.0, c1 = 0.0;
+                const int rows = (th - r0 + 1) >> 1;  // this lane's kept rows
+                if (rows == kSegP / 2) {
+#pragma unroll
+                    for (int i = 0; i < kSegP / 2; ++i) {
+                        const float y = in[2 * i * ldx];
+                        o[qo] = y;
+                        qo += 2u * (unsigned)nx;
+                        if (fel) {
+                            const double2 e = s_eq[r0 + 2 * i];  // times e^{-i q}
+                            cre += (double)y * e.x;
+                            cim -= (double)y * e.y;
+                            if (rk4) c1 += (double)y;
+                        }
+                    }
+                } else {
+                    for (int i = 0; i < rows; ++i) {
+                        const float y = in[2 * i * ldx];
+                        o[qo] = y;
+                        qo += 2u * (unsigned)nx;
+                        if (fel) {
+                            const double2 e = s_eq[r0 + 2 * i];
+                            cre += (double)y * e.x;
+                            cim -= (double)y * e.y;
+                            if (rk4) c1 += (double)y;
+                        }
+                    }
+                }
+                if (fel) {
+                    const double2 e = I.fel_ex[X0 + c];  // times e^{-i phi}
                     acc_re = cre * e.x + cim * e.y;
                     acc_im = cim * e.x - cre * e.y;
                     acc1_re = c1 * e.x;
@@ -816,8 +957,8 @@ __global__ __launch_bounds__(kFieldThreads) void k_fel_field(LaunchArgs A) {
 
 // ---------------------------------------------------------------------------
 // k_fel_stage: the bunching at the phases of the Runge-Kutta step's stages 3
-// and 4 (FEL only), FP64, one per-tile partial per solve tile of 32 x 32 nodes
-// (one wavefront: lane l takes column l mod 32 and every other row).  With
+// and 4 (FEL only), FP64, one per-tile partial per solve tile of kSegX x kSegP
+// nodes (one wavefront: lane l takes column l mod kSegX and every other row).  With
 // k1 = a1 cos phi + b1 sin phi and k2 = a2 cos psi2 + b2 sin psi2 the slopes of
 // stages 1 and 2 (fields A1 = A, A2 = A + dz/2 b1), the phases are
 // psi3 = phi + q + dz^2/4 k1 and psi4 = phi + 2 q + dz^2/2 k2, q the half drift
@@ -832,10 +973,10 @@ __global__ __launch_bounds__(kStageThreads) void k_fel_stage(LaunchArgs A) {
         if (I.push.kind != kFel || !I.push.rk4) continue;
         const int t = item - A.off[d];
         const int nx = I.push.nx, np = I.push.np;
-        const int tiles_x = (nx + kSeg - 1) / kSeg;
+        const int tiles_x = (nx + kSegX - 1) / kSegX;
         const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
-        const int X0 = txi * kSeg, tw = min(kSeg, nx - X0);
-        const int Y0 = tyi * kSeg, th = min(kSeg, np - Y0);
+        const int X0 = txi * kSegX, tw = min(kSegX, nx - X0);
+        const int Y0 = tyi * kSegP, th = min(kSegP, np - Y0);
         const int par = (I.parity0 + A.parity) & 1;
         const float* __restrict__ w = I.w[par];
         const double* st = I.fel_state;
@@ -846,12 +987,13 @@ __global__ __launch_bounds__(kStageThreads) void k_fel_stage(LaunchArgs A) {
         const double a2r = st[kA] + 0.5 * h * b1r - sg * b2i, a2i = st[kA + 1] + 0.5 * h * b1i + sg * b2r;
         const double t3 = 0.25 * h * h, t4 = 0.5 * h * h;
         double s3r = 0.0, s3i = 0.0, s4r = 0.0, s4i = 0.0;
-        const int col = lane & 31;
+        static_assert(kStageThreads == 2 * kSegX, "a tile column and a row parity per lane");
+        const int col = lane & (kSegX - 1);
         if (col < tw) {
             const int gx = X0 + col;
             const double2 ex = I.fel_ex[gx];
             double cre = 0.0, cim = 0.0;
-            for (int r = lane >> 5; r < th; r += 2) {
+            for (int r = lane / kSegX; r < th; r += 2) {
                 const int j = Y0 + r;
                 const double wk = (double)w[(size_t)j * nx + gx];
                 const double2 eq = I.fel_eq[j];
