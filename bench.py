@@ -190,6 +190,8 @@ def main():
     ap.add_argument("--fel-steps", type=int, default=2000)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--serve-overload", type=float, default=1.2,
+                    help="a second served run with arrivals above the batched capacity (0: skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=4.0)
     ap.add_argument("--tiles", default=None,
                     help="deposit launch shape COLSxROWSxTHREADS for the tuned path instead of autotuning "
@@ -289,6 +291,10 @@ def main():
         line["served"] = bench_served(binding, args.serve_requests, args.serve_load,
                                       line["batched"]["value"], args.serve_budget_gib)
         log(f"served: {line['served']}")
+        if args.serve_overload > 0:
+            line["served_overload"] = bench_served(binding, args.serve_requests, args.serve_overload,
+                                                   line["batched"]["value"], args.serve_budget_gib)
+            log(f"served_overload: {line['served_overload']}")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inst, args.cpu_steps)
     print(json.dumps(line), flush=True)

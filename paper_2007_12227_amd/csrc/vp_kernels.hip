@@ -915,6 +915,18 @@ __global__ __launch_bounds__(kFieldThreads) void k_fel_field(LaunchArgs A) {
     __shared__ double s_red[kPartialsPerTile][kFieldThreads / 64];
     const VpInst& I = A.inst[blockIdx.x];
     if (I.push.kind != kFel || (A.mode == 1 && !I.push.rk4)) return;
+    // the field state the update needs, loaded while the partials are summed
+    double* st = I.fel_state;
+    double n0 = 0.0, a[2] = {0.0, 0.0}, bn[2] = {0.0, 0.0}, b1[2] = {0.0, 0.0}, an[2] = {0.0, 0.0};
+    if (threadIdx.x == 0) {
+        n0 = st[kN0];
+        for (int c = 0; c < 2; ++c) {
+            a[c] = st[kA + c];
+            bn[c] = st[kBn + c];
+            b1[c] = st[kB1 + c];
+            an[c] = st[kAn + c];
+        }
+    }
     double acc[kPartialsPerTile] = {0.0, 0.0, 0.0, 0.0};
     for (int k = threadIdx.x; k < I.k2_tiles; k += kFieldThreads)
         for (int c = 0; c < kPartialsPerTile; ++c) acc[c] += I.partials[kPartialsPerTile * k + c];
@@ -929,25 +941,24 @@ __global__ __launch_bounds__(kFieldThreads) void k_fel_field(LaunchArgs A) {
             acc[c] = 0.0;
             for (int k = 0; k < kFieldThreads / 64; ++k) acc[c] += s_red[c][k];
         }
-        double* st = I.fel_state;
-        const double inv_n0 = 1.0 / st[kN0], h = I.fel_dz;
+        const double inv_n0 = 1.0 / n0, h = I.fel_dz;
         if (A.mode == 1) {
-            st[kB3] = acc[0] * inv_n0;
-            st[kB3 + 1] = acc[1] * inv_n0;
-            st[kB4] = acc[2] * inv_n0;
-            st[kB4 + 1] = acc[3] * inv_n0;
-            for (int c = 0; c < 2; ++c)
-                st[kAn + c] = st[kA + c] + h / 6.0 * (st[kB1 + c] + 2.0 * st[kBn + c] + 2.0 * st[kB3 + c] + st[kB4 + c]);
+            const double b3[2] = {acc[0] * inv_n0, acc[1] * inv_n0}, b4[2] = {acc[2] * inv_n0, acc[3] * inv_n0};
+            for (int c = 0; c < 2; ++c) {
+                st[kB3 + c] = b3[c];
+                st[kB4 + c] = b4[c];
+                st[kAn + c] = a[c] + h / 6.0 * (b1[c] + 2.0 * bn[c] + 2.0 * b3[c] + b4[c]);
+            }
             return;
         }
         if (I.push.rk4) {
-            st[kA] = st[kAn];
-            st[kA + 1] = st[kAn + 1];
+            st[kA] = an[0];
+            st[kA + 1] = an[1];
             st[kB1] = acc[2] * inv_n0;
             st[kB1 + 1] = acc[3] * inv_n0;
         } else {
-            st[kA] += h * st[kBn];
-            st[kA + 1] += h * st[kBn + 1];
+            st[kA] = a[0] + h * bn[0];
+            st[kA + 1] = a[1] + h * bn[1];
         }
         st[kBn] = acc[0] * inv_n0;
         st[kBn + 1] = acc[1] * inv_n0;
@@ -955,18 +966,35 @@ __global__ __launch_bounds__(kFieldThreads) void k_fel_field(LaunchArgs A) {
     }
 }
 
+// sin and cos of x: for |x| < 2^-6 by their Taylor series to the x^9 and x^10
+// terms (the first omitted terms are below 2^-70 relative), else sincos.  The
+// Runge-Kutta stage angles dz^2/2 k are that small unless dz or the field is large.
+__device__ inline void sincos_small(double x, double* s, double* c) {
+    if (fabs(x) < 0.015625) {
+        const double x2 = x * x;
+        *s = x * (1.0 + x2 * (-1.0 / 6.0 + x2 * (1.0 / 120.0 + x2 * (-1.0 / 5040.0 + x2 * (1.0 / 362880.0)))));
+        *c = 1.0 + x2 * (-0.5 + x2 * (1.0 / 24.0 + x2 * (-1.0 / 720.0 + x2 * (1.0 / 40320.0 + x2 * (-1.0 / 3628800.0)))));
+    } else {
+        sincos(x, s, c);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_fel_stage: the bunching at the phases of the Runge-Kutta step's stages 3
 // and 4 (FEL only), FP64, one per-tile partial per solve tile of kSegX x kSegP
-// nodes (one wavefront: lane l takes column l mod kSegX and every other row).  With
-// k1 = a1 cos phi + b1 sin phi and k2 = a2 cos psi2 + b2 sin psi2 the slopes of
-// stages 1 and 2 (fields A1 = A, A2 = A + dz/2 b1), the phases are
-// psi3 = phi + q + dz^2/4 k1 and psi4 = phi + 2 q + dz^2/2 k2, q the half drift
-// of the node's row.  k1 depends on the column only, so stage 3's sum is a
-// column sum of w e^{-i q} turned by e^{-i(phi + dz^2/4 k1)}.
+// nodes.  A workgroup of four wavefronts per tile: thread t takes column
+// t mod kSegX and rows t / kSegX + kRowStep i; the sums are reduced in a fixed
+// order (shuffle tree per wavefront, then the wavefronts in turn).  With
+// k1 = a1 cos phi + b1 sin phi and k2 = a2 cos psi2 + b2 sin psi2 the slopes
+// of stages 1 and 2 (fields A1 = A, A2 = A + dz/2 b1), the phases are
+// psi3 = phi + q + dz^2/4 k1 and psi4 = phi + 2 q + dz^2/2 k2, q the half
+// drift of the node's row.  k1 depends on the column only, so stage 3's sum
+// is a column sum of w e^{-i q} turned by e^{-i(phi + dz^2/4 k1)}.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kStageThreads) void k_fel_stage(LaunchArgs A) {
-    const int lane = threadIdx.x;
+    constexpr int kWaves = kStageThreads / 64, kRowStep = kStageThreads / kSegX;
+    __shared__ double s_red[kWaves][4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     for (int item = blockIdx.x; item < A.total; item += gridDim.x) {
         const int d = __builtin_amdgcn_readfirstlane(find_instance(A.off, A.ninst, item));
         const VpInst& I = A.inst[d];
@@ -986,14 +1014,13 @@ __global__ __launch_bounds__(kStageThreads) void k_fel_stage(LaunchArgs A) {
         const double a1r = st[kA] - sg * b1i, a1i = st[kA + 1] + sg * b1r;
         const double a2r = st[kA] + 0.5 * h * b1r - sg * b2i, a2i = st[kA + 1] + 0.5 * h * b1i + sg * b2r;
         const double t3 = 0.25 * h * h, t4 = 0.5 * h * h;
-        double s3r = 0.0, s3i = 0.0, s4r = 0.0, s4i = 0.0;
-        static_assert(kStageThreads == 2 * kSegX, "a tile column and a row parity per lane");
-        const int col = lane & (kSegX - 1);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};  // stage 3 (re, im), stage 4 (re, im)
+        const int col = tid & (kSegX - 1);
         if (col < tw) {
             const int gx = X0 + col;
             const double2 ex = I.fel_ex[gx];
             double cre = 0.0, cim = 0.0;
-            for (int r = lane / kSegX; r < th; r += 2) {
+            for (int r = tid / kSegX; r < th; r += kRowStep) {
                 const int j = Y0 + r;
                 const double wk = (double)w[(size_t)j * nx + gx];
                 const double2 eq = I.fel_eq[j];
@@ -1003,33 +1030,31 @@ __global__ __launch_bounds__(kStageThreads) void k_fel_stage(LaunchArgs A) {
                 const double c2 = ex.x * eq.x - ex.y * eq.y, s2 = ex.y * eq.x + ex.x * eq.y;
                 const double k2 = -2.0 * (a2r * c2 - a2i * s2);
                 double sn, cs;
-                sincos(t4 * k2, &sn, &cs);
+                sincos_small(t4 * k2, &sn, &cs);
                 // e^{i psi4} = e^{i psi2} e^{i q} e^{i t4 k2}
                 const double c2q = c2 * eq.x - s2 * eq.y, s2q = s2 * eq.x + c2 * eq.y;
                 const double c4 = c2q * cs - s2q * sn, s4 = s2q * cs + c2q * sn;
-                s4r += wk * c4;
-                s4i -= wk * s4;
+                acc[2] += wk * c4;
+                acc[3] -= wk * s4;
             }
             const double k1 = -2.0 * (a1r * ex.x - a1i * ex.y);
             double sn, cs;
-            sincos(t3 * k1, &sn, &cs);
+            sincos_small(t3 * k1, &sn, &cs);
             const double c3 = ex.x * cs - ex.y * sn, s3 = ex.y * cs + ex.x * sn;  // e^{i(phi + t3 k1)}
-            s3r = cre * c3 + cim * s3;
-            s3i = cim * c3 - cre * s3;
+            acc[0] = cre * c3 + cim * s3;
+            acc[1] = cim * c3 - cre * s3;
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            s3r += __shfl_down(s3r, o);
-            s3i += __shfl_down(s3i, o);
-            s4r += __shfl_down(s4r, o);
-            s4i += __shfl_down(s4i, o);
+        for (int o = 32; o > 0; o >>= 1)
+            for (int c = 0; c < 4; ++c) acc[c] += __shfl_down(acc[c], o);
+        if (lane == 0)
+            for (int c = 0; c < 4; ++c) s_red[wid][c] = acc[c];
+        __syncthreads();
+        if (tid < 4) {
+            double v = 0.0;
+            for (int k = 0; k < kWaves; ++k) v += s_red[k][tid];
+            I.partials[kPartialsPerTile * t + tid] = v;
         }
-        if (lane == 0) {
-            double* pt = I.partials + kPartialsPerTile * t;
-            pt[0] = s3r;
-            pt[1] = s3i;
-            pt[2] = s4r;
-            pt[3] = s4i;
-        }
+        __syncthreads();
     }
 }
 

@@ -113,6 +113,32 @@ def test_one_step_small_lattices(B, nx, np_):
     assert oracle.rel_l1(got, ref) <= 1e-5
 
 
+@pytest.mark.parametrize("nx,np_", [(80, 96), (70, 80), (100, 97), (64, 200), (96, 160)])
+def test_one_step_solve_window_paths(B, nx, np_):
+    """Lattices whose momentum lines take each of the solve's window cases: a
+    whole line shorter than a window (70x80), a line of exactly one window
+    whose second tile keeps rows 64..95 (80x96), a window shifted to end at the
+    top edge (100x97), interior windows (64x200, 96x160)."""
+    x, p = pendulum_axes(nx, np_)
+    w = (gaussian(x, p, 0.4, -0.3, 0.7) + 1e-3 * rng(36).random((np_, nx))).astype(np.float32)
+    ham = Hamiltonian(H_PENDULUM, a=1.1)
+    got, _ = gpu_run(B, x, p, ham, w, 0.06, 1, (32, 16))
+    ref = one_step_ref(x, p, ham, w, 0.06)
+    assert oracle.rel_l1(got, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("nx,np_", [(40, 96), (64, 80), (100, 130), (130, 64)])
+def test_one_step_open_x_window_paths(B, nx, np_):
+    """The exact rotation needs an open x axis: x lines shorter than a window,
+    exactly one window, and windows shifted to end at either edge."""
+    x, p = Axis(-4, 4, nx, False), Axis(-4, 4, np_, False)
+    ham = Hamiltonian(H_SHO_EXACT, omega=1.0)
+    w = (gaussian(x, p, 0.8, -0.4, 0.7) + 1e-3 * rng(37).random((np_, nx))).astype(np.float32)
+    got, _ = gpu_run(B, x, p, ham, w, 0.3, 1, (32, 16))
+    ref = one_step_ref(x, p, ham, w, 0.3)
+    assert oracle.rel_l1(got, ref) <= 1e-5
+
+
 def test_graph_and_plain_launches_agree(B):
     inst = pendulum_gaussian(128)
     w32 = inst.w0.astype(np.float32)
