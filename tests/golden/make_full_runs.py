@@ -10,6 +10,7 @@ relative L1 distance of the FP32-state run (state rounded to float after every
 step) from the FP64 run: the floor any implementation with FP32 state reaches.
 """
 import argparse
+import dataclasses
 import os
 import sys
 import time
@@ -20,13 +21,21 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
-from paper_2007_12227_amd.inputs import fel_gaussian, pendulum_band, pendulum_gaussian  # noqa: E402
+from paper_2007_12227_amd.inputs import FEL_RK4, fel_gaussian, pendulum_band, pendulum_gaussian  # noqa: E402
+
+
+def fel_rk4(inst):
+    return dataclasses.replace(inst, ham=dataclasses.replace(inst.ham, integrator=FEL_RK4))
+
 
 WORKLOADS = {
     # name: (instance factory, checkpoints, sample stride)
     "pendulum_gaussian_128": (lambda: pendulum_gaussian(128), (1, 100, 200), 1),
     "pendulum_band_2048": (lambda: pendulum_band(2048), (1, 500, 1000), 16),
     "fel_gaussian_1024": (lambda: fel_gaussian(1024), (1, 500, 1000, 1500, 2000), 8),
+    # the same start advanced by the classical Runge-Kutta integrator, through the
+    # exponential growth (before saturation)
+    "fel_gaussian_1024_rk4": (lambda: fel_rk4(fel_gaussian(1024)), (1, 250, 500), 8),
 }
 
 

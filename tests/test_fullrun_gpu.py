@@ -3,13 +3,14 @@ the benchmark times (autotuned tiles, steps replayed from HIP graphs), against
 strided samples of the FP64 oracle's run (tests/golden/make_full_runs.py).
 Bar: relative L1 <= 1e-4 on the sample; the FP32-storage floor of the same
 run (oracle with its state rounded to float every step) is printed beside it."""
+import dataclasses
 import os
 
 import numpy as np
 import pytest
 
 import oracle
-from paper_2007_12227_amd.inputs import fel_gaussian, pendulum_band, pendulum_gaussian
+from paper_2007_12227_amd.inputs import FEL_RK4, fel_gaussian, pendulum_band, pendulum_gaussian
 
 pytestmark = pytest.mark.gpu
 
@@ -94,3 +95,11 @@ def test_full_run_fel_gaussian_1024(B):
     early, late = run_against_golden(B, fel_gaussian(1024), "fel_gaussian_1024", chaotic_after=min(chaotic) - 1)
     assert early <= 1e-4
     assert late <= 1e-4
+
+
+def test_full_run_fel_gaussian_1024_rk4(B):
+    """The 1024^2 FEL start advanced by the classical Runge-Kutta integrator
+    through the exponential growth (500 steps), against the oracle's run."""
+    inst = fel_gaussian(1024)
+    inst = dataclasses.replace(inst, ham=dataclasses.replace(inst.ham, integrator=FEL_RK4))
+    assert run_against_golden(B, inst, "fel_gaussian_1024_rk4") <= 1e-4

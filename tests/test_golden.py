@@ -23,7 +23,7 @@ def test_stored_pendulum_gaussian_128_matches_oracle():
 
 
 def test_stored_fixtures_are_consistent():
-    for name in ("pendulum_band_2048", "fel_gaussian_1024"):
+    for name in ("pendulum_band_2048", "fel_gaussian_1024", "fel_gaussian_1024_rk4"):
         ref = np.load(os.path.join(GOLDEN, f"oracle_{name}.npz"))
         stride = int(ref["stride"])
         for s in ref["steps"]:
