@@ -147,14 +147,16 @@ int vp_set_hamiltonian(vp_grid* g, const vp_hamiltonian* h);
 
 /* Set the weights w (n_p*n_x floats; device pointer if on_device, else host).
  * Records N0 = sum w (FP64) and max|w| (the deposit's fixed-point scale),
- * clears the range flag and resets the step counter. */
+ * clears the range flag and resets the step counter.  VP_ENONFINITE if a
+ * weight is NaN or infinite (the grid then holds no density). */
 int vp_set_density(vp_grid* g, const float* w, int32_t on_device);
 
 /* Copy the current weights out (n_p*n_x floats). */
 int vp_get_density(vp_grid* g, float* w, int32_t on_device);
 
 /* Advance nsteps steps of size dt (dz for the FEL) on the grid's stream.
- * VP_ESTATE if no density or Hamiltonian has been set. */
+ * VP_ESTATE if no density or Hamiltonian has been set, or for the FEL if the
+ * initial weights sum to zero (N0 normalises the bunching, eq. 13c). */
 int vp_step(vp_grid* g, double dt, int64_t nsteps);
 
 /* Diagnostics of the current state; waits for the stream. */

@@ -418,6 +418,8 @@ int prepare(vp_grid* g, double dt) {
     if (!g->has_ham || !g->has_density)
         return fail(VP_ESTATE, "set the Hamiltonian and the density before stepping");
     if (!isfinite(dt)) return fail(VP_EINVAL, "dt must be finite");
+    if (g->ham.kind == VP_H_FEL && !(g->N0 != 0.0))
+        return fail(VP_ESTATE, "the FEL needs a nonzero sum of the initial weights (N0 normalises the bunching)");
     if (!g->plan_valid || g->plan_dt != dt) {
         int rc = plan(g, dt);
         if (rc) return rc;
@@ -532,6 +534,11 @@ int vp_set_density(vp_grid* g, const float* w, int32_t on_device) {
     double m[kMoments];
     HIP_TRY(hipMemcpyAsync(m, g->at<double>(g->L.moments), sizeof m, hipMemcpyDeviceToHost, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
+    if (m[9] > 0.0) {
+        // the deposit's fixed-point taps would drop a non-finite weight silently
+        g->has_density = false;
+        return fail(VP_ENONFINITE, "%lld non-finite weights in the density", (long long)m[9]);
+    }
     g->N0 = m[0];
     {
         // fixed-point scale of the deposit cell sums: 2^(40 - e), max|w0| < 2^e

@@ -1,0 +1,117 @@
+"""Degenerate and extreme inputs on the GPU, through the C interface: an empty
+(all-zero) density, no steps, no motion, axes at the largest supported node
+count, a non-finite weight, and an FEL whose weights sum to zero."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_12227_amd.inputs import (H_FEL, H_PENDULUM, H_SHO_EXACT, Axis, Hamiltonian, fel_gaussian,
+                                         gaussian, pendulum_axes, rng)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2007_12227_amd import binding
+    binding.lib()
+    return binding
+
+
+def grid(B, x, p, ham, w):
+    g = B.Grid(x, p)
+    g.set_hamiltonian(ham)
+    g.set_density(np.ascontiguousarray(w, dtype=np.float32))
+    return g
+
+
+def test_zero_density_stays_zero(B):
+    x, p = pendulum_axes(96, 80)
+    g = grid(B, x, p, Hamiltonian(H_PENDULUM, a=1.0), np.zeros((80, 96)))
+    g.step(0.05, 3)
+    assert not np.any(g.density())
+    m = g.moments()
+    assert m["sum_w"] == 0.0 and m["step"] == 3
+    g.close()
+
+
+def test_zero_steps_leave_the_state(B):
+    x, p = pendulum_axes(96, 80)
+    w = (gaussian(x, p, 0.2, 0.4, 0.5) + 1e-3 * rng(60).random((80, 96))).astype(np.float32)
+    g = grid(B, x, p, Hamiltonian(H_PENDULUM, a=1.0), w)
+    g.step(0.05, 0)
+    assert np.array_equal(g.density(), w)
+    assert g.moments()["step"] == 0
+    g.close()
+
+
+@pytest.mark.parametrize("kind", [H_PENDULUM, H_SHO_EXACT])
+def test_no_motion_is_identity(B, kind):
+    """dt = 0: every node deposits onto itself, b = M w, and the solve returns
+    w (the truncated mass matrix at open edges included)."""
+    if kind == H_SHO_EXACT:
+        x, p = Axis(-4, 4, 100, False), Axis(-4, 4, 130, False)
+        ham = Hamiltonian(kind, omega=1.0)
+    else:
+        x, p = pendulum_axes(100, 130)
+        ham = Hamiltonian(kind, a=1.0)
+    w = (0.5 + rng(61).random((130, 100))).astype(np.float32)
+    g = grid(B, x, p, ham, w)
+    g.step(0.0, 1)
+    got = g.density().astype(np.float64)
+    g.close()
+    assert oracle.rel_l1(got, w.astype(np.float64)) <= 1e-6
+
+
+@pytest.mark.parametrize("nx,np_", [(1 << 16, 4), (4, 1 << 16)])
+def test_largest_axis(B, nx, np_):
+    """An axis at the largest node count the library accepts (2^16), the other
+    at the smallest (4): one step against the oracle."""
+    x, p = pendulum_axes(nx, np_)
+    w = (0.5 + rng(62).random((np_, nx))).astype(np.float32)
+    ham = Hamiltonian(H_PENDULUM, a=0.7)
+    g = grid(B, x, p, ham, w)
+    g.step(0.01, 1)
+    got = g.density().astype(np.float64)
+    g.close()
+    ref = oracle.run(x, p, ham, w.astype(np.float64), 0.01, 1).w
+    assert oracle.rel_l1(got, ref) <= 1e-5
+
+
+def test_axis_beyond_the_largest_is_refused(B):
+    x, p = pendulum_axes((1 << 16) + 1, 4)
+    with pytest.raises(B.VpError) as e:
+        B.Grid(x, p)
+    assert e.value.code in (B.VP_EINVAL, B.VP_ENOMEM)
+
+
+def test_nonfinite_weight_is_refused(B):
+    """A NaN or infinite weight is refused when the density is set (the
+    deposit's fixed-point taps would otherwise drop it without a trace), and
+    the grid holds no density afterwards."""
+    x, p = pendulum_axes(96, 80)
+    for bad in (np.nan, np.inf):
+        w = (0.5 + rng(63).random((80, 96))).astype(np.float32)
+        w[40, 50] = bad
+        g = B.Grid(x, p)
+        g.set_hamiltonian(Hamiltonian(H_PENDULUM, a=1.0))
+        with pytest.raises(B.VpError) as e:
+            g.set_density(w)
+        assert e.value.code == B.VP_ENONFINITE
+        with pytest.raises(B.VpError) as e:
+            g.step(0.05, 1)
+        assert e.value.code == B.VP_ESTATE
+        g.close()
+
+
+def test_fel_with_zero_weight_sum_is_refused(B):
+    """N0 = sum of the initial weights normalises the bunching (eq. 13c); the
+    FEL cannot step a beam whose weights sum to zero."""
+    inst = fel_gaussian(64, 1, npp=64)
+    g = grid(B, inst.x, inst.p, Hamiltonian(H_FEL, A_re=1e-3), np.zeros((64, 64)))
+    with pytest.raises(B.VpError) as e:
+        g.step(inst.dt, 1)
+    assert e.value.code == B.VP_ESTATE
+    g.close()
