@@ -317,24 +317,27 @@ __device__ inline void deposit_node(long long* acc, int j, int ii, float w, floa
     }
 }
 
-// The box's sources s = r bw + c, handed out to the wavefronts in chunks of
-// 64 kU consecutive sources from an LDS counter: a wave that runs ahead takes
-// more chunks, so the waves of a tile finish together (a static split leaves
-// them waiting at the barrier for the slowest one).  Lane l takes sources
-// c0 + l + 64 h of chunk c0.  COL: 0 open x axis; 1 periodic, box within
-// [-nx, 2 nx) (one correction per side); 2 periodic, general wrap.  Kind and
-// wrap mode are template parameters, so the loop body is one basic block,
-// free of per-node branches.
-constexpr int kU = 4;            // sources per lane per chunk, their loads all in flight
-constexpr int kChunk = 64 * kU;  // sources per chunk
+// The box's sources go to the wavefronts in chunks claimed from an LDS
+// counter: a wave that runs ahead takes more chunks, so the waves of a tile
+// finish together (a static split leaves them waiting at the barrier for the
+// slowest one).  The unit of work is a column of kU consecutive box rows: unit
+// u = q bw + c covers rows kU q .. kU q + kU of box column c.  A chunk is 64
+// consecutive units, one per lane, so no lane idles but in the last chunk (and
+// past the box's last row); a lane wraps its column and reads its push table
+// once for its kU sources, and neighbouring lanes read neighbouring columns of
+// the same rows.  COL: 0 open x axis; 1 periodic, box within [-nx, 2 nx) (one
+// correction per side); 2 periodic, general wrap.  Kind and wrap mode are
+// template parameters, so the loop body is one basic block, free of per-node
+// branches.
+constexpr int kU = 4;  // sources (rows) per unit
 
 struct SourceScan {
     long long* acc;
-    int* next;  // LDS: start of the next unclaimed chunk
+    int* next;  // LDS: the first unclaimed unit
     gfloat* w;
     gfloat4* tab_x;
     gfloat4* tab_p;
-    int nx, bx0, by0, bw, nsrc;
+    int nx, bx0, by0, bw, bh, nunits;
     float inv_nx, scale, alpha, beta, kd;
     double inv_bw;
     int X0, Y0, tw, th, ldw;
@@ -349,9 +352,8 @@ __device__ inline void scan_sources(const SourceScan& S) {
     settle(w_g);
     settle(tab_x);
     settle(tab_p);
-    const int nx = S.nx, bw = S.bw, nsrc = S.nsrc;
+    const int nx = S.nx, bw = S.bw, bh = S.bh, nunits = S.nunits;
     const int lane = (int)(threadIdx.x & 63);
-    const int dr = 64 / bw, dc = 64 - dr * bw;  // step between a lane's sources
     auto column = [&](int iu) {
         if (COL == 0) return iu;
         if (COL == 1) return iu + (iu < 0 ? nx : 0) - (iu >= nx ? nx : 0);
@@ -359,35 +361,32 @@ __device__ inline void scan_sources(const SourceScan& S) {
     };
     for (;;) {
         int claim = 0;
-        if (lane == 0) claim = atomicAdd(S.next, kChunk);
-        const int c0 = __builtin_amdgcn_readfirstlane(claim);
-        if (c0 >= nsrc) break;
-        // (row, column) of the lane's first source: an FP64 quotient, within
-        // one unit of the exact one, then corrected
-        const int s0 = c0 + lane;
-        int r = (int)((double)s0 * S.inv_bw);
-        int c = s0 - r * bw;
-        r += c < 0 ? -1 : (c >= bw ? 1 : 0);
+        if (lane == 0) claim = atomicAdd(S.next, 64);
+        const int u0 = __builtin_amdgcn_readfirstlane(claim);
+        if (u0 >= nunits) break;
+        // (row quad, column) of the lane's unit: an FP64 quotient, within one
+        // unit of the exact one, then corrected; a unit past the box reads
+        // the box's first node and weighs zero
+        const int u = u0 + lane;
+        const bool uvalid = u < nunits;
+        int q = (int)((double)u * S.inv_bw);
+        int c = u - q * bw;
+        q += c < 0 ? -1 : (c >= bw ? 1 : 0);
         c += c < 0 ? bw : (c >= bw ? -bw : 0);
-        int jj[kU], iiu[kU];
+        const int iu = S.bx0 + (uvalid ? c : 0);
+        const int i = column(iu);
+        const float4 tx = tab_x[(unsigned)i];
+        const int r0 = uvalid ? kU * q : 0;
+        int jj[kU];
         float wv[kU];
-        float4 txv[kU], tpv[kU];
+        float4 tpv[kU];
 #pragma unroll
         for (int h = 0; h < kU; ++h) {
-            // a source past the box (last chunk) reads row by0 and weighs zero
-            const bool valid = s0 + 64 * h < nsrc;
-            jj[h] = S.by0 + (valid ? r : 0);
-            iiu[h] = S.bx0 + c;
-            const int i = column(iiu[h]);
+            const bool valid = uvalid && r0 + h < bh;
+            jj[h] = S.by0 + (valid ? r0 + h : 0);
             wv[h] = w_g[(size_t)__umul24(jj[h], nx) + i];  // < 2^32: both axes have at most 2^16 nodes
             wv[h] = valid ? wv[h] : 0.0f;
-            txv[h] = tab_x[(unsigned)i];
             tpv[h] = tab_p[(unsigned)jj[h]];
-            c += dc;
-            r += dr;
-            const bool carry = c >= bw;
-            c -= carry ? bw : 0;
-            r += carry ? 1 : 0;
         }
         // keep the table loads above the skip test (issued with the weights)
         asm volatile("" ::: "memory");
@@ -398,8 +397,8 @@ __device__ inline void scan_sources(const SourceScan& S) {
         if (!__any(live)) continue;
 #pragma unroll
         for (int h = 0; h < kU; ++h)
-            deposit_node<PUSH>(S.acc, jj[h], iiu[h], wv[h] * S.scale, txv[h], tpv[h], S.alpha, S.beta, S.kd, S.rk,
-                               S.X0, S.Y0, S.tw, S.th, S.ldw);
+            deposit_node<PUSH>(S.acc, jj[h], iu, wv[h] * S.scale, tx, tpv[h], S.alpha, S.beta, S.kd, S.rk, S.X0,
+                               S.Y0, S.tw, S.th, S.ldw);
     }
 }
 
@@ -525,7 +524,8 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
         S.bx0 = bx0;
         S.by0 = by0;
         S.bw = bw;
-        S.nsrc = nsrc_live;
+        S.bh = bh;
+        S.nunits = nsrc_live > 0 ? bw * ((bh + kU - 1) / kU) : 0;
         S.inv_nx = inv_nx;
         S.inv_bw = 1.0 / (double)bw;
         S.scale = scale;
