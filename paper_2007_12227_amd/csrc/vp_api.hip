@@ -48,9 +48,7 @@ void raise_lds_limit() {
         if (hipGetDevice(&dev) != hipSuccess) return;
         if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return;
         if (lim <= (int)kDefaultLds) return;
-        for (bool fel : {false, true})
-            if (hipFuncSetAttribute(deposit_kernel(fel), hipFuncAttributeMaxDynamicSharedMemorySize, lim - 1024) != hipSuccess)
-                return;
+        if (hipFuncSetAttribute(deposit_kernel(), hipFuncAttributeMaxDynamicSharedMemorySize, lim - 1024) != hipSuccess) return;
         g_max_lds = (size_t)(lim - 1024);
     });
 }
@@ -64,7 +62,7 @@ double spacing(const vp_axis& a) { return (a.hi - a.lo) / (a.periodic ? a.n : a.
 
 // Workspace layout: every piece 256-byte aligned.
 struct Layout {
-    size_t w0, w1, b, tab_x, tab_p, fel_ex, fel_eq, fel_state, bpart, spart, partials, counters,
+    size_t w0, w1, b, tab_x, tab_p, fel_ex, fel_eq, fel_state, partials, counters,
         inst, off, moments, boxes, total;
     size_t partial_doubles;
 };
@@ -81,12 +79,9 @@ Layout layout(int nx, int np) {
     L.fel_ex = take((size_t)nx * 16);
     L.fel_eq = take((size_t)np * 16);
     L.fel_state = take(kFelStateLen * 8);
-    // FEL bunching partials per solve tile (the state's, the Runge-Kutta
-    // stages'), and the reduction's per-block sums
+    // solve tiles (FEL bunching partials) and reduction blocks
     size_t tiles = (size_t)((nx + kSegX - 1) / kSegX) * ((np + kSegP - 1) / kSegP);
-    L.bpart = take(kPartialsPerTile * tiles * 8);
-    L.spart = take(kPartialsPerTile * tiles * 8);
-    L.partial_doubles = (size_t)kReduceBlocks * kMoments;
+    L.partial_doubles = std::max((size_t)kReduceBlocks * kMoments, kPartialsPerTile * tiles);
     L.partials = take(L.partial_doubles * 8);
     L.counters = take(4 * sizeof(uint32_t));
     L.inst = take(sizeof(VpInst));
@@ -103,7 +98,7 @@ struct LaunchList {
     int32_t* d_off1 = nullptr;  // deposit tiles
     int32_t* d_off2 = nullptr;  // solve tiles
     int ninst = 0, total1 = 0, total2 = 0;
-    bool has_fel = false;  // an FEL instance: the deposit that also advances FEL instances
+    bool has_fel = false;  // an FEL instance: the field kernel follows the solve
     bool has_rk4 = false;  // a Runge-Kutta FEL instance: its stage sums precede the deposit
     size_t lds1 = 0;
     int threads1 = 256;  // deposit workgroup size
@@ -114,22 +109,30 @@ struct LaunchList {
         for (auto& e : exec)
             if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
     }
-    LaunchArgs args(const int32_t* off, int total, int parity) const {
-        return LaunchArgs{d_inst, off, ninst, total, parity, 0};
+    LaunchArgs args(const int32_t* off, int total, int parity, int mode = 0) const {
+        return LaunchArgs{d_inst, off, ninst, total, parity, mode};
     }
-    // the kernels of one step: {kernel, off, total (= grid), lds, threads}
-    struct K { const void* fn; const int32_t* off; int total; size_t lds; int threads; };
-    int kernels(K (&k)[3]) const {
+    // the kernels of one step: {kernel, off, total (= grid), lds, threads, mode}
+    struct K { const void* fn; const int32_t* off; int total; size_t lds; int threads; int mode; };
+    int kernels(K (&k)[5]) const {
         int n = 0;
-        if (has_rk4) k[n++] = K{fel_stage_kernel(), d_off2, total2, 0, kStageThreads};
-        k[n++] = K{deposit_kernel(has_fel), d_off1, total1, lds1, threads1};
-        k[n++] = K{solve_kernel(), d_off2, total2, 0, kSolveThreads};
+        if (has_rk4) {
+            k[n++] = K{fel_stage_kernel(), d_off2, total2, 0, kStageThreads, 0};
+            k[n++] = K{fel_field_kernel(), d_off2, ninst, 0, kFieldThreads, 1};
+        }
+        k[n++] = K{deposit_kernel(), d_off1, total1, lds1, threads1, 0};
+        k[n++] = K{solve_kernel(), d_off2, total2, 0, kSolveThreads, 0};
+        if (has_fel) k[n++] = K{fel_field_kernel(), d_off2, ninst, 0, kFieldThreads, 0};
         return n;
     }
     int enqueue_step(int parity) const {
-        if (has_rk4) HIP_TRY(launch_fel_stage(args(d_off2, total2, parity), total2, stream));
-        HIP_TRY(launch_deposit(args(d_off1, total1, parity), total1, lds1, threads1, has_fel, stream));
+        if (has_rk4) {
+            HIP_TRY(launch_fel_stage(args(d_off2, total2, parity), total2, stream));
+            HIP_TRY(launch_fel_field(args(d_off2, ninst, parity, 1), stream));
+        }
+        HIP_TRY(launch_deposit(args(d_off1, total1, parity), total1, lds1, threads1, stream));
         HIP_TRY(launch_solve(args(d_off2, total2, parity), total2, stream));
+        if (has_fel) HIP_TRY(launch_fel_field(args(d_off2, ninst, parity), stream));
         return VP_OK;
     }
     int build_graph(int rel_parity) {
@@ -137,13 +140,13 @@ struct LaunchList {
         HIP_TRY(hipGraphCreate(&graph, 0));
         hipGraphNode_t prev = nullptr;
         std::vector<LaunchArgs> keep;
-        keep.reserve(3 * kGraphSteps);
-        K ks[3];
+        keep.reserve(5 * kGraphSteps);
+        K ks[5];
         const int nk = kernels(ks);
         for (int s = 0; s < kGraphSteps; ++s) {
             for (int ki = 0; ki < nk; ++ki) {
                 const K& k = ks[ki];
-                keep.push_back(args(k.off, k.total, (rel_parity + s) & 1));
+                keep.push_back(args(k.off, k.total, (rel_parity + s) & 1, k.mode));
                 void* kp[1] = {&keep.back()};
                 hipKernelNodeParams p{};
                 p.func = const_cast<void*>(k.fn);
@@ -402,8 +405,6 @@ int launch_reduce_on(vp_grid* g, int mode, double dt) {
     R.fel_ex = g->at<double2>(g->L.fel_ex);
     R.fel_eq = g->at<double2>(g->L.fel_eq);
     R.partials = g->at<double>(g->L.partials);
-    R.bpart = g->at<double>(g->L.bpart);
-    R.tiles = g->inst.k2_tiles;
     R.counter = g->at<uint32_t>(g->L.counters) + 1;
     R.out = mode == 1 ? g->at<double>(g->L.fel_state) : g->at<double>(g->L.moments);
     R.dz = dt;
@@ -475,8 +476,7 @@ int vp_create_grid(const vp_grid_desc* d, vp_grid** out) {
     I.fel_ex = g->at<double2>(L.fel_ex);
     I.fel_eq = g->at<double2>(L.fel_eq);
     I.fel_state = g->at<double>(L.fel_state);
-    I.bpart = g->at<double>(L.bpart);
-    I.spart = g->at<double>(L.spart);
+    I.partials = g->at<double>(L.partials);
     I.counters = g->at<uint32_t>(L.counters);
     std::vector<double> st(kFelStateLen, 0.0);
     hipError_t e = hipSuccess;
@@ -516,7 +516,7 @@ int vp_set_hamiltonian(vp_grid* g, const vp_hamiltonian* h) {
     g->plan_valid = false;
     g->bunch_valid = false;
     if (h->kind == VP_H_FEL) {
-        const double A[4] = {h->A_re, h->A_im, h->A_re, h->A_im};  // the field of either state parity
+        double A[2] = {h->A_re, h->A_im};
         HIP_TRY(hipMemcpyAsync(g->at<double>(g->L.fel_state) + kA, A, sizeof A, hipMemcpyHostToDevice, g->stream));
         HIP_TRY(hipStreamSynchronize(g->stream));
     }
@@ -597,10 +597,14 @@ int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]) {
     for (int64_t s = 0; s < nsteps; ++s) {
         const int par = (int)((g->parity + s) & 1);
         HIP_TRY(hipEventRecord(ev[3 * s], g->stream));
-        if (L.has_rk4) HIP_TRY(launch_fel_stage(L.args(L.d_off2, L.total2, par), L.total2, g->stream));
-        HIP_TRY(launch_deposit(L.args(L.d_off1, L.total1, par), L.total1, L.lds1, L.threads1, L.has_fel, g->stream));
+        if (L.has_rk4) {
+            HIP_TRY(launch_fel_stage(L.args(L.d_off2, L.total2, par), L.total2, g->stream));
+            HIP_TRY(launch_fel_field(L.args(L.d_off2, L.ninst, par, 1), g->stream));
+        }
+        HIP_TRY(launch_deposit(L.args(L.d_off1, L.total1, par), L.total1, L.lds1, L.threads1, g->stream));
         HIP_TRY(hipEventRecord(ev[3 * s + 1], g->stream));
         HIP_TRY(launch_solve(L.args(L.d_off2, L.total2, par), L.total2, g->stream));
+        if (L.has_fel) HIP_TRY(launch_fel_field(L.args(L.d_off2, L.ninst, par), g->stream));
         HIP_TRY(hipEventRecord(ev[3 * s + 2], g->stream));
     }
     HIP_TRY(hipEventSynchronize(ev.back()));
@@ -642,12 +646,11 @@ int vp_moments(vp_grid* g, vp_moments_t* out) {
     out->nonfinite = (int64_t)m[9];
     if (g->has_ham && g->ham.kind == VP_H_FEL) {
         const double n0 = g->N0 != 0.0 ? g->N0 : 1.0;
-        const double A_re = st[kA + 2 * g->parity], A_im = st[kA + 2 * g->parity + 1];
-        out->A_re = A_re;
-        out->A_im = A_im;
+        out->A_re = st[kA];
+        out->A_im = st[kA + 1];
         out->bunch_re = m[6] / n0;
         out->bunch_im = m[7] / n0;
-        out->fel_invariant = A_re * A_re + A_im * A_im + m[4] / n0;
+        out->fel_invariant = st[kA] * st[kA] + st[kA + 1] * st[kA + 1] + m[4] / n0;
     }
     if (out->nonfinite) return fail(VP_ENONFINITE, "%lld non-finite weights", (long long)out->nonfinite);
     if (flags[kRangeFlag])

@@ -2,7 +2,7 @@
 //
 // One step of the method (Edelen & Webb, Sec. "An Algorithm Based on Phase
 // Space Density Conservation", eqs. 6-10) runs as two kernels (plus, for the
-// FEL by Runge-Kutta, the stage sums k_fel_stage before them):
+// FEL, a one-workgroup field update, k_fel_field):
 //   k_deposit: every lattice node is pushed (its position is its index, so
 //              nothing but w is read) and its weight is scattered onto the
 //              4x4 lattice taps of its moved tent with cubic B-spline weights
@@ -15,9 +15,8 @@
 //              around it (a 16-node halo per side makes the tile independent of
 //              its neighbours to within (2-sqrt 3)^16 ~ 7e-10), columns then
 //              rows, one line per lane.  For the FEL its epilogue also forms
-//              the FP64 bunching partials of the new state; the next step's
-//              kernels sum them (each workgroup alike, in a fixed order) and
-//              the deposit advances the FEL field.
+//              the FP64 bunching partials of the new state, which k_fel_field
+//              sums to advance the FEL field.
 #pragma once
 
 #include <stdint.h>
@@ -42,6 +41,7 @@ constexpr int kSegP = 64;
 constexpr int kLineX = kSegX + 2 * kHalo;  // window line along x: the kept segment plus both halos
 constexpr int kLineP = kSegP + 2 * kHalo;  // window line along p
 constexpr int kSolveThreads = 64;          // solve: one wavefront (a window column, then a kept row, per lane)
+constexpr int kFieldThreads = 256;       // FEL field update: one workgroup per instance
 constexpr int kStageThreads = 256;       // FEL Runge-Kutta stage sums: four wavefronts per solve tile
 constexpr int kReduceBlocks = 256;
 constexpr int kReduceThreads = 256;
@@ -196,9 +196,8 @@ struct VpInst {
     const float4* tab_p;     // per row push table
     const double2* fel_ex;   // (cos phi_i, sin phi_i)
     const double2* fel_eq;   // (cos q_j, sin q_j), q_j the half drift of row j
-    double* fel_state;       // field by state parity, N0, dz of the bunchings (kA .. kFelStateLen)
-    double* bpart;           // per solve tile: the state's bunching partials (kPartialsPerTile)
-    double* spart;           // per solve tile: the Runge-Kutta stage 3 and 4 bunching partials
+    double* fel_state;       // [A_re, A_im, b_re, b_im, N0, dz_b, ...]
+    double* partials;        // per solve tile: bunching partial (re, im)
     uint32_t* counters;      // [1]: reduction, [kRangeFlag]: deposit range
     const int4* boxes;       // per deposit tile: source box (x0, x1, y0, y1) planned on the host,
                              // or null: the deposit plans it (the FEL kick depends on the field)
@@ -213,14 +212,13 @@ inline size_t box_capacity(int nx, int np) {
 
 constexpr int kRangeFlag = 2;  // counters slot set when a deposit cell sum leaves half its range
 
-// fel_state slots: kA + 2 par: the field A (re, im) that goes with state par
-// (the step from state par writes the field of state par ^ 1); kN0: the sum
-// of the initial weights; kDzB: the dz the state's bunchings were formed for.
-enum { kA = 0, kN0 = 4, kDzB = 5, kFelStateLen = 8 };
-// Bunching partials per solve tile (FP64 sums of w e^{-i psi}, not divided by
-// N0): at the half-drift phases (re, im) and at the lattice phases (re, im);
-// for the Runge-Kutta stage sums, at the stage 3 and stage 4 phases.
-constexpr int kPartialsPerTile = 4;
+// fel_state slots
+//   A: field; Bn: bunching at the half-drift phases (the exact-kick step's,
+//   and the Runge-Kutta step's stage 2); B1, B3, B4: the Runge-Kutta stages'
+//   bunchings at the lattice phases and at stages 3 and 4; An: the field after
+//   the Runge-Kutta step in progress
+enum { kA = 0, kBn = 2, kN0 = 4, kDzB = 5, kB1 = 6, kB3 = 8, kB4 = 10, kAn = 12, kFelStateLen = 16 };
+constexpr int kPartialsPerTile = 4;  // per solve tile: two complex FP64 bunching sums
 
 struct LaunchArgs {
     const VpInst* inst;
@@ -228,7 +226,7 @@ struct LaunchArgs {
     int32_t ninst;
     int32_t total;
     int32_t parity;      // step parity relative to each instance's parity0
-    int32_t pad;
+    int32_t mode;        // k_fel_field: 0 after the solve, 1 after the Runge-Kutta stage sums
 };
 
 struct ReduceArgs {
@@ -242,18 +240,17 @@ struct ReduceArgs {
     uint32_t* counter;
     double* out;                  // moments: [kMoments]; bunching: fel_state
     double dz;
-    double* bpart;                // bunching: the state's per-tile partials (the sums go to tile 0)
-    int32_t tiles;                // bunching: solve tiles of the grid
-    int32_t pad;
 };
 
 // launchers (vp_kernels.hip)
-hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, bool fel, hipStream_t s);
+hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s);
 hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s);
+hipError_t launch_fel_field(const LaunchArgs& a, hipStream_t s);
 hipError_t launch_fel_stage(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
-const void* deposit_kernel(bool fel);  // fel: the variant that also advances FEL instances
+const void* deposit_kernel();
 const void* solve_kernel();
+const void* fel_field_kernel();
 const void* fel_stage_kernel();
 
 // Deposit LDS image: (tx + 8) x (ty + 8) 64-bit cells.

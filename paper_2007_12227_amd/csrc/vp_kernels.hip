@@ -71,38 +71,6 @@ __device__ inline unsigned long long fix48_word(double a, double b) {
 }
 __device__ inline long long fix48_value(long long sum) { return (long long)((unsigned long long)sum << 16) >> 16; }
 
-// Sum of the per-tile bunching partials part[4 t + c] (c < 4) over the tiles,
-// by one wavefront in a fixed order (lane l takes the tiles t = l mod 64 in
-// turn, then a fixed shuffle tree): every workgroup that sums them gets the
-// same bits, whatever its size.  Every lane receives the sums.
-__device__ inline void bunch_sums(const double* __restrict__ part, int tiles, double (&s)[4]) {
-    const int l = threadIdx.x & 63;
-    const double2* __restrict__ p2 = reinterpret_cast<const double2*>(part);  // a tile: two 16-byte pairs
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
-    auto add = [&](double2 lo, double2 hi) {
-        a[0] += lo.x;
-        a[1] += lo.y;
-        a[2] += hi.x;
-        a[3] += hi.y;
-    };
-    int t = l;
-    constexpr int kBatch = 8;  // tiles per lane with their loads in flight together
-    for (; t + 64 * (kBatch - 1) < tiles; t += 64 * kBatch) {
-        double2 v[2 * kBatch];
-#pragma unroll
-        for (int k = 0; k < kBatch; ++k) {
-            v[2 * k] = p2[2 * (t + 64 * k)];
-            v[2 * k + 1] = p2[2 * (t + 64 * k) + 1];
-        }
-#pragma unroll
-        for (int k = 0; k < kBatch; ++k) add(v[2 * k], v[2 * k + 1]);
-    }
-    for (; t < tiles; t += 64) add(p2[2 * t], p2[2 * t + 1]);
-    for (int o = 32; o > 0; o >>= 1)
-        for (int c = 0; c < 4; ++c) a[c] += __shfl_xor(a[c], o);
-    for (int c = 0; c < 4; ++c) s[c] = a[c];
-}
-
 // Locate the instance of a flattened tile index (thread 0 only).
 __device__ inline int find_instance(const int32_t* off, int ninst, int item) {
     int lo = 0, hi = ninst - 1;
@@ -443,15 +411,11 @@ __device__ inline void scan_sources(const SourceScan& S) {
 // that takes the taps of nodes near the tile's edge which fall outside it;
 // they are dropped with it.
 // ---------------------------------------------------------------------------
-// FEL: compiled only into k_deposit_fel, which also advances FEL instances
-// (k_deposit carries no FEL code, so the other pushes keep its registers).
-template <bool FEL>
-__device__ inline void deposit_tiles(const LaunchArgs& A) {
+__global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
     extern __shared__ __align__(16) long long acc[];  // 16-byte aligned: read four cells at a time
     __shared__ int s_d, s_box[4], s_next;
     __shared__ float s_ab[2];
     __shared__ RkConsts s_rk;
-    __shared__ double s_bunch[8];  // FEL: the state's bunchings b2, b1, then b3, b4 (re, im)
 
     for (int it = blockIdx.x; it < A.total; it += gridDim.x) {
         const int item = tile_of(it, A.total);
@@ -472,20 +436,6 @@ __device__ inline void deposit_tiles(const LaunchArgs& A) {
         int4 hb = make_int4(0, 0, 0, 0);
         if (threadIdx.x == 0 && I.boxes) hb = I.boxes[t];
         for (int k = threadIdx.x; k < ldw * ldh; k += blockDim.x) acc[k] = 0ll;
-        const bool fel = FEL && I.push.kind == kFel;
-        if (fel && threadIdx.x < 64) {
-            // the bunchings of the state being pushed: its solve's per-tile
-            // partials (and the stage sums of this step), over N0
-            const double inv_n0 = 1.0 / I.fel_state[kN0];
-            double b[4];
-            bunch_sums(I.bpart, I.k2_tiles, b);
-            if (threadIdx.x < 4) s_bunch[threadIdx.x] = b[threadIdx.x] * inv_n0;
-            if (I.push.rk4) {
-                bunch_sums(I.spart, I.k2_tiles, b);
-                if (threadIdx.x < 4) s_bunch[4 + threadIdx.x] = b[threadIdx.x] * inv_n0;
-            }
-        }
-        if (FEL) __syncthreads();
         if (threadIdx.x == 0 && I.boxes) {
             s_ab[0] = I.push.alpha;
             s_ab[1] = I.push.beta;
@@ -496,53 +446,39 @@ __device__ inline void deposit_tiles(const LaunchArgs& A) {
             s_box[3] = hb.w;
         } else if (threadIdx.x == 0) {
             PushParams P = I.push;
-            if (fel) {
-                double* st = I.fel_state;
+            if (P.kind == kFel && P.rk4) {
+                // stage fields A_s and bunchings b_s of the Runge-Kutta step
+                // (b1, b2 of the state, b3, b4 from k_fel_stage), FP64
+                const double* st = I.fel_state;
                 const double h = I.fel_dz, sg = (double)I.fel_sigma2;
-                const double Are = st[kA + 2 * par], Aim = st[kA + 2 * par + 1];
-                double an_re, an_im;  // the field after this step (eq. 13c)
-                if (P.rk4) {
-                    // stage fields A_s and bunchings b_s of the Runge-Kutta step
-                    // (b1, b2 of the state, b3, b4 from k_fel_stage), FP64
-                    const double bre[4] = {s_bunch[2], s_bunch[0], s_bunch[4], s_bunch[6]};
-                    const double bim[4] = {s_bunch[3], s_bunch[1], s_bunch[5], s_bunch[7]};
-                    const double cA[4] = {0.0, 0.5 * h, 0.5 * h, h};  // A_s = A + cA_s b_{s-1}
-                    double rmax = 0.0;
-                    for (int k = 0; k < 4; ++k) {
-                        const double are = Are + (k ? cA[k] * bre[k - 1] : 0.0);
-                        const double aim = Aim + (k ? cA[k] * bim[k - 1] : 0.0);
-                        // F = -2 Re[(A + i sigma2 b) e^{i psi}] = a cos psi + b sin psi
-                        const double re = are - sg * bim[k], im = aim + sg * bre[k];
-                        s_rk.a[k] = (float)(-2.0 * re);
-                        s_rk.b[k] = (float)(2.0 * im);
-                        rmax = fmax(rmax, sqrt(re * re + im * im));
-                    }
-                    const double hp = (double)P.hp, hx = (double)P.hx;
-                    s_rk.cdv = (float)(h / (6.0 * hp));
-                    s_rk.cdu = (float)(h * h / (6.0 * hx));
-                    s_rk.t3 = (float)(0.25 * h * h);
-                    s_rk.t4 = (float)(0.5 * h * h);
-                    // |dv| <= (h / hp) 2 max_s |A_s + i sigma2 b_s|; |du - drift| <= kd |dv|max
-                    P.alpha = (float)(2.0 * h / hp * rmax);
-                    P.beta = 0.0f;
-                    an_re = Are + h / 6.0 * (bre[0] + 2.0 * bre[1] + 2.0 * bre[2] + bre[3]);
-                    an_im = Aim + h / 6.0 * (bim[0] + 2.0 * bim[1] + 2.0 * bim[2] + bim[3]);
-                } else {
-                    // kick field: A at mid-kick plus the space-charge term, A + b dz/2 + i sigma2 b
-                    const double b2r = s_bunch[0], b2i = s_bunch[1];
-                    const double are = Are + 0.5 * h * b2r - sg * b2i;
-                    const double aim = Aim + 0.5 * h * b2i + sg * b2r;
-                    P.alpha = (float)(I.fel_kick * are);
-                    P.beta = (float)(-I.fel_kick * aim);
-                    an_re = Are + h * b2r;
-                    an_im = Aim + h * b2i;
+                const double bre[4] = {st[kB1], st[kBn], st[kB3], st[kB4]};
+                const double bim[4] = {st[kB1 + 1], st[kBn + 1], st[kB3 + 1], st[kB4 + 1]};
+                const double cA[4] = {0.0, 0.5 * h, 0.5 * h, h};  // A_s = A + cA_s b_{s-1}
+                double rmax = 0.0;
+                for (int k = 0; k < 4; ++k) {
+                    const double are = st[kA] + (k ? cA[k] * bre[k - 1] : 0.0);
+                    const double aim = st[kA + 1] + (k ? cA[k] * bim[k - 1] : 0.0);
+                    // F = -2 Re[(A + i sigma2 b) e^{i psi}] = a cos psi + b sin psi
+                    const double re = are - sg * bim[k], im = aim + sg * bre[k];
+                    s_rk.a[k] = (float)(-2.0 * re);
+                    s_rk.b[k] = (float)(2.0 * im);
+                    rmax = fmax(rmax, sqrt(re * re + im * im));
                 }
-                // the instance's first tile keeps the field of the next state
-                // (nothing reads that slot during this step)
-                if (t == 0) {
-                    st[kA + 2 * (par ^ 1)] = an_re;
-                    st[kA + 2 * (par ^ 1) + 1] = an_im;
-                }
+                const double hp = (double)P.hp, hx = (double)P.hx;
+                s_rk.cdv = (float)(h / (6.0 * hp));
+                s_rk.cdu = (float)(h * h / (6.0 * hx));
+                s_rk.t3 = (float)(0.25 * h * h);
+                s_rk.t4 = (float)(0.5 * h * h);
+                // |dv| <= (h / hp) 2 max_s |A_s + i sigma2 b_s|; |du - drift| <= kd |dv|max
+                P.alpha = (float)(2.0 * h / hp * rmax);
+                P.beta = 0.0f;
+            } else if (P.kind == kFel) {
+                // kick field: A at mid-kick plus the space-charge term, A + b dz/2 + i sigma2 b
+                const double* st = I.fel_state;
+                double are = st[kA] + 0.5 * I.fel_dz * st[kBn] - (double)I.fel_sigma2 * st[kBn + 1];
+                double aim = st[kA + 1] + 0.5 * I.fel_dz * st[kBn + 1] + (double)I.fel_sigma2 * st[kBn];
+                P.alpha = (float)(I.fel_kick * are);
+                P.beta = (float)(-I.fel_kick * aim);
             }
             s_ab[0] = P.alpha;
             s_ab[1] = P.beta;
@@ -601,7 +537,7 @@ __device__ inline void deposit_tiles(const LaunchArgs& A) {
         S.tw = X1 - X0;
         S.th = Y1 - Y0;
         S.ldw = ldw;
-        const bool rk4 = FEL && kind == kFel && I.push.rk4;
+        const bool rk4 = kind == kFel && I.push.rk4;
         if (rk4) {
             auto uni = [](float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); };
             for (int k = 0; k < 4; ++k) {
@@ -680,9 +616,6 @@ __device__ inline void deposit_tiles(const LaunchArgs& A) {
     }
 }
 
-__global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) { deposit_tiles<false>(A); }
-__global__ __launch_bounds__(kDepositMaxThreads) void k_deposit_fel(LaunchArgs A) { deposit_tiles<true>(A); }
-
 // ---------------------------------------------------------------------------
 // k_solve: w_new = (M_x^{-1} (x) M_p^{-1}) b in one pass, one lattice line per
 // lane (line_solve: the LU recursions of T = tridiag(1,4,1),
@@ -702,7 +635,7 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit_fel(LaunchArgs A
 // The intermediate never leaves LDS (16.6 KB), and with at most 256 VGPRs
 // eight tiles are resident per compute unit: all 2048 tiles of a 2048^2
 // lattice at once.  For the FEL the write-out also forms the FP64 bunching
-// partials of the new state, per tile (the next step's kernels sum them).
+// partials of the new state, per tile (k_fel_field sums them).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_solve(LaunchArgs A) {
     static_assert(kSolveThreads == kLineX && kSolveThreads == kSegP && kSegX * 2 == kSolveThreads,
@@ -943,8 +876,8 @@ __global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2
 
         if (fel) {
             // FP64 bunching of the new state: this tile's partials, at the
-            // half-drift phases and (Runge-Kutta) at the lattice phases (the
-            // next step's kernels sum them)
+            // half-drift phases and (Runge-Kutta) at the lattice phases
+            // (k_fel_field sums the partials)
             for (int o = 32; o > 0; o >>= 1) {
                 acc_re += __shfl_down(acc_re, o);
                 acc_im += __shfl_down(acc_im, o);
@@ -952,7 +885,7 @@ __global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2
                 acc1_im += __shfl_down(acc1_im, o);
             }
             if (lane == 0) {
-                double* pt = I.bpart + kPartialsPerTile * t;
+                double* pt = I.partials + kPartialsPerTile * t;
                 pt[0] = acc_re;
                 pt[1] = acc_im;
                 pt[2] = acc1_re;
@@ -960,6 +893,76 @@ __global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2
             }
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_fel_field: one workgroup per instance of the launch list; for an FEL
+// instance it sums the per-tile bunching partials of the preceding kernel in a
+// fixed order (thread-strided, then a fixed shuffle tree) and advances the
+// field (eq. 13c).  A kernel of its own, because a last-tile-sums scheme
+// inside k_solve needs a device-scope release per tile, which on a multi-XCD
+// part writes back the L2 and costs more than the solve.
+//  mode 0 (after k_solve; partials: the new state's bunching at the half-drift
+//    and at the lattice phases).  Exact-kick step: A moves by dz times the
+//    bunching of the state that was pushed; Runge-Kutta: A takes the step's
+//    new value.  The new bunchings are kept for the next step.
+//  mode 1 (after k_fel_stage, Runge-Kutta only; partials: the bunching at the
+//    phases of stages 3 and 4): keeps b3, b4 and forms the step's new field
+//    A + dz/6 (b1 + 2 b2 + 2 b3 + b4).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kFieldThreads) void k_fel_field(LaunchArgs A) {
+    __shared__ double s_red[kPartialsPerTile][kFieldThreads / 64];
+    const VpInst& I = A.inst[blockIdx.x];
+    if (I.push.kind != kFel || (A.mode == 1 && !I.push.rk4)) return;
+    // the field state the update needs, loaded while the partials are summed
+    double* st = I.fel_state;
+    double n0 = 0.0, a[2] = {0.0, 0.0}, bn[2] = {0.0, 0.0}, b1[2] = {0.0, 0.0}, an[2] = {0.0, 0.0};
+    if (threadIdx.x == 0) {
+        n0 = st[kN0];
+        for (int c = 0; c < 2; ++c) {
+            a[c] = st[kA + c];
+            bn[c] = st[kBn + c];
+            b1[c] = st[kB1 + c];
+            an[c] = st[kAn + c];
+        }
+    }
+    double acc[kPartialsPerTile] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < I.k2_tiles; k += kFieldThreads)
+        for (int c = 0; c < kPartialsPerTile; ++c) acc[c] += I.partials[kPartialsPerTile * k + c];
+    for (int o = 32; o > 0; o >>= 1)
+        for (int c = 0; c < kPartialsPerTile; ++c) acc[c] += __shfl_down(acc[c], o);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int c = 0; c < kPartialsPerTile; ++c) s_red[c][wid] = acc[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int c = 0; c < kPartialsPerTile; ++c) {
+            acc[c] = 0.0;
+            for (int k = 0; k < kFieldThreads / 64; ++k) acc[c] += s_red[c][k];
+        }
+        const double inv_n0 = 1.0 / n0, h = I.fel_dz;
+        if (A.mode == 1) {
+            const double b3[2] = {acc[0] * inv_n0, acc[1] * inv_n0}, b4[2] = {acc[2] * inv_n0, acc[3] * inv_n0};
+            for (int c = 0; c < 2; ++c) {
+                st[kB3 + c] = b3[c];
+                st[kB4 + c] = b4[c];
+                st[kAn + c] = a[c] + h / 6.0 * (b1[c] + 2.0 * bn[c] + 2.0 * b3[c] + b4[c]);
+            }
+            return;
+        }
+        if (I.push.rk4) {
+            st[kA] = an[0];
+            st[kA + 1] = an[1];
+            st[kB1] = acc[2] * inv_n0;
+            st[kB1 + 1] = acc[3] * inv_n0;
+        } else {
+            st[kA] = a[0] + h * bn[0];
+            st[kA + 1] = a[1] + h * bn[1];
+        }
+        st[kBn] = acc[0] * inv_n0;
+        st[kBn + 1] = acc[1] * inv_n0;
+        st[kDzB] = h;
     }
 }
 
@@ -979,7 +982,7 @@ __device__ inline void sincos_small(double x, double* s, double* c) {
 // ---------------------------------------------------------------------------
 // k_fel_stage: the bunching at the phases of the Runge-Kutta step's stages 3
 // and 4 (FEL only), FP64, one per-tile partial per solve tile of kSegX x kSegP
-// nodes (the deposit sums them).  A workgroup of four wavefronts per tile: thread t takes column
+// nodes.  A workgroup of four wavefronts per tile: thread t takes column
 // t mod kSegX and rows t / kSegX + kRowStep i; the sums are reduced in a fixed
 // order (shuffle tree per wavefront, then the wavefronts in turn).  With
 // k1 = a1 cos phi + b1 sin phi and k2 = a2 cos psi2 + b2 sin psi2 the slopes
@@ -991,7 +994,6 @@ __device__ inline void sincos_small(double x, double* s, double* c) {
 __global__ __launch_bounds__(kStageThreads) void k_fel_stage(LaunchArgs A) {
     constexpr int kWaves = kStageThreads / 64, kRowStep = kStageThreads / kSegX;
     __shared__ double s_red[kWaves][4];
-    __shared__ double s_b[4];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     for (int item = blockIdx.x; item < A.total; item += gridDim.x) {
         const int d = __builtin_amdgcn_readfirstlane(find_instance(A.off, A.ninst, item));
@@ -1007,19 +1009,10 @@ __global__ __launch_bounds__(kStageThreads) void k_fel_stage(LaunchArgs A) {
         const float* __restrict__ w = I.w[par];
         const double* st = I.fel_state;
         const double h = I.fel_dz, sg = (double)I.fel_sigma2;
-        // the state's bunchings b2 (half-drift phases) and b1 (lattice phases):
-        // its solve's per-tile partials, summed as the deposit sums them
-        if (wid == 0) {
-            double b[4];
-            bunch_sums(I.bpart, I.k2_tiles, b);
-            if (lane < 4) s_b[lane] = b[lane] / st[kN0];
-        }
-        __syncthreads();
         // slope coefficients of stages 1 and 2 (as in the deposit, FP64)
-        const double b1r = s_b[2], b1i = s_b[3], b2r = s_b[0], b2i = s_b[1];
-        const double Are = st[kA + 2 * par], Aim = st[kA + 2 * par + 1];
-        const double a1r = Are - sg * b1i, a1i = Aim + sg * b1r;
-        const double a2r = Are + 0.5 * h * b1r - sg * b2i, a2i = Aim + 0.5 * h * b1i + sg * b2r;
+        const double b1r = st[kB1], b1i = st[kB1 + 1], b2r = st[kBn], b2i = st[kBn + 1];
+        const double a1r = st[kA] - sg * b1i, a1i = st[kA + 1] + sg * b1r;
+        const double a2r = st[kA] + 0.5 * h * b1r - sg * b2i, a2i = st[kA + 1] + 0.5 * h * b1i + sg * b2r;
         const double t3 = 0.25 * h * h, t4 = 0.5 * h * h;
         double acc[4] = {0.0, 0.0, 0.0, 0.0};  // stage 3 (re, im), stage 4 (re, im)
         const int col = tid & (kSegX - 1);
@@ -1059,7 +1052,7 @@ __global__ __launch_bounds__(kStageThreads) void k_fel_stage(LaunchArgs A) {
         if (tid < 4) {
             double v = 0.0;
             for (int k = 0; k < kWaves; ++k) v += s_red[k][tid];
-            I.spart[kPartialsPerTile * t + tid] = v;
+            I.partials[kPartialsPerTile * t + tid] = v;
         }
         __syncthreads();
     }
@@ -1070,8 +1063,8 @@ __global__ __launch_bounds__(kStageThreads) void k_fel_stage(LaunchArgs A) {
 //  mode 0 (diagnostics): sum w, sum_{w<0} w, sum |w|, sum_{w>0} w ln w,
 //    sum w p, sum w (kinetic + potential), sum w cos x, sum w sin x, max |w|,
 //    #nonfinite.
-//  mode 1 (FEL bunching): sum w e^{-i (phi_i + q_j)} and sum w e^{-i phi_i}
-//    -> the state's bunching partials (all in the first solve tile's slots).
+//  mode 1 (FEL bunching): sum w e^{-i (phi_i + q_j)} / N0 and
+//    sum w e^{-i phi_i} / N0 -> fel_state.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
     __shared__ double s_part[kReduceThreads / 64][kMoments];
@@ -1144,16 +1137,13 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
             s = threadIdx.x == 8 ? fmax(s, v) : s + v;
         }
         if (R.mode == 1) {
-            // the state's bunching, as the partials of its first solve tile
-            if (threadIdx.x < 4) R.bpart[threadIdx.x] = s;
+            if (threadIdx.x < 2) R.out[kBn + threadIdx.x] = s * R.inv_n0;
+            else if (threadIdx.x < 4) R.out[kB1 + threadIdx.x - 2] = s * R.inv_n0;
             if (threadIdx.x == 0) R.out[kDzB] = R.dz;
         } else {
             R.out[threadIdx.x] = s;
         }
     }
-    if (R.mode == 1)  // and zero for every other tile
-        for (int k = kPartialsPerTile + (int)threadIdx.x; k < kPartialsPerTile * R.tiles; k += blockDim.x)
-            R.bpart[k] = 0.0;
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
@@ -1161,14 +1151,18 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
     }
 }
 
-hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, bool fel, hipStream_t s) {
-    if (fel) hipLaunchKernelGGL(k_deposit_fel, dim3(grid), dim3(threads), lds, s, a);
-    else hipLaunchKernelGGL(k_deposit, dim3(grid), dim3(threads), lds, s, a);
+hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s) {
+    hipLaunchKernelGGL(k_deposit, dim3(grid), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_solve, dim3(grid), dim3(kSolveThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fel_field(const LaunchArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_fel_field, dim3(a.ninst), dim3(kFieldThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1182,10 +1176,9 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-const void* deposit_kernel(bool fel) {
-    return fel ? reinterpret_cast<const void*>(&k_deposit_fel) : reinterpret_cast<const void*>(&k_deposit);
-}
+const void* deposit_kernel() { return reinterpret_cast<const void*>(&k_deposit); }
 const void* solve_kernel() { return reinterpret_cast<const void*>(&k_solve); }
+const void* fel_field_kernel() { return reinterpret_cast<const void*>(&k_fel_field); }
 const void* fel_stage_kernel() { return reinterpret_cast<const void*>(&k_fel_stage); }
 
 }  // namespace vp
