@@ -125,7 +125,7 @@ typedef struct {
 
 /* Launch shape of the deposit kernel: destination tile (in lattice nodes) and
  * threads per workgroup (a multiple of 64, at most 1024).  Zero fields keep
- * the current value.  (The solve works on fixed 32x32 tiles.) */
+ * the current value.  (The solve works on fixed tiles of 32 x 64 nodes.) */
 typedef struct {
     int32_t k1_tx, k1_ty;
     int32_t k1_threads;
