@@ -329,6 +329,31 @@ def test_fel_rk4_step_against_independent_integrator():
         assert 24.0 < e0 / e1 < 40.0, errs
 
 
+def test_fel_exact_kick_step_is_second_order_against_independent_integrator():
+    """The exact-kick drift-kick-drift FEL step (the default integrator) against
+    DOP853 on the same particle system, with detuning and space charge: a
+    Strang splitting of two exactly integrated sub-flows, so its local error
+    falls by ~8 per halving of dz (second order), in the nodes and in A."""
+    x, p = Axis(0.0, 2 * math.pi, 16, True), Axis(-0.5, 0.5, 12, False)
+    w = np.exp(-p.nodes()[:, None] ** 2 / (2 * 0.2**2)) * (1 + 0.3 * rng(51).uniform(-1, 1, (12, 16)))
+    N0, A0 = w.sum(), complex(0.02, 0.01)
+    delta, sigma2 = 0.2, 0.3
+    ham = Hamiltonian(H_FEL, fel_delta=delta, fel_sigma2=sigma2)
+    errs = []
+    for dz in (0.2, 0.1, 0.05):
+        # the step as the oracle takes it: the bunching at the half-drift
+        # phases, the mid-kick field with the space-charge term, the push
+        b = oracle.bunching(x, p, ham, dz, w, N0)
+        kick = A0 + 0.5 * dz * b + 1j * sigma2 * b
+        du, dv = oracle.push(x, p, ham, dz, np.array([kick.real, kick.imag]))
+        A1 = A0 + dz * b
+        dpsi, deta, Aref = _fel_particles_ode(x, p, w, N0, A0, delta, sigma2, dz)
+        errs.append(max(np.abs(du * x.h - dpsi).max(), np.abs(dv * p.h - deta).max(), abs(A1 - Aref)))
+    assert errs[-1] < 1e-5, errs
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 6.0 < e0 / e1 < 10.0, errs
+
+
 def test_fel_rk4_run_keeps_the_invariant_to_its_order():
     """RK4 does not conserve |A|^2 + <eta> exactly (exact-kick DKD does), but
     its drift is fourth order: halving dz over the same distance cuts it ~16x."""
