@@ -191,8 +191,8 @@ int vp_autotune(vp_grid* g, double dt, double* best_us);
 /* Batched execution: n grids (each with its density and Hamiltonian set)
  * advance together, one launch of each per-step kernel covering every tile of
  * every grid.  dt[i] is grid i's step size.  All grids must use the same
- * stream; the batch uses grids[0]'s stream.  The grids must outlive the batch
- * and must not be stepped on their own while it exists. */
+ * stream (VP_EINVAL otherwise); the batch uses it.  The grids must outlive the
+ * batch and must not be stepped on their own while it exists (VP_ESTATE). */
 int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch** out);
 int vp_batch_step(vp_batch* b, int64_t nsteps);
 int vp_batch_destroy(vp_batch* b);

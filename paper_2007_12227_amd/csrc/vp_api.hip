@@ -54,6 +54,24 @@ void raise_lds_limit() {
 }
 constexpr int kGraphSteps = 16;
 
+// HIP events destroyed with their holder (also on an early error return).
+struct Events {
+    std::vector<hipEvent_t> ev;
+    explicit Events(size_t n) : ev(n, nullptr) {}
+    Events(const Events&) = delete;
+    Events& operator=(const Events&) = delete;
+    ~Events() {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    hipError_t create() {
+        for (auto& e : ev)
+            if (hipError_t r = hipEventCreate(&e); r != hipSuccess) return r;
+        return hipSuccess;
+    }
+    hipEvent_t& operator[](size_t k) { return ev[k]; }
+};
+
 bool axis_ok(const vp_axis* a) {
     return a && a->n >= 4 && a->n <= (1 << 16) && isfinite(a->lo) && isfinite(a->hi) && a->hi > a->lo;
 }
@@ -591,8 +609,8 @@ int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]) {
     if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
     int rc = prepare(g, dt);
     if (rc) return rc;
-    std::vector<hipEvent_t> ev(3 * nsteps);
-    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    Events ev((size_t)(3 * nsteps));
+    HIP_TRY(ev.create());
     const LaunchList& L = g->list;
     for (int64_t s = 0; s < nsteps; ++s) {
         const int par = (int)((g->parity + s) & 1);
@@ -607,7 +625,7 @@ int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]) {
         if (L.has_fel) HIP_TRY(launch_fel_field(L.args(L.d_off2, L.ninst, par), g->stream));
         HIP_TRY(hipEventRecord(ev[3 * s + 2], g->stream));
     }
-    HIP_TRY(hipEventSynchronize(ev.back()));
+    HIP_TRY(hipEventSynchronize(ev[3 * nsteps - 1]));
     double t[2] = {0.0, 0.0};
     for (int64_t s = 0; s < nsteps; ++s)
         for (int k = 0; k < 2; ++k) {
@@ -615,7 +633,6 @@ int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]) {
             HIP_TRY(hipEventElapsedTime(&ms, ev[3 * s + k], ev[3 * s + k + 1]));
             t[k] += ms;
         }
-    for (auto& e : ev) (void)hipEventDestroy(e);
     for (int k = 0; k < 2; ++k) us[k] = 1000.0 * t[k] / nsteps;
     g->parity = (int)((g->parity + nsteps) & 1);
     g->step += nsteps;
@@ -714,9 +731,9 @@ int vp_autotune(vp_grid* g, double dt, double* best_us) {
     const int saved_parity = g->parity;
     const int64_t saved_step = g->step;
     const bool saved_graph = g->use_graph;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    Events ev(2);
+    HIP_TRY(ev.create());
+    hipEvent_t e0 = ev[0], e1 = ev[1];
     auto time_tiles = [&](const vp_tiles& t, float* us) -> int {
         if (validate_tiles(g, t)) return VP_EINVAL;
         g->tiles = t;
@@ -750,8 +767,6 @@ int vp_autotune(vp_grid* g, double dt, double* best_us) {
         // noise) do not flip the choice from run to run
         if (time_tiles(t, &us) == VP_OK && us < 0.98f * best_t) { best_t = us; best = t; }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     g->tiles = best;
     g->plan_valid = false;
     g->parity = saved_parity;
@@ -778,6 +793,7 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
     for (int k = 0; k < n; ++k) {
         if (!grids[k]) return fail(VP_EINVAL, "null grid %d", k);
         if (grids[k]->in_batch) return fail(VP_ESTATE, "grid %d already belongs to a batch", k);
+        if (grids[k]->stream != s) return fail(VP_EINVAL, "grid %d is on another stream than grid 0", k);
         for (int q = 0; q < k; ++q)
             if (grids[q] == grids[k]) return fail(VP_EINVAL, "grid %d listed twice", k);
     }

@@ -86,3 +86,19 @@ def test_grid_in_batch_refuses_own_steps(B):
     batch.close()
     g.step(inst.dt, 1)
     g.close()
+
+
+def test_batch_of_grids_on_different_streams_is_refused(B):
+    """A batch runs on one stream: grids on two streams are refused (their
+    work would not be ordered)."""
+    import torch
+    insts = batch_instances(2, seed=42, steps=5, n_min=64, n_max=64)
+    side = torch.cuda.Stream()  # default priority
+    g0 = B.grid_for(insts[0])
+    g1 = B.grid_for(insts[1], stream=side)
+    with pytest.raises(B.VpError) as e:
+        B.Batch([g0, g1], [i.dt for i in insts])
+    assert e.value.code == B.VP_EINVAL
+    side.synchronize()
+    g1.close()
+    g0.close()
