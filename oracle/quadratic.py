@@ -1,0 +1,103 @@
+"""FP64 oracle of the method with quadratic B-spline basis functions (test
+infrastructure: only the tests use it; the product library does not).
+
+The paper expands the density in tents (eq. 4) and builds the update from
+the basis functions' overlaps (eqs. 8-10); smoother local basis functions are
+the extension its discussion points to.  Here the basis function of a node is
+the centred quadratic B-spline of width 3h, B2((x - x_j) / h).  The overlap of
+two of them whose centres are s h apart is h B5(s), B5 the centred quintic
+B-spline, so with this basis:
+  * Delta (eq. 9): a node moved to u (in cells) gives weight B5(u - c) to the
+    six nodes c = floor(u) - 2 .. floor(u) + 3 of each axis;
+  * Lambda (eq. 8) = h_x h_p M_x (x) M_p, M = [1, 26, 66, 26, 1] / 120, cyclic
+    on a periodic axis and truncated on an open one (full basis functions at
+    the edge nodes; weight moved past an edge is lost, as with tents);
+  * the update is w_fin = Lambda^{-1} Delta^T w (eq. 10), the push being the
+    tent oracle's (it does not depend on the basis).
+Every step here is written out plainly (numpy scatter, dense per-axis solves)
+and is meant for lattices of a few hundred nodes per axis.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import push as _push
+
+
+def bspline(k: int, s) -> np.ndarray:
+    """Centred cardinal B-spline of degree k (support [-(k+1)/2, (k+1)/2]):
+    B_k(s) = 1/k! sum_j (-1)^j C(k+1, j) (s + (k+1)/2 - j)_+^k."""
+    s = np.asarray(s, dtype=np.float64)
+    out = np.zeros_like(s)
+    for j in range(k + 2):
+        out += (-1) ** j * math.comb(k + 1, j) * np.maximum(s + 0.5 * (k + 1) - j, 0.0) ** k
+    out /= math.factorial(k)
+    # the sum cancels to rounding outside the support: make it exact there
+    return np.where(np.abs(s) < 0.5 * (k + 1), out, 0.0)
+
+
+TAPS = 6  # per axis: cells floor(u) - 2 .. floor(u) + 3
+
+
+def taps(u) -> tuple[np.ndarray, np.ndarray]:
+    """First tap cell floor(u) - 2 and the six weights B5(u - c)."""
+    u = np.asarray(u, dtype=np.float64)
+    k0 = np.floor(u).astype(np.int64) - 2
+    c = k0[..., None] + np.arange(TAPS)
+    return k0, bspline(5, u[..., None] - c)
+
+
+def deposit(x, p, du, dv, w) -> np.ndarray:
+    """b = Delta^T w / (h_x h_p) for nodes moved by (du, dv) cells."""
+    n_p, n_x = p.n, x.n
+    jj, ii = np.meshgrid(np.arange(n_p), np.arange(n_x), indexing="ij")
+    kx, bx = taps(ii + np.asarray(du, dtype=np.float64))
+    kp, bp = taps(jj + np.asarray(dv, dtype=np.float64))
+    b = np.zeros((n_p, n_x))
+    w = np.asarray(w, dtype=np.float64)
+    for q in range(TAPS):
+        rows = kp + q
+        rows = np.mod(rows, n_p) if p.periodic else rows
+        for r in range(TAPS):
+            cols = kx + r
+            cols = np.mod(cols, n_x) if x.periodic else cols
+            # on an open axis, taps past the edge nodes are dropped
+            keep = (rows >= 0) & (rows < n_p) & (cols >= 0) & (cols < n_x)
+            np.add.at(b, (rows[keep], cols[keep]), (w * bp[..., q] * bx[..., r])[keep])
+    return b
+
+
+def mass_line(n: int, periodic: bool) -> np.ndarray:
+    """M along one axis: B5 at the integer offsets, wrapped on a periodic axis."""
+    M = np.zeros((n, n))
+    for a in range(n):
+        for d in range(-2, 3):
+            bval = float(bspline(5, d))
+            if periodic:
+                M[a, (a + d) % n] += bval
+            elif 0 <= a + d < n:
+                M[a, a + d] += bval
+    return M
+
+
+def solve(x, p, b) -> np.ndarray:
+    """(M_x^{-1} (x) M_p^{-1}) b: dense solves along each axis."""
+    b = np.asarray(b, dtype=np.float64)
+    y = np.linalg.solve(mass_line(x.n, x.periodic), b.T).T
+    return np.linalg.solve(mass_line(p.n, p.periodic), y)
+
+
+def step(x, p, du, dv, w) -> np.ndarray:
+    return solve(x, p, deposit(x, p, du, dv, w))
+
+
+def run(x, p, ham, w0, dt, steps) -> np.ndarray:
+    """``steps`` steps of a Hamiltonian whose push does not depend on the
+    state (free streaming, the exact rotation, the pendulum)."""
+    du, dv = _push(x, p, ham, dt)
+    w = np.array(w0, dtype=np.float64, copy=True)
+    for _ in range(int(steps)):
+        w = step(x, p, du, dv, w)
+    return w
