@@ -64,6 +64,35 @@ def bench_fel(binding, steps, integrator=0):
             "ms_per_step": 1e3 * sec / steps, "A_abs": abs(complex(m["A_re"], m["A_im"]))}
 
 
+def bench_quadratic(binding, n, steps, warmup):
+    """The headline workload (pendulum band, n^2) with quadratic B-spline basis
+    functions: autotuned deposit tiles, graph replay; per-kernel times and
+    the negative mass beside the tent basis's after the same steps."""
+    from paper_2007_12227_amd.inputs import pendulum_band
+    inst = pendulum_band(n)
+    out = {"workload": f"pendulum_band_{n}_quadratic", "steps": steps}
+    for basis, tag in ((binding.BASIS_QUADRATIC, ""), (binding.BASIS_TENT, "tent_")):
+        g = binding.Grid(inst.x, inst.p)
+        g.set_basis(basis)
+        g.set_hamiltonian(inst.ham)
+        g.set_density(inst.w0)
+        if basis == binding.BASIS_QUADRATIC:
+            g.autotune(inst.dt)
+            sec, _ = timed_steps(g, inst.dt, steps, warmup)
+            out.update(value=inst.nodes * steps / sec, ms_per_step=1e3 * sec / steps, tiles=g.tiles()["k1"])
+            kus = dict(zip(KERNELS, g.step_timed(inst.dt, min(steps, 200))))
+            out["kernels_us"] = kus
+            out["kernel_roofline_frac"] = {k: ALG_BYTES_PER_NODE * inst.nodes / (v * 1e-6) / 1e9 / HBM_PEAK_GBS
+                                           for k, v in kus.items()}
+        else:
+            g.autotune(inst.dt, cached=True)
+            g.step(inst.dt, steps + warmup)
+        m = g.moments()
+        g.close()
+        out[tag + "neg_mass_fraction"] = m["neg_mass"] / m["mass"]
+    return out
+
+
 def bench_batched(binding, steps, count):
     """256 pendulum instances, n log-uniform in [64, 1024], one launch per kernel
     per step for all of them, against each instance run alone (plain)."""
@@ -188,6 +217,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--fel-steps", type=int, default=2000)
+    ap.add_argument("--quadratic-steps", type=int, default=1000)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-overload", type=float, default=1.2,
@@ -286,6 +316,8 @@ def main():
         log(f"fel: {line['fel']}")
         line["fel_rk4"] = bench_fel(binding, args.fel_steps, integrator=1)
         log(f"fel_rk4: {line['fel_rk4']}")
+        line["quadratic"] = bench_quadratic(binding, args.n, args.quadratic_steps, args.warmup)
+        log(f"quadratic: {line['quadratic']}")
         line["batched"] = bench_batched(binding, args.batch_steps, args.batch_count)
         log(f"batched: {line['batched']}")
         line["served"] = bench_served(binding, args.serve_requests, args.serve_load,

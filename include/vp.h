@@ -13,6 +13,11 @@
  * (eq. 9).  Coordinates are periodic and momenta open (Sec. "Numerical
  * Examples"); weight pushed past an open edge is lost.
  *
+ * The tents can be replaced by quadratic B-spline basis functions, the
+ * smoother local basis the paper's discussion proposes (vp_set_basis): the
+ * overlaps of eq. 9 become quintic B-spline weights on 6 x 6 nodes and the
+ * mass matrix of eq. 8 the pentadiagonal (1/120)[1, 26, 66, 26, 1] per axis.
+ *
  * Conventions for every call:
  *  - return 0 on success, a negative VP_E* code on failure; no call throws;
  *    vp_last_error() gives a thread-local message for the last failure;
@@ -49,6 +54,10 @@ extern "C" {
 #define VP_H_SHO_EXACT 1  /* H = (p^2+x^2)/2 advanced by its exact rotation (Sec. Harmonic Oscillators) */
 #define VP_H_PENDULUM 2   /* H = p^2/2 - a cos x, drift-kick-drift leapfrog (Sec. Harmonic Oscillators) */
 #define VP_H_FEL 3        /* 1-D FEL, eqs. 13a-c, self-consistent field A (Sec. FEL simulations) */
+
+/* Basis functions of the expansion (vp_set_basis) */
+#define VP_BASIS_TENT 0      /* tents, eq. 4 (the default) */
+#define VP_BASIS_QUADRATIC 1 /* centred quadratic B-splines of width 3h on every node */
 
 /* FEL integrators */
 #define VP_FEL_DKD 0 /* drift dz/2, exact kick dz, drift dz/2 (one bunching per step) */
@@ -101,14 +110,16 @@ typedef struct {
 } vp_hamiltonian;
 
 /* Diagnostics (Sec. "Numerical Examples": phase-space volume and entropy),
- * accumulated in FP64.  With the tent basis, integrals of f are exact sums:
+ * accumulated in FP64.  Integrals of f are exact sums (either basis):
  *  sum_w    = sum_j w_j
  *  mass     = h_x h_p sum_j w_j                      (integral of f)
  *  neg_mass = -h_x h_p sum_{w_j<0} w_j
  *  l1       = h_x h_p sum_j |w_j|
  *  entropy  = -h_x h_p sum_{w_j>0} w_j ln w_j
  *  mean_p   = sum_j w_j p_j / sum_j w_j
- *  energy   = integral of H f; exact tent integrals of p^2, x^2 and cos x
+ *  energy   = integral of H f; exact integrals of p^2, x^2 and cos x over the
+ *             basis functions (h^2/6 and sinc^2(h/2) for tents, h^2/4 and
+ *             sinc^3(h/2) for quadratic B-splines)
  *  FEL: A, bunching <e^{-i psi}> at the lattice phases, and
  *       fel_invariant = |A|^2 + N0^{-1} sum_j w_j eta_j (conserved by the step)
  *  nonfinite = number of NaN/Inf weights (the call then returns VP_ENONFINITE).
@@ -125,7 +136,8 @@ typedef struct {
 
 /* Launch shape of the deposit kernel: destination tile (in lattice nodes) and
  * threads per workgroup (a multiple of 64, at most 1024).  Zero fields keep
- * the current value.  (The solve works on fixed tiles of 32 x 64 nodes.) */
+ * the current value.  (The solve works on fixed tiles of 32 x 64 nodes, or
+ * of 80 x 80 nodes with the quadratic basis.) */
 typedef struct {
     int32_t k1_tx, k1_ty;
     int32_t k1_threads;
@@ -150,6 +162,16 @@ int vp_set_hamiltonian(vp_grid* g, const vp_hamiltonian* h);
  * clears the range flag and resets the step counter.  VP_ENONFINITE if a
  * weight is NaN or infinite (the grid then holds no density). */
 int vp_set_density(vp_grid* g, const float* w, int32_t on_device);
+
+/* Choose the basis functions (VP_BASIS_TENT or VP_BASIS_QUADRATIC; VP_EINVAL
+ * otherwise).  The weights are read as coefficients of the chosen basis from
+ * the next step on; the density already set is kept as it is.  The quadratic
+ * basis serves the FREE, SHO_EXACT and PENDULUM Hamiltonians: vp_step returns
+ * VP_EUNSUPPORTED for the FEL with it.  A deposit tile whose local memory no
+ * longer fits with the wider border of the quadratic basis is replaced by
+ * the default shape.  VP_ESTATE while the grid belongs to a batch; a batch
+ * takes grids of one basis (VP_EUNSUPPORTED otherwise). */
+int vp_set_basis(vp_grid* g, int32_t basis);
 
 /* Copy the current weights out (n_p*n_x floats). */
 int vp_get_density(vp_grid* g, float* w, int32_t on_device);
@@ -203,13 +225,13 @@ const char* vp_last_error(void);
 
 /* Host-side planning helper (no GPU needed): the source box a deposit tile
  * scans.  Destination tile rows [by0,by1) and columns [bx0,bx1) of a grid with
- * axes x, p under Hamiltonian h, step dt and (FEL) kick field
- * kick_re + i kick_im.  box[4] receives [x0, x1, y0, y1): unwrapped source
- * columns and source rows.  Every node whose pushed position deposits into
- * the tile lies in the box. */
-int vp_plan_source_box(const vp_axis* x, const vp_axis* p, const vp_hamiltonian* h, double dt,
-                       double kick_re, double kick_im, int32_t bx0, int32_t bx1, int32_t by0,
-                       int32_t by1, int32_t box[4]);
+ * axes x, p and basis functions `basis` under Hamiltonian h, step dt and
+ * (FEL) kick field kick_re + i kick_im.  box[4] receives [x0, x1, y0, y1):
+ * unwrapped source columns and source rows.  Every node whose pushed position
+ * deposits into the tile lies in the box. */
+int vp_plan_source_box(const vp_axis* x, const vp_axis* p, const vp_hamiltonian* h, int32_t basis,
+                       double dt, double kick_re, double kick_im, int32_t bx0, int32_t bx1,
+                       int32_t by0, int32_t by1, int32_t box[4]);
 
 #ifdef __cplusplus
 }

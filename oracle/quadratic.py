@@ -25,6 +25,8 @@ import numpy as np
 
 from . import push as _push
 
+H_SHO_EXACT, H_PENDULUM = 1, 2
+
 
 def bspline(k: int, s) -> np.ndarray:
     """Centred cardinal B-spline of degree k (support [-(k+1)/2, (k+1)/2]):
@@ -101,3 +103,31 @@ def run(x, p, ham, w0, dt, steps) -> np.ndarray:
     for _ in range(int(steps)):
         w = step(x, p, du, dv, w)
     return w
+
+
+def moments(x, p, ham, w) -> dict:
+    """Diagnostics of f = sum_j w_j B2((x - x_j)/h_x) B2((p - p_j)/h_p), the C
+    oracle's quantities with this basis: every basis function integrates to
+    h, its second moment about its centre is h^3/4 (three unit boxes
+    convolved: 3 x 1/12), and its integral against cos x is
+    h sinc(h/2)^3 cos x_j (the transform of a box is a sinc).  The entropy and
+    the negative mass are sums over the weights, as for tents."""
+    w = np.asarray(w, dtype=np.float64)
+    cell = x.h * p.h
+    X, P = np.meshgrid(x.nodes(), p.nodes())
+    e = 0.5 * (P ** 2 + 0.25 * p.h ** 2)
+    if ham.kind == H_PENDULUM:
+        y = 0.5 * x.h
+        e = e - ham.a * (math.sin(y) / y) ** 3 * np.cos(X)
+    elif ham.kind == H_SHO_EXACT:
+        e = e + 0.5 * (X ** 2 + 0.25 * x.h ** 2)
+    pos = w > 0
+    return {
+        "sum_w": float(w.sum()),
+        "mass": cell * float(w.sum()),
+        "neg_mass": -cell * float(w[w < 0].sum()),
+        "l1": cell * float(np.abs(w).sum()),
+        "entropy": -cell * float((w[pos] * np.log(w[pos])).sum()),
+        "mean_p": float((w * P).sum() / w.sum()) if w.sum() != 0 else 0.0,
+        "energy": cell * float((w * e).sum()),
+    }

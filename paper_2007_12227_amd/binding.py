@@ -19,6 +19,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "vp.h")
 
 VP_OK, VP_EINVAL, VP_ENOMEM, VP_ESTATE, VP_EHIP, VP_EUNSUPPORTED, VP_ENONFINITE, VP_ERANGE = 0, -1, -2, -3, -4, -5, -6, -7
 H_FREE, H_SHO_EXACT, H_PENDULUM, H_FEL = 0, 1, 2, 3
+BASIS_TENT, BASIS_QUADRATIC = 0, 1
 
 
 class VpError(RuntimeError):
@@ -96,8 +97,9 @@ def lib(load_torch: bool = True):
     L.vp_status_string.restype = C.c_char_p
     L.vp_status_string.argtypes = [C.c_int]
     L.vp_last_error.restype = C.c_char_p
-    L.vp_plan_source_box.argtypes = [P(Axis), P(Axis), P(Hamiltonian), C.c_double, C.c_double, C.c_double,
-                                     C.c_int32, C.c_int32, C.c_int32, C.c_int32, P(C.c_int32)]
+    L.vp_plan_source_box.argtypes = [P(Axis), P(Axis), P(Hamiltonian), C.c_int32, C.c_double, C.c_double,
+                                     C.c_double, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P(C.c_int32)]
+    L.vp_set_basis.argtypes = [C.c_void_p, C.c_int32]
     for name in declared_functions():
         if name not in ("vp_workspace_bytes", "vp_status_string", "vp_last_error"):
             getattr(L, name).restype = C.c_int
@@ -126,9 +128,9 @@ def workspace_bytes(x, p) -> int:
     return int(lib().vp_workspace_bytes(C.byref(axis(x)), C.byref(axis(p))))
 
 
-def plan_source_box(x, p, ham, dt, kick=0j, bx=(0, 0), by=(0, 0)) -> tuple[int, int, int, int]:
+def plan_source_box(x, p, ham, dt, kick=0j, bx=(0, 0), by=(0, 0), basis=BASIS_TENT) -> tuple[int, int, int, int]:
     box = (C.c_int32 * 4)()
-    check(lib().vp_plan_source_box(C.byref(axis(x)), C.byref(axis(p)), C.byref(hamiltonian(ham)),
+    check(lib().vp_plan_source_box(C.byref(axis(x)), C.byref(axis(p)), C.byref(hamiltonian(ham)), int(basis),
                                    float(dt), float(complex(kick).real), float(complex(kick).imag),
                                    int(bx[0]), int(bx[1]), int(by[0]), int(by[1]), box))
     return tuple(int(v) for v in box)
@@ -175,6 +177,10 @@ class Grid:
 
     def set_hamiltonian(self, ham):
         check(lib().vp_set_hamiltonian(self._h, C.byref(hamiltonian(ham))))
+
+    def set_basis(self, basis: int):
+        """BASIS_TENT or BASIS_QUADRATIC (quadratic B-spline basis functions)."""
+        check(lib().vp_set_basis(self._h, int(basis)))
 
     def set_density(self, w):
         import torch

@@ -41,14 +41,17 @@ constexpr size_t kDefaultLds = 64 * 1024;
 size_t g_max_lds = kDefaultLds;  // raised once per process to what the device allows (160 KiB on gfx950)
 std::once_flag g_lds_once;
 
-// Let both per-step kernels use the device's full LDS per workgroup.
+// Let the deposit kernels use the device's full LDS per workgroup.
 void raise_lds_limit() {
     std::call_once(g_lds_once, [] {
         int dev = 0, lim = 0;
         if (hipGetDevice(&dev) != hipSuccess) return;
         if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return;
         if (lim <= (int)kDefaultLds) return;
-        if (hipFuncSetAttribute(deposit_kernel(), hipFuncAttributeMaxDynamicSharedMemorySize, lim - 1024) != hipSuccess) return;
+        for (int basis : {kBasisTent, kBasisQuadratic})
+            if (hipFuncSetAttribute(deposit_kernel(basis), hipFuncAttributeMaxDynamicSharedMemorySize, lim - 1024) !=
+                hipSuccess)
+                return;
         g_max_lds = (size_t)(lim - 1024);
     });
 }
@@ -118,6 +121,7 @@ struct LaunchList {
     int ninst = 0, total1 = 0, total2 = 0;
     bool has_fel = false;  // an FEL instance: the field kernel follows the solve
     bool has_rk4 = false;  // a Runge-Kutta FEL instance: its stage sums precede the deposit
+    int basis = kBasisTent;  // of every instance in the list
     size_t lds1 = 0;
     int threads1 = 256;  // deposit workgroup size
     hipStream_t stream = nullptr;
@@ -138,8 +142,8 @@ struct LaunchList {
             k[n++] = K{fel_stage_kernel(), d_off2, total2, 0, kStageThreads, 0};
             k[n++] = K{fel_field_kernel(), d_off2, ninst, 0, kFieldThreads, 1};
         }
-        k[n++] = K{deposit_kernel(), d_off1, total1, lds1, threads1, 0};
-        k[n++] = K{solve_kernel(), d_off2, total2, 0, kSolveThreads, 0};
+        k[n++] = K{deposit_kernel(basis), d_off1, total1, lds1, threads1, 0};
+        k[n++] = K{solve_kernel(basis), d_off2, total2, 0, solve_threads(basis), 0};
         if (has_fel) k[n++] = K{fel_field_kernel(), d_off2, ninst, 0, kFieldThreads, 0};
         return n;
     }
@@ -148,8 +152,8 @@ struct LaunchList {
             HIP_TRY(launch_fel_stage(args(d_off2, total2, parity), total2, stream));
             HIP_TRY(launch_fel_field(args(d_off2, ninst, parity, 1), stream));
         }
-        HIP_TRY(launch_deposit(args(d_off1, total1, parity), total1, lds1, threads1, stream));
-        HIP_TRY(launch_solve(args(d_off2, total2, parity), total2, stream));
+        HIP_TRY(launch_deposit(args(d_off1, total1, parity), total1, lds1, threads1, stream, basis));
+        HIP_TRY(launch_solve(args(d_off2, total2, parity), total2, stream, basis));
         if (has_fel) HIP_TRY(launch_fel_field(args(d_off2, ninst, parity), stream));
         return VP_OK;
     }
@@ -224,6 +228,7 @@ struct vp_grid {
     vp_tiles tiles{};
     bool use_graph = true;
     bool in_batch = false;
+    int basis = kBasisTent;
 
     template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
@@ -236,17 +241,16 @@ struct vp_batch {
 
 namespace {
 
-int validate_tiles(const vp_grid* g, const vp_tiles& t) {
+int validate_tiles(int basis, const vp_tiles& t) {
     if (t.k1_tx < kMinTile || t.k1_ty < 1)
         return fail(VP_EINVAL, "deposit tile below the minimum (k1_tx >= %d, k1_ty >= 1)", kMinTile);
     if (t.k1_tx > 4096 || t.k1_ty > 1024) return fail(VP_EINVAL, "deposit tile too large");
     if (t.k1_threads < 64 || t.k1_threads > kDepositMaxThreads || t.k1_threads % 64)
         return fail(VP_EINVAL, "deposit threads %d: need a multiple of 64 in [64, %d]", t.k1_threads,
                     kDepositMaxThreads);
-    if (deposit_lds_bytes(t.k1_tx, t.k1_ty) > g_max_lds)
+    if (deposit_lds_bytes(t.k1_tx, t.k1_ty, basis) > g_max_lds)
         return fail(VP_EINVAL, "deposit tile %dx%d needs %zu bytes of LDS (limit %zu)", t.k1_tx, t.k1_ty,
-                    deposit_lds_bytes(t.k1_tx, t.k1_ty), g_max_lds);
-    (void)g;
+                    deposit_lds_bytes(t.k1_tx, t.k1_ty, basis), g_max_lds);
     return VP_OK;
 }
 
@@ -274,7 +278,7 @@ int upload_inst(vp_grid* g) {
     I.k1_ty = t.k1_ty;
     I.k1_tiles_x = (g->x.n + t.k1_tx - 1) / t.k1_tx;
     I.k1_tiles = I.k1_tiles_x * ((g->p.n + t.k1_ty - 1) / t.k1_ty);
-    I.k2_tiles = ((g->x.n + kSegX - 1) / kSegX) * ((g->p.n + kSegP - 1) / kSegP);
+    I.k2_tiles = solve_tiles(g->x.n, g->p.n, g->basis);
     I.parity0 = 0;
     // source boxes of a push that does not depend on the state: planned here
     // once, instead of by one thread of every deposit tile at every step
@@ -302,7 +306,8 @@ int upload_inst(vp_grid* g) {
     g->list.has_rk4 = I.push.kind == kFel && I.push.rk4;
     g->list.total1 = I.k1_tiles;
     g->list.total2 = I.k2_tiles;
-    g->list.lds1 = deposit_lds_bytes(t.k1_tx, t.k1_ty);
+    g->list.lds1 = deposit_lds_bytes(t.k1_tx, t.k1_ty, g->basis);
+    g->list.basis = g->basis;
     g->list.threads1 = t.k1_threads;
     g->list.drop_graphs();
     return VP_OK;
@@ -316,11 +321,12 @@ void split(double v, float& hi, float& lo) {
 // Push parameters in cell units for step dt (FEL: the kick amplitudes alpha,
 // beta come from the device field at each step; kick_re/kick_im fill them in
 // for host-side planning).
-PushParams push_params(const vp_axis& x, const vp_axis& p, const vp_hamiltonian& H, double dt,
+PushParams push_params(const vp_axis& x, const vp_axis& p, const vp_hamiltonian& H, double dt, int basis,
                        double kick_re = 0.0, double kick_im = 0.0) {
     const double hx = spacing(x), hp = spacing(p);
     PushParams P{};
     P.kind = H.kind;
+    P.wide = basis == kBasisQuadratic ? 1 : 0;
     P.nx = x.n;
     P.np = p.n;
     P.x_periodic = x.periodic ? 1 : 0;
@@ -357,7 +363,7 @@ int plan(vp_grid* g, double dt) {
     const vp_hamiltonian& H = g->ham;
     std::vector<float4> tx(nx), tp(np);
     std::vector<double2> ex(nx), eq(np);
-    g->inst.push = push_params(g->x, g->p, H, dt);
+    g->inst.push = push_params(g->x, g->p, H, dt, g->basis);
     const double delta = H.kind == VP_H_FEL ? H.fel_delta : 0.0;
     if (H.kind == VP_H_SHO_EXACT) {
         const double th = H.omega * dt, c = cos(th), s = sin(th), cm1 = -2.0 * sin(0.5 * th) * sin(0.5 * th);
@@ -426,6 +432,12 @@ int launch_reduce_on(vp_grid* g, int mode, double dt) {
     R.counter = g->at<uint32_t>(g->L.counters) + 1;
     R.out = mode == 1 ? g->at<double>(g->L.fel_state) : g->at<double>(g->L.moments);
     R.dz = dt;
+    // integrals of p^2 and cos x over a basis function (per unit of spacing):
+    // h^2/6 and sinc(h/2)^2 for a tent (its transform is sinc^2), h^2/4 and
+    // sinc(h/2)^3 for the quadratic B-spline (three unit boxes convolved)
+    const double y = 0.5 * R.hx, sc = y == 0.0 ? 1.0 : sin(y) / y;
+    R.var_c = g->basis == kBasisQuadratic ? 0.25 : 1.0 / 6.0;
+    R.cos_fac = g->basis == kBasisQuadratic ? sc * sc * sc : sc * sc;
     HIP_TRY(launch_reduce(R, g->stream));
     return VP_OK;
 }
@@ -436,6 +448,8 @@ int prepare(vp_grid* g, double dt) {
     if (!g->has_ham || !g->has_density)
         return fail(VP_ESTATE, "set the Hamiltonian and the density before stepping");
     if (!isfinite(dt)) return fail(VP_EINVAL, "dt must be finite");
+    if (g->ham.kind == VP_H_FEL && g->basis != kBasisTent)
+        return fail(VP_EUNSUPPORTED, "the FEL runs with the tent basis only");
     if (g->ham.kind == VP_H_FEL && !(g->N0 != 0.0))
         return fail(VP_ESTATE, "the FEL needs a nonzero sum of the initial weights (N0 normalises the bunching)");
     if (!g->plan_valid || g->plan_dt != dt) {
@@ -451,7 +465,7 @@ int prepare(vp_grid* g, double dt) {
 }
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, long>, vp_tiles> g_tune_cache;  // shape class -> tiles
+std::map<std::tuple<int, int, int, long, int>, vp_tiles> g_tune_cache;  // shape class -> tiles
 
 }  // namespace
 
@@ -619,9 +633,9 @@ int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]) {
             HIP_TRY(launch_fel_stage(L.args(L.d_off2, L.total2, par), L.total2, g->stream));
             HIP_TRY(launch_fel_field(L.args(L.d_off2, L.ninst, par, 1), g->stream));
         }
-        HIP_TRY(launch_deposit(L.args(L.d_off1, L.total1, par), L.total1, L.lds1, L.threads1, g->stream));
+        HIP_TRY(launch_deposit(L.args(L.d_off1, L.total1, par), L.total1, L.lds1, L.threads1, g->stream, L.basis));
         HIP_TRY(hipEventRecord(ev[3 * s + 1], g->stream));
-        HIP_TRY(launch_solve(L.args(L.d_off2, L.total2, par), L.total2, g->stream));
+        HIP_TRY(launch_solve(L.args(L.d_off2, L.total2, par), L.total2, g->stream, L.basis));
         if (L.has_fel) HIP_TRY(launch_fel_field(L.args(L.d_off2, L.ninst, par), g->stream));
         HIP_TRY(hipEventRecord(ev[3 * s + 2], g->stream));
     }
@@ -675,6 +689,17 @@ int vp_moments(vp_grid* g, vp_moments_t* out) {
     return VP_OK;
 }
 
+int vp_set_basis(vp_grid* g, int32_t basis) {
+    if (!g) return fail(VP_EINVAL, "null grid");
+    if (basis != VP_BASIS_TENT && basis != VP_BASIS_QUADRATIC) return fail(VP_EINVAL, "unknown basis %d", basis);
+    if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
+    // the deposit tile must still fit the LDS with the basis's border
+    if (validate_tiles(basis, g->tiles) != VP_OK) g->tiles = default_tiles(g->x.n, g->p.n);
+    g->basis = basis;
+    g->plan_valid = false;
+    return VP_OK;
+}
+
 int vp_set_tiles(vp_grid* g, const vp_tiles* t) {
     if (!g || !t) return fail(VP_EINVAL, "null argument");
     if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
@@ -682,7 +707,7 @@ int vp_set_tiles(vp_grid* g, const vp_tiles* t) {
     if (t->k1_tx) n.k1_tx = t->k1_tx;
     if (t->k1_ty) n.k1_ty = t->k1_ty;
     if (t->k1_threads) n.k1_threads = t->k1_threads;
-    int rc = validate_tiles(g, n);
+    int rc = validate_tiles(g->basis, n);
     if (rc) return rc;
     g->tiles = n;
     g->plan_valid = false;
@@ -711,7 +736,8 @@ int vp_autotune(vp_grid* g, double dt, double* best_us) {
     const double hx = spacing(g->x), hp = spacing(g->p);
     const double disp = fabs(dt) * (std::max(fabs(g->p.lo), fabs(g->p.hi)) / hx + fabs(g->ham.a) / hp);
     const auto key = std::make_tuple((int)g->ham.kind, (int)lround(2.0 * log2((double)g->x.n)),
-                                     (int)lround(2.0 * log2((double)g->p.n)), (long)lround(2.0 * log2(1.0 + disp)));
+                                     (int)lround(2.0 * log2((double)g->p.n)), (long)lround(2.0 * log2(1.0 + disp)),
+                                     g->basis);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -735,7 +761,7 @@ int vp_autotune(vp_grid* g, double dt, double* best_us) {
     HIP_TRY(ev.create());
     hipEvent_t e0 = ev[0], e1 = ev[1];
     auto time_tiles = [&](const vp_tiles& t, float* us) -> int {
-        if (validate_tiles(g, t)) return VP_EINVAL;
+        if (validate_tiles(g->basis, t)) return VP_EINVAL;
         g->tiles = t;
         g->plan_valid = false;
         int r = prepare(g, dt);
@@ -794,6 +820,8 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
         if (!grids[k]) return fail(VP_EINVAL, "null grid %d", k);
         if (grids[k]->in_batch) return fail(VP_ESTATE, "grid %d already belongs to a batch", k);
         if (grids[k]->stream != s) return fail(VP_EINVAL, "grid %d is on another stream than grid 0", k);
+        if (grids[k]->basis != grids[0]->basis)
+            return fail(VP_EUNSUPPORTED, "grid %d has another basis than grid 0 (a batch runs one basis)", k);
         for (int q = 0; q < k; ++q)
             if (grids[q] == grids[k]) return fail(VP_EINVAL, "grid %d listed twice", k);
     }
@@ -818,7 +846,7 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
         insts[k].parity0 = grids[k]->parity;
         off1[k + 1] = off1[k] + insts[k].k1_tiles;
         off2[k + 1] = off2[k] + insts[k].k2_tiles;
-        lds1 = std::max(lds1, deposit_lds_bytes(insts[k].k1_tx, insts[k].k1_ty));
+        lds1 = std::max(lds1, deposit_lds_bytes(insts[k].k1_tx, insts[k].k1_ty, grids[k]->basis));
     }
     vp_batch* b = new vp_batch();
     b->grids.assign(grids, grids + n);
@@ -834,6 +862,7 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
     }
     L.lds1 = lds1;
     L.threads1 = threads1;
+    L.basis = grids[0]->basis;
     hipError_t e = hipMalloc(&L.d_inst, sizeof(VpInst) * n);
     if (e == hipSuccess) e = hipMalloc(&L.d_off1, sizeof(int32_t) * 2 * (n + 1));
     L.d_off2 = L.d_off1 + (n + 1);
@@ -893,10 +922,12 @@ const char* vp_status_string(int s) {
 
 const char* vp_last_error(void) { return g_err; }
 
-int vp_plan_source_box(const vp_axis* x, const vp_axis* p, const vp_hamiltonian* h, double dt, double kick_re,
-                       double kick_im, int32_t bx0, int32_t bx1, int32_t by0, int32_t by1, int32_t box[4]) {
+int vp_plan_source_box(const vp_axis* x, const vp_axis* p, const vp_hamiltonian* h, int32_t basis, double dt,
+                       double kick_re, double kick_im, int32_t bx0, int32_t bx1, int32_t by0, int32_t by1,
+                       int32_t box[4]) {
     if (!axis_ok(x) || !axis_ok(p) || !h || !box) return fail(VP_EINVAL, "invalid argument");
-    PushParams P = push_params(*x, *p, *h, dt, kick_re, kick_im);
+    if (basis != VP_BASIS_TENT && basis != VP_BASIS_QUADRATIC) return fail(VP_EINVAL, "unknown basis %d", basis);
+    PushParams P = push_params(*x, *p, *h, dt, basis, kick_re, kick_im);
     int b[4];
     source_box(P, bx0, bx1, by0, by1, b);
     for (int k = 0; k < 4; ++k) box[k] = b[k];

@@ -17,6 +17,10 @@
 //              rows, one line per lane.  For the FEL its epilogue also forms
 //              the FP64 bunching partials of the new state, which k_fel_field
 //              sums to advance the FEL field.
+// With quadratic B-spline basis functions in place of tents (the smoother
+// basis the paper's discussion proposes) the overlaps are quintic B-splines:
+// k_deposit scatters 6x6 taps per node, and k_solve_q solves the
+// pentadiagonal mass matrix (1/120)[1, 26, 66, 26, 1] along both axes.
 #pragma once
 
 #include <stdint.h>
@@ -47,6 +51,16 @@ constexpr int kReduceBlocks = 256;
 constexpr int kReduceThreads = 256;
 constexpr int kMoments = 10;      // FP64 sums produced by the reduction kernel
 
+// Basis functions of the expansion: tents (eq. 4), or quadratic B-splines.
+enum Basis : int32_t { kBasisTent = 0, kBasisQuadratic = 1 };
+constexpr int kPadQ = 6;          // quadratic basis: trash border of a deposit tile (5 taps past it, even for alignment)
+constexpr int kHaloQ = 24;        // quadratic basis: warm-up nodes per side of a solve tile (0.4306^24 ~ 1.6e-9)
+constexpr int kSegQ = 80;         // quadratic basis: solve tile of kSegQ x kSegQ kept nodes
+constexpr int kLineQ = kSegQ + 2 * kHaloQ;  // its window line (both axes)
+constexpr int kPitchQ = kLineQ + 1;         // LDS row pitch of the window (odd: rows and columns are conflict-free)
+constexpr int kSolveQThreads = kLineQ;      // one window line per thread
+constexpr int kEdgeQ = 16;        // nodes from an open edge whose LDL^T coefficients are tabulated
+
 // Parameters of the push in cell units and of the source-box bound.
 //  FREE / PENDULUM / FEL: node (i, j) moves by
 //     dv = alpha cos(phi_i + q_j) + beta sin(phi_i + q_j)
@@ -63,6 +77,7 @@ struct PushParams {
     float kd;
     float c, s;
     int32_t rk4;  // FEL by Runge-Kutta (the deposit reads its stage constants; alpha bounds |dv|)
+    int32_t wide; // 1: quadratic basis functions, whose overlaps reach one cell further (6 taps per axis)
 };
 
 __host__ __device__ inline float vp_floor(float v) {
@@ -104,16 +119,19 @@ __host__ __device__ inline int ifloor(float v) { return (int)vp_floor(v); }
 __host__ __device__ inline int iceil(float v) { return -(int)vp_floor(-v); }
 
 // Box of source nodes [x0,x1) x [y0,y1) (columns unwrapped on a periodic axis)
-// whose moved tents can deposit into destination columns [bx0,bx1) and rows
-// [by0,by1).  A node at cell position (u, v) touches columns floor(u)-1 ..
-// floor(u)+2, so it reaches the tile only if u in [bx0-2, bx1+1) and
-// v in [by0-2, by1+1); one more cell of margin absorbs rounding.  The
-// displacement is bounded by interval arithmetic over the candidate box, then
-// the bound is tightened once with the phase range of that box.
+// whose moved basis functions can deposit into destination columns [bx0,bx1)
+// and rows [by0,by1).  A moved tent at cell position (u, v) touches columns
+// floor(u)-1 .. floor(u)+2, so it reaches the tile only if u in
+// [bx0-2, bx1+1) and v in [by0-2, by1+1) (a quadratic basis function, columns
+// floor(u)-2 .. floor(u)+3: one cell more on each side); one more cell of
+// margin absorbs rounding.  The displacement is bounded by interval
+// arithmetic over the candidate box, then the bound is tightened once with
+// the phase range of that box.
 __host__ __device__ inline void source_box(const PushParams& P, int bx0, int bx1, int by0, int by1,
                                            int box[4]) {
-    const float ulo = (float)bx0 - 3.0f, uhi = (float)bx1 + 2.0f;
-    const float vlo = (float)by0 - 3.0f, vhi = (float)by1 + 2.0f;
+    const float reach = P.wide ? 1.0f : 0.0f;
+    const float ulo = (float)bx0 - 3.0f - reach, uhi = (float)bx1 + 2.0f + reach;
+    const float vlo = (float)by0 - 3.0f - reach, vhi = (float)by1 + 2.0f + reach;
     int x0, x1, y0, y1;
     if (P.kind == kSho) {
         // preimage of the dest rectangle under the rotation: rotate its corners back
@@ -240,20 +258,30 @@ struct ReduceArgs {
     uint32_t* counter;
     double* out;                  // moments: [kMoments]; bunching: fel_state
     double dz;
+    double var_c;                 // integral of s^2 over the basis function of unit width: 1/6 tent, 1/4 quadratic
+    double cos_fac;               // integral of cos over the basis function of width h_x, per h_x: sinc(h_x/2)^(2 or 3)
 };
 
 // launchers (vp_kernels.hip)
-hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s);
-hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s);
+hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s, int basis);
+hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s, int basis);
 hipError_t launch_fel_field(const LaunchArgs& a, hipStream_t s);
 hipError_t launch_fel_stage(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
-const void* deposit_kernel();
-const void* solve_kernel();
+const void* deposit_kernel(int basis);
+const void* solve_kernel(int basis);
+inline int solve_threads(int basis) { return basis == kBasisQuadratic ? kSolveQThreads : kSolveThreads; }
+inline int solve_tiles(int nx, int np, int basis) {
+    if (basis == kBasisQuadratic) return ((nx + kSegQ - 1) / kSegQ) * ((np + kSegQ - 1) / kSegQ);
+    return ((nx + kSegX - 1) / kSegX) * ((np + kSegP - 1) / kSegP);
+}
 const void* fel_field_kernel();
 const void* fel_stage_kernel();
 
-// Deposit LDS image: (tx + 8) x (ty + 8) 64-bit cells.
-inline size_t deposit_lds_bytes(int tx, int ty) { return sizeof(int64_t) * (size_t)(tx + 2 * kPad) * (ty + 2 * kPad); }
+// Deposit LDS image: the tile and its border, (tx + 2 pad) x (ty + 2 pad) 64-bit cells.
+inline size_t deposit_lds_bytes(int tx, int ty, int basis) {
+    const int pad = basis == kBasisQuadratic ? kPadQ : kPad;
+    return sizeof(int64_t) * (size_t)(tx + 2 * pad) * (ty + 2 * pad);
+}
 
 }  // namespace vp

@@ -56,6 +56,38 @@ __device__ inline void bspline_taps(float tf, double (&b)[4]) {
     b[1] = 1.0 - ((b[0] + b[3]) + b[2]);
 }
 
+// Quintic B-spline tap weights B5(t+2), B5(t+1), B5(t), B5(1-t), B5(2-t),
+// B5(3-t) for t in [0,1): the overlaps of a quadratic B-spline basis function
+// moved to cell position k + t with those of nodes k-2 .. k+3.  Each piece as
+// a polynomial in s = 1 - t or in t, times 120:
+//   s^5,  1 + 5s + 10s^2 + 10s^3 + 5s^4 - 5s^5,  26 + 50s + 20s^2 - 20s^3 - 20s^4 + 10s^5,
+// and the same in t from the other end; the tap at cell k is one minus the
+// others (partition of unity), as for the cubic taps.
+__device__ inline void quintic_taps(float tf, double (&b)[6]) {
+#pragma clang fp contract(off)
+    const double c = 1.0 / 120.0;
+    const double t = (double)tf, s = 1.0 - t;
+    auto near = [](double v) {  // 1 + 5v + 10v^2 + 10v^3 + 5v^4 - 5v^5
+        return fma(fma(fma(fma(fma(-5.0, v, 5.0), v, 10.0), v, 10.0), v, 5.0), v, 1.0);
+    };
+    auto mid = [](double v) {  // 26 + 50v + 20v^2 - 20v^3 - 20v^4 + 10v^5
+        return fma(fma(fma(fma(fma(10.0, v, -20.0), v, -20.0), v, 20.0), v, 50.0), v, 26.0);
+    };
+    const double s2 = s * s, t2 = t * t;
+    b[0] = ((s2 * s2) * s) * c;
+    b[1] = near(s) * c;
+    b[3] = mid(t) * c;
+    b[4] = near(t) * c;
+    b[5] = ((t2 * t2) * t) * c;
+    b[2] = 1.0 - ((((b[0] + b[5]) + (b[1] + b[4])) + b[3]));
+}
+
+template <int TAPS>
+__device__ inline void basis_taps(float t, double (&b)[TAPS]) {
+    if constexpr (TAPS == 4) bspline_taps(t, b);
+    else quintic_taps(t, b);
+}
+
 // 1.5 * 2^52: adding it to a value of magnitude below 2^51 leaves the value
 // rounded to the nearest integer in the low bits of the sum's encoding,
 // two's complement on top of the constant's encoding 0x4338 << 48.
@@ -250,8 +282,9 @@ struct RkConsts {
 };
 
 // Push one node (source row j, unwrapped column ii, weight w already scaled to
-// fixed point) and add its 16 B-spline taps into the LDS tile.
-template <int PUSH>
+// fixed point) and add its TAPS x TAPS B-spline taps into the LDS tile: 4 x 4
+// cubic taps for tents, 6 x 6 quintic taps for quadratic basis functions.
+template <int PUSH, int TAPS>
 __device__ inline void deposit_node(long long* acc, int j, int ii, float w, float4 tx, float4 tp,
                                     float alpha, float beta, float kd, const RkConsts& rk, int X0, int Y0,
                                     int tw, int th, int ldw) {
@@ -296,24 +329,29 @@ __device__ inline void deposit_node(long long* acc, int j, int ii, float w, floa
     }
     // tap (q, r) lands on tile row row0 + q, column col0 + r; a node none of
     // whose taps meets the tile adds nothing (its lane sits the taps out).
-    // The test also bounds every access: col0 in [-3, tw) and row0 in
-    // [-3, th) put the taps inside the tile and its border of kPad cells,
-    // whatever the push produced (a non-finite position included).
-    const int col0 = ii + ku - 1 - X0, row0 = j + kv - 1 - Y0;
-    if ((unsigned)(col0 + 3) >= (unsigned)(tw + 3) || (unsigned)(row0 + 3) >= (unsigned)(th + 3)) return;
-    double bx[4], bp[4];
-    bspline_taps(fu, bx);
-    bspline_taps(fv, bp);
-    long long* base = acc + __umul24(row0 + kPad, ldw) + (col0 + kPad);
+    // The test also bounds every access: col0 in [1 - TAPS, tw) and row0 in
+    // [1 - TAPS, th) put the taps inside the tile and its border of PAD >=
+    // TAPS - 1 cells, whatever the push produced (a non-finite position
+    // included).
+    constexpr int LO = TAPS / 2 - 1, PAD = TAPS == 4 ? kPad : kPadQ;
+    static_assert(PAD >= TAPS - 1, "the tile border must take every tap of a node that meets the tile");
+    const int col0 = ii + ku - LO - X0, row0 = j + kv - LO - Y0;
+    if ((unsigned)(col0 + TAPS - 1) >= (unsigned)(tw + TAPS - 1) ||
+        (unsigned)(row0 + TAPS - 1) >= (unsigned)(th + TAPS - 1))
+        return;
+    double bx[TAPS], bp[TAPS];
+    basis_taps<TAPS>(fu, bx);
+    basis_taps<TAPS>(fv, bp);
+    long long* base = acc + __umul24(row0 + PAD, ldw) + (col0 + PAD);
     // tap value w * bp * bx: FP64 product, rounded once, exactly, into the
     // fixed-point tile sum, so the deposit adds no product rounding to the
     // state (the FEL instability amplifies it)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < TAPS; ++q) {
         const double wq = (double)w * bp[q];
         unsigned long long* row = (unsigned long long*)(base + q * ldw);
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) atomicAdd(row + rr, fix48_word(wq, bx[rr]));
+        for (int rr = 0; rr < TAPS; ++rr) atomicAdd(row + rr, fix48_word(wq, bx[rr]));
     }
 }
 
@@ -344,7 +382,7 @@ struct SourceScan {
     RkConsts rk;
 };
 
-template <int PUSH, int COL>
+template <int PUSH, int COL, int TAPS>
 __device__ inline void scan_sources(const SourceScan& S) {
     gfloat* __restrict__ w_g = S.w;
     gfloat4* __restrict__ tab_x = S.tab_x;
@@ -397,7 +435,7 @@ __device__ inline void scan_sources(const SourceScan& S) {
         if (!__any(live)) continue;
 #pragma unroll
         for (int h = 0; h < kU; ++h)
-            deposit_node<PUSH>(S.acc, jj[h], iu, wv[h] * S.scale, tx, tpv[h], S.alpha, S.beta, S.kd, S.rk, S.X0,
+            deposit_node<PUSH, TAPS>(S.acc, jj[h], iu, wv[h] * S.scale, tx, tpv[h], S.alpha, S.beta, S.kd, S.rk, S.X0,
                                S.Y0, S.tw, S.th, S.ldw);
     }
 }
@@ -407,11 +445,13 @@ __device__ inline void scan_sources(const SourceScan& S) {
 // into the LDS image of the destination tile, then write the tile of b once.
 // (Integer LDS atomics: gfx950 executes ds_add_f32 some 40x slower than
 // ds_add_u32, and integer sums are order independent.)
-// LDS holds (tx + 8) x (ty + 8) cells: the tile plus a border of kPad cells
-// that takes the taps of nodes near the tile's edge which fall outside it;
-// they are dropped with it.
+// LDS holds (tx + 2 PAD) x (ty + 2 PAD) cells: the tile plus a border of PAD
+// cells that takes the taps of nodes near the tile's edge which fall outside
+// it; they are dropped with it.  TAPS: 4 (tents) or 6 (quadratic basis).
 // ---------------------------------------------------------------------------
+template <int TAPS>
 __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
+    constexpr int PAD = TAPS == 4 ? kPad : kPadQ;
     extern __shared__ __align__(16) long long acc[];  // 16-byte aligned: read four cells at a time
     __shared__ int s_d, s_box[4], s_next;
     __shared__ float s_ab[2];
@@ -428,7 +468,7 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
         const int nx = I.push.nx, np = I.push.np;
         const int X0 = txi * I.k1_tx, X1 = min(X0 + I.k1_tx, nx);
         const int Y0 = tyi * I.k1_ty, Y1 = min(Y0 + I.k1_ty, np);
-        const int ldw = I.k1_tx + 2 * kPad, ldh = I.k1_ty + 2 * kPad;
+        const int ldw = I.k1_tx + 2 * PAD, ldh = I.k1_ty + 2 * PAD;
         const int par = (I.parity0 + A.parity) & 1;
         const float* __restrict__ w_in = I.w[par];
 
@@ -552,17 +592,17 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
         const bool wrap_near = bx0 >= -nx && bx0 + bw <= 2 * nx;
         const int col = !periodic ? 0 : wrap_near ? 1 : 2;
         if (kind == kSho) {
-            if (col == 0) scan_sources<kPushSho, 0>(S);
-            else if (col == 1) scan_sources<kPushSho, 1>(S);
-            else scan_sources<kPushSho, 2>(S);
+            if (col == 0) scan_sources<kPushSho, 0, TAPS>(S);
+            else if (col == 1) scan_sources<kPushSho, 1, TAPS>(S);
+            else scan_sources<kPushSho, 2, TAPS>(S);
         } else if (rk4) {
-            if (col == 0) scan_sources<kPushRk4, 0>(S);
-            else if (col == 1) scan_sources<kPushRk4, 1>(S);
-            else scan_sources<kPushRk4, 2>(S);
+            if (col == 0) scan_sources<kPushRk4, 0, TAPS>(S);
+            else if (col == 1) scan_sources<kPushRk4, 1, TAPS>(S);
+            else scan_sources<kPushRk4, 2, TAPS>(S);
         } else {
-            if (col == 0) scan_sources<kPushPhase, 0>(S);
-            else if (col == 1) scan_sources<kPushPhase, 1>(S);
-            else scan_sources<kPushPhase, 2>(S);
+            if (col == 0) scan_sources<kPushPhase, 0, TAPS>(S);
+            else if (col == 1) scan_sources<kPushPhase, 1, TAPS>(S);
+            else scan_sources<kPushPhase, 2, TAPS>(S);
         }
         __syncthreads();
 
@@ -582,13 +622,13 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
         // (rr, cc) advance by (T / w, T % w) with one carry.
         if ((I.k1_tx & 3) == 0 && (nx & 3) == 0) {
             // four consecutive cells per item (two 16-byte LDS reads, one
-            // 16-byte store): rows of the tile and of b start 32-byte and
-            // 16-byte aligned
+            // 16-byte store): rows of the tile and of b start 16-byte
+            // aligned (the pad is even)
             const int tq = tw >> 2;
             const int wdr = T / tq, wdc = T - wdr * tq;
             int rr = (int)threadIdx.x / tq, cq = (int)threadIdx.x - rr * tq;
             while (rr < th) {
-                const long long* src = acc + (rr + kPad) * ldw + 4 * cq + kPad;
+                const long long* src = acc + (rr + PAD) * ldw + 4 * cq + PAD;
                 const longlong2 a0 = reinterpret_cast<const longlong2*>(src)[0];
                 const longlong2 a1 = reinterpret_cast<const longlong2*>(src)[1];
                 const float4 o = make_float4(cell(a0.x), cell(a0.y), cell(a1.x), cell(a1.y));
@@ -603,7 +643,7 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
             const int wdr = T / tw, wdc = T - wdr * tw;
             int rr = (int)threadIdx.x / tw, cc = (int)threadIdx.x - rr * tw;
             while (rr < th) {
-                b[(size_t)(Y0 + rr) * nx + X0 + cc] = cell(acc[(rr + kPad) * ldw + cc + kPad]);
+                b[(size_t)(Y0 + rr) * nx + X0 + cc] = cell(acc[(rr + PAD) * ldw + cc + PAD]);
                 cc += wdc;
                 rr += wdr;
                 const bool carry = cc >= tw;
@@ -897,6 +937,151 @@ __global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2
 }
 
 // ---------------------------------------------------------------------------
+// Quadratic basis: the mass matrix (eq. 8) of quadratic B-splines is
+// M = P / 120, P = pentadiag(1, 26, 66, 26, 1), truncated at an open edge.
+// P = L D L^T with L unit lower triangular (row k: l1_k at column k-1, l2_k at
+// column k-2).  On a line that starts at an open edge the factors of its
+// first rows are those of the truncated matrix; they reach the interior limits
+// (l1 = -(r1 + r2), l2 = r1 r2, d = 1 / (r1 r2), with r1 = -0.0431 and
+// r2 = -0.4306 the roots of z^2 + (13 +- sqrt 105) z + 1: P factors into
+// tridiag(1, 13 + sqrt 105, 1) tridiag(1, 13 - sqrt 105, 1) in the interior)
+// to FP32 precision within ~10 rows.  The truncation at the far end of a line
+// changes no factor, so the same table serves lines that end at an edge.
+// ---------------------------------------------------------------------------
+struct PentaLdl {
+    float l1[kEdgeQ + 1], l2[kEdgeQ + 1], dinv[kEdgeQ + 1];  // row kEdgeQ: the interior limits; dinv = 120 / d
+};
+
+constexpr PentaLdl penta_ldl_table() {
+    constexpr int K = 64;
+    double d[K] = {}, l1[K] = {}, l2[K] = {};
+    d[0] = 66.0;
+    l1[1] = 26.0 / d[0];
+    d[1] = 66.0 - l1[1] * l1[1] * d[0];
+    for (int k = 2; k < K; ++k) {
+        l2[k] = 1.0 / d[k - 2];
+        l1[k] = (26.0 - l2[k] * l1[k - 1] * d[k - 2]) / d[k - 1];
+        d[k] = 66.0 - l1[k] * l1[k] * d[k - 1] - l2[k] * l2[k] * d[k - 2];
+    }
+    PentaLdl T{};
+    for (int k = 0; k <= kEdgeQ; ++k) {
+        const int r = k < kEdgeQ ? k : K - 1;
+        T.l1[k] = (float)l1[r];
+        T.l2[k] = (float)l2[r];
+        T.dinv[k] = (float)(120.0 / d[r]);
+    }
+    return T;
+}
+constexpr PentaLdl kPentaLdl = penta_ldl_table();
+
+// Solve M y = v in place along one window line, element k at v[k * S], k < n.
+// EDGE: the line starts at an open edge (the tabulated first rows); else it
+// starts at a cut inside the lattice or on a periodic wrap, where the
+// recursions start from zero with the interior factors, an error that decays
+// by 0.4306 per node.  The far end needs no flag (see above); a cut there
+// starts the backward recursion from zero, with the same decay.  The values go
+// through registers U at a time, so the loads of a group issue together.
+template <int S>
+__device__ inline void penta_line(float* v, int n, bool edge) {
+    constexpr int U = 8;
+    static_assert(kEdgeQ % U == 0, "a group of rows is wholly inside or outside the table");
+    // forward: z_k = v_k - l1_k z_{k-1} - l2_k z_{k-2};  v_k <- z_k / d_k
+    float z1 = 0.0f, z2 = 0.0f;
+    for (int k0 = 0; k0 < n; k0 += U) {
+        float r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) r[u] = k0 + u < n ? v[(k0 + u) * S] : 0.0f;
+        const bool tab = edge && k0 < kEdgeQ;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = tab ? k0 + u : kEdgeQ;
+            const float z = fmaf(-kPentaLdl.l2[k], z2, fmaf(-kPentaLdl.l1[k], z1, r[u]));
+            z2 = z1;
+            z1 = z;
+            r[u] = z * kPentaLdl.dinv[k];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u < n) v[(k0 + u) * S] = r[u];
+    }
+    // backward: y_k = v_k - l1_{k+1} y_{k+1} - l2_{k+2} y_{k+2}
+    float y1 = 0.0f, y2 = 0.0f;
+    for (int k1 = n - 1; k1 >= 0; k1 -= U) {
+        float r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) r[u] = k1 - u >= 0 ? v[(k1 - u) * S] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k1 - u;
+            const int a1 = edge && k + 1 < kEdgeQ ? k + 1 : kEdgeQ;
+            const int a2 = edge && k + 2 < kEdgeQ ? k + 2 : kEdgeQ;
+            const float y = fmaf(-kPentaLdl.l2[a2], y2, fmaf(-kPentaLdl.l1[a1], y1, r[u]));
+            y2 = y1;
+            y1 = y;
+            r[u] = y;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k1 - u >= 0) v[(k1 - u) * S] = r[u];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_solve_q: w_new = (M_x^{-1} (x) M_p^{-1}) b for quadratic basis functions.
+// A workgroup of kLineQ threads owns a kSegQ x kSegQ output tile and holds the
+// window around it in LDS (kHaloQ more nodes per side, wrapped on a periodic
+// axis and shifted to end at the edge on an open one; a lattice narrower than
+// the window is taken whole): thread c loads window column c, solves it along
+// p, then thread r solves kept row r along x, and the kept nodes go out.
+// The window's pitch is odd, so both the column and the row passes address
+// LDS without bank conflicts.  The basis is not used with the FEL.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kSolveQThreads) void k_solve_q(LaunchArgs A) {
+    __shared__ float win[kLineQ * kPitchQ];
+    __shared__ int s_d;
+    const int tid = threadIdx.x;
+    for (int it = blockIdx.x; it < A.total; it += gridDim.x) {
+        const int item = tile_of(it, A.total);
+        if (tid == 0) s_d = find_instance(A.off, A.ninst, item);
+        __syncthreads();
+        const int d = __builtin_amdgcn_readfirstlane(s_d);
+        const VpInst& I = A.inst[d];
+        const int t = item - A.off[d];
+        const int nx = I.push.nx, np = I.push.np;
+        const bool periodic = I.push.x_periodic != 0;
+        const int tiles_x = (nx + kSegQ - 1) / kSegQ;
+        const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
+        const int X0 = txi * kSegQ, kw = min(kSegQ, nx - X0);
+        const int P0 = tyi * kSegQ, kp = min(kSegQ, np - P0);
+        // windows: columns [xs, xs + lx) (unwrapped on a periodic axis), rows [ps, ps + lp)
+        const int lx = periodic ? kw + 2 * kHaloQ : min(nx, kLineQ);
+        const int xs = periodic ? X0 - kHaloQ : max(0, min(X0 - kHaloQ, nx - lx));
+        const int lp = min(np, kLineQ);
+        const int ps = max(0, min(P0 - kHaloQ, np - lp));
+        const int ox = X0 - xs, op = P0 - ps;  // the kept nodes: window columns ox .. ox + kw, rows op .. op + kp
+        const int par = (I.parity0 + A.parity) & 1;
+        const float* __restrict__ b = I.b;
+        float* __restrict__ dst = I.w[par ^ 1];
+
+        if (tid < lx) {
+            const int col = periodic ? wrap_index(xs + tid, nx, 1.0f / (float)nx) : xs + tid;
+            const float* src = b + (size_t)ps * nx + col;
+            for (int r = 0; r < lp; ++r) win[r * kPitchQ + tid] = src[(size_t)r * nx];
+        }
+        __syncthreads();
+        if (tid < lx) penta_line<kPitchQ>(win + tid, lp, ps == 0);
+        __syncthreads();
+        if (tid < kp) penta_line<1>(win + (op + tid) * kPitchQ, lx, !periodic && xs == 0);
+        __syncthreads();
+        if (tid < kw) {
+            float* out = dst + (size_t)P0 * nx + X0 + tid;
+            for (int r = 0; r < kp; ++r) out[(size_t)r * nx] = win[(op + r) * kPitchQ + ox + tid];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_fel_field: one workgroup per instance of the launch list; for an FEL
 // instance it sums the per-tile bunching partials of the preceding kernel in a
 // fixed order (thread-strided, then a fixed shuffle tree) and advances the
@@ -1073,11 +1258,6 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
 #pragma unroll
     for (int k = 0; k < kMoments; ++k) acc[k] = 0.0;
     const long n = (long)R.nx * R.np;
-    const double cosfac = [&] {
-        double y = 0.5 * R.hx;
-        double sc = y == 0.0 ? 1.0 : sin(y) / y;
-        return sc * sc;
-    }();
     for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
         const int j = (int)(k / R.nx), i = (int)(k - (long)j * R.nx);
         const double w = (double)R.w[k];
@@ -1099,9 +1279,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
         acc[2] += fabs(w);
         if (w > 0.0) acc[3] += w * log(w);
         acc[4] += w * p;
-        double e = 0.5 * (p * p + R.hp * R.hp / 6.0);
-        if (R.kind == kPendulum) e -= R.a * cosfac * cos(x);
-        else if (R.kind == kSho) e += 0.5 * (x * x + R.hx * R.hx / 6.0);
+        double e = 0.5 * (p * p + R.hp * R.hp * R.var_c);
+        if (R.kind == kPendulum) e -= R.a * R.cos_fac * cos(x);
+        else if (R.kind == kSho) e += 0.5 * (x * x + R.hx * R.hx * R.var_c);
         acc[5] += w * e;
         if (R.kind == kFel) {
             acc[6] += w * cos(x);
@@ -1151,13 +1331,15 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
     }
 }
 
-hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s) {
-    hipLaunchKernelGGL(k_deposit, dim3(grid), dim3(threads), lds, s, a);
+hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s, int basis) {
+    if (basis == kBasisQuadratic) hipLaunchKernelGGL(k_deposit<6>, dim3(grid), dim3(threads), lds, s, a);
+    else hipLaunchKernelGGL(k_deposit<4>, dim3(grid), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_solve, dim3(grid), dim3(kSolveThreads), 0, s, a);
+hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s, int basis) {
+    if (basis == kBasisQuadratic) hipLaunchKernelGGL(k_solve_q, dim3(grid), dim3(kSolveQThreads), 0, s, a);
+    else hipLaunchKernelGGL(k_solve, dim3(grid), dim3(kSolveThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1176,8 +1358,13 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-const void* deposit_kernel() { return reinterpret_cast<const void*>(&k_deposit); }
-const void* solve_kernel() { return reinterpret_cast<const void*>(&k_solve); }
+const void* deposit_kernel(int basis) {
+    return basis == kBasisQuadratic ? reinterpret_cast<const void*>(&k_deposit<6>)
+                                    : reinterpret_cast<const void*>(&k_deposit<4>);
+}
+const void* solve_kernel(int basis) {
+    return basis == kBasisQuadratic ? reinterpret_cast<const void*>(&k_solve_q) : reinterpret_cast<const void*>(&k_solve);
+}
 const void* fel_field_kernel() { return reinterpret_cast<const void*>(&k_fel_field); }
 const void* fel_stage_kernel() { return reinterpret_cast<const void*>(&k_fel_stage); }
 

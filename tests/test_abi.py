@@ -69,7 +69,9 @@ def test_status_strings(L):
 
 # ---- the deposit tile's source box: every node that reaches the tile is in it ----
 
-def _check_box(x, p, ham, dt, kick, tile, box):
+def _check_box(x, p, ham, dt, kick, tile, box, wide=0):
+    """A moved tent at cell position u touches columns floor(u)-1 .. floor(u)+2;
+    a quadratic basis function (wide=1) floor(u)-2 .. floor(u)+3."""
     du, dv = oracle.push(x, p, ham, dt, None if kick is None else np.array([kick.real, kick.imag]))
     bx0, bx1, by0, by1 = tile
     x0, x1, y0, y1 = box
@@ -77,10 +79,10 @@ def _check_box(x, p, ham, dt, kick, tile, box):
     u = i + du
     v = j + dv
     ku, kv = np.floor(u), np.floor(v)
-    row_hit = (kv >= by0 - 2) & (kv <= by1)
+    row_hit = (kv >= by0 - 2 - wide) & (kv <= by1 + wide)
     shifts = range(-3, 4) if x.periodic else (0,)
     for m in shifts:
-        col_hit = (ku + m * x.n >= bx0 - 2) & (ku + m * x.n <= bx1)
+        col_hit = (ku + m * x.n >= bx0 - 2 - wide) & (ku + m * x.n <= bx1 + wide)
         hit = row_hit & col_hit
         ii = i[hit] + m * x.n
         jj = j[hit]
@@ -88,8 +90,9 @@ def _check_box(x, p, ham, dt, kick, tile, box):
         assert np.all((jj >= y0) & (jj < y1)), (tile, box, jj.min(), jj.max())
 
 
+@pytest.mark.parametrize("basis", [B.BASIS_TENT, B.BASIS_QUADRATIC])
 @pytest.mark.parametrize("seed", range(6))
-def test_source_box_contains_every_reaching_node(seed):
+def test_source_box_contains_every_reaching_node(seed, basis):
     g = rng(100 + seed)
     for _ in range(12):
         kind = [H_FREE, H_PENDULUM, H_FEL, H_SHO_EXACT][g.integers(0, 4)]
@@ -115,8 +118,8 @@ def test_source_box_contains_every_reaching_node(seed):
         bx0 = int(g.integers(0, x.n)) // tx * tx
         by0 = int(g.integers(0, p.n)) // ty * ty
         tile = (bx0, min(bx0 + tx, x.n), by0, min(by0 + ty, p.n))
-        box = B.plan_source_box(x, p, ham, dt, kick if kick is not None else 0j, tile[:2], tile[2:])
-        _check_box(x, p, ham, dt, kick, tile, box)
+        box = B.plan_source_box(x, p, ham, dt, kick if kick is not None else 0j, tile[:2], tile[2:], basis)
+        _check_box(x, p, ham, dt, kick, tile, box, wide=basis)
 
 
 def test_source_box_is_tight_for_smooth_pendulum():

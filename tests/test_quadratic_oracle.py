@@ -192,3 +192,40 @@ def test_pendulum_run_conserves_mass_away_from_the_edges():
     w0 = np.exp(-(X ** 2 + P ** 2) / (2 * 0.5 ** 2))
     w = Q.run(x, p, Hamiltonian(H_PENDULUM, a=1.0), w0, 0.1, 20)
     assert abs(w.sum() - w0.sum()) <= 1e-10 * w0.sum()
+
+
+@pytest.mark.parametrize("kind", [H_PENDULUM, H_SHO_EXACT])
+def test_moments_are_integrals_of_the_expansion(kind):
+    """Mass and energy of f = sum w_j B2 B2 on 9 x 7 nodes against quadrature
+    of f itself (per axis: every polynomial piece of each basis function)."""
+    if kind == H_PENDULUM:
+        x, p = Axis(-math.pi, math.pi, 9, True), Axis(-2.0, 2.0, 7, False)
+        ham = Hamiltonian(kind, a=1.3)
+    else:
+        x, p = Axis(-2.0, 2.5, 9, False), Axis(-2.0, 2.0, 7, False)
+        ham = Hamiltonian(kind, omega=1.0)
+    w = rng(904).random((p.n, x.n)) - 0.2
+
+    def integral(axis, j, g):
+        c = axis.lo + j * axis.h
+        total = 0.0
+        for k in range(3):
+            lo = c + (k - 1.5) * axis.h
+            mid, half = lo + 0.5 * axis.h, 0.5 * axis.h
+            for xg, wg in zip(*np.polynomial.legendre.leggauss(12)):
+                t = mid + half * xg
+                total += half * wg * b2((t - c) / axis.h) * g(t)
+        return total
+
+    one_x = np.array([integral(x, i, lambda t: 1.0) for i in range(x.n)])
+    one_p = np.array([integral(p, j, lambda t: 1.0) for j in range(p.n)])
+    p2 = np.array([integral(p, j, lambda t: 0.5 * t * t) for j in range(p.n)])
+    if kind == H_PENDULUM:
+        vx = np.array([integral(x, i, lambda t: -ham.a * math.cos(t)) for i in range(x.n)])
+    else:
+        vx = np.array([integral(x, i, lambda t: 0.5 * t * t) for i in range(x.n)])
+    mass = float((w * np.outer(one_p, one_x)).sum())
+    energy = float((w * (np.outer(p2, one_x) + np.outer(one_p, vx))).sum())
+    m = Q.moments(x, p, ham, w)
+    assert abs(m["mass"] - mass) <= 1e-13
+    assert abs(m["energy"] - energy) <= 1e-12 * abs(energy)
