@@ -227,6 +227,8 @@ def main():
                     help="deposit launch shape COLSxROWSxTHREADS for the tuned path instead of autotuning "
                          "(uniform dispatches for profiling)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (untuned, no graph) run")
+    ap.add_argument("--basis", choices=("tent", "quadratic"), default="tent",
+                    help="basis functions of the timed workload (quadratic: for profiling its kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -242,6 +244,14 @@ def main():
     binding.lib()
     inst = pendulum_band(args.n)
     N = inst.nodes
+    quad = args.basis == "quadratic"
+    workload = f"pendulum_band_{args.n}" + ("_quadratic" if quad else "")
+
+    def grid_of(inst):
+        g = binding.grid_for(inst)
+        if quad:
+            g.set_basis(binding.BASIS_QUADRATIC)
+        return g
 
     if args.copy_probe:
         a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
@@ -253,7 +263,7 @@ def main():
     # plain path: default tiles, one launch per kernel
     plain = plain_s = None
     if not args.no_plain:
-        gp = binding.grid_for(inst)
+        gp = grid_of(inst)
         gp.set_launch(False)
         plain_s, _ = timed_steps(gp, inst.dt, args.steps, args.warmup)
         gp.close()
@@ -261,7 +271,7 @@ def main():
         log(f"plain: {plain:.3e} node-steps/s ({1e6 * plain_s / args.steps:.2f} us/step)")
 
     # tuned path: autotuned deposit tiles, steps replayed from HIP graphs
-    g = binding.grid_for(inst)
+    g = grid_of(inst)
     if args.tiles:
         tx, ty, nt = (int(v) for v in args.tiles.lower().split("x"))
         g.set_tiles((tx, ty), nt)
@@ -283,7 +293,7 @@ def main():
     dom = max(kus, key=kus.get)
     alg_bytes = ALG_BYTES_PER_NODE * N  # per launch of either step kernel
     achieved = alg_bytes / (kus[dom] * 1e-6) / 1e9
-    traffic = measured_traffic(dom, f"pendulum_band_{args.n}", deposit_shape(tiles))
+    traffic = measured_traffic(dom, workload, deposit_shape(tiles))
 
     line = {
         "metric": METRIC,
@@ -298,7 +308,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"pendulum_band_{args.n}", "nx": args.n, "np": args.n, "dt": inst.dt,
+        "config": {"workload": workload, "nx": args.n, "np": args.n, "dt": inst.dt,
                    "a": 1.0, "deposit_tiles": tiles["k1"], "deposit_threads": tiles["threads"],
                    "launch": "hip-graph"},
         "plain": None if plain is None else {"value": plain, "ms_per_step": 1e3 * plain_s / args.steps,

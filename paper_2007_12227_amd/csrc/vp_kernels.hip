@@ -995,7 +995,7 @@ __device__ inline void penta_line(float* v, int n, bool edge) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = tab ? k0 + u : kEdgeQ;
-            const float z = fmaf(-kPentaLdl.l2[k], z2, fmaf(-kPentaLdl.l1[k], z1, r[u]));
+            const float z = fmaf(-kPentaLdl.l1[k], z1, fmaf(-kPentaLdl.l2[k], z2, r[u]));
             z2 = z1;
             z1 = z;
             r[u] = z * kPentaLdl.dinv[k];
@@ -1015,7 +1015,7 @@ __device__ inline void penta_line(float* v, int n, bool edge) {
             const int k = k1 - u;
             const int a1 = edge && k + 1 < kEdgeQ ? k + 1 : kEdgeQ;
             const int a2 = edge && k + 2 < kEdgeQ ? k + 2 : kEdgeQ;
-            const float y = fmaf(-kPentaLdl.l2[a2], y2, fmaf(-kPentaLdl.l1[a1], y1, r[u]));
+            const float y = fmaf(-kPentaLdl.l1[a1], y1, fmaf(-kPentaLdl.l2[a2], y2, r[u]));
             y2 = y1;
             y1 = y;
             r[u] = y;
@@ -1026,15 +1026,63 @@ __device__ inline void penta_line(float* v, int n, bool edge) {
     }
 }
 
+// The same solve on a full window line held in registers (n = kLineQ; every
+// index is a constant, so the factors are instruction operands).  The term of
+// the older neighbour is added first, so each recursion step waits on one
+// fused multiply-add of the step before.
+template <bool EDGE>
+__device__ inline void penta_line_reg(float (&v)[kLineQ]) {
+    float z1 = 0.0f, z2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kLineQ; ++k) {
+        const int a = EDGE && k < kEdgeQ ? k : kEdgeQ;
+        const float z = fmaf(-kPentaLdl.l1[a], z1, fmaf(-kPentaLdl.l2[a], z2, v[k]));
+        z2 = z1;
+        z1 = z;
+        v[k] = z * kPentaLdl.dinv[a];
+    }
+    float y1 = 0.0f, y2 = 0.0f;
+#pragma unroll
+    for (int k = kLineQ - 1; k >= 0; --k) {
+        const int a1 = EDGE && k + 1 < kEdgeQ ? k + 1 : kEdgeQ;
+        const int a2 = EDGE && k + 2 < kEdgeQ ? k + 2 : kEdgeQ;
+        const float y = fmaf(-kPentaLdl.l1[a1], y1, fmaf(-kPentaLdl.l2[a2], y2, v[k]));
+        y2 = y1;
+        y1 = y;
+        v[k] = y;
+    }
+}
+
+// One window line at win[k * S], k < n: in registers when it is a whole
+// window line, else (a lattice axis shorter than the window) through LDS.
+template <int S>
+__device__ inline void penta_solve(float* line, int n, bool edge) {
+    if (n == kLineQ) {
+        float v[kLineQ];
+#pragma unroll
+        for (int k = 0; k < kLineQ; ++k) v[k] = line[k * S];
+        if (edge) penta_line_reg<true>(v);
+        else penta_line_reg<false>(v);
+#pragma unroll
+        for (int k = 0; k < kLineQ; ++k) line[k * S] = v[k];
+    } else {
+        penta_line<S>(line, n, edge);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_solve_q: w_new = (M_x^{-1} (x) M_p^{-1}) b for quadratic basis functions.
 // A workgroup of kLineQ threads owns a kSegQ x kSegQ output tile and holds the
 // window around it in LDS (kHaloQ more nodes per side, wrapped on a periodic
 // axis and shifted to end at the edge on an open one; a lattice narrower than
-// the window is taken whole): thread c loads window column c, solves it along
-// p, then thread r solves kept row r along x, and the kept nodes go out.
-// The window's pitch is odd, so both the column and the row passes address
-// LDS without bank conflicts.  The basis is not used with the FEL.
+// the window is taken whole): the window arrives in LDS by direct loads (one
+// row of a wavefront's 64 columns per instruction, every row in flight), then
+// thread c solves window column c along p, thread r kept row r along x, and
+// the kept nodes go out, whole rows per store.  The window's pitch is odd, so
+// both the column and the row passes address LDS without bank conflicts.  On
+// a periodic axis the window is always a whole line (the halo on the far
+// side of a narrow last tile is only longer).  The basis is not used with
+// the FEL.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kSolveQThreads) void k_solve_q(LaunchArgs A) {
     __shared__ float win[kLineQ * kPitchQ];
@@ -1054,7 +1102,7 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_q(LaunchArgs A) {
         const int X0 = txi * kSegQ, kw = min(kSegQ, nx - X0);
         const int P0 = tyi * kSegQ, kp = min(kSegQ, np - P0);
         // windows: columns [xs, xs + lx) (unwrapped on a periodic axis), rows [ps, ps + lp)
-        const int lx = periodic ? kw + 2 * kHaloQ : min(nx, kLineQ);
+        const int lx = periodic ? kLineQ : min(nx, kLineQ);
         const int xs = periodic ? X0 - kHaloQ : max(0, min(X0 - kHaloQ, nx - lx));
         const int lp = min(np, kLineQ);
         const int ps = max(0, min(P0 - kHaloQ, np - lp));
@@ -1065,13 +1113,18 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_q(LaunchArgs A) {
 
         if (tid < lx) {
             const int col = periodic ? wrap_index(xs + tid, nx, 1.0f / (float)nx) : xs + tid;
-            const float* src = b + (size_t)ps * nx + col;
-            for (int r = 0; r < lp; ++r) win[r * kPitchQ + tid] = src[(size_t)r * nx];
+            gfloat* src = as_global(b) + (size_t)ps * nx + col;
+            // LDS destination of the wavefront's row: its first lane's column
+            float* row0 = win + __builtin_amdgcn_readfirstlane(tid & ~63);
+            for (int r = 0; r < lp; ++r)
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + (size_t)r * nx),
+                                                 (__attribute__((address_space(3))) void*)(row0 + r * kPitchQ), 4, 0, 0);
         }
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         __syncthreads();
-        if (tid < lx) penta_line<kPitchQ>(win + tid, lp, ps == 0);
+        if (tid < lx) penta_solve<kPitchQ>(win + tid, lp, ps == 0);
         __syncthreads();
-        if (tid < kp) penta_line<1>(win + (op + tid) * kPitchQ, lx, !periodic && xs == 0);
+        if (tid < kp) penta_solve<1>(win + (op + tid) * kPitchQ, lx, !periodic && xs == 0);
         __syncthreads();
         if (tid < kw) {
             float* out = dst + (size_t)P0 * nx + X0 + tid;
