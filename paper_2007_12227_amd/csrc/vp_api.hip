@@ -122,6 +122,7 @@ struct LaunchList {
     bool has_fel = false;  // an FEL instance: the field kernel follows the solve
     bool has_rk4 = false;  // a Runge-Kutta FEL instance: its stage sums precede the deposit
     int basis = kBasisTent;  // of every instance in the list
+    int solve = kSolveTent;  // the solve kernel serving every instance in the list
     size_t lds1 = 0;
     int threads1 = 256;  // deposit workgroup size
     hipStream_t stream = nullptr;
@@ -143,7 +144,7 @@ struct LaunchList {
             k[n++] = K{fel_field_kernel(), d_off2, ninst, 0, kFieldThreads, 1};
         }
         k[n++] = K{deposit_kernel(basis), d_off1, total1, lds1, threads1, 0};
-        k[n++] = K{solve_kernel(basis), d_off2, total2, 0, solve_threads(basis), 0};
+        k[n++] = K{solve_kernel(solve), d_off2, total2, 0, solve_threads(solve), 0};
         if (has_fel) k[n++] = K{fel_field_kernel(), d_off2, ninst, 0, kFieldThreads, 0};
         return n;
     }
@@ -153,7 +154,7 @@ struct LaunchList {
             HIP_TRY(launch_fel_field(args(d_off2, ninst, parity, 1), stream));
         }
         HIP_TRY(launch_deposit(args(d_off1, total1, parity), total1, lds1, threads1, stream, basis));
-        HIP_TRY(launch_solve(args(d_off2, total2, parity), total2, stream, basis));
+        HIP_TRY(launch_solve(args(d_off2, total2, parity), total2, stream, solve));
         if (has_fel) HIP_TRY(launch_fel_field(args(d_off2, ninst, parity), stream));
         return VP_OK;
     }
@@ -308,6 +309,7 @@ int upload_inst(vp_grid* g) {
     g->list.total2 = I.k2_tiles;
     g->list.lds1 = deposit_lds_bytes(t.k1_tx, t.k1_ty, g->basis);
     g->list.basis = g->basis;
+    g->list.solve = solve_kind(g->basis, g->x.n, g->p.n, g->x.periodic != 0);
     g->list.threads1 = t.k1_threads;
     g->list.drop_graphs();
     return VP_OK;
@@ -635,7 +637,7 @@ int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]) {
         }
         HIP_TRY(launch_deposit(L.args(L.d_off1, L.total1, par), L.total1, L.lds1, L.threads1, g->stream, L.basis));
         HIP_TRY(hipEventRecord(ev[3 * s + 1], g->stream));
-        HIP_TRY(launch_solve(L.args(L.d_off2, L.total2, par), L.total2, g->stream, L.basis));
+        HIP_TRY(launch_solve(L.args(L.d_off2, L.total2, par), L.total2, g->stream, L.solve));
         if (L.has_fel) HIP_TRY(launch_fel_field(L.args(L.d_off2, L.ninst, par), g->stream));
         HIP_TRY(hipEventRecord(ev[3 * s + 2], g->stream));
     }
@@ -863,6 +865,9 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
     L.lds1 = lds1;
     L.threads1 = threads1;
     L.basis = grids[0]->basis;
+    // one solve kernel for the launch: the narrow-lattice one if any grid needs it
+    L.solve = kSolveTent;
+    for (int k = 0; k < n; ++k) L.solve = std::max(L.solve, grids[k]->list.solve);
     hipError_t e = hipMalloc(&L.d_inst, sizeof(VpInst) * n);
     if (e == hipSuccess) e = hipMalloc(&L.d_off1, sizeof(int32_t) * 2 * (n + 1));
     L.d_off2 = L.d_off1 + (n + 1);

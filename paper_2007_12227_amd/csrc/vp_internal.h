@@ -264,13 +264,20 @@ struct ReduceArgs {
 
 // launchers (vp_kernels.hip)
 hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s, int basis);
-hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s, int basis);
+hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s, int kind);
 hipError_t launch_fel_field(const LaunchArgs& a, hipStream_t s);
 hipError_t launch_fel_stage(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 const void* deposit_kernel(int basis);
-const void* solve_kernel(int basis);
-inline int solve_threads(int basis) { return basis == kBasisQuadratic ? kSolveQThreads : kSolveThreads; }
+// Solve kernels: tents (k_solve); quadratic basis (k_solve_q), and its
+// variant for lattices with an open axis shorter than a window line.
+enum SolveKind : int32_t { kSolveTent = 0, kSolveQuad = 1, kSolveQuadNarrow = 2 };
+inline int solve_kind(int basis, int nx, int np, bool x_periodic) {
+    if (basis != kBasisQuadratic) return kSolveTent;
+    return np < kLineQ || (!x_periodic && nx < kLineQ) ? kSolveQuadNarrow : kSolveQuad;
+}
+const void* solve_kernel(int kind);
+inline int solve_threads(int kind) { return kind == kSolveTent ? kSolveThreads : kSolveQThreads; }
 inline int solve_tiles(int nx, int np, int basis) {
     if (basis == kBasisQuadratic) return ((nx + kSegQ - 1) / kSegQ) * ((np + kSegQ - 1) / kSegQ);
     return ((nx + kSegX - 1) / kSegX) * ((np + kSegP - 1) / kSegP);

@@ -974,18 +974,47 @@ constexpr PentaLdl penta_ldl_table() {
 }
 constexpr PentaLdl kPentaLdl = penta_ldl_table();
 
-// Solve M y = v in place along one window line, element k at v[k * S], k < n.
-// EDGE: the line starts at an open edge (the tabulated first rows); else it
-// starts at a cut inside the lattice or on a periodic wrap, where the
-// recursions start from zero with the interior factors, an error that decays
-// by 0.4306 per node.  The far end needs no flag (see above); a cut there
-// starts the backward recursion from zero, with the same decay.  The values go
-// through registers U at a time, so the loads of a group issue together.
+// Solve M y = v in place along one whole window line (kLineQ elements) held
+// in registers (every index is a constant: the interior factors are
+// instruction operands).  edge: the line starts at an open edge (the
+// tabulated first rows, chosen by scalar selects); else it starts at a cut
+// inside the lattice or on a periodic wrap, where the recursions start from
+// zero with the interior factors, an error that decays by 0.4306 per node.
+// The far end needs no flag (see above); a cut there starts the backward
+// recursion from zero, with the same decay.  The term of the older neighbour
+// is added first, so each recursion step waits on one fused multiply-add of
+// the step before.
+__device__ inline void penta_line(float (&v)[kLineQ], bool edge) {
+    auto l1 = [&](int k) { return k < kEdgeQ && edge ? kPentaLdl.l1[k] : kPentaLdl.l1[kEdgeQ]; };
+    auto l2 = [&](int k) { return k < kEdgeQ && edge ? kPentaLdl.l2[k] : kPentaLdl.l2[kEdgeQ]; };
+    auto dinv = [&](int k) { return k < kEdgeQ && edge ? kPentaLdl.dinv[k] : kPentaLdl.dinv[kEdgeQ]; };
+    // forward: z_k = v_k - l1_k z_{k-1} - l2_k z_{k-2};  v_k <- z_k / d_k
+    float z1 = 0.0f, z2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kLineQ; ++k) {
+        const float z = fmaf(-l1(k), z1, fmaf(-l2(k), z2, v[k]));
+        z2 = z1;
+        z1 = z;
+        v[k] = z * dinv(k);
+    }
+    // backward: y_k = v_k - l1_{k+1} y_{k+1} - l2_{k+2} y_{k+2}
+    float y1 = 0.0f, y2 = 0.0f;
+#pragma unroll
+    for (int k = kLineQ - 1; k >= 0; --k) {
+        const float y = fmaf(-l1(k + 1), y1, fmaf(-l2(k + 2), y2, v[k]));
+        y2 = y1;
+        y1 = y;
+        v[k] = y;
+    }
+}
+
+// The same solve along a line of n <= kLineQ elements in LDS, v[k * S], for
+// lattice axes shorter than the window (taken whole): a loop, the values
+// going through registers U at a time.
 template <int S>
-__device__ inline void penta_line(float* v, int n, bool edge) {
+__device__ inline void penta_line_lds(float* v, int n, bool edge) {
     constexpr int U = 8;
     static_assert(kEdgeQ % U == 0, "a group of rows is wholly inside or outside the table");
-    // forward: z_k = v_k - l1_k z_{k-1} - l2_k z_{k-2};  v_k <- z_k / d_k
     float z1 = 0.0f, z2 = 0.0f;
     for (int k0 = 0; k0 < n; k0 += U) {
         float r[U];
@@ -1004,7 +1033,6 @@ __device__ inline void penta_line(float* v, int n, bool edge) {
         for (int u = 0; u < U; ++u)
             if (k0 + u < n) v[(k0 + u) * S] = r[u];
     }
-    // backward: y_k = v_k - l1_{k+1} y_{k+1} - l2_{k+2} y_{k+2}
     float y1 = 0.0f, y2 = 0.0f;
     for (int k1 = n - 1; k1 >= 0; k1 -= U) {
         float r[U];
@@ -1026,111 +1054,137 @@ __device__ inline void penta_line(float* v, int n, bool edge) {
     }
 }
 
-// The same solve on a full window line held in registers (n = kLineQ; every
-// index is a constant, so the factors are instruction operands).  The term of
-// the older neighbour is added first, so each recursion step waits on one
-// fused multiply-add of the step before.
-template <bool EDGE>
-__device__ inline void penta_line_reg(float (&v)[kLineQ]) {
-    float z1 = 0.0f, z2 = 0.0f;
-#pragma unroll
-    for (int k = 0; k < kLineQ; ++k) {
-        const int a = EDGE && k < kEdgeQ ? k : kEdgeQ;
-        const float z = fmaf(-kPentaLdl.l1[a], z1, fmaf(-kPentaLdl.l2[a], z2, v[k]));
-        z2 = z1;
-        z1 = z;
-        v[k] = z * kPentaLdl.dinv[a];
+// Window geometry of a solve tile (quadratic basis): kept nodes [X0, X0 + kw)
+// x [P0, P0 + kp); window columns [xs, xs + lx) (unwrapped on a periodic
+// axis: always a whole line there, the halo on the far side of a narrow last
+// tile only longer) and rows [ps, ps + lp), shifted to end at an open edge; an
+// open axis shorter than the window is taken whole.
+struct QuadTile {
+    int nx, np, X0, kw, P0, kp, lx, xs, lp, ps, ox, op;
+    bool periodic;
+    __device__ QuadTile(const VpInst& I, int t) {
+        nx = I.push.nx;
+        np = I.push.np;
+        periodic = I.push.x_periodic != 0;
+        const int tiles_x = (nx + kSegQ - 1) / kSegQ;
+        const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
+        X0 = txi * kSegQ;
+        kw = min(kSegQ, nx - X0);
+        P0 = tyi * kSegQ;
+        kp = min(kSegQ, np - P0);
+        lx = periodic ? kLineQ : min(nx, kLineQ);
+        xs = periodic ? X0 - kHaloQ : max(0, min(X0 - kHaloQ, nx - lx));
+        lp = min(np, kLineQ);
+        ps = max(0, min(P0 - kHaloQ, np - lp));
+        ox = X0 - xs;
+        op = P0 - ps;
     }
-    float y1 = 0.0f, y2 = 0.0f;
-#pragma unroll
-    for (int k = kLineQ - 1; k >= 0; --k) {
-        const int a1 = EDGE && k + 1 < kEdgeQ ? k + 1 : kEdgeQ;
-        const int a2 = EDGE && k + 2 < kEdgeQ ? k + 2 : kEdgeQ;
-        const float y = fmaf(-kPentaLdl.l1[a1], y1, fmaf(-kPentaLdl.l2[a2], y2, v[k]));
-        y2 = y1;
-        y1 = y;
-        v[k] = y;
-    }
-}
-
-// One window line at win[k * S], k < n: in registers when it is a whole
-// window line, else (a lattice axis shorter than the window) through LDS.
-template <int S>
-__device__ inline void penta_solve(float* line, int n, bool edge) {
-    if (n == kLineQ) {
-        float v[kLineQ];
-#pragma unroll
-        for (int k = 0; k < kLineQ; ++k) v[k] = line[k * S];
-        if (edge) penta_line_reg<true>(v);
-        else penta_line_reg<false>(v);
-#pragma unroll
-        for (int k = 0; k < kLineQ; ++k) line[k * S] = v[k];
-    } else {
-        penta_line<S>(line, n, edge);
-    }
-}
+};
 
 // ---------------------------------------------------------------------------
-// k_solve_q: w_new = (M_x^{-1} (x) M_p^{-1}) b for quadratic basis functions.
-// A workgroup of kLineQ threads owns a kSegQ x kSegQ output tile and holds the
-// window around it in LDS (kHaloQ more nodes per side, wrapped on a periodic
-// axis and shifted to end at the edge on an open one; a lattice narrower than
-// the window is taken whole): the window arrives in LDS by direct loads (one
-// row of a wavefront's 64 columns per instruction, every row in flight), then
-// thread c solves window column c along p, thread r kept row r along x, and
-// the kept nodes go out, whole rows per store.  The window's pitch is odd, so
-// both the column and the row passes address LDS without bank conflicts.  On
-// a periodic axis the window is always a whole line (the halo on the far
-// side of a narrow last tile is only longer).  The basis is not used with
-// the FEL.
+// k_solve_q: w_new = (M_x^{-1} (x) M_p^{-1}) b for quadratic basis functions,
+// on lattices whose open axes have at least kLineQ nodes (k_solve_q_narrow
+// takes the others).  A workgroup of kLineQ threads owns a kSegQ x kSegQ
+// output tile inside the kLineQ x kLineQ window around it (QuadTile).
+//  p phase: thread c loads window column c into registers through a buffer
+//    resource based at the window's first row (the row's byte offset advances
+//    by a register add; every row in flight at once; a wavefront's lanes read
+//    64 consecutive nodes of a row per instruction), solves it, and puts the
+//    kept rows into LDS (rows outside them go to two trash rows, so the
+//    writes need no branches).  (Half the rows staged by direct loads into
+//    LDS instead measured 2.7 us slower at 2048^2: the column has to reach
+//    the registers anyway.)
+//  x phase: thread r solves kept row r in registers.
+//  out:     the kept columns of the kept rows go out, whole rows per store.
+// The LDS holds the kept rows and two trash rows at an odd pitch (42 KB:
+// three tiles per compute unit, the 676 tiles of a 2048^2 lattice in one
+// round), and both passes address it without bank conflicts.  The basis is
+// not used with the FEL.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kSolveQThreads) void k_solve_q(LaunchArgs A) {
+    __shared__ float win[(kSegQ + 2) * kPitchQ];  // row 1 + r: kept row r; rows 0 and kSegQ + 1: trash
+    __shared__ int s_d;
+    const int tid = threadIdx.x;
+    const int item = tile_of(blockIdx.x, A.total);  // one tile per workgroup (the grid is the tile count)
+    if (tid == 0) s_d = find_instance(A.off, A.ninst, item);
+    __syncthreads();
+    const int d = __builtin_amdgcn_readfirstlane(s_d);
+    const VpInst& I = A.inst[d];
+    const QuadTile T(I, item - A.off[d]);
+    const int nx = T.nx;
+    float* __restrict__ dst = I.w[((I.parity0 + A.parity) & 1) ^ 1];
+
+    {
+        // p phase, thread = window column (lx = lp = kLineQ here)
+        const int col = T.periodic ? wrap_index(T.xs + tid, nx, 1.0f / (float)nx) : T.xs + tid;
+        float v[kLineQ];
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void*)(I.b + (size_t)T.ps * nx), (short)0, -1, kBufferWord3);
+        // byte offset of the lane's node in row k: col 4 + k nx 4 < 2^25 (both
+        // axes have at most 2^16 nodes), advanced row by row
+        const int row_bytes = nx * 4;
+        int off = col * 4;
+#pragma unroll
+        for (int k = 0; k < kLineQ; ++k, off += row_bytes)
+            v[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+        penta_line(v, T.ps == 0);
+        // window row k -> LDS row 1 + (k - op), clamped to the trash rows
+#pragma unroll
+        for (int k = 0; k < kLineQ; ++k) win[(min(max(k - T.op, -1), kSegQ) + 1) * kPitchQ + tid] = v[k];
+    }
+    __syncthreads();
+    if (tid < T.kp) {
+        // x phase, thread = kept row
+        float* row = win + (tid + 1) * kPitchQ;
+        float v[kLineQ];
+#pragma unroll
+        for (int k = 0; k < kLineQ; ++k) v[k] = row[k];
+        penta_line(v, !T.periodic && T.xs == 0);
+#pragma unroll
+        for (int k = 0; k < kLineQ; ++k) row[k] = v[k];
+    }
+    __syncthreads();
+    if (tid < T.kw) {
+        float* out = dst + (size_t)T.P0 * nx + T.X0 + tid;
+        for (int r = 0; r < T.kp; ++r) out[(size_t)r * nx] = win[(r + 1) * kPitchQ + T.ox + tid];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_solve_q_narrow: the same solve for launches with an open axis shorter
+// than kLineQ nodes.  The whole window (up to kLineQ x kLineQ) is staged in
+// LDS by direct loads and every line is solved there by penta_line_lds:
+// slower, and only small lattices take it.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kSolveQThreads) void k_solve_q_narrow(LaunchArgs A) {
     __shared__ float win[kLineQ * kPitchQ];
     __shared__ int s_d;
     const int tid = threadIdx.x;
-    for (int it = blockIdx.x; it < A.total; it += gridDim.x) {
-        const int item = tile_of(it, A.total);
-        if (tid == 0) s_d = find_instance(A.off, A.ninst, item);
-        __syncthreads();
-        const int d = __builtin_amdgcn_readfirstlane(s_d);
-        const VpInst& I = A.inst[d];
-        const int t = item - A.off[d];
-        const int nx = I.push.nx, np = I.push.np;
-        const bool periodic = I.push.x_periodic != 0;
-        const int tiles_x = (nx + kSegQ - 1) / kSegQ;
-        const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
-        const int X0 = txi * kSegQ, kw = min(kSegQ, nx - X0);
-        const int P0 = tyi * kSegQ, kp = min(kSegQ, np - P0);
-        // windows: columns [xs, xs + lx) (unwrapped on a periodic axis), rows [ps, ps + lp)
-        const int lx = periodic ? kLineQ : min(nx, kLineQ);
-        const int xs = periodic ? X0 - kHaloQ : max(0, min(X0 - kHaloQ, nx - lx));
-        const int lp = min(np, kLineQ);
-        const int ps = max(0, min(P0 - kHaloQ, np - lp));
-        const int ox = X0 - xs, op = P0 - ps;  // the kept nodes: window columns ox .. ox + kw, rows op .. op + kp
-        const int par = (I.parity0 + A.parity) & 1;
-        const float* __restrict__ b = I.b;
-        float* __restrict__ dst = I.w[par ^ 1];
-
-        if (tid < lx) {
-            const int col = periodic ? wrap_index(xs + tid, nx, 1.0f / (float)nx) : xs + tid;
-            gfloat* src = as_global(b) + (size_t)ps * nx + col;
-            // LDS destination of the wavefront's row: its first lane's column
-            float* row0 = win + __builtin_amdgcn_readfirstlane(tid & ~63);
-            for (int r = 0; r < lp; ++r)
-                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + (size_t)r * nx),
-                                                 (__attribute__((address_space(3))) void*)(row0 + r * kPitchQ), 4, 0, 0);
-        }
-        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-        __syncthreads();
-        if (tid < lx) penta_solve<kPitchQ>(win + tid, lp, ps == 0);
-        __syncthreads();
-        if (tid < kp) penta_solve<1>(win + (op + tid) * kPitchQ, lx, !periodic && xs == 0);
-        __syncthreads();
-        if (tid < kw) {
-            float* out = dst + (size_t)P0 * nx + X0 + tid;
-            for (int r = 0; r < kp; ++r) out[(size_t)r * nx] = win[(op + r) * kPitchQ + ox + tid];
-        }
-        __syncthreads();
+    const int item = tile_of(blockIdx.x, A.total);
+    if (tid == 0) s_d = find_instance(A.off, A.ninst, item);
+    __syncthreads();
+    const int d = __builtin_amdgcn_readfirstlane(s_d);
+    const VpInst& I = A.inst[d];
+    const QuadTile T(I, item - A.off[d]);
+    const int nx = T.nx;
+    float* __restrict__ dst = I.w[((I.parity0 + A.parity) & 1) ^ 1];
+    if (tid < T.lx) {
+        const int col = T.periodic ? wrap_index(T.xs + tid, nx, 1.0f / (float)nx) : T.xs + tid;
+        gfloat* src = as_global(I.b) + (size_t)T.ps * nx + col;
+        float* row0 = win + __builtin_amdgcn_readfirstlane(tid & ~63);
+        for (int r = 0; r < T.lp; ++r)
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + (size_t)r * nx),
+                                             (__attribute__((address_space(3))) void*)(row0 + r * kPitchQ), 4, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();
+    if (tid < T.lx) penta_line_lds<kPitchQ>(win + tid, T.lp, T.ps == 0);
+    __syncthreads();
+    if (tid < T.kp) penta_line_lds<1>(win + (T.op + tid) * kPitchQ, T.lx, !T.periodic && T.xs == 0);
+    __syncthreads();
+    if (tid < T.kw) {
+        float* out = dst + (size_t)T.P0 * nx + T.X0 + tid;
+        for (int r = 0; r < T.kp; ++r) out[(size_t)r * nx] = win[(T.op + r) * kPitchQ + T.ox + tid];
     }
 }
 
@@ -1390,8 +1444,9 @@ hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads
     return hipGetLastError();
 }
 
-hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s, int basis) {
-    if (basis == kBasisQuadratic) hipLaunchKernelGGL(k_solve_q, dim3(grid), dim3(kSolveQThreads), 0, s, a);
+hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s, int kind) {
+    if (kind == kSolveQuad) hipLaunchKernelGGL(k_solve_q, dim3(grid), dim3(kSolveQThreads), 0, s, a);
+    else if (kind == kSolveQuadNarrow) hipLaunchKernelGGL(k_solve_q_narrow, dim3(grid), dim3(kSolveQThreads), 0, s, a);
     else hipLaunchKernelGGL(k_solve, dim3(grid), dim3(kSolveThreads), 0, s, a);
     return hipGetLastError();
 }
@@ -1415,8 +1470,10 @@ const void* deposit_kernel(int basis) {
     return basis == kBasisQuadratic ? reinterpret_cast<const void*>(&k_deposit<6>)
                                     : reinterpret_cast<const void*>(&k_deposit<4>);
 }
-const void* solve_kernel(int basis) {
-    return basis == kBasisQuadratic ? reinterpret_cast<const void*>(&k_solve_q) : reinterpret_cast<const void*>(&k_solve);
+const void* solve_kernel(int kind) {
+    if (kind == kSolveQuad) return reinterpret_cast<const void*>(&k_solve_q);
+    if (kind == kSolveQuadNarrow) return reinterpret_cast<const void*>(&k_solve_q_narrow);
+    return reinterpret_cast<const void*>(&k_solve);
 }
 const void* fel_field_kernel() { return reinterpret_cast<const void*>(&k_fel_field); }
 const void* fel_stage_kernel() { return reinterpret_cast<const void*>(&k_fel_stage); }
