@@ -1054,6 +1054,63 @@ __device__ inline void penta_line_lds(float* v, int n, bool edge) {
     }
 }
 
+// FEL: a solve tile's FP64 bunching of the new state at the half-drift phases,
+// sum over its kept nodes of w e^{-i(phi_i + q_j)} (k_fel_field sums the
+// tiles); re, im: this thread's part.  The lattice-phase slots stay zero (the
+// Runge-Kutta step is not offered with this basis).  Called by every thread.
+__device__ inline void quad_tile_partials(double* pt, double re, double im, double (&s_red)[kSolveQThreads / 64][2]) {
+    for (int o = 32; o > 0; o >>= 1) {
+        re += __shfl_down(re, o);
+        im += __shfl_down(im, o);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_red[wid][0] = re;
+        s_red[wid][1] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < kSolveQThreads / 64; ++k) {
+            a += s_red[k][0];
+            b += s_red[k][1];
+        }
+        pt[0] = a;
+        pt[1] = b;
+        pt[2] = 0.0;
+        pt[3] = 0.0;
+    }
+}
+
+// The kept nodes of a solve tile out of LDS (kept row r at win[r * kPitchQ],
+// column c at ox + c), whole rows per store; for the FEL also the tile's
+// bunching partials.
+__device__ inline void quad_tile_out(const VpInst& I, int t, const float* win, int ox, int X0, int kw, int P0, int kp,
+                                     int nx, float* dst, double (&s_red)[kSolveQThreads / 64][2]) {
+    const int tid = threadIdx.x;
+    const bool fel = I.push.kind == kFel;
+    double re = 0.0, im = 0.0;
+    if (tid < kw) {
+        float* out = dst + (size_t)P0 * nx + X0 + tid;
+        double cre = 0.0, cim = 0.0;
+        for (int r = 0; r < kp; ++r) {
+            const float y = win[r * kPitchQ + ox + tid];
+            out[(size_t)r * nx] = y;
+            if (fel) {
+                const double2 e = I.fel_eq[P0 + r];  // times e^{-i q}
+                cre += (double)y * e.x;
+                cim -= (double)y * e.y;
+            }
+        }
+        if (fel) {
+            const double2 e = I.fel_ex[X0 + tid];  // times e^{-i phi}
+            re = cre * e.x + cim * e.y;
+            im = cim * e.x - cre * e.y;
+        }
+    }
+    if (fel) quad_tile_partials(I.partials + kPartialsPerTile * t, re, im, s_red);
+}
+
 // Window geometry of a solve tile (quadratic basis): kept nodes [X0, X0 + kw)
 // x [P0, P0 + kp); window columns [xs, xs + lx) (unwrapped on a periodic
 // axis: always a whole line there, the halo on the far side of a narrow last
@@ -1098,11 +1155,12 @@ struct QuadTile {
 //  out:     the kept columns of the kept rows go out, whole rows per store.
 // The LDS holds the kept rows and two trash rows at an odd pitch (42 KB:
 // three tiles per compute unit, the 676 tiles of a 2048^2 lattice in one
-// round), and both passes address it without bank conflicts.  The basis is
-// not used with the FEL.
+// round), and both passes address it without bank conflicts.  For the FEL
+// (drift-kick-drift) the write-out also forms the tile's bunching partials.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kSolveQThreads) void k_solve_q(LaunchArgs A) {
     __shared__ float win[(kSegQ + 2) * kPitchQ];  // row 1 + r: kept row r; rows 0 and kSegQ + 1: trash
+    __shared__ double s_red[kSolveQThreads / 64][2];
     __shared__ int s_d;
     const int tid = threadIdx.x;
     const int item = tile_of(blockIdx.x, A.total);  // one tile per workgroup (the grid is the tile count)
@@ -1110,7 +1168,8 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_q(LaunchArgs A) {
     __syncthreads();
     const int d = __builtin_amdgcn_readfirstlane(s_d);
     const VpInst& I = A.inst[d];
-    const QuadTile T(I, item - A.off[d]);
+    const int t = item - A.off[d];
+    const QuadTile T(I, t);
     const int nx = T.nx;
     float* __restrict__ dst = I.w[((I.parity0 + A.parity) & 1) ^ 1];
 
@@ -1144,10 +1203,7 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_q(LaunchArgs A) {
         for (int k = 0; k < kLineQ; ++k) row[k] = v[k];
     }
     __syncthreads();
-    if (tid < T.kw) {
-        float* out = dst + (size_t)T.P0 * nx + T.X0 + tid;
-        for (int r = 0; r < T.kp; ++r) out[(size_t)r * nx] = win[(r + 1) * kPitchQ + T.ox + tid];
-    }
+    quad_tile_out(I, t, win + kPitchQ, T.ox, T.X0, T.kw, T.P0, T.kp, nx, dst, s_red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1158,6 +1214,7 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_q(LaunchArgs A) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kSolveQThreads) void k_solve_q_narrow(LaunchArgs A) {
     __shared__ float win[kLineQ * kPitchQ];
+    __shared__ double s_red[kSolveQThreads / 64][2];
     __shared__ int s_d;
     const int tid = threadIdx.x;
     const int item = tile_of(blockIdx.x, A.total);
@@ -1165,7 +1222,8 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_q_narrow(LaunchArgs A)
     __syncthreads();
     const int d = __builtin_amdgcn_readfirstlane(s_d);
     const VpInst& I = A.inst[d];
-    const QuadTile T(I, item - A.off[d]);
+    const int t = item - A.off[d];
+    const QuadTile T(I, t);
     const int nx = T.nx;
     float* __restrict__ dst = I.w[((I.parity0 + A.parity) & 1) ^ 1];
     if (tid < T.lx) {
@@ -1182,10 +1240,7 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_q_narrow(LaunchArgs A)
     __syncthreads();
     if (tid < T.kp) penta_line_lds<1>(win + (T.op + tid) * kPitchQ, T.lx, !T.periodic && T.xs == 0);
     __syncthreads();
-    if (tid < T.kw) {
-        float* out = dst + (size_t)T.P0 * nx + T.X0 + tid;
-        for (int r = 0; r < T.kp; ++r) out[(size_t)r * nx] = win[(T.op + r) * kPitchQ + T.ox + tid];
-    }
+    quad_tile_out(I, t, win + T.op * kPitchQ, T.ox, T.X0, T.kw, T.P0, T.kp, nx, dst, s_red);
 }
 
 // ---------------------------------------------------------------------------

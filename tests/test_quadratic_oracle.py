@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from oracle import quadratic as Q
-from paper_2007_12227_amd.inputs import H_PENDULUM, H_SHO_EXACT, Axis, Hamiltonian, rng
+from paper_2007_12227_amd.inputs import H_FEL, H_PENDULUM, H_SHO_EXACT, Axis, Hamiltonian, fel_gaussian, rng
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 
@@ -229,3 +229,21 @@ def test_moments_are_integrals_of_the_expansion(kind):
     m = Q.moments(x, p, ham, w)
     assert abs(m["mass"] - mass) <= 1e-13
     assert abs(m["energy"] - energy) <= 1e-12 * abs(energy)
+
+
+@pytest.mark.parametrize("delta,sigma2", [(0.0, 0.0), (0.3, 0.4)])
+def test_fel_invariant_is_conserved_with_quadratic_basis(delta, sigma2):
+    """|A|^2 + N0^-1 sum w eta is conserved by the exact-kick step and the
+    projection: linear functions lie in the span of the quadratic splines too
+    (they reproduce polynomials of degree 2), and the nodal sum of w eta is
+    the integral of eta f over the expansion (each spline is symmetric), so
+    the projection keeps it while the beam is clear of the energy edges."""
+    inst = fel_gaussian(64, 1, npp=128)
+    ham = Hamiltonian(H_FEL, A_re=2e-2, A_im=-1e-2, fel_delta=delta, fel_sigma2=sigma2)
+    eta = inst.p.nodes()[:, None]
+    N0 = float(inst.w0.sum())
+    e0 = abs(complex(ham.A_re, ham.A_im)) ** 2 + float((inst.w0 * eta).sum()) / N0
+    w, A = Q.run_fel(inst.x, inst.p, ham, inst.w0, 0.05, 40)
+    e1 = abs(A) ** 2 + float((w * eta).sum()) / N0
+    assert abs(e1 - e0) <= 1e-12, (e0, e1)
+    assert abs(A - complex(ham.A_re, ham.A_im)) > 1e-4  # the field did move
