@@ -67,7 +67,8 @@ def bench_fel(binding, steps, integrator=0):
 def bench_quadratic(binding, n, steps, warmup):
     """The headline workload (pendulum band, n^2) with quadratic B-spline basis
     functions: autotuned deposit tiles, graph replay; per-kernel times and
-    the negative mass beside the tent basis's after the same steps."""
+    the negative mass beside the tent basis's after the same steps, and the
+    same comparison on the FEL flat-top start."""
     from paper_2007_12227_amd.inputs import pendulum_band
     inst = pendulum_band(n)
     out = {"workload": f"pendulum_band_{n}_quadratic", "steps": steps}
@@ -90,6 +91,19 @@ def bench_quadratic(binding, n, steps, warmup):
         m = g.moments()
         g.close()
         out[tag + "neg_mass_fraction"] = m["neg_mass"] / m["mass"]
+    # the FEL start with a hard energy edge (the case whose negative weights
+    # the paper discusses), 500 steps at 1024^2, both bases
+    from paper_2007_12227_amd.inputs import fel_flattop
+    fl = fel_flattop(1024, 500)
+    for basis, tag in ((binding.BASIS_QUADRATIC, ""), (binding.BASIS_TENT, "tent_")):
+        g = binding.Grid(fl.x, fl.p)
+        g.set_basis(basis)
+        g.set_hamiltonian(fl.ham)
+        g.set_density(fl.w0)
+        g.step(fl.dt, fl.steps)
+        m = g.moments()
+        g.close()
+        out[tag + "fel_flattop_neg_mass_fraction"] = m["neg_mass"] / m["mass"]
     return out
 
 
