@@ -1092,17 +1092,18 @@ __device__ inline void quad_tile_out(const VpInst& I, int t, const float* win, i
     double re = 0.0, im = 0.0;
     if (tid < kw) {
         float* out = dst + (size_t)P0 * nx + X0 + tid;
-        double cre = 0.0, cim = 0.0;
-        for (int r = 0; r < kp; ++r) {
-            const float y = win[r * kPitchQ + ox + tid];
-            out[(size_t)r * nx] = y;
-            if (fel) {
+        const float* in = win + ox + tid;
+        if (!fel) {
+            for (int r = 0; r < kp; ++r) out[(size_t)r * nx] = in[r * kPitchQ];
+        } else {
+            double cre = 0.0, cim = 0.0;
+            for (int r = 0; r < kp; ++r) {
+                const float y = in[r * kPitchQ];
+                out[(size_t)r * nx] = y;
                 const double2 e = I.fel_eq[P0 + r];  // times e^{-i q}
                 cre += (double)y * e.x;
                 cim -= (double)y * e.y;
             }
-        }
-        if (fel) {
             const double2 e = I.fel_ex[X0 + tid];  // times e^{-i phi}
             re = cre * e.x + cim * e.y;
             im = cim * e.x - cre * e.y;
