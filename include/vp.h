@@ -165,11 +165,10 @@ int vp_set_density(vp_grid* g, const float* w, int32_t on_device);
 
 /* Choose the basis functions (VP_BASIS_TENT or VP_BASIS_QUADRATIC; VP_EINVAL
  * otherwise).  The weights are read as coefficients of the chosen basis from
- * the next step on; the density already set is kept as it is.  The quadratic
- * basis serves every Hamiltonian but the FEL by Runge-Kutta: vp_step returns
- * VP_EUNSUPPORTED for VP_FEL_RK4 with it.  A deposit tile whose local memory no
- * longer fits with the wider border of the quadratic basis is replaced by
- * the default shape.  VP_ESTATE while the grid belongs to a batch; a batch
+ * the next step on; the density already set is kept as it is.  Every
+ * Hamiltonian and integrator works with either basis.  A deposit tile whose
+ * local memory no longer fits with the wider border of the quadratic basis
+ * is replaced by the default shape.  VP_ESTATE while the grid belongs to a batch; a batch
  * takes grids of one basis (VP_EUNSUPPORTED otherwise). */
 int vp_set_basis(vp_grid* g, int32_t basis);
 

@@ -105,22 +105,30 @@ def run(x, p, ham, w0, dt, steps) -> np.ndarray:
     return w
 
 
+FEL_RK4 = 1
+
+
 def run_fel(x, p, ham, w0, dz, steps, A0=None, N0=None):
-    """``steps`` steps of the 1-D FEL (eqs. 13a-c) by drift-kick-drift with the
-    kick integrated exactly, as the tent oracle takes it: the bunching
-    b = N0^-1 sum w e^{-i psi} of the state at its half-drift phases (the tent
-    oracle's nodal sum; it does not depend on the basis), the kick in the
-    field A + b dz/2 + i sigma2 b, then A += b dz, then the projection onto
-    this basis.  Returns (w, A)."""
+    """``steps`` steps of the 1-D FEL (eqs. 13a-c), the push as the tent oracle
+    takes it (it does not depend on the basis), then the projection onto this
+    basis.  Drift-kick-drift with the kick integrated exactly: the bunching
+    b = N0^-1 sum w e^{-i psi} of the state at its half-drift phases, the kick
+    in the field A + b dz/2 + i sigma2 b, then A += b dz.  Runge-Kutta
+    (ham.integrator == FEL_RK4): the nodes as particles of charge w, and A,
+    advanced by the classical fourth-order method.  Returns (w, A)."""
     from . import bunching as _bunching
+    from . import push_rk4 as _push_rk4
     w = np.array(w0, dtype=np.float64, copy=True)
     A = complex(ham.A_re, ham.A_im) if A0 is None else complex(A0)
     N0 = float(w.sum()) if N0 is None else float(N0)
     for _ in range(int(steps)):
-        bn = _bunching(x, p, ham, dz, w, N0)
-        At = A + 0.5 * dz * bn + 1j * ham.fel_sigma2 * bn
-        du, dv = _push(x, p, ham, dz, np.array([At.real, At.imag]))
-        A += dz * bn
+        if getattr(ham, "integrator", 0) == FEL_RK4:
+            du, dv, A = _push_rk4(x, p, ham, dz, w, N0, A)
+        else:
+            bn = _bunching(x, p, ham, dz, w, N0)
+            At = A + 0.5 * dz * bn + 1j * ham.fel_sigma2 * bn
+            du, dv = _push(x, p, ham, dz, np.array([At.real, At.imag]))
+            A += dz * bn
         w = step(x, p, du, dv, w)
     return w, A
 

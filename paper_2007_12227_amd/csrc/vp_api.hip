@@ -450,8 +450,6 @@ int prepare(vp_grid* g, double dt) {
     if (!g->has_ham || !g->has_density)
         return fail(VP_ESTATE, "set the Hamiltonian and the density before stepping");
     if (!isfinite(dt)) return fail(VP_EINVAL, "dt must be finite");
-    if (g->ham.kind == VP_H_FEL && g->ham.integrator == VP_FEL_RK4 && g->basis != kBasisTent)
-        return fail(VP_EUNSUPPORTED, "the Runge-Kutta FEL runs with the tent basis only");
     if (g->ham.kind == VP_H_FEL && !(g->N0 != 0.0))
         return fail(VP_ESTATE, "the FEL needs a nonzero sum of the initial weights (N0 normalises the bunching)");
     if (!g->plan_valid || g->plan_dt != dt) {

@@ -1054,31 +1054,22 @@ __device__ inline void penta_line_lds(float* v, int n, bool edge) {
     }
 }
 
-// FEL: a solve tile's FP64 bunching of the new state at the half-drift phases,
-// sum over its kept nodes of w e^{-i(phi_i + q_j)} (k_fel_field sums the
-// tiles); re, im: this thread's part.  The lattice-phase slots stay zero (the
-// Runge-Kutta step is not offered with this basis).  Called by every thread.
-__device__ inline void quad_tile_partials(double* pt, double re, double im, double (&s_red)[kSolveQThreads / 64][2]) {
-    for (int o = 32; o > 0; o >>= 1) {
-        re += __shfl_down(re, o);
-        im += __shfl_down(im, o);
-    }
+// FEL: a solve tile's FP64 bunching of the new state, the sums over its kept
+// nodes of w e^{-i(phi_i + q_j)} (half-drift phases) and of w e^{-i phi_i}
+// (lattice phases, the Runge-Kutta step's stage 1); k_fel_field sums the
+// tiles.  v: this thread's parts.  Called by every thread.
+__device__ inline void quad_tile_partials(double* pt, double (&v)[kPartialsPerTile],
+                                          double (&s_red)[kSolveQThreads / 64][kPartialsPerTile]) {
+    for (int o = 32; o > 0; o >>= 1)
+        for (int c = 0; c < kPartialsPerTile; ++c) v[c] += __shfl_down(v[c], o);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) {
-        s_red[wid][0] = re;
-        s_red[wid][1] = im;
-    }
+    if (lane == 0)
+        for (int c = 0; c < kPartialsPerTile; ++c) s_red[wid][c] = v[c];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double a = 0.0, b = 0.0;
-        for (int k = 0; k < kSolveQThreads / 64; ++k) {
-            a += s_red[k][0];
-            b += s_red[k][1];
-        }
-        pt[0] = a;
-        pt[1] = b;
-        pt[2] = 0.0;
-        pt[3] = 0.0;
+    if (threadIdx.x < kPartialsPerTile) {
+        double a = 0.0;
+        for (int k = 0; k < kSolveQThreads / 64; ++k) a += s_red[k][threadIdx.x];
+        pt[threadIdx.x] = a;
     }
 }
 
@@ -1086,30 +1077,33 @@ __device__ inline void quad_tile_partials(double* pt, double re, double im, doub
 // column c at ox + c), whole rows per store; for the FEL also the tile's
 // bunching partials.
 __device__ inline void quad_tile_out(const VpInst& I, int t, const float* win, int ox, int X0, int kw, int P0, int kp,
-                                     int nx, float* dst, double (&s_red)[kSolveQThreads / 64][2]) {
+                                     int nx, float* dst, double (&s_red)[kSolveQThreads / 64][kPartialsPerTile]) {
     const int tid = threadIdx.x;
     const bool fel = I.push.kind == kFel;
-    double re = 0.0, im = 0.0;
+    double v[kPartialsPerTile] = {0.0, 0.0, 0.0, 0.0};
     if (tid < kw) {
         float* out = dst + (size_t)P0 * nx + X0 + tid;
         const float* in = win + ox + tid;
         if (!fel) {
             for (int r = 0; r < kp; ++r) out[(size_t)r * nx] = in[r * kPitchQ];
         } else {
-            double cre = 0.0, cim = 0.0;
+            double cre = 0.0, cim = 0.0, c1 = 0.0;
             for (int r = 0; r < kp; ++r) {
                 const float y = in[r * kPitchQ];
                 out[(size_t)r * nx] = y;
                 const double2 e = I.fel_eq[P0 + r];  // times e^{-i q}
                 cre += (double)y * e.x;
                 cim -= (double)y * e.y;
+                c1 += (double)y;
             }
             const double2 e = I.fel_ex[X0 + tid];  // times e^{-i phi}
-            re = cre * e.x + cim * e.y;
-            im = cim * e.x - cre * e.y;
+            v[0] = cre * e.x + cim * e.y;
+            v[1] = cim * e.x - cre * e.y;
+            v[2] = c1 * e.x;
+            v[3] = -c1 * e.y;
         }
     }
-    if (fel) quad_tile_partials(I.partials + kPartialsPerTile * t, re, im, s_red);
+    if (fel) quad_tile_partials(I.partials + kPartialsPerTile * t, v, s_red);
 }
 
 // Window geometry of a solve tile (quadratic basis): kept nodes [X0, X0 + kw)
@@ -1157,11 +1151,11 @@ struct QuadTile {
 // The LDS holds the kept rows and two trash rows at an odd pitch (42 KB:
 // three tiles per compute unit, the 676 tiles of a 2048^2 lattice in one
 // round), and both passes address it without bank conflicts.  For the FEL
-// (drift-kick-drift) the write-out also forms the tile's bunching partials.
+// the write-out also forms the tile's bunching partials.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kSolveQThreads) void k_solve_q(LaunchArgs A) {
     __shared__ float win[(kSegQ + 2) * kPitchQ];  // row 1 + r: kept row r; rows 0 and kSegQ + 1: trash
-    __shared__ double s_red[kSolveQThreads / 64][2];
+    __shared__ double s_red[kSolveQThreads / 64][kPartialsPerTile];
     __shared__ int s_d;
     const int tid = threadIdx.x;
     const int item = tile_of(blockIdx.x, A.total);  // one tile per workgroup (the grid is the tile count)
@@ -1215,7 +1209,7 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_q(LaunchArgs A) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kSolveQThreads) void k_solve_q_narrow(LaunchArgs A) {
     __shared__ float win[kLineQ * kPitchQ];
-    __shared__ double s_red[kSolveQThreads / 64][2];
+    __shared__ double s_red[kSolveQThreads / 64][kPartialsPerTile];
     __shared__ int s_d;
     const int tid = threadIdx.x;
     const int item = tile_of(blockIdx.x, A.total);
@@ -1329,9 +1323,9 @@ __device__ inline void sincos_small(double x, double* s, double* c) {
 
 // ---------------------------------------------------------------------------
 // k_fel_stage: the bunching at the phases of the Runge-Kutta step's stages 3
-// and 4 (FEL only), FP64, one per-tile partial per solve tile of kSegX x kSegP
-// nodes.  A workgroup of four wavefronts per tile: thread t takes column
-// t mod kSegX and rows t / kSegX + kRowStep i; the sums are reduced in a fixed
+// and 4 (FEL only), FP64, one per-tile partial per solve tile of the
+// instance's solve.  A workgroup of four wavefronts per tile: thread t takes
+// a column and every kRowStep-th row of it; the sums are reduced in a fixed
 // order (shuffle tree per wavefront, then the wavefronts in turn).  With
 // k1 = a1 cos phi + b1 sin phi and k2 = a2 cos psi2 + b2 sin psi2 the slopes
 // of stages 1 and 2 (fields A1 = A, A2 = A + dz/2 b1), the phases are
@@ -1339,70 +1333,78 @@ __device__ inline void sincos_small(double x, double* s, double* c) {
 // drift of the node's row.  k1 depends on the column only, so stage 3's sum
 // is a column sum of w e^{-i q} turned by e^{-i(phi + dz^2/4 k1)}.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kStageThreads) void k_fel_stage(LaunchArgs A) {
-    constexpr int kWaves = kStageThreads / 64, kRowStep = kStageThreads / kSegX;
-    __shared__ double s_red[kWaves][4];
+// One solve tile of SX x SP nodes (the tiles of the instance's solve: tents
+// 32 x 64, quadratic basis 80 x 80); thread t takes column t mod SX and rows
+// t / SX + (256 / SX) i (threads past the last whole row group idle).
+template <int SX, int SP>
+__device__ inline void stage_tile(const VpInst& I, int t, int parity, double (&s_red)[kStageThreads / 64][4]) {
+    constexpr int kWaves = kStageThreads / 64, kRowStep = kStageThreads / SX;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nx = I.push.nx, np = I.push.np;
+    const int tiles_x = (nx + SX - 1) / SX;
+    const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
+    const int X0 = txi * SX, tw = min(SX, nx - X0);
+    const int Y0 = tyi * SP, th = min(SP, np - Y0);
+    const int par = (I.parity0 + parity) & 1;
+    const float* __restrict__ w = I.w[par];
+    const double* st = I.fel_state;
+    const double h = I.fel_dz, sg = (double)I.fel_sigma2;
+    // slope coefficients of stages 1 and 2 (as in the deposit, FP64)
+    const double b1r = st[kB1], b1i = st[kB1 + 1], b2r = st[kBn], b2i = st[kBn + 1];
+    const double a1r = st[kA] - sg * b1i, a1i = st[kA + 1] + sg * b1r;
+    const double a2r = st[kA] + 0.5 * h * b1r - sg * b2i, a2i = st[kA + 1] + 0.5 * h * b1i + sg * b2r;
+    const double t3 = 0.25 * h * h, t4 = 0.5 * h * h;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};  // stage 3 (re, im), stage 4 (re, im)
+    const int col = tid % SX, r0 = tid / SX;
+    if (col < tw && r0 < kRowStep) {
+        const int gx = X0 + col;
+        const double2 ex = I.fel_ex[gx];
+        double cre = 0.0, cim = 0.0;
+        for (int r = r0; r < th; r += kRowStep) {
+            const int j = Y0 + r;
+            const double wk = (double)w[(size_t)j * nx + gx];
+            const double2 eq = I.fel_eq[j];
+            cre += wk * eq.x;
+            cim -= wk * eq.y;
+            // e^{i psi2} = e^{i phi} e^{i q}
+            const double c2 = ex.x * eq.x - ex.y * eq.y, s2 = ex.y * eq.x + ex.x * eq.y;
+            const double k2 = -2.0 * (a2r * c2 - a2i * s2);
+            double sn, cs;
+            sincos_small(t4 * k2, &sn, &cs);
+            // e^{i psi4} = e^{i psi2} e^{i q} e^{i t4 k2}
+            const double c2q = c2 * eq.x - s2 * eq.y, s2q = s2 * eq.x + c2 * eq.y;
+            const double c4 = c2q * cs - s2q * sn, s4 = s2q * cs + c2q * sn;
+            acc[2] += wk * c4;
+            acc[3] -= wk * s4;
+        }
+        const double k1 = -2.0 * (a1r * ex.x - a1i * ex.y);
+        double sn, cs;
+        sincos_small(t3 * k1, &sn, &cs);
+        const double c3 = ex.x * cs - ex.y * sn, s3 = ex.y * cs + ex.x * sn;  // e^{i(phi + t3 k1)}
+        acc[0] = cre * c3 + cim * s3;
+        acc[1] = cim * c3 - cre * s3;
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        for (int c = 0; c < 4; ++c) acc[c] += __shfl_down(acc[c], o);
+    if (lane == 0)
+        for (int c = 0; c < 4; ++c) s_red[wid][c] = acc[c];
+    __syncthreads();
+    if (tid < 4) {
+        double v = 0.0;
+        for (int k = 0; k < kWaves; ++k) v += s_red[k][tid];
+        I.partials[kPartialsPerTile * t + tid] = v;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kStageThreads) void k_fel_stage(LaunchArgs A) {
+    __shared__ double s_red[kStageThreads / 64][4];
     for (int item = blockIdx.x; item < A.total; item += gridDim.x) {
         const int d = __builtin_amdgcn_readfirstlane(find_instance(A.off, A.ninst, item));
         const VpInst& I = A.inst[d];
         if (I.push.kind != kFel || !I.push.rk4) continue;
-        const int t = item - A.off[d];
-        const int nx = I.push.nx, np = I.push.np;
-        const int tiles_x = (nx + kSegX - 1) / kSegX;
-        const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
-        const int X0 = txi * kSegX, tw = min(kSegX, nx - X0);
-        const int Y0 = tyi * kSegP, th = min(kSegP, np - Y0);
-        const int par = (I.parity0 + A.parity) & 1;
-        const float* __restrict__ w = I.w[par];
-        const double* st = I.fel_state;
-        const double h = I.fel_dz, sg = (double)I.fel_sigma2;
-        // slope coefficients of stages 1 and 2 (as in the deposit, FP64)
-        const double b1r = st[kB1], b1i = st[kB1 + 1], b2r = st[kBn], b2i = st[kBn + 1];
-        const double a1r = st[kA] - sg * b1i, a1i = st[kA + 1] + sg * b1r;
-        const double a2r = st[kA] + 0.5 * h * b1r - sg * b2i, a2i = st[kA + 1] + 0.5 * h * b1i + sg * b2r;
-        const double t3 = 0.25 * h * h, t4 = 0.5 * h * h;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};  // stage 3 (re, im), stage 4 (re, im)
-        const int col = tid & (kSegX - 1);
-        if (col < tw) {
-            const int gx = X0 + col;
-            const double2 ex = I.fel_ex[gx];
-            double cre = 0.0, cim = 0.0;
-            for (int r = tid / kSegX; r < th; r += kRowStep) {
-                const int j = Y0 + r;
-                const double wk = (double)w[(size_t)j * nx + gx];
-                const double2 eq = I.fel_eq[j];
-                cre += wk * eq.x;
-                cim -= wk * eq.y;
-                // e^{i psi2} = e^{i phi} e^{i q}
-                const double c2 = ex.x * eq.x - ex.y * eq.y, s2 = ex.y * eq.x + ex.x * eq.y;
-                const double k2 = -2.0 * (a2r * c2 - a2i * s2);
-                double sn, cs;
-                sincos_small(t4 * k2, &sn, &cs);
-                // e^{i psi4} = e^{i psi2} e^{i q} e^{i t4 k2}
-                const double c2q = c2 * eq.x - s2 * eq.y, s2q = s2 * eq.x + c2 * eq.y;
-                const double c4 = c2q * cs - s2q * sn, s4 = s2q * cs + c2q * sn;
-                acc[2] += wk * c4;
-                acc[3] -= wk * s4;
-            }
-            const double k1 = -2.0 * (a1r * ex.x - a1i * ex.y);
-            double sn, cs;
-            sincos_small(t3 * k1, &sn, &cs);
-            const double c3 = ex.x * cs - ex.y * sn, s3 = ex.y * cs + ex.x * sn;  // e^{i(phi + t3 k1)}
-            acc[0] = cre * c3 + cim * s3;
-            acc[1] = cim * c3 - cre * s3;
-        }
-        for (int o = 32; o > 0; o >>= 1)
-            for (int c = 0; c < 4; ++c) acc[c] += __shfl_down(acc[c], o);
-        if (lane == 0)
-            for (int c = 0; c < 4; ++c) s_red[wid][c] = acc[c];
-        __syncthreads();
-        if (tid < 4) {
-            double v = 0.0;
-            for (int k = 0; k < kWaves; ++k) v += s_red[k][tid];
-            I.partials[kPartialsPerTile * t + tid] = v;
-        }
-        __syncthreads();
+        if (I.push.wide) stage_tile<kSegQ, kSegQ>(I, item - A.off[d], A.parity, s_red);
+        else stage_tile<kSegX, kSegP>(I, item - A.off[d], A.parity, s_red);
     }
 }
 

@@ -162,22 +162,13 @@ def test_one_step_at_2048_in_the_benchmark_launch(B):
     assert err <= 1e-5
 
 
-def test_fel_runge_kutta_is_refused(B):
-    inst = fel_gaussian(64, 1, npp=64)
-    g = quad_grid(B, inst.x, inst.p, Hamiltonian(H_FEL, A_re=1e-3, integrator=FEL_RK4), inst.w0)
-    with pytest.raises(B.VpError) as e:
-        g.step(inst.dt, 1)
-    assert e.value.code == B.VP_EUNSUPPORTED
-    g.close()
-
-
+@pytest.mark.parametrize("integrator", [0, FEL_RK4])
 @pytest.mark.parametrize("delta,sigma2", [(0.0, 0.0), (0.3, 0.4)])
-def test_fel_one_step(B, delta, sigma2):
-    """One exact-kick FEL step with the quadratic basis: the state and the new
-    field against the oracle (the bunching comes from the solve tiles'
-    partials of the quadratic solve)."""
+def test_fel_one_step(B, delta, sigma2, integrator):
+    """One FEL step (exact kick, or Runge-Kutta) with the quadratic basis: the
+    state and the new field against the oracle."""
     inst = fel_gaussian(96, 1, npp=160)
-    ham = Hamiltonian(H_FEL, A_re=0.02, A_im=-0.01, fel_delta=delta, fel_sigma2=sigma2)
+    ham = Hamiltonian(H_FEL, A_re=0.02, A_im=-0.01, fel_delta=delta, fel_sigma2=sigma2, integrator=integrator)
     w32 = inst.w0.astype(np.float32)
     g = quad_grid(B, inst.x, inst.p, ham, w32)
     g.step(inst.dt, 1)
@@ -189,12 +180,14 @@ def test_fel_one_step(B, delta, sigma2):
     assert abs(complex(m["A_re"], m["A_im"]) - A) <= 1e-12
 
 
-def test_fel_run_256(B):
-    """200 exact-kick FEL steps at 256^2 with detuning and space charge (the
-    field grows several-fold): state, field and the invariant |A|^2 + <eta> against
-    the oracle's run."""
+@pytest.mark.parametrize("integrator", [0, FEL_RK4])
+def test_fel_run_256(B, integrator):
+    """200 FEL steps at 256^2 with detuning and space charge (the field grows
+    several-fold): state, field and the invariant |A|^2 + <eta> against the
+    oracle's run (the bunchings come from the quadratic solve's per-tile
+    partials and, for Runge-Kutta, the stage kernel on the quadratic tiles)."""
     inst = fel_gaussian(256, 200)
-    ham = Hamiltonian(H_FEL, A_re=1e-3, fel_delta=0.2, fel_sigma2=0.3)
+    ham = Hamiltonian(H_FEL, A_re=1e-3, fel_delta=0.2, fel_sigma2=0.3, integrator=integrator)
     w32 = inst.w0.astype(np.float32)
     g = quad_grid(B, inst.x, inst.p, ham, w32)
     g.step(inst.dt, 200)
@@ -204,7 +197,7 @@ def test_fel_run_256(B):
     ref, A = Q.run_fel(inst.x, inst.p, ham, w32.astype(np.float64), inst.dt, 200)
     err = oracle.rel_l1(got, ref)
     Ag = complex(m["A_re"], m["A_im"])
-    print(f"FEL 256^2 quadratic, 200 steps: rel L1 {err:.3e}, |A| {abs(Ag):.6e} (oracle {abs(A):.6e})", flush=True)
+    print(f"FEL 256^2 quadratic (integrator {integrator}), 200 steps: rel L1 {err:.3e}, |A| {abs(Ag):.6e} (oracle {abs(A):.6e})", flush=True)
     assert err <= 1e-4
     assert abs(Ag - A) <= 1e-4 * abs(A)
     eta = inst.p.nodes()[:, None]
