@@ -3,8 +3,8 @@
 Only the tests, the GPU smoke check and the CPU-baseline leg of the benchmark
 import this package.  The product library never does.  The numerics live in
 ``vp_oracle.c`` (plain C, FP64); ``brute.py`` holds quadrature and dense
-linear-algebra checks for tiny grids; ``quadratic.py`` is the method with
-quadratic B-spline basis functions.  See ``vp_oracle.c`` for the equations
+linear-algebra checks for tiny grids; ``spline_basis.py`` is the method with
+quadratic or cubic B-spline basis functions.  See ``vp_oracle.c`` for the equations
 followed and the readings taken where the paper is silent.
 """
 from __future__ import annotations

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import quadratic as Q
+from oracle import spline_basis as Q
 from paper_2007_12227_amd.inputs import (FEL_RK4, H_FEL, H_FREE, H_PENDULUM, H_SHO_EXACT, Axis, Hamiltonian,
                                          fel_gaussian, gaussian, pendulum_axes, pendulum_band, rng)
 
