@@ -13,10 +13,12 @@
  * (eq. 9).  Coordinates are periodic and momenta open (Sec. "Numerical
  * Examples"); weight pushed past an open edge is lost.
  *
- * The tents can be replaced by quadratic B-spline basis functions, the
- * smoother local basis the paper's discussion proposes (vp_set_basis): the
- * overlaps of eq. 9 become quintic B-spline weights on 6 x 6 nodes and the
- * mass matrix of eq. 8 the pentadiagonal (1/120)[1, 26, 66, 26, 1] per axis.
+ * The tents can be replaced by quadratic or cubic B-spline basis functions,
+ * the smoother local basis the paper's discussion proposes (vp_set_basis):
+ * the overlaps of eq. 9 become B-spline weights of degree 5 or 7 on 6 x 6 or
+ * 8 x 8 nodes and the mass matrix of eq. 8 the band
+ * (1/120)[1, 26, 66, 26, 1] or (1/5040)[1, 120, 1191, 2416, 1191, 120, 1]
+ * per axis.
  *
  * Conventions for every call:
  *  - return 0 on success, a negative VP_E* code on failure; no call throws;
@@ -58,6 +60,7 @@ extern "C" {
 /* Basis functions of the expansion (vp_set_basis) */
 #define VP_BASIS_TENT 0      /* tents, eq. 4 (the default) */
 #define VP_BASIS_QUADRATIC 1 /* centred quadratic B-splines of width 3h on every node */
+#define VP_BASIS_CUBIC 2     /* centred cubic B-splines of width 4h on every node */
 
 /* FEL integrators */
 #define VP_FEL_DKD 0 /* drift dz/2, exact kick dz, drift dz/2 (one bunching per step) */
@@ -118,8 +121,8 @@ typedef struct {
  *  entropy  = -h_x h_p sum_{w_j>0} w_j ln w_j
  *  mean_p   = sum_j w_j p_j / sum_j w_j
  *  energy   = integral of H f; exact integrals of p^2, x^2 and cos x over the
- *             basis functions (h^2/6 and sinc^2(h/2) for tents, h^2/4 and
- *             sinc^3(h/2) for quadratic B-splines)
+ *             basis functions (for the B-spline of degree d, tents d = 1:
+ *             h^2 (d+1)/12 and sinc^(d+1)(h/2))
  *  FEL: A, bunching <e^{-i psi}> at the lattice phases, and
  *       fel_invariant = |A|^2 + N0^{-1} sum_j w_j eta_j (conserved by the step)
  *  nonfinite = number of NaN/Inf weights (the call then returns VP_ENONFINITE).
@@ -137,7 +140,7 @@ typedef struct {
 /* Launch shape of the deposit kernel: destination tile (in lattice nodes) and
  * threads per workgroup (a multiple of 64, at most 1024).  Zero fields keep
  * the current value.  (The solve works on fixed tiles of 32 x 64 nodes, or
- * of 80 x 80 nodes with the quadratic basis.) */
+ * of 80 x 80 (quadratic basis) or 60 x 60 (cubic) nodes.) */
 typedef struct {
     int32_t k1_tx, k1_ty;
     int32_t k1_threads;
@@ -163,8 +166,8 @@ int vp_set_hamiltonian(vp_grid* g, const vp_hamiltonian* h);
  * weight is NaN or infinite (the grid then holds no density). */
 int vp_set_density(vp_grid* g, const float* w, int32_t on_device);
 
-/* Choose the basis functions (VP_BASIS_TENT or VP_BASIS_QUADRATIC; VP_EINVAL
- * otherwise).  The weights are read as coefficients of the chosen basis from
+/* Choose the basis functions (VP_BASIS_TENT, VP_BASIS_QUADRATIC or
+ * VP_BASIS_CUBIC; VP_EINVAL otherwise).  The weights are read as coefficients of the chosen basis from
  * the next step on; the density already set is kept as it is.  Every
  * Hamiltonian and integrator works with either basis.  A deposit tile whose
  * local memory no longer fits with the wider border of the quadratic basis

@@ -19,7 +19,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "vp.h")
 
 VP_OK, VP_EINVAL, VP_ENOMEM, VP_ESTATE, VP_EHIP, VP_EUNSUPPORTED, VP_ENONFINITE, VP_ERANGE = 0, -1, -2, -3, -4, -5, -6, -7
 H_FREE, H_SHO_EXACT, H_PENDULUM, H_FEL = 0, 1, 2, 3
-BASIS_TENT, BASIS_QUADRATIC = 0, 1
+BASIS_TENT, BASIS_QUADRATIC, BASIS_CUBIC = 0, 1, 2
 
 
 class VpError(RuntimeError):
@@ -179,7 +179,7 @@ class Grid:
         check(lib().vp_set_hamiltonian(self._h, C.byref(hamiltonian(ham))))
 
     def set_basis(self, basis: int):
-        """BASIS_TENT or BASIS_QUADRATIC (quadratic B-spline basis functions)."""
+        """BASIS_TENT, BASIS_QUADRATIC or BASIS_CUBIC (B-spline basis functions)."""
         check(lib().vp_set_basis(self._h, int(basis)))
 
     def set_density(self, w):

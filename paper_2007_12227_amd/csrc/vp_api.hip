@@ -48,7 +48,7 @@ void raise_lds_limit() {
         if (hipGetDevice(&dev) != hipSuccess) return;
         if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return;
         if (lim <= (int)kDefaultLds) return;
-        for (int basis : {kBasisTent, kBasisQuadratic})
+        for (int basis : {kBasisTent, kBasisQuadratic, kBasisCubic})
             if (hipFuncSetAttribute(deposit_kernel(basis), hipFuncAttributeMaxDynamicSharedMemorySize, lim - 1024) !=
                 hipSuccess)
                 return;
@@ -258,9 +258,10 @@ int validate_tiles(int basis, const vp_tiles& t) {
 // Starting deposit shape by lattice size: the largest of the timed shapes
 // that still gives every compute unit a tile (256 of them), since larger
 // tiles rescan fewer halo sources and keep more waves per compute unit.
-vp_tiles default_tiles(int nx, int np) {
+vp_tiles default_tiles(int nx, int np, int basis = kBasisTent) {
     const double nodes = (double)nx * np;
-    if (nodes >= 256.0 * 128 * 128) return vp_tiles{128, 128, 1024};
+    // (the cubic basis's 8-cell border leaves a 128 x 128 tile without room)
+    if (nodes >= 256.0 * 128 * 128) return basis == kBasisCubic ? vp_tiles{128, 112, 1024} : vp_tiles{128, 128, 1024};
     if (nodes >= 256.0 * 128 * 64) return vp_tiles{128, 64, 512};
     return vp_tiles{64, 32, 256};
 }
@@ -328,7 +329,7 @@ PushParams push_params(const vp_axis& x, const vp_axis& p, const vp_hamiltonian&
     const double hx = spacing(x), hp = spacing(p);
     PushParams P{};
     P.kind = H.kind;
-    P.wide = basis == kBasisQuadratic ? 1 : 0;
+    P.wide = basis;  // the overlaps reach `basis` cells further than tents
     P.nx = x.n;
     P.np = p.n;
     P.x_periodic = x.periodic ? 1 : 0;
@@ -435,11 +436,12 @@ int launch_reduce_on(vp_grid* g, int mode, double dt) {
     R.out = mode == 1 ? g->at<double>(g->L.fel_state) : g->at<double>(g->L.moments);
     R.dz = dt;
     // integrals of p^2 and cos x over a basis function (per unit of spacing):
-    // h^2/6 and sinc(h/2)^2 for a tent (its transform is sinc^2), h^2/4 and
-    // sinc(h/2)^3 for the quadratic B-spline (three unit boxes convolved)
+    // the B-spline of degree d (d = 1 the tent) is d + 1 unit boxes
+    // convolved, so its variance is (d + 1)/12 and its transform sinc^(d+1)
     const double y = 0.5 * R.hx, sc = y == 0.0 ? 1.0 : sin(y) / y;
-    R.var_c = g->basis == kBasisQuadratic ? 0.25 : 1.0 / 6.0;
-    R.cos_fac = g->basis == kBasisQuadratic ? sc * sc * sc : sc * sc;
+    const int degree = g->basis + 1;
+    R.var_c = (degree + 1) / 12.0;
+    R.cos_fac = pow(sc, degree + 1);
     HIP_TRY(launch_reduce(R, g->stream));
     return VP_OK;
 }
@@ -691,10 +693,10 @@ int vp_moments(vp_grid* g, vp_moments_t* out) {
 
 int vp_set_basis(vp_grid* g, int32_t basis) {
     if (!g) return fail(VP_EINVAL, "null grid");
-    if (basis != VP_BASIS_TENT && basis != VP_BASIS_QUADRATIC) return fail(VP_EINVAL, "unknown basis %d", basis);
+    if (basis < VP_BASIS_TENT || basis > VP_BASIS_CUBIC) return fail(VP_EINVAL, "unknown basis %d", basis);
     if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
     // the deposit tile must still fit the LDS with the basis's border
-    if (validate_tiles(basis, g->tiles) != VP_OK) g->tiles = default_tiles(g->x.n, g->p.n);
+    if (validate_tiles(basis, g->tiles) != VP_OK) g->tiles = default_tiles(g->x.n, g->p.n, basis);
     g->basis = basis;
     g->plan_valid = false;
     return VP_OK;
@@ -929,7 +931,7 @@ int vp_plan_source_box(const vp_axis* x, const vp_axis* p, const vp_hamiltonian*
                        double kick_re, double kick_im, int32_t bx0, int32_t bx1, int32_t by0, int32_t by1,
                        int32_t box[4]) {
     if (!axis_ok(x) || !axis_ok(p) || !h || !box) return fail(VP_EINVAL, "invalid argument");
-    if (basis != VP_BASIS_TENT && basis != VP_BASIS_QUADRATIC) return fail(VP_EINVAL, "unknown basis %d", basis);
+    if (basis < VP_BASIS_TENT || basis > VP_BASIS_CUBIC) return fail(VP_EINVAL, "unknown basis %d", basis);
     PushParams P = push_params(*x, *p, *h, dt, basis, kick_re, kick_im);
     int b[4];
     source_box(P, bx0, bx1, by0, by1, b);

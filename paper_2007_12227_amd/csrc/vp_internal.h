@@ -17,10 +17,11 @@
 //              rows, one line per lane.  For the FEL its epilogue also forms
 //              the FP64 bunching partials of the new state, which k_fel_field
 //              sums to advance the FEL field.
-// With quadratic B-spline basis functions in place of tents (the smoother
-// basis the paper's discussion proposes) the overlaps are quintic B-splines:
-// k_deposit scatters 6x6 taps per node, and k_solve_q solves the
-// pentadiagonal mass matrix (1/120)[1, 26, 66, 26, 1] along both axes.
+// With quadratic or cubic B-spline basis functions in place of tents (the
+// smoother basis the paper's discussion proposes) the overlaps are B-splines
+// of degree 5 or 7: k_deposit scatters 6x6 or 8x8 taps per node, and
+// k_solve_spline solves the banded mass matrix ((1/120)[1, 26, 66, 26, 1] or
+// (1/5040)[1, 120, 1191, 2416, 1191, 120, 1]) along both axes.
 #pragma once
 
 #include <stdint.h>
@@ -52,14 +53,22 @@ constexpr int kReduceThreads = 256;
 constexpr int kMoments = 10;      // FP64 sums produced by the reduction kernel
 
 // Basis functions of the expansion: tents (eq. 4), or quadratic B-splines.
-enum Basis : int32_t { kBasisTent = 0, kBasisQuadratic = 1 };
+// Basis functions of the expansion: tents (eq. 4), or B-splines of degree 2 or
+// 3 (degree = basis + 1; the overlaps reach `basis` cells further than tents).
+enum Basis : int32_t { kBasisTent = 0, kBasisQuadratic = 1, kBasisCubic = 2 };
 constexpr int kPadQ = 6;          // quadratic basis: trash border of a deposit tile (5 taps past it, even for alignment)
-constexpr int kHaloQ = 24;        // quadratic basis: warm-up nodes per side of a solve tile (0.4306^24 ~ 1.6e-9)
-constexpr int kSegQ = 80;         // quadratic basis: solve tile of kSegQ x kSegQ kept nodes
-constexpr int kLineQ = kSegQ + 2 * kHaloQ;  // its window line (both axes)
+constexpr int kPadC = 8;          // cubic basis: the same for 7 taps past it
+constexpr int kLineQ = 128;       // spline bases: window line of a solve tile (both axes)
 constexpr int kPitchQ = kLineQ + 1;         // LDS row pitch of the window (odd: rows and columns are conflict-free)
 constexpr int kSolveQThreads = kLineQ;      // one window line per thread
-constexpr int kEdgeQ = 16;        // nodes from an open edge whose LDL^T coefficients are tabulated
+constexpr int kEdgeQ = 24;        // nodes from an open edge whose LDL^T coefficients are tabulated
+// warm-up nodes per side of a solve tile, by band (2: quadratic, 3: cubic):
+// the slowest decay of the inverse mass matrix, 0.4306 and 0.5353 per node,
+// reaches ~1.6e-9 over the halo
+constexpr int spline_halo(int band) { return band == 2 ? 24 : 34; }
+constexpr int spline_seg(int band) { return kLineQ - 2 * spline_halo(band); }  // kept nodes per axis
+constexpr int kHaloQ = spline_halo(2), kSegQ = spline_seg(2);  // quadratic: 80 x 80 tiles
+constexpr int kHaloC = spline_halo(3), kSegC = spline_seg(3);  // cubic: 60 x 60 tiles
 
 // Parameters of the push in cell units and of the source-box bound.
 //  FREE / PENDULUM / FEL: node (i, j) moves by
@@ -77,7 +86,7 @@ struct PushParams {
     float kd;
     float c, s;
     int32_t rk4;  // FEL by Runge-Kutta (the deposit reads its stage constants; alpha bounds |dv|)
-    int32_t wide; // 1: quadratic basis functions, whose overlaps reach one cell further (6 taps per axis)
+    int32_t wide; // the basis (Basis): its overlaps reach `wide` cells further than tents (4 + 2 wide taps per axis)
 };
 
 __host__ __device__ inline float vp_floor(float v) {
@@ -129,7 +138,7 @@ __host__ __device__ inline int iceil(float v) { return -(int)vp_floor(-v); }
 // the phase range of that box.
 __host__ __device__ inline void source_box(const PushParams& P, int bx0, int bx1, int by0, int by1,
                                            int box[4]) {
-    const float reach = P.wide ? 1.0f : 0.0f;
+    const float reach = (float)P.wide;
     const float ulo = (float)bx0 - 3.0f - reach, uhi = (float)bx1 + 2.0f + reach;
     const float vlo = (float)by0 - 3.0f - reach, vhi = (float)by1 + 2.0f + reach;
     int x0, x1, y0, y1;
@@ -269,17 +278,21 @@ hipError_t launch_fel_field(const LaunchArgs& a, hipStream_t s);
 hipError_t launch_fel_stage(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 const void* deposit_kernel(int basis);
-// Solve kernels: tents (k_solve); quadratic basis (k_solve_q), and its
+// Solve kernels: tents (k_solve); spline bases (k_solve_spline), each with a
 // variant for lattices with an open axis shorter than a window line.
-enum SolveKind : int32_t { kSolveTent = 0, kSolveQuad = 1, kSolveQuadNarrow = 2 };
+enum SolveKind : int32_t { kSolveTent = 0, kSolveQuad = 1, kSolveQuadNarrow = 2, kSolveCubic = 3, kSolveCubicNarrow = 4 };
 inline int solve_kind(int basis, int nx, int np, bool x_periodic) {
-    if (basis != kBasisQuadratic) return kSolveTent;
-    return np < kLineQ || (!x_periodic && nx < kLineQ) ? kSolveQuadNarrow : kSolveQuad;
+    if (basis == kBasisTent) return kSolveTent;
+    const bool narrow = np < kLineQ || (!x_periodic && nx < kLineQ);
+    return (basis == kBasisQuadratic ? kSolveQuad : kSolveCubic) + (narrow ? 1 : 0);
 }
 const void* solve_kernel(int kind);
 inline int solve_threads(int kind) { return kind == kSolveTent ? kSolveThreads : kSolveQThreads; }
 inline int solve_tiles(int nx, int np, int basis) {
-    if (basis == kBasisQuadratic) return ((nx + kSegQ - 1) / kSegQ) * ((np + kSegQ - 1) / kSegQ);
+    if (basis != kBasisTent) {
+        const int seg = basis == kBasisQuadratic ? kSegQ : kSegC;
+        return ((nx + seg - 1) / seg) * ((np + seg - 1) / seg);
+    }
     return ((nx + kSegX - 1) / kSegX) * ((np + kSegP - 1) / kSegP);
 }
 const void* fel_field_kernel();
@@ -287,7 +300,7 @@ const void* fel_stage_kernel();
 
 // Deposit LDS image: the tile and its border, (tx + 2 pad) x (ty + 2 pad) 64-bit cells.
 inline size_t deposit_lds_bytes(int tx, int ty, int basis) {
-    const int pad = basis == kBasisQuadratic ? kPadQ : kPad;
+    const int pad = basis == kBasisQuadratic ? kPadQ : basis == kBasisCubic ? kPadC : kPad;
     return sizeof(int64_t) * (size_t)(tx + 2 * pad) * (ty + 2 * pad);
 }
 

@@ -82,10 +82,45 @@ __device__ inline void quintic_taps(float tf, double (&b)[6]) {
     b[2] = 1.0 - ((((b[0] + b[5]) + (b[1] + b[4])) + b[3]));
 }
 
+// Septic B-spline tap weights B7(t+3) .. B7(4-t) for t in [0,1): the
+// overlaps of a cubic B-spline basis function moved to cell position k + t
+// with those of nodes k-3 .. k+4.  Each piece as a polynomial in s = 1 - t or
+// in t, times 5040:
+//   v^7,  1 + 7v + 21v^2 + 35v^3 + 35v^4 + 21v^5 + 7v^6 - 7v^7,
+//   120 + 392v + 504v^2 + 280v^3 - 84v^5 - 42v^6 + 21v^7,
+//   1191 + 1715v + 315v^2 - 665v^3 - 315v^4 + 105v^5 + 105v^6 - 35v^7,
+// the tap at cell k (the fourth) one minus the others.
+__device__ inline void septic_taps(float tf, double (&b)[8]) {
+#pragma clang fp contract(off)
+    const double c = 1.0 / 5040.0;
+    const double t = (double)tf, s = 1.0 - t;
+    auto p1 = [](double v) {
+        return fma(fma(fma(fma(fma(fma(fma(-7.0, v, 7.0), v, 21.0), v, 35.0), v, 35.0), v, 21.0), v, 7.0), v, 1.0);
+    };
+    auto p2 = [](double v) {
+        return fma(fma(fma(fma(fma(fma(fma(21.0, v, -42.0), v, -84.0), v, 0.0), v, 280.0), v, 504.0), v, 392.0), v,
+                   120.0);
+    };
+    auto p3 = [](double v) {
+        return fma(fma(fma(fma(fma(fma(fma(-35.0, v, 105.0), v, 105.0), v, -315.0), v, -665.0), v, 315.0), v, 1715.0),
+                   v, 1191.0);
+    };
+    const double s2 = s * s, t2 = t * t, s4 = s2 * s2, t4 = t2 * t2;
+    b[0] = ((s4 * s2) * s) * c;
+    b[1] = p1(s) * c;
+    b[2] = p2(s) * c;
+    b[4] = p3(t) * c;
+    b[5] = p2(t) * c;
+    b[6] = p1(t) * c;
+    b[7] = ((t4 * t2) * t) * c;
+    b[3] = 1.0 - ((((b[0] + b[7]) + (b[1] + b[6])) + (b[2] + b[5])) + b[4]);
+}
+
 template <int TAPS>
 __device__ inline void basis_taps(float t, double (&b)[TAPS]) {
     if constexpr (TAPS == 4) bspline_taps(t, b);
-    else quintic_taps(t, b);
+    else if constexpr (TAPS == 6) quintic_taps(t, b);
+    else septic_taps(t, b);
 }
 
 // 1.5 * 2^52: adding it to a value of magnitude below 2^51 leaves the value
@@ -333,7 +368,7 @@ __device__ inline void deposit_node(long long* acc, int j, int ii, float w, floa
     // [1 - TAPS, th) put the taps inside the tile and its border of PAD >=
     // TAPS - 1 cells, whatever the push produced (a non-finite position
     // included).
-    constexpr int LO = TAPS / 2 - 1, PAD = TAPS == 4 ? kPad : kPadQ;
+    constexpr int LO = TAPS / 2 - 1, PAD = TAPS == 4 ? kPad : TAPS == 6 ? kPadQ : kPadC;
     static_assert(PAD >= TAPS - 1, "the tile border must take every tap of a node that meets the tile");
     const int col0 = ii + ku - LO - X0, row0 = j + kv - LO - Y0;
     if ((unsigned)(col0 + TAPS - 1) >= (unsigned)(tw + TAPS - 1) ||
@@ -447,11 +482,12 @@ __device__ inline void scan_sources(const SourceScan& S) {
 // ds_add_u32, and integer sums are order independent.)
 // LDS holds (tx + 2 PAD) x (ty + 2 PAD) cells: the tile plus a border of PAD
 // cells that takes the taps of nodes near the tile's edge which fall outside
-// it; they are dropped with it.  TAPS: 4 (tents) or 6 (quadratic basis).
+// it; they are dropped with it.  TAPS: 4 (tents), 6 (quadratic basis) or 8
+// (cubic basis).
 // ---------------------------------------------------------------------------
 template <int TAPS>
 __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
-    constexpr int PAD = TAPS == 4 ? kPad : kPadQ;
+    constexpr int PAD = TAPS == 4 ? kPad : TAPS == 6 ? kPadQ : kPadC;
     extern __shared__ __align__(16) long long acc[];  // 16-byte aligned: read four cells at a time
     __shared__ int s_d, s_box[4], s_next;
     __shared__ float s_ab[2];
@@ -937,85 +973,114 @@ __global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2
 }
 
 // ---------------------------------------------------------------------------
-// Quadratic basis: the mass matrix (eq. 8) of quadratic B-splines is
-// M = P / 120, P = pentadiag(1, 26, 66, 26, 1), truncated at an open edge.
-// P = L D L^T with L unit lower triangular (row k: l1_k at column k-1, l2_k at
-// column k-2).  On a line that starts at an open edge the factors of its
-// first rows are those of the truncated matrix; they reach the interior limits
-// (l1 = -(r1 + r2), l2 = r1 r2, d = 1 / (r1 r2), with r1 = -0.0431 and
-// r2 = -0.4306 the roots of z^2 + (13 +- sqrt 105) z + 1: P factors into
-// tridiag(1, 13 + sqrt 105, 1) tridiag(1, 13 - sqrt 105, 1) in the interior)
-// to FP32 precision within ~10 rows.  The truncation at the far end of a line
-// changes no factor, so the same table serves lines that end at an edge.
+// Spline bases: the mass matrix (eq. 8) of B-spline basis functions of degree
+// d is M = P / scale, P the symmetric Toeplitz band of the degree-(2d+1)
+// spline at the integers, truncated at an open edge: BW = d sub-diagonals,
+// P = pentadiag(1, 26, 66, 26, 1) / 120 (quadratic), or
+// heptadiag(1, 120, 1191, 2416, 1191, 120, 1) / 5040 (cubic).
+// P = L D L^T with L unit lower triangular with BW sub-diagonals (l_m(k): row
+// k, column k - m).  On a line that starts at an open edge the factors of the
+// first rows are those of the truncated matrix; they reach their interior
+// limits (set by the poles of the band's symbol: -0.0431 and -0.4306 for the
+// quadratic, down to -0.5353 for the cubic) to FP32 precision within ~20
+// rows, and kEdgeQ rows are tabulated at compile time (FP64, rounded once).
+// The truncation at the far end of a line changes no factor, so the same
+// table serves lines that end at an edge.
 // ---------------------------------------------------------------------------
-struct PentaLdl {
-    float l1[kEdgeQ + 1], l2[kEdgeQ + 1], dinv[kEdgeQ + 1];  // row kEdgeQ: the interior limits; dinv = 120 / d
+template <int BW>
+struct BandLdl {
+    float l[BW + 1][kEdgeQ + 1];  // l[m][k], m = 1 .. BW; row kEdgeQ: the interior limits
+    float dinv[kEdgeQ + 1];       // scale / d_k
 };
 
-constexpr PentaLdl penta_ldl_table() {
-    constexpr int K = 64;
-    double d[K] = {}, l1[K] = {}, l2[K] = {};
-    d[0] = 66.0;
-    l1[1] = 26.0 / d[0];
-    d[1] = 66.0 - l1[1] * l1[1] * d[0];
-    for (int k = 2; k < K; ++k) {
-        l2[k] = 1.0 / d[k - 2];
-        l1[k] = (26.0 - l2[k] * l1[k - 1] * d[k - 2]) / d[k - 1];
-        d[k] = 66.0 - l1[k] * l1[k] * d[k - 1] - l2[k] * l2[k] * d[k - 2];
+template <int BW>
+constexpr BandLdl<BW> band_ldl_table(const double (&c)[BW + 1], double scale) {
+    constexpr int K = 128;
+    double d[K] = {}, l[K][BW + 1] = {};
+    for (int k = 0; k < K; ++k) {
+        // l_m(k) for m = BW .. 1 (the sums use the larger offsets, done first)
+        for (int m = BW; m >= 1; --m) {
+            const int j = k - m;
+            if (j < 0) continue;
+            double acc = c[m];
+            for (int i = (k - BW > 0 ? k - BW : 0); i < j; ++i) acc -= l[k][k - i] * d[i] * l[j][j - i];
+            l[k][m] = acc / d[j];
+        }
+        double dk = c[0];
+        for (int m = 1; m <= BW && m <= k; ++m) dk -= l[k][m] * l[k][m] * d[k - m];
+        d[k] = dk;
     }
-    PentaLdl T{};
+    BandLdl<BW> T{};
     for (int k = 0; k <= kEdgeQ; ++k) {
         const int r = k < kEdgeQ ? k : K - 1;
-        T.l1[k] = (float)l1[r];
-        T.l2[k] = (float)l2[r];
-        T.dinv[k] = (float)(120.0 / d[r]);
+        for (int m = 1; m <= BW; ++m) T.l[m][k] = (float)l[r][m];
+        T.dinv[k] = (float)(scale / d[r]);
     }
     return T;
 }
-constexpr PentaLdl kPentaLdl = penta_ldl_table();
+constexpr double kBandQuad[3] = {66.0, 26.0, 1.0};
+constexpr double kBandCubic[4] = {2416.0, 1191.0, 120.0, 1.0};
+template <int BW>
+struct BandTable;
+template <>
+struct BandTable<2> {
+    static constexpr BandLdl<2> T = band_ldl_table<2>(kBandQuad, 120.0);
+};
+template <>
+struct BandTable<3> {
+    static constexpr BandLdl<3> T = band_ldl_table<3>(kBandCubic, 5040.0);
+};
 
 // Solve M y = v in place along one whole window line (kLineQ elements) held
 // in registers (every index is a constant: the interior factors are
 // instruction operands).  edge: the line starts at an open edge (the
 // tabulated first rows, chosen by scalar selects); else it starts at a cut
 // inside the lattice or on a periodic wrap, where the recursions start from
-// zero with the interior factors, an error that decays by 0.4306 per node.
+// zero with the interior factors, an error that decays with the slowest pole.
 // The far end needs no flag (see above); a cut there starts the backward
-// recursion from zero, with the same decay.  The term of the older neighbour
-// is added first, so each recursion step waits on one fused multiply-add of
-// the step before.
-__device__ inline void penta_line(float (&v)[kLineQ], bool edge) {
-    auto l1 = [&](int k) { return k < kEdgeQ && edge ? kPentaLdl.l1[k] : kPentaLdl.l1[kEdgeQ]; };
-    auto l2 = [&](int k) { return k < kEdgeQ && edge ? kPentaLdl.l2[k] : kPentaLdl.l2[kEdgeQ]; };
-    auto dinv = [&](int k) { return k < kEdgeQ && edge ? kPentaLdl.dinv[k] : kPentaLdl.dinv[kEdgeQ]; };
-    // forward: z_k = v_k - l1_k z_{k-1} - l2_k z_{k-2};  v_k <- z_k / d_k
-    float z1 = 0.0f, z2 = 0.0f;
+// recursion from zero, with the same decay.  The terms of the older
+// neighbours are added first, so each recursion step waits on one fused
+// multiply-add of the step before.
+template <int BW>
+__device__ inline void band_line(float (&v)[kLineQ], bool edge) {
+    constexpr const BandLdl<BW>& T = BandTable<BW>::T;
+    auto lm = [&](int m, int k) { return k < kEdgeQ && edge ? T.l[m][k] : T.l[m][kEdgeQ]; };
+    auto dinv = [&](int k) { return k < kEdgeQ && edge ? T.dinv[k] : T.dinv[kEdgeQ]; };
+    // forward: z_k = v_k - sum_m l_m(k) z_{k-m};  v_k <- z_k / d_k
+    float z[BW + 1] = {};  // z[m]: z_{k-m}
 #pragma unroll
     for (int k = 0; k < kLineQ; ++k) {
-        const float z = fmaf(-l1(k), z1, fmaf(-l2(k), z2, v[k]));
-        z2 = z1;
-        z1 = z;
-        v[k] = z * dinv(k);
+        float acc = v[k];
+#pragma unroll
+        for (int m = BW; m >= 1; --m) acc = fmaf(-lm(m, k), z[m], acc);
+#pragma unroll
+        for (int m = BW; m >= 2; --m) z[m] = z[m - 1];
+        z[1] = acc;
+        v[k] = acc * dinv(k);
     }
-    // backward: y_k = v_k - l1_{k+1} y_{k+1} - l2_{k+2} y_{k+2}
-    float y1 = 0.0f, y2 = 0.0f;
+    // backward: y_k = v_k - sum_m l_m(k+m) y_{k+m}
+    float y[BW + 1] = {};  // y[m]: y_{k+m}
 #pragma unroll
     for (int k = kLineQ - 1; k >= 0; --k) {
-        const float y = fmaf(-l1(k + 1), y1, fmaf(-l2(k + 2), y2, v[k]));
-        y2 = y1;
-        y1 = y;
-        v[k] = y;
+        float acc = v[k];
+#pragma unroll
+        for (int m = BW; m >= 1; --m) acc = fmaf(-lm(m, k + m), y[m], acc);
+#pragma unroll
+        for (int m = BW; m >= 2; --m) y[m] = y[m - 1];
+        y[1] = acc;
+        v[k] = acc;
     }
 }
 
 // The same solve along a line of n <= kLineQ elements in LDS, v[k * S], for
 // lattice axes shorter than the window (taken whole): a loop, the values
 // going through registers U at a time.
-template <int S>
-__device__ inline void penta_line_lds(float* v, int n, bool edge) {
+template <int S, int BW>
+__device__ inline void band_line_lds(float* v, int n, bool edge) {
+    constexpr const BandLdl<BW>& T = BandTable<BW>::T;
     constexpr int U = 8;
     static_assert(kEdgeQ % U == 0, "a group of rows is wholly inside or outside the table");
-    float z1 = 0.0f, z2 = 0.0f;
+    float z[BW + 1] = {};
     for (int k0 = 0; k0 < n; k0 += U) {
         float r[U];
 #pragma unroll
@@ -1024,16 +1089,19 @@ __device__ inline void penta_line_lds(float* v, int n, bool edge) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = tab ? k0 + u : kEdgeQ;
-            const float z = fmaf(-kPentaLdl.l1[k], z1, fmaf(-kPentaLdl.l2[k], z2, r[u]));
-            z2 = z1;
-            z1 = z;
-            r[u] = z * kPentaLdl.dinv[k];
+            float acc = r[u];
+#pragma unroll
+            for (int m = BW; m >= 1; --m) acc = fmaf(-T.l[m][k], z[m], acc);
+#pragma unroll
+            for (int m = BW; m >= 2; --m) z[m] = z[m - 1];
+            z[1] = acc;
+            r[u] = acc * T.dinv[k];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (k0 + u < n) v[(k0 + u) * S] = r[u];
     }
-    float y1 = 0.0f, y2 = 0.0f;
+    float y[BW + 1] = {};
     for (int k1 = n - 1; k1 >= 0; k1 -= U) {
         float r[U];
 #pragma unroll
@@ -1041,12 +1109,13 @@ __device__ inline void penta_line_lds(float* v, int n, bool edge) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = k1 - u;
-            const int a1 = edge && k + 1 < kEdgeQ ? k + 1 : kEdgeQ;
-            const int a2 = edge && k + 2 < kEdgeQ ? k + 2 : kEdgeQ;
-            const float y = fmaf(-kPentaLdl.l1[a1], y1, fmaf(-kPentaLdl.l2[a2], y2, r[u]));
-            y2 = y1;
-            y1 = y;
-            r[u] = y;
+            float acc = r[u];
+#pragma unroll
+            for (int m = BW; m >= 1; --m) acc = fmaf(-T.l[m][edge && k + m < kEdgeQ ? k + m : kEdgeQ], y[m], acc);
+#pragma unroll
+            for (int m = BW; m >= 2; --m) y[m] = y[m - 1];
+            y[1] = acc;
+            r[u] = acc;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -1058,7 +1127,7 @@ __device__ inline void penta_line_lds(float* v, int n, bool edge) {
 // nodes of w e^{-i(phi_i + q_j)} (half-drift phases) and of w e^{-i phi_i}
 // (lattice phases, the Runge-Kutta step's stage 1); k_fel_field sums the
 // tiles.  v: this thread's parts.  Called by every thread.
-__device__ inline void quad_tile_partials(double* pt, double (&v)[kPartialsPerTile],
+__device__ inline void spline_tile_partials(double* pt, double (&v)[kPartialsPerTile],
                                           double (&s_red)[kSolveQThreads / 64][kPartialsPerTile]) {
     for (int o = 32; o > 0; o >>= 1)
         for (int c = 0; c < kPartialsPerTile; ++c) v[c] += __shfl_down(v[c], o);
@@ -1076,7 +1145,7 @@ __device__ inline void quad_tile_partials(double* pt, double (&v)[kPartialsPerTi
 // The kept nodes of a solve tile out of LDS (kept row r at win[r * kPitchQ],
 // column c at ox + c), whole rows per store; for the FEL also the tile's
 // bunching partials.
-__device__ inline void quad_tile_out(const VpInst& I, int t, const float* win, int ox, int X0, int kw, int P0, int kp,
+__device__ inline void spline_tile_out(const VpInst& I, int t, const float* win, int ox, int X0, int kw, int P0, int kp,
                                      int nx, float* dst, double (&s_red)[kSolveQThreads / 64][kPartialsPerTile]) {
     const int tid = threadIdx.x;
     const bool fel = I.push.kind == kFel;
@@ -1103,58 +1172,64 @@ __device__ inline void quad_tile_out(const VpInst& I, int t, const float* win, i
             v[3] = -c1 * e.y;
         }
     }
-    if (fel) quad_tile_partials(I.partials + kPartialsPerTile * t, v, s_red);
+    if (fel) spline_tile_partials(I.partials + kPartialsPerTile * t, v, s_red);
 }
 
-// Window geometry of a solve tile (quadratic basis): kept nodes [X0, X0 + kw)
-// x [P0, P0 + kp); window columns [xs, xs + lx) (unwrapped on a periodic
-// axis: always a whole line there, the halo on the far side of a narrow last
-// tile only longer) and rows [ps, ps + lp), shifted to end at an open edge; an
-// open axis shorter than the window is taken whole.
-struct QuadTile {
+// Window geometry of a solve tile (spline basis of band BW): kept nodes
+// [X0, X0 + kw) x [P0, P0 + kp), seg x seg at most; window columns
+// [xs, xs + lx) (unwrapped on a periodic axis: always a whole line there, the
+// halo on the far side of a narrow last tile only longer) and rows
+// [ps, ps + lp), shifted to end at an open edge; an open axis shorter than the
+// window is taken whole.
+template <int BW>
+struct SplineTile {
+    static constexpr int kHalo = spline_halo(BW), kSeg = spline_seg(BW);
     int nx, np, X0, kw, P0, kp, lx, xs, lp, ps, ox, op;
     bool periodic;
-    __device__ QuadTile(const VpInst& I, int t) {
+    __device__ SplineTile(const VpInst& I, int t) {
         nx = I.push.nx;
         np = I.push.np;
         periodic = I.push.x_periodic != 0;
-        const int tiles_x = (nx + kSegQ - 1) / kSegQ;
+        const int tiles_x = (nx + kSeg - 1) / kSeg;
         const int tyi = t / tiles_x, txi = t - tyi * tiles_x;
-        X0 = txi * kSegQ;
-        kw = min(kSegQ, nx - X0);
-        P0 = tyi * kSegQ;
-        kp = min(kSegQ, np - P0);
+        X0 = txi * kSeg;
+        kw = min(kSeg, nx - X0);
+        P0 = tyi * kSeg;
+        kp = min(kSeg, np - P0);
         lx = periodic ? kLineQ : min(nx, kLineQ);
-        xs = periodic ? X0 - kHaloQ : max(0, min(X0 - kHaloQ, nx - lx));
+        xs = periodic ? X0 - kHalo : max(0, min(X0 - kHalo, nx - lx));
         lp = min(np, kLineQ);
-        ps = max(0, min(P0 - kHaloQ, np - lp));
+        ps = max(0, min(P0 - kHalo, np - lp));
         ox = X0 - xs;
         op = P0 - ps;
     }
 };
 
 // ---------------------------------------------------------------------------
-// k_solve_q: w_new = (M_x^{-1} (x) M_p^{-1}) b for quadratic basis functions,
-// on lattices whose open axes have at least kLineQ nodes (k_solve_q_narrow
-// takes the others).  A workgroup of kLineQ threads owns a kSegQ x kSegQ
-// output tile inside the kLineQ x kLineQ window around it (QuadTile).
+// k_solve_spline<BW>: w_new = (M_x^{-1} (x) M_p^{-1}) b for spline basis
+// functions (BW 2: quadratic, 80 x 80 tiles; 3: cubic, 60 x 60), on lattices
+// whose open axes have at least kLineQ nodes (k_solve_spline_narrow takes the
+// others).  A workgroup of kLineQ threads owns a tile inside the
+// kLineQ x kLineQ window around it (SplineTile).
 //  p phase: thread c loads window column c into registers through a buffer
 //    resource based at the window's first row (the row's byte offset advances
 //    by a register add; every row in flight at once; a wavefront's lanes read
 //    64 consecutive nodes of a row per instruction), solves it, and puts the
 //    kept rows into LDS (rows outside them go to two trash rows, so the
 //    writes need no branches).  (Half the rows staged by direct loads into
-//    LDS instead measured 2.7 us slower at 2048^2: the column has to reach
-//    the registers anyway.)
+//    LDS instead measured 2.7 us slower at 2048^2, quadratic: the column has
+//    to reach the registers anyway.)
 //  x phase: thread r solves kept row r in registers.
 //  out:     the kept columns of the kept rows go out, whole rows per store.
-// The LDS holds the kept rows and two trash rows at an odd pitch (42 KB:
-// three tiles per compute unit, the 676 tiles of a 2048^2 lattice in one
-// round), and both passes address it without bank conflicts.  For the FEL
-// the write-out also forms the tile's bunching partials.
+// The LDS holds the kept rows and two trash rows at an odd pitch (42 KB for
+// the quadratic: three tiles per compute unit, the 676 tiles of a 2048^2
+// lattice in one round), and both passes address it without bank conflicts.
+// For the FEL the write-out also forms the tile's bunching partials.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kSolveQThreads) void k_solve_q(LaunchArgs A) {
-    __shared__ float win[(kSegQ + 2) * kPitchQ];  // row 1 + r: kept row r; rows 0 and kSegQ + 1: trash
+template <int BW>
+__global__ __launch_bounds__(kSolveQThreads) void k_solve_spline(LaunchArgs A) {
+    constexpr int kSeg = spline_seg(BW);
+    __shared__ float win[(kSeg + 2) * kPitchQ];  // row 1 + r: kept row r; rows 0 and kSeg + 1: trash
     __shared__ double s_red[kSolveQThreads / 64][kPartialsPerTile];
     __shared__ int s_d;
     const int tid = threadIdx.x;
@@ -1164,7 +1239,7 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_q(LaunchArgs A) {
     const int d = __builtin_amdgcn_readfirstlane(s_d);
     const VpInst& I = A.inst[d];
     const int t = item - A.off[d];
-    const QuadTile T(I, t);
+    const SplineTile<BW> T(I, t);
     const int nx = T.nx;
     float* __restrict__ dst = I.w[((I.parity0 + A.parity) & 1) ^ 1];
 
@@ -1181,10 +1256,10 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_q(LaunchArgs A) {
 #pragma unroll
         for (int k = 0; k < kLineQ; ++k, off += row_bytes)
             v[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
-        penta_line(v, T.ps == 0);
+        band_line<BW>(v, T.ps == 0);
         // window row k -> LDS row 1 + (k - op), clamped to the trash rows
 #pragma unroll
-        for (int k = 0; k < kLineQ; ++k) win[(min(max(k - T.op, -1), kSegQ) + 1) * kPitchQ + tid] = v[k];
+        for (int k = 0; k < kLineQ; ++k) win[(min(max(k - T.op, -1), kSeg) + 1) * kPitchQ + tid] = v[k];
     }
     __syncthreads();
     if (tid < T.kp) {
@@ -1193,21 +1268,22 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_q(LaunchArgs A) {
         float v[kLineQ];
 #pragma unroll
         for (int k = 0; k < kLineQ; ++k) v[k] = row[k];
-        penta_line(v, !T.periodic && T.xs == 0);
+        band_line<BW>(v, !T.periodic && T.xs == 0);
 #pragma unroll
         for (int k = 0; k < kLineQ; ++k) row[k] = v[k];
     }
     __syncthreads();
-    quad_tile_out(I, t, win + kPitchQ, T.ox, T.X0, T.kw, T.P0, T.kp, nx, dst, s_red);
+    spline_tile_out(I, t, win + kPitchQ, T.ox, T.X0, T.kw, T.P0, T.kp, nx, dst, s_red);
 }
 
 // ---------------------------------------------------------------------------
-// k_solve_q_narrow: the same solve for launches with an open axis shorter
-// than kLineQ nodes.  The whole window (up to kLineQ x kLineQ) is staged in
-// LDS by direct loads and every line is solved there by penta_line_lds:
-// slower, and only small lattices take it.
+// k_solve_spline_narrow<BW>: the same solve for launches with an open axis
+// shorter than kLineQ nodes.  The whole window (up to kLineQ x kLineQ) is
+// staged in LDS by direct loads and every line is solved there by
+// band_line_lds: slower, and only small lattices take it.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kSolveQThreads) void k_solve_q_narrow(LaunchArgs A) {
+template <int BW>
+__global__ __launch_bounds__(kSolveQThreads) void k_solve_spline_narrow(LaunchArgs A) {
     __shared__ float win[kLineQ * kPitchQ];
     __shared__ double s_red[kSolveQThreads / 64][kPartialsPerTile];
     __shared__ int s_d;
@@ -1218,7 +1294,7 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_q_narrow(LaunchArgs A)
     const int d = __builtin_amdgcn_readfirstlane(s_d);
     const VpInst& I = A.inst[d];
     const int t = item - A.off[d];
-    const QuadTile T(I, t);
+    const SplineTile<BW> T(I, t);
     const int nx = T.nx;
     float* __restrict__ dst = I.w[((I.parity0 + A.parity) & 1) ^ 1];
     if (tid < T.lx) {
@@ -1231,11 +1307,11 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_q_narrow(LaunchArgs A)
     }
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
-    if (tid < T.lx) penta_line_lds<kPitchQ>(win + tid, T.lp, T.ps == 0);
+    if (tid < T.lx) band_line_lds<kPitchQ, BW>(win + tid, T.lp, T.ps == 0);
     __syncthreads();
-    if (tid < T.kp) penta_line_lds<1>(win + (T.op + tid) * kPitchQ, T.lx, !T.periodic && T.xs == 0);
+    if (tid < T.kp) band_line_lds<1, BW>(win + (T.op + tid) * kPitchQ, T.lx, !T.periodic && T.xs == 0);
     __syncthreads();
-    quad_tile_out(I, t, win + T.op * kPitchQ, T.ox, T.X0, T.kw, T.P0, T.kp, nx, dst, s_red);
+    spline_tile_out(I, t, win + T.op * kPitchQ, T.ox, T.X0, T.kw, T.P0, T.kp, nx, dst, s_red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1334,7 +1410,7 @@ __device__ inline void sincos_small(double x, double* s, double* c) {
 // is a column sum of w e^{-i q} turned by e^{-i(phi + dz^2/4 k1)}.
 // ---------------------------------------------------------------------------
 // One solve tile of SX x SP nodes (the tiles of the instance's solve: tents
-// 32 x 64, quadratic basis 80 x 80); thread t takes column t mod SX and rows
+// 32 x 64, quadratic basis 80 x 80, cubic 60 x 60); thread t takes column t mod SX and rows
 // t / SX + (256 / SX) i (threads past the last whole row group idle).
 template <int SX, int SP>
 __device__ inline void stage_tile(const VpInst& I, int t, int parity, double (&s_red)[kStageThreads / 64][4]) {
@@ -1403,7 +1479,8 @@ __global__ __launch_bounds__(kStageThreads) void k_fel_stage(LaunchArgs A) {
         const int d = __builtin_amdgcn_readfirstlane(find_instance(A.off, A.ninst, item));
         const VpInst& I = A.inst[d];
         if (I.push.kind != kFel || !I.push.rk4) continue;
-        if (I.push.wide) stage_tile<kSegQ, kSegQ>(I, item - A.off[d], A.parity, s_red);
+        if (I.push.wide == kBasisQuadratic) stage_tile<kSegQ, kSegQ>(I, item - A.off[d], A.parity, s_red);
+        else if (I.push.wide == kBasisCubic) stage_tile<kSegC, kSegC>(I, item - A.off[d], A.parity, s_red);
         else stage_tile<kSegX, kSegP>(I, item - A.off[d], A.parity, s_red);
     }
 }
@@ -1498,13 +1575,16 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
 
 hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s, int basis) {
     if (basis == kBasisQuadratic) hipLaunchKernelGGL(k_deposit<6>, dim3(grid), dim3(threads), lds, s, a);
+    else if (basis == kBasisCubic) hipLaunchKernelGGL(k_deposit<8>, dim3(grid), dim3(threads), lds, s, a);
     else hipLaunchKernelGGL(k_deposit<4>, dim3(grid), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s, int kind) {
-    if (kind == kSolveQuad) hipLaunchKernelGGL(k_solve_q, dim3(grid), dim3(kSolveQThreads), 0, s, a);
-    else if (kind == kSolveQuadNarrow) hipLaunchKernelGGL(k_solve_q_narrow, dim3(grid), dim3(kSolveQThreads), 0, s, a);
+    if (kind == kSolveQuad) hipLaunchKernelGGL(k_solve_spline<2>, dim3(grid), dim3(kSolveQThreads), 0, s, a);
+    else if (kind == kSolveQuadNarrow) hipLaunchKernelGGL(k_solve_spline_narrow<2>, dim3(grid), dim3(kSolveQThreads), 0, s, a);
+    else if (kind == kSolveCubic) hipLaunchKernelGGL(k_solve_spline<3>, dim3(grid), dim3(kSolveQThreads), 0, s, a);
+    else if (kind == kSolveCubicNarrow) hipLaunchKernelGGL(k_solve_spline_narrow<3>, dim3(grid), dim3(kSolveQThreads), 0, s, a);
     else hipLaunchKernelGGL(k_solve, dim3(grid), dim3(kSolveThreads), 0, s, a);
     return hipGetLastError();
 }
@@ -1525,12 +1605,15 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
 }
 
 const void* deposit_kernel(int basis) {
-    return basis == kBasisQuadratic ? reinterpret_cast<const void*>(&k_deposit<6>)
-                                    : reinterpret_cast<const void*>(&k_deposit<4>);
+    if (basis == kBasisQuadratic) return reinterpret_cast<const void*>(&k_deposit<6>);
+    if (basis == kBasisCubic) return reinterpret_cast<const void*>(&k_deposit<8>);
+    return reinterpret_cast<const void*>(&k_deposit<4>);
 }
 const void* solve_kernel(int kind) {
-    if (kind == kSolveQuad) return reinterpret_cast<const void*>(&k_solve_q);
-    if (kind == kSolveQuadNarrow) return reinterpret_cast<const void*>(&k_solve_q_narrow);
+    if (kind == kSolveQuad) return reinterpret_cast<const void*>(&k_solve_spline<2>);
+    if (kind == kSolveQuadNarrow) return reinterpret_cast<const void*>(&k_solve_spline_narrow<2>);
+    if (kind == kSolveCubic) return reinterpret_cast<const void*>(&k_solve_spline<3>);
+    if (kind == kSolveCubicNarrow) return reinterpret_cast<const void*>(&k_solve_spline_narrow<3>);
     return reinterpret_cast<const void*>(&k_solve);
 }
 const void* fel_field_kernel() { return reinterpret_cast<const void*>(&k_fel_field); }

@@ -1,0 +1,198 @@
+"""Cubic B-spline basis functions on the GPU (8x8 septic-tap deposit and the
+heptadiagonal solve, 60-node solve tiles) against the FP64 spline-basis
+oracle of degree 3, through the C interface.  Bars as for tents: relative L1
+<= 1e-5 after one step from the same weights, <= 1e-4 after a run."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import spline_basis as Q
+from paper_2007_12227_amd.inputs import (FEL_RK4, H_FEL, H_FREE, H_PENDULUM, H_SHO_EXACT, Axis, Hamiltonian,
+                                         fel_gaussian, gaussian, pendulum_axes, pendulum_band, rng)
+
+pytestmark = pytest.mark.gpu
+DEG = 3
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2007_12227_amd import binding
+    binding.lib()
+    return binding
+
+
+def cubic_grid(B, x, p, ham, w, tiles=None):
+    g = B.Grid(x, p)
+    g.set_basis(B.BASIS_CUBIC)
+    if tiles:
+        g.set_tiles(tiles[:2], tiles[2] if len(tiles) > 2 else 0)
+    g.set_hamiltonian(ham)
+    g.set_density(np.ascontiguousarray(w, dtype=np.float32))
+    return g
+
+
+def gpu_steps(B, x, p, ham, w, dt, steps, tiles=None):
+    g = cubic_grid(B, x, p, ham, w, tiles)
+    g.step(dt, steps)
+    out = g.density().astype(np.float64)
+    m = g.moments()
+    g.close()
+    return out, m
+
+
+def oracle_step(x, p, ham, w32, dt):
+    du, dv = oracle.push(x, p, ham, dt)
+    return Q.step(x, p, du, dv, w32.astype(np.float64), DEG)
+
+
+def case(kind):
+    if kind == H_SHO_EXACT:
+        x, p = Axis(-4, 4, 130, False), Axis(-4, 4, 171, False)
+        return x, p, Hamiltonian(kind, omega=1.0), 0.4, gaussian(x, p, 1.0, -0.5, 0.6)
+    x, p = pendulum_axes(200, 170)
+    w = gaussian(x, p, 0.3, 0.8, 0.5) + 1e-3 * rng(81).random((p.n, x.n))
+    return x, p, Hamiltonian(kind, a=1.3), 0.07, w
+
+
+@pytest.mark.parametrize("kind", [H_FREE, H_PENDULUM, H_SHO_EXACT])
+def test_one_step_each_kind(B, kind):
+    x, p, ham, dt, w = case(kind)
+    w = w.astype(np.float32)
+    got, _ = gpu_steps(B, x, p, ham, w, dt, 1)
+    err = oracle.rel_l1(got, oracle_step(x, p, ham, w, dt))
+    print(f"cubic, kind {kind}: rel L1 {err:.3e}", flush=True)
+    assert err <= 1e-5
+
+
+def test_deposit_tilings_agree_bitwise(B):
+    x, p, ham, dt, w = case(H_PENDULUM)
+    w = w.astype(np.float32)
+    ref = oracle_step(x, p, ham, w, dt)
+    first = None
+    for t in [None, (64, 16), (24, 5, 64), (200, 24, 1024), (128, 112, 1024)]:
+        got, _ = gpu_steps(B, x, p, ham, w, dt, 1, t)
+        assert oracle.rel_l1(got, ref) <= 1e-5, t
+        if first is None:
+            first = got
+        assert np.array_equal(got, first), t
+
+
+def test_tile_too_large_for_the_border_is_refused(B):
+    """A 128 x 128 deposit tile with the cubic basis's 8-cell border needs more
+    LDS than a workgroup has."""
+    x, p = pendulum_axes(256)
+    g = B.Grid(x, p)
+    g.set_basis(B.BASIS_CUBIC)
+    with pytest.raises(B.VpError) as e:
+        g.set_tiles((128, 128), 1024)
+    assert e.value.code == B.VP_EINVAL
+    g.close()
+
+
+@pytest.mark.parametrize("nx,np_,periodic", [(4, 64, True), (40, 24, False), (7, 130, False), (90, 300, True),
+                                             (300, 90, False), (128, 128, False)])
+def test_one_step_window_shapes(B, nx, np_, periodic):
+    if periodic:
+        x, p = pendulum_axes(nx, np_)
+        ham, dt = Hamiltonian(H_PENDULUM, a=0.8), 0.05
+    else:
+        x, p = Axis(-3, 3, nx, False), Axis(-3, 3, np_, False)
+        ham, dt = Hamiltonian(H_SHO_EXACT, omega=1.0), 0.3
+    w = (0.5 + rng(82).random((np_, nx))).astype(np.float32)
+    got, _ = gpu_steps(B, x, p, ham, w, dt, 1)
+    assert oracle.rel_l1(got, oracle_step(x, p, ham, w, dt)) <= 1e-5
+
+
+def test_whole_cell_free_streaming_and_no_motion(B):
+    """Row j streams by j - 8 whole cells: the step returns the rolled rows up
+    to the FP32 rounding of b amplified by the inverse mass matrix, at most
+    1 / lambda_min^2 = 343 per unit (lambda_min = 272/5040, the cubic band's
+    symbol at the highest frequency, per axis); random weights carry that
+    frequency."""
+    x, p = Axis(0.0, 64.0, 64, True), Axis(-8.0, 8.0, 17, False)
+    w = (0.5 + rng(83).random((p.n, x.n))).astype(np.float32)
+    bound = 2.0 * 2.0 ** -24 * float(np.abs(w).max()) * (5040.0 / 272.0) ** 2
+    got, _ = gpu_steps(B, x, p, Hamiltonian(H_FREE), w, 1.0, 1)
+    err = max(float(np.abs(got[j] - np.roll(w[j], j - 8)).max()) for j in range(p.n))
+    print(f"cubic whole-cell stream: max error {err:.3e} (bound {bound:.3e})", flush=True)
+    assert err <= bound
+    got, _ = gpu_steps(B, x, p, Hamiltonian(H_FREE), w, 0.0, 1)
+    assert oracle.rel_l1(got, w.astype(np.float64)) <= 1e-5
+
+
+@pytest.mark.parametrize("kind", [H_PENDULUM, H_SHO_EXACT])
+def test_moments_match_oracle(B, kind):
+    x, p, ham, dt, w = case(kind)
+    g = cubic_grid(B, x, p, ham, w)
+    g.step(dt, 3)
+    state = g.density().astype(np.float64)
+    m = g.moments()
+    g.close()
+    ref = Q.moments(x, p, ham, state, DEG)
+    for k in ("sum_w", "mass", "neg_mass", "l1", "entropy", "mean_p", "energy"):
+        assert abs(m[k] - ref[k]) <= 1e-9 * max(1.0, abs(ref[k])), (k, m[k], ref[k])
+
+
+def test_run_pendulum_gaussian_256(B):
+    x, p = pendulum_axes(256)
+    w0 = gaussian(x, p, 0.0, 1.0, 0.3) + 1e-3 * rng(84).random((256, 256))
+    ham = Hamiltonian(H_PENDULUM, a=1.0)
+    got, _ = gpu_steps(B, x, p, ham, w0, 0.05, 100)
+    ref = Q.run(x, p, ham, w0.astype(np.float32).astype(np.float64), 0.05, 100, DEG)
+    err = oracle.rel_l1(got, ref)
+    print(f"cubic pendulum 256^2, 100 steps: rel L1 {err:.3e}", flush=True)
+    assert err <= 1e-4
+
+
+def test_one_step_at_2048_in_the_benchmark_launch(B):
+    inst = pendulum_band(2048)
+    g = cubic_grid(B, inst.x, inst.p, inst.ham, inst.w0)
+    g.autotune(inst.dt)
+    w32 = inst.w0.astype(np.float32)
+    g.step(inst.dt, 1)
+    got = g.density().astype(np.float64)
+    g.close()
+    err = oracle.rel_l1(got, oracle_step(inst.x, inst.p, inst.ham, w32, inst.dt))
+    print(f"cubic 2048^2 band: rel L1 {err:.3e}", flush=True)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("integrator", [0, FEL_RK4])
+def test_fel_run_256(B, integrator):
+    inst = fel_gaussian(256, 200)
+    ham = Hamiltonian(H_FEL, A_re=1e-3, fel_delta=0.2, fel_sigma2=0.3, integrator=integrator)
+    w32 = inst.w0.astype(np.float32)
+    g = cubic_grid(B, inst.x, inst.p, ham, w32)
+    g.step(inst.dt, 1)
+    one = g.density().astype(np.float64)
+    g.step(inst.dt, 199)
+    got = g.density().astype(np.float64)
+    m = g.moments()
+    g.close()
+    ref1, _ = Q.run_fel(inst.x, inst.p, ham, w32.astype(np.float64), inst.dt, 1, degree=DEG)
+    assert oracle.rel_l1(one, ref1) <= 1e-5
+    ref, A = Q.run_fel(inst.x, inst.p, ham, w32.astype(np.float64), inst.dt, 200, degree=DEG)
+    err = oracle.rel_l1(got, ref)
+    Ag = complex(m["A_re"], m["A_im"])
+    print(f"cubic FEL 256^2 (integrator {integrator}), 200 steps: rel L1 {err:.3e}, |A| {abs(Ag):.6e} "
+          f"(oracle {abs(A):.6e})", flush=True)
+    assert err <= 1e-4
+    assert abs(Ag - A) <= 1e-4 * abs(A)
+
+
+def test_batch_of_cubic_grids_matches_single_runs(B):
+    cases = []
+    for k, (nx, npp, a) in enumerate([(96, 80, 0.7), (200, 170, 1.3), (64, 130, 1.0)]):
+        x, p = pendulum_axes(nx, npp)
+        w = (gaussian(x, p, 0.2, 0.3, 0.5) + 1e-3 * rng(85 + k).random((npp, nx))).astype(np.float32)
+        cases.append((x, p, Hamiltonian(H_PENDULUM, a=a), w, 0.05))
+    singles = [gpu_steps(B, x, p, h, w, dt, 20)[0] for x, p, h, w, dt in cases]
+    grids = [cubic_grid(B, x, p, h, w) for x, p, h, w, _ in cases]
+    bt = B.Batch(grids, [c[4] for c in cases])
+    bt.step(20)
+    bt.close()
+    for g, ref in zip(grids, singles):
+        assert np.array_equal(g.density().astype(np.float64), ref)
+        g.close()
