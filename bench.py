@@ -64,20 +64,21 @@ def bench_fel(binding, steps, integrator=0):
             "ms_per_step": 1e3 * sec / steps, "A_abs": abs(complex(m["A_re"], m["A_im"]))}
 
 
-def bench_quadratic(binding, n, steps, warmup):
-    """The headline workload (pendulum band, n^2) with quadratic B-spline basis
-    functions: autotuned deposit tiles, graph replay; per-kernel times and
-    the negative mass beside the tent basis's after the same steps, and the
-    same comparison on the FEL flat-top start."""
+def bench_spline(binding, name, n, steps, warmup):
+    """The headline workload (pendulum band, n^2) with quadratic or cubic
+    B-spline basis functions (name): autotuned deposit tiles, graph replay;
+    per-kernel times and the negative mass beside the tent basis's after the
+    same steps, and the same comparison on the FEL flat-top start."""
     from paper_2007_12227_amd.inputs import pendulum_band
+    spline = {"quadratic": binding.BASIS_QUADRATIC, "cubic": binding.BASIS_CUBIC}[name]
     inst = pendulum_band(n)
-    out = {"workload": f"pendulum_band_{n}_quadratic", "steps": steps}
-    for basis, tag in ((binding.BASIS_QUADRATIC, ""), (binding.BASIS_TENT, "tent_")):
+    out = {"workload": f"pendulum_band_{n}_{name}", "steps": steps}
+    for basis, tag in ((spline, ""), (binding.BASIS_TENT, "tent_")):
         g = binding.Grid(inst.x, inst.p)
         g.set_basis(basis)
         g.set_hamiltonian(inst.ham)
         g.set_density(inst.w0)
-        if basis == binding.BASIS_QUADRATIC:
+        if basis == spline:
             g.autotune(inst.dt)
             sec, _ = timed_steps(g, inst.dt, steps, warmup)
             out.update(value=inst.nodes * steps / sec, ms_per_step=1e3 * sec / steps, tiles=g.tiles()["k1"])
@@ -95,7 +96,7 @@ def bench_quadratic(binding, n, steps, warmup):
     # the paper discusses), 500 steps at 1024^2, both bases
     from paper_2007_12227_amd.inputs import fel_flattop
     fl = fel_flattop(1024, 500)
-    for basis, tag in ((binding.BASIS_QUADRATIC, ""), (binding.BASIS_TENT, "tent_")):
+    for basis, tag in ((spline, ""), (binding.BASIS_TENT, "tent_")):
         g = binding.Grid(fl.x, fl.p)
         g.set_basis(basis)
         g.set_hamiltonian(fl.ham)
@@ -231,7 +232,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--fel-steps", type=int, default=2000)
-    ap.add_argument("--quadratic-steps", type=int, default=1000)
+    ap.add_argument("--spline-steps", type=int, default=1000,
+                    help="steps of the quadratic and cubic basis lines")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-overload", type=float, default=1.2,
@@ -241,8 +243,8 @@ def main():
                     help="deposit launch shape COLSxROWSxTHREADS for the tuned path instead of autotuning "
                          "(uniform dispatches for profiling)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (untuned, no graph) run")
-    ap.add_argument("--basis", choices=("tent", "quadratic"), default="tent",
-                    help="basis functions of the timed workload (quadratic: for profiling its kernels)")
+    ap.add_argument("--basis", choices=("tent", "quadratic", "cubic"), default="tent",
+                    help="basis functions of the timed workload (quadratic, cubic: for profiling their kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -258,13 +260,12 @@ def main():
     binding.lib()
     inst = pendulum_band(args.n)
     N = inst.nodes
-    quad = args.basis == "quadratic"
-    workload = f"pendulum_band_{args.n}" + ("_quadratic" if quad else "")
+    basis = {"tent": binding.BASIS_TENT, "quadratic": binding.BASIS_QUADRATIC, "cubic": binding.BASIS_CUBIC}[args.basis]
+    workload = f"pendulum_band_{args.n}" + ("" if args.basis == "tent" else f"_{args.basis}")
 
     def grid_of(inst):
         g = binding.grid_for(inst)
-        if quad:
-            g.set_basis(binding.BASIS_QUADRATIC)
+        g.set_basis(basis)
         return g
 
     if args.copy_probe:
@@ -340,8 +341,9 @@ def main():
         log(f"fel: {line['fel']}")
         line["fel_rk4"] = bench_fel(binding, args.fel_steps, integrator=1)
         log(f"fel_rk4: {line['fel_rk4']}")
-        line["quadratic"] = bench_quadratic(binding, args.n, args.quadratic_steps, args.warmup)
-        log(f"quadratic: {line['quadratic']}")
+        for name in ("quadratic", "cubic"):
+            line[name] = bench_spline(binding, name, args.n, args.spline_steps, args.warmup)
+            log(f"{name}: {line[name]}")
         line["batched"] = bench_batched(binding, args.batch_steps, args.batch_count)
         log(f"batched: {line['batched']}")
         line["served"] = bench_served(binding, args.serve_requests, args.serve_load,
