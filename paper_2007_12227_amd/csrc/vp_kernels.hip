@@ -982,11 +982,15 @@ __global__ __launch_bounds__(kSolveThreads) __attribute__((amdgpu_waves_per_eu(2
 // k, column k - m).  On a line that starts at an open edge the factors of the
 // first rows are those of the truncated matrix; they reach their interior
 // limits (set by the poles of the band's symbol: -0.0431 and -0.4306 for the
-// quadratic, down to -0.5353 for the cubic) to FP32 precision within ~20
-// rows, and kEdgeQ rows are tabulated at compile time (FP64, rounded once).
+// quadratic, down to -0.5353 for the cubic) to FP32 precision within ~10 and
+// ~20 rows; band_edge_rows(BW) rows are tabulated at compile time (FP64,
+// rounded once), the fewest that reach the limits (every tabulated row of a
+// line costs a scalar select per factor).
 // The truncation at the far end of a line changes no factor, so the same
 // table serves lines that end at an edge.
 // ---------------------------------------------------------------------------
+constexpr int band_edge_rows(int bw) { return bw == 2 ? 16 : kEdgeQ; }
+
 template <int BW>
 struct BandLdl {
     float l[BW + 1][kEdgeQ + 1];  // l[m][k], m = 1 .. BW; row kEdgeQ: the interior limits
@@ -1012,7 +1016,7 @@ constexpr BandLdl<BW> band_ldl_table(const double (&c)[BW + 1], double scale) {
     }
     BandLdl<BW> T{};
     for (int k = 0; k <= kEdgeQ; ++k) {
-        const int r = k < kEdgeQ ? k : K - 1;
+        const int r = k < band_edge_rows(BW) ? k : K - 1;
         for (int m = 1; m <= BW; ++m) T.l[m][k] = (float)l[r][m];
         T.dinv[k] = (float)(scale / d[r]);
     }
@@ -1044,8 +1048,9 @@ struct BandTable<3> {
 template <int BW>
 __device__ inline void band_line(float (&v)[kLineQ], bool edge) {
     constexpr const BandLdl<BW>& T = BandTable<BW>::T;
-    auto lm = [&](int m, int k) { return k < kEdgeQ && edge ? T.l[m][k] : T.l[m][kEdgeQ]; };
-    auto dinv = [&](int k) { return k < kEdgeQ && edge ? T.dinv[k] : T.dinv[kEdgeQ]; };
+    constexpr int E = band_edge_rows(BW);
+    auto lm = [&](int m, int k) { return k < E && edge ? T.l[m][k] : T.l[m][kEdgeQ]; };
+    auto dinv = [&](int k) { return k < E && edge ? T.dinv[k] : T.dinv[kEdgeQ]; };
     // forward: z_k = v_k - sum_m l_m(k) z_{k-m};  v_k <- z_k / d_k
     float z[BW + 1] = {};  // z[m]: z_{k-m}
 #pragma unroll
@@ -1078,14 +1083,14 @@ __device__ inline void band_line(float (&v)[kLineQ], bool edge) {
 template <int S, int BW>
 __device__ inline void band_line_lds(float* v, int n, bool edge) {
     constexpr const BandLdl<BW>& T = BandTable<BW>::T;
-    constexpr int U = 8;
-    static_assert(kEdgeQ % U == 0, "a group of rows is wholly inside or outside the table");
+    constexpr int U = 8, E = band_edge_rows(BW);
+    static_assert(E % U == 0, "a group of rows is wholly inside or outside the table");
     float z[BW + 1] = {};
     for (int k0 = 0; k0 < n; k0 += U) {
         float r[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) r[u] = k0 + u < n ? v[(k0 + u) * S] : 0.0f;
-        const bool tab = edge && k0 < kEdgeQ;
+        const bool tab = edge && k0 < E;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = tab ? k0 + u : kEdgeQ;
@@ -1111,7 +1116,7 @@ __device__ inline void band_line_lds(float* v, int n, bool edge) {
             const int k = k1 - u;
             float acc = r[u];
 #pragma unroll
-            for (int m = BW; m >= 1; --m) acc = fmaf(-T.l[m][edge && k + m < kEdgeQ ? k + m : kEdgeQ], y[m], acc);
+            for (int m = BW; m >= 1; --m) acc = fmaf(-T.l[m][edge && k + m < E ? k + m : kEdgeQ], y[m], acc);
 #pragma unroll
             for (int m = BW; m >= 2; --m) y[m] = y[m - 1];
             y[1] = acc;
