@@ -260,8 +260,9 @@ int validate_tiles(int basis, const vp_tiles& t) {
 // tiles rescan fewer halo sources and keep more waves per compute unit.
 vp_tiles default_tiles(int nx, int np, int basis = kBasisTent) {
     const double nodes = (double)nx * np;
-    // (the cubic basis's 8-cell border leaves a 128 x 128 tile without room)
-    if (nodes >= 256.0 * 128 * 128) return basis == kBasisCubic ? vp_tiles{128, 112, 1024} : vp_tiles{128, 128, 1024};
+    // (the cubic basis's 8-cell border leaves a 128 x 128 tile without room;
+    // 128 x 64 is the timed best for it at 2048^2)
+    if (nodes >= 256.0 * 128 * 128) return basis == kBasisCubic ? vp_tiles{128, 64, 1024} : vp_tiles{128, 128, 1024};
     if (nodes >= 256.0 * 128 * 64) return vp_tiles{128, 64, 512};
     return vp_tiles{64, 32, 256};
 }
