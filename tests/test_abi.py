@@ -71,7 +71,7 @@ def test_status_strings(L):
 
 def _check_box(x, p, ham, dt, kick, tile, box, wide=0):
     """A moved tent at cell position u touches columns floor(u)-1 .. floor(u)+2;
-    a quadratic basis function (wide=1) floor(u)-2 .. floor(u)+3."""
+    a B-spline basis function of degree wide + 1, floor(u)-1-wide .. floor(u)+2+wide."""
     du, dv = oracle.push(x, p, ham, dt, None if kick is None else np.array([kick.real, kick.imag]))
     bx0, bx1, by0, by1 = tile
     x0, x1, y0, y1 = box
@@ -90,7 +90,7 @@ def _check_box(x, p, ham, dt, kick, tile, box, wide=0):
         assert np.all((jj >= y0) & (jj < y1)), (tile, box, jj.min(), jj.max())
 
 
-@pytest.mark.parametrize("basis", [B.BASIS_TENT, B.BASIS_QUADRATIC])
+@pytest.mark.parametrize("basis", [B.BASIS_TENT, B.BASIS_QUADRATIC, B.BASIS_CUBIC])
 @pytest.mark.parametrize("seed", range(6))
 def test_source_box_contains_every_reaching_node(seed, basis):
     g = rng(100 + seed)
