@@ -1024,16 +1024,15 @@ constexpr BandLdl<BW> band_ldl_table(const double (&c)[BW + 1], double scale) {
 }
 constexpr double kBandQuad[3] = {66.0, 26.0, 1.0};
 constexpr double kBandCubic[4] = {2416.0, 1191.0, 120.0, 1.0};
+// namespace-scope constants, so that unrolled code folds every factor into an
+// instruction operand
+constexpr BandLdl<2> kBandLdl2 = band_ldl_table<2>(kBandQuad, 120.0);
+constexpr BandLdl<3> kBandLdl3 = band_ldl_table<3>(kBandCubic, 5040.0);
 template <int BW>
-struct BandTable;
-template <>
-struct BandTable<2> {
-    static constexpr BandLdl<2> T = band_ldl_table<2>(kBandQuad, 120.0);
-};
-template <>
-struct BandTable<3> {
-    static constexpr BandLdl<3> T = band_ldl_table<3>(kBandCubic, 5040.0);
-};
+__host__ __device__ constexpr const BandLdl<BW>& band_table() {
+    if constexpr (BW == 2) return kBandLdl2;
+    else return kBandLdl3;
+}
 
 // Solve M y = v in place along one whole window line (kLineQ elements) held
 // in registers (every index is a constant: the interior factors are
@@ -1047,7 +1046,7 @@ struct BandTable<3> {
 // multiply-add of the step before.
 template <int BW>
 __device__ inline void band_line(float (&v)[kLineQ], bool edge) {
-    constexpr const BandLdl<BW>& T = BandTable<BW>::T;
+    constexpr const BandLdl<BW>& T = band_table<BW>();
     constexpr int E = band_edge_rows(BW);
     auto lm = [&](int m, int k) { return k < E && edge ? T.l[m][k] : T.l[m][kEdgeQ]; };
     auto dinv = [&](int k) { return k < E && edge ? T.dinv[k] : T.dinv[kEdgeQ]; };
@@ -1082,7 +1081,7 @@ __device__ inline void band_line(float (&v)[kLineQ], bool edge) {
 // going through registers U at a time.
 template <int S, int BW>
 __device__ inline void band_line_lds(float* v, int n, bool edge) {
-    constexpr const BandLdl<BW>& T = BandTable<BW>::T;
+    constexpr const BandLdl<BW>& T = band_table<BW>();
     constexpr int U = 8, E = band_edge_rows(BW);
     static_assert(E % U == 0, "a group of rows is wholly inside or outside the table");
     float z[BW + 1] = {};
@@ -1262,9 +1261,21 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_spline(LaunchArgs A) {
         for (int k = 0; k < kLineQ; ++k, off += row_bytes)
             v[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
         band_line<BW>(v, T.ps == 0);
-        // window row k -> LDS row 1 + (k - op), clamped to the trash rows
+        // window row k -> LDS row 1 + (k - op).  Interior tiles (op = the
+        // halo) and tiles at the first edge (op = 0) write their kept rows at
+        // constant offsets; the others clamp the rows outside to the trash rows
+        const int op = __builtin_amdgcn_readfirstlane(T.op);
+        float* colp = win + kPitchQ + tid;
+        if (op == T.kHalo) {
 #pragma unroll
-        for (int k = 0; k < kLineQ; ++k) win[(min(max(k - T.op, -1), kSeg) + 1) * kPitchQ + tid] = v[k];
+            for (int k = 0; k < kSeg; ++k) colp[k * kPitchQ] = v[T.kHalo + k];
+        } else if (op == 0) {
+#pragma unroll
+            for (int k = 0; k < kSeg; ++k) colp[k * kPitchQ] = v[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < kLineQ; ++k) colp[min(max(k - op, -1), kSeg) * kPitchQ] = v[k];
+        }
     }
     __syncthreads();
     if (tid < T.kp) {
