@@ -318,7 +318,8 @@ struct RkConsts {
 
 // Push one node (source row j, unwrapped column ii, weight w already scaled to
 // fixed point) and add its TAPS x TAPS B-spline taps into the LDS tile: 4 x 4
-// cubic taps for tents, 6 x 6 quintic taps for quadratic basis functions.
+// cubic taps for tents, 6 x 6 quintic or 8 x 8 septic taps for quadratic or
+// cubic basis functions.
 template <int PUSH, int TAPS>
 __device__ inline void deposit_node(long long* acc, int j, int ii, float w, float4 tx, float4 tp,
                                     float alpha, float beta, float kd, const RkConsts& rk, int X0, int Y0,
