@@ -464,3 +464,136 @@ def test_moments_mass_and_energy_are_integrals_of_the_expansion(kind):
     assert m["mass"] == pytest.approx(mass, rel=1e-12)
     assert m["energy"] == pytest.approx(energy, rel=1e-10)
     assert m["neg_mass"] == pytest.approx(-x.h * p.h * w[w < 0].sum(), rel=1e-14)
+
+
+# ---- diagnostics the quadrature pin above does not reach: entropy, <p>, bunching ----
+# (Sec. Numerical Examples reports the entropy and the sum of the weights; the
+# entropy is read as S = -h_x h_p sum_{w>0} w ln w, the FEL bunching of
+# eq. 13c as N0^{-1} sum_j w_j e^{-i psi_j})
+
+def _diag_axes():
+    return Axis(-math.pi, math.pi, 16, True), Axis(-3.0, 3.0, 13, False)
+
+
+def test_entropy_of_a_uniform_density_is_minus_mass_log_value():
+    """Closed form: every nodal value c gives S = -M ln c, M the mass (the
+    quadrature pin fixes M = h_x h_p sum w), for c below and above 1."""
+    x, p = _diag_axes()
+    for c in (0.3, 1.0, 2.5):
+        w = np.full((p.n, x.n), c)
+        m = oracle.moments(x, p, Hamiltonian(H_PENDULUM, a=1.0), w)
+        assert m["entropy"] == pytest.approx(-x.h * p.h * w.size * c * math.log(c), rel=1e-13, abs=1e-14)
+        assert m["entropy"] == pytest.approx(-m["mass"] * math.log(c), rel=1e-13, abs=1e-14)
+
+
+def test_entropy_scaling_identity():
+    """S(lam w) = lam S(w) - lam ln(lam) M+, M+ = h_x h_p sum_{w>0} w, for
+    lam > 0: it fixes the w ln w form, its sign and the cell factor."""
+    x, p = _diag_axes()
+    w = rng(31).uniform(-0.2, 1.5, (p.n, x.n))
+    ham = Hamiltonian(H_PENDULUM, a=1.0)
+    m1 = oracle.moments(x, p, ham, w)
+    m_pos = m1["mass"] + m1["neg_mass"]   # mass of the positive nodes
+    for lam in (0.25, 3.0, 40.0):
+        ml = oracle.moments(x, p, ham, lam * w)
+        assert ml["entropy"] == pytest.approx(lam * m1["entropy"] - lam * math.log(lam) * m_pos, rel=1e-12)
+
+
+def test_entropy_ignores_negative_weights_and_is_permutation_invariant():
+    """Negative weights do not enter S (the reading of the entropy for a
+    signed expansion), and a lattice-aligned step (a permutation of the
+    weights: a quarter turn of the oscillator, pin P4) leaves S unchanged."""
+    n, h = 16, 0.25
+    half = 0.5 * (n - 1) * h
+    x = Axis(-half, half, n, False)
+    p = Axis(-half, half, n, False)
+    ham = Hamiltonian(H_SHO_EXACT, omega=1.0)
+    w = rng(32).uniform(-0.5, 1.5, (n, n))
+    wp = np.where(w > 0, w, 0.0)
+    assert oracle.moments(x, p, ham, w)["entropy"] == pytest.approx(
+        oracle.moments(x, p, ham, wp)["entropy"], rel=1e-14)
+    turned = oracle.run(x, p, ham, w, math.pi / 2, 1).w
+    np.testing.assert_allclose(turned, np.rot90(w), atol=1e-12, rtol=0)
+    assert oracle.moments(x, p, ham, turned)["entropy"] == pytest.approx(
+        oracle.moments(x, p, ham, w)["entropy"], rel=1e-11)
+
+
+def test_mean_p_of_a_single_row_and_of_a_symmetric_density():
+    """<p> of weights on one lattice row j is p_j exactly; a density
+    symmetric about row j0 has <p> = p_j0; a sum of two rows is their
+    weight-averaged momentum."""
+    x, p = _diag_axes()
+    ham = Hamiltonian(H_PENDULUM, a=1.0)
+    pj = p.nodes()
+    g = rng(33)
+    for j in (0, 4, 12):
+        w = np.zeros((p.n, x.n))
+        w[j] = g.uniform(0.1, 1.0, x.n)
+        assert oracle.moments(x, p, ham, w)["mean_p"] == pytest.approx(pj[j], abs=1e-14)
+    j0 = 6
+    prof = g.uniform(0.1, 1.0, x.n)
+    w = np.zeros((p.n, x.n))
+    for d, amp in ((0, 1.0), (1, 0.6), (2, 0.3), (3, 0.05)):
+        w[j0 - d] += amp * prof
+        if d:
+            w[j0 + d] += amp * prof
+    assert oracle.moments(x, p, ham, w)["mean_p"] == pytest.approx(pj[j0], abs=1e-14)
+    w = np.zeros((p.n, x.n))
+    w[2], w[9] = 1.0, 3.0
+    assert oracle.moments(x, p, ham, w)["mean_p"] == pytest.approx((pj[2] + 3 * pj[9]) / 4, abs=1e-14)
+    # signed weights: <p> is normalised by the signed sum (the mass), not by the L1 norm
+    w[9] = -0.5
+    assert oracle.moments(x, p, ham, w)["mean_p"] == pytest.approx((pj[2] - 0.5 * pj[9]) / 0.5, abs=1e-13)
+
+
+def test_lattice_bunching_of_a_modulated_beam_is_half_the_modulation():
+    """w = g(eta) (1 + eps cos psi) on a full periodic phase lattice has
+    bunching N0^{-1} sum w e^{-i psi} = eps/2 exactly (sum cos^2 = N/2, sum
+    cos = sum e^{-i psi} = 0); with sin psi it is -i eps/2, which fixes the
+    sign of the phase factor.  The invariant |A|^2 + N0^{-1} sum w eta of a
+    beam on one energy row is |A|^2 + eta_j (sum w)/N0."""
+    x = Axis(0.0, 2 * math.pi, 32, True)
+    p = Axis(-0.5, 0.5, 21, False)
+    ham = Hamiltonian(H_FEL)
+    psi, eta = x.nodes(), p.nodes()
+    gpro = np.exp(-eta**2 / (2 * 0.1**2))
+    for eps in (0.01, 0.3):
+        w = gpro[:, None] * (1 + eps * np.cos(psi))[None, :]
+        m = oracle.moments(x, p, ham, w, A=0.2 - 0.1j, N0=w.sum())
+        assert m["bunch_re"] == pytest.approx(eps / 2, abs=1e-15)
+        assert abs(m["bunch_im"]) < 1e-15
+        # N0 is the initial weight sum, not the current one: half the beam left
+        m = oracle.moments(x, p, ham, w, N0=2.0 * w.sum())
+        assert m["bunch_re"] == pytest.approx(eps / 4, abs=1e-15)
+        w = gpro[:, None] * (1 + eps * np.sin(psi))[None, :]
+        m = oracle.moments(x, p, ham, w, N0=w.sum())
+        assert abs(m["bunch_re"]) < 1e-15
+        assert m["bunch_im"] == pytest.approx(-eps / 2, abs=1e-15)
+    w = np.zeros((p.n, x.n))
+    w[15] = 2.0
+    N0 = 3.0 * w.sum()
+    m = oracle.moments(x, p, ham, w, A=0.3 + 0.4j, N0=N0)
+    assert m["fel_invariant"] == pytest.approx(0.25 + eta[15] / 3.0, abs=1e-15)
+    assert (m["A_re"], m["A_im"]) == (0.3, 0.4)
+
+
+@pytest.mark.parametrize("degree", [2, 3])
+def test_spline_oracle_entropy_and_mean_p_closed_forms(degree):
+    """The spline-basis oracle's entropy and <p> follow the same closed forms
+    (uniform density, scaling identity, single and signed rows)."""
+    from oracle import spline_basis
+    x, p = _diag_axes()
+    ham = Hamiltonian(H_PENDULUM, a=1.0)
+    w = np.full((p.n, x.n), 2.5)
+    m = spline_basis.moments(x, p, ham, w, degree)
+    assert m["entropy"] == pytest.approx(-m["mass"] * math.log(2.5), rel=1e-13)
+    w = rng(34).uniform(-0.2, 1.5, (p.n, x.n))
+    m1 = spline_basis.moments(x, p, ham, w, degree)
+    ml = spline_basis.moments(x, p, ham, 3.0 * w, degree)
+    assert ml["entropy"] == pytest.approx(3.0 * m1["entropy"] - 3.0 * math.log(3.0) * (m1["mass"] + m1["neg_mass"]),
+                                          rel=1e-12)
+    pj = p.nodes()
+    w = np.zeros((p.n, x.n))
+    w[2], w[9] = 1.0, -0.5
+    assert spline_basis.moments(x, p, ham, w, degree)["mean_p"] == pytest.approx((pj[2] - 0.5 * pj[9]) / 0.5,
+                                                                                 abs=1e-13)
