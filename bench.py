@@ -31,9 +31,19 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def timed_steps(g, dt, steps, warmup):
+def timed_steps(g, dt, steps, warmup, restore=None):
+    """Time exactly `steps` steps replayed as the library runs them.  Before the
+    timed region: `warmup` steps, then the same `steps` once more (rounded up to
+    an even count, so the timed run starts at the same step parity) to build
+    every HIP graph the timed run replays; `restore` (optional) then resets
+    the state, and a zero-step call plans the step (tables, the FEL's first
+    bunching) outside the timed region."""
     import torch
     g.step(dt, warmup)
+    g.step(dt, steps + (steps & 1))
+    if restore is not None:
+        restore()
+    g.step(dt, 0)
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -56,7 +66,12 @@ def bench_fel(binding, steps, integrator=0):
     inst = dataclasses.replace(inst, ham=dataclasses.replace(inst.ham, integrator=integrator))
     g = binding.grid_for(inst)
     g.autotune(inst.dt)
-    sec, _ = timed_steps(g, inst.dt, steps, 0)
+
+    def restore():  # the timed run starts from the initial state and field
+        g.set_hamiltonian(inst.ham)
+        g.set_density(inst.w0)
+
+    sec, _ = timed_steps(g, inst.dt, steps, 0, restore)
     m = g.moments()
     g.close()
     name = "fel_gaussian_1024" + ("_rk4" if integrator else "")
@@ -80,16 +95,17 @@ def bench_spline(binding, name, n, steps, warmup):
         g.set_density(inst.w0)
         if basis == spline:
             g.autotune(inst.dt)
-            sec, _ = timed_steps(g, inst.dt, steps, warmup)
+            sec, _ = timed_steps(g, inst.dt, steps, warmup, restore=lambda: g.set_density(inst.w0))
             out.update(value=inst.nodes * steps / sec, ms_per_step=1e3 * sec / steps, tiles=g.tiles()["k1"])
+            m = g.moments()  # after `steps` steps from the start, as the tent grid below
             kus = dict(zip(KERNELS, g.step_timed(inst.dt, min(steps, 200))))
             out["kernels_us"] = kus
             out["kernel_roofline_frac"] = {k: ALG_BYTES_PER_NODE * inst.nodes / (v * 1e-6) / 1e9 / HBM_PEAK_GBS
                                            for k, v in kus.items()}
         else:
             g.autotune(inst.dt, cached=True)
-            g.step(inst.dt, steps + warmup)
-        m = g.moments()
+            g.step(inst.dt, steps)
+            m = g.moments()
         g.close()
         out[tag + "neg_mass_fraction"] = m["neg_mass"] / m["mass"]
     # the FEL start with a hard energy edge (the case whose negative weights
@@ -121,7 +137,7 @@ def bench_batched(binding, steps, count):
     # the GPU by themselves, which a batch does not need
     grids = [binding.grid_for(i) for i in insts]
     batch = binding.Batch(grids, [i.dt for i in insts])
-    batch.step(2)
+    batch.step(steps + (steps & 1))  # builds the graphs the timed run replays
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     batch.step(steps)
@@ -182,6 +198,22 @@ def deposit_shape(tiles):
     return "x".join(str(v) for v in (*tiles["k1"], tiles["threads"]))
 
 
+def profiled_kernel_us(kernel, workload, shape):
+    """Average duration (us) of `kernel` in the committed rocprofv3 kernel-trace
+    summary of this workload, or None unless it was taken of the current kernel
+    sources at this deposit launch shape."""
+    path = os.path.join(PROFILES, f"step_kernels_{workload}_kernel_trace.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if f"kernel source sha256[:16]: {kernel_source_sha()}" not in text or f"shape (columns x rows x threads): {shape}" not in text:
+        return None
+    for line in text.splitlines():
+        if not line.startswith("#") and kernel in line.split("(")[0]:
+            return float(line.split()[-4])
+    return None
+
+
 def measured_traffic(kernel, workload, shape):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a copy of
@@ -234,7 +266,7 @@ def main():
     ap.add_argument("--fel-steps", type=int, default=2000)
     ap.add_argument("--spline-steps", type=int, default=1000,
                     help="steps of the quadratic and cubic basis lines")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-overload", type=float, default=1.2,
                     help="a second served run with arrivals above the batched capacity (0: skip)")
@@ -309,6 +341,7 @@ def main():
     alg_bytes = ALG_BYTES_PER_NODE * N  # per launch of either step kernel
     achieved = alg_bytes / (kus[dom] * 1e-6) / 1e9
     traffic = measured_traffic(dom, workload, deposit_shape(tiles))
+    prof_us = profiled_kernel_us(dom, workload, deposit_shape(tiles))
 
     line = {
         "metric": METRIC,
@@ -331,7 +364,9 @@ def main():
         "kernels_us": kus,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": alg_bytes},
+                     "alg_bytes_per_launch": alg_bytes, "kernel_us_events": kus[dom],
+                     "kernel_us_rocprof": prof_us,
+                     "frac_rocprof": None if prof_us is None else alg_bytes / (prof_us * 1e-6) / 1e9 / HBM_PEAK_GBS},
         "kernel_roofline_frac": {k: alg_bytes / (v * 1e-6) / 1e9 / HBM_PEAK_GBS for k, v in kus.items()},
         "step_roofline_frac": alg_bytes / (sec / args.steps) / 1e9 / HBM_PEAK_GBS,
         "final_sum_w": m["sum_w"],

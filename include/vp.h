@@ -146,25 +146,50 @@ typedef struct {
     int32_t k1_threads;
 } vp_tiles;
 
-/* Bytes of device workspace a grid of this shape needs (0 if the axes are invalid). */
+/* Bytes of device workspace a grid of this shape needs (0 if the axes are
+ * invalid): three FP32 arrays of n_p*n_x weights (the state, ping-pong, and
+ * the projection's right-hand side Delta^T w of eq. 10) plus per-axis push
+ * tables and small per-tile buffers. */
 size_t vp_workspace_bytes(const vp_axis* x, const vp_axis* p);
 
-/* Create a grid on the caller's workspace.  Fails with VP_EINVAL for invalid
- * axes, VP_ENOMEM for a missing or small workspace, VP_EUNSUPPORTED for a
- * periodic p axis. */
+/* Create a grid: the fixed lattice of nodes z_j of the expansion (eq. 4) with
+ * a periodic coordinate and an open momentum axis (Sec. "Numerical Examples":
+ * coordinates periodic, momenta open).  desc->workspace is caller-owned device
+ * memory (see vp_grid_desc); *out receives the handle.  Fails with VP_EINVAL
+ * for invalid axes, VP_ENOMEM for a missing or small workspace,
+ * VP_EUNSUPPORTED for a periodic p axis, VP_EHIP if the runtime fails. */
 int vp_create_grid(const vp_grid_desc* desc, vp_grid** out);
 
-/* Destroy a grid (NULL is allowed).  Waits for the grid's stream. */
+/* Destroy a grid (NULL is allowed).  Waits for the grid's stream; the
+ * workspace stays the caller's.  VP_ESTATE while the grid belongs to a batch. */
 int vp_destroy_grid(vp_grid* g);
 
-/* Set the Hamiltonian (kind and parameters; for the FEL also the current field). */
+/* Set the Hamiltonian whose flow moves the nodes (Sec. "The Vlasov Equation as
+ * Flows on Phase Space": any particle pusher; the examples of Sec. "Harmonic
+ * Oscillators" and the FEL of eqs. 13a-c; kinds and pushers as listed at
+ * vp_hamiltonian).  For the FEL, A_re and A_im set the current field.
+ * VP_EINVAL for an unknown kind or integrator or a non-finite parameter,
+ * VP_EUNSUPPORTED for the exact rotation on a periodic x axis. */
 int vp_set_hamiltonian(vp_grid* g, const vp_hamiltonian* h);
 
-/* Set the weights w (n_p*n_x floats; device pointer if on_device, else host).
- * Records N0 = sum w (FP64) and max|w| (the deposit's fixed-point scale),
- * clears the range flag and resets the step counter.  VP_ENONFINITE if a
- * weight is NaN or infinite (the grid then holds no density). */
+/* Set the weights w_j of the expansion f = sum_j w_j Lambda_j (eq. 4): n_p*n_x
+ * floats, [n_p][n_x], x fastest; a device pointer if on_device, else host
+ * memory (copied before the call returns).  Records N0 = sum w (FP64, the FEL
+ * normalisation of eq. 13c) and max|w| (the deposit's fixed-point exponent
+ * e, max|w0| < 2^e), clears the range flag and resets the step counter.
+ * VP_ENONFINITE if a weight is NaN or infinite (the grid then holds no
+ * density). */
 int vp_set_density(vp_grid* g, const float* w, int32_t on_device);
+
+/* Exponent e of the deposit's fixed-point cell sums (the tile sums of
+ * Delta^T w, eq. 9): taps are rounded to the grid 2^(e-40) and summed exactly
+ * while a cell stays below 2^(e+7) in magnitude; beyond 2^(e+6) the range flag
+ * is set.  vp_set_density picks the smallest e with max|w0| < 2^e; a caller
+ * that expects the weights to grow can raise it (each unit halves the
+ * resolution).  Takes effect from the next step; vp_set_density resets it.
+ * VP_EINVAL for e outside [-86, 127], VP_ESTATE before a density is set or
+ * while the grid belongs to a batch. */
+int vp_set_fixed_point(vp_grid* g, int32_t e);
 
 /* Choose the basis functions (VP_BASIS_TENT, VP_BASIS_QUADRATIC or
  * VP_BASIS_CUBIC; VP_EINVAL otherwise).  The weights are read as coefficients of the chosen basis from
@@ -175,15 +200,28 @@ int vp_set_density(vp_grid* g, const float* w, int32_t on_device);
  * takes grids of one basis (VP_EUNSUPPORTED otherwise). */
 int vp_set_basis(vp_grid* g, int32_t basis);
 
-/* Copy the current weights out (n_p*n_x floats). */
+/* Copy the current weights w_j (eq. 4) out: n_p*n_x floats into w (device
+ * memory if on_device, else host); waits for the stream.  VP_ESTATE before a
+ * density is set; VP_ERANGE (after copying) if a deposit cell sum has left
+ * the fixed-point range since the density was set: the weights are then not
+ * valid. */
 int vp_get_density(vp_grid* g, float* w, int32_t on_device);
 
-/* Advance nsteps steps of size dt (dz for the FEL) on the grid's stream.
- * VP_ESTATE if no density or Hamiltonian has been set, or for the FEL if the
- * initial weights sum to zero (N0 normalises the bunching, eq. 13c). */
+/* Advance nsteps steps of size dt (dz for the FEL) on the grid's stream.  One
+ * step is the update w_fin = Lambda^{-1} Delta^T w_in of eq. 10: every node
+ * pushed by the Hamiltonian's integrator (eqs. 6-7), its basis function
+ * projected back onto the lattice (eqs. 8-9), the mass-matrix system solved.
+ * Returns once the work is enqueued.  VP_ESTATE if no density or Hamiltonian
+ * has been set, or for the FEL if the initial weights sum to zero (N0
+ * normalises the bunching, eq. 13c); VP_ERANGE, without stepping, once a
+ * completed earlier step has set the range flag (see vp_set_fixed_point;
+ * a step still in flight reports on a later call or in vp_moments /
+ * vp_get_density); VP_EINVAL for a negative count or non-finite dt. */
 int vp_step(vp_grid* g, double dt, int64_t nsteps);
 
-/* Diagnostics of the current state; waits for the stream. */
+/* Diagnostics of the current state (the list at vp_moments_t); waits for the
+ * stream.  Returns VP_ENONFINITE or VP_ERANGE after filling *out when the
+ * state holds NaN/Inf or the range flag is set. */
 int vp_moments(vp_grid* g, vp_moments_t* out);
 
 /* Deposit launch shape.  vp_set_tiles validates it (VP_EINVAL if the tile's
@@ -218,7 +256,11 @@ int vp_autotune(vp_grid* g, double dt, double* best_us);
  * stream (VP_EINVAL otherwise); the batch uses it.  The grids must outlive the
  * batch and must not be stepped on their own while it exists (VP_ESTATE). */
 int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch** out);
+/* nsteps steps of eq. 10 for every grid of the batch, enqueued on its stream.
+ * VP_ERANGE, without stepping, once a completed earlier batch step has set the
+ * range flag of any of its grids (vp_moments of each grid names which). */
 int vp_batch_step(vp_batch* b, int64_t nsteps);
+/* Release the batch (the grids stay; they can be stepped alone again). */
 int vp_batch_destroy(vp_batch* b);
 
 /* Status text and the calling thread's last error message. */

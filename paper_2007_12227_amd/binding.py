@@ -100,6 +100,7 @@ def lib(load_torch: bool = True):
     L.vp_plan_source_box.argtypes = [P(Axis), P(Axis), P(Hamiltonian), C.c_int32, C.c_double, C.c_double,
                                      C.c_double, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P(C.c_int32)]
     L.vp_set_basis.argtypes = [C.c_void_p, C.c_int32]
+    L.vp_set_fixed_point.argtypes = [C.c_void_p, C.c_int32]
     for name in declared_functions():
         if name not in ("vp_workspace_bytes", "vp_status_string", "vp_last_error"):
             getattr(L, name).restype = C.c_int
@@ -212,15 +213,23 @@ class Grid:
         check(lib().vp_step_timed(self._h, float(dt), int(n), us))
         return us[0], us[1]
 
-    def moments(self) -> dict:
+    def moments(self, check_state: bool = True) -> dict:
+        """FP64 diagnostics.  A state with NaN/Inf weights or a deposit that
+        left its fixed-point range raises VpError (VP_ENONFINITE, VP_ERANGE);
+        with check_state=False the moments are returned anyway, with the code
+        in d["status"]."""
         m = Moments()
         rc = lib().vp_moments(self._h, C.byref(m))
         d = {f: getattr(m, f) for f in MOMENT_FIELDS}
         d["step"], d["nonfinite"] = m.step, m.nonfinite
-        if rc not in (VP_OK, VP_ENONFINITE, VP_ERANGE):
+        if check_state or rc not in (VP_OK, VP_ENONFINITE, VP_ERANGE):
             check(rc)
         d["status"] = rc
         return d
+
+    def set_fixed_point(self, e: int):
+        """Exponent of the deposit's fixed-point cell sums (vp_set_fixed_point)."""
+        check(lib().vp_set_fixed_point(self._h, int(e)))
 
     def set_tiles(self, k1=(0, 0), threads: int = 0):
         """Deposit launch shape: tile (columns, rows) and threads per workgroup

@@ -126,14 +126,20 @@ struct LaunchList {
     size_t lds1 = 0;
     int threads1 = 256;  // deposit workgroup size
     hipStream_t stream = nullptr;
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    // graphs of r steps (r = 1 .. kGraphSteps), by the relative parity they start at
+    hipGraphExec_t exec[kGraphSteps + 1][2] = {};
+    // the launch's range word (device) and its host copy, refreshed after
+    // every run (pinned, read without waiting for the stream)
+    uint32_t* d_any = nullptr;
+    volatile uint32_t* h_any = nullptr;
 
     void drop_graphs() {
-        for (auto& e : exec)
-            if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
+        for (auto& row : exec)
+            for (auto& e : row)
+                if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
     }
     LaunchArgs args(const int32_t* off, int total, int parity, int mode = 0) const {
-        return LaunchArgs{d_inst, off, ninst, total, parity, mode};
+        return LaunchArgs{d_inst, off, ninst, total, parity, mode, d_any};
     }
     // the kernels of one step: {kernel, off, total (= grid), lds, threads, mode}
     struct K { const void* fn; const int32_t* off; int total; size_t lds; int threads; int mode; };
@@ -158,15 +164,15 @@ struct LaunchList {
         if (has_fel) HIP_TRY(launch_fel_field(args(d_off2, ninst, parity), stream));
         return VP_OK;
     }
-    int build_graph(int rel_parity) {
+    int build_graph(int rel_parity, int steps) {
         hipGraph_t graph;
         HIP_TRY(hipGraphCreate(&graph, 0));
         hipGraphNode_t prev = nullptr;
         std::vector<LaunchArgs> keep;
-        keep.reserve(5 * kGraphSteps);
+        keep.reserve(5 * steps);
         K ks[5];
         const int nk = kernels(ks);
-        for (int s = 0; s < kGraphSteps; ++s) {
+        for (int s = 0; s < steps; ++s) {
             for (int ki = 0; ki < nk; ++ki) {
                 const K& k = ks[ki];
                 keep.push_back(args(k.off, k.total, (rel_parity + s) & 1, k.mode));
@@ -187,28 +193,61 @@ struct LaunchList {
                 prev = node;
             }
         }
-        hipError_t e = hipGraphInstantiate(&exec[rel_parity], graph, nullptr, nullptr, 0);
+        hipError_t e = hipGraphInstantiate(&exec[steps][rel_parity], graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return fail(VP_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
         return VP_OK;
     }
+    // A deposit cell sum left the fixed-point range in a run whose copy of the
+    // range word has arrived (a run still in flight reports on a later call).
+    bool range_seen() const { return h_any && *h_any != 0u; }
+    // Copy the range word to the host behind the work just enqueued.
+    int post_range_copy() const {
+        if (h_any) HIP_TRY(hipMemcpyAsync((void*)h_any, d_any, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+        return VP_OK;
+    }
     // Run n steps starting at relative parity rp.
+    // With use_graph: whole graphs of kGraphSteps steps, then one graph of
+    // the remaining steps (the graphs of every length are built on first use
+    // and kept; 16 is even, so the remainder starts at parity rp too).
     int run(int64_t n, int rp, bool use_graph) {
         int64_t done = 0;
-        if (use_graph && n >= kGraphSteps) {
-            if (!exec[rp]) {
-                int rc = build_graph(rp);
-                if (rc) return rc;
+        if (use_graph) {
+            auto launch = [&](int steps) -> int {
+                if (!exec[steps][rp]) {
+                    int rc = build_graph(rp, steps);
+                    if (rc) return rc;
+                }
+                HIP_TRY(hipGraphLaunch(exec[steps][rp], stream));
+                return VP_OK;
+            };
+            for (; done + kGraphSteps <= n; done += kGraphSteps)
+                if (int rc = launch(kGraphSteps)) return rc;
+            if (done < n) {
+                if (int rc = launch((int)(n - done))) return rc;
+                done = n;
             }
-            for (; done + kGraphSteps <= n; done += kGraphSteps) HIP_TRY(hipGraphLaunch(exec[rp], stream));
         }
         for (; done < n; ++done) {
             int rc = enqueue_step((int)((rp + done) & 1));
             if (rc) return rc;
         }
-        return VP_OK;
+        return post_range_copy();
     }
 };
+
+// Small pinned host word for a launch list's range flag.
+int alloc_host_flag(volatile uint32_t** out) {
+    void* p = nullptr;
+    HIP_TRY(hipHostMalloc(&p, 64, hipHostMallocDefault));
+    *reinterpret_cast<uint32_t*>(p) = 0u;
+    *out = reinterpret_cast<volatile uint32_t*>(p);
+    return VP_OK;
+}
+void free_host_flag(volatile uint32_t** p) {
+    if (*p) (void)hipHostFree((void*)*p);
+    *p = nullptr;
+}
 
 }  // namespace
 
@@ -304,22 +343,24 @@ int upload_inst(vp_grid* g) {
     HIP_TRY(hipMemcpyAsync(g->list.d_inst, &I, sizeof(VpInst), hipMemcpyHostToDevice, g->stream));
     HIP_TRY(hipMemcpyAsync(g->list.d_off1, off, sizeof off, hipMemcpyHostToDevice, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
-    g->list.ninst = 1;
-    g->list.has_fel = I.push.kind == kFel;
-    g->list.has_rk4 = I.push.kind == kFel && I.push.rk4;
-    g->list.total1 = I.k1_tiles;
-    g->list.total2 = I.k2_tiles;
-    g->list.lds1 = deposit_lds_bytes(t.k1_tx, t.k1_ty, g->basis);
-    g->list.basis = g->basis;
-    g->list.solve = solve_kind(g->basis, g->x.n, g->p.n, g->x.periodic != 0);
-    g->list.threads1 = t.k1_threads;
-    g->list.drop_graphs();
+    // the graphs hold launch shapes and kernel choices, not the descriptor
+    // (it is read from device memory): keep them while those stay the same
+    LaunchList& L = g->list;
+    const auto shape = std::make_tuple(L.ninst, L.has_fel, L.has_rk4, L.total1, L.total2, L.lds1, L.basis, L.solve,
+                                       L.threads1);
+    L.ninst = 1;
+    L.has_fel = I.push.kind == kFel;
+    L.has_rk4 = I.push.kind == kFel && I.push.rk4;
+    L.total1 = I.k1_tiles;
+    L.total2 = I.k2_tiles;
+    L.lds1 = deposit_lds_bytes(t.k1_tx, t.k1_ty, g->basis);
+    L.basis = g->basis;
+    L.solve = solve_kind(g->basis, g->x.n, g->p.n, g->x.periodic != 0);
+    L.threads1 = t.k1_threads;
+    if (shape != std::make_tuple(L.ninst, L.has_fel, L.has_rk4, L.total1, L.total2, L.lds1, L.basis, L.solve,
+                                 L.threads1))
+        L.drop_graphs();
     return VP_OK;
-}
-
-void split(double v, float& hi, float& lo) {
-    hi = (float)v;
-    lo = (float)(v - (double)hi);
 }
 
 // Push parameters in cell units for step dt (FEL: the kick amplitudes alpha,
@@ -359,48 +400,31 @@ PushParams push_params(const vp_axis& x, const vp_axis& p, const vp_hamiltonian&
     return P;
 }
 
+TableParams table_params(const vp_axis& x, const vp_axis& p, const vp_hamiltonian& H, double dt) {
+    TableParams T{};
+    T.kind = H.kind;
+    T.x_lo = x.lo;
+    T.hx = spacing(x);
+    T.p_lo = p.lo;
+    T.hp = spacing(p);
+    T.dt = dt;
+    T.delta = H.kind == VP_H_FEL ? H.fel_delta : 0.0;
+    T.omega = H.omega;
+    return T;
+}
+
 // Per-step tables of the push for step dt (FP64 on the host, stored FP32),
 // and the FP64 phase tables of the FEL bunching.
 int plan(vp_grid* g, double dt) {
     const int nx = g->x.n, np = g->p.n;
-    const double hx = spacing(g->x), hp = spacing(g->p);
+    const double hp = spacing(g->p);
     const vp_hamiltonian& H = g->ham;
     std::vector<float4> tx(nx), tp(np);
     std::vector<double2> ex(nx), eq(np);
     g->inst.push = push_params(g->x, g->p, H, dt, g->basis);
-    const double delta = H.kind == VP_H_FEL ? H.fel_delta : 0.0;
-    if (H.kind == VP_H_SHO_EXACT) {
-        const double th = H.omega * dt, c = cos(th), s = sin(th), cm1 = -2.0 * sin(0.5 * th) * sin(0.5 * th);
-        for (int i = 0; i < nx; ++i) {
-            double x = g->x.lo + i * hx;
-            float a, b, c2, d;
-            split(x * cm1 / hx, a, b);
-            split(-x * s / hp, c2, d);
-            tx[i] = make_float4(a, b, c2, d);
-        }
-        for (int j = 0; j < np; ++j) {
-            double p = g->p.lo + j * hp;
-            float a, b, c2, d;
-            split(p * s / hx, a, b);
-            split(p * cm1 / hp, c2, d);
-            tp[j] = make_float4(a, b, c2, d);
-        }
-        (void)c;
-    } else {
-        for (int i = 0; i < nx; ++i) {
-            double x = g->x.lo + i * hx;
-            tx[i] = make_float4((float)sin(x), (float)cos(x), 0.f, 0.f);
-            ex[i] = make_double2(cos(x), sin(x));
-        }
-        for (int j = 0; j < np; ++j) {
-            double v = delta + g->p.lo + j * hp;  // drift velocity of row j
-            double q = 0.5 * dt * v;
-            float a, b;
-            split(v * dt / hx, a, b);
-            tp[j] = make_float4(a, b, (float)sin(q), (float)cos(q));
-            eq[j] = make_double2(cos(q), sin(q));
-        }
-    }
+    const TableParams T = table_params(g->x, g->p, H, dt);
+    for (int i = 0; i < nx; ++i) table_x(T, i, tx[i], ex[i]);
+    for (int j = 0; j < np; ++j) table_p(T, j, tp[j], eq[j]);
     VpInst& I = g->inst;
     I.fel_kick = -2.0 * dt / hp;
     I.fel_sigma2 = (float)H.fel_sigma2;
@@ -502,6 +526,11 @@ int vp_create_grid(const vp_grid_desc* d, vp_grid** out) {
     g->list.d_inst = g->at<VpInst>(L.inst);
     g->list.d_off1 = g->at<int32_t>(L.off);
     g->list.d_off2 = g->at<int32_t>(L.off) + 2;
+    g->list.d_any = g->at<uint32_t>(L.counters) + kRangeFlag;
+    if (alloc_host_flag(&g->list.h_any) != VP_OK) {
+        delete g;
+        return VP_EHIP;
+    }
     VpInst& I = g->inst;
     I.w[0] = g->at<float>(L.w0);
     I.w[1] = g->at<float>(L.w1);
@@ -519,6 +548,7 @@ int vp_create_grid(const vp_grid_desc* d, vp_grid** out) {
     if (e == hipSuccess) e = hipMemsetAsync(g->at<uint32_t>(L.counters), 0, 4 * sizeof(uint32_t), g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) {
+        free_host_flag(&g->list.h_any);
         delete g;
         return fail(VP_EHIP, "grid initialisation: %s", hipGetErrorString(e));
     }
@@ -531,6 +561,7 @@ int vp_destroy_grid(vp_grid* g) {
     if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
     (void)hipStreamSynchronize(g->stream);
     g->list.drop_graphs();
+    free_host_flag(&g->list.h_any);
     delete g;
     return VP_OK;
 }
@@ -564,7 +595,7 @@ int vp_set_density(vp_grid* g, const float* w, int32_t on_device) {
     const size_t bytes = (size_t)g->x.n * g->p.n * sizeof(float);
     float* dst = g->at<float>(g->parity ? g->L.w1 : g->L.w0);
     HIP_TRY(hipMemcpyAsync(dst, w, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, g->stream));
-    int rc = launch_reduce_on(g, 0, 0.0);
+    int rc = launch_reduce_on(g, 2, 0.0);
     if (rc) return rc;
     double m[kMoments];
     HIP_TRY(hipMemcpyAsync(m, g->at<double>(g->L.moments), sizeof m, hipMemcpyDeviceToHost, g->stream));
@@ -590,6 +621,7 @@ int vp_set_density(vp_grid* g, const float* w, int32_t on_device) {
     HIP_TRY(hipMemcpyAsync(g->at<double>(g->L.fel_state) + kN0, &g->N0, sizeof(double), hipMemcpyHostToDevice, g->stream));
     HIP_TRY(hipMemsetAsync(g->at<uint32_t>(g->L.counters) + kRangeFlag, 0, sizeof(uint32_t), g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
+    *g->list.h_any = 0u;  // every copy of the old word has arrived
     g->has_density = true;
     g->bunch_valid = false;
     g->step = 0;
@@ -602,7 +634,11 @@ int vp_get_density(vp_grid* g, float* w, int32_t on_device) {
     const size_t bytes = (size_t)g->x.n * g->p.n * sizeof(float);
     HIP_TRY(hipMemcpyAsync(w, g->at<float>(g->parity ? g->L.w1 : g->L.w0), bytes,
                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, g->stream));
+    int rc = g->list.post_range_copy();
+    if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(g->stream));
+    if (g->list.range_seen())
+        return fail(VP_ERANGE, "a deposit cell sum exceeded 2^6 x 2^e (fixed-point range): the weights are not valid");
     return VP_OK;
 }
 
@@ -610,6 +646,8 @@ int vp_step(vp_grid* g, double dt, int64_t nsteps) {
     if (!g) return fail(VP_EINVAL, "null grid");
     if (nsteps < 0) return fail(VP_EINVAL, "negative step count");
     if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
+    if (g->list.range_seen())
+        return fail(VP_ERANGE, "an earlier step left the deposit's fixed-point range; set a density again");
     int rc = prepare(g, dt);
     if (rc) return rc;
     if (nsteps == 0) return VP_OK;
@@ -626,31 +664,37 @@ int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]) {
     if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
     int rc = prepare(g, dt);
     if (rc) return rc;
-    Events ev((size_t)(3 * nsteps));
+    // per step: start and end of the deposit phase (for the Runge-Kutta FEL
+    // from the stage sums before the deposit), start and end of the solve
+    // phase (for the FEL up to the field update after it), each recorded with
+    // the kernel's own dispatch
+    Events ev((size_t)(4 * nsteps));
     HIP_TRY(ev.create());
     const LaunchList& L = g->list;
     for (int64_t s = 0; s < nsteps; ++s) {
         const int par = (int)((g->parity + s) & 1);
-        HIP_TRY(hipEventRecord(ev[3 * s], g->stream));
+        hipEvent_t* e = &ev[4 * s];
         if (L.has_rk4) {
-            HIP_TRY(launch_fel_stage(L.args(L.d_off2, L.total2, par), L.total2, g->stream));
+            HIP_TRY(launch_fel_stage(L.args(L.d_off2, L.total2, par), L.total2, g->stream, e[0], nullptr));
             HIP_TRY(launch_fel_field(L.args(L.d_off2, L.ninst, par, 1), g->stream));
         }
-        HIP_TRY(launch_deposit(L.args(L.d_off1, L.total1, par), L.total1, L.lds1, L.threads1, g->stream, L.basis));
-        HIP_TRY(hipEventRecord(ev[3 * s + 1], g->stream));
-        HIP_TRY(launch_solve(L.args(L.d_off2, L.total2, par), L.total2, g->stream, L.solve));
-        if (L.has_fel) HIP_TRY(launch_fel_field(L.args(L.d_off2, L.ninst, par), g->stream));
-        HIP_TRY(hipEventRecord(ev[3 * s + 2], g->stream));
+        HIP_TRY(launch_deposit(L.args(L.d_off1, L.total1, par), L.total1, L.lds1, L.threads1, g->stream, L.basis,
+                               L.has_rk4 ? nullptr : e[0], e[1]));
+        HIP_TRY(launch_solve(L.args(L.d_off2, L.total2, par), L.total2, g->stream, L.solve, e[2],
+                             L.has_fel ? nullptr : e[3]));
+        if (L.has_fel) HIP_TRY(launch_fel_field(L.args(L.d_off2, L.ninst, par), g->stream, nullptr, e[3]));
     }
-    HIP_TRY(hipEventSynchronize(ev[3 * nsteps - 1]));
+    HIP_TRY(hipEventSynchronize(ev[4 * nsteps - 1]));
     double t[2] = {0.0, 0.0};
     for (int64_t s = 0; s < nsteps; ++s)
         for (int k = 0; k < 2; ++k) {
             float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, ev[3 * s + k], ev[3 * s + k + 1]));
+            HIP_TRY(hipEventElapsedTime(&ms, ev[4 * s + 2 * k], ev[4 * s + 2 * k + 1]));
             t[k] += ms;
         }
     for (int k = 0; k < 2; ++k) us[k] = 1000.0 * t[k] / nsteps;
+    rc = L.post_range_copy();
+    if (rc) return rc;
     g->parity = (int)((g->parity + nsteps) & 1);
     g->step += nsteps;
     return VP_OK;
@@ -689,6 +733,18 @@ int vp_moments(vp_grid* g, vp_moments_t* out) {
     if (out->nonfinite) return fail(VP_ENONFINITE, "%lld non-finite weights", (long long)out->nonfinite);
     if (flags[kRangeFlag])
         return fail(VP_ERANGE, "a deposit cell sum exceeded 2^6 x 2^e, max|w0| < 2^e (fixed-point range)");
+    return VP_OK;
+}
+
+int vp_set_fixed_point(vp_grid* g, int32_t e) {
+    if (!g) return fail(VP_EINVAL, "null grid");
+    if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
+    if (!g->has_density) return fail(VP_ESTATE, "set the density first (it picks the default exponent)");
+    // the scale 2^(40 - e) and its inverse must be normal floats
+    if (e < kFixBits - 126 || e > 127) return fail(VP_EINVAL, "fixed-point exponent %d outside [%d, 127]", e, kFixBits - 126);
+    g->inst.fix_scale = ldexpf(1.0f, kFixBits - e);
+    g->inst.fix_inv = ldexpf(1.0f, e - kFixBits);
+    g->plan_valid = false;
     return VP_OK;
 }
 
@@ -870,8 +926,12 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
     L.solve = kSolveTent;
     for (int k = 0; k < n; ++k) L.solve = std::max(L.solve, grids[k]->list.solve);
     hipError_t e = hipMalloc(&L.d_inst, sizeof(VpInst) * n);
-    if (e == hipSuccess) e = hipMalloc(&L.d_off1, sizeof(int32_t) * 2 * (n + 1));
+    // tile offsets of both kernels, then the batch's range word
+    if (e == hipSuccess) e = hipMalloc(&L.d_off1, sizeof(int32_t) * (2 * (n + 1) + 1));
     L.d_off2 = L.d_off1 + (n + 1);
+    L.d_any = reinterpret_cast<uint32_t*>(L.d_off2 + (n + 1));
+    if (e == hipSuccess && alloc_host_flag(&L.h_any) != VP_OK) e = hipErrorOutOfMemory;
+    if (e == hipSuccess) e = hipMemsetAsync(L.d_any, 0, sizeof(uint32_t), s);
     if (e == hipSuccess) e = hipMemcpyAsync(L.d_inst, insts.data(), sizeof(VpInst) * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(L.d_off1, off1.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(L.d_off2, off2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
@@ -879,6 +939,7 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
     if (e != hipSuccess) {
         (void)hipFree(L.d_inst);
         (void)hipFree(L.d_off1);
+        free_host_flag(&L.h_any);
         delete b;
         return fail(VP_EHIP, "batch setup: %s", hipGetErrorString(e));
     }
@@ -890,6 +951,9 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
 int vp_batch_step(vp_batch* b, int64_t nsteps) {
     if (!b) return fail(VP_EINVAL, "null batch");
     if (nsteps < 0) return fail(VP_EINVAL, "negative step count");
+    if (b->list.range_seen())
+        return fail(VP_ERANGE, "a deposit cell sum of a batched grid left the fixed-point range "
+                               "(vp_moments names the grid)");
     if (nsteps == 0) return VP_OK;
     int rc = b->list.run(nsteps, (int)(b->steps_done & 1), true);
     if (rc) return rc;
@@ -907,6 +971,7 @@ int vp_batch_destroy(vp_batch* b) {
     b->list.drop_graphs();
     (void)hipFree(b->list.d_inst);
     (void)hipFree(b->list.d_off1);
+    free_host_flag(&b->list.h_any);
     for (auto* g : b->grids) g->in_batch = false;
     delete b;
     return VP_OK;

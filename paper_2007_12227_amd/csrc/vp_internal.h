@@ -52,7 +52,6 @@ constexpr int kReduceBlocks = 256;
 constexpr int kReduceThreads = 256;
 constexpr int kMoments = 10;      // FP64 sums produced by the reduction kernel
 
-// Basis functions of the expansion: tents (eq. 4), or quadratic B-splines.
 // Basis functions of the expansion: tents (eq. 4), or B-splines of degree 2 or
 // 3 (degree = basis + 1; the overlaps reach `basis` cells further than tents).
 enum Basis : int32_t { kBasisTent = 0, kBasisQuadratic = 1, kBasisCubic = 2 };
@@ -121,6 +120,50 @@ __host__ __device__ inline void sin_range(float a, float b, float* lo, float* hi
     // guard against rounding of the endpoint values
     *lo = l - 1e-6f;
     *hi = h + 1e-6f;
+}
+
+// Push tables of one step, formed in FP64 and stored as the kernels read them
+// (the host planner and the allocation-free entry point's device set-up use
+// the same code).  Column i, tab_x: sin and cos of x_i, or for the exact
+// rotation the x terms of the displacement in cells as hi + lo float pairs;
+// fel_ex: e^{i x_i} in FP64.  Row j, tab_p: the drift p_j dt / h_x in cells as
+// a hi + lo pair and sin, cos of the half-drift phase q_j = (delta + p_j) dt/2
+// (rotation: the p terms as pairs); fel_eq: e^{i q_j} in FP64.
+struct TableParams {
+    int32_t kind;
+    double x_lo, hx, p_lo, hp, dt, delta, omega;
+};
+__host__ __device__ inline void split_pair(double v, float& hi, float& lo) {
+    hi = (float)v;
+    lo = (float)(v - (double)hi);
+}
+__host__ __device__ inline void table_x(const TableParams& T, int i, float4& tx, double2& ex) {
+    const double x = T.x_lo + i * T.hx;
+    if (T.kind == kSho) {
+        const double th = T.omega * T.dt, s = sin(th), cm1 = -2.0 * sin(0.5 * th) * sin(0.5 * th);
+        split_pair(x * cm1 / T.hx, tx.x, tx.y);
+        split_pair(-x * s / T.hp, tx.z, tx.w);
+        ex = make_double2(0.0, 0.0);
+    } else {
+        tx = make_float4((float)sin(x), (float)cos(x), 0.f, 0.f);
+        ex = make_double2(cos(x), sin(x));
+    }
+}
+__host__ __device__ inline void table_p(const TableParams& T, int j, float4& tp, double2& eq) {
+    const double p = T.p_lo + j * T.hp;
+    if (T.kind == kSho) {
+        const double th = T.omega * T.dt, s = sin(th), cm1 = -2.0 * sin(0.5 * th) * sin(0.5 * th);
+        split_pair(p * s / T.hx, tp.x, tp.y);
+        split_pair(p * cm1 / T.hp, tp.z, tp.w);
+        eq = make_double2(0.0, 0.0);
+    } else {
+        const double v = T.delta + p;  // drift velocity of row j
+        const double q = 0.5 * T.dt * v;
+        split_pair(v * T.dt / T.hx, tp.x, tp.y);
+        tp.z = (float)sin(q);
+        tp.w = (float)cos(q);
+        eq = make_double2(cos(q), sin(q));
+    }
 }
 
 __host__ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -254,11 +297,13 @@ struct LaunchArgs {
     int32_t total;
     int32_t parity;      // step parity relative to each instance's parity0
     int32_t mode;        // k_fel_field: 0 after the solve, 1 after the Runge-Kutta stage sums
+    uint32_t* any_range; // set (with the instance's own flag) by a deposit cell out of range:
+                         // one word for the whole launch list, polled by the host
 };
 
 struct ReduceArgs {
     const float* w;
-    int32_t nx, np, kind, mode;   // mode 0: moments, 1: FEL bunching
+    int32_t nx, np, kind, mode;   // mode 0: moments, 1: FEL bunching, 2: sum, max|w| and non-finite count
     double x_lo, hx, p_lo, hp, a;
     double inv_n0;
     const double2* fel_ex;
@@ -272,10 +317,14 @@ struct ReduceArgs {
 };
 
 // launchers (vp_kernels.hip)
-hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s, int basis);
-hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s, int kind);
-hipError_t launch_fel_field(const LaunchArgs& a, hipStream_t s);
-hipError_t launch_fel_stage(const LaunchArgs& a, int grid, hipStream_t s);
+// (optional events e0, e1: recorded at the kernel's start and end, for timing)
+hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s, int basis,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s, int kind, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
+hipError_t launch_fel_field(const LaunchArgs& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_fel_stage(const LaunchArgs& a, int grid, hipStream_t s, hipEvent_t e0 = nullptr,
+                            hipEvent_t e1 = nullptr);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 const void* deposit_kernel(int basis);
 // Solve kernels: tents (k_solve); spline bases (k_solve_spline), each with a

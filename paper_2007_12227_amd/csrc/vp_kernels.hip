@@ -9,6 +9,8 @@
 // solves are FP32; the deposit's tap weights and products are FP64 (full rate
 // on gfx950), rounded once into exact fixed-point tile sums; the FEL bunching
 // sum and the diagnostics are FP64.
+#include <hip/hip_ext.h>
+
 #include "vp_internal.h"
 
 namespace vp {
@@ -688,7 +690,10 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
                 rr += carry ? 1 : 0;
             }
         }
-        if (out_of_range) atomicOr(&I.counters[kRangeFlag], 1u);
+        if (out_of_range) {
+            atomicOr(&I.counters[kRangeFlag], 1u);
+            atomicOr(A.any_range, 1u);
+        }
         __syncthreads();
     }
 }
@@ -1531,6 +1536,11 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
             continue;
         }
         if (!isfinite(w)) { acc[9] += 1.0; continue; }
+        if (R.mode == 2) {  // sum, largest magnitude and non-finite count only
+            acc[0] += w;
+            acc[8] = fmax(acc[8], fabs(w));
+            continue;
+        }
         const double x = R.x_lo + (double)i * R.hx, p = R.p_lo + (double)j * R.hp;
         acc[0] += w;
         acc[8] = fmax(acc[8], fabs(w));
@@ -1590,30 +1600,31 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
     }
 }
 
-hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s, int basis) {
-    if (basis == kBasisQuadratic) hipLaunchKernelGGL(k_deposit<6>, dim3(grid), dim3(threads), lds, s, a);
-    else if (basis == kBasisCubic) hipLaunchKernelGGL(k_deposit<8>, dim3(grid), dim3(threads), lds, s, a);
-    else hipLaunchKernelGGL(k_deposit<4>, dim3(grid), dim3(threads), lds, s, a);
-    return hipGetLastError();
+// One launch of a per-step kernel.  With events (timing), hipExtLaunchKernel
+// records them with the kernel's own dispatch, so their interval is the
+// kernel's execution, without the gaps a separate event record adds.
+static hipError_t launch_k(const void* fn, int grid, int threads, size_t lds, hipStream_t s, const LaunchArgs& a,
+                           hipEvent_t e0, hipEvent_t e1) {
+    void* args[1] = {const_cast<LaunchArgs*>(&a)};
+    if (e0 || e1) return hipExtLaunchKernel(fn, dim3(grid), dim3(threads), args, lds, s, e0, e1, 0);
+    return hipLaunchKernel(fn, dim3(grid), dim3(threads), args, lds, s);
 }
 
-hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s, int kind) {
-    if (kind == kSolveQuad) hipLaunchKernelGGL(k_solve_spline<2>, dim3(grid), dim3(kSolveQThreads), 0, s, a);
-    else if (kind == kSolveQuadNarrow) hipLaunchKernelGGL(k_solve_spline_narrow<2>, dim3(grid), dim3(kSolveQThreads), 0, s, a);
-    else if (kind == kSolveCubic) hipLaunchKernelGGL(k_solve_spline<3>, dim3(grid), dim3(kSolveQThreads), 0, s, a);
-    else if (kind == kSolveCubicNarrow) hipLaunchKernelGGL(k_solve_spline_narrow<3>, dim3(grid), dim3(kSolveQThreads), 0, s, a);
-    else hipLaunchKernelGGL(k_solve, dim3(grid), dim3(kSolveThreads), 0, s, a);
-    return hipGetLastError();
+hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s, int basis,
+                          hipEvent_t e0, hipEvent_t e1) {
+    return launch_k(deposit_kernel(basis), grid, threads, lds, s, a, e0, e1);
 }
 
-hipError_t launch_fel_field(const LaunchArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_fel_field, dim3(a.ninst), dim3(kFieldThreads), 0, s, a);
-    return hipGetLastError();
+hipError_t launch_solve(const LaunchArgs& a, int grid, hipStream_t s, int kind, hipEvent_t e0, hipEvent_t e1) {
+    return launch_k(solve_kernel(kind), grid, solve_threads(kind), 0, s, a, e0, e1);
 }
 
-hipError_t launch_fel_stage(const LaunchArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_fel_stage, dim3(grid), dim3(kStageThreads), 0, s, a);
-    return hipGetLastError();
+hipError_t launch_fel_field(const LaunchArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    return launch_k(fel_field_kernel(), a.ninst, kFieldThreads, 0, s, a, e0, e1);
+}
+
+hipError_t launch_fel_stage(const LaunchArgs& a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    return launch_k(fel_stage_kernel(), grid, kStageThreads, 0, s, a, e0, e1);
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {

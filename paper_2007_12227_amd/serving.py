@@ -32,6 +32,7 @@ class Result:
     completed: float = 0.0
     moments: dict = field(default_factory=dict)
     density: np.ndarray | None = None
+    error: str | None = None  # why the request failed (its results are then not valid)
 
     @property
     def latency(self) -> float:
@@ -58,6 +59,17 @@ class DeviceBackend:
 
     def make_batch(self, grids, dts):
         return self.B.Batch(grids, dts)
+
+    def collect(self, grid, keep_density: bool):
+        """(moments, density or None, error or None) of a finished grid: a
+        state the library reports as invalid (non-finite weights, a deposit
+        out of its fixed-point range) fails the request."""
+        try:
+            m = grid.moments()
+            d = grid.density() if keep_density else None
+            return m, d, None
+        except self.B.VpError as e:
+            return grid.moments(check_state=False), None, str(e)
 
     def step_alone(self, grid, dt, n):
         grid.step(dt, n)
@@ -119,6 +131,12 @@ class Server:
                 req = pending[0]
                 inst = req.instance()
                 need = be.footprint(inst)
+                if need > self.budget:
+                    # can never fit: refused, not run
+                    pending.popleft()
+                    results.append(Result(req.rid, req.kind, req.n, req.steps, req.arrival, admitted=now(),
+                                          completed=now(), error=f"needs {need} bytes, budget {self.budget}"))
+                    continue
                 if resident and used + need > self.budget:
                     break  # wait for memory to free up (FIFO admission)
                 pending.popleft()
@@ -142,7 +160,28 @@ class Server:
                 batch = be.make_batch([r.grid for r in resident], [r.inst.dt for r in resident])
                 self.batch_rebuilds += 1
             s = min(self.chunk, min(r.remaining for r in resident))
-            batch.step(s)
+            try:
+                batch.step(s)
+            except getattr(getattr(be, "B", None), "VpError", ()) as e:
+                if getattr(e, "code", None) != -7:
+                    raise
+                # a resident's deposit left its fixed-point range: fail the
+                # residents whose state says so, keep serving the others
+                be.sync()
+                batch.close()
+                batch = None
+                keep = []
+                for r in resident:
+                    m, _, err = be.collect(r.grid, False)
+                    if err:
+                        r.result.completed, r.result.moments, r.result.error = now(), m, err
+                        r.grid.close()
+                        used -= r.nbytes
+                        results.append(r.result)
+                    else:
+                        keep.append(r)
+                resident = keep
+                continue
             self.iterations += 1
             for r in resident:
                 r.remaining -= s
@@ -154,9 +193,7 @@ class Server:
                 tdone = now()
                 for r in done:
                     r.result.completed = tdone
-                    r.result.moments = r.grid.moments()
-                    if self.keep_density:
-                        r.result.density = r.grid.density()
+                    r.result.moments, r.result.density, r.result.error = be.collect(r.grid, self.keep_density)
                     r.grid.close()
                     used -= r.nbytes
                     results.append(r.result)
@@ -186,18 +223,20 @@ def serve_one_at_a_time(requests, realtime: bool = True, backend=None) -> list[R
         be.step_alone(g, inst.dt, req.steps)
         be.sync()
         res.completed = time.perf_counter() - t0 + offset
-        res.moments = g.moments()
+        res.moments, _, res.error = be.collect(g, False)
         g.close()
         out.append(res)
     return out
 
 
 def summary(results: list[Result], wall: float | None = None) -> dict:
+    failed = [r for r in results if r.error]
+    results = [r for r in results if not r.error]
     lat = np.array([r.latency for r in results])
     work = float(sum(r.node_steps for r in results))
     if wall is None:
         wall = max(r.completed for r in results) - min(r.arrival for r in results)
-    return {"requests": len(results), "node_steps": work, "wall_s": wall,
+    return {"requests": len(results), "failed": len(failed), "node_steps": work, "wall_s": wall,
             "node_steps_per_s": work / wall if wall > 0 else float("nan"),
             "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)),

@@ -59,6 +59,7 @@ def test_null_handles(L):
     assert L.vp_set_hamiltonian(None, None) == B.VP_EINVAL
     assert L.vp_batch_step(None, 1) == B.VP_EINVAL
     assert L.vp_set_basis(None, B.BASIS_CUBIC) == B.VP_EINVAL
+    assert L.vp_set_fixed_point(None, 0) == B.VP_EINVAL
     assert L.vp_batch_create(None, 0, None, None) == B.VP_EINVAL
 
 

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
+from _parity import assert_step_parity
 from oracle import spline_basis as Q
 from paper_2007_12227_amd.inputs import (FEL_RK4, H_FEL, H_FREE, H_PENDULUM, H_SHO_EXACT, Axis, Hamiltonian,
                                          fel_gaussian, gaussian, pendulum_axes, pendulum_band, rng)
@@ -61,9 +62,7 @@ def test_one_step_each_kind(B, kind):
     x, p, ham, dt, w = case(kind)
     w = w.astype(np.float32)
     got, _ = gpu_steps(B, x, p, ham, w, dt, 1)
-    err = oracle.rel_l1(got, oracle_step(x, p, ham, w, dt))
-    print(f"cubic, kind {kind}: rel L1 {err:.3e}", flush=True)
-    assert err <= 1e-5
+    assert_step_parity(got, oracle_step(x, p, ham, w, dt), label=f"cubic, kind {kind}:")
 
 
 def test_deposit_tilings_agree_bitwise(B):
@@ -73,7 +72,7 @@ def test_deposit_tilings_agree_bitwise(B):
     first = None
     for t in [None, (64, 16), (24, 5, 64), (200, 24, 1024), (128, 112, 1024)]:
         got, _ = gpu_steps(B, x, p, ham, w, dt, 1, t)
-        assert oracle.rel_l1(got, ref) <= 1e-5, t
+        assert_step_parity(got, ref, label=str(t))
         if first is None:
             first = got
         assert np.array_equal(got, first), t
@@ -102,7 +101,7 @@ def test_one_step_window_shapes(B, nx, np_, periodic):
         ham, dt = Hamiltonian(H_SHO_EXACT, omega=1.0), 0.3
     w = (0.5 + rng(82).random((np_, nx))).astype(np.float32)
     got, _ = gpu_steps(B, x, p, ham, w, dt, 1)
-    assert oracle.rel_l1(got, oracle_step(x, p, ham, w, dt)) <= 1e-5
+    assert_step_parity(got, oracle_step(x, p, ham, w, dt))
 
 
 def test_whole_cell_free_streaming_and_no_motion(B):
@@ -119,7 +118,7 @@ def test_whole_cell_free_streaming_and_no_motion(B):
     print(f"cubic whole-cell stream: max error {err:.3e} (bound {bound:.3e})", flush=True)
     assert err <= bound
     got, _ = gpu_steps(B, x, p, Hamiltonian(H_FREE), w, 0.0, 1)
-    assert oracle.rel_l1(got, w.astype(np.float64)) <= 1e-5
+    assert_step_parity(got, w.astype(np.float64))
 
 
 @pytest.mark.parametrize("kind", [H_PENDULUM, H_SHO_EXACT])
@@ -154,9 +153,7 @@ def test_one_step_at_2048_in_the_benchmark_launch(B):
     g.step(inst.dt, 1)
     got = g.density().astype(np.float64)
     g.close()
-    err = oracle.rel_l1(got, oracle_step(inst.x, inst.p, inst.ham, w32, inst.dt))
-    print(f"cubic 2048^2 band: rel L1 {err:.3e}", flush=True)
-    assert err <= 1e-5
+    assert_step_parity(got, oracle_step(inst.x, inst.p, inst.ham, w32, inst.dt), label="cubic 2048^2 band:")
 
 
 @pytest.mark.parametrize("integrator", [0, FEL_RK4])
@@ -172,7 +169,7 @@ def test_fel_run_256(B, integrator):
     m = g.moments()
     g.close()
     ref1, _ = Q.run_fel(inst.x, inst.p, ham, w32.astype(np.float64), inst.dt, 1, degree=DEG)
-    assert oracle.rel_l1(one, ref1) <= 1e-5
+    assert_step_parity(one, ref1)
     ref, A = Q.run_fel(inst.x, inst.p, ham, w32.astype(np.float64), inst.dt, 200, degree=DEG)
     err = oracle.rel_l1(got, ref)
     Ag = complex(m["A_re"], m["A_im"])

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
+from _parity import assert_step_parity
 from paper_2007_12227_amd.inputs import (H_FEL, H_PENDULUM, H_SHO_EXACT, Axis, Hamiltonian, fel_gaussian,
                                          gaussian, pendulum_axes, rng)
 
@@ -77,7 +78,7 @@ def test_largest_axis(B, nx, np_):
     got = g.density().astype(np.float64)
     g.close()
     ref = oracle.run(x, p, ham, w.astype(np.float64), 0.01, 1).w
-    assert oracle.rel_l1(got, ref) <= 1e-5
+    assert_step_parity(got, ref)
 
 
 def test_axis_beyond_the_largest_is_refused(B):
@@ -114,4 +115,64 @@ def test_fel_with_zero_weight_sum_is_refused(B):
     with pytest.raises(B.VpError) as e:
         g.step(inst.dt, 1)
     assert e.value.code == B.VP_ESTATE
+    g.close()
+
+
+def test_deposit_range_error_surfaces_everywhere(B):
+    """A deposit whose cell sums leave the fixed-point range (forced by lowering
+    the exponent below what max|w0| needs) is reported: vp_get_density and
+    vp_moments return VP_ERANGE, the next vp_step and vp_batch_step refuse to
+    step, and a new density clears it.  A second grid in the same batch that
+    stays in range keeps its own flag clear."""
+    import torch
+    x, p = pendulum_axes(96, 80)
+    w = (0.75 + 0.2 * rng(61).random((80, 96))).astype(np.float32)  # max|w0| < 1 = 2^0
+    g = grid(B, x, p, Hamiltonian(H_PENDULUM, a=1.0), w)
+    g.set_fixed_point(-8)  # cells near 0.75 now exceed the 2^(-8+6) bound
+    g.step(0.05, 2)
+    with pytest.raises(B.VpError) as e:
+        g.density()
+    assert e.value.code == B.VP_ERANGE
+    with pytest.raises(B.VpError) as e:
+        g.moments()
+    assert e.value.code == B.VP_ERANGE
+    assert g.moments(check_state=False)["status"] == B.VP_ERANGE
+    with pytest.raises(B.VpError) as e:
+        g.step(0.05, 1)
+    assert e.value.code == B.VP_ERANGE
+    g.set_density(w)  # resets the exponent and the flag
+    g.step(0.05, 2)
+    assert np.isfinite(g.density()).all() and g.moments()["status"] == B.VP_OK
+
+    ok = grid(B, x, p, Hamiltonian(H_PENDULUM, a=1.0), w)
+    g.set_fixed_point(-8)
+    batch = B.Batch([g, ok], [0.05, 0.05])
+    batch.step(2)
+    torch.cuda.synchronize()
+    with pytest.raises(B.VpError) as e:
+        batch.step(1)
+    assert e.value.code == B.VP_ERANGE
+    batch.close()
+    assert ok.moments()["status"] == B.VP_OK
+    with pytest.raises(B.VpError):
+        g.moments()
+    g.close()
+    ok.close()
+
+
+def test_fixed_point_exponent_is_validated(B):
+    x, p = pendulum_axes(32, 32)
+    g = B.Grid(x, p)
+    with pytest.raises(B.VpError) as e:
+        g.set_fixed_point(0)  # before a density
+    assert e.value.code == B.VP_ESTATE
+    g.set_hamiltonian(Hamiltonian(H_PENDULUM, a=1.0))
+    g.set_density(np.ones((32, 32), np.float32))
+    for bad in (-87, 128):
+        with pytest.raises(B.VpError) as e:
+            g.set_fixed_point(bad)
+        assert e.value.code == B.VP_EINVAL
+    g.set_fixed_point(4)  # coarser grid, wider range: still a valid step
+    g.step(0.05, 3)
+    assert g.moments()["status"] == B.VP_OK
     g.close()

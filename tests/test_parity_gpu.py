@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+from _parity import assert_step_parity
 import dataclasses
 
 from paper_2007_12227_amd.inputs import (FEL_RK4, H_FEL, H_FREE, H_PENDULUM, H_SHO_EXACT, Axis, Hamiltonian,
@@ -61,7 +62,7 @@ def test_one_step_pendulum_ragged(B, tiles):
     ham = Hamiltonian(H_PENDULUM, a=1.3)
     got, _ = gpu_run(B, x, p, ham, w, 0.07, 1, tiles)
     ref = one_step_ref(x, p, ham, w, 0.07)
-    assert oracle.rel_l1(got, ref) <= 1e-5
+    assert_step_parity(got, ref)
 
 
 @pytest.mark.parametrize("kind", [H_FREE, H_PENDULUM, H_SHO_EXACT, H_FEL])
@@ -87,7 +88,7 @@ def test_one_step_each_kind(B, kind):
         ref = oracle.run(x, p, ham, w.astype(np.float64), dt, 1, A0=A0).w
     else:
         ref = one_step_ref(x, p, ham, w, dt)
-    assert oracle.rel_l1(got, ref) <= 1e-5
+    assert_step_parity(got, ref)
 
 
 def test_full_run_pendulum_gaussian_128(B):
@@ -110,7 +111,7 @@ def test_one_step_small_lattices(B, nx, np_):
     ham = Hamiltonian(H_PENDULUM, a=0.8)
     got, _ = gpu_run(B, x, p, ham, w, 0.05, 1, (16, 8))
     ref = one_step_ref(x, p, ham, w, 0.05)
-    assert oracle.rel_l1(got, ref) <= 1e-5
+    assert_step_parity(got, ref)
 
 
 @pytest.mark.parametrize("nx,np_", [(80, 96), (70, 80), (100, 97), (64, 200), (96, 160)])
@@ -124,7 +125,7 @@ def test_one_step_solve_window_paths(B, nx, np_):
     ham = Hamiltonian(H_PENDULUM, a=1.1)
     got, _ = gpu_run(B, x, p, ham, w, 0.06, 1, (32, 16))
     ref = one_step_ref(x, p, ham, w, 0.06)
-    assert oracle.rel_l1(got, ref) <= 1e-5
+    assert_step_parity(got, ref)
 
 
 @pytest.mark.parametrize("nx,np_", [(40, 96), (64, 80), (100, 130), (130, 64)])
@@ -136,7 +137,7 @@ def test_one_step_open_x_window_paths(B, nx, np_):
     w = (gaussian(x, p, 0.8, -0.4, 0.7) + 1e-3 * rng(37).random((np_, nx))).astype(np.float32)
     got, _ = gpu_run(B, x, p, ham, w, 0.3, 1, (32, 16))
     ref = one_step_ref(x, p, ham, w, 0.3)
-    assert oracle.rel_l1(got, ref) <= 1e-5
+    assert_step_parity(got, ref)
 
 
 def test_graph_and_plain_launches_agree(B):
@@ -285,7 +286,7 @@ def test_fel_rk4_one_step(B):
     w32 = inst.w0.astype(np.float32)
     got, m = gpu_run(B, inst.x, inst.p, ham, w32, inst.dt, 1, (64, 16))
     r = oracle.run(inst.x, inst.p, ham, w32.astype(np.float64), inst.dt, 1)
-    assert oracle.rel_l1(got, r.w) <= 1e-5
+    assert_step_parity(got, r.w)
     assert abs(complex(m["A_re"], m["A_im"]) - r.A) <= 1e-12
 
 
@@ -341,7 +342,7 @@ def test_one_step_full_size_pendulum_band_2048(B):
     w32 = inst.w0.astype(np.float32)
     got, _ = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 1)
     ref = one_step_ref(inst.x, inst.p, inst.ham, w32, inst.dt)
-    assert oracle.rel_l1(got, ref) <= 1e-5
+    assert_step_parity(got, ref)
 
 
 def test_one_step_full_size_fel_rk4_1024(B):
@@ -349,7 +350,7 @@ def test_one_step_full_size_fel_rk4_1024(B):
     w32 = inst.w0.astype(np.float32)
     got, m = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 1)
     r = oracle.run(inst.x, inst.p, inst.ham, w32.astype(np.float64), inst.dt, 1)
-    assert oracle.rel_l1(got, r.w) <= 1e-5
+    assert_step_parity(got, r.w)
     assert abs(complex(m["A_re"], m["A_im"]) - r.A) <= 1e-12
 
 
@@ -358,4 +359,4 @@ def test_one_step_full_size_fel_1024(B):
     w32 = inst.w0.astype(np.float32)
     got, _ = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 1)
     ref = oracle.run(inst.x, inst.p, inst.ham, w32.astype(np.float64), inst.dt, 1).w
-    assert oracle.rel_l1(got, ref) <= 1e-5
+    assert_step_parity(got, ref)

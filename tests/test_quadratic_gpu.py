@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
+from _parity import assert_step_parity
 from oracle import spline_basis as Q
 from paper_2007_12227_amd.inputs import (FEL_RK4, H_FEL, H_FREE, H_PENDULUM, H_SHO_EXACT, Axis, Hamiltonian,
                                          fel_gaussian, gaussian, pendulum_axes, pendulum_band, rng)
@@ -63,9 +64,7 @@ def test_one_step_each_kind(B, kind):
     w = w.astype(np.float32)
     got, _ = gpu_steps(B, x, p, ham, w, dt, 1)
     ref = oracle_step(x, p, ham, w, dt)
-    err = oracle.rel_l1(got, ref)
-    print(f"kind {kind}: rel L1 {err:.3e}", flush=True)
-    assert err <= 1e-5
+    assert_step_parity(got, ref, label=f"kind {kind}:")
 
 
 TILINGS = [None, (64, 16), (24, 5, 64), (200, 24, 1024), (128, 128, 1024)]
@@ -79,7 +78,7 @@ def test_deposit_tilings_agree_bitwise(B):
     first = None
     for t in TILINGS:
         got, _ = gpu_steps(B, x, p, ham, w, dt, 1, t)
-        assert oracle.rel_l1(got, ref) <= 1e-5, t
+        assert_step_parity(got, ref, label=str(t))
         if first is None:
             first = got
         assert np.array_equal(got, first), t
@@ -98,7 +97,7 @@ def test_one_step_window_shapes(B, nx, np_, periodic):
         ham, dt = Hamiltonian(H_SHO_EXACT, omega=1.0), 0.3
     w = (0.5 + rng(72).random((np_, nx))).astype(np.float32)
     got, _ = gpu_steps(B, x, p, ham, w, dt, 1)
-    assert oracle.rel_l1(got, oracle_step(x, p, ham, w, dt)) <= 1e-5
+    assert_step_parity(got, oracle_step(x, p, ham, w, dt))
 
 
 def test_whole_cell_free_streaming_is_a_row_rotation(B):
@@ -157,9 +156,7 @@ def test_one_step_at_2048_in_the_benchmark_launch(B):
     g.step(inst.dt, 1)
     got = g.density().astype(np.float64)
     g.close()
-    err = oracle.rel_l1(got, oracle_step(inst.x, inst.p, inst.ham, w32, inst.dt))
-    print(f"2048^2 band: rel L1 {err:.3e}", flush=True)
-    assert err <= 1e-5
+    assert_step_parity(got, oracle_step(inst.x, inst.p, inst.ham, w32, inst.dt), label="2048^2 band:")
 
 
 @pytest.mark.parametrize("integrator", [0, FEL_RK4])
@@ -176,7 +173,7 @@ def test_fel_one_step(B, delta, sigma2, integrator):
     m = g.moments()
     g.close()
     ref, A = Q.run_fel(inst.x, inst.p, ham, w32.astype(np.float64), inst.dt, 1)
-    assert oracle.rel_l1(got, ref) <= 1e-5
+    assert_step_parity(got, ref)
     assert abs(complex(m["A_re"], m["A_im"]) - A) <= 1e-12
 
 

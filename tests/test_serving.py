@@ -52,6 +52,9 @@ class FakeBackend:
     def sync(self):
         pass
 
+    def collect(self, grid, keep_density):
+        return grid.moments(), grid.density() if keep_density else None, None
+
 
 def small_trace():
     return request_trace(40, seed=9, rate=1e6, n_min=16, n_max=64, steps_min=5, steps_max=60)
@@ -93,3 +96,18 @@ def test_one_at_a_time_baseline_and_summary():
     assert [r.rid for r in res] == sorted(r.rid for r in res)
     s = summary(res)
     assert s["requests"] == 40 and s["node_steps"] > 0 and s["p99_latency_s"] >= s["p50_latency_s"]
+
+
+def test_request_larger_than_the_budget_is_refused_not_run():
+    trace = small_trace()
+    be = FakeBackend()
+    big = max(trace, key=lambda r: r.n)
+    budget = be.footprint(big.instance()) - 1
+    res = Server(budget_bytes=budget, chunk=8, realtime=False, backend=be).run(trace)
+    assert len(res) == len(trace)
+    refused = [r for r in res if r.error]
+    assert refused and all(be.footprint(next(q for q in trace if q.rid == r.rid).instance()) > budget
+                           for r in refused)
+    assert all(r.moments["step"] == r.steps for r in res if not r.error)
+    s = summary(res)
+    assert s["failed"] == len(refused) and s["requests"] == len(trace) - len(refused)
