@@ -263,6 +263,36 @@ int vp_batch_step(vp_batch* b, int64_t nsteps);
 /* Release the batch (the grids stay; they can be stepped alone again). */
 int vp_batch_destroy(vp_batch* b);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops and harnesses that forbid hipMalloc): the steps of vp_step on one
+ * lattice given by its axes, with no grid, no workspace and no allocation of
+ * any kind.  Its scratch (the right-hand side b, push tables, FEL state,
+ * per-tile partials, counters, the descriptor) lives in a static device
+ * array of the library (20 MiB, held on every device the library runs on
+ * until the process ends): lattices of at most 2^22 nodes (VP_ENOMEM beyond).
+ * Every call on a device shares that array: calls that overlap on one device
+ * (other streams, other threads) race, and must be ordered by the caller.
+ *  x, p, h, basis, dt, nsteps: as for vp_create_grid, vp_set_hamiltonian,
+ *      vp_set_basis and vp_step (deposit tiles: the default shape);
+ *  w_in:   device, n_p*n_x floats, the weights at the start (not written);
+ *  w_out:  device, n_p*n_x floats, the weights after nsteps steps (may equal
+ *          w_in: the step then runs in place);
+ *  fel_n0: FEL only, N0 of eq. 13c (the sum of the weights when the run
+ *          started; the caller keeps it across calls), nonzero;
+ *  fel_A:  FEL only, device double[2], the field (re, im): read at the start,
+ *          written with the field after the steps;
+ *  status: optional device int32, written when the steps are done: VP_OK,
+ *          VP_ENONFINITE (w_in holds NaN/Inf: nothing is deposited, w_out
+ *          ends zero) or VP_ERANGE (a deposit cell left the fixed-point range
+ *          set from max|w_in|, see vp_set_fixed_point);
+ *  stream: hipStream_t (NULL = default) on which everything is enqueued; the
+ *          call returns without waiting.
+ * Argument errors return VP_EINVAL / VP_EUNSUPPORTED / VP_ESTATE as the
+ * grid calls do, before anything is enqueued. */
+int vp_step_noalloc(const vp_axis* x, const vp_axis* p, const vp_hamiltonian* h, int32_t basis, double dt,
+                    int64_t nsteps, const float* w_in, float* w_out, double fel_n0, double* fel_A,
+                    int32_t* status, void* stream);
+
 /* Status text and the calling thread's last error message. */
 const char* vp_status_string(int status);
 const char* vp_last_error(void);

@@ -101,6 +101,8 @@ def lib(load_torch: bool = True):
                                      C.c_double, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P(C.c_int32)]
     L.vp_set_basis.argtypes = [C.c_void_p, C.c_int32]
     L.vp_set_fixed_point.argtypes = [C.c_void_p, C.c_int32]
+    L.vp_step_noalloc.argtypes = [P(Axis), P(Axis), P(Hamiltonian), C.c_int32, C.c_double, C.c_int64,
+                                  C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
     for name in declared_functions():
         if name not in ("vp_workspace_bytes", "vp_status_string", "vp_last_error"):
             getattr(L, name).restype = C.c_int
@@ -279,6 +281,19 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def step_noalloc(x, p, ham, dt, nsteps, w_in, w_out, basis=BASIS_TENT, fel_n0=0.0, fel_A=None, status=None,
+                 stream=None):
+    """vp_step_noalloc on CUDA tensors: w_in, w_out float32 [n_p][n_x]; fel_A a
+    float64 tensor of 2 (FEL); status an int32 tensor of 1 (optional)."""
+    import torch
+    for t in (w_in, w_out):
+        assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == x.n * p.n
+    ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+    check(lib().vp_step_noalloc(C.byref(axis(x)), C.byref(axis(p)), C.byref(hamiltonian(ham)), int(basis),
+                                float(dt), int(nsteps), ptr(w_in), ptr(w_out), float(fel_n0), ptr(fel_A),
+                                ptr(status), _stream_handle(stream)))
 
 
 def grid_for(inst, stream=None) -> Grid:

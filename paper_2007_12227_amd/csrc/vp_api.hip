@@ -977,6 +977,129 @@ int vp_batch_destroy(vp_batch* b) {
     return VP_OK;
 }
 
+int vp_step_noalloc(const vp_axis* x, const vp_axis* p, const vp_hamiltonian* h, int32_t basis, double dt,
+                    int64_t nsteps, const float* w_in, float* w_out, double fel_n0, double* fel_A, int32_t* status,
+                    void* stream) {
+    if (!x || !p || !h || !w_in || !w_out) return fail(VP_EINVAL, "null argument");
+    if (!axis_ok(x) || !axis_ok(p)) return fail(VP_EINVAL, "invalid axis (need n >= 4, hi > lo, finite)");
+    if (p->periodic) return fail(VP_EUNSUPPORTED, "the momentum axis must be open");
+    if (h->kind < VP_H_FREE || h->kind > VP_H_FEL) return fail(VP_EINVAL, "unknown Hamiltonian kind %d", h->kind);
+    if (!isfinite(h->a) || !isfinite(h->omega) || !isfinite(h->fel_delta) || !isfinite(h->fel_sigma2))
+        return fail(VP_EINVAL, "non-finite Hamiltonian parameter");
+    if (h->kind == VP_H_SHO_EXACT && x->periodic) return fail(VP_EUNSUPPORTED, "the exact rotation needs an open x axis");
+    if (h->integrator != VP_FEL_DKD && !(h->kind == VP_H_FEL && h->integrator == VP_FEL_RK4))
+        return fail(VP_EINVAL, "integrator %d: only the FEL takes VP_FEL_RK4", h->integrator);
+    if (basis < VP_BASIS_TENT || basis > VP_BASIS_CUBIC) return fail(VP_EINVAL, "unknown basis %d", basis);
+    if (!isfinite(dt)) return fail(VP_EINVAL, "dt must be finite");
+    if (nsteps < 0) return fail(VP_EINVAL, "negative step count");
+    const bool fel = h->kind == VP_H_FEL;
+    if (fel && (!fel_A || !(fel_n0 != 0.0) || !isfinite(fel_n0)))
+        return fail(VP_ESTATE, "the FEL needs its field (fel_A) and a nonzero finite N0");
+    const int nx = x->n, np = p->n;
+    if ((long)nx * np > kNoAllocMaxNodes)
+        return fail(VP_ENOMEM, "%d x %d nodes: the allocation-free step takes at most %ld", nx, np, kNoAllocMaxNodes);
+    const Layout L = layout(nx, np);
+    const size_t need = L.boxes - L.b;  // b .. the moments: everything but the state and the host boxes
+    if (need > kNoAllocScratchBytes)
+        return fail(VP_ENOMEM, "%zu bytes of scratch needed, %zu available", need, kNoAllocScratchBytes);
+    raise_lds_limit();
+    hipError_t e = hipSuccess;
+    char* scr = static_cast<char*>(noalloc_scratch(&e));
+    if (!scr) return fail(VP_EHIP, "scratch address: %s", hipGetErrorString(e));
+    auto at = [&](size_t off) { return scr + (off - L.b); };
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+    // the descriptor of a grid of this shape, as upload_inst builds it, with
+    // the state in w_out (read and written in place: the deposit reads it into
+    // b, the solve writes it back) and the source boxes planned in the kernel
+    VpInst I{};
+    I.push = push_params(*x, *p, *h, dt, basis);
+    vp_tiles t = default_tiles(nx, np, basis);
+    t.k1_tx = std::min(t.k1_tx, nx);
+    t.k1_ty = std::min(t.k1_ty, np);
+    I.k1_tx = t.k1_tx;
+    I.k1_ty = t.k1_ty;
+    I.k1_tiles_x = (nx + t.k1_tx - 1) / t.k1_tx;
+    I.k1_tiles = I.k1_tiles_x * ((np + t.k1_ty - 1) / t.k1_ty);
+    I.k2_tiles = solve_tiles(nx, np, basis);
+    I.fel_kick = -2.0 * dt / spacing(*p);
+    I.fel_sigma2 = (float)h->fel_sigma2;
+    I.fel_dz = dt;
+    I.w[0] = I.w[1] = w_out;
+    I.b = reinterpret_cast<float*>(at(L.b));
+    I.tab_x = reinterpret_cast<float4*>(at(L.tab_x));
+    I.tab_p = reinterpret_cast<float4*>(at(L.tab_p));
+    I.fel_ex = reinterpret_cast<double2*>(at(L.fel_ex));
+    I.fel_eq = reinterpret_cast<double2*>(at(L.fel_eq));
+    I.fel_state = reinterpret_cast<double*>(at(L.fel_state));
+    I.partials = reinterpret_cast<double*>(at(L.partials));
+    I.counters = reinterpret_cast<uint32_t*>(at(L.counters));
+    I.boxes = nullptr;
+    NoAllocSetup S{};
+    S.inst = I;
+    S.inst_out = reinterpret_cast<VpInst*>(at(L.inst));
+    S.off_out = reinterpret_cast<int32_t*>(at(L.off));
+    S.tables = table_params(*x, *p, *h, dt);
+    S.tab_x = const_cast<float4*>(I.tab_x);
+    S.tab_p = const_cast<float4*>(I.tab_p);
+    S.fel_ex = const_cast<double2*>(I.fel_ex);
+    S.fel_eq = const_cast<double2*>(I.fel_eq);
+    S.fel_state = I.fel_state;
+    S.counters = I.counters;
+    S.fel_A = fel ? fel_A : nullptr;
+    S.n0 = fel ? fel_n0 : 0.0;
+    double* moments = reinterpret_cast<double*>(at(L.moments));
+
+    const size_t bytes = (size_t)nx * np * sizeof(float);
+    if (w_out != w_in) HIP_TRY(hipMemcpyAsync(w_out, w_in, bytes, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_noalloc_setup(S, nx, np, s));
+    ReduceArgs R{};
+    R.w = w_out;
+    R.nx = nx;
+    R.np = np;
+    R.kind = h->kind;
+    R.mode = 2;
+    R.x_lo = x->lo;
+    R.hx = spacing(*x);
+    R.p_lo = p->lo;
+    R.hp = spacing(*p);
+    R.inv_n0 = fel ? 1.0 / fel_n0 : 0.0;
+    R.fel_ex = I.fel_ex;
+    R.fel_eq = I.fel_eq;
+    R.partials = I.partials;
+    R.counter = I.counters + 1;
+    R.out = moments;
+    R.dz = dt;
+    HIP_TRY(launch_reduce(R, s));
+    HIP_TRY(launch_noalloc_scale(S.inst_out, moments, s));
+    if (fel) {  // the bunching of the starting state at the half-drift phases
+        R.mode = 1;
+        R.out = I.fel_state;
+        HIP_TRY(launch_reduce(R, s));
+    }
+    LaunchList LL;
+    LL.d_inst = S.inst_out;
+    LL.d_off1 = S.off_out;
+    LL.d_off2 = S.off_out + 2;
+    LL.d_any = I.counters + kRangeFlag;
+    LL.ninst = 1;
+    LL.total1 = I.k1_tiles;
+    LL.total2 = I.k2_tiles;
+    LL.has_fel = fel;
+    LL.has_rk4 = fel && h->integrator == VP_FEL_RK4;
+    LL.basis = basis;
+    LL.solve = solve_kind(basis, nx, np, x->periodic != 0);
+    LL.lds1 = deposit_lds_bytes(t.k1_tx, t.k1_ty, basis);
+    LL.threads1 = t.k1_threads;
+    LL.stream = s;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        int rc = LL.enqueue_step((int)(k & 1));
+        if (rc) return rc;
+    }
+    HIP_TRY(launch_noalloc_finish(moments, I.fel_state, I.counters, fel ? fel_A : nullptr, status, s));
+    return VP_OK;
+}
+
 const char* vp_status_string(int s) {
     switch (s) {
     case VP_OK: return "ok";

@@ -316,6 +316,37 @@ struct ReduceArgs {
     double cos_fac;               // integral of cos over the basis function of width h_x, per h_x: sinc(h_x/2)^(2 or 3)
 };
 
+// Allocation-free stepping (vp_step_noalloc): one lattice's scratch (b, the
+// push tables, FEL state, per-tile partials, counters, descriptor and tile
+// offsets) in a static device array of this size, for at most this many nodes.
+constexpr size_t kNoAllocScratchBytes = (size_t)20 << 20;
+constexpr long kNoAllocMaxNodes = 1l << 22;
+
+struct NoAllocSetup {
+    VpInst inst;            // the descriptor, pointers into the scratch
+    VpInst* inst_out;       // where the kernels read it
+    int32_t* off_out;       // tile offsets {0, deposit tiles, 0, solve tiles}
+    TableParams tables;
+    float4* tab_x;
+    float4* tab_p;
+    double2* fel_ex;
+    double2* fel_eq;
+    double* fel_state;
+    uint32_t* counters;
+    const double* fel_A;    // FEL field at the start (device), or null
+    double n0;              // FEL normalisation
+};
+// Device address of the allocation-free scratch on the current device (looked
+// up once per device); null with the error in *err on failure.
+void* noalloc_scratch(hipError_t* err);
+hipError_t launch_noalloc_setup(const NoAllocSetup& S, int nx, int np, hipStream_t s);
+// fixed-point scale from max|w| (moments[8]); a non-finite input (moments[9])
+// zeroes the scale, so nothing is deposited
+hipError_t launch_noalloc_scale(VpInst* inst, const double* moments, hipStream_t s);
+// the field back to the caller, the status word (VP_OK, VP_ENONFINITE, VP_ERANGE)
+hipError_t launch_noalloc_finish(const double* moments, const double* fel_state, const uint32_t* counters,
+                                 double* fel_A, int32_t* status, hipStream_t s);
+
 // launchers (vp_kernels.hip)
 // (optional events e0, e1: recorded at the kernel's start and end, for timing)
 hipError_t launch_deposit(const LaunchArgs& a, int grid, size_t lds, int threads, hipStream_t s, int basis,

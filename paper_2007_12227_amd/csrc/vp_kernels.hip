@@ -9,6 +9,8 @@
 // solves are FP32; the deposit's tap weights and products are FP64 (full rate
 // on gfx950), rounded once into exact fixed-point tile sums; the FEL bunching
 // sum and the diagnostics are FP64.
+#include <mutex>
+
 #include <hip/hip_ext.h>
 
 #include "vp_internal.h"
@@ -1598,6 +1600,95 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
         __threadfence();
         atomicExch(R.counter, 0u);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free stepping: the scratch array and the kernels that set it up
+// for one call of vp_step_noalloc and report back.  Each call writes every
+// byte it reads later (tables, descriptor, offsets, FEL state, counters; b is
+// written by the deposit before the solve reads it), so nothing of an earlier
+// call leaks into a later one; calls that overlap on one device race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+void* noalloc_scratch(hipError_t* err) {
+    constexpr int kMaxDevices = 64;
+    static void* ptr[kMaxDevices] = {};
+    static std::mutex mu;
+    int dev = 0;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        // the array's name is a host-side stand-in: kernels get this address
+        void* p = nullptr;
+        *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess) return nullptr;
+        ptr[dev] = p;
+    }
+    return ptr[dev];
+}
+
+__global__ void k_noalloc_setup(NoAllocSetup S) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nx = S.inst.push.nx, np = S.inst.push.np;
+    if (k < nx) table_x(S.tables, k, S.tab_x[k], S.fel_ex[k]);
+    if (k < np) table_p(S.tables, k, S.tab_p[k], S.fel_eq[k]);
+    if (k == 0) {
+        *S.inst_out = S.inst;
+        S.off_out[0] = 0;
+        S.off_out[1] = S.inst.k1_tiles;
+        S.off_out[2] = 0;
+        S.off_out[3] = S.inst.k2_tiles;
+        for (int q = 0; q < kFelStateLen; ++q) S.fel_state[q] = 0.0;
+        if (S.fel_A) {
+            S.fel_state[kA] = S.fel_A[0];
+            S.fel_state[kA + 1] = S.fel_A[1];
+        }
+        S.fel_state[kN0] = S.n0;
+        for (int q = 0; q < 4; ++q) S.counters[q] = 0u;
+    }
+}
+
+__global__ void k_noalloc_scale(VpInst* inst, const double* m) {
+    // 2^(40 - e) with max|w| < 2^e, as vp_set_density sets it
+    const double wmax = m[8];
+    int e = 0;
+    if (wmax > 0.0 && isfinite(wmax)) {
+        (void)frexp(wmax, &e);
+        e = max(e, kFixBits - 126);
+    }
+    const bool bad = m[9] > 0.0;
+    inst->fix_scale = bad ? 0.0f : ldexpf(1.0f, kFixBits - e);
+    inst->fix_inv = ldexpf(1.0f, e - kFixBits);
+}
+
+__global__ void k_noalloc_finish(const double* m, const double* fel_state, const uint32_t* counters, double* fel_A,
+                                 int32_t* status) {
+    if (fel_A) {
+        fel_A[0] = fel_state[kA];
+        fel_A[1] = fel_state[kA + 1];
+    }
+    if (status) *status = m[9] > 0.0 ? -6 : (counters[kRangeFlag] ? -7 : 0);  // VP_ENONFINITE, VP_ERANGE, VP_OK
+}
+
+hipError_t launch_noalloc_setup(const NoAllocSetup& S, int nx, int np, hipStream_t s) {
+    const int n = max(nx, np), threads = 256;
+    hipLaunchKernelGGL(k_noalloc_setup, dim3((n + threads - 1) / threads), dim3(threads), 0, s, S);
+    return hipGetLastError();
+}
+hipError_t launch_noalloc_scale(VpInst* inst, const double* moments, hipStream_t s) {
+    hipLaunchKernelGGL(k_noalloc_scale, dim3(1), dim3(1), 0, s, inst, moments);
+    return hipGetLastError();
+}
+hipError_t launch_noalloc_finish(const double* moments, const double* fel_state, const uint32_t* counters,
+                                 double* fel_A, int32_t* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_noalloc_finish, dim3(1), dim3(1), 0, s, moments, fel_state, counters, fel_A, status);
+    return hipGetLastError();
 }
 
 // One launch of a per-step kernel.  With events (timing), hipExtLaunchKernel
