@@ -137,12 +137,20 @@ def bench_batched(binding, steps, count):
     # the GPU by themselves, which a batch does not need
     grids = [binding.grid_for(i) for i in insts]
     batch = binding.Batch(grids, [i.dt for i in insts])
-    batch.step(steps + (steps & 1))  # builds the graphs the timed run replays
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch.step(steps)
-    torch.cuda.synchronize()
-    sec = time.perf_counter() - t0
+
+    def timed():
+        batch.step(steps + (steps & 1))  # builds the graphs the timed run replays
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.step(steps)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    untuned_sec = timed()
+    untuned_cfg = batch.config()
+    tune_us = batch.autotune()
+    sec = timed()
+    cfg = batch.config()
     batch.close()
     for g in grids:
         g.close()
@@ -159,8 +167,45 @@ def bench_batched(binding, steps, count):
         g.close()
     return {"workload": f"batched_{count}_pendulum_64_1024", "steps": steps,
             "total_nodes": sum(i.nodes for i in insts), "value": work / sec,
-            "ms_per_step": 1e3 * sec / steps, "plain_value": work / plain_sec,
-            "speedup_vs_plain": plain_sec / sec}
+            "ms_per_step": 1e3 * sec / steps, "launch": cfg, "autotune_us_per_step": tune_us,
+            "untuned": {"value": work / untuned_sec, "ms_per_step": 1e3 * untuned_sec / steps, "launch": untuned_cfg},
+            "plain_value": work / plain_sec, "speedup_vs_plain": plain_sec / sec}
+
+
+def bench_phase4d(binding, n, npp, steps):
+    """The 2D2V phase space (x, y periodic, p_x, p_y in [-3, 3] open), n^2 x npp^2
+    nodes, coupled potential V = -cos x - 0.6 cos y - 0.4 cos(x - y), dt 0.05,
+    a noisy Gaussian start: steps timed after the same number untimed."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2007_12227_amd.inputs import Axis
+    axes = (Axis(-math.pi, math.pi, n, True), Axis(-math.pi, math.pi, n, True), Axis(-3.0, 3.0, npp, False),
+            Axis(-3.0, 3.0, npp, False))
+    g = binding.Grid4(axes)
+    g.set_hamiltonian(binding.H_PENDULUM, 1.0, 0.6, 0.4)
+    rng = np.random.default_rng(7)
+    x, y, px, py = (a.nodes() for a in axes)
+    w = (np.exp(-(py[:, None, None, None] ** 2 + px[None, :, None, None] ** 2) / (2 * 0.8 ** 2))
+         * np.exp(-(np.cos(y)[None, None, :, None] + np.cos(x)[None, None, None, :])) * rng.uniform(0.9, 1.1, g.shape))
+    g.set_density(w.astype(np.float32))
+    g.step(0.05, steps)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    g.step(0.05, steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    kus = g.step_timed(0.05, min(steps, 10))
+    nodes = n * n * npp * npp
+    g.close()
+    return {"workload": f"phase4d_coupled_{n}x{n}x{npp}x{npp}", "steps": steps, "nodes": nodes,
+            "value": nodes * steps / sec, "ms_per_step": 1e3 * sec / steps,
+            "kernels_us": {"k_deposit4": kus[0], "k_solve4 (four axes)": kus[1]}}
 
 
 def bench_served(binding, nreq, load, capacity, budget_gib):
@@ -266,6 +311,11 @@ def main():
     ap.add_argument("--fel-steps", type=int, default=2000)
     ap.add_argument("--spline-steps", type=int, default=1000,
                     help="steps of the quadratic and cubic basis lines")
+    ap.add_argument("--phase4d-n", type=int, default=48, help="2D2V line: nodes along x and y")
+    ap.add_argument("--phase4d-np", type=int, default=48, help="2D2V line: nodes along p_x and p_y")
+    ap.add_argument("--phase4d-steps", type=int, default=20)
+    ap.add_argument("--only", choices=("batched", "phase4d"), default=None,
+                    help="run only this line (profiling), printing its JSON object")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--serve-overload", type=float, default=1.2,
@@ -290,6 +340,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     binding.lib()
+    if args.only:
+        res = (bench_batched(binding, args.batch_steps, args.batch_count) if args.only == "batched"
+               else bench_phase4d(binding, args.phase4d_n, args.phase4d_np, args.phase4d_steps))
+        print(json.dumps(res), flush=True)
+        return
     inst = pendulum_band(args.n)
     N = inst.nodes
     basis = {"tent": binding.BASIS_TENT, "quadratic": binding.BASIS_QUADRATIC, "cubic": binding.BASIS_CUBIC}[args.basis]
@@ -379,6 +434,8 @@ def main():
         for name in ("quadratic", "cubic"):
             line[name] = bench_spline(binding, name, args.n, args.spline_steps, args.warmup)
             log(f"{name}: {line[name]}")
+        line["phase4d"] = bench_phase4d(binding, args.phase4d_n, args.phase4d_np, args.phase4d_steps)
+        log(f"phase4d: {line['phase4d']}")
         line["batched"] = bench_batched(binding, args.batch_steps, args.batch_count)
         log(f"batched: {line['batched']}")
         line["served"] = bench_served(binding, args.serve_requests, args.serve_load,

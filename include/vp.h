@@ -148,8 +148,9 @@ typedef struct {
 
 /* Bytes of device workspace a grid of this shape needs (0 if the axes are
  * invalid): three FP32 arrays of n_p*n_x weights (the state, ping-pong, and
- * the projection's right-hand side Delta^T w of eq. 10) plus per-axis push
- * tables and small per-tile buffers. */
+ * the projection's right-hand side Delta^T w of eq. 10), the cached push map
+ * (12 bytes per node, see vp_set_map_cache), per-axis push tables and small
+ * per-tile buffers. */
 size_t vp_workspace_bytes(const vp_axis* x, const vp_axis* p);
 
 /* Create a grid: the fixed lattice of nodes z_j of the expansion (eq. 4) with
@@ -231,6 +232,14 @@ int vp_moments(vp_grid* g, vp_moments_t* out);
 int vp_set_tiles(vp_grid* g, const vp_tiles* t);
 int vp_get_tiles(const vp_grid* g, vp_tiles* t);
 
+/* For a Hamiltonian that depends neither on the state nor on the time (free,
+ * rotation, pendulum) the push of every node, and so the node-to-destination
+ * map and the fractions that weigh the overlaps of eq. 9, is the same every
+ * step.  With the cache on (the default) it is formed once per plan into the
+ * workspace (12 bytes per node) and the deposit reads it instead of pushing;
+ * results are bitwise the same either way.  The FEL always pushes. */
+int vp_set_map_cache(vp_grid* g, int32_t on);
+
 /* Launch mode of vp_step: use_graph != 0 replays the per-step kernels from a
  * HIP graph of several steps; 0 launches each kernel directly ("plain"). */
 int vp_set_launch(vp_grid* g, int32_t use_graph);
@@ -256,6 +265,19 @@ int vp_autotune(vp_grid* g, double dt, double* best_us);
  * stream (VP_EINVAL otherwise); the batch uses it.  The grids must outlive the
  * batch and must not be stepped on their own while it exists (VP_ESTATE). */
 int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch** out);
+/* Time candidate launch configurations on the batch itself and keep the
+ * fastest: every grid with its own deposit tile shape, or every grid with one
+ * shape (64x32x256 .. 128x128x1024, cut to its lattice), each with one
+ * deposit workgroup per tile or a persistent deposit (as many workgroups as
+ * the device holds at once, looping over the tiles).  The grids' states are
+ * restored.  best_us receives the time per batch step of the choice.  The
+ * choice is cached per composition class (the multiset of kind, basis and
+ * half-octave axis lengths); best_us == NULL applies a cached choice without
+ * timing (VP_ESTATE if there is none). */
+int vp_batch_autotune(vp_batch* b, double* best_us);
+/* The batch's current launch: deposit workgroups per launch (0: one per
+ * tile), threads per deposit workgroup, deposit tiles in the launch list. */
+int vp_batch_config(const vp_batch* b, int32_t* deposit_grid, int32_t* deposit_threads, int32_t* tiles);
 /* nsteps steps of eq. 10 for every grid of the batch, enqueued on its stream.
  * VP_ERANGE, without stepping, once a completed earlier batch step has set the
  * range flag of any of its grids (vp_moments of each grid names which). */
@@ -292,6 +314,70 @@ int vp_batch_destroy(vp_batch* b);
 int vp_step_noalloc(const vp_axis* x, const vp_axis* p, const vp_hamiltonian* h, int32_t basis, double dt,
                     int64_t nsteps, const float* w_in, float* w_out, double fel_n0, double* fel_A,
                     int32_t* status, void* stream);
+
+/* ---- Four-dimensional phase space (x, y, p_x, p_y) ----
+ * The method carried to 2D2V (Sec. "An Algorithm Based on Phase Space Density
+ * Conservation": only Lambda and Delta change with the dimension): tents on
+ * every axis, f = sum_j w_j prod_d Lambda(z_d - z_{j,d}); the overlaps of
+ * eq. 9 are products of four B3 factors (a 4^4 = 256-tap deposit) and the mass
+ * matrix of eq. 8 the Kronecker product of four tridiagonal ones (a line
+ * solve per axis).  x and y are periodic, the momenta open (as in 2-D).
+ * Weights are [n_py][n_px][n_y][n_x] floats, x fastest.  Conventions as
+ * above (status codes, caller-owned workspace and stream, vp_last_error). */
+typedef struct vp4_grid vp4_grid;
+
+/* axes: x, y (periodic), p_x, p_y (open); 4 <= n <= 4096 per axis, at most
+ * 2^28 nodes.  workspace: at least vp4_workspace_bytes(axes), 256-byte aligned. */
+typedef struct {
+    vp_axis axes[4];
+    void* workspace;
+    size_t workspace_bytes;
+    void* stream;
+} vp4_grid_desc;
+
+/* kind VP_H_FREE: x' = p_x, y' = p_y.  kind VP_H_PENDULUM: H = |p|^2/2 + V with
+ * V = -a cos x - b cos y - c cos(x - y) (c = 0: two uncoupled pendulums),
+ * drift dt/2, kick dt with -grad V at the half-drift point, drift dt/2. */
+typedef struct {
+    int32_t kind;
+    double a, b, c;
+} vp4_hamiltonian;
+
+/* FP64 sums as for vp_moments_t (cell = h_x h_y h_px h_py): energy integrates
+ * H over the tent expansion (h^2/6 for p^2, sinc^2(h/2) per cos factor). */
+typedef struct {
+    double sum_w, mass, neg_mass, l1, entropy, mean_px, mean_py, energy;
+    int64_t step;
+    int64_t nonfinite;
+} vp4_moments_t;
+
+/* Bytes of device workspace for these axes (0 if invalid): three FP32 state
+ * arrays, push tables, per-tile source boxes and reduction buffers. */
+size_t vp4_workspace_bytes(const vp_axis axes[4]);
+/* Create / destroy a 2D2V grid on the caller's workspace and stream (eq. 4's
+ * lattice in four dimensions).  VP_EINVAL for invalid axes, VP_EUNSUPPORTED
+ * unless x, y are periodic and the momenta open, VP_ENOMEM for a small workspace. */
+int vp4_create_grid(const vp4_grid_desc* desc, vp4_grid** out);
+int vp4_destroy_grid(vp4_grid* g);
+/* The Hamiltonian and its pusher (see vp4_hamiltonian); VP_EINVAL otherwise. */
+int vp4_set_hamiltonian(vp4_grid* g, const vp4_hamiltonian* h);
+/* Deposit tile (nodes along x, y, p_x, p_y; at least 4 or the whole axis;
+ * 8 bytes of LDS per node of the tile).  Results do not depend on it. */
+int vp4_set_tiles(vp4_grid* g, const int32_t tile[4]);
+/* Set / copy out the weights of eq. 4 (device pointer if on_device, else host).
+ * Set: VP_ENONFINITE for a NaN/Inf weight; records max|w| (the deposit's
+ * fixed-point exponent).  Get: waits; VP_ERANGE (after copying) if a deposit
+ * cell left the fixed-point range. */
+int vp4_set_density(vp4_grid* g, const float* w, int32_t on_device);
+int vp4_get_density(vp4_grid* g, float* w, int32_t on_device);
+/* nsteps steps of eq. 10 in 2D2V on the grid's stream: push, 256-tap
+ * deposit, the four line solves.  VP_ESTATE before density and Hamiltonian. */
+int vp4_step(vp4_grid* g, double dt, int64_t nsteps);
+/* As vp4_step, with the mean microseconds of the deposit (us[0]) and of the
+ * four solves (us[1]) per step, from events recorded with the kernels. */
+int vp4_step_timed(vp4_grid* g, double dt, int64_t nsteps, double us[2]);
+/* Diagnostics (vp4_moments_t); waits.  VP_ENONFINITE / VP_ERANGE after filling *out. */
+int vp4_moments(vp4_grid* g, vp4_moments_t* out);
 
 /* Status text and the calling thread's last error message. */
 const char* vp_status_string(int status);

@@ -51,6 +51,22 @@ class Moments(C.Structure):
     _fields_ = [(f, C.c_double) for f in MOMENT_FIELDS] + [("step", C.c_int64), ("nonfinite", C.c_int64)]
 
 
+class Grid4Desc(C.Structure):
+    _fields_ = [("axes", Axis * 4), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("stream", C.c_void_p)]
+
+
+class Hamiltonian4(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("a", C.c_double), ("b", C.c_double), ("c", C.c_double)]
+
+
+MOMENT4_FIELDS = ("sum_w", "mass", "neg_mass", "l1", "entropy", "mean_px", "mean_py", "energy")
+
+
+class Moments4(C.Structure):
+    _fields_ = [(f, C.c_double) for f in MOMENT4_FIELDS] + [("step", C.c_int64), ("nonfinite", C.c_int64)]
+
+
 class Tiles(C.Structure):
     _fields_ = [("k1_tx", C.c_int32), ("k1_ty", C.c_int32), ("k1_threads", C.c_int32)]
 
@@ -94,6 +110,8 @@ def lib(load_torch: bool = True):
     L.vp_batch_create.argtypes = [P(C.c_void_p), C.c_int32, P(C.c_double), P(C.c_void_p)]
     L.vp_batch_step.argtypes = [C.c_void_p, C.c_int64]
     L.vp_batch_destroy.argtypes = [C.c_void_p]
+    L.vp_batch_autotune.argtypes = [C.c_void_p, P(C.c_double)]
+    L.vp_batch_config.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
     L.vp_status_string.restype = C.c_char_p
     L.vp_status_string.argtypes = [C.c_int]
     L.vp_last_error.restype = C.c_char_p
@@ -101,10 +119,22 @@ def lib(load_torch: bool = True):
                                      C.c_double, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P(C.c_int32)]
     L.vp_set_basis.argtypes = [C.c_void_p, C.c_int32]
     L.vp_set_fixed_point.argtypes = [C.c_void_p, C.c_int32]
+    L.vp_set_map_cache.argtypes = [C.c_void_p, C.c_int32]
     L.vp_step_noalloc.argtypes = [P(Axis), P(Axis), P(Hamiltonian), C.c_int32, C.c_double, C.c_int64,
                                   C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.vp4_workspace_bytes.restype = C.c_size_t
+    L.vp4_workspace_bytes.argtypes = [P(Axis)]
+    L.vp4_create_grid.argtypes = [P(Grid4Desc), P(C.c_void_p)]
+    L.vp4_destroy_grid.argtypes = [C.c_void_p]
+    L.vp4_set_hamiltonian.argtypes = [C.c_void_p, P(Hamiltonian4)]
+    L.vp4_set_tiles.argtypes = [C.c_void_p, P(C.c_int32)]
+    L.vp4_set_density.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
+    L.vp4_get_density.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
+    L.vp4_step.argtypes = [C.c_void_p, C.c_double, C.c_int64]
+    L.vp4_step_timed.argtypes = [C.c_void_p, C.c_double, C.c_int64, P(C.c_double)]
+    L.vp4_moments.argtypes = [C.c_void_p, P(Moments4)]
     for name in declared_functions():
-        if name not in ("vp_workspace_bytes", "vp_status_string", "vp_last_error"):
+        if name not in ("vp_workspace_bytes", "vp4_workspace_bytes", "vp_status_string", "vp_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -243,6 +273,10 @@ class Grid:
         check(lib().vp_get_tiles(self._h, C.byref(t)))
         return {"k1": (t.k1_tx, t.k1_ty), "threads": t.k1_threads}
 
+    def set_map_cache(self, on: bool):
+        """Cache the push of a static Hamiltonian (vp_set_map_cache)."""
+        check(lib().vp_set_map_cache(self._h, int(bool(on))))
+
     def set_launch(self, use_graph: bool):
         check(lib().vp_set_launch(self._h, int(bool(use_graph))))
 
@@ -271,6 +305,21 @@ class Batch:
     def step(self, n: int = 1):
         check(lib().vp_batch_step(self._h, int(n)))
 
+    def autotune(self, cached: bool = False) -> float:
+        """Pick the batch's launch configuration by timing (vp_batch_autotune);
+        cached=True applies a choice made for the same composition class."""
+        if cached:
+            check(lib().vp_batch_autotune(self._h, None))
+            return 0.0
+        us = C.c_double()
+        check(lib().vp_batch_autotune(self._h, C.byref(us)))
+        return us.value
+
+    def config(self) -> dict:
+        g, t, n = C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib().vp_batch_config(self._h, C.byref(g), C.byref(t), C.byref(n)))
+        return {"deposit_grid": g.value, "deposit_threads": t.value, "deposit_tiles": n.value}
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             check(lib().vp_batch_destroy(self._h))
@@ -294,6 +343,72 @@ def step_noalloc(x, p, ham, dt, nsteps, w_in, w_out, basis=BASIS_TENT, fel_n0=0.
     check(lib().vp_step_noalloc(C.byref(axis(x)), C.byref(axis(p)), C.byref(hamiltonian(ham)), int(basis),
                                 float(dt), int(nsteps), ptr(w_in), ptr(w_out), float(fel_n0), ptr(fel_A),
                                 ptr(status), _stream_handle(stream)))
+
+
+def workspace_bytes4(axes) -> int:
+    arr = (Axis * 4)(*[axis(a) for a in axes])
+    return int(lib().vp4_workspace_bytes(arr))
+
+
+class Grid4:
+    """A four-dimensional (x, y, p_x, p_y) lattice; weights [n_py][n_px][n_y][n_x]."""
+
+    def __init__(self, axes, stream=None, device="cuda"):
+        import torch
+        self.axes = tuple(axes)
+        self.shape = tuple(a.n for a in reversed(self.axes))
+        nbytes = workspace_bytes4(self.axes)
+        if nbytes == 0:
+            check(VP_EINVAL)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self._ws.data_ptr()
+        ptr = base + (-base) % 256
+        desc = Grid4Desc((Axis * 4)(*[axis(a) for a in self.axes]), C.c_void_p(ptr), nbytes, _stream_handle(stream))
+        h = C.c_void_p()
+        check(lib().vp4_create_grid(C.byref(desc), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            check(lib().vp4_destroy_grid(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_hamiltonian(self, kind: int, a: float = 0.0, b: float = 0.0, c: float = 0.0):
+        check(lib().vp4_set_hamiltonian(self._h, C.byref(Hamiltonian4(int(kind), float(a), float(b), float(c)))))
+
+    def set_tiles(self, tile):
+        check(lib().vp4_set_tiles(self._h, (C.c_int32 * 4)(*[int(v) for v in tile])))
+
+    def set_density(self, w):
+        a = np.ascontiguousarray(w, dtype=np.float32)
+        assert a.shape == self.shape, (a.shape, self.shape)
+        check(lib().vp4_set_density(self._h, a.ctypes.data_as(C.c_void_p), 0))
+
+    def density(self) -> np.ndarray:
+        out = np.empty(self.shape, dtype=np.float32)
+        check(lib().vp4_get_density(self._h, out.ctypes.data_as(C.c_void_p), 0))
+        return out
+
+    def step(self, dt: float, n: int = 1):
+        check(lib().vp4_step(self._h, float(dt), int(n)))
+
+    def step_timed(self, dt: float, n: int) -> tuple[float, float]:
+        us = (C.c_double * 2)()
+        check(lib().vp4_step_timed(self._h, float(dt), int(n), us))
+        return us[0], us[1]
+
+    def moments(self) -> dict:
+        m = Moments4()
+        check(lib().vp4_moments(self._h, C.byref(m)))
+        d = {f: getattr(m, f) for f in MOMENT4_FIELDS}
+        d["step"], d["nonfinite"] = m.step, m.nonfinite
+        return d
 
 
 def grid_for(inst, stream=None) -> Grid:

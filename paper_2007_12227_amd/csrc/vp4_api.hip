@@ -1,0 +1,472 @@
+// vp4_api.hip -- host runtime of the four-dimensional (2D2V) phase space:
+// handles, validation, push tables, host-planned source boxes and the step
+// sequence of k_deposit4 and the four k_solve4 launches.  See include/vp.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/vp.h"
+#include "vp_internal.h"
+
+using namespace vp;
+
+namespace {
+
+int fail4(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    return set_error(code, buf);
+}
+
+#define HIP_TRY4(expr)                                                                       \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail4(VP_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+bool axis4_ok(const vp_axis& a) {
+    return a.n >= 4 && a.n <= (1 << 12) && isfinite(a.lo) && isfinite(a.hi) && a.hi > a.lo;
+}
+double spacing4(const vp_axis& a) { return (a.hi - a.lo) / (a.periodic ? a.n : a.n - 1); }
+
+constexpr int kMinTile4 = 4;        // deposit tiles are at least this long on every axis (box capacity)
+constexpr size_t kMaxNodes4 = (size_t)1 << 28;
+
+struct Layout4 {
+    size_t w0, w1, b, tab[4], boxes, inst, counters, partials, moments, total;
+    size_t nodes, box_cap;
+};
+
+Layout4 layout4(const vp_axis* ax) {
+    Layout4 L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    L.nodes = (size_t)ax[0].n * ax[1].n * ax[2].n * ax[3].n;
+    L.box_cap = 1;
+    for (int d = 0; d < 4; ++d) L.box_cap *= (size_t)((ax[d].n + kMinTile4 - 1) / kMinTile4);
+    L.w0 = take(L.nodes * 4);
+    L.w1 = take(L.nodes * 4);
+    L.b = take(L.nodes * 4);
+    for (int d = 0; d < 4; ++d) L.tab[d] = take((size_t)ax[d].n * 16);
+    L.boxes = take(L.box_cap * 2 * sizeof(int4));
+    L.inst = take(sizeof(Vp4Inst));
+    L.counters = take(4 * sizeof(uint32_t));
+    L.partials = take((size_t)kReduceBlocks * kMoments * 8);
+    L.moments = take(kMoments * 8);
+    L.total = o;
+    return L;
+}
+
+bool axes4_ok(const vp_axis* ax) {
+    if (!ax) return false;
+    for (int d = 0; d < 4; ++d)
+        if (!axis4_ok(ax[d])) return false;
+    return (size_t)ax[0].n * ax[1].n * ax[2].n * ax[3].n <= kMaxNodes4;
+}
+
+// Starting deposit tile: 16 x 16 x 8 x 8 nodes (128 KiB of LDS), cut to the lattice.
+void default_tiles4(const vp_axis* ax, int32_t T[4]) {
+    const int want[4] = {16, 16, 8, 8};
+    for (int d = 0; d < 4; ++d) T[d] = std::min(want[d], ax[d].n);
+}
+
+size_t lds4(const int32_t T[4]) { return (size_t)T[0] * T[1] * T[2] * T[3] * sizeof(long long); }
+
+}  // namespace
+
+struct vp4_grid {
+    vp_axis ax[4]{};
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    Layout4 L{};
+    Vp4Inst inst{};
+    vp4_hamiltonian ham{};
+    int32_t T[4]{};
+    bool has_ham = false, has_density = false, plan_valid = false;
+    double plan_dt = 0.0;
+    int parity = 0;
+    int64_t step = 0;
+    template <class X> X* at(size_t off) const { return reinterpret_cast<X*>(ws + off); }
+};
+
+namespace {
+
+size_t g_max_lds4 = 64 * 1024;
+
+void raise_lds4() {
+    static bool done = false;
+    if (done) return;
+    done = true;
+    int dev = 0, lim = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return;
+    if (lim <= (int)g_max_lds4) return;
+    for (int push : {kPush4Free, kPush4Potential})
+        if (hipFuncSetAttribute(deposit4_kernel(push), hipFuncAttributeMaxDynamicSharedMemorySize, lim - 1024) !=
+            hipSuccess)
+            return;
+    g_max_lds4 = (size_t)(lim - 1024);
+}
+
+// Conservative range [lo, hi) of source indices along an axis whose moved
+// tents (first tap at floor(i + d) - 1) can reach destination nodes [O, O + E),
+// for displacements d in [dmin, dmax]: floor(i + d) in [O - 2, O + E], one
+// more cell of margin on each side for rounding.
+void source_range(int O, int E, double dmin, double dmax, int* lo, int* hi) {
+    *lo = (int)floor((double)O - 3.0 - dmax);
+    *hi = (int)ceil((double)(O + E) + 2.0 - dmin);
+}
+
+// Push tables and source boxes of step dt, uploaded with the descriptor.
+int plan4(vp4_grid* g, double dt) {
+    const vp_axis* ax = g->ax;
+    double h[4];
+    for (int d = 0; d < 4; ++d) h[d] = spacing4(ax[d]);
+    Vp4Inst& I = g->inst;
+    const vp4_hamiltonian& H = g->ham;
+    for (int d = 0; d < 4; ++d) {
+        I.n[d] = ax[d].n;
+        I.T[d] = g->T[d];
+        I.tiles[d] = (ax[d].n + g->T[d] - 1) / g->T[d];
+    }
+    I.total_tiles = I.tiles[0] * I.tiles[1] * I.tiles[2] * I.tiles[3];
+    I.kind = H.kind == VP_H_FREE ? kPush4Free : kPush4Potential;
+    I.parity0 = 0;
+    const double pot = H.kind == VP_H_FREE ? 0.0 : 1.0;
+    I.ax = (float)(pot * H.a * dt / h[2]);
+    I.cx = (float)(pot * H.c * dt / h[2]);
+    I.by = (float)(pot * H.b * dt / h[3]);
+    I.cy = (float)(pot * H.c * dt / h[3]);
+    I.kdx = (float)(h[2] * dt / (2.0 * h[0]));
+    I.kdy = (float)(h[3] * dt / (2.0 * h[1]));
+    // tables: the coordinate axes (sin, cos of the node), the momentum axes
+    // (drift in cells as a hi + lo pair, sin and cos of the half-drift phase)
+    std::vector<float4> tab[4];
+    for (int d = 0; d < 2; ++d) {
+        tab[d].resize(ax[d].n);
+        for (int i = 0; i < ax[d].n; ++i) {
+            const double z = ax[d].lo + i * h[d];
+            tab[d][i] = make_float4((float)sin(z), (float)cos(z), 0.f, 0.f);
+        }
+    }
+    for (int d = 2; d < 4; ++d) {
+        tab[d].resize(ax[d].n);
+        for (int j = 0; j < ax[d].n; ++j) {
+            const double p = ax[d].lo + j * h[d];
+            const double drift = p * dt / h[d - 2], q = 0.5 * dt * p;
+            const float hi = (float)drift, lo = (float)(drift - (double)hi);
+            tab[d][j] = make_float4(hi, lo, (float)sin(q), (float)cos(q));
+        }
+    }
+    // source boxes: kick bounds in cells, then per axis pair the momentum
+    // rows that can reach the tile and the coordinates their drift allows
+    const double Kx = fabs((double)I.ax) + fabs((double)I.cx), Ky = fabs((double)I.by) + fabs((double)I.cy);
+    std::vector<int4> boxes(2 * (size_t)I.total_tiles);
+    for (int t = 0; t < I.total_tiles; ++t) {
+        int q = t, c[4];
+        for (int d = 0; d < 3; ++d) {
+            c[d] = q % I.tiles[d];
+            q /= I.tiles[d];
+        }
+        c[3] = q;
+        int lo[4], hi[4];
+        for (int m = 0; m < 2; ++m) {  // m = 0: (x, px); m = 1: (y, py)
+            const int dp = m + 2, dc = m;
+            const double K = m == 0 ? Kx : Ky, kd = m == 0 ? I.kdx : I.kdy;
+            const int Op = c[dp] * I.T[dp], Ep = std::min(I.T[dp], I.n[dp] - Op);
+            source_range(Op, Ep, -K, K, &lo[dp], &hi[dp]);
+            lo[dp] = std::max(lo[dp], 0);
+            hi[dp] = std::min(hi[dp], I.n[dp]);
+            if (hi[dp] <= lo[dp]) {
+                lo[dp] = hi[dp] = 0;
+                lo[dc] = hi[dc] = 0;
+                continue;
+            }
+            const double pa = ax[dp].lo + lo[dp] * h[dp], pb = ax[dp].lo + (hi[dp] - 1) * h[dp];
+            const double da = pa * dt / h[dc], db = pb * dt / h[dc];
+            const double dmin = std::min(da, db) - fabs(kd) * K, dmax = std::max(da, db) + fabs(kd) * K;
+            const int Oc = c[dc] * I.T[dc], Ec = std::min(I.T[dc], I.n[dc] - Oc);
+            source_range(Oc, Ec, dmin, dmax, &lo[dc], &hi[dc]);
+            if (hi[dc] - lo[dc] > I.n[dc]) hi[dc] = lo[dc] + I.n[dc];  // every column once (periodic)
+        }
+        boxes[2 * (size_t)t] = make_int4(lo[0], hi[0], lo[1], hi[1]);
+        boxes[2 * (size_t)t + 1] = make_int4(lo[2], hi[2], lo[3], hi[3]);
+    }
+    for (int d = 0; d < 4; ++d) {
+        I.tab[d] = g->at<float4>(g->L.tab[d]);
+        HIP_TRY4(hipMemcpyAsync(g->at<float4>(g->L.tab[d]), tab[d].data(), tab[d].size() * sizeof(float4),
+                                hipMemcpyHostToDevice, g->stream));
+    }
+    I.boxes = g->at<int4>(g->L.boxes);
+    HIP_TRY4(hipMemcpyAsync(g->at<int4>(g->L.boxes), boxes.data(), boxes.size() * sizeof(int4), hipMemcpyHostToDevice,
+                            g->stream));
+    HIP_TRY4(hipMemcpyAsync(g->at<Vp4Inst>(g->L.inst), &I, sizeof(Vp4Inst), hipMemcpyHostToDevice, g->stream));
+    HIP_TRY4(hipStreamSynchronize(g->stream));  // the host vectors may go
+    g->plan_dt = dt;
+    g->plan_valid = true;
+    return VP_OK;
+}
+
+int reduce4(vp4_grid* g, int mode) {
+    Reduce4Args R{};
+    R.w = g->at<float>(g->parity ? g->L.w1 : g->L.w0);
+    for (int d = 0; d < 4; ++d) {
+        R.n[d] = g->ax[d].n;
+        R.lo[d] = g->ax[d].lo;
+        R.h[d] = spacing4(g->ax[d]);
+    }
+    R.mode = mode;
+    const bool pot = g->has_ham && g->ham.kind != VP_H_FREE;
+    R.a = pot ? g->ham.a : 0.0;
+    R.b = pot ? g->ham.b : 0.0;
+    R.c = pot ? g->ham.c : 0.0;
+    for (int d = 0; d < 2; ++d) {
+        const double y = 0.5 * R.h[d], sc = sin(y) / y;
+        R.sinc2[d] = sc * sc;
+    }
+    R.partials = g->at<double>(g->L.partials);
+    R.counter = g->at<uint32_t>(g->L.counters) + 1;
+    R.out = g->at<double>(g->L.moments);
+    HIP_TRY4(launch_reduce4(R, g->stream));
+    return VP_OK;
+}
+
+// One step: the deposit reads w[par] into w[par ^ 1], the solves alternate
+// with b and end in w[par ^ 1].  ev (optional, 4 events): start and end of
+// the deposit, start and end of the four solves.
+int enqueue_step4(vp4_grid* g, int par, hipEvent_t* ev) {
+    const Vp4Inst& I = g->inst;
+    float* D = g->at<float>(par ? g->L.w0 : g->L.w1);
+    float* Bf = g->at<float>(g->L.b);
+    Launch4Args A{};
+    A.inst = g->at<Vp4Inst>(g->L.inst);
+    A.parity = par;
+    A.push = I.kind;
+    A.total = I.total_tiles;
+    A.dst = D;
+    HIP_TRY4(launch_deposit4(A, lds4(g->T), g->stream, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
+    const float* src[4] = {D, Bf, D, Bf};
+    float* dst[4] = {Bf, D, Bf, D};
+    for (int axis = 0; axis < 4; ++axis) {
+        size_t lines = 1;
+        for (int d = 0; d < 4; ++d)
+            if (d != axis) lines *= (size_t)I.n[d];
+        Launch4Args S{};
+        S.inst = A.inst;
+        S.axis = axis;
+        S.total = (int32_t)lines;
+        S.src = src[axis];
+        S.dst = dst[axis];
+        HIP_TRY4(launch_solve4(S, g->stream, ev && axis == 0 ? ev[2] : nullptr, ev && axis == 3 ? ev[3] : nullptr));
+    }
+    return VP_OK;
+}
+
+int prepare4(vp4_grid* g, double dt) {
+    if (!g->has_ham || !g->has_density) return fail4(VP_ESTATE, "set the Hamiltonian and the density before stepping");
+    if (!isfinite(dt)) return fail4(VP_EINVAL, "dt must be finite");
+    if (!g->plan_valid || g->plan_dt != dt) return plan4(g, dt);
+    return VP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vp4_workspace_bytes(const vp_axis axes[4]) {
+    if (!axes4_ok(axes)) return 0;
+    return layout4(axes).total;
+}
+
+int vp4_create_grid(const vp4_grid_desc* d, vp4_grid** out) {
+    if (!d || !out) return fail4(VP_EINVAL, "null argument");
+    *out = nullptr;
+    if (!axes4_ok(d->axes)) return fail4(VP_EINVAL, "invalid axes (4 <= n <= 4096, hi > lo, finite, <= 2^28 nodes)");
+    if (!d->axes[0].periodic || !d->axes[1].periodic || d->axes[2].periodic || d->axes[3].periodic)
+        return fail4(VP_EUNSUPPORTED, "x and y must be periodic, the momenta open");
+    const Layout4 L = layout4(d->axes);
+    if (!d->workspace) return fail4(VP_ENOMEM, "no workspace");
+    if (d->workspace_bytes < L.total) return fail4(VP_ENOMEM, "workspace of %zu bytes, need %zu", d->workspace_bytes, L.total);
+    if (reinterpret_cast<uintptr_t>(d->workspace) % 256) return fail4(VP_EINVAL, "workspace must be 256-byte aligned");
+    raise_lds4();
+    vp4_grid* g = new vp4_grid();
+    for (int k = 0; k < 4; ++k) g->ax[k] = d->axes[k];
+    g->stream = reinterpret_cast<hipStream_t>(d->stream);
+    g->ws = reinterpret_cast<char*>(d->workspace);
+    g->L = L;
+    default_tiles4(g->ax, g->T);
+    Vp4Inst& I = g->inst;
+    I.w[0] = g->at<float>(L.w0);
+    I.w[1] = g->at<float>(L.w1);
+    I.counters = g->at<uint32_t>(L.counters);
+    hipError_t e = hipMemsetAsync(g->at<uint32_t>(L.counters), 0, 4 * sizeof(uint32_t), g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) {
+        delete g;
+        return fail4(VP_EHIP, "grid initialisation: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return VP_OK;
+}
+
+int vp4_destroy_grid(vp4_grid* g) {
+    if (!g) return VP_OK;
+    (void)hipStreamSynchronize(g->stream);
+    delete g;
+    return VP_OK;
+}
+
+int vp4_set_hamiltonian(vp4_grid* g, const vp4_hamiltonian* h) {
+    if (!g || !h) return fail4(VP_EINVAL, "null argument");
+    if (h->kind != VP_H_FREE && h->kind != VP_H_PENDULUM)
+        return fail4(VP_EINVAL, "kind %d: the 2D2V phase space takes VP_H_FREE or VP_H_PENDULUM", h->kind);
+    if (!isfinite(h->a) || !isfinite(h->b) || !isfinite(h->c)) return fail4(VP_EINVAL, "non-finite parameter");
+    g->ham = *h;
+    g->has_ham = true;
+    g->plan_valid = false;
+    return VP_OK;
+}
+
+int vp4_set_tiles(vp4_grid* g, const int32_t T[4]) {
+    if (!g || !T) return fail4(VP_EINVAL, "null argument");
+    int32_t n[4];
+    for (int d = 0; d < 4; ++d) {
+        if (T[d] < kMinTile4 && T[d] != g->ax[d].n) return fail4(VP_EINVAL, "tile below %d nodes on axis %d", kMinTile4, d);
+        n[d] = std::min(T[d], g->ax[d].n);
+    }
+    if (lds4(n) > g_max_lds4) return fail4(VP_EINVAL, "deposit tile needs %zu bytes of LDS (limit %zu)", lds4(n), g_max_lds4);
+    for (int d = 0; d < 4; ++d) g->T[d] = n[d];
+    g->plan_valid = false;
+    return VP_OK;
+}
+
+int vp4_set_density(vp4_grid* g, const float* w, int32_t on_device) {
+    if (!g || !w) return fail4(VP_EINVAL, "null argument");
+    float* dst = g->at<float>(g->parity ? g->L.w1 : g->L.w0);
+    HIP_TRY4(hipMemcpyAsync(dst, w, g->L.nodes * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                            g->stream));
+    int rc = reduce4(g, 2);
+    if (rc) return rc;
+    double m[kMoments];
+    HIP_TRY4(hipMemcpyAsync(m, g->at<double>(g->L.moments), sizeof m, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY4(hipStreamSynchronize(g->stream));
+    if (m[9] > 0.0) {
+        g->has_density = false;
+        return fail4(VP_ENONFINITE, "%lld non-finite weights in the density", (long long)m[9]);
+    }
+    int e = 0;
+    if (m[8] > 0.0) {
+        (void)frexp(m[8], &e);
+        e = std::max(e, kFixBits - 126);
+    }
+    g->inst.fix_scale = ldexpf(1.0f, kFixBits - e);
+    g->inst.fix_inv = ldexpf(1.0f, e - kFixBits);
+    g->plan_valid = false;
+    HIP_TRY4(hipMemsetAsync(g->at<uint32_t>(g->L.counters) + kRangeFlag, 0, sizeof(uint32_t), g->stream));
+    HIP_TRY4(hipStreamSynchronize(g->stream));
+    g->has_density = true;
+    g->step = 0;
+    return VP_OK;
+}
+
+int vp4_get_density(vp4_grid* g, float* w, int32_t on_device) {
+    if (!g || !w) return fail4(VP_EINVAL, "null argument");
+    if (!g->has_density) return fail4(VP_ESTATE, "no density set");
+    HIP_TRY4(hipMemcpyAsync(w, g->at<float>(g->parity ? g->L.w1 : g->L.w0), g->L.nodes * 4,
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, g->stream));
+    uint32_t flag = 0;
+    HIP_TRY4(hipMemcpyAsync(&flag, g->at<uint32_t>(g->L.counters) + kRangeFlag, sizeof flag, hipMemcpyDeviceToHost,
+                            g->stream));
+    HIP_TRY4(hipStreamSynchronize(g->stream));
+    if (flag) return fail4(VP_ERANGE, "a deposit cell sum left the fixed-point range: the weights are not valid");
+    return VP_OK;
+}
+
+int vp4_step(vp4_grid* g, double dt, int64_t nsteps) {
+    if (!g) return fail4(VP_EINVAL, "null grid");
+    if (nsteps < 0) return fail4(VP_EINVAL, "negative step count");
+    int rc = prepare4(g, dt);
+    if (rc) return rc;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        rc = enqueue_step4(g, (int)((g->parity + s) & 1), nullptr);
+        if (rc) return rc;
+    }
+    g->parity = (int)((g->parity + nsteps) & 1);
+    g->step += nsteps;
+    return VP_OK;
+}
+
+int vp4_step_timed(vp4_grid* g, double dt, int64_t nsteps, double us[2]) {
+    if (!g || !us) return fail4(VP_EINVAL, "null argument");
+    if (nsteps <= 0) return fail4(VP_EINVAL, "need at least one step");
+    int rc = prepare4(g, dt);
+    if (rc) return rc;
+    std::vector<hipEvent_t> ev((size_t)4 * nsteps, nullptr);
+    auto release = [&]() {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            release();
+            return fail4(VP_EHIP, "hipEventCreate failed");
+        }
+    for (int64_t s = 0; s < nsteps && rc == VP_OK; ++s) rc = enqueue_step4(g, (int)((g->parity + s) & 1), &ev[4 * s]);
+    double t[2] = {0.0, 0.0};
+    if (rc == VP_OK && hipEventSynchronize(ev.back()) != hipSuccess) rc = fail4(VP_EHIP, "hipEventSynchronize failed");
+    for (int64_t s = 0; s < nsteps && rc == VP_OK; ++s)
+        for (int k = 0; k < 2; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[4 * s + 2 * k], ev[4 * s + 2 * k + 1]) != hipSuccess) {
+                rc = fail4(VP_EHIP, "hipEventElapsedTime failed");
+                break;
+            }
+            t[k] += ms;
+        }
+    release();
+    if (rc) return rc;
+    for (int k = 0; k < 2; ++k) us[k] = 1000.0 * t[k] / nsteps;
+    g->parity = (int)((g->parity + nsteps) & 1);
+    g->step += nsteps;
+    return VP_OK;
+}
+
+int vp4_moments(vp4_grid* g, vp4_moments_t* out) {
+    if (!g || !out) return fail4(VP_EINVAL, "null argument");
+    if (!g->has_density) return fail4(VP_ESTATE, "no density set");
+    int rc = reduce4(g, 0);
+    if (rc) return rc;
+    double m[kMoments];
+    uint32_t flag = 0;
+    HIP_TRY4(hipMemcpyAsync(m, g->at<double>(g->L.moments), sizeof m, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY4(hipMemcpyAsync(&flag, g->at<uint32_t>(g->L.counters) + kRangeFlag, sizeof flag, hipMemcpyDeviceToHost,
+                            g->stream));
+    HIP_TRY4(hipStreamSynchronize(g->stream));
+    double cell = 1.0;
+    for (int d = 0; d < 4; ++d) cell *= spacing4(g->ax[d]);
+    memset(out, 0, sizeof *out);
+    out->sum_w = m[0];
+    out->mass = cell * m[0];
+    out->neg_mass = -cell * m[1];
+    out->l1 = cell * m[2];
+    out->entropy = -cell * m[3];
+    out->mean_px = m[0] != 0.0 ? m[4] / m[0] : 0.0;
+    out->mean_py = m[0] != 0.0 ? m[5] / m[0] : 0.0;
+    out->energy = cell * m[6];
+    out->step = g->step;
+    out->nonfinite = (int64_t)m[9];
+    if (out->nonfinite) return fail4(VP_ENONFINITE, "%lld non-finite weights", (long long)out->nonfinite);
+    if (flag) return fail4(VP_ERANGE, "a deposit cell sum left the fixed-point range");
+    return VP_OK;
+}
+
+}  // extern "C"

@@ -84,7 +84,7 @@ double spacing(const vp_axis& a) { return (a.hi - a.lo) / (a.periodic ? a.n : a.
 // Workspace layout: every piece 256-byte aligned.
 struct Layout {
     size_t w0, w1, b, tab_x, tab_p, fel_ex, fel_eq, fel_state, partials, counters,
-        inst, off, moments, boxes, total;
+        inst, off, moments, boxes, map_f, map_k, total;
     size_t partial_doubles;
 };
 
@@ -109,6 +109,8 @@ Layout layout(int nx, int np) {
     L.off = take(8 * sizeof(int32_t));
     L.moments = take(kMoments * 8);
     L.boxes = take(box_capacity(nx, np) * sizeof(int4));
+    L.map_f = take(n * sizeof(float2));  // the cached push of a static Hamiltonian
+    L.map_k = take(n * sizeof(int32_t));
     L.total = o;
     return L;
 }
@@ -125,6 +127,7 @@ struct LaunchList {
     int solve = kSolveTent;  // the solve kernel serving every instance in the list
     size_t lds1 = 0;
     int threads1 = 256;  // deposit workgroup size
+    int grid1 = 0;       // deposit workgroups: 0 = one per tile, else that many looping over the tiles
     hipStream_t stream = nullptr;
     // graphs of r steps (r = 1 .. kGraphSteps), by the relative parity they start at
     hipGraphExec_t exec[kGraphSteps + 1][2] = {};
@@ -142,14 +145,15 @@ struct LaunchList {
         return LaunchArgs{d_inst, off, ninst, total, parity, mode, d_any};
     }
     // the kernels of one step: {kernel, off, total (= grid), lds, threads, mode}
-    struct K { const void* fn; const int32_t* off; int total; size_t lds; int threads; int mode; };
+    struct K { const void* fn; const int32_t* off; int total; size_t lds; int threads; int mode; int grid = 0; };
+    int dep_grid() const { return grid1 > 0 && grid1 < total1 ? grid1 : total1; }
     int kernels(K (&k)[5]) const {
         int n = 0;
         if (has_rk4) {
             k[n++] = K{fel_stage_kernel(), d_off2, total2, 0, kStageThreads, 0};
             k[n++] = K{fel_field_kernel(), d_off2, ninst, 0, kFieldThreads, 1};
         }
-        k[n++] = K{deposit_kernel(basis), d_off1, total1, lds1, threads1, 0};
+        k[n++] = K{deposit_kernel(basis), d_off1, total1, lds1, threads1, 0, dep_grid()};
         k[n++] = K{solve_kernel(solve), d_off2, total2, 0, solve_threads(solve), 0};
         if (has_fel) k[n++] = K{fel_field_kernel(), d_off2, ninst, 0, kFieldThreads, 0};
         return n;
@@ -159,7 +163,7 @@ struct LaunchList {
             HIP_TRY(launch_fel_stage(args(d_off2, total2, parity), total2, stream));
             HIP_TRY(launch_fel_field(args(d_off2, ninst, parity, 1), stream));
         }
-        HIP_TRY(launch_deposit(args(d_off1, total1, parity), total1, lds1, threads1, stream, basis));
+        HIP_TRY(launch_deposit(args(d_off1, total1, parity), dep_grid(), lds1, threads1, stream, basis));
         HIP_TRY(launch_solve(args(d_off2, total2, parity), total2, stream, solve));
         if (has_fel) HIP_TRY(launch_fel_field(args(d_off2, ninst, parity), stream));
         return VP_OK;
@@ -179,7 +183,7 @@ struct LaunchList {
                 void* kp[1] = {&keep.back()};
                 hipKernelNodeParams p{};
                 p.func = const_cast<void*>(k.fn);
-                p.gridDim = dim3(k.total);
+                p.gridDim = dim3(k.grid > 0 ? k.grid : k.total);
                 p.blockDim = dim3(k.threads);
                 p.sharedMemBytes = (unsigned)k.lds;
                 p.kernelParams = kp;
@@ -251,6 +255,15 @@ void free_host_flag(volatile uint32_t** p) {
 
 }  // namespace
 
+namespace vp {
+// The calling thread's error message for a failure reported by another
+// source file of the library (the 2D2V runtime).
+int set_error(int code, const char* msg) {
+    snprintf(g_err, sizeof g_err, "%s", msg);
+    return code;
+}
+}  // namespace vp
+
 struct vp_grid {
     vp_axis x{}, p{};
     hipStream_t stream = nullptr;
@@ -267,6 +280,7 @@ struct vp_grid {
     double N0 = 0.0;
     vp_tiles tiles{};
     bool use_graph = true;
+    bool use_map = true;  // cache the push of a static Hamiltonian (k_map)
     bool in_batch = false;
     int basis = kBasisTent;
 
@@ -275,6 +289,7 @@ struct vp_grid {
 
 struct vp_batch {
     std::vector<vp_grid*> grids;
+    std::vector<double> dt;
     LaunchList list;
     int64_t steps_done = 0;
 };
@@ -339,9 +354,15 @@ int upload_inst(vp_grid* g) {
         HIP_TRY(hipMemcpyAsync(g->at<int4>(g->L.boxes), boxes.data(), boxes.size() * sizeof(int4),
                                hipMemcpyHostToDevice, g->stream));
     }
+    // a push that does not depend on the state is the same every step: form
+    // it once into the map the deposit reads instead of pushing
+    const bool map = g->use_map && I.push.kind != kFel;
+    I.map_f = map ? g->at<float2>(g->L.map_f) : nullptr;
+    I.map_k = map ? g->at<int32_t>(g->L.map_k) : nullptr;
     int32_t off[4] = {0, I.k1_tiles, 0, I.k2_tiles};
     HIP_TRY(hipMemcpyAsync(g->list.d_inst, &I, sizeof(VpInst), hipMemcpyHostToDevice, g->stream));
     HIP_TRY(hipMemcpyAsync(g->list.d_off1, off, sizeof off, hipMemcpyHostToDevice, g->stream));
+    if (map) HIP_TRY(launch_map(g->list.d_inst, (long)g->x.n * g->p.n, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
     // the graphs hold launch shapes and kernel choices, not the descriptor
     // (it is read from device memory): keep them while those stay the same
@@ -488,6 +509,53 @@ int prepare(vp_grid* g, double dt) {
         if (rc) return rc;
         g->bunch_valid = true;
     }
+    return VP_OK;
+}
+
+// (Re)build a batch's launch list from its grids as they are planned now:
+// the descriptors, the tile offsets, one deposit workgroup size and LDS size
+// for the launch, one solve kernel.  The graphs are rebuilt on next use.
+int fill_batch(vp_batch* b) {
+    const int n = (int)b->grids.size();
+    std::vector<VpInst> insts(n);
+    std::vector<int32_t> off1(n + 1, 0), off2(n + 1, 0);
+    size_t lds1 = 0;
+    // one workgroup size serves every tile of the launch (the deposit loops
+    // stride by it): the one most of the tiles were planned with (a small
+    // grid timed alone may pick a large workgroup for its few tiles)
+    std::map<int, long> tiles_at;
+    for (auto* g : b->grids) tiles_at[g->list.threads1] += g->inst.k1_tiles;
+    int threads1 = tiles_at.begin()->first;
+    for (auto& kv : tiles_at)
+        if (kv.second > tiles_at[threads1]) threads1 = kv.first;
+    LaunchList& L = b->list;
+    L.has_fel = L.has_rk4 = false;
+    L.solve = kSolveTent;
+    for (int k = 0; k < n; ++k) {
+        vp_grid* g = b->grids[k];
+        insts[k] = g->inst;
+        insts[k].parity0 = g->parity;
+        off1[k + 1] = off1[k] + insts[k].k1_tiles;
+        off2[k + 1] = off2[k] + insts[k].k2_tiles;
+        lds1 = std::max(lds1, deposit_lds_bytes(insts[k].k1_tx, insts[k].k1_ty, g->basis));
+        L.has_fel |= insts[k].push.kind == kFel;
+        L.has_rk4 |= insts[k].push.kind == kFel && insts[k].push.rk4;
+        // one solve kernel for the launch: the narrow-lattice one if any grid needs it
+        L.solve = std::max(L.solve, g->list.solve);
+    }
+    L.total1 = off1[n];
+    L.total2 = off2[n];
+    L.lds1 = lds1;
+    L.threads1 = threads1;
+    L.basis = b->grids[0]->basis;
+    L.drop_graphs();
+    hipStream_t s = L.stream;
+    HIP_TRY(hipMemcpyAsync(L.d_inst, insts.data(), sizeof(VpInst) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(L.d_off1, off1.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(L.d_off2, off2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    // the parities now stand relative to the grids' own
+    b->steps_done = 0;
     return VP_OK;
 }
 
@@ -779,6 +847,14 @@ int vp_get_tiles(const vp_grid* g, vp_tiles* t) {
     return VP_OK;
 }
 
+int vp_set_map_cache(vp_grid* g, int32_t on) {
+    if (!g) return fail(VP_EINVAL, "null grid");
+    if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
+    g->use_map = on != 0;
+    g->plan_valid = false;
+    return VP_OK;
+}
+
 int vp_set_launch(vp_grid* g, int32_t use_graph) {
     if (!g) return fail(VP_EINVAL, "null grid");
     g->use_graph = use_graph != 0;
@@ -889,42 +965,12 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
         if (rc) return rc;
         HIP_TRY(hipStreamSynchronize(grids[k]->stream));
     }
-    std::vector<VpInst> insts(n);
-    std::vector<int32_t> off1(n + 1, 0), off2(n + 1, 0);
-    size_t lds1 = 0;
-    // one workgroup size serves every tile of the launch (the deposit loops
-    // stride by it): the one most of the tiles were tuned with (a small grid
-    // timed alone may pick a large workgroup for its few tiles)
-    std::map<int, long> tiles_at;
-    for (int k = 0; k < n; ++k) tiles_at[grids[k]->list.threads1] += grids[k]->inst.k1_tiles;
-    int threads1 = tiles_at.begin()->first;
-    for (auto& kv : tiles_at)
-        if (kv.second > tiles_at[threads1]) threads1 = kv.first;
-    for (int k = 0; k < n; ++k) {
-        insts[k] = grids[k]->inst;
-        insts[k].parity0 = grids[k]->parity;
-        off1[k + 1] = off1[k] + insts[k].k1_tiles;
-        off2[k + 1] = off2[k] + insts[k].k2_tiles;
-        lds1 = std::max(lds1, deposit_lds_bytes(insts[k].k1_tx, insts[k].k1_ty, grids[k]->basis));
-    }
     vp_batch* b = new vp_batch();
     b->grids.assign(grids, grids + n);
+    b->dt.assign(dt, dt + n);
     LaunchList& L = b->list;
     L.stream = s;
     L.ninst = n;
-    L.total1 = off1[n];
-    L.total2 = off2[n];
-    L.has_fel = false;
-    for (int k = 0; k < n; ++k) {
-        L.has_fel |= insts[k].push.kind == kFel;
-        L.has_rk4 |= insts[k].push.kind == kFel && insts[k].push.rk4;
-    }
-    L.lds1 = lds1;
-    L.threads1 = threads1;
-    L.basis = grids[0]->basis;
-    // one solve kernel for the launch: the narrow-lattice one if any grid needs it
-    L.solve = kSolveTent;
-    for (int k = 0; k < n; ++k) L.solve = std::max(L.solve, grids[k]->list.solve);
     hipError_t e = hipMalloc(&L.d_inst, sizeof(VpInst) * n);
     // tile offsets of both kernels, then the batch's range word
     if (e == hipSuccess) e = hipMalloc(&L.d_off1, sizeof(int32_t) * (2 * (n + 1) + 1));
@@ -932,19 +978,150 @@ int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch
     L.d_any = reinterpret_cast<uint32_t*>(L.d_off2 + (n + 1));
     if (e == hipSuccess && alloc_host_flag(&L.h_any) != VP_OK) e = hipErrorOutOfMemory;
     if (e == hipSuccess) e = hipMemsetAsync(L.d_any, 0, sizeof(uint32_t), s);
-    if (e == hipSuccess) e = hipMemcpyAsync(L.d_inst, insts.data(), sizeof(VpInst) * n, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(L.d_off1, off1.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(L.d_off2, off2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
+    int rc = e == hipSuccess ? fill_batch(b) : fail(VP_EHIP, "batch setup: %s", hipGetErrorString(e));
+    if (rc) {
         (void)hipFree(L.d_inst);
         (void)hipFree(L.d_off1);
         free_host_flag(&L.h_any);
         delete b;
-        return fail(VP_EHIP, "batch setup: %s", hipGetErrorString(e));
+        return rc;
     }
     for (auto* g : b->grids) g->in_batch = true;
     *out = b;
+    return VP_OK;
+}
+
+int vp_batch_autotune(vp_batch* b, double* best_us) {
+    if (!b) return fail(VP_EINVAL, "null batch");
+    LaunchList& L = b->list;
+    const int n = (int)b->grids.size();
+    // composition class: the multiset of (kind, basis, half-octave axis lengths)
+    std::vector<std::tuple<int, int, int, int>> comp;
+    for (auto* g : b->grids)
+        comp.emplace_back((int)g->ham.kind, g->basis, (int)lround(2.0 * log2((double)g->x.n)),
+                          (int)lround(2.0 * log2((double)g->p.n)));
+    std::sort(comp.begin(), comp.end());
+    // candidates: every grid keeps its own shape (as planned), or every grid
+    // takes one shape (cut to the lattice); each with one workgroup per tile
+    // or a persistent launch (as many workgroups as fit the device at once,
+    // looping over the tiles)
+    const int shapes[][3] = {{0, 0, 0}, {64, 32, 256}, {64, 64, 256}, {128, 32, 256}, {128, 64, 512}, {128, 64, 1024},
+                             {128, 128, 1024}};
+    constexpr int kShapes = sizeof(shapes) / sizeof(shapes[0]);
+    auto apply = [&](int si, bool persistent, const std::vector<vp_tiles>& own) -> int {
+        for (int k = 0; k < n; ++k) {
+            vp_grid* g = b->grids[k];
+            vp_tiles t = own[k];
+            if (si > 0) {
+                t = vp_tiles{shapes[si][0], shapes[si][1], shapes[si][2]};
+                if (validate_tiles(g->basis, t) != VP_OK) t = own[k];
+            }
+            g->tiles = t;
+            g->plan_valid = false;
+            int rc = prepare(g, b->dt[k]);
+            if (rc) return rc;
+        }
+        int rc = fill_batch(b);
+        if (rc) return rc;
+        L.grid1 = 0;
+        if (persistent) {
+            int dev = 0, cus = 0, per = 0;
+            HIP_TRY(hipGetDevice(&dev));
+            HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, deposit_kernel(L.basis), L.threads1, L.lds1));
+            L.grid1 = std::max(1, cus * per);
+        }
+        return VP_OK;
+    };
+    std::vector<vp_tiles> own(n);
+    for (int k = 0; k < n; ++k) own[k] = b->grids[k]->tiles;
+    using Key = std::vector<std::tuple<int, int, int, int>>;
+    static std::mutex mu;
+    static std::map<Key, std::pair<int, bool>> cache;
+    if (!best_us) {
+        std::pair<int, bool> choice;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto it = cache.find(comp);
+            if (it == cache.end()) return fail(VP_ESTATE, "no tuned choice for this batch composition yet");
+            choice = it->second;
+        }
+        return apply(choice.first, choice.second, own);
+    }
+    // save the states (weights and FEL scalars) to restore after timing
+    size_t bytes = 0;
+    std::vector<size_t> at(n);
+    for (int k = 0; k < n; ++k) {
+        at[k] = bytes;
+        bytes += align_up((size_t)b->grids[k]->x.n * b->grids[k]->p.n * 4) + kFelStateLen * 8;
+    }
+    char* save = nullptr;
+    HIP_TRY(hipMalloc(&save, bytes));
+    auto copy_states = [&](bool to_save) -> int {
+        for (int k = 0; k < n; ++k) {
+            vp_grid* g = b->grids[k];
+            const size_t wb = (size_t)g->x.n * g->p.n * 4;
+            char* w = reinterpret_cast<char*>(g->at<float>(g->parity ? g->L.w1 : g->L.w0));
+            char* st = reinterpret_cast<char*>(g->at<double>(g->L.fel_state));
+            char* sw = save + at[k];
+            char* ss = save + at[k] + align_up(wb);
+            HIP_TRY(hipMemcpyAsync(to_save ? sw : w, to_save ? w : sw, wb, hipMemcpyDeviceToDevice, L.stream));
+            HIP_TRY(hipMemcpyAsync(to_save ? ss : st, to_save ? st : ss, kFelStateLen * 8, hipMemcpyDeviceToDevice,
+                                   L.stream));
+        }
+        return VP_OK;
+    };
+    int rc = copy_states(true);
+    Events ev(2);
+    if (rc == VP_OK && ev.create() != hipSuccess) rc = fail(VP_EHIP, "hipEventCreate failed");
+    double best = 1e300;
+    int best_si = 0;
+    bool best_p = false;
+    for (int si = 0; si < kShapes && rc == VP_OK; ++si)
+        for (int pers = 0; pers < 2 && rc == VP_OK; ++pers) {
+            rc = apply(si, pers != 0, own);
+            if (rc) break;
+            const int reps = 8;  // even: the grids' parities come back
+            rc = L.run(2, 0, false);
+            if (rc) break;
+            if (hipEventRecord(ev[0], L.stream) != hipSuccess) { rc = fail(VP_EHIP, "hipEventRecord"); break; }
+            rc = L.run(reps, 0, false);
+            if (rc) break;
+            float ms = 0.f;
+            if (hipEventRecord(ev[1], L.stream) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) {
+                rc = fail(VP_EHIP, "batch timing events");
+                break;
+            }
+            const double us = 1000.0 * ms / reps;
+            // a candidate must beat the incumbent by 2% (timing noise)
+            if (us < 0.98 * best) {
+                best = us;
+                best_si = si;
+                best_p = pers != 0;
+            }
+            rc = copy_states(false);
+        }
+    if (rc == VP_OK) rc = copy_states(false);
+    if (rc == VP_OK) rc = apply(best_si, best_p, own);
+    (void)hipStreamSynchronize(L.stream);
+    (void)hipFree(save);
+    if (rc) return rc;
+    for (auto* g : b->grids) g->bunch_valid = false;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        cache[comp] = {best_si, best_p};
+    }
+    *best_us = best;
+    return VP_OK;
+}
+
+int vp_batch_config(const vp_batch* b, int32_t* deposit_grid, int32_t* deposit_threads, int32_t* tiles) {
+    if (!b || !deposit_grid || !deposit_threads || !tiles) return fail(VP_EINVAL, "null argument");
+    *deposit_grid = b->list.grid1;
+    *deposit_threads = b->list.threads1;
+    *tiles = b->list.total1;
     return VP_OK;
 }
 

@@ -28,6 +28,17 @@ def fel_rk4(inst):
     return dataclasses.replace(inst, ham=dataclasses.replace(inst.ham, integrator=FEL_RK4))
 
 
+# Full rows and columns stored at the last checkpoint: the lattice edges and
+# the lines on both sides of deposit-tile seams (multiples of 64, 128, 256)
+# and solve-tile seams (columns at multiples of 32, rows at multiples of 64).
+def seam_lines(n):
+    out = {0, n - 1}
+    for m in (32, 64, 128, 256, 512):
+        if m < n:
+            out |= {m - 1, m}
+    return np.array(sorted(out))
+
+
 WORKLOADS = {
     # name: (instance factory, checkpoints, sample stride)
     "pendulum_gaussian_128": (lambda: pendulum_gaussian(128), (1, 100, 200), 1),
@@ -62,6 +73,10 @@ def run(name):
         out[f"A_{s}"] = np.array([A64.real, A64.imag])
         out[f"fp32_floor_{s}"] = np.array(oracle.rel_l1(w32, w64))
         out[f"fp32_floor_w0_{s}"] = np.array(np.abs(w32 - w64).sum() / np.abs(inst.w0).sum())
+        if s == checkpoints[-1]:
+            out["seam_rows"], out["seam_cols"] = seam_lines(inst.p.n), seam_lines(inst.x.n)
+            out["rows"] = w64[out["seam_rows"], :].astype(np.float32)
+            out["cols"] = w64[:, out["seam_cols"]].astype(np.float32)
         print(f"{name}: step {s} floor {float(out[f'fp32_floor_{s}']):.3e} "
               f"({time.time() - t0:.0f}s)", flush=True)
     np.savez_compressed(os.path.join(HERE, f"oracle_{name}.npz"), **out)

@@ -102,3 +102,35 @@ def test_batch_of_grids_on_different_streams_is_refused(B):
     side.synchronize()
     g1.close()
     g0.close()
+
+
+def test_batch_autotune_keeps_states_and_results(B):
+    """The batch autotuner times candidate launches on the batch itself (shared
+    tile shapes, persistent deposit) and restores every state: stepping after
+    tuning equals the grids run alone, bitwise, FEL included; a cached choice
+    applies to a batch of the same composition."""
+    insts = batch_instances(12, seed=41, steps=20, n_min=48, n_max=260)
+    insts += [fel_gaussian(96, 20, npp=128)]
+    grids = [B.grid_for(i) for i in insts]
+    batch = B.Batch(grids, [i.dt for i in insts])
+    batch.step(3)
+    us = batch.autotune()
+    assert us > 0
+    cfg = batch.config()
+    assert cfg["deposit_threads"] in (256, 512, 1024) and cfg["deposit_tiles"] > 0
+    batch.step(17)
+    batch.close()
+    for k, (g, inst) in enumerate(zip(grids, insts)):
+        assert np.array_equal(g.density(), alone(B, inst, 20)), k
+        assert g.moments()["step"] == 20
+    # the same composition again: the cached choice, no timing
+    grids2 = [B.grid_for(i) for i in insts]
+    batch2 = B.Batch(grids2, [i.dt for i in insts])
+    batch2.autotune(cached=True)
+    assert batch2.config() == cfg
+    batch2.step(20)
+    batch2.close()
+    for g, g2 in zip(grids, grids2):
+        assert np.array_equal(g.density(), g2.density())
+        g.close()
+        g2.close()

@@ -7,6 +7,14 @@ import pytest
 
 import oracle
 from _parity import assert_step_parity
+
+# Node-wise bar of the cubic basis: the FP32 rounding of b (2^-24 relative, on
+# either side) amplified by the inverse mass matrix, at most 1 / lambda_min^2 =
+# (5040 / 272)^2 = 343 per unit of the largest weight (lambda_min: the band's
+# symbol at the highest frequency, per axis): 2 x 2^-24 x 343 = 4.1e-5.  The
+# relative-L1 bar stays 1e-5.  (At 2048^2 the largest node error, 1.1e-5, is
+# the same at solve-tile seams and inside the tiles.)
+NODE_TOL = 2.0 * 2.0 ** -24 * (5040.0 / 272.0) ** 2
 from oracle import spline_basis as Q
 from paper_2007_12227_amd.inputs import (FEL_RK4, H_FEL, H_FREE, H_PENDULUM, H_SHO_EXACT, Axis, Hamiltonian,
                                          fel_gaussian, gaussian, pendulum_axes, pendulum_band, rng)
@@ -62,7 +70,7 @@ def test_one_step_each_kind(B, kind):
     x, p, ham, dt, w = case(kind)
     w = w.astype(np.float32)
     got, _ = gpu_steps(B, x, p, ham, w, dt, 1)
-    assert_step_parity(got, oracle_step(x, p, ham, w, dt), label=f"cubic, kind {kind}:")
+    assert_step_parity(got, oracle_step(x, p, ham, w, dt), label=f"cubic, kind {kind}:", tol_max=NODE_TOL)
 
 
 def test_deposit_tilings_agree_bitwise(B):
@@ -72,7 +80,7 @@ def test_deposit_tilings_agree_bitwise(B):
     first = None
     for t in [None, (64, 16), (24, 5, 64), (200, 24, 1024), (128, 112, 1024)]:
         got, _ = gpu_steps(B, x, p, ham, w, dt, 1, t)
-        assert_step_parity(got, ref, label=str(t))
+        assert_step_parity(got, ref, label=str(t), tol_max=NODE_TOL)
         if first is None:
             first = got
         assert np.array_equal(got, first), t
@@ -101,7 +109,7 @@ def test_one_step_window_shapes(B, nx, np_, periodic):
         ham, dt = Hamiltonian(H_SHO_EXACT, omega=1.0), 0.3
     w = (0.5 + rng(82).random((np_, nx))).astype(np.float32)
     got, _ = gpu_steps(B, x, p, ham, w, dt, 1)
-    assert_step_parity(got, oracle_step(x, p, ham, w, dt))
+    assert_step_parity(got, oracle_step(x, p, ham, w, dt), tol_max=NODE_TOL)
 
 
 def test_whole_cell_free_streaming_and_no_motion(B):
@@ -118,7 +126,7 @@ def test_whole_cell_free_streaming_and_no_motion(B):
     print(f"cubic whole-cell stream: max error {err:.3e} (bound {bound:.3e})", flush=True)
     assert err <= bound
     got, _ = gpu_steps(B, x, p, Hamiltonian(H_FREE), w, 0.0, 1)
-    assert_step_parity(got, w.astype(np.float64))
+    assert_step_parity(got, w.astype(np.float64), tol_max=NODE_TOL)
 
 
 @pytest.mark.parametrize("kind", [H_PENDULUM, H_SHO_EXACT])
@@ -153,7 +161,7 @@ def test_one_step_at_2048_in_the_benchmark_launch(B):
     g.step(inst.dt, 1)
     got = g.density().astype(np.float64)
     g.close()
-    assert_step_parity(got, oracle_step(inst.x, inst.p, inst.ham, w32, inst.dt), label="cubic 2048^2 band:")
+    assert_step_parity(got, oracle_step(inst.x, inst.p, inst.ham, w32, inst.dt), label="cubic 2048^2 band:", tol_max=NODE_TOL)
 
 
 @pytest.mark.parametrize("integrator", [0, FEL_RK4])
@@ -169,7 +177,7 @@ def test_fel_run_256(B, integrator):
     m = g.moments()
     g.close()
     ref1, _ = Q.run_fel(inst.x, inst.p, ham, w32.astype(np.float64), inst.dt, 1, degree=DEG)
-    assert_step_parity(one, ref1)
+    assert_step_parity(one, ref1, tol_max=NODE_TOL)
     ref, A = Q.run_fel(inst.x, inst.p, ham, w32.astype(np.float64), inst.dt, 200, degree=DEG)
     err = oracle.rel_l1(got, ref)
     Ag = complex(m["A_re"], m["A_im"])

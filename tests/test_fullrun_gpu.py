@@ -1,8 +1,11 @@
 """Full-length runs at the workloads' real sizes, in the launch configuration
 the benchmark times (autotuned tiles, steps replayed from HIP graphs), against
-strided samples of the FP64 oracle's run (tests/golden/make_full_runs.py).
-Bar: relative L1 <= 1e-4 on the sample; the FP32-storage floor of the same
-run (oracle with its state rounded to float every step) is printed beside it."""
+strided samples of the FP64 oracle's run and, at the last checkpoint, against
+the full rows and columns on both sides of the deposit and solve tile seams
+(tests/golden/make_full_runs.py).  Bar: relative L1 <= 1e-4, except where the
+FEL's saturated state makes the standard number a matter of rounding (see
+test_full_run_fel_gaussian_1024); the FP32-state floor of the same run (the
+oracle with its state rounded to float every step) is printed beside it."""
 import dataclasses
 import os
 
@@ -26,9 +29,12 @@ def B():
     return binding
 
 
-def run_against_golden(B, inst, name, autotune=True, chaotic_after=None):
-    """Largest relative L1 (sample) over the checkpoints.  Checkpoints past
-    chaotic_after are checked against ||w0||_1 instead (returned separately)."""
+def run_against_golden(B, inst, name, autotune=True):
+    """Run the GPU through the stored checkpoints; per checkpoint the relative
+    L1 distance over the strided sample, both to the oracle's ||w||_1 (the
+    standard number) and to ||w0||_1, and the relative field error; at the
+    last checkpoint the same over the stored full rows and columns on both
+    sides of the tile seams."""
     ref = np.load(os.path.join(GOLDEN, f"oracle_{name}.npz"))
     stride = int(ref["stride"])
     g = B.Grid(inst.x, inst.p)
@@ -36,65 +42,98 @@ def run_against_golden(B, inst, name, autotune=True, chaotic_after=None):
     g.set_density(inst.w0.astype(np.float32))
     if autotune:
         g.autotune(inst.dt)
-    done, worst, worst_w0 = 0, 0.0, 0.0
-    l1_w0 = float(np.abs(inst.w0.astype(np.float32).astype(np.float64)[::stride, ::stride]).sum())
+    done, out = 0, {}
+    w0 = inst.w0.astype(np.float32).astype(np.float64)
+    l1_w0 = float(np.abs(w0[::stride, ::stride]).sum())
+    last = int(ref["steps"][-1])
     for s in ref["steps"]:
         g.step(inst.dt, int(s) - done)
         done = int(s)
-        got = g.density()[::stride, ::stride].astype(np.float64)
+        w = g.density().astype(np.float64)
+        got = w[::stride, ::stride]
         exp = ref[f"sample_{s}"].astype(np.float64)
-        err = float(np.abs(got - exp).sum() / np.abs(exp).sum())
+        diff = float(np.abs(got - exp).sum())
         m = g.moments()
-        print(f"{name} step {s}: rel L1 (sample) {err:.3e}  FP32-state floor {float(ref[f'fp32_floor_{s}']):.3e}"
-              f"  sum_w gpu {m['sum_w']:.10e} oracle {float(ref[f'sum_{s}']):.10e}", flush=True)
-        err_w0 = float(np.abs(got - exp).sum() / l1_w0)
-        print(f"    relative to ||w0||_1: {err_w0:.3e}", flush=True)
-        if chaotic_after is not None and s > chaotic_after:
-            worst_w0 = max(worst_w0, err_w0)
-        else:
-            worst = max(worst, err)
+        dA = 0.0
+        if inst.ham.kind == 3:
+            A = complex(*ref[f"A_{s}"])
+            dA = abs(complex(m["A_re"], m["A_im"]) - A) / abs(A)
+        row = {"err": diff / float(np.abs(exp).sum()), "err_w0": diff / l1_w0, "dA": dA}
+        if int(s) == last and "rows" in ref:
+            r, c = ref["seam_rows"], ref["seam_cols"]
+            seam_got = np.concatenate([w[r, :].ravel(), w[:, c].ravel()])
+            seam_exp = np.concatenate([ref["rows"].astype(np.float64).ravel(), ref["cols"].astype(np.float64).ravel()])
+            seam_l1_w0 = float(np.abs(np.concatenate([w0[r, :].ravel(), w0[:, c].ravel()])).sum())
+            sd = float(np.abs(seam_got - seam_exp).sum())
+            row["seam_err"], row["seam_err_w0"] = sd / float(np.abs(seam_exp).sum()), sd / seam_l1_w0
+        out[int(s)] = row
+        print(f"{name} step {s}: rel L1 (sample) {row['err']:.3e}  FP32-state floor "
+              f"{float(ref[f'fp32_floor_{s}']):.3e}  relative to ||w0||_1 {row['err_w0']:.3e}  |dA|/|A| {dA:.2e}"
+              + (f"  seams: {row['seam_err']:.3e} ({row['seam_err_w0']:.3e} of ||w0||_1)" if "seam_err" in row else ""),
+              flush=True)
         # mass accounting against the initial mass (the FEL loses almost all of
         # it through the open energy edges after saturation)
         assert abs(m["sum_w"] - float(ref[f"sum_{s}"])) <= 1e-6 * abs(float(ref["sum_1"]))
-        if inst.ham.kind == 3:
-            A = complex(*ref[f"A_{s}"])
-            assert abs(complex(m["A_re"], m["A_im"]) - A) <= 1e-3 * abs(A), (m["A_re"], m["A_im"], A)
     g.close()
-    return worst if chaotic_after is None else (worst, worst_w0)
+    return out
 
 
 def test_full_run_pendulum_gaussian_128(B):
-    assert run_against_golden(B, pendulum_gaussian(128), "pendulum_gaussian_128", autotune=False) <= 1e-4
+    res = run_against_golden(B, pendulum_gaussian(128), "pendulum_gaussian_128", autotune=False)
+    assert all(r["err"] <= 1e-4 for r in res.values())
 
 
 def test_full_run_pendulum_band_2048(B):
-    assert run_against_golden(B, pendulum_band(2048), "pendulum_band_2048") <= 1e-4
+    res = run_against_golden(B, pendulum_band(2048), "pendulum_band_2048")
+    assert all(r["err"] <= 1e-4 for r in res.values())
+    assert res[1000]["seam_err"] <= 1e-4
 
 
-def chaotic_checkpoints(bar=1e-4):
-    """FEL checkpoints whose result rounding decides: there, equally valid FP32
-    runs (tests/golden/fel_sensitivity.py: the FP32-state oracle with 1e-7
-    relative noise per step, two seeds) already drift from the exact run by
-    more than a tenth of the bar."""
-    rows = np.loadtxt(os.path.join(GOLDEN, "fel_sensitivity.txt"))
-    return sorted({int(k) for _, k, err, _ in rows if err > 0.1 * bar})
+def fp32_run_spread(model="random"):
+    """Per checkpoint, the largest relative-L1 error, relative-to-||w0||_1
+    error and field error of the oracle's FP32-state runs with per-step
+    perturbations of rounding size (tests/golden/fel_sensitivity.py)."""
+    out = {}
+    for line in open(os.path.join(GOLDEN, "fel_sensitivity.txt")):
+        f = line.split("#", 1)[0].split()
+        if len(f) == 6 and f[0] == model:
+            step, vals = int(f[2]), [float(v) for v in f[3:]]
+            out[step] = [max(a, b) for a, b in zip(out.get(step, [0.0, 0.0, 0.0]), vals)]
+    return out
+
+
+def chaotic_checkpoints(bar=1e-5):
+    """FEL checkpoints where equally valid FP32 runs (the oracle's FP32-state
+    run with unbiased rounding-size noise, four seeds) already land more than
+    1e-5 from the exact run: there rounding, not the implementation, decides
+    the standard number."""
+    return sorted(s for s, (err, _, _) in fp32_run_spread().items() if err > bar)
 
 
 def test_full_run_fel_gaussian_1024(B):
-    """Standard relative L1 <= 1e-4 where the result is a property of the
-    implementation (through step 500: noisy FP32 runs agree with the exact
-    one to ~1e-6).  By step 1000 the field has saturated, the beam has left
-    the energy window through the open edges (the weights inside sum to 0.4%
-    of the start, later to a Gibbs residue), and two noisy FP32 runs that
-    differ only in the noise seed land 3.6e-6 and 9.0e-5 from the exact run:
-    there the error is held to 1e-4 of ||w0||_1 (printed beside the standard
-    number and the FP32-state floor), with the field A and the mass
-    accounting checked at every checkpoint."""
+    """The 1024^2 FEL through saturation (2000 steps) against the oracle.
+    Where the result is a property of the implementation (through step 500)
+    the standard relative L1 is held to 10x the worst unbiased FP32 run (at
+    most 1e-4): 1.2e-5 at step 500, which a per-step bias of rounding size
+    (one-sided rounding, a 1e-7 gain: 8e-5 to 1.4e-4 there) fails.  After
+    saturation the beam has left the energy window and two FP32 runs that
+    differ only in the noise seed land up to 100x apart (fel_sensitivity.txt):
+    there the error relative to ||w0||_1 is held to twice the worst unbiased
+    FP32 run (1.1e-6, 3.4e-7, 1.2e-7 at steps 1000, 1500, 2000), which the
+    biased runs fail, and the standard number is printed.  The field is held
+    to 1e-3 relative at every checkpoint."""
+    spread = fp32_run_spread()
     chaotic = chaotic_checkpoints()
-    assert chaotic and min(chaotic) > 500, chaotic
-    early, late = run_against_golden(B, fel_gaussian(1024), "fel_gaussian_1024", chaotic_after=min(chaotic) - 1)
-    assert early <= 1e-4
-    assert late <= 1e-4
+    assert chaotic == [1000, 1500, 2000], chaotic
+    res = run_against_golden(B, fel_gaussian(1024), "fel_gaussian_1024")
+    for s, r in res.items():
+        err_max, err_w0_max, _ = spread[s]
+        if s in chaotic:
+            assert r["err_w0"] <= 2.0 * err_w0_max, (s, r, err_w0_max)
+        else:
+            assert r["err"] <= min(1e-4, 10.0 * max(err_max, 1e-8)), (s, r, err_max)
+        assert r["dA"] <= 1e-3, (s, r)
+    assert res[2000]["seam_err_w0"] <= 2.0 * spread[2000][1]
 
 
 def test_full_run_fel_gaussian_1024_rk4(B):
@@ -102,4 +141,5 @@ def test_full_run_fel_gaussian_1024_rk4(B):
     through the exponential growth (500 steps), against the oracle's run."""
     inst = fel_gaussian(1024)
     inst = dataclasses.replace(inst, ham=dataclasses.replace(inst.ham, integrator=FEL_RK4))
-    assert run_against_golden(B, inst, "fel_gaussian_1024_rk4") <= 1e-4
+    res = run_against_golden(B, inst, "fel_gaussian_1024_rk4")
+    assert all(r["err"] <= 1e-4 for r in res.values())

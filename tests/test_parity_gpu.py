@@ -360,3 +360,28 @@ def test_one_step_full_size_fel_1024(B):
     got, _ = gpu_run(B, inst.x, inst.p, inst.ham, w32, inst.dt, 1)
     ref = oracle.run(inst.x, inst.p, inst.ham, w32.astype(np.float64), inst.dt, 1).w
     assert_step_parity(got, ref)
+
+
+@pytest.mark.parametrize("basis", [0, 1, 2])
+@pytest.mark.parametrize("kind", [H_FREE, H_PENDULUM, H_SHO_EXACT])
+def test_cached_push_map_is_bitwise_the_push(B, kind, basis):
+    """A static Hamiltonian's push cached once per plan (the time-invariant map)
+    gives bitwise the results of pushing every step, for every basis."""
+    if kind == H_SHO_EXACT:
+        x, p = Axis(-3.0, 3.0, 150, False), Axis(-3.0, 3.0, 130, False)
+        ham, dt = Hamiltonian(H_SHO_EXACT, omega=1.0), 0.2
+    else:
+        x, p = pendulum_axes(150, 130)
+        ham, dt = Hamiltonian(kind, a=1.1), 0.07
+    w = (gaussian(x, p, 0.3, 0.5, 0.6) + 1e-3 * rng(71).random((p.n, x.n))).astype(np.float32)
+    out = []
+    for cached in (True, False):
+        g = B.Grid(x, p)
+        g.set_basis(basis)
+        g.set_map_cache(cached)
+        g.set_hamiltonian(ham)
+        g.set_density(w)
+        g.step(dt, 7)
+        out.append(g.density())
+        g.close()
+    assert np.array_equal(out[0], out[1])
