@@ -24,7 +24,8 @@ HBM_PEAK_GBS = 8000.0
 ALG_BYTES_PER_NODE = 8  # a step (and each of its kernels) must read one FP32 array and write one
 KERNELS = ("k_deposit", "k_solve")
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2007_12227_amd", "csrc", f) for f in ("vp_kernels.hip", "vp_internal.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2007_12227_amd", "csrc", f)
+                  for f in ("vp_kernels.hip", "vp_internal.h", "vp_device.h")]
 
 
 def log(msg):
@@ -325,6 +326,8 @@ def main():
                     help="deposit launch shape COLSxROWSxTHREADS for the tuned path instead of autotuning "
                          "(uniform dispatches for profiling)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (untuned, no graph) run")
+    ap.add_argument("--no-map", action="store_true",
+                    help="push every step instead of reading the cached push map (for comparison)")
     ap.add_argument("--basis", choices=("tent", "quadratic", "cubic"), default="tent",
                     help="basis functions of the timed workload (quadratic, cubic: for profiling their kernels)")
     args = ap.parse_args()
@@ -340,6 +343,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     binding.lib()
+    if args.copy_probe:
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if args.only:
         res = (bench_batched(binding, args.batch_steps, args.batch_count) if args.only == "batched"
                else bench_phase4d(binding, args.phase4d_n, args.phase4d_np, args.phase4d_steps))
@@ -353,14 +362,10 @@ def main():
     def grid_of(inst):
         g = binding.grid_for(inst)
         g.set_basis(basis)
+        if args.no_map:
+            g.set_map_cache(False)
         return g
 
-    if args.copy_probe:
-        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
 
     # plain path: default tiles, one launch per kernel
     plain = plain_s = None
@@ -413,7 +418,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "nx": args.n, "np": args.n, "dt": inst.dt,
                    "a": 1.0, "deposit_tiles": tiles["k1"], "deposit_threads": tiles["threads"],
-                   "launch": "hip-graph"},
+                   "launch": "hip-graph", "push_map_cached": not args.no_map},
         "plain": None if plain is None else {"value": plain, "ms_per_step": 1e3 * plain_s / args.steps,
                                              "speedup": value / plain},
         "kernels_us": kus,

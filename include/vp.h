@@ -201,6 +201,31 @@ int vp_set_fixed_point(vp_grid* g, int32_t e);
  * takes grids of one basis (VP_EUNSUPPORTED otherwise). */
 int vp_set_basis(vp_grid* g, int32_t basis);
 
+/* The scalars that, with the weights, make up a run's state: a run stopped
+ * after any step resumes bitwise on another grid of the same axes, basis and
+ * Hamiltonian from vp_get_density + vp_get_run_state, then vp_set_density +
+ * vp_set_run_state (checkpoint / restart).
+ *  fix_exponent: the deposit's fixed-point exponent (vp_set_fixed_point);
+ *  step:         the step counter;
+ *  n0:           N0 of eq. 13c, the weight sum when the run started;
+ *  bunch_dz:     the FEL step size the bunchings in fel[] belong to (NaN: none);
+ *  fel:          the FEL field A and the current and stage bunchings (opaque). */
+typedef struct {
+    int32_t fix_exponent;
+    int32_t reserved;
+    int64_t step;
+    double n0;
+    double bunch_dz;
+    double fel[16];
+} vp_run_state;
+
+/* Read the run state (waits for the stream).  VP_ESTATE before a density. */
+int vp_get_run_state(vp_grid* g, vp_run_state* out);
+/* Restore a run state after vp_set_density (which it overrides: N0, the
+ * exponent, the step counter, the FEL field and bunchings).  VP_EINVAL for an
+ * exponent out of range or non-finite values, VP_ESTATE before a density. */
+int vp_set_run_state(vp_grid* g, const vp_run_state* s);
+
 /* Copy the current weights w_j (eq. 4) out: n_p*n_x floats into w (device
  * memory if on_device, else host); waits for the stream.  VP_ESTATE before a
  * density is set; VP_ERANGE (after copying) if a deposit cell sum has left

@@ -67,6 +67,11 @@ class Moments4(C.Structure):
     _fields_ = [(f, C.c_double) for f in MOMENT4_FIELDS] + [("step", C.c_int64), ("nonfinite", C.c_int64)]
 
 
+class RunState(C.Structure):
+    _fields_ = [("fix_exponent", C.c_int32), ("reserved", C.c_int32), ("step", C.c_int64), ("n0", C.c_double),
+                ("bunch_dz", C.c_double), ("fel", C.c_double * 16)]
+
+
 class Tiles(C.Structure):
     _fields_ = [("k1_tx", C.c_int32), ("k1_ty", C.c_int32), ("k1_threads", C.c_int32)]
 
@@ -120,6 +125,8 @@ def lib(load_torch: bool = True):
     L.vp_set_basis.argtypes = [C.c_void_p, C.c_int32]
     L.vp_set_fixed_point.argtypes = [C.c_void_p, C.c_int32]
     L.vp_set_map_cache.argtypes = [C.c_void_p, C.c_int32]
+    L.vp_get_run_state.argtypes = [C.c_void_p, P(RunState)]
+    L.vp_set_run_state.argtypes = [C.c_void_p, P(RunState)]
     L.vp_step_noalloc.argtypes = [P(Axis), P(Axis), P(Hamiltonian), C.c_int32, C.c_double, C.c_int64,
                                   C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
     L.vp4_workspace_bytes.restype = C.c_size_t
@@ -258,6 +265,15 @@ class Grid:
             check(rc)
         d["status"] = rc
         return d
+
+    def run_state(self) -> RunState:
+        """The scalars of the run beside the weights (vp_get_run_state)."""
+        st = RunState()
+        check(lib().vp_get_run_state(self._h, C.byref(st)))
+        return st
+
+    def set_run_state(self, st: RunState):
+        check(lib().vp_set_run_state(self._h, C.byref(st)))
 
     def set_fixed_point(self, e: int):
         """Exponent of the deposit's fixed-point cell sums (vp_set_fixed_point)."""

@@ -8,8 +8,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libvp.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("vp_kernels.hip", "vp_api.hip", "vp4_api.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "vp_internal.h"), os.path.join(ROOT, "include", "vp.h")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("vp_kernels.hip", "vp_api.hip", "vp4_kernels.hip", "vp4_api.hip")]
+HEADERS = [os.path.join(HERE, "csrc", f) for f in ("vp_internal.h", "vp_device.h", "vp4_internal.h")] + [
+    os.path.join(ROOT, "include", "vp.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

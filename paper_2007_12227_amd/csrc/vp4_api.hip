@@ -10,7 +10,7 @@
 #include <vector>
 
 #include "../../include/vp.h"
-#include "vp_internal.h"
+#include "vp4_internal.h"
 
 using namespace vp;
 
@@ -266,6 +266,7 @@ int enqueue_step4(vp4_grid* g, int par, hipEvent_t* ev) {
         S.total = (int32_t)lines;
         S.src = src[axis];
         S.dst = dst[axis];
+        S.inst_nx = I.n[0];
         HIP_TRY4(launch_solve4(S, g->stream, ev && axis == 0 ? ev[2] : nullptr, ev && axis == 3 ? ev[3] : nullptr));
     }
     return VP_OK;

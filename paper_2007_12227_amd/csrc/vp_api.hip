@@ -274,6 +274,7 @@ struct vp_grid {
     vp_hamiltonian ham{};
     bool has_ham = false, has_density = false;
     bool plan_valid = false, bunch_valid = false;
+    double bunch_dz = 0.0;  // the FEL step size the bunching in the device state belongs to
     double plan_dt = 0.0;
     int parity = 0;
     int64_t step = 0;
@@ -458,7 +459,6 @@ int plan(vp_grid* g, double dt) {
     if (rc) return rc;
     g->plan_dt = dt;
     g->plan_valid = true;
-    if (H.kind == VP_H_FEL) g->bunch_valid = false;
     return VP_OK;
 }
 
@@ -504,10 +504,13 @@ int prepare(vp_grid* g, double dt) {
         int rc = plan(g, dt);
         if (rc) return rc;
     }
-    if (g->ham.kind == VP_H_FEL && !g->bunch_valid) {
+    // the FEL bunching at the half-drift phases of this dz: the solve's
+    // epilogue keeps it current while dz stays; otherwise reduce the state
+    if (g->ham.kind == VP_H_FEL && (!g->bunch_valid || g->bunch_dz != dt)) {
         int rc = launch_reduce_on(g, 1, dt);
         if (rc) return rc;
         g->bunch_valid = true;
+        g->bunch_dz = dt;
     }
     return VP_OK;
 }
@@ -812,6 +815,46 @@ int vp_set_fixed_point(vp_grid* g, int32_t e) {
     if (e < kFixBits - 126 || e > 127) return fail(VP_EINVAL, "fixed-point exponent %d outside [%d, 127]", e, kFixBits - 126);
     g->inst.fix_scale = ldexpf(1.0f, kFixBits - e);
     g->inst.fix_inv = ldexpf(1.0f, e - kFixBits);
+    g->plan_valid = false;
+    return VP_OK;
+}
+
+int vp_get_run_state(vp_grid* g, vp_run_state* out) {
+    if (!g || !out) return fail(VP_EINVAL, "null argument");
+    if (!g->has_density) return fail(VP_ESTATE, "no density set");
+    double st[kFelStateLen];
+    HIP_TRY(hipMemcpyAsync(st, g->at<double>(g->L.fel_state), sizeof st, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    memset(out, 0, sizeof *out);
+    out->fix_exponent = kFixBits - ilogbf(g->inst.fix_scale);
+    out->step = g->step;
+    out->n0 = g->N0;
+    out->bunch_dz = g->bunch_valid ? g->bunch_dz : NAN;
+    static_assert(sizeof(out->fel) == sizeof st, "the FEL state fits the record");
+    memcpy(out->fel, st, sizeof st);
+    return VP_OK;
+}
+
+int vp_set_run_state(vp_grid* g, const vp_run_state* s) {
+    if (!g || !s) return fail(VP_EINVAL, "null argument");
+    if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
+    if (!g->has_density) return fail(VP_ESTATE, "set the density first");
+    const int32_t e = s->fix_exponent;
+    if (e < kFixBits - 126 || e > 127) return fail(VP_EINVAL, "fixed-point exponent %d outside [%d, 127]", e, kFixBits - 126);
+    for (double v : s->fel)
+        if (!isfinite(v)) return fail(VP_EINVAL, "non-finite FEL state");
+    if (!isfinite(s->n0) || s->step < 0) return fail(VP_EINVAL, "invalid normalisation or step");
+    double st[kFelStateLen];
+    memcpy(st, s->fel, sizeof st);
+    st[kN0] = s->n0;
+    HIP_TRY(hipMemcpyAsync(g->at<double>(g->L.fel_state), st, sizeof st, hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->N0 = s->n0;
+    g->inst.fix_scale = ldexpf(1.0f, kFixBits - e);
+    g->inst.fix_inv = ldexpf(1.0f, e - kFixBits);
+    g->step = s->step;
+    g->bunch_valid = isfinite(s->bunch_dz);
+    g->bunch_dz = g->bunch_valid ? s->bunch_dz : 0.0;
     g->plan_valid = false;
     return VP_OK;
 }

@@ -14,298 +14,9 @@
 #include <hip/hip_ext.h>
 
 #include "vp_internal.h"
+#include "vp_device.h"
 
 namespace vp {
-
-namespace {
-
-// 2 - sqrt(3): interior LU multiplier of tridiag(1,4,1), equal to 1/d_inf.
-constexpr float kMinf = 0.267949192431122706f;
-
-__device__ inline void two_sum(float a, float b, float& s, float& e) {
-    s = a + b;
-    float bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
-
-// Integer part and fraction of hi + lo, |lo| small: the fraction of hi plus
-// lo lies in [-1, 2), and its own floor moves the carry into the integer part
-// (no branches).  The fraction is in [0, 1], reaching 1 only when a tiny
-// negative fraction rounds up; the taps of t = 1 at cell k are those of
-// t = 0 at cell k + 1, so either form deposits the same weights.
-__device__ inline void split_cell(float hi, float lo, int& k, float& t) {
-    const float f = floorf(hi);
-    const float r = (hi - f) + lo;
-    const float g = floorf(r);
-    k = (int)(f + g);
-    t = r - g;
-}
-
-// Cubic B-spline tap weights B3(t+1), B3(t), B3(1-t), B3(2-t) for t in [0,1),
-// in FP64 (eq. 9).  The second tap is one minus the other three, so the taps
-// sum to one to FP64 rounding (the partition of unity behind the conservation
-// argument of eqs. 11-12), far below the 2^-40 fixed-point grid the products
-// are rounded to.
-// Every fused multiply-add is written out and the compiler forms no other:
-// the taps are the same bits in every inlined copy, so the deposit's exact
-// sums do not depend on which copy (kind of push, wrap mode) pushed a node.
-__device__ inline void bspline_taps(float tf, double (&b)[4]) {
-#pragma clang fp contract(off)
-    const double sixth = 1.0 / 6.0;
-    const double t = (double)tf, s = 1.0 - t, t2 = t * t;
-    b[0] = (s * sixth) * (s * s);
-    const double t3 = (t * sixth) * t2;
-    b[3] = t3;
-    b[2] = fma(-3.0, t3, fma(0.5, fma(t, t, t), sixth));
-    b[1] = 1.0 - ((b[0] + b[3]) + b[2]);
-}
-
-// Quintic B-spline tap weights B5(t+2), B5(t+1), B5(t), B5(1-t), B5(2-t),
-// B5(3-t) for t in [0,1): the overlaps of a quadratic B-spline basis function
-// moved to cell position k + t with those of nodes k-2 .. k+3.  Each piece as
-// a polynomial in s = 1 - t or in t, times 120:
-//   s^5,  1 + 5s + 10s^2 + 10s^3 + 5s^4 - 5s^5,  26 + 50s + 20s^2 - 20s^3 - 20s^4 + 10s^5,
-// and the same in t from the other end; the tap at cell k is one minus the
-// others (partition of unity), as for the cubic taps.
-__device__ inline void quintic_taps(float tf, double (&b)[6]) {
-#pragma clang fp contract(off)
-    const double c = 1.0 / 120.0;
-    const double t = (double)tf, s = 1.0 - t;
-    auto near = [](double v) {  // 1 + 5v + 10v^2 + 10v^3 + 5v^4 - 5v^5
-        return fma(fma(fma(fma(fma(-5.0, v, 5.0), v, 10.0), v, 10.0), v, 5.0), v, 1.0);
-    };
-    auto mid = [](double v) {  // 26 + 50v + 20v^2 - 20v^3 - 20v^4 + 10v^5
-        return fma(fma(fma(fma(fma(10.0, v, -20.0), v, -20.0), v, 20.0), v, 50.0), v, 26.0);
-    };
-    const double s2 = s * s, t2 = t * t;
-    b[0] = ((s2 * s2) * s) * c;
-    b[1] = near(s) * c;
-    b[3] = mid(t) * c;
-    b[4] = near(t) * c;
-    b[5] = ((t2 * t2) * t) * c;
-    b[2] = 1.0 - ((((b[0] + b[5]) + (b[1] + b[4])) + b[3]));
-}
-
-// Septic B-spline tap weights B7(t+3) .. B7(4-t) for t in [0,1): the
-// overlaps of a cubic B-spline basis function moved to cell position k + t
-// with those of nodes k-3 .. k+4.  Each piece as a polynomial in s = 1 - t or
-// in t, times 5040:
-//   v^7,  1 + 7v + 21v^2 + 35v^3 + 35v^4 + 21v^5 + 7v^6 - 7v^7,
-//   120 + 392v + 504v^2 + 280v^3 - 84v^5 - 42v^6 + 21v^7,
-//   1191 + 1715v + 315v^2 - 665v^3 - 315v^4 + 105v^5 + 105v^6 - 35v^7,
-// the tap at cell k (the fourth) one minus the others.
-__device__ inline void septic_taps(float tf, double (&b)[8]) {
-#pragma clang fp contract(off)
-    const double c = 1.0 / 5040.0;
-    const double t = (double)tf, s = 1.0 - t;
-    auto p1 = [](double v) {
-        return fma(fma(fma(fma(fma(fma(fma(-7.0, v, 7.0), v, 21.0), v, 35.0), v, 35.0), v, 21.0), v, 7.0), v, 1.0);
-    };
-    auto p2 = [](double v) {
-        return fma(fma(fma(fma(fma(fma(fma(21.0, v, -42.0), v, -84.0), v, 0.0), v, 280.0), v, 504.0), v, 392.0), v,
-                   120.0);
-    };
-    auto p3 = [](double v) {
-        return fma(fma(fma(fma(fma(fma(fma(-35.0, v, 105.0), v, 105.0), v, -315.0), v, -665.0), v, 315.0), v, 1715.0),
-                   v, 1191.0);
-    };
-    const double s2 = s * s, t2 = t * t, s4 = s2 * s2, t4 = t2 * t2;
-    b[0] = ((s4 * s2) * s) * c;
-    b[1] = p1(s) * c;
-    b[2] = p2(s) * c;
-    b[4] = p3(t) * c;
-    b[5] = p2(t) * c;
-    b[6] = p1(t) * c;
-    b[7] = ((t4 * t2) * t) * c;
-    b[3] = 1.0 - ((((b[0] + b[7]) + (b[1] + b[6])) + (b[2] + b[5])) + b[4]);
-}
-
-template <int TAPS>
-__device__ inline void basis_taps(float t, double (&b)[TAPS]) {
-    if constexpr (TAPS == 4) bspline_taps(t, b);
-    else if constexpr (TAPS == 6) quintic_taps(t, b);
-    else septic_taps(t, b);
-}
-
-// 1.5 * 2^52: adding it to a value of magnitude below 2^51 leaves the value
-// rounded to the nearest integer in the low bits of the sum's encoding,
-// two's complement on top of the constant's encoding 0x4338 << 48.
-constexpr double kFixMagic = 6755399441055744.0;
-
-// Encoding of round(a * b) + 1.5 * 2^52, |a b| < 2^47: the FMA rounds the
-// exact product once, straight onto the integer grid.  Summed as 64-bit
-// integers, n such words give n (0x4338 << 48) + sum of the integers, whose
-// low 48 bits are the sum itself modulo 2^48: exact while |sum| < 2^47
-// (fix48_value), with no per-tap subtraction of the constant.
-__device__ inline unsigned long long fix48_word(double a, double b) {
-    return (unsigned long long)__double_as_longlong(fma(a, b, kFixMagic));
-}
-__device__ inline long long fix48_value(long long sum) { return (long long)((unsigned long long)sum << 16) >> 16; }
-
-// Locate the instance of a flattened tile index (thread 0 only).
-__device__ inline int find_instance(const int32_t* off, int ninst, int item) {
-    int lo = 0, hi = ninst - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= item) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-__device__ inline int wrap_index(int i, int n, float inv_n) {
-    int q = (int)floorf(((float)i + 0.5f) * inv_n);
-    int r = i - q * n;
-    r += r < 0 ? n : 0;
-    r -= r >= n ? n : 0;
-    return r;
-}
-
-// Global-memory views of device pointers (loads through them are global, not
-// flat, loads) and a 32-bit offset pinned to a vector register: a running
-// row offset then costs one register and one add per row, instead of one
-// precomputed 64-bit address per row.
-#ifdef __HIP_DEVICE_COMPILE__
-#define VP_GLOBAL __attribute__((address_space(1)))
-#else
-#define VP_GLOBAL
-#endif
-typedef VP_GLOBAL const float gfloat;
-typedef VP_GLOBAL const float4 gfloat4;
-typedef VP_GLOBAL float gfloat_out;
-__device__ inline gfloat* as_global(const float* p) { return (gfloat*)p; }
-__device__ inline gfloat4* as_global(const float4* p) { return (gfloat4*)p; }
-// Stores through a global (not flat) pointer: a flat store also counts on
-// the LDS counter, so a later wait for an LDS read would wait for it too.
-__device__ inline gfloat_out* as_global_out(float* p) { return (gfloat_out*)p; }
-__device__ inline unsigned in_vgpr(unsigned v) {
-    asm volatile("" : "+v"(v));
-    return v;
-}
-// Make a wave-uniform value available here (its scalar load waited for
-// before a loop, not inside it: there the wait would also drain every LDS
-// operation in flight, since both share one counter).
-template <class T>
-__device__ inline void settle(T v) {
-    asm volatile("" ::"s"(v));
-}
-
-// s_waitcnt immediate that waits for every vector-memory load (vmcnt 0) and
-// nothing else (expcnt 7, lgkmcnt 15).
-constexpr int kWaitVmcnt0 = 0x0F70;
-
-// Fourth word of a raw buffer resource (gfx9 family): 32-bit data format,
-// no range check beyond the 2^32-byte window the resource spans.
-constexpr int kBufferWord3 = 0x00020000;
-
-// Workgroups are dispatched to the 8 XCDs round-robin.  When the grid has
-// one workgroup per tile, give each XCD a contiguous run of tiles, so that
-// neighbouring tiles (which share halo and source data) meet in one L2.
-constexpr int kXcds = 8;
-__device__ inline int xcd_tile(int b, int total) {
-    const int xcd = b % kXcds, k = b / kXcds, q = total / kXcds, r = total % kXcds;
-    return xcd < r ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
-}
-__device__ inline int tile_of(int item, int total) {
-    return (int)gridDim.x == total ? xcd_tile(item, total) : item;
-}
-
-// LU coefficients of T = tridiag(1, 4, 1) on a line that starts at an open
-// edge: d_0 = 4, m_k = 1/d_{k-1}, d_k = 4 - m_k.  They converge to the interior
-// constants m = 1/d = 2 - sqrt 3 well within kEdge nodes.  Computed at compile
-// time in FP64 and rounded once, so an unrolled solve folds them into its
-// instructions (no table, no registers).
-struct LuEdge {
-    float m[kEdge], dinv[kEdge];
-};
-constexpr LuEdge lu_edge_table() {
-    LuEdge t{};
-    double dprev = 0.0;
-    for (int k = 0; k < kEdge; ++k) {
-        const double m = k == 0 ? 0.0 : 1.0 / dprev;
-        const double d = 4.0 - m;
-        t.m[k] = (float)m;
-        t.dinv[k] = (float)(1.0 / d);
-        dprev = d;
-    }
-    return t;
-}
-constexpr LuEdge kLuEdge = lu_edge_table();
-
-// Coefficients at position k of a line (a compile-time index once unrolled):
-// the edge values on a line that starts at an open edge (EDGE), the interior
-// constant elsewhere and on every line that starts at a cut.
-template <bool EDGE>
-__device__ inline float lu_m(int k) { return (EDGE && k < kEdge) ? kLuEdge.m[k] : kMinf; }
-template <bool EDGE>
-__device__ inline float lu_dinv(int k) { return (EDGE && k < kEdge) ? kLuEdge.dinv[k] : kMinf; }
-
-// Solve M y = b, M = tridiag(1/6, 2/3, 1/6), along one line of N values
-// v[] (registers), written as
-//     y = b - T^{-1} (D2 b),   T = 6 M = tridiag(1, 4, 1),  D2 b = b[k-1] - 2 b[k] + b[k+1]
-// (T = 6 I + D2, so 6 T^{-1} = I - T^{-1} D2).  The LU recursions of T then only
-// carry the correction T^{-1} D2 b, so their FP32 rounding (whose fixed point
-// is biased on slowly varying data) acts on a term much smaller than b: the
-// mass a line carries is kept to ~1e-10 per step instead of ~1e-8.
-// Neighbours outside the line count as zero: exact at an open edge (the
-// truncated M), and a cut inside the lattice only disturbs the halo.
-// MASKED: the lattice line is shorter than N; v[k] is zero for k >= n
-// and the recursion ends at n (an open edge).  Otherwise every index
-// condition is a compile-time one.  The solution replaces v[LO..N); the
-// backward sweep stops at LO, below which the caller keeps nothing (the
-// values there are left as they were), so z[k < LO] and v[k < LO] are dead
-// after the forward sweep and hold no registers.
-template <int N, int LO, bool EDGE, bool MASKED>
-__device__ inline void line_solve(float (&v)[N], int n) {
-    float z[N];
-    float acc = 0.0f;
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const float r = ((k > 0 ? v[k - 1] : 0.0f) + (k + 1 < N ? v[k + 1] : 0.0f)) - 2.0f * v[k];
-        acc = fmaf(-lu_m<EDGE>(k), acc, r);
-        if (MASKED) acc = k < n ? acc : 0.0f;
-        z[k] = acc;
-    }
-    float c = 0.0f;
-#pragma unroll
-    for (int k = N - 1; k >= LO; --k) {
-        c = (z[k] - c) * lu_dinv<EDGE>(k);
-        v[k] -= c;
-    }
-}
-
-// The same solve on a line that starts at an open edge (or is a whole short
-// line, MASKED) with the forward sweep's z of the first NL nodes kept in LDS
-// (zs[k * stride]) rather than in registers: not much more than one line of
-// registers is live, where v and z would take two.  For the few windows that need it; the backward sweep's LDS reads do not
-// depend on the recursion, so they are issued ahead of it.
-template <int N, int NL, bool MASKED>
-__device__ inline void line_solve_lds(float (&v)[N], int n, float* zs, int stride) {
-    float zr[N - NL];  // z of the nodes past the first NL
-    float acc = 0.0f;
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const float r = ((k > 0 ? v[k - 1] : 0.0f) + (k + 1 < N ? v[k + 1] : 0.0f)) - 2.0f * v[k];
-        acc = fmaf(-lu_m<true>(k), acc, r);
-        if (MASKED) acc = k < n ? acc : 0.0f;
-        if (k < NL) zs[k * stride] = acc;
-        else zr[k - NL] = acc;
-    }
-    asm volatile("" ::: "memory");  // read z back from LDS (not forwarded from the stores)
-    float c = 0.0f;
-#pragma unroll
-    for (int k = N - 1; k >= 0; --k) {
-        c = ((k < NL ? zs[k * stride] : zr[k - NL]) - c) * lu_dinv<true>(k);
-        v[k] -= c;
-    }
-}
-
-// Start of the window of `line` nodes around a segment starting at s0 on an
-// open axis of n nodes: kHalo before the segment, shifted to lie inside
-// [0, n) so that a window near an edge ends exactly at it (0 when n < line).
-__device__ inline int open_window(int s0, int n, int line) { return max(0, min(s0 - kHalo, n - line)); }
-
-}  // namespace
 
 // Push kinds of the deposit: a phase-dependent kick (free, pendulum, FEL by
 // the exact-kick step), the exact rotation, and the FEL by Runge-Kutta.
@@ -1677,312 +1388,6 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(ReduceArgs R) {
 }
 
 // ---------------------------------------------------------------------------
-// Four-dimensional phase space: the same step with tensor-product tents on
-// (x, y, p_x, p_y) (the closing remark of the algorithm section: only Lambda
-// and Delta depend on the dimension).  The overlap of two 4-D tents is the
-// product of four B3 factors (eq. 9), the mass matrix the Kronecker product of
-// four tridiagonal ones (eq. 8).
-// ---------------------------------------------------------------------------
-
-// Wrap an index into [0, n) (any integer, small multiples of n away).
-__device__ inline int wrap4(int i, int n) {
-    int r = i % n;
-    return r < 0 ? r + n : r;
-}
-
-// k_deposit4: a workgroup owns one destination tile of T0 x T1 x T2 x T3
-// lattice nodes held in LDS (no border: every tap is tested against the tile
-// and the blocks of taps that miss it are skipped), scans the host-planned
-// source box, pushes each source and adds its 4^4 B3 taps as exact
-// fixed-point integers (the 2-D deposit's encoding), then writes the tile of
-// b once.  The blocks of taps along p_y, p_x and y are skipped when the
-// lane's taps there miss the tile; along x each tap is its own test.
-template <int PUSH>
-__global__ __launch_bounds__(kDeposit4Threads) void k_deposit4(Launch4Args A) {
-    extern __shared__ __align__(16) long long acc4[];
-    const Vp4Inst& I = *A.inst;
-    const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2], n3 = I.n[3];
-    const int T0 = I.T[0], T1 = I.T[1], T2 = I.T[2], T3 = I.T[3];
-    const int S1 = T0, S2 = T0 * T1, S3 = T0 * T1 * T2, cells = S3 * T3;
-    const int par = (I.parity0 + A.parity) & 1;
-    gfloat* __restrict__ w_in = as_global(I.w[par]);
-    gfloat4* __restrict__ tx = as_global(I.tab[0]);
-    gfloat4* __restrict__ ty = as_global(I.tab[1]);
-    gfloat4* __restrict__ tpx = as_global(I.tab[2]);
-    gfloat4* __restrict__ tpy = as_global(I.tab[3]);
-    const float scale = I.fix_scale;
-    for (int t = blockIdx.x; t < A.total; t += gridDim.x) {
-        int q = t;
-        const int c0 = q % I.tiles[0];
-        q /= I.tiles[0];
-        const int c1 = q % I.tiles[1];
-        q /= I.tiles[1];
-        const int c2 = q % I.tiles[2];
-        const int c3 = q / I.tiles[2];
-        const int O0 = c0 * T0, O1 = c1 * T1, O2 = c2 * T2, O3 = c3 * T3;
-        const int E0 = min(T0, n0 - O0), E1 = min(T1, n1 - O1), E2 = min(T2, n2 - O2), E3 = min(T3, n3 - O3);
-        const int4 ba = I.boxes[2 * t], bb = I.boxes[2 * t + 1];
-        const int B0 = ba.y - ba.x, B1 = ba.w - ba.z, B2 = bb.y - bb.x, B3 = bb.w - bb.z;
-        const int V = (B0 > 0 && B1 > 0 && B2 > 0 && B3 > 0 && scale > 0.0f) ? B0 * B1 * B2 * B3 : 0;
-        for (int k = threadIdx.x; k < cells; k += blockDim.x) acc4[k] = 0ll;
-        __syncthreads();
-        for (int s = threadIdx.x; s < V; s += blockDim.x) {
-            int r = s;
-            const int i0 = r % B0;
-            r /= B0;
-            const int i1 = r % B1;
-            r /= B1;
-            const int i2 = r % B2;
-            const int i3 = r / B2;
-            const int ix = wrap4(ba.x + i0, n0), iy = wrap4(ba.z + i1, n1);
-            const int ipx = bb.x + i2, ipy = bb.z + i3;
-            const float wv = w_in[(((size_t)ipy * n2 + ipx) * n1 + iy) * n0 + ix];
-            if (wv == 0.0f) continue;
-            const float4 X = tx[ix], Y = ty[iy], PX = tpx[ipx], PY = tpy[ipy];
-            int ku0, ku1, kv0, kv1;
-            float fu0, fu1, fv0, fv1;
-            {
-#pragma clang fp contract(off)
-                float dvx = 0.0f, dvy = 0.0f;
-                if (PUSH == kPush4Potential) {
-                    // phases at the half drift: x + q_px, y + q_py, from the tables
-                    const float sxh = fmaf(X.x, PX.w, X.y * PX.z), cxh = fmaf(X.y, PX.w, -(X.x * PX.z));
-                    const float syh = fmaf(Y.x, PY.w, Y.y * PY.z), cyh = fmaf(Y.y, PY.w, -(Y.x * PY.z));
-                    const float sd = fmaf(sxh, cyh, -(cxh * syh));  // sin(xh - yh)
-                    dvx = -fmaf(I.ax, sxh, I.cx * sd);
-                    dvy = -fmaf(I.by, syh, -(I.cy * sd));
-                }
-                float su, eu;
-                two_sum(PX.x, dvx * I.kdx, su, eu);
-                split_cell(su, eu + PX.y, ku0, fu0);
-                two_sum(PY.x, dvy * I.kdy, su, eu);
-                split_cell(su, eu + PY.y, ku1, fu1);
-                split_cell(dvx, 0.0f, kv0, fv0);
-                split_cell(dvy, 0.0f, kv1, fv1);
-            }
-            // first tap of each axis relative to the tile origin (periodic axes
-            // wrapped into [-3, n - 3), so the four taps need no further wrap)
-            const int r0 = wrap4(ix + ku0 - 1 - O0 + 3, n0) - 3;
-            const int r1 = wrap4(iy + ku1 - 1 - O1 + 3, n1) - 3;
-            const int r2 = ipx + kv0 - 1 - O2, r3 = ipy + kv1 - 1 - O3;
-            if (r0 < -3 || r0 >= E0 || r1 < -3 || r1 >= E1 || r2 < -3 || r2 >= E2 || r3 < -3 || r3 >= E3) continue;
-            double bx[4], byy[4], bpx[4], bpy[4];
-            bspline_taps(fu0, bx);
-            bspline_taps(fu1, byy);
-            bspline_taps(fv0, bpx);
-            bspline_taps(fv1, bpy);
-            // tap positions in the tile; on a periodic axis a tap before the
-            // origin wraps to the axis's end (a tile spanning the whole axis
-            // takes both ends of a wrapped footprint)
-            int p0[4], p1[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                p0[k] = r0 + k + (r0 + k < 0 ? n0 : 0);
-                p1[k] = r1 + k + (r1 + k < 0 ? n1 : 0);
-            }
-            const double ws = (double)(wv * scale);
-            for (int q3 = 0; q3 < 4; ++q3) {
-                if ((unsigned)(r3 + q3) >= (unsigned)E3) continue;
-                const double w3 = ws * bpy[q3];
-                for (int q2 = 0; q2 < 4; ++q2) {
-                    if ((unsigned)(r2 + q2) >= (unsigned)E2) continue;
-                    const double w2 = w3 * bpx[q2];
-                    long long* plane = acc4 + (r3 + q3) * S3 + (r2 + q2) * S2;
-#pragma unroll
-                    for (int q1 = 0; q1 < 4; ++q1) {
-                        if ((unsigned)p1[q1] >= (unsigned)E1) continue;
-                        const double w1 = w2 * byy[q1];
-                        unsigned long long* row = (unsigned long long*)(plane + p1[q1] * S1);
-#pragma unroll
-                        for (int q0 = 0; q0 < 4; ++q0)
-                            if ((unsigned)p0[q0] < (unsigned)E0) atomicAdd(row + p0[q0], fix48_word(w1, bx[q0]));
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        bool out_of_range = false;
-        const double inv = (double)I.fix_inv;
-        for (int k = threadIdx.x; k < cells; k += blockDim.x) {
-            int r = k;
-            const int e0 = r % T0;
-            r /= T0;
-            const int e1 = r % T1;
-            r /= T1;
-            const int e2 = r % T2;
-            const int e3 = r / T2;
-            if (e0 >= E0 || e1 >= E1 || e2 >= E2 || e3 >= E3) continue;
-            const long long v = fix48_value(acc4[k]);
-            out_of_range |= (unsigned long long)v + (1ull << 46) >= (1ull << 47);
-            A.dst[(((size_t)(O3 + e3) * n2 + (O2 + e2)) * n1 + (O1 + e1)) * n0 + (O0 + e0)] = (float)((double)v * inv);
-        }
-        if (out_of_range) atomicOr(&I.counters[kRangeFlag], 1u);
-        __syncthreads();
-    }
-}
-
-// One line of the mass-matrix solve M y = b, M = tridiag(1/6, 2/3, 1/6), as
-// y = b - T^{-1}(D2 b) with T = 6M = tridiag(1, 4, 1) (the 2-D solve's form:
-// the FP32 recursions only carry the small correction).  Element k of the
-// line is in[k * stride], the result goes to out[k * stride] (z is kept there
-// between the sweeps).  A periodic line is solved on the line extended by
-// kSolve4Halo wrapped nodes per side with the recursions starting from zero
-// (the error decays by 2 - sqrt 3 per node, ~7e-10 at the line); an open line
-// is the truncated matrix, exact, with the LU factors of the first rows from
-// the edge (d_0 = 4, d_k = 4 - 1/d_{k-1}).
-__device__ inline void solve_line4(const float* __restrict__ in, float* __restrict__ out, int n, size_t stride,
-                                   bool periodic, const float (&dinv)[kEdge], const float (&mult)[kEdge]) {
-    auto b = [&](int k) { return in[(size_t)k * stride]; };
-    if (periodic) {
-        constexpr int H = kSolve4Halo;
-        float zt[H];
-        float acc = 0.0f;
-        // warm-up over the wrapped halo before the line
-        float bm = b(wrap4(-H - 1, n)), b0 = b(wrap4(-H, n));
-        for (int k = -H; k < n + H; ++k) {
-            const float bp = b(wrap4(k + 1, n));
-            acc = fmaf(-kMinf, acc, (bm + bp) - 2.0f * b0);
-            if (k >= 0 && k < n) out[(size_t)k * stride] = acc;
-            else if (k >= n) zt[k - n] = acc;
-            bm = b0;
-            b0 = bp;
-        }
-        float c = 0.0f;
-#pragma unroll
-        for (int k = H - 1; k >= 0; --k) c = (zt[k] - c) * kMinf;
-        for (int k = n - 1; k >= 0; --k) {
-            c = (out[(size_t)k * stride] - c) * kMinf;
-            out[(size_t)k * stride] = b(k) - c;
-        }
-        return;
-    }
-    float acc = 0.0f, bm = 0.0f, b0 = b(0);
-    for (int k = 0; k < n; ++k) {
-        const float bp = k + 1 < n ? b(k + 1) : 0.0f;
-        acc = fmaf(-(k < kEdge ? mult[k] : kMinf), acc, (bm + bp) - 2.0f * b0);
-        out[(size_t)k * stride] = acc;
-        bm = b0;
-        b0 = bp;
-    }
-    float c = 0.0f;
-    for (int k = n - 1; k >= 0; --k) {
-        c = (out[(size_t)k * stride] - c) * (k < kEdge ? dinv[k] : kMinf);
-        out[(size_t)k * stride] = b(k) - c;
-    }
-}
-
-// k_solve4: one thread per lattice line along A.axis, from A.src into A.dst.
-// Along y, p_x and p_y neighbouring threads take neighbouring x, so every
-// access is coalesced; along x a thread walks its own contiguous line.
-__global__ __launch_bounds__(kSolve4Threads) void k_solve4(Launch4Args A) {
-    const Vp4Inst& I = *A.inst;
-    float dinv[kEdge], mult[kEdge];
-#pragma unroll
-    for (int k = 0; k < kEdge; ++k) {
-        dinv[k] = kLuEdge.dinv[k];
-        mult[k] = kLuEdge.m[k];
-    }
-    const int L = blockIdx.x * blockDim.x + threadIdx.x;
-    if (L >= A.total) return;
-    const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2];
-    size_t start, stride;
-    int n;
-    if (A.axis == 0) {
-        start = (size_t)L * n0;
-        stride = 1;
-        n = n0;
-    } else {
-        const int ix = L % n0, rest = L / n0;
-        if (A.axis == 1) {  // rest = ipy * n2 + ipx
-            start = (size_t)rest * n1 * n0 + ix;
-            stride = n0;
-            n = n1;
-        } else if (A.axis == 2) {  // rest = ipy * n1 + iy
-            const int iy = rest % n1, ipy = rest / n1;
-            start = (size_t)ipy * n2 * n1 * n0 + (size_t)iy * n0 + ix;
-            stride = (size_t)n1 * n0;
-            n = n2;
-        } else {  // rest = ipx * n1 + iy
-            start = (size_t)rest * n0 + ix;
-            stride = (size_t)n2 * n1 * n0;
-            n = I.n[3];
-        }
-    }
-    solve_line4(A.src + start, A.dst + start, n, stride, A.axis < 2, dinv, mult);
-}
-
-// k_reduce4: FP64 fixed-order sums over a 4-D state (the moments of the 2-D
-// reduction, axis by axis).
-__global__ __launch_bounds__(kReduceThreads) void k_reduce4(Reduce4Args R) {
-    __shared__ double s_part[kReduceThreads / 64][kMoments];
-    __shared__ int s_last;
-    double acc[kMoments];
-#pragma unroll
-    for (int k = 0; k < kMoments; ++k) acc[k] = 0.0;
-    const long n = (long)R.n[0] * R.n[1] * R.n[2] * R.n[3];
-    for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        const double w = (double)R.w[k];
-        if (!isfinite(w)) { acc[9] += 1.0; continue; }
-        acc[0] += w;
-        acc[8] = fmax(acc[8], fabs(w));
-        if (R.mode == 2) continue;
-        long r = k;
-        const int i0 = (int)(r % R.n[0]);
-        r /= R.n[0];
-        const int i1 = (int)(r % R.n[1]);
-        r /= R.n[1];
-        const int i2 = (int)(r % R.n[2]);
-        const int i3 = (int)(r / R.n[2]);
-        const double x = R.lo[0] + i0 * R.h[0], y = R.lo[1] + i1 * R.h[1];
-        const double px = R.lo[2] + i2 * R.h[2], py = R.lo[3] + i3 * R.h[3];
-        if (w < 0.0) acc[1] += w;
-        acc[2] += fabs(w);
-        if (w > 0.0) acc[3] += w * log(w);
-        acc[4] += w * px;
-        acc[5] += w * py;
-        const double e = 0.5 * (px * px + R.h[2] * R.h[2] / 6.0) + 0.5 * (py * py + R.h[3] * R.h[3] / 6.0) -
-                         R.a * R.sinc2[0] * cos(x) - R.b * R.sinc2[1] * cos(y) -
-                         R.c * R.sinc2[0] * R.sinc2[1] * cos(x - y);
-        acc[6] += w * e;
-    }
-#pragma unroll
-    for (int k = 0; k < kMoments; ++k)
-        for (int o = 32; o > 0; o >>= 1) {
-            const double v = __shfl_down(acc[k], o);
-            acc[k] = k == 8 ? fmax(acc[k], v) : acc[k] + v;
-        }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0)
-        for (int k = 0; k < kMoments; ++k) s_part[wid][k] = acc[k];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < kMoments; ++k) {
-            double s = 0.0;
-            for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s = k == 8 ? fmax(s, s_part[q][k]) : s + s_part[q][k];
-            R.partials[blockIdx.x * kMoments + k] = s;
-        }
-        __threadfence();
-        s_last = (atomicAdd(R.counter, 1u) == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    if (threadIdx.x < kMoments) {
-        double s = 0.0;
-        for (unsigned q = 0; q < gridDim.x; ++q) {
-            const double v = __builtin_nontemporal_load(&R.partials[q * kMoments + threadIdx.x]);
-            s = threadIdx.x == 8 ? fmax(s, v) : s + v;
-        }
-        R.out[threadIdx.x] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        atomicExch(R.counter, 0u);
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Allocation-free stepping: the scratch array and the kernels that set it up
 // for one call of vp_step_noalloc and report back.  Each call writes every
 // byte it reads later (tables, descriptor, offsets, FEL state, counters; b is
@@ -2103,31 +1508,6 @@ hipError_t launch_map(const VpInst* inst, long nodes, hipStream_t s) {
     return hipGetLastError();
 }
 
-const void* deposit4_kernel(int push) {
-    return push == kPush4Free ? reinterpret_cast<const void*>(&k_deposit4<kPush4Free>)
-                              : reinterpret_cast<const void*>(&k_deposit4<kPush4Potential>);
-}
-
-hipError_t launch_deposit4(const Launch4Args& a, size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    void* args[1] = {const_cast<Launch4Args*>(&a)};
-    const void* k = a.push == kPush4Free ? reinterpret_cast<const void*>(&k_deposit4<kPush4Free>)
-                                         : reinterpret_cast<const void*>(&k_deposit4<kPush4Potential>);
-    if (e0 || e1) return hipExtLaunchKernel(k, dim3(a.total), dim3(kDeposit4Threads), args, lds, s, e0, e1, 0);
-    return hipLaunchKernel(k, dim3(a.total), dim3(kDeposit4Threads), args, lds, s);
-}
-
-hipError_t launch_solve4(const Launch4Args& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-    void* args[1] = {const_cast<Launch4Args*>(&a)};
-    const dim3 grid((a.total + kSolve4Threads - 1) / kSolve4Threads);
-    const void* k = reinterpret_cast<const void*>(&k_solve4);
-    if (e0 || e1) return hipExtLaunchKernel(k, grid, dim3(kSolve4Threads), args, 0, s, e0, e1, 0);
-    return hipLaunchKernel(k, grid, dim3(kSolve4Threads), args, 0, s);
-}
-
-hipError_t launch_reduce4(const Reduce4Args& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce4, dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a);
-    return hipGetLastError();
-}
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(kReduceBlocks), dim3(kReduceThreads), 0, s, a);

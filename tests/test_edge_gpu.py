@@ -176,3 +176,44 @@ def test_fixed_point_exponent_is_validated(B):
     g.step(0.05, 3)
     assert g.moments()["status"] == B.VP_OK
     g.close()
+
+
+@pytest.mark.parametrize("case", ["pendulum", "fel_dkd", "fel_rk4", "quadratic_fel"])
+def test_checkpoint_restart_is_bitwise(B, case):
+    """n steps equal k steps, a checkpoint (weights and run state), a new grid
+    restored from it, and n - k more steps, bitwise (FEL field included)."""
+    import dataclasses
+    from paper_2007_12227_amd.inputs import FEL_RK4
+    if case == "pendulum":
+        x, p = pendulum_axes(120, 100)
+        ham, dt = Hamiltonian(H_PENDULUM, a=1.2), 0.05
+        w = (gaussian(x, p, 0.3, 0.5, 0.5) + 1e-3 * rng(62).random((100, 120))).astype(np.float32)
+    else:
+        inst = fel_gaussian(128, 30, npp=96)
+        x, p, dt = inst.x, inst.p, inst.dt
+        ham = dataclasses.replace(inst.ham, integrator=FEL_RK4 if case == "fel_rk4" else 0)
+        w = inst.w0.astype(np.float32)
+    basis = 1 if case == "quadratic_fel" else 0
+
+    def fresh():
+        g = B.Grid(x, p)
+        g.set_basis(basis)
+        g.set_hamiltonian(ham)
+        return g
+    ref = fresh()
+    ref.set_density(w)
+    ref.step(dt, 30)
+    a = fresh()
+    a.set_density(w)
+    a.step(dt, 11)
+    saved_w, saved_s = a.density(), a.run_state()
+    a.close()
+    b = fresh()
+    b.set_density(saved_w)
+    b.set_run_state(saved_s)
+    b.step(dt, 19)
+    assert np.array_equal(b.density(), ref.density())
+    mb, mr = b.moments(), ref.moments()
+    assert (mb["A_re"], mb["A_im"], mb["step"]) == (mr["A_re"], mr["A_im"], mr["step"])
+    ref.close()
+    b.close()

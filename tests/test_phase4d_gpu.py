@@ -61,10 +61,12 @@ COUPLED = P4.Ham4(P4.H4_POTENTIAL, a=1.0, b=0.6, c=0.4)
 
 
 @pytest.mark.parametrize("shape,tiles", [((12, 10, 9, 11), None), ((20, 18, 13, 12), (4, 4, 4, 4)),
-                                         ((20, 18, 13, 12), (8, 6, 5, 4)), ((6, 5, 6, 5), None)])
+                                         ((20, 18, 13, 12), (8, 6, 5, 4)), ((6, 5, 6, 5), None),
+                                         ((130, 6, 5, 6), None)])
 def test_one_step_coupled(B, shape, tiles):
     """One step with the coupled potential: ragged tiles, a tile spanning a
-    whole periodic axis (footprints wrapping back into it), several tiles."""
+    whole periodic axis (footprints wrapping back into it), several tiles, and
+    x lines too long to be staged in LDS (130 nodes: the global-memory solve)."""
     axes = axes4(*shape)
     w = start(axes, 90)
     got, _ = gpu_run(B, axes, COUPLED, w, 0.3, 1, tiles)
