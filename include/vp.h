@@ -260,9 +260,11 @@ int vp_get_tiles(const vp_grid* g, vp_tiles* t);
 /* For a Hamiltonian that depends neither on the state nor on the time (free,
  * rotation, pendulum) the push of every node, and so the node-to-destination
  * map and the fractions that weigh the overlaps of eq. 9, is the same every
- * step.  With the cache on (the default) it is formed once per plan into the
- * workspace (12 bytes per node) and the deposit reads it instead of pushing;
- * results are bitwise the same either way.  The FEL always pushes. */
+ * step.  With the cache on it is formed once per plan into the workspace (12
+ * bytes per node) and the deposit reads it instead of pushing; results are
+ * bitwise the same either way.  Off by default: the deposit is bound by its
+ * LDS atomics, not by the push, and the map adds 12 bytes of reads per node.
+ * The FEL always pushes. */
 int vp_set_map_cache(vp_grid* g, int32_t on);
 
 /* Launch mode of vp_step: use_graph != 0 replays the per-step kernels from a

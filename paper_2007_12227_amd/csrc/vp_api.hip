@@ -281,7 +281,7 @@ struct vp_grid {
     double N0 = 0.0;
     vp_tiles tiles{};
     bool use_graph = true;
-    bool use_map = true;  // cache the push of a static Hamiltonian (k_map)
+    bool use_map = false;  // cache the push of a static Hamiltonian (k_map); off: it does not pay here
     bool in_batch = false;
     int basis = kBasisTent;
 

@@ -121,7 +121,8 @@ def test_full_run_fel_gaussian_1024(B):
     there the error relative to ||w0||_1 is held to twice the worst unbiased
     FP32 run (1.1e-6, 3.4e-7, 1.2e-7 at steps 1000, 1500, 2000), which the
     biased runs fail, and the standard number is printed.  The field is held
-    to 1e-3 relative at every checkpoint."""
+    to 10x the worst unbiased run's field error (at least 1e-6) at every
+    checkpoint: 3.4e-6 to 4.4e-6, which the biased runs (2e-5 to 6e-5) fail."""
     spread = fp32_run_spread()
     chaotic = chaotic_checkpoints()
     assert chaotic == [1000, 1500, 2000], chaotic
@@ -132,7 +133,7 @@ def test_full_run_fel_gaussian_1024(B):
             assert r["err_w0"] <= 2.0 * err_w0_max, (s, r, err_w0_max)
         else:
             assert r["err"] <= min(1e-4, 10.0 * max(err_max, 1e-8)), (s, r, err_max)
-        assert r["dA"] <= 1e-3, (s, r)
+        assert r["dA"] <= max(1e-6, 10.0 * spread[s][2]), (s, r, spread[s][2])
     assert res[2000]["seam_err_w0"] <= 2.0 * spread[2000][1]
 
 
