@@ -326,8 +326,8 @@ def main():
                     help="deposit launch shape COLSxROWSxTHREADS for the tuned path instead of autotuning "
                          "(uniform dispatches for profiling)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (untuned, no graph) run")
-    ap.add_argument("--no-map", action="store_true",
-                    help="push every step instead of reading the cached push map (for comparison)")
+    ap.add_argument("--map", action="store_true",
+                    help="read the cached push map instead of pushing every step (for comparison; off by default)")
     ap.add_argument("--basis", choices=("tent", "quadratic", "cubic"), default="tent",
                     help="basis functions of the timed workload (quadratic, cubic: for profiling their kernels)")
     args = ap.parse_args()
@@ -362,8 +362,8 @@ def main():
     def grid_of(inst):
         g = binding.grid_for(inst)
         g.set_basis(basis)
-        if args.no_map:
-            g.set_map_cache(False)
+        if args.map:
+            g.set_map_cache(True)
         return g
 
 
@@ -418,7 +418,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "nx": args.n, "np": args.n, "dt": inst.dt,
                    "a": 1.0, "deposit_tiles": tiles["k1"], "deposit_threads": tiles["threads"],
-                   "launch": "hip-graph", "push_map_cached": not args.no_map},
+                   "launch": "hip-graph", "push_map_cached": args.map},
         "plain": None if plain is None else {"value": plain, "ms_per_step": 1e3 * plain_s / args.steps,
                                              "speedup": value / plain},
         "kernels_us": kus,
