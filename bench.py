@@ -152,6 +152,8 @@ def bench_batched(binding, steps, count):
     tune_us = batch.autotune()
     sec = timed()
     cfg = batch.config()
+    # per-kernel durations of the batched launches (events on the dispatches)
+    kus = dict(zip(KERNELS, batch.step_timed(min(steps, 40))))
     batch.close()
     for g in grids:
         g.close()
@@ -166,9 +168,19 @@ def bench_batched(binding, steps, count):
         torch.cuda.synchronize()
         plain_sec += time.perf_counter() - t1
         g.close()
-    return {"workload": f"batched_{count}_pendulum_64_1024", "steps": steps,
+    workload = f"batched_{count}_pendulum_64_1024"
+    alg = ALG_BYTES_PER_NODE * sum(i.nodes for i in insts)  # per launch of either kernel
+    prof_us, traffic = batched_profile(workload, cfg)
+    roof = {"bound": "hbm", "kernel": "k_deposit", "achieved": alg / (kus["k_deposit"] * 1e-6) / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": alg / (kus["k_deposit"] * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "traffic": traffic, "alg_bytes_per_launch": alg, "kernel_us_events": kus["k_deposit"],
+            "kernel_us_rocprof": prof_us,
+            "frac_rocprof": None if prof_us is None else alg / (prof_us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+    return {"workload": workload, "steps": steps,
             "total_nodes": sum(i.nodes for i in insts), "value": work / sec,
             "ms_per_step": 1e3 * sec / steps, "launch": cfg, "autotune_us_per_step": tune_us,
+            "kernels_us": kus, "roofline": roof,
+            "kernel_roofline_frac": {k: alg / (v * 1e-6) / 1e9 / HBM_PEAK_GBS for k, v in kus.items()},
             "untuned": {"value": work / untuned_sec, "ms_per_step": 1e3 * untuned_sec / steps, "launch": untuned_cfg},
             "plain_value": work / plain_sec, "speedup_vs_plain": plain_sec / sec}
 
@@ -279,6 +291,34 @@ def measured_traffic(kernel, workload, shape):
     if kernel == "k_deposit" and vals.get("deposit_shape") != shape:
         return None
     return float(vals["bytes_per_launch"])
+
+
+def batched_profile(workload, cfg):
+    """(mean deposit duration in us, HBM bytes per deposit launch) of the
+    batched launch in configuration `cfg` from the committed rocprofv3
+    summaries of this workload, each None unless it was taken of the current
+    kernel sources in the same launch configuration (dispatch grid, workgroup)."""
+    grid = (cfg["deposit_grid"] or cfg["deposit_tiles"]) * cfg["deposit_threads"]
+    key = ("k_deposit<4>", str(grid), str(cfg["deposit_threads"]))
+    sha = kernel_source_sha()
+    us = traffic = None
+    path = os.path.join(PROFILES, f"step_kernels_{workload}_kernel_trace.txt")
+    if os.path.exists(path):
+        text = open(path).read()
+        if f"kernel source sha256[:16]: {sha}" in text:
+            for line in text.splitlines():
+                f = line.split()
+                if len(f) == 5 and tuple(f[:3]) == key:
+                    us = float(f[4])
+    path = os.path.join(PROFILES, f"k_deposit_k_solve_{workload}_hbm_traffic.txt")
+    if os.path.exists(path):
+        text = open(path).read()
+        if f"kernel_source_sha256_16: {sha}" in text:
+            for line in text.splitlines():
+                f = line.split()
+                if len(f) == 7 and f[0] == "config:" and tuple(f[1:4]) == key:
+                    traffic = float(f[5])
+    return us, traffic
 
 
 def cpu_baseline(inst, steps):

@@ -309,6 +309,12 @@ int vp_batch_config(const vp_batch* b, int32_t* deposit_grid, int32_t* deposit_t
  * VP_ERANGE, without stepping, once a completed earlier batch step has set the
  * range flag of any of its grids (vp_moments of each grid names which). */
 int vp_batch_step(vp_batch* b, int64_t nsteps);
+/* Measurement helper: nsteps batch steps exactly as vp_batch_step with direct
+ * launches (the batch's launch configuration), with HIP events attached to the
+ * dispatches; us[0] and us[1] receive the mean duration in microseconds of
+ * the batch's deposit launch and of its solve launch, as vp_step_timed.
+ * Waits for the stream.  VP_EINVAL for nsteps < 1, VP_ERANGE as vp_batch_step. */
+int vp_batch_step_timed(vp_batch* b, int64_t nsteps, double us[2]);
 /* Release the batch (the grids stay; they can be stepped alone again). */
 int vp_batch_destroy(vp_batch* b);
 

@@ -114,6 +114,7 @@ def lib(load_torch: bool = True):
     L.vp_autotune.argtypes = [C.c_void_p, C.c_double, P(C.c_double)]
     L.vp_batch_create.argtypes = [P(C.c_void_p), C.c_int32, P(C.c_double), P(C.c_void_p)]
     L.vp_batch_step.argtypes = [C.c_void_p, C.c_int64]
+    L.vp_batch_step_timed.argtypes = [C.c_void_p, C.c_int64, P(C.c_double)]
     L.vp_batch_destroy.argtypes = [C.c_void_p]
     L.vp_batch_autotune.argtypes = [C.c_void_p, P(C.c_double)]
     L.vp_batch_config.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
@@ -320,6 +321,12 @@ class Batch:
 
     def step(self, n: int = 1):
         check(lib().vp_batch_step(self._h, int(n)))
+
+    def step_timed(self, n: int) -> tuple[float, float]:
+        """n batch steps with per-kernel HIP events: mean (deposit, solve) microseconds."""
+        us = (C.c_double * 2)()
+        check(lib().vp_batch_step_timed(self._h, int(n), us))
+        return us[0], us[1]
 
     def autotune(self, cached: bool = False) -> float:
         """Pick the batch's launch configuration by timing (vp_batch_autotune);

@@ -238,6 +238,37 @@ struct LaunchList {
         }
         return post_range_copy();
     }
+    // Run n steps from relative parity rp with direct launches and HIP events
+    // attached to the dispatches: us[0] the mean duration of the deposit
+    // phase (for the Runge-Kutta FEL from the stage sums before it), us[1]
+    // of the solve phase (for the FEL up to the field update after it).
+    // Waits for the stream.
+    int timed(int64_t n, int rp, double us[2]) {
+        Events ev((size_t)(4 * n));
+        HIP_TRY(ev.create());
+        for (int64_t s = 0; s < n; ++s) {
+            const int par = (int)((rp + s) & 1);
+            hipEvent_t* e = &ev[4 * s];
+            if (has_rk4) {
+                HIP_TRY(launch_fel_stage(args(d_off2, total2, par), total2, stream, e[0], nullptr));
+                HIP_TRY(launch_fel_field(args(d_off2, ninst, par, 1), stream));
+            }
+            HIP_TRY(launch_deposit(args(d_off1, total1, par), dep_grid(), lds1, threads1, stream, basis,
+                                   has_rk4 ? nullptr : e[0], e[1]));
+            HIP_TRY(launch_solve(args(d_off2, total2, par), total2, stream, solve, e[2], has_fel ? nullptr : e[3]));
+            if (has_fel) HIP_TRY(launch_fel_field(args(d_off2, ninst, par), stream, nullptr, e[3]));
+        }
+        HIP_TRY(hipEventSynchronize(ev[4 * n - 1]));
+        double t[2] = {0.0, 0.0};
+        for (int64_t s = 0; s < n; ++s)
+            for (int k = 0; k < 2; ++k) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, ev[4 * s + 2 * k], ev[4 * s + 2 * k + 1]));
+                t[k] += ms;
+            }
+        for (int k = 0; k < 2; ++k) us[k] = 1000.0 * t[k] / n;
+        return post_range_copy();
+    }
 };
 
 // Small pinned host word for a launch list's range flag.
@@ -735,36 +766,7 @@ int vp_step_timed(vp_grid* g, double dt, int64_t nsteps, double us[2]) {
     if (g->in_batch) return fail(VP_ESTATE, "grid belongs to a live batch");
     int rc = prepare(g, dt);
     if (rc) return rc;
-    // per step: start and end of the deposit phase (for the Runge-Kutta FEL
-    // from the stage sums before the deposit), start and end of the solve
-    // phase (for the FEL up to the field update after it), each recorded with
-    // the kernel's own dispatch
-    Events ev((size_t)(4 * nsteps));
-    HIP_TRY(ev.create());
-    const LaunchList& L = g->list;
-    for (int64_t s = 0; s < nsteps; ++s) {
-        const int par = (int)((g->parity + s) & 1);
-        hipEvent_t* e = &ev[4 * s];
-        if (L.has_rk4) {
-            HIP_TRY(launch_fel_stage(L.args(L.d_off2, L.total2, par), L.total2, g->stream, e[0], nullptr));
-            HIP_TRY(launch_fel_field(L.args(L.d_off2, L.ninst, par, 1), g->stream));
-        }
-        HIP_TRY(launch_deposit(L.args(L.d_off1, L.total1, par), L.total1, L.lds1, L.threads1, g->stream, L.basis,
-                               L.has_rk4 ? nullptr : e[0], e[1]));
-        HIP_TRY(launch_solve(L.args(L.d_off2, L.total2, par), L.total2, g->stream, L.solve, e[2],
-                             L.has_fel ? nullptr : e[3]));
-        if (L.has_fel) HIP_TRY(launch_fel_field(L.args(L.d_off2, L.ninst, par), g->stream, nullptr, e[3]));
-    }
-    HIP_TRY(hipEventSynchronize(ev[4 * nsteps - 1]));
-    double t[2] = {0.0, 0.0};
-    for (int64_t s = 0; s < nsteps; ++s)
-        for (int k = 0; k < 2; ++k) {
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, ev[4 * s + 2 * k], ev[4 * s + 2 * k + 1]));
-            t[k] += ms;
-        }
-    for (int k = 0; k < 2; ++k) us[k] = 1000.0 * t[k] / nsteps;
-    rc = L.post_range_copy();
+    rc = g->list.timed(nsteps, g->parity, us);
     if (rc) return rc;
     g->parity = (int)((g->parity + nsteps) & 1);
     g->step += nsteps;
@@ -1176,6 +1178,22 @@ int vp_batch_step(vp_batch* b, int64_t nsteps) {
                                "(vp_moments names the grid)");
     if (nsteps == 0) return VP_OK;
     int rc = b->list.run(nsteps, (int)(b->steps_done & 1), true);
+    if (rc) return rc;
+    b->steps_done += nsteps;
+    for (auto* g : b->grids) {
+        g->parity = (int)((g->parity + nsteps) & 1);
+        g->step += nsteps;
+    }
+    return VP_OK;
+}
+
+int vp_batch_step_timed(vp_batch* b, int64_t nsteps, double us[2]) {
+    if (!b || !us) return fail(VP_EINVAL, "null argument");
+    if (nsteps <= 0) return fail(VP_EINVAL, "need at least one step");
+    if (b->list.range_seen())
+        return fail(VP_ERANGE, "a deposit cell sum of a batched grid left the fixed-point range "
+                               "(vp_moments names the grid)");
+    int rc = b->list.timed(nsteps, (int)(b->steps_done & 1), us);
     if (rc) return rc;
     b->steps_done += nsteps;
     for (auto* g : b->grids) {

@@ -134,3 +134,27 @@ def test_batch_autotune_keeps_states_and_results(B):
         assert np.array_equal(g.density(), g2.density())
         g.close()
         g2.close()
+
+
+def test_batch_timed_steps_equal_batch_steps(B):
+    """vp_batch_step_timed advances the batch exactly as vp_batch_step (the
+    same launches, direct instead of from graphs, parity kept across calls),
+    FEL with both integrators included, and reports positive kernel times."""
+    insts = batch_instances(6, seed=42, steps=12, n_min=48, n_max=200)
+    insts += [fel_gaussian(96, 12, npp=128)]
+    rk = fel_gaussian(80, 12, npp=64)
+    insts.append(dataclasses.replace(rk, ham=dataclasses.replace(rk.ham, integrator=FEL_RK4)))
+    grids = [B.grid_for(i) for i in insts]
+    batch = B.Batch(grids, [i.dt for i in insts])
+    batch.step(3)
+    dep_us, solve_us = batch.step_timed(5)
+    assert dep_us > 0 and solve_us > 0
+    batch.step(4)
+    with pytest.raises(B.VpError) as e:
+        batch.step_timed(0)
+    assert e.value.code == B.VP_EINVAL
+    batch.close()
+    for k, (g, inst) in enumerate(zip(grids, insts)):
+        assert np.array_equal(g.density(), alone(B, inst, 12)), k
+        assert g.moments()["step"] == 12
+        g.close()
