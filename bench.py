@@ -188,21 +188,15 @@ def bench_batched(binding, steps, count):
 def bench_phase4d(binding, n, npp, steps):
     """The 2D2V phase space (x, y periodic, p_x, p_y in [-3, 3] open), n^2 x npp^2
     nodes, coupled potential V = -cos x - 0.6 cos y - 0.4 cos(x - y), dt 0.05,
-    a noisy Gaussian start: steps timed after the same number untimed."""
-    import math
-
+    a noisy near-equilibrium start: steps timed after the same number untimed."""
     import numpy as np
     import torch
 
-    from paper_2007_12227_amd.inputs import Axis
-    axes = (Axis(-math.pi, math.pi, n, True), Axis(-math.pi, math.pi, n, True), Axis(-3.0, 3.0, npp, False),
-            Axis(-3.0, 3.0, npp, False))
+    from paper_2007_12227_amd.inputs import phase4d_axes, phase4d_thermal
+    axes = phase4d_axes(n, npp)
     g = binding.Grid4(axes)
     g.set_hamiltonian(binding.H_PENDULUM, 1.0, 0.6, 0.4)
-    rng = np.random.default_rng(7)
-    x, y, px, py = (a.nodes() for a in axes)
-    w = (np.exp(-(py[:, None, None, None] ** 2 + px[None, :, None, None] ** 2) / (2 * 0.8 ** 2))
-         * np.exp(-(np.cos(y)[None, None, :, None] + np.cos(x)[None, None, None, :])) * rng.uniform(0.9, 1.1, g.shape))
+    w = phase4d_thermal(axes)
     g.set_density(w.astype(np.float32))
     g.step(0.05, steps)
     torch.cuda.synchronize()

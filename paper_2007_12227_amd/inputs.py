@@ -182,3 +182,23 @@ def request_trace(count: int = 1000, seed: int = 5, rate: float = 100.0,
         steps = int(g.integers(steps_min, steps_max + 1))
         out.append(Request(rid, t, kind, n, steps, int(g.integers(0, 2**31 - 1))))
     return out
+
+
+# --- the 2D2V phase space (x, y, p_x, p_y) -----------------------------------
+
+def phase4d_axes(n: int, npp: int, pmax: float = 3.0) -> tuple[Axis, Axis, Axis, Axis]:
+    """x, y periodic on [-pi, pi) with n nodes; p_x, p_y open on [-pmax, pmax] with npp nodes."""
+    return (Axis(-math.pi, math.pi, n, True), Axis(-math.pi, math.pi, n, True),
+            Axis(-pmax, pmax, npp, False), Axis(-pmax, pmax, npp, False))
+
+
+def phase4d_thermal(axes, seed: int = 7, sigma: float = 0.8) -> np.ndarray:
+    """A state near equilibrium in V = -cos x - cos y: exp(-|p|^2 / (2 sigma^2))
+    exp(cos x + cos y) at the nodes, times seeded U[0.9, 1.1] noise per node.
+    float64 [n_py][n_px][n_y][n_x]."""
+    x, y, px, py = axes
+    g = rng(seed)
+    shape = (py.n, px.n, y.n, x.n)
+    w = (np.exp(-(py.nodes()[:, None, None, None] ** 2 + px.nodes()[None, :, None, None] ** 2) / (2 * sigma**2))
+         * np.exp(np.cos(y.nodes())[None, None, :, None] + np.cos(x.nodes())[None, None, None, :]))
+    return w * g.uniform(0.9, 1.1, shape)

@@ -3,13 +3,16 @@ the four-dimensional oracle (oracle/phase4d.py) on the same seeded inputs.
 Bars as in 2-D: relative L1 <= 1e-5 (and every node within 1e-5 of the
 largest weight) after one step, <= 1e-4 after a run."""
 import math
+import os
 
 import numpy as np
 import pytest
 
 from _parity import assert_step_parity
 from oracle import phase4d as P4
-from paper_2007_12227_amd.inputs import H_FREE, H_PENDULUM, Axis, rng
+from paper_2007_12227_amd.inputs import H_FREE, H_PENDULUM, Axis, phase4d_axes, phase4d_thermal, rng
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_phase4d_coupled_48.npz")
 
 pytestmark = pytest.mark.gpu
 
@@ -129,6 +132,31 @@ def test_larger_lattice_one_step(B):
     w = start(axes, 95)
     got, _ = gpu_run(B, axes, COUPLED, w, 0.2, 1)
     assert_step_parity(got, P4.step(axes, COUPLED, 0.2, w.astype(np.float64)), label="32x32x24x24")
+
+
+def test_full_size_one_step_against_stored_oracle(B):
+    """The benchmark's 2D2V workload (48^4 nodes, coupled potential, dt 0.05,
+    default tiles: 324 tiles, two rounds on the device): one step against the
+    FP64 oracle's stored samples (tests/golden/make_phase4d_golden.py), a
+    strided sub-lattice and one full line along each axis next to tile seams,
+    relative L1 and node-wise within 1e-5; the total weight within 1e-6 of the
+    oracle's full-array sum."""
+    ref = np.load(GOLDEN)
+    n, npp, dt, s = int(ref["n"]), int(ref["np"]), float(ref["dt"]), int(ref["stride"])
+    axes = phase4d_axes(n, npp)
+    g = B.Grid4(axes)
+    g.set_hamiltonian(H_PENDULUM, *(float(v) for v in ref["ham"]))
+    g.set_density(phase4d_thermal(axes).astype(np.float32))
+    g.step(dt, 1)
+    got = g.density().astype(np.float64)
+    m = g.moments()
+    g.close()
+    assert_step_parity(got[::s, ::s, ::s, ::s], ref["sample"], label="48^4 strided sample")
+    py, px, y, x = (int(v) for v in ref["anchor"])
+    for name, line in (("line_x", got[py, px, y, :]), ("line_y", got[py, px, :, x]),
+                       ("line_px", got[py, :, y, x]), ("line_py", got[:, px, y, x])):
+        assert_step_parity(line, ref[name], label=f"48^4 {name}")
+    assert abs(m["sum_w"] - float(ref["sum"])) <= 1e-6 * float(ref["sum_w0"])
 
 
 def test_refusals(B):
