@@ -188,7 +188,8 @@ def bench_batched(binding, steps, count):
 def bench_phase4d(binding, n, npp, steps):
     """The 2D2V phase space (x, y periodic, p_x, p_y in [-3, 3] open), n^2 x npp^2
     nodes, coupled potential V = -cos x - 0.6 cos y - 0.4 cos(x - y), dt 0.05,
-    a noisy near-equilibrium start: steps timed after the same number untimed."""
+    a noisy near-equilibrium start: steps timed after the same number untimed,
+    with the starting deposit tile and then with the autotuned one."""
     import numpy as np
     import torch
 
@@ -198,21 +199,32 @@ def bench_phase4d(binding, n, npp, steps):
     g.set_hamiltonian(binding.H_PENDULUM, 1.0, 0.6, 0.4)
     w = phase4d_thermal(axes)
     g.set_density(w.astype(np.float32))
-    g.step(0.05, steps)
-    torch.cuda.synchronize()
     s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    g.step(0.05, steps)
-    e1.record(s)
-    torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) / 1e3
+
+    def timed():
+        g.step(0.05, steps)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        g.step(0.05, steps)
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    untuned_tiles = g.tiles()
+    untuned_sec = timed()
+    tune_us = g.autotune(0.05)
+    sec = timed()
     kus = g.step_timed(0.05, min(steps, 10))
     nodes = n * n * npp * npp
+    tiles = g.tiles()
     g.close()
     return {"workload": f"phase4d_coupled_{n}x{n}x{npp}x{npp}", "steps": steps, "nodes": nodes,
             "value": nodes * steps / sec, "ms_per_step": 1e3 * sec / steps,
-            "kernels_us": {"k_deposit4": kus[0], "k_solve4 (four axes)": kus[1]}}
+            "tiles": tiles, "autotune_us_per_step": tune_us,
+            "kernels_us": {"k_deposit4": kus[0], "k_solve4 (four axes)": kus[1]},
+            "untuned": {"tiles": untuned_tiles, "value": nodes * steps / untuned_sec,
+                        "ms_per_step": 1e3 * untuned_sec / steps}}
 
 
 def bench_served(binding, nreq, load, capacity, budget_gib):

@@ -397,6 +397,8 @@ int vp4_set_hamiltonian(vp4_grid* g, const vp4_hamiltonian* h);
 /* Deposit tile (nodes along x, y, p_x, p_y; at least 4 or the whole axis;
  * 8 bytes of LDS per node of the tile).  Results do not depend on it. */
 int vp4_set_tiles(vp4_grid* g, const int32_t tile[4]);
+/* The current deposit tile (nodes along x, y, p_x, p_y). */
+int vp4_get_tiles(const vp4_grid* g, int32_t tile[4]);
 /* Set / copy out the weights of eq. 4 (device pointer if on_device, else host).
  * Set: VP_ENONFINITE for a NaN/Inf weight; records max|w| (the deposit's
  * fixed-point exponent).  Get: waits; VP_ERANGE (after copying) if a deposit
@@ -409,6 +411,16 @@ int vp4_step(vp4_grid* g, double dt, int64_t nsteps);
 /* As vp4_step, with the mean microseconds of the deposit (us[0]) and of the
  * four solves (us[1]) per step, from events recorded with the kernels. */
 int vp4_step_timed(vp4_grid* g, double dt, int64_t nsteps, double us[2]);
+/* Pick the deposit tile by timing: up to twelve candidate tiles (16x16x8x8
+ * and smaller or flatter ones, cut to the lattice and to the device's LDS),
+ * each over a few steps of size dt from the current state, which is restored
+ * (with the range flag).  The fastest is kept (a candidate must beat the
+ * incumbent by 2%) and best_us receives its time per step; results do not
+ * depend on the choice.  The choice is cached per shape class (push kind,
+ * half-octave axis lengths); best_us == NULL applies a cached choice without
+ * timing (VP_ESTATE if there is none).  VP_ESTATE before density and
+ * Hamiltonian. */
+int vp4_autotune(vp4_grid* g, double dt, double* best_us);
 /* Diagnostics (vp4_moments_t); waits.  VP_ENONFINITE / VP_ERANGE after filling *out. */
 int vp4_moments(vp4_grid* g, vp4_moments_t* out);
 

@@ -140,6 +140,8 @@ def lib(load_torch: bool = True):
     L.vp4_get_density.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
     L.vp4_step.argtypes = [C.c_void_p, C.c_double, C.c_int64]
     L.vp4_step_timed.argtypes = [C.c_void_p, C.c_double, C.c_int64, P(C.c_double)]
+    L.vp4_autotune.argtypes = [C.c_void_p, C.c_double, P(C.c_double)]
+    L.vp4_get_tiles.argtypes = [C.c_void_p, P(C.c_int32)]
     L.vp4_moments.argtypes = [C.c_void_p, P(Moments4)]
     for name in declared_functions():
         if name not in ("vp_workspace_bytes", "vp4_workspace_bytes", "vp_status_string", "vp_last_error"):
@@ -407,6 +409,21 @@ class Grid4:
 
     def set_tiles(self, tile):
         check(lib().vp4_set_tiles(self._h, (C.c_int32 * 4)(*[int(v) for v in tile])))
+
+    def tiles(self) -> tuple:
+        t = (C.c_int32 * 4)()
+        check(lib().vp4_get_tiles(self._h, t))
+        return tuple(t)
+
+    def autotune(self, dt: float, cached: bool = False) -> float:
+        """Pick the deposit tile by timing (vp4_autotune); cached=True applies
+        the choice made for the same shape class (returns 0.0)."""
+        if cached:
+            check(lib().vp4_autotune(self._h, float(dt), None))
+            return 0.0
+        us = C.c_double()
+        check(lib().vp4_autotune(self._h, float(dt), C.byref(us)))
+        return us.value
 
     def set_density(self, w):
         a = np.ascontiguousarray(w, dtype=np.float32)

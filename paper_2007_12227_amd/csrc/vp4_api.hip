@@ -7,6 +7,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/vp.h"
@@ -350,6 +353,12 @@ int vp4_set_tiles(vp4_grid* g, const int32_t T[4]) {
     return VP_OK;
 }
 
+int vp4_get_tiles(const vp4_grid* g, int32_t T[4]) {
+    if (!g || !T) return fail4(VP_EINVAL, "null argument");
+    for (int d = 0; d < 4; ++d) T[d] = g->T[d];
+    return VP_OK;
+}
+
 int vp4_set_density(vp4_grid* g, const float* w, int32_t on_device) {
     if (!g || !w) return fail4(VP_EINVAL, "null argument");
     float* dst = g->at<float>(g->parity ? g->L.w1 : g->L.w0);
@@ -438,6 +447,108 @@ int vp4_step_timed(vp4_grid* g, double dt, int64_t nsteps, double us[2]) {
     for (int k = 0; k < 2; ++k) us[k] = 1000.0 * t[k] / nsteps;
     g->parity = (int)((g->parity + nsteps) & 1);
     g->step += nsteps;
+    return VP_OK;
+}
+
+int vp4_autotune(vp4_grid* g, double dt, double* best_us) {
+    if (!g) return fail4(VP_EINVAL, "null grid");
+    int rc = prepare4(g, dt);
+    if (rc) return rc;
+    // shape class: the push kind and the half-octave axis lengths
+    std::array<int, 5> key{g->ham.kind == VP_H_FREE ? 0 : 1};
+    for (int d = 0; d < 4; ++d) key[d + 1] = (int)lround(2.0 * log2((double)g->ax[d].n));
+    static std::mutex mu;
+    static std::map<std::array<int, 5>, std::array<int32_t, 4>> cache;
+    auto apply = [&](const int32_t (&T)[4]) -> int {
+        for (int d = 0; d < 4; ++d) g->T[d] = T[d];
+        g->plan_valid = false;
+        return prepare4(g, dt);
+    };
+    if (!best_us) {
+        std::array<int32_t, 4> t;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto it = cache.find(key);
+            if (it == cache.end()) return fail4(VP_ESTATE, "no tuned choice for this shape class yet");
+            t = it->second;
+        }
+        int32_t T[4];
+        for (int d = 0; d < 4; ++d) T[d] = std::min(t[d], g->ax[d].n);
+        if (lds4(T) > g_max_lds4) return fail4(VP_ESTATE, "the cached tile does not fit this device");
+        return apply(T);
+    }
+    // candidate tiles (x, y, p_x, p_y), cut to the lattice; the first is the
+    // starting tile.  Smaller tiles than the largest that fits the LDS pay off
+    // where the larger ones leave a last round of workgroups mostly empty.
+    static const int32_t cand[][4] = {{16, 16, 8, 8}, {16, 12, 8, 8}, {12, 16, 8, 8}, {16, 16, 8, 6},
+                                      {16, 16, 6, 8}, {16, 16, 8, 4}, {16, 8, 8, 8},  {24, 16, 8, 4},
+                                      {24, 12, 8, 8}, {32, 16, 8, 4}, {24, 24, 8, 4}, {16, 16, 12, 6}};
+    std::vector<std::array<int32_t, 4>> shapes;
+    for (const auto& c : cand) {
+        std::array<int32_t, 4> t;
+        for (int d = 0; d < 4; ++d) t[d] = std::min(c[d], g->ax[d].n);
+        int32_t T[4] = {t[0], t[1], t[2], t[3]};
+        if (lds4(T) > g_max_lds4 || std::find(shapes.begin(), shapes.end(), t) != shapes.end()) continue;
+        shapes.push_back(t);
+    }
+    // the state is saved and restored around the timed steps
+    float* w = g->at<float>(g->parity ? g->L.w1 : g->L.w0);
+    const size_t bytes = g->L.nodes * 4;
+    float* save = nullptr;
+    HIP_TRY4(hipMalloc(&save, bytes));
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
+        rc = fail4(VP_EHIP, "hipEventCreate failed");
+    if (rc == VP_OK && hipMemcpyAsync(save, w, bytes, hipMemcpyDeviceToDevice, g->stream) != hipSuccess)
+        rc = fail4(VP_EHIP, "state copy failed");
+    // the range flag as the caller's own steps left it, put back afterwards
+    uint32_t* flag = g->at<uint32_t>(g->L.counters) + kRangeFlag;
+    uint32_t flag0 = 0;
+    if (rc == VP_OK && (hipMemcpyAsync(&flag0, flag, sizeof flag0, hipMemcpyDeviceToHost, g->stream) != hipSuccess ||
+                        hipStreamSynchronize(g->stream) != hipSuccess))
+        rc = fail4(VP_EHIP, "flag copy failed");
+    const int32_t T0[4] = {g->T[0], g->T[1], g->T[2], g->T[3]};
+    int32_t best_T[4] = {T0[0], T0[1], T0[2], T0[3]};
+    double best = 1e300;
+    for (size_t k = 0; k < shapes.size() && rc == VP_OK; ++k) {
+        const int32_t T[4] = {shapes[k][0], shapes[k][1], shapes[k][2], shapes[k][3]};
+        rc = apply(T);
+        // two untimed and four timed steps: an even count, so the state ends
+        // in the buffer it started in, and is restored from the copy
+        for (int s = 0; s < 2 && rc == VP_OK; ++s) rc = enqueue_step4(g, (g->parity + s) & 1, nullptr);
+        if (rc == VP_OK && hipEventRecord(ev[0], g->stream) != hipSuccess) rc = fail4(VP_EHIP, "hipEventRecord");
+        for (int s = 0; s < 4 && rc == VP_OK; ++s) rc = enqueue_step4(g, (g->parity + s) & 1, nullptr);
+        float ms = 0.f;
+        if (rc == VP_OK && (hipEventRecord(ev[1], g->stream) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                            hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
+            rc = fail4(VP_EHIP, "timing events");
+        if (rc == VP_OK && hipMemcpyAsync(w, save, bytes, hipMemcpyDeviceToDevice, g->stream) != hipSuccess)
+            rc = fail4(VP_EHIP, "state copy failed");
+        const double us = 1000.0 * ms / 4;
+        // a candidate must beat the incumbent by 2% (timing noise)
+        if (rc == VP_OK && us < 0.98 * best) {
+            best = us;
+            for (int d = 0; d < 4; ++d) best_T[d] = T[d];
+        }
+    }
+    (void)hipMemcpyAsync(w, save, bytes, hipMemcpyDeviceToDevice, g->stream);  // whatever failed, the state returns
+    if (rc == VP_OK && hipMemcpyAsync(flag, &flag0, sizeof flag0, hipMemcpyHostToDevice, g->stream) != hipSuccess)
+        rc = fail4(VP_EHIP, "flag copy failed");
+    (void)hipStreamSynchronize(g->stream);
+    (void)hipFree(save);
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc) {
+        (void)apply(T0);
+        return rc;
+    }
+    rc = apply(best_T);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        cache[key] = {best_T[0], best_T[1], best_T[2], best_T[3]};
+    }
+    *best_us = best;
     return VP_OK;
 }
 

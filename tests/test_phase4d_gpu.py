@@ -134,6 +134,35 @@ def test_larger_lattice_one_step(B):
     assert_step_parity(got, P4.step(axes, COUPLED, 0.2, w.astype(np.float64)), label="32x32x24x24")
 
 
+def test_autotune_keeps_state_and_results(B):
+    """vp4_autotune times candidate tiles on the grid and restores its state:
+    the weights are untouched, stepping afterwards equals an untuned grid
+    bitwise, and a cached choice applies to a grid of the same shape class."""
+    axes = axes4(40, 36, 20, 22)
+    w = start(axes, 96)
+    g = B.Grid4(axes)
+    g.set_hamiltonian(H_PENDULUM, COUPLED.a, COUPLED.b, COUPLED.c)
+    g.set_density(w)
+    g.step(0.2, 1)
+    before = g.density()
+    us = g.autotune(0.2)
+    assert us > 0
+    tiles = g.tiles()
+    assert all(1 <= t <= n for t, n in zip(tiles, (40, 36, 20, 22)))
+    assert np.array_equal(g.density(), before)
+    assert g.moments()["step"] == 1
+    g.step(0.2, 3)
+    ref, _ = gpu_run(B, axes, COUPLED, w, 0.2, 4)
+    assert np.array_equal(g.density(), ref)
+    g.close()
+    g2 = B.Grid4(axes)
+    g2.set_hamiltonian(H_PENDULUM, COUPLED.a, COUPLED.b, COUPLED.c)
+    g2.set_density(w)
+    g2.autotune(0.2, cached=True)
+    assert g2.tiles() == tiles
+    g2.close()
+
+
 def test_full_size_one_step_against_stored_oracle(B):
     """The benchmark's 2D2V workload (48^4 nodes, coupled potential, dt 0.05,
     default tiles: 324 tiles, two rounds on the device): one step against the
