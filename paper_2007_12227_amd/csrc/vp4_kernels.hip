@@ -147,7 +147,9 @@ __global__ __launch_bounds__(kDeposit4Threads) void k_deposit4(Launch4Args A) {
             out_of_range |= (unsigned long long)v + (1ull << 46) >= (1ull << 47);
             A.dst[(((size_t)(O3 + e3) * n2 + (O2 + e2)) * n1 + (O1 + e1)) * n0 + (O0 + e0)] = (float)((double)v * inv);
         }
-        if (out_of_range) atomicOr(&I.counters[kRangeFlag], 1u);
+        // one flag write per wavefront that saw a cell out of range (an
+        // atomic per thread on one address would serialise the launch)
+        if (__any(out_of_range) && (threadIdx.x & 63) == 0) atomicOr(&I.counters[kRangeFlag], 1u);
         __syncthreads();
     }
 }

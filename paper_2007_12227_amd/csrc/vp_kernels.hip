@@ -477,7 +477,9 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
                 rr += carry ? 1 : 0;
             }
         }
-        if (out_of_range) {
+        // one flag write per wavefront that saw a cell out of range: an
+        // atomic per thread on one address would serialise the whole launch
+        if (__any(out_of_range) && (threadIdx.x & 63) == 0) {
             atomicOr(&I.counters[kRangeFlag], 1u);
             atomicOr(A.any_range, 1u);
         }

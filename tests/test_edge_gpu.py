@@ -160,6 +160,25 @@ def test_deposit_range_error_surfaces_everywhere(B):
     ok.close()
 
 
+def test_out_of_range_deposit_keeps_its_speed(B):
+    """A deposit whose cells all leave the fixed-point range raises the flag
+    once per wavefront, not once per thread (per-thread atomics on one word
+    serialised the whole launch, tens of times its normal duration)."""
+    x, p = pendulum_axes(1024, 1024)
+    w = (0.75 + 0.2 * rng(62).random((1024, 1024))).astype(np.float32)
+    g = grid(B, x, p, Hamiltonian(H_PENDULUM, a=1.0), w)
+    g.set_tiles((128, 128), 1024)
+    g.step_timed(0.02, 4)
+    normal, _ = g.step_timed(0.02, 8)
+    g.set_density(w)
+    g.set_fixed_point(-30)  # every cell far beyond the range
+    g.step_timed(0.02, 1)
+    flagged, _ = g.step_timed(0.02, 8)
+    print(f"deposit {normal:.1f} us in range, {flagged:.1f} us out of range", flush=True)
+    assert flagged < 3.0 * normal, (flagged, normal)
+    g.close()
+
+
 def test_fixed_point_exponent_is_validated(B):
     x, p = pendulum_axes(32, 32)
     g = B.Grid(x, p)
