@@ -22,8 +22,7 @@
  * lattice line along each axis.  Lambda^{-1} = M_x^{-1} (x) M_p^{-1} exactly,
  * so this is the paper's dense update to rounding.
  *
- * Readings where the paper is silent (each one is listed with its reason in
- * the design notes of the repository):
+ * Readings where the paper is silent, ambiguous or garbled:
  *  - force sign: Hamilton's equations x' = p, p' = -V'(x)  (eq. 2 is garbled);
  *  - pendulum V(x) = -a cos x; the symplectic integrator is drift-kick-drift;
  *  - the harmonic oscillator is advanced by the exact rotation of
