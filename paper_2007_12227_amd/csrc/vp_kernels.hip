@@ -124,20 +124,21 @@ __device__ inline void deposit_node(long long* acc, int j, int ii, float w, floa
     scatter_node<TAPS>(acc, j, ii, w, ku, fu, kv, fv, X0, Y0, tw, th, ldw);
 }
 
-// Quadratic basis: the taps of two sources of one column in consecutive rows
+// Spline bases: the taps of two sources of one column in consecutive rows
 // j0, j0 + 1 (a work unit's row pair, starting at an even lattice row) merged
-// into one 7 x 7 window when their whole cells agree along p and differ by at
-// most one along x (their drifts differ by dt h_p / h_x cells): 49 atomics
-// for the pair instead of 72.  A window cell's word is the first source's
+// into one (TAPS + 1) x (TAPS + 1) window when their whole cells agree along p
+// and differ by at most one along x (their drifts differ by dt h_p / h_x
+// cells): 49 atomics for a quadratic pair instead of 72, 81 for a cubic one
+// instead of 128.  A window cell's word is the first source's
 // tap rounded onto the fixed-point grid by the FMA with the 1.5 2^52
 // constant, then the second's added by a second FMA, which rounds that tap
 // onto the same integer grid (the first result is an integer of that
 // binade): each tap is still rounded once.  Other pairs are scattered source
-// by source.  (Measured: 7% off the quadratic deposit; slower for tents,
-// whose loop is instruction-bound, and for the cubic basis, whose second set
-// of taps does not fit the registers of 16 wavefronts per compute unit.)
+// by source.  (Measured: 7% off the quadratic deposit, 10% off the cubic one;
+// slower for tents, whose loop is bound by instruction issue.)
 template <int TAPS>
-__device__ inline void scatter_pair(long long* acc, int j0, int j1, int ii, float w0, float w1, int ku0, float fu0,
+__device__ __attribute__((always_inline)) inline void scatter_pair(long long* acc, int j0, int j1, int ii, float w0,
+                                                                   float w1, int ku0, float fu0,
                                     int kv0, float fv0, int ku1, float fu1, int kv1, float fv1, int X0, int Y0, int tw,
                                     int th, int ldw) {
 #pragma clang fp contract(off)
@@ -167,13 +168,13 @@ __device__ inline void scatter_pair(long long* acc, int j0, int j1, int ii, floa
         wq1[q] = (double)w1 * bp1[q];
     }
     long long* corner = acc + __umul24(row0 + PAD, ldw) + (col0 + PAD);
-#pragma unroll
+#pragma clang loop unroll(full)
     for (int c = 0; c <= TAPS; ++c) {
         // each source's x tap at window column c (its taps shifted by its offset)
         const double e0 = d0 ? (c >= 1 ? bx0[c - 1] : 0.0) : (c < TAPS ? bx0[c] : 0.0);
         const double e1 = d1 ? (c >= 1 ? bx1[c - 1] : 0.0) : (c < TAPS ? bx1[c] : 0.0);
         unsigned long long* colp = (unsigned long long*)(corner + c);
-#pragma unroll
+#pragma clang loop unroll(full)
         for (int d = 0; d <= TAPS; ++d) {
             double v = kFixMagic;
             if (d < TAPS) v = fma(wq0[d], e0, v);
@@ -193,8 +194,9 @@ __device__ inline void unpack_cells(int32_t k, int& ku, int& kv) {
 // The box's sources go to the wavefronts in chunks claimed from an LDS
 // counter: a wave that runs ahead takes more chunks, so the waves of a tile
 // finish together (a static split leaves them waiting at the barrier for the
-// slowest one).  The unit of work is a column of kU consecutive box rows: unit
-// u = q bw + c covers rows kU q .. kU q + kU of box column c.  A chunk is 64
+// slowest one).  The unit of work is a column of kU consecutive box rows (two
+// for the cubic basis, unit_rows): unit u = q bw + c covers rows kU q .. kU q +
+// kU of box column c.  A chunk is 64
 // consecutive units, one per lane, so no lane idles but in the last chunk (and
 // past the box's last row); a lane wraps its column and reads its push table
 // once for its kU sources, and neighbouring lanes read neighbouring columns of
@@ -203,6 +205,10 @@ __device__ inline void unpack_cells(int32_t k, int& ku, int& kv) {
 // template parameters, so the loop body is one basic block, free of per-node
 // branches.
 constexpr int kU = 4;  // sources (rows) per unit
+// The cubic basis takes units of one row pair: the pair's two sets of 8 + 8
+// taps leave no registers for a second pair's loads in flight.
+template <int TAPS>
+constexpr int unit_rows() { return TAPS == 8 ? 2 : kU; }
 
 struct SourceScan {
     long long* acc;
@@ -250,16 +256,17 @@ __device__ inline void scan_sources(const SourceScan& S) {
         c += c < 0 ? bw : (c >= bw ? -bw : 0);
         const int iu = S.bx0 + (uvalid ? c : 0);
         const int i = column(iu);
-        const int r0 = uvalid ? kU * q : 0;
+        constexpr int UR = unit_rows<TAPS>();
+        const int r0 = uvalid ? UR * q : 0;
         float4 tx;
         if (PUSH != kPushMapped) tx = tab_x[(unsigned)i];
-        int jj[kU];
-        float wv[kU];
-        float4 tpv[kU];
-        float2 mf[kU];
-        int32_t mk[kU];
+        int jj[UR];
+        float wv[UR];
+        float4 tpv[UR];
+        float2 mf[UR];
+        int32_t mk[UR];
 #pragma unroll
-        for (int h = 0; h < kU; ++h) {
+        for (int h = 0; h < UR; ++h) {
             const bool valid = uvalid && r0 + h < bh;
             jj[h] = S.by0 + (valid ? r0 + h : 0);
             const size_t node = (size_t)__umul24(jj[h], nx) + i;  // < 2^32: both axes have at most 2^16 nodes
@@ -277,11 +284,11 @@ __device__ inline void scan_sources(const SourceScan& S) {
         // a chunk whose weights are all zero (in every lane) adds nothing
         bool live = false;
 #pragma unroll
-        for (int h = 0; h < kU; ++h) live |= wv[h] != 0.0f;
+        for (int h = 0; h < UR; ++h) live |= wv[h] != 0.0f;
         if (!__any(live)) continue;
-        if constexpr (TAPS == 6) {
+        if constexpr (TAPS >= 6) {
 #pragma unroll
-            for (int h = 0; h < kU; h += 2) {
+            for (int h = 0; h < UR; h += 2) {
                 int ku0, kv0, ku1, kv1;
                 float fu0, fv0, fu1, fv1;
                 if (PUSH == kPushMapped) {
@@ -301,7 +308,7 @@ __device__ inline void scan_sources(const SourceScan& S) {
             continue;
         }
 #pragma unroll
-        for (int h = 0; h < kU; ++h) {
+        for (int h = 0; h < UR; ++h) {
             if (PUSH == kPushMapped) {
                 int ku, kv;
                 unpack_cells(mk[h], ku, kv);
@@ -431,11 +438,11 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
         // are scalar
         const int bx0 = __builtin_amdgcn_readfirstlane(s_box[0]);
         const int bx1 = __builtin_amdgcn_readfirstlane(s_box[1]);
-        // quadratic basis: the box starts at an even row, so the work units'
-        // row pairs are the lattice's (2m, 2m + 1) in every tile and their
-        // merged sums do not depend on the tiling
+        // spline bases: the box starts at an even row, so the work units' row
+        // pairs are the lattice's (2m, 2m + 1) in every tile and their merged
+        // sums do not depend on the tiling
         const int by0_box = __builtin_amdgcn_readfirstlane(s_box[2]);
-        const int by0 = TAPS == 6 ? (by0_box & ~1) : by0_box;
+        const int by0 = TAPS >= 6 ? (by0_box & ~1) : by0_box;
         const int bh = __builtin_amdgcn_readfirstlane(s_box[3]) - by0;
         const int bw = max(bx1 - bx0, 1);
         const int nsrc = (bx1 > bx0 && bh > 0) ? bw * bh : 0;
@@ -469,7 +476,7 @@ __global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
         S.by0 = by0;
         S.bw = bw;
         S.bh = bh;
-        S.nunits = nsrc_live > 0 ? bw * ((bh + kU - 1) / kU) : 0;
+        S.nunits = nsrc_live > 0 ? bw * ((bh + unit_rows<TAPS>() - 1) / unit_rows<TAPS>()) : 0;
         S.inv_nx = inv_nx;
         S.inv_bw = 1.0 / (double)bw;
         S.scale = scale;
