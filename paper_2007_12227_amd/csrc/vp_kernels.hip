@@ -174,12 +174,17 @@ __device__ __attribute__((always_inline)) inline void scatter_pair(long long* ac
         const double e0 = d0 ? (c >= 1 ? bx0[c - 1] : 0.0) : (c < TAPS ? bx0[c] : 0.0);
         const double e1 = d1 ? (c >= 1 ? bx1[c - 1] : 0.0) : (c < TAPS ? bx1[c] : 0.0);
         unsigned long long* colp = (unsigned long long*)(corner + c);
+        // the last column holds taps only when the two sources' columns differ
+        // (skipped for the quadratic basis: 3% faster there; for the cubic
+        // basis the branch costs as many spilled registers as it saves atomics)
+        if (TAPS == 8 || c < TAPS || (d0 | d1)) {
 #pragma clang loop unroll(full)
-        for (int d = 0; d <= TAPS; ++d) {
-            double v = kFixMagic;
-            if (d < TAPS) v = fma(wq0[d], e0, v);
-            if (d >= 1) v = fma(wq1[d - 1], e1, v);
-            atomicAdd(colp + d * ldw, (unsigned long long)__double_as_longlong(v));
+            for (int d = 0; d <= TAPS; ++d) {
+                double v = kFixMagic;
+                if (d < TAPS) v = fma(wq0[d], e0, v);
+                if (d >= 1) v = fma(wq1[d - 1], e1, v);
+                atomicAdd(colp + d * ldw, (unsigned long long)__double_as_longlong(v));
+            }
         }
     }
 }
@@ -195,8 +200,8 @@ __device__ inline void unpack_cells(int32_t k, int& ku, int& kv) {
 // counter: a wave that runs ahead takes more chunks, so the waves of a tile
 // finish together (a static split leaves them waiting at the barrier for the
 // slowest one).  The unit of work is a column of kU consecutive box rows (two
-// for the cubic basis, unit_rows): unit u = q bw + c covers rows kU q .. kU q +
-// kU of box column c.  A chunk is 64
+// for the spline bases, unit_rows): unit u = q bw + c covers rows kU q .. kU q
+// + kU of box column c.  A chunk is 64
 // consecutive units, one per lane, so no lane idles but in the last chunk (and
 // past the box's last row); a lane wraps its column and reads its push table
 // once for its kU sources, and neighbouring lanes read neighbouring columns of
@@ -205,10 +210,11 @@ __device__ inline void unpack_cells(int32_t k, int& ku, int& kv) {
 // template parameters, so the loop body is one basic block, free of per-node
 // branches.
 constexpr int kU = 4;  // sources (rows) per unit
-// The cubic basis takes units of one row pair: the pair's two sets of 8 + 8
-// taps leave no registers for a second pair's loads in flight.
+// The spline bases take units of one row pair: a pair's two sets of taps
+// leave no registers for a second pair's loads in flight (at four rows the
+// quadratic loop spilled 24 bytes, the cubic one more, for no gain).
 template <int TAPS>
-constexpr int unit_rows() { return TAPS == 8 ? 2 : kU; }
+constexpr int unit_rows() { return TAPS >= 6 ? 2 : kU; }
 
 struct SourceScan {
     long long* acc;
