@@ -138,7 +138,8 @@ typedef struct {
 } vp_moments_t;
 
 /* Launch shape of the deposit kernel: destination tile (in lattice nodes) and
- * threads per workgroup (a multiple of 64, at most 1024).  Zero fields keep
+ * threads per workgroup (a multiple of 64, at most 1024; 768 with the cubic
+ * basis).  Zero fields keep
  * the current value.  (The solve works on fixed tiles of 32 x 64 nodes, or
  * of 80 x 80 (quadratic basis) or 60 x 60 (cubic) nodes.) */
 typedef struct {
@@ -252,8 +253,9 @@ int vp_moments(vp_grid* g, vp_moments_t* out);
 
 /* Deposit launch shape.  vp_set_tiles validates it (VP_EINVAL if the tile's
  * local memory would exceed the device limit or the thread count is not a
- * multiple of 64 in [64, 1024]).  A new grid starts from a shape chosen by
- * its lattice size; vp_autotune picks one by timing. */
+ * multiple of 64 in [64, 1024], [64, 768] with the cubic basis).  A new grid
+ * starts from a shape chosen by its lattice size; vp_autotune picks one by
+ * timing. */
 int vp_set_tiles(vp_grid* g, const vp_tiles* t);
 int vp_get_tiles(const vp_grid* g, vp_tiles* t);
 

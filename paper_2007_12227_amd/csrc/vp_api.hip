@@ -332,9 +332,9 @@ int validate_tiles(int basis, const vp_tiles& t) {
     if (t.k1_tx < kMinTile || t.k1_ty < 1)
         return fail(VP_EINVAL, "deposit tile below the minimum (k1_tx >= %d, k1_ty >= 1)", kMinTile);
     if (t.k1_tx > 4096 || t.k1_ty > 1024) return fail(VP_EINVAL, "deposit tile too large");
-    if (t.k1_threads < 64 || t.k1_threads > kDepositMaxThreads || t.k1_threads % 64)
-        return fail(VP_EINVAL, "deposit threads %d: need a multiple of 64 in [64, %d]", t.k1_threads,
-                    kDepositMaxThreads);
+    const int max_threads = basis == kBasisCubic ? kDepositCubicThreads : kDepositMaxThreads;
+    if (t.k1_threads < 64 || t.k1_threads > max_threads || t.k1_threads % 64)
+        return fail(VP_EINVAL, "deposit threads %d: need a multiple of 64 in [64, %d]", t.k1_threads, max_threads);
     if (deposit_lds_bytes(t.k1_tx, t.k1_ty, basis) > g_max_lds)
         return fail(VP_EINVAL, "deposit tile %dx%d needs %zu bytes of LDS (limit %zu)", t.k1_tx, t.k1_ty,
                     deposit_lds_bytes(t.k1_tx, t.k1_ty, basis), g_max_lds);
@@ -348,7 +348,7 @@ vp_tiles default_tiles(int nx, int np, int basis = kBasisTent) {
     const double nodes = (double)nx * np;
     // (the cubic basis's 8-cell border leaves a 128 x 128 tile without room;
     // 128 x 64 is the timed best for it at 2048^2)
-    if (nodes >= 256.0 * 128 * 128) return basis == kBasisCubic ? vp_tiles{128, 64, 1024} : vp_tiles{128, 128, 1024};
+    if (nodes >= 256.0 * 128 * 128) return basis == kBasisCubic ? vp_tiles{128, 64, 768} : vp_tiles{128, 128, 1024};
     if (nodes >= 256.0 * 128 * 64) return vp_tiles{128, 64, 512};
     return vp_tiles{64, 32, 256};
 }
@@ -959,8 +959,9 @@ int vp_autotune(vp_grid* g, double dt, double* best_us) {
         *us = 1000.f * ms / reps;
         return VP_OK;
     };
-    const int k1c[][3] = {{64, 16, 256},  {64, 32, 256},  {64, 64, 256},   {128, 32, 256},  {64, 64, 512},
-                          {128, 64, 512}, {128, 64, 640}, {128, 64, 1024}, {128, 128, 1024}, {256, 64, 1024}};
+    const int k1c[][3] = {{64, 16, 256},  {64, 32, 256},  {64, 64, 256},  {128, 32, 256},   {64, 64, 512},
+                          {128, 64, 512}, {128, 64, 640}, {128, 64, 768}, {128, 64, 1024}, {128, 128, 1024},
+                          {256, 64, 1024}};
     vp_tiles best = g->tiles;
     float best_t = 1e30f;
     for (auto& c : k1c) {

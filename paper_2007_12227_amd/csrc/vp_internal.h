@@ -41,6 +41,9 @@ constexpr int kEdge = 32;         // nodes from an open edge whose LU coefficien
 constexpr int kPad = 4;           // trash border of a deposit tile (per side)
 constexpr int kFixBits = 40;      // deposit cell sums: 64-bit fixed point at 2^-40 of 2^e > max|w0|
 constexpr int kDepositMaxThreads = 1024;  // deposit workgroup: a multiple of 64 up to this
+// The cubic basis's deposit is compiled for at most 768 threads per workgroup:
+// its row pairs' taps then fit the registers (158 VGPRs) without spilling.
+constexpr int kDepositCubicThreads = 768;
 constexpr int kSegX = 32;                  // solve tile: kSegX columns by kSegP rows (kept nodes)
 constexpr int kSegP = 64;
 constexpr int kLineX = kSegX + 2 * kHalo;  // window line along x: the kept segment plus both halos

@@ -363,7 +363,7 @@ __global__ __launch_bounds__(256) void k_map(const VpInst* inst) {
 // (cubic basis).
 // ---------------------------------------------------------------------------
 template <int TAPS>
-__global__ __launch_bounds__(kDepositMaxThreads) void k_deposit(LaunchArgs A) {
+__global__ __launch_bounds__(TAPS == 8 ? kDepositCubicThreads : kDepositMaxThreads) void k_deposit(LaunchArgs A) {
     constexpr int PAD = TAPS == 4 ? kPad : TAPS == 6 ? kPadQ : kPadC;
     extern __shared__ __align__(16) long long acc[];  // 16-byte aligned: read four cells at a time
     __shared__ int s_d, s_box[4], s_next;

@@ -78,7 +78,7 @@ def test_deposit_tilings_agree_bitwise(B):
     w = w.astype(np.float32)
     ref = oracle_step(x, p, ham, w, dt)
     first = None
-    for t in [None, (64, 16), (24, 5, 64), (200, 24, 1024), (128, 112, 1024)]:
+    for t in [None, (64, 16), (24, 5, 64), (200, 24, 768), (128, 112, 768)]:
         got, _ = gpu_steps(B, x, p, ham, w, dt, 1, t)
         assert_step_parity(got, ref, label=str(t), tol_max=NODE_TOL)
         if first is None:
@@ -93,8 +93,13 @@ def test_tile_too_large_for_the_border_is_refused(B):
     g = B.Grid(x, p)
     g.set_basis(B.BASIS_CUBIC)
     with pytest.raises(B.VpError) as e:
-        g.set_tiles((128, 128), 1024)
+        g.set_tiles((128, 128), 768)
     assert e.value.code == B.VP_EINVAL
+    # the cubic deposit is built for at most 768 threads per workgroup
+    with pytest.raises(B.VpError) as e:
+        g.set_tiles((128, 64), 1024)
+    assert e.value.code == B.VP_EINVAL
+    g.set_tiles((128, 64), 768)
     g.close()
 
 
