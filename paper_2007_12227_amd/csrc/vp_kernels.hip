@@ -175,9 +175,9 @@ __device__ __attribute__((always_inline)) inline void scatter_pair(long long* ac
         const double e1 = d1 ? (c >= 1 ? bx1[c - 1] : 0.0) : (c < TAPS ? bx1[c] : 0.0);
         unsigned long long* colp = (unsigned long long*)(corner + c);
         // the last column holds taps only when the two sources' columns differ
-        // (skipped for the quadratic basis: 3% faster there; for the cubic
-        // basis the branch costs as many spilled registers as it saves atomics)
-        if (TAPS == 8 || c < TAPS || (d0 | d1)) {
+        // (2% of the pairs at the benchmark's lattice): skipped when no lane of
+        // the wavefront needs it
+        if (c < TAPS || (d0 | d1)) {
 #pragma clang loop unroll(full)
             for (int d = 0; d <= TAPS; ++d) {
                 double v = kFixMagic;
