@@ -440,6 +440,18 @@ int vp_plan_source_box(const vp_axis* x, const vp_axis* p, const vp_hamiltonian*
                        double dt, double kick_re, double kick_im, int32_t bx0, int32_t bx1,
                        int32_t by0, int32_t by1, int32_t box[4]);
 
+/* Host-side planning helper of the 2D2V deposit (no GPU needed): the source
+ * box of the destination tile [tile_lo[d], tile_hi[d]) on every axis d (x, y,
+ * p_x, p_y) under Hamiltonian h and step dt.  box[2d], box[2d+1] receive the
+ * source range [lo, hi) along axis d: on x and y lo is in [0, n) and the range
+ * holds at most n columns, taken modulo n; an empty range has lo = hi.  Every
+ * node whose moved tent (first tap at floor of its pushed cell position, less
+ * one) deposits into the tile lies in the box (the tent reach of the
+ * algorithm section's overlap, eq. 9, per axis).  VP_EINVAL for invalid axes,
+ * a tile outside them, an unknown kind or non-finite parameters. */
+int vp4_plan_source_box(const vp_axis axes[4], const vp4_hamiltonian* h, double dt, const int32_t tile_lo[4],
+                        const int32_t tile_hi[4], int32_t box[8]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -143,6 +143,8 @@ def lib(load_torch: bool = True):
     L.vp4_autotune.argtypes = [C.c_void_p, C.c_double, P(C.c_double)]
     L.vp4_get_tiles.argtypes = [C.c_void_p, P(C.c_int32)]
     L.vp4_moments.argtypes = [C.c_void_p, P(Moments4)]
+    L.vp4_plan_source_box.argtypes = [P(Axis), P(Hamiltonian4), C.c_double, P(C.c_int32), P(C.c_int32),
+                                      P(C.c_int32)]
     for name in declared_functions():
         if name not in ("vp_workspace_bytes", "vp4_workspace_bytes", "vp_status_string", "vp_last_error"):
             getattr(L, name).restype = C.c_int
@@ -177,6 +179,16 @@ def plan_source_box(x, p, ham, dt, kick=0j, bx=(0, 0), by=(0, 0), basis=BASIS_TE
                                    float(dt), float(complex(kick).real), float(complex(kick).imag),
                                    int(bx[0]), int(bx[1]), int(by[0]), int(by[1]), box))
     return tuple(int(v) for v in box)
+
+
+def plan_source_box4(axes, kind, a, b, c, dt, tile_lo, tile_hi) -> tuple:
+    """The 2D2V deposit's source box of a tile (vp4_plan_source_box): ((lo, hi) per axis x, y, p_x, p_y)."""
+    ax = (Axis * 4)(*[axis(v) for v in axes])
+    box = (C.c_int32 * 8)()
+    check(lib().vp4_plan_source_box(ax, C.byref(Hamiltonian4(int(kind), float(a), float(b), float(c))), float(dt),
+                                    (C.c_int32 * 4)(*[int(v) for v in tile_lo]),
+                                    (C.c_int32 * 4)(*[int(v) for v in tile_hi]), box))
+    return tuple((int(box[2 * d]), int(box[2 * d + 1])) for d in range(4))
 
 
 def _stream_handle(stream):

@@ -120,13 +120,67 @@ void raise_lds4() {
     g_max_lds4 = (size_t)(lim - 1024);
 }
 
-// Conservative range [lo, hi) of source indices along an axis whose moved
-// tents (first tap at floor(i + d) - 1) can reach destination nodes [O, O + E),
-// for displacements d in [dmin, dmax]: floor(i + d) in [O - 2, O + E], one
-// more cell of margin on each side for rounding.
+// Range [lo, hi) of source indices along an axis whose moved tents (first
+// tap at floor(i + d) - 1) can reach destination nodes [O, O + E), for
+// displacements d in [dmin, dmax]: floor(i + d) in [O - 2, O + E], i.e.
+// i + d in [O - 2, O + E + 1).  The margin eps covers the rounding of the
+// FP32 push against these FP64 bounds (~1e-6 of the magnitudes involved).
 void source_range(int O, int E, double dmin, double dmax, int* lo, int* hi) {
-    *lo = (int)floor((double)O - 3.0 - dmax);
-    *hi = (int)ceil((double)(O + E) + 2.0 - dmin);
+    const double eps = 1e-3 + 1e-6 * (fabs((double)O) + E + fabs(dmin) + fabs(dmax));
+    *lo = (int)ceil((double)O - 2.0 - dmax - eps);
+    *hi = (int)ceil((double)(O + E) + 1.0 - dmin + eps);
+}
+
+// Push constants of step dt as the kernel takes them: kicks in cells, the
+// kick's share of the drift, and the kick bounds.
+struct Box4Params {
+    float ax, cx, by, cy, kdx, kdy;
+    double h[4], dt;
+};
+Box4Params box4_params(const vp_axis* ax, const vp4_hamiltonian& H, double dt) {
+    Box4Params B{};
+    for (int d = 0; d < 4; ++d) B.h[d] = spacing4(ax[d]);
+    const double pot = H.kind == VP_H_FREE ? 0.0 : 1.0;
+    B.ax = (float)(pot * H.a * dt / B.h[2]);
+    B.cx = (float)(pot * H.c * dt / B.h[2]);
+    B.by = (float)(pot * H.b * dt / B.h[3]);
+    B.cy = (float)(pot * H.c * dt / B.h[3]);
+    B.kdx = (float)(B.h[2] * dt / (2.0 * B.h[0]));
+    B.kdy = (float)(B.h[3] * dt / (2.0 * B.h[1]));
+    B.dt = dt;
+    return B;
+}
+
+// Source box of the destination tile [O_d, O_d + E_d) on every axis: per
+// axis pair, the momentum rows that the kick bound lets reach the tile, then
+// the coordinates whose drift over those rows (plus the kick's share) lets
+// them reach it.  x and y come back as [lo, hi) with lo in [0, n) and at most
+// n columns (periodic); an empty box has lo = hi on every axis of its pair.
+void tile_source_box4(const vp_axis* ax, const Box4Params& B, const int O[4], const int E[4], int lo[4], int hi[4]) {
+    const double Kx = fabs((double)B.ax) + fabs((double)B.cx), Ky = fabs((double)B.by) + fabs((double)B.cy);
+    for (int m = 0; m < 2; ++m) {  // m = 0: (x, px); m = 1: (y, py)
+        const int dp = m + 2, dc = m;
+        const double K = m == 0 ? Kx : Ky, kd = m == 0 ? B.kdx : B.kdy;
+        source_range(O[dp], E[dp], -K, K, &lo[dp], &hi[dp]);
+        lo[dp] = std::max(lo[dp], 0);
+        hi[dp] = std::min(hi[dp], ax[dp].n);
+        if (hi[dp] <= lo[dp]) {
+            lo[dp] = hi[dp] = 0;
+            lo[dc] = hi[dc] = 0;
+            continue;
+        }
+        const double pa = ax[dp].lo + lo[dp] * B.h[dp], pb = ax[dp].lo + (hi[dp] - 1) * B.h[dp];
+        const double da = pa * B.dt / B.h[dc], db = pb * B.dt / B.h[dc];
+        const double dmin = std::min(da, db) - fabs(kd) * K, dmax = std::max(da, db) + fabs(kd) * K;
+        source_range(O[dc], E[dc], dmin, dmax, &lo[dc], &hi[dc]);
+        const int n = ax[dc].n;
+        if (hi[dc] - lo[dc] > n) hi[dc] = lo[dc] + n;  // every column once (periodic)
+        // the same columns from a first one in [0, n) (the kernel wraps an
+        // index within one period with one step)
+        const int first = ((lo[dc] % n) + n) % n;
+        hi[dc] += first - lo[dc];
+        lo[dc] = first;
+    }
 }
 
 // Push tables and source boxes of step dt, uploaded with the descriptor.
@@ -144,13 +198,13 @@ int plan4(vp4_grid* g, double dt) {
     I.total_tiles = I.tiles[0] * I.tiles[1] * I.tiles[2] * I.tiles[3];
     I.kind = H.kind == VP_H_FREE ? kPush4Free : kPush4Potential;
     I.parity0 = 0;
-    const double pot = H.kind == VP_H_FREE ? 0.0 : 1.0;
-    I.ax = (float)(pot * H.a * dt / h[2]);
-    I.cx = (float)(pot * H.c * dt / h[2]);
-    I.by = (float)(pot * H.b * dt / h[3]);
-    I.cy = (float)(pot * H.c * dt / h[3]);
-    I.kdx = (float)(h[2] * dt / (2.0 * h[0]));
-    I.kdy = (float)(h[3] * dt / (2.0 * h[1]));
+    const Box4Params BP = box4_params(ax, H, dt);
+    I.ax = BP.ax;
+    I.cx = BP.cx;
+    I.by = BP.by;
+    I.cy = BP.cy;
+    I.kdx = BP.kdx;
+    I.kdy = BP.kdy;
     // tables: the coordinate axes (sin, cos of the node), the momentum axes
     // (drift in cells as a hi + lo pair, sin and cos of the half-drift phase)
     std::vector<float4> tab[4];
@@ -170,37 +224,18 @@ int plan4(vp4_grid* g, double dt) {
             tab[d][j] = make_float4(hi, lo, (float)sin(q), (float)cos(q));
         }
     }
-    // source boxes: kick bounds in cells, then per axis pair the momentum
-    // rows that can reach the tile and the coordinates their drift allows
-    const double Kx = fabs((double)I.ax) + fabs((double)I.cx), Ky = fabs((double)I.by) + fabs((double)I.cy);
+    // source boxes of the tiles
     std::vector<int4> boxes(2 * (size_t)I.total_tiles);
     for (int t = 0; t < I.total_tiles; ++t) {
-        int q = t, c[4];
-        for (int d = 0; d < 3; ++d) {
-            c[d] = q % I.tiles[d];
-            q /= I.tiles[d];
+        int q = t, O[4], E[4];
+        for (int d = 0; d < 4; ++d) {
+            const int c = d < 3 ? q % I.tiles[d] : q;
+            q /= d < 3 ? I.tiles[d] : 1;
+            O[d] = c * I.T[d];
+            E[d] = std::min(I.T[d], I.n[d] - O[d]);
         }
-        c[3] = q;
         int lo[4], hi[4];
-        for (int m = 0; m < 2; ++m) {  // m = 0: (x, px); m = 1: (y, py)
-            const int dp = m + 2, dc = m;
-            const double K = m == 0 ? Kx : Ky, kd = m == 0 ? I.kdx : I.kdy;
-            const int Op = c[dp] * I.T[dp], Ep = std::min(I.T[dp], I.n[dp] - Op);
-            source_range(Op, Ep, -K, K, &lo[dp], &hi[dp]);
-            lo[dp] = std::max(lo[dp], 0);
-            hi[dp] = std::min(hi[dp], I.n[dp]);
-            if (hi[dp] <= lo[dp]) {
-                lo[dp] = hi[dp] = 0;
-                lo[dc] = hi[dc] = 0;
-                continue;
-            }
-            const double pa = ax[dp].lo + lo[dp] * h[dp], pb = ax[dp].lo + (hi[dp] - 1) * h[dp];
-            const double da = pa * dt / h[dc], db = pb * dt / h[dc];
-            const double dmin = std::min(da, db) - fabs(kd) * K, dmax = std::max(da, db) + fabs(kd) * K;
-            const int Oc = c[dc] * I.T[dc], Ec = std::min(I.T[dc], I.n[dc] - Oc);
-            source_range(Oc, Ec, dmin, dmax, &lo[dc], &hi[dc]);
-            if (hi[dc] - lo[dc] > I.n[dc]) hi[dc] = lo[dc] + I.n[dc];  // every column once (periodic)
-        }
+        tile_source_box4(ax, BP, O, E, lo, hi);
         boxes[2 * (size_t)t] = make_int4(lo[0], hi[0], lo[1], hi[1]);
         boxes[2 * (size_t)t + 1] = make_int4(lo[2], hi[2], lo[3], hi[3]);
     }
@@ -578,6 +613,30 @@ int vp4_moments(vp4_grid* g, vp4_moments_t* out) {
     out->nonfinite = (int64_t)m[9];
     if (out->nonfinite) return fail4(VP_ENONFINITE, "%lld non-finite weights", (long long)out->nonfinite);
     if (flag) return fail4(VP_ERANGE, "a deposit cell sum left the fixed-point range");
+    return VP_OK;
+}
+
+int vp4_plan_source_box(const vp_axis axes[4], const vp4_hamiltonian* h, double dt, const int32_t tile_lo[4],
+                        const int32_t tile_hi[4], int32_t box[8]) {
+    if (!axes || !h || !tile_lo || !tile_hi || !box) return fail4(VP_EINVAL, "null argument");
+    for (int d = 0; d < 4; ++d) {
+        if (!axis4_ok(axes[d])) return fail4(VP_EINVAL, "invalid axis %d", d);
+        if (tile_lo[d] < 0 || tile_hi[d] > axes[d].n || tile_hi[d] <= tile_lo[d])
+            return fail4(VP_EINVAL, "tile [%d, %d) outside axis %d", tile_lo[d], tile_hi[d], d);
+    }
+    if (h->kind != VP_H_FREE && h->kind != VP_H_PENDULUM) return fail4(VP_EINVAL, "kind %d", h->kind);
+    if (!isfinite(dt) || !isfinite(h->a) || !isfinite(h->b) || !isfinite(h->c)) return fail4(VP_EINVAL, "non-finite");
+    const Box4Params B = box4_params(axes, *h, dt);
+    int O[4], E[4], lo[4], hi[4];
+    for (int d = 0; d < 4; ++d) {
+        O[d] = tile_lo[d];
+        E[d] = tile_hi[d] - tile_lo[d];
+    }
+    tile_source_box4(axes, B, O, E, lo, hi);
+    for (int d = 0; d < 4; ++d) {
+        box[2 * d] = lo[d];
+        box[2 * d + 1] = hi[d];
+    }
     return VP_OK;
 }
 

@@ -21,6 +21,135 @@ __device__ inline int wrap4(int i, int n) {
     return r < 0 ? r + n : r;
 }
 
+// A periodic index into [0, n): one conditional step for an index within a
+// period of the range, the remainder for any other (rare) value.
+__device__ inline int wrap_once4(int i, int n) {
+    i -= i >= n ? n : 0;
+    i += i < 0 ? n : 0;
+    return (unsigned)i < (unsigned)n ? i : wrap4(i, n);
+}
+
+// The push of one source into whole cells and fractions along x, y (drift)
+// and p_x, p_y (kick), from the per-axis tables.
+template <int PUSH>
+__device__ inline void push4(const Vp4Inst& I, float4 X, float4 Y, float4 PX, float4 PY, int& ku0, float& fu0,
+                             int& ku1, float& fu1, int& kv0, float& fv0, int& kv1, float& fv1) {
+#pragma clang fp contract(off)
+    float dvx = 0.0f, dvy = 0.0f;
+    if (PUSH == kPush4Potential) {
+        // phases at the half drift: x + q_px, y + q_py, from the tables
+        const float sxh = fmaf(X.x, PX.w, X.y * PX.z), cxh = fmaf(X.y, PX.w, -(X.x * PX.z));
+        const float syh = fmaf(Y.x, PY.w, Y.y * PY.z), cyh = fmaf(Y.y, PY.w, -(Y.x * PY.z));
+        const float sd = fmaf(sxh, cyh, -(cxh * syh));  // sin(xh - yh)
+        dvx = -fmaf(I.ax, sxh, I.cx * sd);
+        dvy = -fmaf(I.by, syh, -(I.cy * sd));
+    }
+    float su, eu;
+    two_sum(PX.x, dvx * I.kdx, su, eu);
+    split_cell(su, eu + PX.y, ku0, fu0);
+    two_sum(PY.x, dvy * I.kdy, su, eu);
+    split_cell(su, eu + PY.y, ku1, fu1);
+    split_cell(dvx, 0.0f, kv0, fv0);
+    split_cell(dvy, 0.0f, kv1, fv1);
+}
+
+// The sources of one tile's box.  Thread k takes sources k, k + blockDim.x,
+// ... of the box in x-fastest order; its box coordinates advance by the
+// stride's own coordinates with one carry per axis (no division per source).
+// NEAR: the tile is at least 3 cells short of spanning each periodic axis,
+// so a tap before its origin never wraps into it and a node's four x taps
+// are four consecutive LDS cells (one address per block of four, immediate
+// offsets); otherwise a tap before the origin wraps to the axis's end.
+template <int PUSH, bool NEAR>
+__device__ inline void scan_box4(const Vp4Inst& I, long long* acc4, gfloat* __restrict__ w_in, int4 ba,
+                                 int4 bb, int B0, int B1, int B2, int B3, int O0, int O1, int O2, int O3, int E0,
+                                 int E1, int E2, int E3) {
+    const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2];
+    const int T0 = I.T[0], T1 = I.T[1], T2 = I.T[2];
+    const int S1 = T0, S2 = T0 * T1, S3 = T0 * T1 * T2;
+    gfloat4* __restrict__ tx = as_global(I.tab[0]);
+    gfloat4* __restrict__ ty = as_global(I.tab[1]);
+    gfloat4* __restrict__ tpx = as_global(I.tab[2]);
+    gfloat4* __restrict__ tpy = as_global(I.tab[3]);
+    const float scale = I.fix_scale;
+    // the thread's first source and the stride, as box coordinates
+    const int st = (int)blockDim.x, BB = B0 * B1;
+    const int st0 = st % B0, st1 = (st / B0) % B1, st2 = (st / BB) % B2, st3 = st / (BB * B2);
+    const int k = (int)threadIdx.x;
+    int i0 = k % B0, i1 = (k / B0) % B1, i2 = (k / BB) % B2, i3 = k / (BB * B2);
+    for (; i3 < B3;) {
+        const int ix = wrap_once4(ba.x + i0, n0), iy = wrap_once4(ba.z + i1, n1);
+        const int ipx = bb.x + i2, ipy = bb.z + i3;
+        const unsigned node = (__umul24(__umul24(ipy, n2) + ipx, n1) + iy) * (unsigned)n0 + ix;
+        const float wv = w_in[node];
+        const float4 X = tx[ix], Y = ty[iy], PX = tpx[ipx], PY = tpy[ipy];
+        // the next source's box coordinates
+        i0 += st0;
+        int c = i0 >= B0;
+        i0 -= c ? B0 : 0;
+        i1 += st1 + c;
+        c = i1 >= B1;
+        i1 -= c ? B1 : 0;
+        i2 += st2 + c;
+        c = i2 >= B2;
+        i2 -= c ? B2 : 0;
+        i3 += st3 + c;
+        if (wv == 0.0f) continue;
+        int ku0, ku1, kv0, kv1;
+        float fu0, fu1, fv0, fv1;
+        push4<PUSH>(I, X, Y, PX, PY, ku0, fu0, ku1, fu1, kv0, fv0, kv1, fv1);
+        // first tap of each axis relative to the tile origin (periodic axes
+        // wrapped into [-3, n - 3))
+        const int r0 = wrap_once4(ix + ku0 + 2 - O0, n0) - 3;
+        const int r1 = wrap_once4(iy + ku1 + 2 - O1, n1) - 3;
+        const int r2 = ipx + kv0 - 1 - O2, r3 = ipy + kv1 - 1 - O3;
+        if (r0 < -3 || r0 >= E0 || r1 < -3 || r1 >= E1 || r2 < -3 || r2 >= E2 || r3 < -3 || r3 >= E3) continue;
+        double bx[4], byy[4], bpx[4], bpy[4];
+        bspline_taps(fu0, bx);
+        bspline_taps(fu1, byy);
+        bspline_taps(fv0, bpx);
+        bspline_taps(fv1, bpy);
+        const double ws = (double)(wv * scale);
+        // tap positions in the tile along x and y; on a periodic axis a tap
+        // before the origin wraps to the axis's end (only a tile within 3
+        // cells of spanning the axis can take it)
+        int p0[4], p1[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            p0[q] = NEAR ? r0 + q : r0 + q + (r0 + q < 0 ? n0 : 0);
+            p1[q] = NEAR ? r1 + q : r1 + q + (r1 + q < 0 ? n1 : 0);
+        }
+        const int lane = NEAR ? r1 * S1 + r0 : 0;  // cell (r0, r1) of the lane's first taps, relative
+#pragma unroll
+        for (int q3 = 0; q3 < 4; ++q3) {
+            if ((unsigned)(r3 + q3) >= (unsigned)E3) continue;
+            const double w3 = ws * bpy[q3];
+#pragma unroll
+            for (int q2 = 0; q2 < 4; ++q2) {
+                if ((unsigned)(r2 + q2) >= (unsigned)E2) continue;
+                const double w2 = w3 * bpx[q2];
+                const int plane = (r3 + q3) * S3 + (r2 + q2) * S2;
+#pragma unroll
+                for (int q1 = 0; q1 < 4; ++q1) {
+                    if ((unsigned)p1[q1] >= (unsigned)E1) continue;
+                    const double w1 = w2 * byy[q1];
+                    if (NEAR) {
+                        unsigned long long* row = (unsigned long long*)(acc4 + (lane + plane + q1 * S1));
+#pragma unroll
+                        for (int q0 = 0; q0 < 4; ++q0)
+                            if ((unsigned)p0[q0] < (unsigned)E0) atomicAdd(row + q0, fix48_word(w1, bx[q0]));
+                    } else {
+                        unsigned long long* row = (unsigned long long*)(acc4 + plane + p1[q1] * S1);
+#pragma unroll
+                        for (int q0 = 0; q0 < 4; ++q0)
+                            if ((unsigned)p0[q0] < (unsigned)E0) atomicAdd(row + p0[q0], fix48_word(w1, bx[q0]));
+                    }
+                }
+            }
+        }
+    }
+}
+
 // k_deposit4: a workgroup owns one destination tile of T0 x T1 x T2 x T3
 // lattice nodes held in LDS (no border: every tap is tested against the tile
 // and the blocks of taps that miss it are skipped), scans the host-planned
@@ -34,14 +163,9 @@ __global__ __launch_bounds__(kDeposit4Threads) void k_deposit4(Launch4Args A) {
     const Vp4Inst& I = *A.inst;
     const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2], n3 = I.n[3];
     const int T0 = I.T[0], T1 = I.T[1], T2 = I.T[2], T3 = I.T[3];
-    const int S1 = T0, S2 = T0 * T1, S3 = T0 * T1 * T2, cells = S3 * T3;
+    const int cells = T0 * T1 * T2 * T3;
     const int par = (I.parity0 + A.parity) & 1;
     gfloat* __restrict__ w_in = as_global(I.w[par]);
-    gfloat4* __restrict__ tx = as_global(I.tab[0]);
-    gfloat4* __restrict__ ty = as_global(I.tab[1]);
-    gfloat4* __restrict__ tpx = as_global(I.tab[2]);
-    gfloat4* __restrict__ tpy = as_global(I.tab[3]);
-    const float scale = I.fix_scale;
     for (int t = blockIdx.x; t < A.total; t += gridDim.x) {
         int q = t;
         const int c0 = q % I.tiles[0];
@@ -53,84 +177,18 @@ __global__ __launch_bounds__(kDeposit4Threads) void k_deposit4(Launch4Args A) {
         const int O0 = c0 * T0, O1 = c1 * T1, O2 = c2 * T2, O3 = c3 * T3;
         const int E0 = min(T0, n0 - O0), E1 = min(T1, n1 - O1), E2 = min(T2, n2 - O2), E3 = min(T3, n3 - O3);
         const int4 ba = I.boxes[2 * t], bb = I.boxes[2 * t + 1];
-        const int B0 = ba.y - ba.x, B1 = ba.w - ba.z, B2 = bb.y - bb.x, B3 = bb.w - bb.z;
-        const int V = (B0 > 0 && B1 > 0 && B2 > 0 && B3 > 0 && scale > 0.0f) ? B0 * B1 * B2 * B3 : 0;
+        int B0 = ba.y - ba.x, B1 = ba.w - ba.z, B2 = bb.y - bb.x, B3 = bb.w - bb.z;
+        if (B0 <= 0 || B1 <= 0 || B2 <= 0 || B3 <= 0 || !(I.fix_scale > 0.0f)) {
+            // an empty box (or an all-zero state): no source
+            B0 = B1 = B2 = 1;
+            B3 = 0;
+        }
         for (int k = threadIdx.x; k < cells; k += blockDim.x) acc4[k] = 0ll;
         __syncthreads();
-        for (int s = threadIdx.x; s < V; s += blockDim.x) {
-            int r = s;
-            const int i0 = r % B0;
-            r /= B0;
-            const int i1 = r % B1;
-            r /= B1;
-            const int i2 = r % B2;
-            const int i3 = r / B2;
-            const int ix = wrap4(ba.x + i0, n0), iy = wrap4(ba.z + i1, n1);
-            const int ipx = bb.x + i2, ipy = bb.z + i3;
-            const float wv = w_in[(((size_t)ipy * n2 + ipx) * n1 + iy) * n0 + ix];
-            if (wv == 0.0f) continue;
-            const float4 X = tx[ix], Y = ty[iy], PX = tpx[ipx], PY = tpy[ipy];
-            int ku0, ku1, kv0, kv1;
-            float fu0, fu1, fv0, fv1;
-            {
-#pragma clang fp contract(off)
-                float dvx = 0.0f, dvy = 0.0f;
-                if (PUSH == kPush4Potential) {
-                    // phases at the half drift: x + q_px, y + q_py, from the tables
-                    const float sxh = fmaf(X.x, PX.w, X.y * PX.z), cxh = fmaf(X.y, PX.w, -(X.x * PX.z));
-                    const float syh = fmaf(Y.x, PY.w, Y.y * PY.z), cyh = fmaf(Y.y, PY.w, -(Y.x * PY.z));
-                    const float sd = fmaf(sxh, cyh, -(cxh * syh));  // sin(xh - yh)
-                    dvx = -fmaf(I.ax, sxh, I.cx * sd);
-                    dvy = -fmaf(I.by, syh, -(I.cy * sd));
-                }
-                float su, eu;
-                two_sum(PX.x, dvx * I.kdx, su, eu);
-                split_cell(su, eu + PX.y, ku0, fu0);
-                two_sum(PY.x, dvy * I.kdy, su, eu);
-                split_cell(su, eu + PY.y, ku1, fu1);
-                split_cell(dvx, 0.0f, kv0, fv0);
-                split_cell(dvy, 0.0f, kv1, fv1);
-            }
-            // first tap of each axis relative to the tile origin (periodic axes
-            // wrapped into [-3, n - 3), so the four taps need no further wrap)
-            const int r0 = wrap4(ix + ku0 - 1 - O0 + 3, n0) - 3;
-            const int r1 = wrap4(iy + ku1 - 1 - O1 + 3, n1) - 3;
-            const int r2 = ipx + kv0 - 1 - O2, r3 = ipy + kv1 - 1 - O3;
-            if (r0 < -3 || r0 >= E0 || r1 < -3 || r1 >= E1 || r2 < -3 || r2 >= E2 || r3 < -3 || r3 >= E3) continue;
-            double bx[4], byy[4], bpx[4], bpy[4];
-            bspline_taps(fu0, bx);
-            bspline_taps(fu1, byy);
-            bspline_taps(fv0, bpx);
-            bspline_taps(fv1, bpy);
-            // tap positions in the tile; on a periodic axis a tap before the
-            // origin wraps to the axis's end (a tile spanning the whole axis
-            // takes both ends of a wrapped footprint)
-            int p0[4], p1[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                p0[k] = r0 + k + (r0 + k < 0 ? n0 : 0);
-                p1[k] = r1 + k + (r1 + k < 0 ? n1 : 0);
-            }
-            const double ws = (double)(wv * scale);
-            for (int q3 = 0; q3 < 4; ++q3) {
-                if ((unsigned)(r3 + q3) >= (unsigned)E3) continue;
-                const double w3 = ws * bpy[q3];
-                for (int q2 = 0; q2 < 4; ++q2) {
-                    if ((unsigned)(r2 + q2) >= (unsigned)E2) continue;
-                    const double w2 = w3 * bpx[q2];
-                    long long* plane = acc4 + (r3 + q3) * S3 + (r2 + q2) * S2;
-#pragma unroll
-                    for (int q1 = 0; q1 < 4; ++q1) {
-                        if ((unsigned)p1[q1] >= (unsigned)E1) continue;
-                        const double w1 = w2 * byy[q1];
-                        unsigned long long* row = (unsigned long long*)(plane + p1[q1] * S1);
-#pragma unroll
-                        for (int q0 = 0; q0 < 4; ++q0)
-                            if ((unsigned)p0[q0] < (unsigned)E0) atomicAdd(row + p0[q0], fix48_word(w1, bx[q0]));
-                    }
-                }
-            }
-        }
+        if (E0 <= n0 - 3 && E1 <= n1 - 3)
+            scan_box4<PUSH, true>(I, acc4, w_in, ba, bb, B0, B1, B2, B3, O0, O1, O2, O3, E0, E1, E2, E3);
+        else
+            scan_box4<PUSH, false>(I, acc4, w_in, ba, bb, B0, B1, B2, B3, O0, O1, O2, O3, E0, E1, E2, E3);
         __syncthreads();
         bool out_of_range = false;
         const double inv = (double)I.fix_inv;

@@ -136,3 +136,53 @@ def test_source_box_is_tight_for_smooth_pendulum():
             x0, x1, y0, y1 = B.plan_source_box(x, p, ham, 0.02, 0j, (bx0, bx0 + 128), (by0, by0 + 32))
             worst = max(worst, (x1 - x0) * (y1 - y0) / (128 * 32))
     assert worst < 1.6
+
+
+# ---- the 2D2V deposit tile's source box (vp4_plan_source_box) ----
+
+def _reaches(cells, lo, hi, n, periodic):
+    """A moved tent whose pushed cell is `cells` has taps at cells - 1 .. cells + 2:
+    does any of them fall in [lo, hi) (modulo n on a periodic axis)?"""
+    hit = np.zeros(cells.shape, dtype=bool)
+    for m in range(-1, 3):
+        c = cells + m
+        hit |= ((c % n >= lo) & (c % n < hi)) if periodic else ((c >= lo) & (c < hi))
+    return hit
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_source_box4_contains_every_reaching_node(seed):
+    """Every node whose moved 4-D tent deposits into the tile (on all four axes
+    at once) lies in the planned box, for the FP64 push of the 2D2V oracle moved
+    by +-1e-4 cells (the FP32 push's rounding is ~1e-6); the box is also no
+    wider than the exact reach plus the planner's one-cell rounding of each end."""
+    from oracle import phase4d as P4
+    g = rng(300 + seed)
+    for _ in range(8):
+        n = [int(v) for v in g.integers(6, 20, 4)]
+        pm = float(g.uniform(1.0, 4.0))
+        axes = (Axis(-math.pi, math.pi, n[0], True), Axis(-math.pi, math.pi, n[1], True),
+                Axis(-pm, pm, n[2], False), Axis(-pm, pm, n[3], False))
+        kind = [H_FREE, H_PENDULUM][int(g.integers(0, 2))]
+        a, b, c = (float(v) for v in g.uniform(-1.5, 1.5, 3))
+        dt = float(g.uniform(0.01, 0.6)) if g.random() < 0.8 else float(g.uniform(1.0, 4.0))
+        lo = [int(g.integers(0, n[d])) for d in range(4)]
+        hi = [int(g.integers(lo[d] + 1, n[d] + 1)) for d in range(4)]
+        box = B.plan_source_box4(axes, kind, a, b, c, dt, lo, hi)
+        disp = P4.push(axes, P4.Ham4(P4.H4_FREE if kind == H_FREE else P4.H4_POTENTIAL, a, b, c), dt)
+        idx = np.meshgrid(*[np.arange(m) for m in reversed(n)], indexing="ij")[::-1]  # x, y, px, py index arrays
+        inbox = np.ones(disp[0].shape, dtype=bool)
+        for d in range(4):
+            bl, bh = box[d]
+            assert 0 <= bh - bl <= n[d]
+            if d < 2:
+                assert 0 <= bl < n[d] or bh == bl
+                inbox &= (idx[d] - bl) % n[d] < bh - bl
+            else:
+                inbox &= (idx[d] >= bl) & (idx[d] < bh)
+        for delta in (-1e-4, 0.0, 1e-4):
+            reach = np.ones(disp[0].shape, dtype=bool)
+            for d in range(4):
+                cells = np.floor(idx[d] + disp[d] + delta).astype(np.int64)
+                reach &= _reaches(cells, lo[d], hi[d], n[d], d < 2)
+            assert not np.any(reach & ~inbox), (n, kind, dt, lo, hi, box, int(np.sum(reach & ~inbox)))
