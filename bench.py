@@ -185,11 +185,12 @@ def bench_batched(binding, steps, count):
             "plain_value": work / plain_sec, "speedup_vs_plain": plain_sec / sec}
 
 
-def bench_phase4d(binding, n, npp, steps):
+def bench_phase4d(binding, n, npp, steps, tiles=None):
     """The 2D2V phase space (x, y periodic, p_x, p_y in [-3, 3] open), n^2 x npp^2
     nodes, coupled potential V = -cos x - 0.6 cos y - 0.4 cos(x - y), dt 0.05,
     a noisy near-equilibrium start: steps timed after the same number untimed,
-    with the starting deposit tile and then with the autotuned one."""
+    with the starting deposit tile and then with the autotuned one (or with
+    `tiles` alone, no autotuning: for profiling one launch shape)."""
     import numpy as np
     import torch
 
@@ -211,10 +212,12 @@ def bench_phase4d(binding, n, npp, steps):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3
 
+    if tiles is not None:
+        g.set_tiles(tiles)
     untuned_tiles = g.tiles()
     untuned_sec = timed()
-    tune_us = g.autotune(0.05)
-    sec = timed()
+    tune_us = g.autotune(0.05) if tiles is None else None
+    sec = timed() if tiles is None else untuned_sec
     kus = g.step_timed(0.05, min(steps, 10))
     nodes = n * n * npp * npp
     tiles = g.tiles()
@@ -361,6 +364,8 @@ def main():
     ap.add_argument("--phase4d-n", type=int, default=48, help="2D2V line: nodes along x and y")
     ap.add_argument("--phase4d-np", type=int, default=48, help="2D2V line: nodes along p_x and p_y")
     ap.add_argument("--phase4d-steps", type=int, default=20)
+    ap.add_argument("--phase4d-tiles", default=None,
+                    help="2D2V line: this deposit tile T0xT1xT2xT3 instead of autotuning (profiling)")
     ap.add_argument("--only", choices=("batched", "phase4d"), default=None,
                     help="run only this line (profiling), printing its JSON object")
     ap.add_argument("--serve-requests", type=int, default=1000)
@@ -395,9 +400,10 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    p4_tiles = tuple(int(v) for v in args.phase4d_tiles.split("x")) if args.phase4d_tiles else None
     if args.only:
         res = (bench_batched(binding, args.batch_steps, args.batch_count) if args.only == "batched"
-               else bench_phase4d(binding, args.phase4d_n, args.phase4d_np, args.phase4d_steps))
+               else bench_phase4d(binding, args.phase4d_n, args.phase4d_np, args.phase4d_steps, p4_tiles))
         print(json.dumps(res), flush=True)
         return
     inst = pendulum_band(args.n)
@@ -485,7 +491,7 @@ def main():
         for name in ("quadratic", "cubic"):
             line[name] = bench_spline(binding, name, args.n, args.spline_steps, args.warmup)
             log(f"{name}: {line[name]}")
-        line["phase4d"] = bench_phase4d(binding, args.phase4d_n, args.phase4d_np, args.phase4d_steps)
+        line["phase4d"] = bench_phase4d(binding, args.phase4d_n, args.phase4d_np, args.phase4d_steps, p4_tiles)
         log(f"phase4d: {line['phase4d']}")
         line["batched"] = bench_batched(binding, args.batch_steps, args.batch_count)
         log(f"batched: {line['batched']}")

@@ -221,44 +221,201 @@ __global__ __launch_bounds__(kDeposit4Threads) void k_deposit4(Launch4Args A) {
 // (the error decays by 2 - sqrt 3 per node, ~7e-10 at the line); an open line
 // is the truncated matrix, exact, with the LU factors of the first rows from
 // the edge (d_0 = 4, d_k = 4 - 1/d_{k-1}).
+// The sweeps take the line in chunks of kChunk4 nodes whose loads are all
+// issued before the chunk's recursion steps (the recursions wait on one FMA
+// per node, not on a load); lines longer than the halo (periodic) or the edge
+// table (open) wrap and pick their factors without a per-node test.  The
+// arithmetic, and so every result bit, is that of the node-by-node sweeps.
+constexpr int kChunk4 = 8;
+static_assert(kEdge % kChunk4 == 0 && kSolve4Halo % kChunk4 == 0, "whole chunks of edge factors and halo");
+
+// The sweeps' arithmetic is written out (no implicit contraction): the
+// forward step z_k = b_{k-1} + b_{k+1} - 2 b_k - m_k z_{k-1} (one FMA), the
+// backward step c_k = (z_k - c_{k+1}) m and y_k = b_k - c_k, each rounded.
+__device__ inline float tri_z(float acc, float m, float bm, float bp, float b0) {
+#pragma clang fp contract(off)
+    return fmaf(-m, acc, (bm + bp) - 2.0f * b0);
+}
+
 __device__ inline void solve_line4(const float* __restrict__ in, float* __restrict__ out, int n, size_t stride,
                                    bool periodic, const float (&dinv)[kEdge], const float (&mult)[kEdge]) {
+#pragma clang fp contract(off)
+    constexpr int C = kChunk4;
     auto b = [&](int k) { return in[(size_t)k * stride]; };
+    auto o = [&](int k) -> float& { return out[(size_t)k * stride]; };
     if (periodic) {
         constexpr int H = kSolve4Halo;
         float zt[H];
         float acc = 0.0f;
-        // warm-up over the wrapped halo before the line
-        float bm = b(wrap4(-H - 1, n)), b0 = b(wrap4(-H, n));
-        for (int k = -H; k < n + H; ++k) {
-            const float bp = b(wrap4(k + 1, n));
-            acc = fmaf(-kMinf, acc, (bm + bp) - 2.0f * b0);
-            if (k >= 0 && k < n) out[(size_t)k * stride] = acc;
-            else if (k >= n) zt[k - n] = acc;
-            bm = b0;
-            b0 = bp;
+        if (n <= H) {  // a line no longer than the halo: general wraps
+            float bm = b(wrap4(-H - 1, n)), b0 = b(wrap4(-H, n));
+            for (int k = -H; k < n + H; ++k) {
+                const float bp = b(wrap4(k + 1, n));
+                acc = tri_z(acc, kMinf, bm, bp, b0);
+                if (k >= 0 && k < n) o(k) = acc;
+                else if (k >= n) zt[k - n] = acc;
+                bm = b0;
+                b0 = bp;
+            }
+        } else {
+            // indices within one period of the line: one conditional wrap
+            auto w = [&](int k) { return k < 0 ? k + n : (k >= n ? k - n : k); };
+            float bm = b(w(-H - 1)), b0 = b(w(-H));
+            // warm-up over the wrapped halo before the line
+#pragma unroll
+            for (int k0 = -H; k0 < 0; k0 += C) {
+                float bb[C];
+#pragma unroll
+                for (int q = 0; q < C; ++q) bb[q] = b(w(k0 + 1 + q));
+#pragma unroll
+                for (int q = 0; q < C; ++q) {
+                    acc = tri_z(acc, kMinf, bm, bb[q], b0);
+                    bm = b0;
+                    b0 = bb[q];
+                }
+            }
+            int k = 0;
+            for (; k + C <= n; k += C) {
+                float bb[C];
+#pragma unroll
+                for (int q = 0; q < C; ++q) bb[q] = b(w(k + 1 + q));
+#pragma unroll
+                for (int q = 0; q < C; ++q) {
+                    acc = tri_z(acc, kMinf, bm, bb[q], b0);
+                    o(k + q) = acc;
+                    bm = b0;
+                    b0 = bb[q];
+                }
+            }
+            for (; k < n; ++k) {
+                const float bp = b(w(k + 1));
+                acc = tri_z(acc, kMinf, bm, bp, b0);
+                o(k) = acc;
+                bm = b0;
+                b0 = bp;
+            }
+            // the halo after the line
+#pragma unroll
+            for (int k0 = 0; k0 < H; k0 += C) {
+                float bb[C];
+#pragma unroll
+                for (int q = 0; q < C; ++q) bb[q] = b(w(n + k0 + 1 + q));
+#pragma unroll
+                for (int q = 0; q < C; ++q) {
+                    acc = tri_z(acc, kMinf, bm, bb[q], b0);
+                    zt[k0 + q] = acc;
+                    bm = b0;
+                    b0 = bb[q];
+                }
+            }
         }
         float c = 0.0f;
 #pragma unroll
         for (int k = H - 1; k >= 0; --k) c = (zt[k] - c) * kMinf;
+        int k = n - 1;
+        for (; k - C + 1 >= 0; k -= C) {
+            float zz[C], bb[C];
+#pragma unroll
+            for (int q = 0; q < C; ++q) {
+                zz[q] = o(k - q);
+                bb[q] = b(k - q);
+            }
+#pragma unroll
+            for (int q = 0; q < C; ++q) {
+                c = (zz[q] - c) * kMinf;
+                o(k - q) = bb[q] - c;
+            }
+        }
+        for (; k >= 0; --k) {
+            c = (o(k) - c) * kMinf;
+            o(k) = b(k) - c;
+        }
+        return;
+    }
+    if (n <= kEdge) {  // an open line within the edge table: node by node
+        float acc = 0.0f, bm = 0.0f, b0 = b(0);
+        for (int k = 0; k < n; ++k) {
+            const float bp = k + 1 < n ? b(k + 1) : 0.0f;
+            acc = tri_z(acc, mult[k], bm, bp, b0);
+            o(k) = acc;
+            bm = b0;
+            b0 = bp;
+        }
+        float c = 0.0f;
         for (int k = n - 1; k >= 0; --k) {
-            c = (out[(size_t)k * stride] - c) * kMinf;
-            out[(size_t)k * stride] = b(k) - c;
+            c = (o(k) - c) * dinv[k];
+            o(k) = b(k) - c;
         }
         return;
     }
     float acc = 0.0f, bm = 0.0f, b0 = b(0);
-    for (int k = 0; k < n; ++k) {
+    // the first kEdge nodes with the edge factors (compile-time operands)
+#pragma unroll
+    for (int k0 = 0; k0 < kEdge; k0 += C) {
+        float bb[C];
+#pragma unroll
+        for (int q = 0; q < C; ++q) bb[q] = b(k0 + 1 + q);  // k0 + 1 + q <= kEdge < n
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            acc = tri_z(acc, kLuEdge.m[k0 + q], bm, bb[q], b0);
+            o(k0 + q) = acc;
+            bm = b0;
+            b0 = bb[q];
+        }
+    }
+    int k = kEdge;
+    for (; k + C <= n; k += C) {
+        float bb[C];
+#pragma unroll
+        for (int q = 0; q < C; ++q) bb[q] = k + 1 + q < n ? b(k + 1 + q) : 0.0f;
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            acc = tri_z(acc, kMinf, bm, bb[q], b0);
+            o(k + q) = acc;
+            bm = b0;
+            b0 = bb[q];
+        }
+    }
+    for (; k < n; ++k) {
         const float bp = k + 1 < n ? b(k + 1) : 0.0f;
-        acc = fmaf(-(k < kEdge ? mult[k] : kMinf), acc, (bm + bp) - 2.0f * b0);
-        out[(size_t)k * stride] = acc;
+        acc = tri_z(acc, kMinf, bm, bp, b0);
+        o(k) = acc;
         bm = b0;
         b0 = bp;
     }
     float c = 0.0f;
-    for (int k = n - 1; k >= 0; --k) {
-        c = (out[(size_t)k * stride] - c) * (k < kEdge ? dinv[k] : kMinf);
-        out[(size_t)k * stride] = b(k) - c;
+    k = n - 1;
+    for (; k - C + 1 >= kEdge; k -= C) {
+        float zz[C], bb[C];
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            zz[q] = o(k - q);
+            bb[q] = b(k - q);
+        }
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            c = (zz[q] - c) * kMinf;
+            o(k - q) = bb[q] - c;
+        }
+    }
+    for (; k >= kEdge; --k) {
+        c = (o(k) - c) * kMinf;
+        o(k) = b(k) - c;
+    }
+    // the first kEdge nodes with the edge factors
+#pragma unroll
+    for (int k0 = kEdge - 1; k0 >= 0; k0 -= C) {
+        float zz[C], bb[C];
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            zz[q] = o(k0 - q);
+            bb[q] = b(k0 - q);
+        }
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            c = (zz[q] - c) * kLuEdge.dinv[k0 - q];
+            o(k0 - q) = bb[q] - c;
+        }
     }
 }
 
