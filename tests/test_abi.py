@@ -73,23 +73,26 @@ def test_status_strings(L):
 
 def _check_box(x, p, ham, dt, kick, tile, box, wide=0):
     """A moved tent at cell position u touches columns floor(u)-1 .. floor(u)+2;
-    a B-spline basis function of degree wide + 1, floor(u)-1-wide .. floor(u)+2+wide."""
+    a B-spline basis function of degree wide + 1, floor(u)-1-wide .. floor(u)+2+wide.
+    The FP64 push of the oracle is also moved by +-1e-4 cells (the FP32 push's
+    rounding is ~1e-6 cells)."""
     du, dv = oracle.push(x, p, ham, dt, None if kick is None else np.array([kick.real, kick.imag]))
     bx0, bx1, by0, by1 = tile
     x0, x1, y0, y1 = box
     j, i = np.meshgrid(np.arange(p.n), np.arange(x.n), indexing="ij")
-    u = i + du
-    v = j + dv
-    ku, kv = np.floor(u), np.floor(v)
-    row_hit = (kv >= by0 - 2 - wide) & (kv <= by1 + wide)
-    shifts = range(-3, 4) if x.periodic else (0,)
-    for m in shifts:
-        col_hit = (ku + m * x.n >= bx0 - 2 - wide) & (ku + m * x.n <= bx1 + wide)
-        hit = row_hit & col_hit
-        ii = i[hit] + m * x.n
-        jj = j[hit]
-        assert np.all((ii >= x0) & (ii < x1)), (tile, box, ii.min(), ii.max())
-        assert np.all((jj >= y0) & (jj < y1)), (tile, box, jj.min(), jj.max())
+    for delta in (-1e-4, 0.0, 1e-4):
+        u = i + du + delta
+        v = j + dv + delta
+        ku, kv = np.floor(u), np.floor(v)
+        row_hit = (kv >= by0 - 2 - wide) & (kv <= by1 + wide)
+        shifts = range(-3, 4) if x.periodic else (0,)
+        for m in shifts:
+            col_hit = (ku + m * x.n >= bx0 - 2 - wide) & (ku + m * x.n <= bx1 + wide)
+            hit = row_hit & col_hit
+            ii = i[hit] + m * x.n
+            jj = j[hit]
+            assert np.all((ii >= x0) & (ii < x1)), (tile, box, ii.min(), ii.max())
+            assert np.all((jj >= y0) & (jj < y1)), (tile, box, jj.min(), jj.max())
 
 
 @pytest.mark.parametrize("basis", [B.BASIS_TENT, B.BASIS_QUADRATIC, B.BASIS_CUBIC])
