@@ -267,17 +267,20 @@ def deposit_shape(tiles):
 
 def profiled_kernel_us(kernel, workload, shape):
     """Average duration (us) of `kernel` in the committed rocprofv3 kernel-trace
-    summary of this workload, or None unless it was taken of the current kernel
-    sources at this deposit launch shape."""
-    path = os.path.join(PROFILES, f"step_kernels_{workload}_kernel_trace.txt")
-    if not os.path.exists(path):
-        return None
-    text = open(path).read()
-    if f"kernel source sha256[:16]: {kernel_source_sha()}" not in text or f"shape (columns x rows x threads): {shape}" not in text:
-        return None
-    for line in text.splitlines():
-        if not line.startswith("#") and kernel in line.split("(")[0]:
-            return float(line.split()[-4])
+    summary of this workload (the one of this deposit launch shape, if there is
+    one), or None unless it was taken of the current kernel sources at this
+    deposit launch shape."""
+    for name in (f"step_kernels_{workload}_{shape}_kernel_trace.txt", f"step_kernels_{workload}_kernel_trace.txt"):
+        path = os.path.join(PROFILES, name)
+        if not os.path.exists(path):
+            continue
+        text = open(path).read()
+        if (f"kernel source sha256[:16]: {kernel_source_sha()}" not in text
+                or f"shape (columns x rows x threads): {shape}" not in text):
+            continue
+        for line in text.splitlines():
+            if not line.startswith("#") and kernel in line.split("(")[0]:
+                return float(line.split()[-4])
     return None
 
 
