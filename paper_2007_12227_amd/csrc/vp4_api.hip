@@ -82,7 +82,9 @@ void default_tiles4(const vp_axis* ax, int32_t T[4]) {
     for (int d = 0; d < 4; ++d) T[d] = std::min(want[d], ax[d].n);
 }
 
-size_t lds4(const int32_t T[4]) { return (size_t)T[0] * T[1] * T[2] * T[3] * sizeof(long long); }
+size_t lds4(const int32_t T[4]) {
+    return ((size_t)T[0] * T[1] * T[2] * T[3] + 2 * kDeposit4Pad) * sizeof(long long);
+}
 
 }  // namespace
 

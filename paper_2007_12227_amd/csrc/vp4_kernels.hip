@@ -59,7 +59,11 @@ __device__ inline void push4(const Vp4Inst& I, float4 X, float4 Y, float4 PX, fl
 // NEAR: the tile is at least 3 cells short of spanning each periodic axis,
 // so a tap before its origin never wraps into it and a node's four x taps
 // are four consecutive LDS cells (one address per block of four, immediate
-// offsets); otherwise a tap before the origin wraps to the axis's end.
+// offsets, no branch): an x tap outside the tile adds the fixed-point zero
+// (a word whose low 48 bits are zero; a cell's sum is the sign-extended low
+// 48 bits) to the cell it addresses, which lies in the neighbouring row or in
+// the kDeposit4Pad cells at either end of the tile's image.  Otherwise a tap
+// before the origin wraps to the axis's end.
 template <int PUSH, bool NEAR>
 __device__ inline void scan_box4(const Vp4Inst& I, long long* acc4, gfloat* __restrict__ w_in, int4 ba,
                                  int4 bb, int B0, int B1, int B2, int B3, int O0, int O1, int O2, int O3, int E0,
@@ -114,10 +118,12 @@ __device__ inline void scan_box4(const Vp4Inst& I, long long* acc4, gfloat* __re
         // before the origin wraps to the axis's end (only a tile within 3
         // cells of spanning the axis can take it)
         int p0[4], p1[4];
+        double bxm[4];  // NEAR: the x taps, zero outside the tile
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             p0[q] = NEAR ? r0 + q : r0 + q + (r0 + q < 0 ? n0 : 0);
             p1[q] = NEAR ? r1 + q : r1 + q + (r1 + q < 0 ? n1 : 0);
+            bxm[q] = (unsigned)(r0 + q) < (unsigned)E0 ? bx[q] : 0.0;
         }
         const int lane = NEAR ? r1 * S1 + r0 : 0;  // cell (r0, r1) of the lane's first taps, relative
 #pragma unroll
@@ -136,8 +142,7 @@ __device__ inline void scan_box4(const Vp4Inst& I, long long* acc4, gfloat* __re
                     if (NEAR) {
                         unsigned long long* row = (unsigned long long*)(acc4 + (lane + plane + q1 * S1));
 #pragma unroll
-                        for (int q0 = 0; q0 < 4; ++q0)
-                            if ((unsigned)p0[q0] < (unsigned)E0) atomicAdd(row + q0, fix48_word(w1, bx[q0]));
+                        for (int q0 = 0; q0 < 4; ++q0) atomicAdd(row + q0, fix48_word(w1, bxm[q0]));
                     } else {
                         unsigned long long* row = (unsigned long long*)(acc4 + plane + p1[q1] * S1);
 #pragma unroll
@@ -159,7 +164,8 @@ __device__ inline void scan_box4(const Vp4Inst& I, long long* acc4, gfloat* __re
 // lane's taps there miss the tile; along x each tap is its own test.
 template <int PUSH>
 __global__ __launch_bounds__(kDeposit4Threads) void k_deposit4(Launch4Args A) {
-    extern __shared__ __align__(16) long long acc4[];
+    extern __shared__ __align__(16) long long lds4d[];
+    long long* acc4 = lds4d + kDeposit4Pad;  // the tile's image, between the padding cells
     const Vp4Inst& I = *A.inst;
     const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2], n3 = I.n[3];
     const int T0 = I.T[0], T1 = I.T[1], T2 = I.T[2], T3 = I.T[3];
