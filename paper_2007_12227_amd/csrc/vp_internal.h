@@ -184,10 +184,8 @@ __host__ __device__ inline int iceil(float v) { return -(int)vp_floor(-v); }
 // range carries a margin of 1e-3 cells plus 2^-20 of the magnitudes involved,
 // for the FP32 rounding of this bound and of the push.  The row range keeps
 // two more cells per side: rows as tight as the columns were measured no
-// faster with 128-row tiles and 10-14% slower with 32-row tiles.  The
-// slowdown follows the lower row bound alone, which sets where the four-row
-// work units start relative to the tile (a tighter upper bound alone is
-// neutral); its mechanism is not established.
+// faster with 128-row tiles and 10-14% slower with 32-row tiles (the cause,
+// in the scheduling of the four-row work units, is not established).
 __host__ __device__ inline float box_margin(float a, float b) {
     return 1e-3f + 9.5367431640625e-7f * ((a < 0 ? -a : a) + (b < 0 ? -b : b));
 }
