@@ -83,7 +83,7 @@ void default_tiles4(const vp_axis* ax, int32_t T[4]) {
 }
 
 size_t lds4(const int32_t T[4]) {
-    return ((size_t)T[0] * T[1] * T[2] * T[3] + 2 * kDeposit4Pad) * sizeof(long long);
+    return ((size_t)(T[0] + kDeposit4RowPad) * T[1] * T[2] * T[3] + 2 * kDeposit4Pad) * sizeof(long long);
 }
 
 }  // namespace

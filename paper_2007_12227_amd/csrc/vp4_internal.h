@@ -15,6 +15,7 @@ namespace vp {
 enum Push4 : int32_t { kPush4Free = 0, kPush4Potential = 2 };
 constexpr int kDeposit4Threads = 1024;
 constexpr int kDeposit4Pad = 4;  // LDS cells before and after the deposit tile's image (x taps past a row's ends)
+constexpr int kDeposit4RowPad = 3;  // LDS cells after each x row of the deposit tile (taps past its ends)
 constexpr int kSolve4Threads = 256;
 constexpr int kSolve4Halo = 16;  // periodic lines: warm-up nodes (wrapped) per side
 constexpr int kSolve4XLines = 64;  // k_solve4_x: lines along x staged in LDS per workgroup

@@ -61,16 +61,18 @@ __device__ inline void push4(const Vp4Inst& I, float4 X, float4 Y, float4 PX, fl
 // are four consecutive LDS cells (one address per block of four, immediate
 // offsets, no branch): an x tap outside the tile adds the fixed-point zero
 // (a word whose low 48 bits are zero; a cell's sum is the sign-extended low
-// 48 bits) to the cell it addresses, which lies in the neighbouring row or in
-// the kDeposit4Pad cells at either end of the tile's image.  Otherwise a tap
+// 48 bits) to the cell it addresses, one of the kDeposit4RowPad cells that
+// end every x row of the LDS image (a tap before the row's start lands in the
+// previous row's, or in the kDeposit4Pad cells before the image).  The padded
+// rows also put neighbouring y rows on different LDS banks.  Otherwise a tap
 // before the origin wraps to the axis's end.
 template <int PUSH, bool NEAR>
 __device__ inline void scan_box4(const Vp4Inst& I, long long* acc4, gfloat* __restrict__ w_in, int4 ba,
                                  int4 bb, int B0, int B1, int B2, int B3, int O0, int O1, int O2, int O3, int E0,
                                  int E1, int E2, int E3) {
     const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2];
-    const int T0 = I.T[0], T1 = I.T[1], T2 = I.T[2];
-    const int S1 = T0, S2 = T0 * T1, S3 = T0 * T1 * T2;
+    const int T1 = I.T[1], T2 = I.T[2];
+    const int S1 = I.T[0] + kDeposit4RowPad, S2 = S1 * T1, S3 = S2 * T2;  // LDS strides (padded x rows)
     gfloat4* __restrict__ tx = as_global(I.tab[0]);
     gfloat4* __restrict__ ty = as_global(I.tab[1]);
     gfloat4* __restrict__ tpx = as_global(I.tab[2]);
@@ -170,6 +172,7 @@ __global__ __launch_bounds__(kDeposit4Threads) void k_deposit4(Launch4Args A) {
     const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2], n3 = I.n[3];
     const int T0 = I.T[0], T1 = I.T[1], T2 = I.T[2], T3 = I.T[3];
     const int cells = T0 * T1 * T2 * T3;
+    const int P0 = T0 + kDeposit4RowPad, lds_cells = P0 * T1 * T2 * T3;  // the LDS image: padded x rows
     const int par = (I.parity0 + A.parity) & 1;
     gfloat* __restrict__ w_in = as_global(I.w[par]);
     for (int t = blockIdx.x; t < A.total; t += gridDim.x) {
@@ -189,7 +192,7 @@ __global__ __launch_bounds__(kDeposit4Threads) void k_deposit4(Launch4Args A) {
             B0 = B1 = B2 = 1;
             B3 = 0;
         }
-        for (int k = threadIdx.x; k < cells; k += blockDim.x) acc4[k] = 0ll;
+        for (int k = threadIdx.x; k < lds_cells; k += blockDim.x) acc4[k] = 0ll;
         __syncthreads();
         if (E0 <= n0 - 3 && E1 <= n1 - 3)
             scan_box4<PUSH, true>(I, acc4, w_in, ba, bb, B0, B1, B2, B3, O0, O1, O2, O3, E0, E1, E2, E3);
@@ -207,7 +210,7 @@ __global__ __launch_bounds__(kDeposit4Threads) void k_deposit4(Launch4Args A) {
             const int e2 = r % T2;
             const int e3 = r / T2;
             if (e0 >= E0 || e1 >= E1 || e2 >= E2 || e3 >= E3) continue;
-            const long long v = fix48_value(acc4[k]);
+            const long long v = fix48_value(acc4[((e3 * T2 + e2) * T1 + e1) * P0 + e0]);
             out_of_range |= (unsigned long long)v + (1ull << 46) >= (1ull << 47);
             A.dst[(((size_t)(O3 + e3) * n2 + (O2 + e2)) * n1 + (O1 + e1)) * n0 + (O0 + e0)] = (float)((double)v * inv);
         }
