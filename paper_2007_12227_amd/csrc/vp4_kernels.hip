@@ -487,17 +487,44 @@ __global__ __launch_bounds__(kSolve4Threads) void k_solve4_x(Launch4Args A) {
     float* in = lds4x;
     float* out = lds4x + kSolve4XLines * pitch;
     const float* src = A.src + (size_t)L0 * nx;
-    for (int e = threadIdx.x; e < lines * nx; e += blockDim.x) {
-        const int l = e / nx, k = e - l * nx;
-        in[l * pitch + k] = src[e];
+    // the copies go in batches of kChunk4 elements per thread, every load of
+    // a batch issued before its stores (the element's line and position from
+    // an exact float quotient: e < 2^14 and nx <= kSolve4XMax)
+    const int total = lines * nx, step = (int)blockDim.x;
+    const float inv_nx = 1.0f / (float)nx;
+    auto slot = [&](int e) {
+        int l = (int)(((float)e + 0.5f) * inv_nx);
+        return l * pitch + (e - l * nx);
+    };
+    for (int e0 = threadIdx.x; e0 < total; e0 += kChunk4 * step) {
+        float v[kChunk4];
+#pragma unroll
+        for (int q = 0; q < kChunk4; ++q) {
+            const int e = e0 + q * step;
+            v[q] = e < total ? src[e] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < kChunk4; ++q) {
+            const int e = e0 + q * step;
+            if (e < total) in[slot(e)] = v[q];
+        }
     }
     __syncthreads();
     if ((int)threadIdx.x < lines) solve_line4(in + threadIdx.x * pitch, out + threadIdx.x * pitch, nx, 1, true, dinv, mult);
     __syncthreads();
     float* dst = A.dst + (size_t)L0 * nx;
-    for (int e = threadIdx.x; e < lines * nx; e += blockDim.x) {
-        const int l = e / nx, k = e - l * nx;
-        dst[e] = out[l * pitch + k];
+    for (int e0 = threadIdx.x; e0 < total; e0 += kChunk4 * step) {
+        float v[kChunk4];
+#pragma unroll
+        for (int q = 0; q < kChunk4; ++q) {
+            const int e = e0 + q * step;
+            v[q] = e < total ? out[slot(e)] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < kChunk4; ++q) {
+            const int e = e0 + q * step;
+            if (e < total) dst[e] = v[q];
+        }
     }
 }
 
