@@ -63,9 +63,9 @@ __device__ inline void push4(const Vp4Inst& I, float4 X, float4 Y, float4 PX, fl
 // (a word whose low 48 bits are zero; a cell's sum is the sign-extended low
 // 48 bits) to the cell it addresses, one of the kDeposit4RowPad cells that
 // end every x row of the LDS image (a tap before the row's start lands in the
-// previous row's, or in the kDeposit4Pad cells before the image).  The padded
-// rows also put neighbouring y rows on different LDS banks.  Otherwise a tap
-// before the origin wraps to the axis's end.
+// previous row's, or in the kDeposit4Pad cells before the image), never on a
+// cell that real taps add to.  Otherwise a tap before the origin wraps to the
+// axis's end.
 template <int PUSH, bool NEAR>
 __device__ inline void scan_box4(const Vp4Inst& I, long long* acc4, gfloat* __restrict__ w_in, int4 ba,
                                  int4 bb, int B0, int B1, int B2, int B3, int O0, int O1, int O2, int O3, int E0,
