@@ -397,7 +397,9 @@ int vp4_destroy_grid(vp4_grid* g);
 /* The Hamiltonian and its pusher (see vp4_hamiltonian); VP_EINVAL otherwise. */
 int vp4_set_hamiltonian(vp4_grid* g, const vp4_hamiltonian* h);
 /* Deposit tile (nodes along x, y, p_x, p_y; at least 4 or the whole axis;
- * 8 bytes of LDS per node of the tile).  Results do not depend on it. */
+ * 8 bytes of LDS per node of the tile with its x rows padded by 3 nodes, plus
+ * 64 bytes).  VP_EINVAL if that exceeds the device's LDS.  Results do not
+ * depend on it. */
 int vp4_set_tiles(vp4_grid* g, const int32_t tile[4]);
 /* The current deposit tile (nodes along x, y, p_x, p_y). */
 int vp4_get_tiles(const vp4_grid* g, int32_t tile[4]);

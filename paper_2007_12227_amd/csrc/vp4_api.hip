@@ -133,8 +133,8 @@ void source_range(int O, int E, double dmin, double dmax, int* lo, int* hi) {
     *hi = (int)ceil((double)(O + E) + 1.0 - dmin + eps);
 }
 
-// Push constants of step dt as the kernel takes them: kicks in cells, the
-// kick's share of the drift, and the kick bounds.
+// Push constants of step dt as the kernel takes them (kicks in cells and the
+// kick's share of the drift) and the axis spacings.
 struct Box4Params {
     float ax, cx, by, cy, kdx, kdy;
     double h[4], dt;
@@ -315,6 +315,19 @@ int enqueue_step4(vp4_grid* g, int par, hipEvent_t* ev) {
 int prepare4(vp4_grid* g, double dt) {
     if (!g->has_ham || !g->has_density) return fail4(VP_ESTATE, "set the Hamiltonian and the density before stepping");
     if (!isfinite(dt)) return fail4(VP_EINVAL, "dt must be finite");
+    // the kernels and the box planner do their cell arithmetic in 32-bit
+    // integers: a drift or kick beyond 2^20 cells per step is refused
+    {
+        const vp_axis* ax = g->ax;
+        const double pot = g->ham.kind == VP_H_FREE ? 0.0 : 1.0;
+        double cells[4];
+        for (int m = 0; m < 2; ++m)
+            cells[m] = fabs(dt) * std::max(fabs(ax[m + 2].lo), fabs(ax[m + 2].hi)) / spacing4(ax[m]);
+        cells[2] = pot * fabs(dt) * (fabs(g->ham.a) + fabs(g->ham.c)) / spacing4(ax[2]);
+        cells[3] = pot * fabs(dt) * (fabs(g->ham.b) + fabs(g->ham.c)) / spacing4(ax[3]);
+        for (double c : cells)
+            if (!(c <= 1048576.0)) return fail4(VP_EINVAL, "dt %g moves nodes by more than 2^20 cells per step", dt);
+    }
     if (!g->plan_valid || g->plan_dt != dt) return plan4(g, dt);
     return VP_OK;
 }

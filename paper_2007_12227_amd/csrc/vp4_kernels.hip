@@ -163,7 +163,9 @@ __device__ inline void scan_box4(const Vp4Inst& I, long long* acc4, gfloat* __re
 // source box, pushes each source and adds its 4^4 B3 taps as exact
 // fixed-point integers (the 2-D deposit's encoding), then writes the tile of
 // b once.  The blocks of taps along p_y, p_x and y are skipped when the
-// lane's taps there miss the tile; along x each tap is its own test.
+// lane's taps there miss the tile; along x a tap outside the tile adds the
+// fixed-point zero to a pad cell (or, in a tile within 3 cells of spanning a
+// periodic axis, is its own test).
 template <int PUSH>
 __global__ __launch_bounds__(kDeposit4Threads) void k_deposit4(Launch4Args A) {
     extern __shared__ __align__(16) long long lds4d[];

@@ -81,6 +81,19 @@ bool axis_ok(const vp_axis* a) {
 
 double spacing(const vp_axis& a) { return (a.hi - a.lo) / (a.periodic ? a.n : a.n - 1); }
 
+// The kernels and the box planner do their cell arithmetic in 32-bit
+// integers: a step whose drift, or whose pendulum kick, moves a node by more
+// than 2^20 cells is refused (the exact rotation stays within the lattice;
+// the FEL kick is bounded by its field, which the planner takes per step).
+constexpr double kMaxCellsPerStep = 1048576.0;
+bool step_too_large(const vp_axis& x, const vp_axis& p, const vp_hamiltonian& h, double dt) {
+    if (h.kind == VP_H_SHO_EXACT) return false;
+    const double v = std::max(fabs(p.lo), fabs(p.hi)) + (h.kind == VP_H_FEL ? fabs(h.fel_delta) : 0.0);
+    const double drift = fabs(dt) * v / spacing(x);
+    const double kick = h.kind == VP_H_PENDULUM ? fabs(dt * h.a) / spacing(p) : 0.0;
+    return !(drift <= kMaxCellsPerStep && kick <= kMaxCellsPerStep);
+}
+
 // Workspace layout: every piece 256-byte aligned.
 struct Layout {
     size_t w0, w1, b, tab_x, tab_p, fel_ex, fel_eq, fel_state, partials, counters,
@@ -529,6 +542,8 @@ int prepare(vp_grid* g, double dt) {
     if (!g->has_ham || !g->has_density)
         return fail(VP_ESTATE, "set the Hamiltonian and the density before stepping");
     if (!isfinite(dt)) return fail(VP_EINVAL, "dt must be finite");
+    if (step_too_large(g->x, g->p, g->ham, dt))
+        return fail(VP_EINVAL, "dt %g moves nodes by more than 2^20 cells per step", dt);
     if (g->ham.kind == VP_H_FEL && !(g->N0 != 0.0))
         return fail(VP_ESTATE, "the FEL needs a nonzero sum of the initial weights (N0 normalises the bunching)");
     if (!g->plan_valid || g->plan_dt != dt) {
@@ -1230,6 +1245,7 @@ int vp_step_noalloc(const vp_axis* x, const vp_axis* p, const vp_hamiltonian* h,
         return fail(VP_EINVAL, "integrator %d: only the FEL takes VP_FEL_RK4", h->integrator);
     if (basis < VP_BASIS_TENT || basis > VP_BASIS_CUBIC) return fail(VP_EINVAL, "unknown basis %d", basis);
     if (!isfinite(dt)) return fail(VP_EINVAL, "dt must be finite");
+    if (step_too_large(*x, *p, *h, dt)) return fail(VP_EINVAL, "dt %g moves nodes by more than 2^20 cells per step", dt);
     if (nsteps < 0) return fail(VP_EINVAL, "negative step count");
     const bool fel = h->kind == VP_H_FEL;
     if (fel && (!fel_A || !(fel_n0 != 0.0) || !isfinite(fel_n0)))

@@ -107,6 +107,24 @@ def test_nonfinite_weight_is_refused(B):
         g.close()
 
 
+def test_step_beyond_the_cell_range_is_refused(B):
+    """The cell arithmetic is 32-bit: a finite dt whose drift or kick moves a
+    node by more than 2^20 cells per step is refused before any launch, and
+    the state is left as it was; a step of 1000 cells is taken."""
+    x, p = pendulum_axes(96, 80)
+    w = (0.5 + rng(64).random((80, 96))).astype(np.float32)
+    g = grid(B, x, p, Hamiltonian(H_PENDULUM, a=1.0), w)
+    vmax = max(abs(p.lo), abs(p.hi))
+    for dt in (1e30, -1e30, 1.01 * (1 << 20) * x.h / vmax):
+        with pytest.raises(B.VpError) as e:
+            g.step(dt, 1)
+        assert e.value.code == B.VP_EINVAL, dt
+    assert np.array_equal(g.density(), w)
+    g.step(1000.0 * x.h / vmax, 1)  # a drift of 1000 cells: accepted
+    assert g.moments()["step"] == 1
+    g.close()
+
+
 def test_fel_with_zero_weight_sum_is_refused(B):
     """N0 = sum of the initial weights normalises the bunching (eq. 13c); the
     FEL cannot step a beam whose weights sum to zero."""

@@ -209,4 +209,8 @@ def test_refusals(B):
     with pytest.raises(B.VpError) as e:
         g.set_tiles((2, 8, 8, 8))
     assert e.value.code == B.VP_EINVAL
+    g.set_density(np.ones(g.shape, np.float32))
+    with pytest.raises(B.VpError) as e:  # a drift beyond 2^20 cells per step
+        g.step(1e30, 1)
+    assert e.value.code == B.VP_EINVAL
     g.close()
