@@ -243,7 +243,9 @@ int vp_get_density(vp_grid* g, float* w, int32_t on_device);
  * normalises the bunching, eq. 13c); VP_ERANGE, without stepping, once a
  * completed earlier step has set the range flag (see vp_set_fixed_point;
  * a step still in flight reports on a later call or in vp_moments /
- * vp_get_density); VP_EINVAL for a negative count or non-finite dt. */
+ * vp_get_density); VP_EINVAL for a negative count, a non-finite dt, or a dt
+ * whose drift or pendulum kick moves a node by more than 2^20 cells per step
+ * (the cell arithmetic is 32-bit). */
 int vp_step(vp_grid* g, double dt, int64_t nsteps);
 
 /* Diagnostics of the current state (the list at vp_moments_t); waits for the
@@ -410,7 +412,9 @@ int vp4_get_tiles(const vp4_grid* g, int32_t tile[4]);
 int vp4_set_density(vp4_grid* g, const float* w, int32_t on_device);
 int vp4_get_density(vp4_grid* g, float* w, int32_t on_device);
 /* nsteps steps of eq. 10 in 2D2V on the grid's stream: push, 256-tap
- * deposit, the four line solves.  VP_ESTATE before density and Hamiltonian. */
+ * deposit, the four line solves.  VP_ESTATE before density and Hamiltonian;
+ * VP_EINVAL for a negative count, a non-finite dt, or a dt whose drift or kick
+ * moves a node by more than 2^20 cells per step. */
 int vp4_step(vp4_grid* g, double dt, int64_t nsteps);
 /* As vp4_step, with the mean microseconds of the deposit (us[0]) and of the
  * four solves (us[1]) per step, from events recorded with the kernels. */
