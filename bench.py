@@ -305,6 +305,36 @@ def measured_traffic(kernel, workload, shape):
     return float(vals["bytes_per_launch"])
 
 
+def issue_profile(kernel, workload, shape):
+    """The committed rocprofv3 SQ-counter summary of `kernel` on this workload
+    and deposit launch shape: VALU- and LDS-active cycles as fractions of the
+    busy cycles, and wave-instructions per 64 lattice nodes; None unless it
+    was taken of the current kernel sources at this shape."""
+    path = os.path.join(PROFILES, f"k_deposit_k_solve_{workload}_{shape}_sq_counters.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if f"kernel source sha256[:16]: {kernel_source_sha()}" not in text:
+        return None
+    vals, cur = {}, None
+    for line in text.splitlines():
+        if line.startswith("#"):
+            continue
+        if not line.startswith(" ") and line.endswith(tuple("0123456789")) and ":" in line:
+            cur = line.split(":")[0].strip()
+            continue
+        if cur == kernel and ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = float(v)
+    if not vals:
+        return None
+    return {"valu_active_over_busy": vals.get("sq_active_inst_valu_over_busy_cu_cycles"),
+            "lds_active_over_busy": vals.get("sq_active_inst_lds_over_busy_cu_cycles"),
+            "valu_insts_per_64_nodes": vals.get("valu_wave_insts_per_64_nodes"),
+            "lds_insts_per_64_nodes": vals.get("lds_wave_insts_per_64_nodes"),
+            "source": os.path.basename(path)}
+
+
 def batched_profile(workload, cfg):
     """(mean deposit duration in us, HBM bytes per deposit launch) of the
     batched launch in configuration `cfg` from the committed rocprofv3
@@ -482,6 +512,8 @@ def main():
                      "alg_bytes_per_launch": alg_bytes, "kernel_us_events": kus[dom],
                      "kernel_us_rocprof": prof_us,
                      "frac_rocprof": None if prof_us is None else alg_bytes / (prof_us * 1e-6) / 1e9 / HBM_PEAK_GBS},
+        # the dominant kernel is bound by instruction issue, not HBM: its SQ counters
+        "issue": issue_profile(dom, workload, deposit_shape(tiles)),
         "kernel_roofline_frac": {k: alg_bytes / (v * 1e-6) / 1e9 / HBM_PEAK_GBS for k, v in kus.items()},
         "step_roofline_frac": alg_bytes / (sec / args.steps) / 1e9 / HBM_PEAK_GBS,
         "final_sum_w": m["sum_w"],
