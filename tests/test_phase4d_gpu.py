@@ -76,6 +76,20 @@ def test_one_step_coupled(B, shape, tiles):
     assert_step_parity(got, P4.step(axes, COUPLED, 0.3, w.astype(np.float64)), label=f"{shape} {tiles}")
 
 
+@pytest.mark.parametrize("ham", [P4.Ham4(P4.H4_FREE), COUPLED])
+def test_drift_beyond_one_period(B, ham):
+    """A step whose drift moves nodes by more than a whole period of x and y
+    (up to ~1.6 periods on a 16 x 14 lattice: the deposit's general wrap of a
+    tap position, not its one-step wrap), on tiles short of the whole axis
+    (the padded-row x taps) and on ragged ones, against the oracle."""
+    axes = axes4(16, 14, 9, 10)
+    w = start(axes, 91)
+    ref = P4.step(axes, ham, 4.0, w.astype(np.float64))
+    for tiles in ((8, 6, 4, 4), (5, 7, 9, 10)):
+        got, _ = gpu_run(B, axes, ham, w, 4.0, 1, tiles)
+        assert_step_parity(got, ref, label=f"dt 4 {ham.kind} {tiles}")
+
+
 def test_results_bitwise_independent_of_tiling(B):
     axes = axes4(20, 18, 13, 12)
     w = start(axes, 91)
