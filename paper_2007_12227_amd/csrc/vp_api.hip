@@ -357,12 +357,16 @@ int validate_tiles(int basis, const vp_tiles& t) {
 // Starting deposit shape by lattice size: the largest of the timed shapes
 // that still gives every compute unit a tile (256 of them), since larger
 // tiles rescan fewer halo sources and keep more waves per compute unit.
+// (The 64 x 64 x 512 rung took the served mix from 6.0e10 to 6.8e10
+// node-steps/s; 512 threads for the smallest tiles too helped it a little
+// more but slowed a batch of 256 small grids by 21%.)
 vp_tiles default_tiles(int nx, int np, int basis = kBasisTent) {
     const double nodes = (double)nx * np;
     // (the cubic basis's 8-cell border leaves a 128 x 128 tile without room;
     // 128 x 64 is the timed best for it at 2048^2)
     if (nodes >= 256.0 * 128 * 128) return basis == kBasisCubic ? vp_tiles{128, 64, 768} : vp_tiles{128, 128, 1024};
     if (nodes >= 256.0 * 128 * 64) return vp_tiles{128, 64, 512};
+    if (nodes >= 256.0 * 64 * 64) return vp_tiles{64, 64, 512};
     return vp_tiles{64, 32, 256};
 }
 
