@@ -44,18 +44,29 @@ class Result:
 
 
 class DeviceBackend:
-    """The libvp device path: grids, batches, synchronisation."""
+    """The libvp device path: grids, batches, synchronisation.
 
-    def __init__(self):
+    Every grid gets the same deposit launch shape (`deposit_tiles`: columns,
+    rows, threads; the library cuts it to smaller lattices): a batch launches
+    one workgroup size and the LDS of its largest tile for every tile, so
+    grids of mixed default shapes would run their small tiles at the
+    occupancy of the largest.  None keeps each grid's default shape."""
+
+    def __init__(self, deposit_tiles=(128, 64, 512)):
         from . import binding
         self.B = binding
+        self.deposit_tiles = deposit_tiles
         binding.lib()
 
     def footprint(self, inst) -> int:
         return self.B.workspace_bytes(inst.x, inst.p) + 256
 
     def make_grid(self, inst):
-        return self.B.grid_for(inst)
+        g = self.B.grid_for(inst)
+        if self.deposit_tiles is not None:
+            t = self.deposit_tiles
+            g.set_tiles((t[0], t[1]), t[2])
+        return g
 
     def make_batch(self, grids, dts):
         return self.B.Batch(grids, dts)
@@ -204,8 +215,9 @@ class Server:
 
 
 def serve_one_at_a_time(requests, realtime: bool = True, backend=None) -> list[Result]:
-    """The plain baseline: requests run alone, first come first served."""
-    be = backend if backend is not None else DeviceBackend()
+    """The plain baseline: requests run alone, first come first served, each
+    grid with its own default deposit shape."""
+    be = backend if backend is not None else DeviceBackend(deposit_tiles=None)
     out = []
     t0 = time.perf_counter()
     offset = 0.0
