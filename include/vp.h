@@ -294,7 +294,11 @@ int vp_autotune(vp_grid* g, double dt, double* best_us);
  * advance together, one launch of each per-step kernel covering every tile of
  * every grid.  dt[i] is grid i's step size.  All grids must use the same
  * stream (VP_EINVAL otherwise); the batch uses it.  The grids must outlive the
- * batch and must not be stepped on their own while it exists (VP_ESTATE). */
+ * batch and must not be stepped on their own while it exists (VP_ESTATE).
+ * The deposit launch takes one workgroup size (the one most of the tiles were
+ * planned with) and the LDS of the largest tile for every tile, so grids of
+ * mixed deposit shapes run their small tiles at the occupancy of the largest:
+ * give them one shape (vp_set_tiles) or let vp_batch_autotune choose one. */
 int vp_batch_create(vp_grid* const* grids, int32_t n, const double* dt, vp_batch** out);
 /* Time candidate launch configurations on the batch itself and keep the
  * fastest: every grid with its own deposit tile shape, or every grid with one
