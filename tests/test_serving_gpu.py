@@ -35,3 +35,21 @@ def test_served_results_equal_alone_results(B):
     s = summary(res)
     print(s)
     assert s["p99_latency_s"] >= s["p50_latency_s"] > 0
+
+
+def test_served_grids_share_one_deposit_shape(B):
+    """The server gives every grid one deposit launch shape (cut to smaller
+    lattices), so a batch's launch does not run small tiles at the LDS of a
+    large one; the one-at-a-time baseline keeps each grid's default."""
+    from paper_2007_12227_amd.inputs import fel_gaussian, pendulum_band
+    from paper_2007_12227_amd.serving import DeviceBackend
+    be, plain = DeviceBackend(), DeviceBackend(deposit_tiles=None)
+    for inst in (pendulum_band(2048, steps=1), pendulum_band(96, steps=1), fel_gaussian(256, steps=1)):
+        g = be.make_grid(inst)
+        t = g.tiles()
+        assert t["k1"] == (128, 64) and t["threads"] == 512, t  # (planning cuts it to a small lattice)
+        g.step(inst.dt, 1)
+        g.close()
+    g = plain.make_grid(pendulum_band(2048, steps=1))
+    assert g.tiles()["k1"] == (128, 128) and g.tiles()["threads"] == 1024
+    g.close()
