@@ -157,8 +157,7 @@ def _reaches(cells, lo, hi, n, periodic):
 def test_source_box4_contains_every_reaching_node(seed):
     """Every node whose moved 4-D tent deposits into the tile (on all four axes
     at once) lies in the planned box, for the FP64 push of the 2D2V oracle moved
-    by +-1e-4 cells (the FP32 push's rounding is ~1e-6); the box is also no
-    wider than the exact reach plus the planner's one-cell rounding of each end."""
+    by +-1e-4 cells (the FP32 push's rounding is ~1e-6)."""
     from oracle import phase4d as P4
     g = rng(300 + seed)
     for _ in range(8):
@@ -189,3 +188,18 @@ def test_source_box4_contains_every_reaching_node(seed):
                 cells = np.floor(idx[d] + disp[d] + delta).astype(np.int64)
                 reach &= _reaches(cells, lo[d], hi[d], n[d], d < 2)
             assert not np.any(reach & ~inbox), (n, kind, dt, lo, hi, box, int(np.sum(reach & ~inbox)))
+
+
+def test_source_box4_is_tight():
+    """The boxes stop at the exact reach: at 48^4 (coupled potential, dt 0.05,
+    16 x 12 x 8 x 8 tiles) the tiles scan 3.2 sources per lattice node; boxes
+    with two more cells of margin per side scanned 6.6."""
+    import itertools
+    from paper_2007_12227_amd.inputs import phase4d_axes
+    axes = phase4d_axes(48, 48)
+    T = (16, 12, 8, 8)
+    total = 0
+    for c in itertools.product(*[range(0, 48, t) for t in T]):
+        box = B.plan_source_box4(axes, H_PENDULUM, 1.0, 0.6, 0.4, 0.05, c, [min(c[d] + T[d], 48) for d in range(4)])
+        total += np.prod([hi - lo for lo, hi in box])
+    assert total / 48 ** 4 < 3.4
