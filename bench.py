@@ -399,7 +399,7 @@ def main():
     ap.add_argument("--phase4d-steps", type=int, default=20)
     ap.add_argument("--phase4d-tiles", default=None,
                     help="2D2V line: this deposit tile T0xT1xT2xT3 instead of autotuning (profiling)")
-    ap.add_argument("--only", choices=("batched", "phase4d"), default=None,
+    ap.add_argument("--only", choices=("batched", "phase4d", "fel", "fel_rk4"), default=None,
                     help="run only this line (profiling), printing its JSON object")
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-load", type=float, default=0.7)
@@ -435,8 +435,12 @@ def main():
         del a, b
     p4_tiles = tuple(int(v) for v in args.phase4d_tiles.split("x")) if args.phase4d_tiles else None
     if args.only:
-        res = (bench_batched(binding, args.batch_steps, args.batch_count) if args.only == "batched"
-               else bench_phase4d(binding, args.phase4d_n, args.phase4d_np, args.phase4d_steps, p4_tiles))
+        if args.only == "batched":
+            res = bench_batched(binding, args.batch_steps, args.batch_count)
+        elif args.only == "phase4d":
+            res = bench_phase4d(binding, args.phase4d_n, args.phase4d_np, args.phase4d_steps, p4_tiles)
+        else:
+            res = bench_fel(binding, args.fel_steps, integrator=int(args.only == "fel_rk4"))
         print(json.dumps(res), flush=True)
         return
     inst = pendulum_band(args.n)

@@ -33,6 +33,22 @@ struct RkConsts {
     float cdv, cdu, t3, t4;
 };
 
+// sin and cos of a Runge-Kutta stage angle t k (t = dz^2/4 or dz^2/2): for
+// |x| < 2^-6 by their Taylor series to the x^5 and x^4 terms (the first
+// omitted terms are below 3e-14 relative, far under FP32 rounding), with
+// every operation written out so all inlined copies round alike; sincosf
+// otherwise (a large field or step).
+__device__ inline void sincos_stage(float x, float* s, float* c) {
+#pragma clang fp contract(off)
+    if (fabsf(x) < 0.015625f) {
+        const float x2 = x * x;
+        *s = x * fmaf(x2, fmaf(x2, 1.0f / 120.0f, -1.0f / 6.0f), 1.0f);
+        *c = fmaf(x2, fmaf(x2, 1.0f / 24.0f, -0.5f), 1.0f);
+    } else {
+        sincosf(x, s, c);
+    }
+}
+
 // Push one node: its displacement in cells, split into whole cells (ku, kv)
 // and fractions (fu, fv) along x and p (the exact rotation, the FEL by
 // Runge-Kutta, or a phase-dependent kick from the per-axis tables).
@@ -54,11 +70,11 @@ __device__ inline void push_cells(float4 tx, float4 tp, float alpha, float beta,
         const float s2 = fmaf(tx.x, tp.w, tx.y * tp.z);
         const float k2 = fmaf(rk.a[1], c2, rk.b[1] * s2);
         float sn, cs;
-        sincosf(rk.t3 * k1, &sn, &cs);
+        sincos_stage(rk.t3 * k1, &sn, &cs);
         const float c3 = fmaf(c2, cs, -(s2 * sn)), s3 = fmaf(s2, cs, c2 * sn);
         const float k3 = fmaf(rk.a[2], c3, rk.b[2] * s3);
         const float c2q = fmaf(c2, tp.w, -(s2 * tp.z)), s2q = fmaf(s2, tp.w, c2 * tp.z);
-        sincosf(rk.t4 * k2, &sn, &cs);
+        sincos_stage(rk.t4 * k2, &sn, &cs);
         const float c4 = fmaf(c2q, cs, -(s2q * sn)), s4 = fmaf(s2q, cs, c2q * sn);
         const float k4 = fmaf(rk.a[3], c4, rk.b[3] * s4);
         const float dv = rk.cdv * ((k1 + k4) + 2.0f * (k2 + k3));
@@ -1344,22 +1360,37 @@ __device__ inline void stage_tile(const VpInst& I, int t, int parity, double (&s
         const int gx = X0 + col;
         const double2 ex = I.fel_ex[gx];
         double cre = 0.0, cim = 0.0;
-        for (int r = r0; r < th; r += kRowStep) {
-            const int j = Y0 + r;
-            const double wk = (double)w[(size_t)j * nx + gx];
-            const double2 eq = I.fel_eq[j];
-            cre += wk * eq.x;
-            cim -= wk * eq.y;
-            // e^{i psi2} = e^{i phi} e^{i q}
-            const double c2 = ex.x * eq.x - ex.y * eq.y, s2 = ex.y * eq.x + ex.x * eq.y;
-            const double k2 = -2.0 * (a2r * c2 - a2i * s2);
-            double sn, cs;
-            sincos_small(t4 * k2, &sn, &cs);
-            // e^{i psi4} = e^{i psi2} e^{i q} e^{i t4 k2}
-            const double c2q = c2 * eq.x - s2 * eq.y, s2q = s2 * eq.x + c2 * eq.y;
-            const double c4 = c2q * cs - s2q * sn, s4 = s2q * cs + c2q * sn;
-            acc[2] += wk * c4;
-            acc[3] -= wk * s4;
+        // Rows in batches of kStageBatch whose loads are all issued before the
+        // first is used (one memory round trip per batch, not per row).  Rows
+        // past the tile load its last row and weigh zero: the sums are never
+        // -0, so adding +-0 leaves them as the rows of the tile alone make them.
+        constexpr int kStageBatch = 8;
+        for (int r1 = r0; r1 < th; r1 += kStageBatch * kRowStep) {
+            float wr[kStageBatch];
+            double2 eqr[kStageBatch];
+#pragma unroll
+            for (int q = 0; q < kStageBatch; ++q) {
+                const int j = Y0 + min(r1 + q * kRowStep, th - 1);
+                wr[q] = w[(size_t)j * nx + gx];
+                eqr[q] = I.fel_eq[j];
+            }
+#pragma unroll
+            for (int q = 0; q < kStageBatch; ++q) {
+                const double wk = r1 + q * kRowStep < th ? (double)wr[q] : 0.0;
+                const double2 eq = eqr[q];
+                cre += wk * eq.x;
+                cim -= wk * eq.y;
+                // e^{i psi2} = e^{i phi} e^{i q}
+                const double c2 = ex.x * eq.x - ex.y * eq.y, s2 = ex.y * eq.x + ex.x * eq.y;
+                const double k2 = -2.0 * (a2r * c2 - a2i * s2);
+                double sn, cs;
+                sincos_small(t4 * k2, &sn, &cs);
+                // e^{i psi4} = e^{i psi2} e^{i q} e^{i t4 k2}
+                const double c2q = c2 * eq.x - s2 * eq.y, s2q = s2 * eq.x + c2 * eq.y;
+                const double c4 = c2q * cs - s2q * sn, s4 = s2q * cs + c2q * sn;
+                acc[2] += wk * c4;
+                acc[3] -= wk * s4;
+            }
         }
         const double k1 = -2.0 * (a1r * ex.x - a1i * ex.y);
         double sn, cs;
