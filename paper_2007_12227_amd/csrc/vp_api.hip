@@ -136,6 +136,9 @@ struct LaunchList {
     int ninst = 0, total1 = 0, total2 = 0;
     bool has_fel = false;  // an FEL instance: the field kernel follows the solve
     bool has_rk4 = false;  // a Runge-Kutta FEL instance: its stage sums precede the deposit
+    // one Runge-Kutta instance whose deposit sums the stage partials itself
+    // (stage_fusable): no field launch between the stage sums and the deposit
+    bool fuse_stage = false;
     int basis = kBasisTent;  // of every instance in the list
     int solve = kSolveTent;  // the solve kernel serving every instance in the list
     size_t lds1 = 0;
@@ -164,9 +167,9 @@ struct LaunchList {
         int n = 0;
         if (has_rk4) {
             k[n++] = K{fel_stage_kernel(), d_off2, total2, 0, kStageThreads, 0};
-            k[n++] = K{fel_field_kernel(), d_off2, ninst, 0, kFieldThreads, 1};
+            if (!fuse_stage) k[n++] = K{fel_field_kernel(), d_off2, ninst, 0, kFieldThreads, 1};
         }
-        k[n++] = K{deposit_kernel(basis), d_off1, total1, lds1, threads1, 0, dep_grid()};
+        k[n++] = K{deposit_kernel(basis), d_off1, total1, lds1, threads1, fuse_stage ? 1 : 0, dep_grid()};
         k[n++] = K{solve_kernel(solve), d_off2, total2, 0, solve_threads(solve), 0};
         if (has_fel) k[n++] = K{fel_field_kernel(), d_off2, ninst, 0, kFieldThreads, 0};
         return n;
@@ -174,9 +177,10 @@ struct LaunchList {
     int enqueue_step(int parity) const {
         if (has_rk4) {
             HIP_TRY(launch_fel_stage(args(d_off2, total2, parity), total2, stream));
-            HIP_TRY(launch_fel_field(args(d_off2, ninst, parity, 1), stream));
+            if (!fuse_stage) HIP_TRY(launch_fel_field(args(d_off2, ninst, parity, 1), stream));
         }
-        HIP_TRY(launch_deposit(args(d_off1, total1, parity), dep_grid(), lds1, threads1, stream, basis));
+        HIP_TRY(launch_deposit(args(d_off1, total1, parity, fuse_stage ? 1 : 0), dep_grid(), lds1, threads1, stream,
+                               basis));
         HIP_TRY(launch_solve(args(d_off2, total2, parity), total2, stream, solve));
         if (has_fel) HIP_TRY(launch_fel_field(args(d_off2, ninst, parity), stream));
         return VP_OK;
@@ -264,10 +268,10 @@ struct LaunchList {
             hipEvent_t* e = &ev[4 * s];
             if (has_rk4) {
                 HIP_TRY(launch_fel_stage(args(d_off2, total2, par), total2, stream, e[0], nullptr));
-                HIP_TRY(launch_fel_field(args(d_off2, ninst, par, 1), stream));
+                if (!fuse_stage) HIP_TRY(launch_fel_field(args(d_off2, ninst, par, 1), stream));
             }
-            HIP_TRY(launch_deposit(args(d_off1, total1, par), dep_grid(), lds1, threads1, stream, basis,
-                                   has_rk4 ? nullptr : e[0], e[1]));
+            HIP_TRY(launch_deposit(args(d_off1, total1, par, fuse_stage ? 1 : 0), dep_grid(), lds1, threads1, stream,
+                                   basis, has_rk4 ? nullptr : e[0], e[1]));
             HIP_TRY(launch_solve(args(d_off2, total2, par), total2, stream, solve, e[2], has_fel ? nullptr : e[3]));
             if (has_fel) HIP_TRY(launch_fel_field(args(d_off2, ninst, par), stream, nullptr, e[3]));
         }
@@ -283,6 +287,16 @@ struct LaunchList {
         return post_range_copy();
     }
 };
+
+// One Runge-Kutta instance on tents with at most kStageFuseTiles solve tiles
+// and deposit workgroups of at least kFieldThreads threads: each deposit
+// workgroup sums the stage partials itself (at most 32 KB of reads), which
+// saves the launch of the one-workgroup field kernel between the stage sums
+// and the deposit.
+bool stage_fusable(const LaunchList& L) {
+    return L.has_rk4 && L.ninst == 1 && L.basis == kBasisTent && L.total2 <= kStageFuseTiles &&
+           L.threads1 >= kFieldThreads;
+}
 
 // Small pinned host word for a launch list's range flag.
 int alloc_host_flag(volatile uint32_t** out) {
@@ -427,6 +441,7 @@ int upload_inst(vp_grid* g) {
     L.basis = g->basis;
     L.solve = solve_kind(g->basis, g->x.n, g->p.n, g->x.periodic != 0);
     L.threads1 = t.k1_threads;
+    L.fuse_stage = stage_fusable(L);
     if (shape != std::make_tuple(L.ninst, L.has_fel, L.has_rk4, L.total1, L.total2, L.lds1, L.basis, L.solve,
                                  L.threads1))
         L.drop_graphs();
@@ -582,7 +597,7 @@ int fill_batch(vp_batch* b) {
     for (auto& kv : tiles_at)
         if (kv.second > tiles_at[threads1]) threads1 = kv.first;
     LaunchList& L = b->list;
-    L.has_fel = L.has_rk4 = false;
+    L.has_fel = L.has_rk4 = L.fuse_stage = false;  // a batch keeps the stage field launch
     L.solve = kSolveTent;
     for (int k = 0; k < n; ++k) {
         vp_grid* g = b->grids[k];
@@ -1361,6 +1376,7 @@ int vp_step_noalloc(const vp_axis* x, const vp_axis* p, const vp_hamiltonian* h,
     LL.solve = solve_kind(basis, nx, np, x->periodic != 0);
     LL.lds1 = deposit_lds_bytes(t.k1_tx, t.k1_ty, basis);
     LL.threads1 = t.k1_threads;
+    LL.fuse_stage = stage_fusable(LL);
     LL.stream = s;
     for (int64_t k = 0; k < nsteps; ++k) {
         int rc = LL.enqueue_step((int)(k & 1));

@@ -51,6 +51,7 @@ constexpr int kLineP = kSegP + 2 * kHalo;  // window line along p
 constexpr int kSolveThreads = 64;          // solve: one wavefront (a window column, then a kept row, per lane)
 constexpr int kFieldThreads = 256;       // FEL field update: one workgroup per instance
 constexpr int kStageThreads = 256;       // FEL Runge-Kutta stage sums: four wavefronts per solve tile
+constexpr int kStageFuseTiles = 1024;    // FEL Runge-Kutta: a single grid's deposit sums the stage partials up to this many solve tiles
 constexpr int kReduceBlocks = 256;
 constexpr int kReduceThreads = 256;
 constexpr int kMoments = 10;      // FP64 sums produced by the reduction kernel

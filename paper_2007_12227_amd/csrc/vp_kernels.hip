@@ -368,6 +368,61 @@ __global__ __launch_bounds__(256) void k_map(const VpInst* inst) {
     I.map_k[k] = (int32_t)(((uint32_t)ku & 0xffffu) | ((uint32_t)kv << 16));
 }
 
+// The per-tile FP64 bunching partials of an instance summed in one fixed
+// order, whichever kernel sums them: thread t < kFieldThreads adds tiles t,
+// t + kFieldThreads, ... in turn (kSumBatch tiles' loads in flight at once),
+// each wavefront reduces by a shuffle tree, and thread 0 adds the first
+// kFieldThreads / 64 wavefronts' sums in turn.  Every thread of the
+// workgroup calls it (it holds a barrier); the sums are thread 0's.
+__device__ inline void sum_tile_partials(const VpInst& I, double (&s_red)[kPartialsPerTile][kFieldThreads / 64],
+                                         double (&sum)[kPartialsPerTile]) {
+    constexpr int kSumBatch = 4;
+    double acc[kPartialsPerTile] = {0.0, 0.0, 0.0, 0.0};
+    const int n = I.k2_tiles;
+    if (threadIdx.x < kFieldThreads)
+        for (int k0 = threadIdx.x; k0 < n; k0 += kSumBatch * kFieldThreads) {
+            double v[kSumBatch][kPartialsPerTile];
+#pragma unroll
+            for (int q = 0; q < kSumBatch; ++q) {
+                const int k = min(k0 + q * kFieldThreads, n - 1);
+#pragma unroll
+                for (int c = 0; c < kPartialsPerTile; ++c) v[q][c] = I.partials[kPartialsPerTile * k + c];
+            }
+#pragma unroll
+            for (int q = 0; q < kSumBatch; ++q)
+                if (k0 + q * kFieldThreads < n)
+#pragma unroll
+                    for (int c = 0; c < kPartialsPerTile; ++c) acc[c] += v[q][c];
+        }
+    for (int o = 32; o > 0; o >>= 1)
+        for (int c = 0; c < kPartialsPerTile; ++c) acc[c] += __shfl_down(acc[c], o);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0 && wid < kFieldThreads / 64)
+        for (int c = 0; c < kPartialsPerTile; ++c) s_red[c][wid] = acc[c];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int c = 0; c < kPartialsPerTile; ++c) {
+            sum[c] = 0.0;
+            for (int k = 0; k < kFieldThreads / 64; ++k) sum[c] += s_red[c][k];
+        }
+}
+
+// The Runge-Kutta step's stage-3 and stage-4 bunchings from their summed
+// partials, and the step's new field A + dz/6 (b1 + 2 b2 + 2 b3 + b4)
+// (eq. 13c), every operation written out so that each kernel forming them
+// rounds alike.
+__device__ inline void rk4_stage_fields(const double (&a)[2], const double (&b1)[2], const double (&b2)[2], double n0,
+                                        double h, const double (&sum)[kPartialsPerTile], double (&b3)[2],
+                                        double (&b4)[2], double (&an)[2]) {
+#pragma clang fp contract(off)
+    const double inv_n0 = 1.0 / n0;
+    for (int c = 0; c < 2; ++c) {
+        b3[c] = sum[c] * inv_n0;
+        b4[c] = sum[2 + c] * inv_n0;
+        an[c] = a[c] + h / 6.0 * (((b1[c] + 2.0 * b2[c]) + 2.0 * b3[c]) + b4[c]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_deposit: push every node of the tile's source box and scatter its weight
 // into the LDS image of the destination tile, then write the tile of b once.
@@ -385,6 +440,7 @@ __global__ __launch_bounds__(TAPS == 8 ? kDepositCubicThreads : kDepositMaxThrea
     __shared__ int s_d, s_box[4], s_next;
     __shared__ float s_ab[2];
     __shared__ RkConsts s_rk;
+    __shared__ double s_stage[kPartialsPerTile][kFieldThreads / 64];
 
     for (int it = blockIdx.x; it < A.total; it += gridDim.x) {
         const int item = tile_of(it, A.total);
@@ -400,6 +456,15 @@ __global__ __launch_bounds__(TAPS == 8 ? kDepositCubicThreads : kDepositMaxThrea
         const int ldw = I.k1_tx + 2 * PAD, ldh = I.k1_ty + 2 * PAD;
         const int par = (I.parity0 + A.parity) & 1;
         const float* __restrict__ w_in = I.w[par];
+
+        // A launch with mode 1 (one Runge-Kutta FEL instance on tents, no field
+        // launch after the stage sums): every workgroup sums the stage-3/4
+        // partials itself, in the order the field kernel would (the same
+        // bits).  Not compiled into the spline deposits, whose loops it would
+        // crowd with spilled scalar registers.
+        const bool stage_here = TAPS == 4 && A.mode == 1 && I.push.kind == kFel && I.push.rk4;
+        double ssum[kPartialsPerTile] = {0.0, 0.0, 0.0, 0.0};
+        if (stage_here) sum_tile_partials(I, s_stage, ssum);
 
         // a host-planned box: its load is in flight while the tile is cleared
         int4 hb = make_int4(0, 0, 0, 0);
@@ -417,11 +482,31 @@ __global__ __launch_bounds__(TAPS == 8 ? kDepositCubicThreads : kDepositMaxThrea
             PushParams P = I.push;
             if (P.kind == kFel && P.rk4) {
                 // stage fields A_s and bunchings b_s of the Runge-Kutta step
-                // (b1, b2 of the state, b3, b4 from k_fel_stage), FP64
-                const double* st = I.fel_state;
+                // (b1, b2 of the state, b3, b4 from k_fel_stage's partials), FP64
+                double* st = I.fel_state;
                 const double h = I.fel_dz, sg = (double)I.fel_sigma2;
-                const double bre[4] = {st[kB1], st[kBn], st[kB3], st[kB4]};
-                const double bim[4] = {st[kB1 + 1], st[kBn + 1], st[kB3 + 1], st[kB4 + 1]};
+                double b3[2], b4[2];
+                if (stage_here) {
+                    const double a0[2] = {st[kA], st[kA + 1]}, b1[2] = {st[kB1], st[kB1 + 1]};
+                    const double b2[2] = {st[kBn], st[kBn + 1]};
+                    double a_new[2];
+                    rk4_stage_fields(a0, b1, b2, st[kN0], h, ssum, b3, b4, a_new);
+                    // the instance's first tile keeps them for the field update
+                    // after the solve (no workgroup of this launch reads them)
+                    if (t == 0)
+                        for (int c = 0; c < 2; ++c) {
+                            st[kB3 + c] = b3[c];
+                            st[kB4 + c] = b4[c];
+                            st[kAn + c] = a_new[c];
+                        }
+                } else {
+                    b3[0] = st[kB3];
+                    b3[1] = st[kB3 + 1];
+                    b4[0] = st[kB4];
+                    b4[1] = st[kB4 + 1];
+                }
+                const double bre[4] = {st[kB1], st[kBn], b3[0], b4[0]};
+                const double bim[4] = {st[kB1 + 1], st[kBn + 1], b3[1], b4[1]};
                 const double cA[4] = {0.0, 0.5 * h, 0.5 * h, h};  // A_s = A + cA_s b_{s-1}
                 double rmax = 0.0;
                 for (int k = 0; k < 4; ++k) {
@@ -1240,9 +1325,8 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_spline_narrow(LaunchAr
 
 // ---------------------------------------------------------------------------
 // k_fel_field: one workgroup per instance of the launch list; for an FEL
-// instance it sums the per-tile bunching partials of the preceding kernel in a
-// fixed order (thread-strided, then a fixed shuffle tree) and advances the
-// field (eq. 13c).  A kernel of its own, because a last-tile-sums scheme
+// instance it sums the per-tile bunching partials of the preceding kernel in
+// the fixed order of sum_tile_partials and advances the field (eq. 13c).  A kernel of its own, because a last-tile-sums scheme
 // inside k_solve needs a device-scope release per tile, which on a multi-XCD
 // part writes back the L2 and costs more than the solve.
 //  mode 0 (after k_solve; partials: the new state's bunching at the half-drift
@@ -1251,7 +1335,8 @@ __global__ __launch_bounds__(kSolveQThreads) void k_solve_spline_narrow(LaunchAr
 //    new value.  The new bunchings are kept for the next step.
 //  mode 1 (after k_fel_stage, Runge-Kutta only; partials: the bunching at the
 //    phases of stages 3 and 4): keeps b3, b4 and forms the step's new field
-//    A + dz/6 (b1 + 2 b2 + 2 b3 + b4).
+//    A + dz/6 (b1 + 2 b2 + 2 b3 + b4).  A launch of one instance with few
+//    enough solve tiles skips it: its deposit sums the same partials itself.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kFieldThreads) void k_fel_field(LaunchArgs A) {
     __shared__ double s_red[kPartialsPerTile][kFieldThreads / 64];
@@ -1269,27 +1354,17 @@ __global__ __launch_bounds__(kFieldThreads) void k_fel_field(LaunchArgs A) {
             an[c] = st[kAn + c];
         }
     }
-    double acc[kPartialsPerTile] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = threadIdx.x; k < I.k2_tiles; k += kFieldThreads)
-        for (int c = 0; c < kPartialsPerTile; ++c) acc[c] += I.partials[kPartialsPerTile * k + c];
-    for (int o = 32; o > 0; o >>= 1)
-        for (int c = 0; c < kPartialsPerTile; ++c) acc[c] += __shfl_down(acc[c], o);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0)
-        for (int c = 0; c < kPartialsPerTile; ++c) s_red[c][wid] = acc[c];
-    __syncthreads();
+    double acc[kPartialsPerTile];
+    sum_tile_partials(I, s_red, acc);
     if (threadIdx.x == 0) {
-        for (int c = 0; c < kPartialsPerTile; ++c) {
-            acc[c] = 0.0;
-            for (int k = 0; k < kFieldThreads / 64; ++k) acc[c] += s_red[c][k];
-        }
         const double inv_n0 = 1.0 / n0, h = I.fel_dz;
         if (A.mode == 1) {
-            const double b3[2] = {acc[0] * inv_n0, acc[1] * inv_n0}, b4[2] = {acc[2] * inv_n0, acc[3] * inv_n0};
+            double b3[2], b4[2], a_new[2];
+            rk4_stage_fields(a, b1, bn, n0, h, acc, b3, b4, a_new);
             for (int c = 0; c < 2; ++c) {
                 st[kB3 + c] = b3[c];
                 st[kB4 + c] = b4[c];
-                st[kAn + c] = a[c] + h / 6.0 * (b1[c] + 2.0 * bn[c] + 2.0 * b3[c] + b4[c]);
+                st[kAn + c] = a_new[c];
             }
             return;
         }
